@@ -1,0 +1,383 @@
+"""Pins of the CPU oracle against the paper and the mathematics (no GPU).
+
+Every check compares the oracle with something other than itself: the
+paper's printed numbers, closed forms, textbook identities, library routines
+or brute force.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.csgraph as csg
+import scipy.sparse.linalg as spla
+
+from paper_2002_00917_amd import workloads as wl
+from oracle import partition as opart
+from oracle import pslr as opslr
+from oracle import krylov as okry
+from oracle import adjoint as oadj
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+# ---------------------------------------------------------------- fixtures
+
+def tiny_cases():
+    """(name, A, labels) small enough for dense brute force."""
+    out = []
+    A = wl.laplacian2d(10, 0.0)
+    out.append(("lap2d_spd", A.to_scipy(), opart.geometric_labels((10, 10), (2, 2))))
+    A = wl.laplacian2d(10, wl.sigma_for_negatives(wl.laplacian_eigs((10, 10)), 6))
+    out.append(("lap2d_shift6", A.to_scipy(), opart.geometric_labels((10, 10), (2, 2))))
+    A = wl.laplacian3d(6, 0.0)
+    out.append(("lap3d_spd", A.to_scipy(), opart.geometric_labels((6, 6, 6), (2, 2, 2))))
+    A = wl.convdiff3d(6, 10.0, 0.3)
+    As = A.to_scipy()
+    out.append(("convdiff_rg", As, opart.region_growing_labels(As, 4, 11)))
+    return out
+
+
+CASES = tiny_cases()
+IDS = [c[0] for c in CASES]
+
+
+# ---------------------------------------------------------------- generators
+
+def test_generators_match_closed_form_spectra():
+    A = wl.laplacian2d(7, 0.0).to_scipy().toarray()
+    np.testing.assert_allclose(np.linalg.eigvalsh(A), wl.laplacian_eigs((7, 7)), atol=1e-12)
+    A = wl.laplacian3d(5, 0.0).to_scipy().toarray()
+    np.testing.assert_allclose(np.linalg.eigvalsh(A), wl.laplacian_eigs((5, 5, 5)), atol=1e-12)
+    A = wl.convdiff3d(5, 10.0, 0.0).to_scipy().toarray()
+    ev = np.sort(np.linalg.eigvals(A).real)
+    np.testing.assert_allclose(ev, wl.convdiff_eigs(5, 10.0), atol=1e-10)
+    # shift convention: A(sigma) = A(0) - sigma I
+    d = wl.laplacian3d(5, 0.25).to_scipy() - wl.laplacian3d(5, 0.0).to_scipy()
+    np.testing.assert_allclose(d.toarray(), -0.25 * np.eye(125))
+
+
+def test_paper_negative_counts():
+    """The paper's printed negative-eigenvalue counts for its shifted 3D Laplacians."""
+    with open(os.path.join(HERE, "golden", "negative_counts.json")) as fh:
+        gold = json.load(fh)
+    for c in gold["cases"]:
+        e = wl.laplacian_eigs((c["N"],) * 3)
+        assert int(np.sum(e < c["shift"])) == c["negatives"], c
+
+
+def test_workload_shifts():
+    assert np.sum(wl.laplacian_eigs((64, 64)) < wl.SIGMA_C1) == 20
+    assert np.sum(wl.laplacian_eigs((64, 64, 64)) < wl.SIGMA_C2) == 102
+    assert np.sum(wl.convdiff_eigs(128, 10.0) < wl.SIGMA_C4) == 133
+
+
+def test_variable_coefficient_reduces_to_laplacian():
+    k = np.ones((9, 9))
+    A = wl.variable_coeff2d(k, 0.3).to_scipy()
+    B = wl.laplacian2d(9, 0.3).to_scipy()
+    np.testing.assert_allclose(A.toarray(), B.toarray())
+    g = wl.gaussian_random_field(32, 0.1, 5)
+    assert abs(g.mean()) < 1e-12 and abs(g.std() - 1.0) < 1e-12
+    A = wl.variable_coeff2d(np.exp(g), 0.0).to_scipy()
+    assert abs(A - A.T).max() < 1e-15          # symmetric
+    np.testing.assert_allclose(A.sum(axis=1).A.ravel() >= -1e-12, True)  # weakly diag. dominant
+
+
+# ---------------------------------------------------------------- partition
+
+def test_splitmix64_reference_values():
+    """Published SplitMix64 outputs for seed 0 (Steele, Lea, Flood 2014 reference code)."""
+    g = opart.splitmix64(0)
+    assert [next(g) for _ in range(3)] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+def test_geometric_sizes_c1_c2():
+    A = wl.laplacian2d(64, 0.0).to_scipy()
+    perm, p, q, ip, fp = opart.reorder(A, opart.geometric_labels((64, 64), (2, 2)))
+    assert (p, q) == (3844, 252)
+    assert list(np.diff(ip)) == [961] * 4 and list(np.diff(fp)) == [63] * 4
+    # 3D 64^3 in 4x4x4: interiors are the points with no coordinate on a cut face
+    lab = opart.geometric_labels((64, 64, 64), (4, 4, 4))
+    A = wl.laplacian3d(64, 0.0).to_scipy()
+    perm, p, q, ip, fp = opart.reorder(A, lab)
+    assert (p, q) == (58 ** 3, 64 ** 3 - 58 ** 3)
+    # a 16^3 box has 1 cut face per axis at the domain edge and 2 inside: 16^3 - prod(16 - c_d)
+    assert sorted(set(np.diff(fp).tolist())) == sorted({16 ** 3 - (16 - a) * (16 - b) * (16 - c)
+                                                        for a in (1, 2) for b in (1, 2) for c in (1, 2)})
+    assert np.all(np.sort(perm) == np.arange(64 ** 3))
+
+
+def test_interface_brute_force():
+    rng = np.random.default_rng(0)
+    n = 40
+    A = sp.random(n, n, density=0.08, random_state=1, format="csr") + sp.eye(n)
+    lab = rng.integers(0, 4, size=n).astype(np.int32)
+    mask = opart.interface_mask(A, lab)
+    D = A.toarray() != 0
+    for v in range(n):
+        expect = any((D[v, w] or D[w, v]) and lab[w] != lab[v] for w in range(n) if w != v)
+        assert mask[v] == expect
+    perm, p, q, ip, fp = opart.reorder(A, lab)
+    # interiors of part 0,1,..., then interfaces of 0,1,...; ascending inside
+    groups = [np.flatnonzero((lab == i) & ~mask) for i in range(4)] + \
+             [np.flatnonzero((lab == i) & mask) for i in range(4)]
+    assert np.array_equal(perm, np.concatenate(groups))
+
+
+def test_region_growing_is_nearest_seed_bfs():
+    A = wl.laplacian2d(23, 0.0, Ny=17).to_scipy()
+    s, seed = 7, 123
+    lab = opart.region_growing_labels(A, s, seed)
+    g = opart.splitmix64(seed)
+    seeds = []
+    while len(seeds) < s:
+        v = next(g) % A.shape[0]
+        if v not in seeds:
+            seeds.append(v)
+    assert [lab[v] for v in seeds] == list(range(s))
+    dist = csg.shortest_path(abs(A), unweighted=True, indices=seeds)
+    dmin = dist.min(axis=0)
+    assert np.all(dist[lab, np.arange(A.shape[0])] == dmin)
+    for l in range(s):                        # each region is connected
+        idx = np.flatnonzero(lab == l)
+        ncomp, _ = csg.connected_components(A[idx][:, idx])
+        assert ncomp == 1
+
+
+# ---------------------------------------------------------------- closed forms
+
+@pytest.mark.parametrize("name,A,lab", CASES, ids=IDS)
+def test_schur_complement_textbook_identity(name, A, lab):
+    blk = opslr.make_blocks(A, lab)
+    S, Es, Pm, Err = opslr.dense_forms(blk, 2)
+    Ap = A.toarray()[np.ix_(blk.perm, blk.perm)]
+    Ainv = np.linalg.inv(Ap)
+    np.testing.assert_allclose(np.linalg.inv(Ainv[blk.p:, blk.p:]), S, atol=1e-10 * np.abs(S).max())
+    np.testing.assert_allclose(Es, blk.C0.toarray() - blk.C.toarray() +
+                               blk.F.toarray() @ np.linalg.solve(blk.B.toarray(), blk.E.toarray()),
+                               atol=1e-12)
+
+
+@pytest.mark.parametrize("name,A,lab", CASES, ids=IDS)
+@pytest.mark.parametrize("m", [0, 1, 3])
+def test_power_series_and_theorem_t2(name, A, lab, m):
+    blk = opslr.make_blocks(A, lab)
+    S, Es, Pm, Err = opslr.dense_forms(blk, m)
+    C0 = blk.C0.toarray()
+    q = blk.q
+    K = np.linalg.solve(C0, Es)
+    # geometric-series closed form: P_m = (I - K^{m+1}) S^{-1}
+    Pm_cf = (np.eye(q) - np.linalg.matrix_power(K, m + 1)) @ np.linalg.inv(S)
+    np.testing.assert_allclose(Pm, Pm_cf, atol=1e-9 * np.abs(Pm).max())
+    # Theorem t2: E_rr(m) = (E_s C0^{-1})^{m+1}
+    T = np.linalg.matrix_power(Es @ np.linalg.inv(C0), m + 1)
+    np.testing.assert_allclose(Err, T, atol=1e-10 * max(1.0, np.abs(T).max()))
+    # eigenvalues of E_rr(m) are the (m+1)-th powers of those of E_s C0^{-1}
+    ev = np.linalg.eigvals(Es @ np.linalg.inv(C0))
+    er = np.linalg.eigvals(Err)
+    a = np.sort_complex(np.round(ev ** (m + 1), 8))
+    b = np.sort_complex(np.round(er, 8))
+    assert np.allclose(np.sort(np.abs(a)), np.sort(np.abs(b)), atol=1e-7)
+    # same result from the matrix-free recurrence
+    pre = opslr.PSLR(A, lab, m, 0)
+    rng = np.random.default_rng(1)
+    y = rng.standard_normal(q)
+    np.testing.assert_allclose(pre.power_series(y), Pm @ y, atol=1e-10 * np.abs(Pm @ y).max())
+    np.testing.assert_allclose(pre.err_op(y), Err @ y, atol=1e-10 * max(1, np.abs(Err @ y).max()))
+    np.testing.assert_allclose(pre.power_series_T(y), Pm.T @ y, atol=1e-10 * np.abs(Pm.T @ y).max())
+
+
+@pytest.mark.parametrize("name", ["lap2d_spd", "lap3d_spd"])
+def test_block_jacobi_sweeps_equal_power_series(name):
+    """P_m y equals m+1 block-Jacobi sweeps u <- u + C0^{-1}(y - S u) from u = 0."""
+    _, A, lab = [c for c in CASES if c[0] == name][0]
+    blk = opslr.make_blocks(A, lab)
+    m = 3
+    S, Es, Pm, Err = opslr.dense_forms(blk, m)
+    C0 = blk.C0.toarray()
+    y = np.arange(blk.q, dtype=float) % 5 - 2.0
+    u = np.zeros(blk.q)
+    for _ in range(m + 1):
+        u = u + np.linalg.solve(C0, y - S @ u)
+    np.testing.assert_allclose(u, Pm @ y, atol=1e-11 * np.abs(u).max())
+
+
+@pytest.mark.parametrize("name", ["lap2d_spd", "lap3d_spd"])
+def test_lemma_l2_and_proposition_t1(name):
+    _, A, lab = [c for c in CASES if c[0] == name][0]
+    blk = opslr.make_blocks(A, lab)
+    S, Es, Pm, Err = opslr.dense_forms(blk, 0)
+    C0 = blk.C0.toarray()
+    K = np.linalg.solve(C0, Es)
+    ev = np.linalg.eigvals(K)
+    assert np.abs(ev.imag).max() < 1e-10
+    assert ev.real.max() < 1.0 and ev.real.min() > -1.0      # Lemma l2 (SPD, C diag. dominant)
+    # Prop. t1 in the C0-energy norm, where ||K|| = rho(K) < 1
+    w, U = np.linalg.eigh(C0)
+    Ch = U @ np.diag(np.sqrt(w)) @ U.T
+    Chi = U @ np.diag(1 / np.sqrt(w)) @ U.T
+    nrm = lambda X: np.linalg.norm(Ch @ X @ Chi, 2)
+    kn = nrm(K)
+    assert kn < 1.0
+    Sinv = np.linalg.inv(S)
+    for m in (0, 2, 5):
+        _, _, Pm, _ = opslr.dense_forms(blk, m)
+        assert nrm(Sinv - Pm) <= kn ** (m + 1) * nrm(np.linalg.inv(C0)) / (1 - kn) * (1 + 1e-10)
+    _, _, P200, _ = opslr.dense_forms(blk, 400)
+    np.testing.assert_allclose(P200, Sinv, atol=1e-8 * np.abs(Sinv).max())
+
+
+def test_neumann_reduction_when_rank_zero():
+    """r_k = 0: PSLR's Schur part is the Neumann polynomial with omega = 1, D = C0."""
+    _, A, lab = CASES[1]
+    blk = opslr.make_blocks(A, lab)
+    m = 4
+    S, Es, Pm, Err = opslr.dense_forms(blk, m)
+    D = blk.C0.toarray()
+    N = np.eye(blk.q) - np.linalg.solve(D, S)
+    acc = np.eye(blk.q)
+    poly = np.eye(blk.q)
+    for _ in range(m):
+        acc = acc @ N
+        poly = poly + acc
+    np.testing.assert_allclose(poly @ np.linalg.inv(D), Pm, atol=1e-10 * np.abs(Pm).max())
+
+
+def test_inertia_invariant_shifted():
+    """symmetric A, C0 SPD: #{lambda(E_s C0^{-1}) > 1} = neg(A) - neg(B) (Haynsworth + Sylvester)."""
+    for N, nneg in ((8, 7), (9, 10)):
+        sig = wl.sigma_for_negatives(wl.laplacian_eigs((N, N, N)), nneg)
+        A = wl.laplacian3d(N, sig).to_scipy()
+        lab = opart.geometric_labels((N, N, N), (2, 2, 1))
+        blk = opslr.make_blocks(A, lab)
+        S, Es, Pm, Err = opslr.dense_forms(blk, 0)
+        C0 = blk.C0.toarray()
+        assert np.linalg.eigvalsh(C0).min() > 0
+        ev = np.linalg.eigvals(Es @ np.linalg.inv(C0))
+        negA = int(np.sum(np.linalg.eigvalsh(A.toarray()) < 0))
+        negB = int(np.sum(np.linalg.eigvalsh(blk.B.toarray()) < 0))
+        assert negA == nneg
+        assert int(np.sum(ev.real > 1.0)) == negA - negB
+
+
+# ---------------------------------------------------------------- Arnoldi, SMW, Prop. l3
+
+@pytest.mark.parametrize("name,A,lab", CASES, ids=IDS)
+def test_arnoldi_invariants_and_low_rank(name, A, lab):
+    m, r = 2, 6
+    pre = opslr.PSLR(A, lab, m, r, v0=wl.start_vector(opslr.make_blocks(A, lab).q, 9))
+    blk = pre.blk
+    S, Es, Pm, Err = opslr.dense_forms(blk, m)
+    V, H, Hb = pre.V, pre.H, pre.Hbar
+    k = V.shape[1]
+    assert np.abs(V.T @ V - np.eye(k)).max() < 1e-12
+    np.testing.assert_allclose(H, V.T @ Err @ V, atol=1e-11 * max(1, np.abs(Err).max()))
+    assert np.allclose(np.tril(H, -2), 0)
+    # Arnoldi relation E_rr V_k = V_{k+1} Hbar_k
+    pre2_V, _, Hbar, vnext = opslr.arnoldi(lambda v: Err @ v, wl.start_vector(blk.q, 9), r)
+    Vp = np.column_stack([pre2_V, vnext])
+    np.testing.assert_allclose(Err @ pre2_V, Vp @ Hbar, atol=1e-11 * max(1, np.abs(Err).max()))
+    # ||E_rr - V_r H_r V_r^T||_F non-increasing in r
+    errs = []
+    for rr in range(1, r + 1):
+        Vr = pre2_V[:, :rr]
+        errs.append(np.linalg.norm(Err - Vr @ (Vr.T @ Err @ Vr) @ Vr.T))
+    assert all(errs[i + 1] <= errs[i] * (1 + 1e-12) for i in range(len(errs) - 1))
+    # Sherman-Morrison-Woodbury: P_m (I + V G V^T) = P_m (I - V H V^T)^{-1}
+    Sai = pre.dense_sapp_inv()
+    Z = np.eye(blk.q) - V @ H @ V.T
+    np.testing.assert_allclose(Sai, Pm @ np.linalg.inv(Z), atol=1e-9 * np.abs(Sai).max())
+    # Prop. l3: S^{-1} - S_app^{-1} = S^{-1} X Z^{-1}, and the relative bound
+    X = Err - V @ H @ V.T
+    Sinv = np.linalg.inv(S)
+    lhs = Sinv - Sai
+    np.testing.assert_allclose(lhs, Sinv @ X @ np.linalg.inv(Z), atol=1e-9 * np.abs(Sinv).max())
+    fro = np.linalg.norm
+    assert fro(lhs) / fro(Sinv) <= fro(X) * fro(np.linalg.inv(Z)) * (1 + 1e-9)
+    # spectrum: lambda(S_app^{-1} S) = 1 - lambda(Z^{-1} X)
+    e1 = np.sort_complex(np.round(np.linalg.eigvals(Sai @ S), 7))
+    e2 = np.sort_complex(np.round(1 - np.linalg.eigvals(np.linalg.solve(Z, X)), 7))
+    assert np.allclose(np.sort(e1.real), np.sort(e2.real), atol=1e-6)
+
+
+@pytest.mark.parametrize("name,A,lab", CASES[:3], ids=IDS[:3])
+def test_full_rank_gives_exact_inverse(name, A, lab):
+    blk = opslr.make_blocks(A, lab)
+    pre = opslr.PSLR(A, lab, 2, blk.q, v0=wl.start_vector(blk.q, 3))
+    if pre.V.shape[1] < blk.q:
+        pytest.skip("Arnoldi broke down early (invariant subspace)")
+    S, _, _, _ = opslr.dense_forms(blk, 2)
+    np.testing.assert_allclose(pre.dense_sapp_inv(), np.linalg.inv(S), atol=1e-8 * np.abs(np.linalg.inv(S)).max())
+    b = np.sin(np.arange(A.shape[0]))
+    x, its, rel, ok = okry.fgmres(A, b, pre.apply, restart=10, tol=1e-10)
+    assert ok and its == 1
+    np.testing.assert_allclose(x, spla.spsolve(A.tocsc(), b), rtol=1e-8, atol=1e-8)
+
+
+# ---------------------------------------------------------------- Algorithm 3
+
+@pytest.mark.parametrize("name,A,lab", CASES, ids=IDS)
+def test_apply_matches_dense_block_inverse(name, A, lab):
+    blk = opslr.make_blocks(A, lab)
+    pre = opslr.PSLR(A, lab, 3, 5, v0=wl.start_vector(blk.q, 4))
+    Minv = pre.dense_inverse()
+    rng = np.random.default_rng(5)
+    b = rng.standard_normal((A.shape[0], 3))
+    z = pre.apply(b)
+    zd = np.empty_like(b)
+    zd[blk.perm] = Minv @ b[blk.perm]
+    np.testing.assert_allclose(z, zd, atol=1e-10 * np.abs(zd).max())
+    # transposed apply: dense transpose and the dot-product test
+    zt = pre.apply_transpose(b)
+    ztd = np.empty_like(b)
+    ztd[blk.perm] = Minv.T @ b[blk.perm]
+    np.testing.assert_allclose(zt, ztd, atol=1e-10 * np.abs(ztd).max())
+    u, v = b[:, 0], b[:, 1]
+    lhs = pre.apply(u) @ v
+    rhs = u @ pre.apply_transpose(v)
+    assert abs(lhs - rhs) <= 1e-13 * (abs(lhs) + np.linalg.norm(pre.apply(u)) * np.linalg.norm(v))
+
+
+# ---------------------------------------------------------------- FGMRES and adjoint
+
+def test_fgmres_reaches_true_solution():
+    w = wl.c1(16)
+    A = w.A.to_scipy()
+    lab = opart.geometric_labels((16, 16), (2, 2))
+    blk = opslr.make_blocks(A, lab)
+    pre = opslr.PSLR(A, lab, 3, 8, v0=wl.start_vector(blk.q, 1))
+    b = w.b[:, 0]
+    x, its, rel, ok = okry.fgmres(A, b, pre.apply, restart=40, tol=1e-8)
+    assert ok and rel <= 1e-8
+    xs = spla.spsolve(A.tocsc(), b)
+    kappa = np.linalg.cond(A.toarray())
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= kappa * 1e-8
+    np.testing.assert_allclose(xs, np.ones(A.shape[0]), rtol=1e-9)      # b = A*1
+    # unpreconditioned full GMRES terminates in at most n steps
+    x2, its2, rel2, ok2 = okry.fgmres(A, b, None, restart=A.shape[0], maxit=A.shape[0], tol=1e-10)
+    assert ok2 and its2 <= A.shape[0]
+    # restarted and preconditioned runs agree with the exact solution
+    x3, its3, rel3, ok3 = okry.fgmres(A, b, pre.apply, restart=5, tol=1e-9)
+    assert ok3 and np.allclose(x3, xs, rtol=1e-6)
+
+
+def test_adjoint_gradient_matches_finite_differences():
+    kappa = np.exp(wl.gaussian_random_field(8, 0.2, 5))
+    A = wl.variable_coeff2d(kappa, 0.5).to_scipy()
+    b = np.linspace(0.5, 1.5, A.shape[0])
+    zstar = np.cos(np.arange(A.shape[0]))
+    L, z, lam, g = oadj.loss_and_grad(A, b, zstar)
+    # closed form -A^{-T} (dL/dz) z^T on the pattern
+    Ad = A.toarray()
+    full = -np.outer(np.linalg.solve(Ad.T, 2 * (z - zstar)), z)
+    rows = np.repeat(np.arange(A.shape[0]), np.diff(A.indptr))
+    np.testing.assert_allclose(g, full[rows, A.indices], rtol=1e-10, atol=1e-14)
+    rng = np.random.default_rng(7)
+    for k in rng.choice(A.nnz, size=10, replace=False):
+        d = 1e-6
+        Ap = A.copy(); Ap.data[k] += d
+        Am = A.copy(); Am.data[k] -= d
+        fd = (oadj.loss_and_grad(Ap, b, zstar)[0] - oadj.loss_and_grad(Am, b, zstar)[0]) / (2 * d)
+        assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(g[k]))
