@@ -1,0 +1,184 @@
+/*
+ * pslr.h -- C ABI of the PSLR (Power Schur complement Low-Rank) preconditioner
+ * for one AMD MI355X (gfx950).
+ *
+ * Method: Q. Zheng, Y. Xi, Y. Saad, "A power Schur complement low-rank
+ * correction preconditioner for general sparse linear systems",
+ * arXiv 2002.00917.  Notation of the paper throughout:
+ *
+ *   After a reordering by subdomains (Sec. 2, eq. resystem)
+ *       A = [ B  E ]   B, E block diagonal (s subdomains),
+ *           [ F  C ]   F shaped like E^T,
+ *   S = C - F B^{-1} E (eq. solve), C0 = blkdiag(C_i), E_s = C0 - S,
+ *   C_g = C - C0 (Sec. 3.1, eq. matrixS),
+ *   P_m = sum_{i=0..m} (C0^{-1} E_s)^i C0^{-1}        (eq. approx1),
+ *   E_rr(m) = I - S P_m = (E_s C0^{-1})^{m+1}         (eqs. err1, err; Thm. t2),
+ *   r_k-step Arnoldi on E_rr(m): E_rr ~ V H V^T       (eq. schur),
+ *   G = (I - H)^{-1} - I, S_app^{-1} = P_m (I + V G V^T)  (eqs. Sinv0, Sinv).
+ *
+ * Local factors are exact sparse LU factorisations of every B_i and C_i (the
+ * paper's Algorithm 4 uses ILU; exact LU makes the closed forms above hold
+ * to rounding).
+ *
+ * Conventions shared by every entry point
+ *   - Every call returns a pslr_status and never aborts; pslr_last_error()
+ *     gives a thread-local message for the last failure.
+ *   - Host arrays (CSR matrix, labels, options) are read during the call only;
+ *     the caller keeps ownership.
+ *   - Device vectors (b, z, x, lambda, grad) are caller-owned device pointers
+ *     (e.g. torch tensors' data_ptr()), column-major n x nrhs with a leading
+ *     dimension; they must not alias and must stay alive until the work on the
+ *     given HIP stream has completed (calls are asynchronous unless stated).
+ *   - Vectors cross the boundary in the ORIGINAL ordering of A and in FP64 in
+ *     both precision modes; the library permutes and casts internally.
+ *   - A handle owns every device buffer it allocates; it holds one workspace,
+ *     so concurrent calls on one handle from different streams race.
+ *   - hip_stream may be NULL (the default stream).
+ */
+#ifndef PSLR_H
+#define PSLR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pslr_ctx* pslr_handle;
+
+typedef enum {
+  PSLR_OK = 0,
+  PSLR_EINVAL = 1,      /* bad argument: sizes, m < 0, rank < 0, label out of range ... */
+  PSLR_ESINGULAR = 2,   /* zero pivot in some B_i or C_i, or I - H singular (eq. s1 assumption) */
+  PSLR_ENOCONV = 3,     /* FGMRES did not reach tol within maxit (the paper's "F");
+                           best iterate, iters and relres are still written */
+  PSLR_EBREAKDOWN = 4,  /* informational: Arnoldi found an invariant subspace and the
+                           rank was reduced; the preconditioner is valid */
+  PSLR_ENOMEM = 5,      /* host or device allocation failed */
+  PSLR_EHIP = 6,        /* a HIP runtime call failed */
+  PSLR_ENOTSUP = 7      /* configuration not supported (e.g. a block too large for LDS) */
+} pslr_status;
+
+typedef struct {
+  int32_t m;                /* power-series upper index: sum_{i=0..m}, i.e. m+1 terms (eq. approx1) */
+  int32_t rank;             /* r_k, Arnoldi steps (eq. schur); capped at q; 0 disables the correction */
+  int32_t precision;        /* 0: FP64 apply; 1: FP32 apply with BF16 V (FGMRES and Arnoldi stay FP64) */
+  int32_t want_transpose;   /* nonzero: also build the layouts pslr_apply_transpose needs */
+  const double* v0;         /* optional host Arnoldi start vector of length q (interface order) */
+  uint64_t seed;            /* used when v0 == NULL: SplitMix64 uniform in [-0.5, 0.5) */
+  double pivot_threshold;   /* tau of restricted threshold partial pivoting; <= 0 means 0.1 */
+  int32_t nthreads;         /* host threads for the factorisation; 0 = hardware concurrency */
+} pslr_options;
+
+typedef struct {
+  int64_t n, p, q;          /* p interior, q interface unknowns (eq. resystem) */
+  int32_t nparts;           /* s */
+  int32_t m, rank, precision;
+  int64_t nnz_A, nnz_E, nnz_F, nnz_Cg;
+  int64_t nnz_LU_B, nnz_LU_C0;        /* stored factor entries (incl. inverted diagonal blocks) */
+  int32_t supernodes_B, supernodes_C0;
+  int32_t max_levels_B, max_levels_C0; /* level-schedule depth of the triangular solves */
+  double fill_lu, fill_lowrank, fill_total;  /* nnz(LU)/nnz(A), nnz(V)+nnz(G) over nnz(A) (Sec. 4) */
+  int64_t apply_bytes;      /* algorithmic HBM bytes of one single-rhs apply (matrix + vectors) */
+  int64_t apply_bytes_rhs;  /* vector bytes added by each further right-hand side */
+  int64_t series_bytes;     /* algorithmic bytes of one power-series step launch, single rhs */
+  double seconds_reorder, seconds_factor, seconds_arnoldi;
+} pslr_info_t;
+
+/* Fill *opt with defaults: m = 3, rank = 16, FP64, no transpose, seed 1, tau 0.1. */
+void pslr_default_options(pslr_options* opt);
+
+/* Build the preconditioner (Algorithm 4): reorder A by the labels `part`
+ * (interiors of part 0..s-1 then interfaces, Sec. 2), exact sparse LU of every
+ * B_i and C_i on the host, upload, then r_k-step Arnoldi on E_rr(m) on the
+ * device in FP64 and G = (I - H)^{-1} - I on the host.
+ *   n, rowptr[n+1], colind[nnz], vals[nnz]: host CSR of A, original ordering.
+ *   part[n]: subdomain label of each row, in [0, nparts).
+ * Vertex v is an interface vertex iff a stored entry A[v,w] or A[w,v] couples
+ * it to a vertex w of another part.  Returns PSLR_EBREAKDOWN (with a valid
+ * handle) when Arnoldi stopped early. */
+pslr_status pslr_setup(int64_t n, const int64_t* rowptr, const int32_t* colind, const double* vals,
+                       const int32_t* part, int32_t nparts, const pslr_options* opt,
+                       void* hip_stream, pslr_handle* out);
+
+/* z = M^{-1} b, the preconditioner of Algorithm 3 (eq. application):
+ *   y = g - F B^{-1} f;  y <- y + V G V^T y;  y <- P_m y;  x = B^{-1}(f - E y).
+ * b, z: device, n x nrhs column-major, leading dimensions ldb, ldz >= n. */
+pslr_status pslr_apply(pslr_handle h, int32_t nrhs, const double* b, int64_t ldb, double* z,
+                       int64_t ldz, void* hip_stream);
+
+/* z = M^{-T} b, the transpose of the operator of Algorithm 3:
+ *   y = g - E^T B^{-T} f;  y <- P_m^T y;  y <- y + V G^T V^T y;  x = B^{-T}(f - F^T y).
+ * Needs a handle built with want_transpose != 0 (else PSLR_EINVAL). */
+pslr_status pslr_apply_transpose(pslr_handle h, int32_t nrhs, const double* b, int64_t ldb,
+                                 double* z, int64_t ldz, void* hip_stream);
+
+/* Right-preconditioned flexible GMRES(restart) in FP64 on A x = b (or A^T x = b
+ * with M^{-T} when transpose != 0), independent Krylov spaces per column.
+ * x: device, in = initial guess, out = solution.  Stops a column when the
+ * Givens residual estimate reaches tol * ||b||, confirms with the true FP64
+ * residual and restarts if needed; at most maxit inner iterations (the paper's
+ * "its" and its 500-iteration failure rule, Sec. 4).  iters[nrhs], relres[nrhs]:
+ * host outputs (true relative residuals).  Synchronises the stream. */
+pslr_status fgmres_solve(pslr_handle h, int32_t nrhs, const double* b, int64_t ldb, double* x,
+                         int64_t ldx, int32_t restart, int32_t maxit, double tol, int32_t transpose,
+                         int32_t* iters, double* relres, void* hip_stream);
+
+/* grad[k] = - sum_r lambda[i_k, r] * z[j_k, r] for every stored entry k of A
+ * (original CSR order): the gradient of a loss of z = A^{-1} b with respect to
+ * A's nonzeros, given the adjoint lambda = A^{-T} dL/dz.  Device arrays. */
+pslr_status pslr_sddmm_grad(pslr_handle h, int32_t nrhs, const double* lambda, int64_t ldl,
+                            const double* z, int64_t ldz, double* grad, void* hip_stream);
+
+pslr_status pslr_info(pslr_handle h, pslr_info_t* out);
+
+/* Replace V and H (host, column-major q x k and k x k) and recompute G; k = 0
+ * removes the low-rank correction.  Used to apply an externally computed
+ * Arnoldi basis. */
+pslr_status pslr_set_lowrank(pslr_handle h, int32_t k, const double* V, int64_t ldv,
+                             const double* H, int64_t ldh);
+
+/* Copy the current V (q x k) and H (k x k) to host arrays (column-major). */
+pslr_status pslr_get_lowrank(pslr_handle h, int32_t* k, double* V, int64_t ldv, double* H,
+                             int64_t ldh);
+
+/* Geometric split of a box grid (x fastest): label = lexicographic index,
+ * x fastest, of floor(i_d * parts[d] / dims[d]).  Host only. */
+pslr_status pslr_partition_geometric(int32_t ndim, const int32_t* dims, const int32_t* parts,
+                                     int32_t* label);
+
+/* Region growing: seeds are the first nparts distinct SplitMix64(seed) mod n,
+ * label l belongs to the l-th seed; multi-source FIFO BFS over the
+ * symmetrised pattern, neighbours in ascending index, first visitor wins;
+ * vertices no seed reaches start new regions in ascending index order.
+ * *nlabels receives the label count.  Host only. */
+pslr_status pslr_partition_region_growing(int64_t n, const int64_t* rowptr, const int32_t* colind,
+                                          int32_t nparts, uint64_t seed, int32_t* label,
+                                          int32_t* nlabels);
+
+/* The reordering of Sec. 2 as used by pslr_setup: perm[new] = old (n entries),
+ * interiors of part 0..s-1 then interfaces of part 0..s-1, ascending original
+ * index inside each group.  Host only. */
+pslr_status pslr_reorder(int64_t n, const int64_t* rowptr, const int32_t* colind,
+                         const int32_t* part, int32_t nparts, int64_t* perm, int64_t* p,
+                         int64_t* q);
+
+/* Host-only consistency check of the setup, no GPU needed: factors every B_i
+ * and C_i, then reports the largest relative factorisation residual
+ * ||P Q M Q^T - L U||_F / ||M||_F and the largest relative residual of the
+ * packed level-scheduled solve layouts executed on the host for a fixed
+ * vector (forward, and transposed when want_transpose).  Diagnostic only: no
+ * other entry point calls it. */
+pslr_status pslr_host_selfcheck(int64_t n, const int64_t* rowptr, const int32_t* colind,
+                                const double* vals, const int32_t* part, int32_t nparts,
+                                const pslr_options* opt, double* factor_residual,
+                                double* solve_residual);
+
+pslr_status pslr_destroy(pslr_handle h);
+const char* pslr_status_string(pslr_status s);
+const char* pslr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PSLR_H */

@@ -1,0 +1,1199 @@
+// C ABI of the PSLR preconditioner (include/pslr.h): setup (Algorithm 4),
+// apply (Algorithm 3) and its transpose, FP64 flexible GMRES, the gradient
+// SDDMM, and the host-only partition / reordering helpers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/pslr.h"
+#include "pslr_dev.h"
+#include "pslr_host.h"
+
+using namespace pslr;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+pslr_status fail(pslr_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return fail(PSLR_EHIP, std::string(#expr " failed: ") + hipGetErrorString(e_));        \
+  } while (0)
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Device allocation list owned by a handle.
+struct DevPool {
+  std::vector<void*> ptrs;
+  size_t bytes = 0;
+  ~DevPool() { release(); }
+  void release() {
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+    bytes = 0;
+  }
+  template <typename X>
+  hipError_t upload(const std::vector<X>& h, const X** out) {
+    X* d = nullptr;
+    size_t nb = std::max<size_t>(h.size(), 1) * sizeof(X);
+    hipError_t e = hipMalloc((void**)&d, nb);
+    if (e != hipSuccess) return e;
+    ptrs.push_back(d);
+    bytes += nb;
+    if (!h.empty()) e = hipMemcpy(d, h.data(), h.size() * sizeof(X), hipMemcpyHostToDevice);
+    *out = d;
+    return e;
+  }
+  template <typename X>
+  hipError_t alloc(size_t count, X** out) {
+    X* d = nullptr;
+    hipError_t e = hipMalloc((void**)&d, std::max<size_t>(count, 1) * sizeof(X));
+    if (e != hipSuccess) return e;
+    ptrs.push_back(d);
+    bytes += std::max<size_t>(count, 1) * sizeof(X);
+    *out = d;
+    return hipSuccess;
+  }
+};
+
+struct TriBytes {
+  int64_t val = 0, idx = 0, meta = 0;  // algorithmic bytes split by kind (values counted as entries)
+};
+
+// Concatenate one factor family over all blocks with absolute offsets.
+template <typename T>
+hipError_t upload_tri(DevPool& pool, const std::vector<BlockFactor>& F, TriHost BlockFactor::*mem,
+                      TriArrays<T>& out, int& max_lrows, int64_t& nval, int64_t& nidx,
+                      int64_t& nmeta) {
+  std::vector<DevTriBlock> blk(F.size());
+  std::vector<int32_t> lev_ptr, lev_g, lrows, row_sn, col, ridx;
+  std::vector<DevSn> sn;
+  std::vector<int64_t> rp;
+  std::vector<T> val, tri;
+  nval = nidx = nmeta = 0;
+  for (size_t i = 0; i < F.size(); ++i) {
+    const TriHost& H = F[i].*mem;
+    DevTriBlock& B = blk[i];
+    B.n = H.n;
+    B.nlev = H.nlev;
+    B.max_lrows = H.max_lrows;
+    B.lower = H.lower ? 1 : 0;
+    B.lev_base = (int64_t)lev_ptr.size();
+    B.row_base = (int64_t)lrows.size();
+    B.rp_base = (int64_t)rp.size();
+    B.sn_base = (int64_t)sn.size();
+    max_lrows = std::max(max_lrows, H.max_lrows);
+    const int64_t vb = (int64_t)val.size(), tb = (int64_t)tri.size(), rb = (int64_t)ridx.size();
+    lev_ptr.insert(lev_ptr.end(), H.lev_ptr.begin(), H.lev_ptr.end());
+    lev_g.insert(lev_g.end(), H.lev_g.begin(), H.lev_g.end());
+    lev_g.push_back(0);
+    lrows.insert(lrows.end(), H.lrows.begin(), H.lrows.end());
+    row_sn.insert(row_sn.end(), H.row_sn.begin(), H.row_sn.end());
+    for (int64_t v : H.rp) rp.push_back(v + vb);
+    col.insert(col.end(), H.col.begin(), H.col.end());
+    for (double v : H.val) val.push_back((T)v);
+    ridx.insert(ridx.end(), H.ridx.begin(), H.ridx.end());
+    for (double v : H.tri) tri.push_back((T)v);
+    for (const SnHost& S : H.sn)
+      sn.push_back(DevSn{S.f, S.w, S.h, 0, S.tri_off + tb, S.panel_off + vb, S.ridx_off + rb});
+    nval += (int64_t)H.val.size() + (int64_t)H.tri.size();
+    nidx += (int64_t)H.col.size() + (int64_t)H.ridx.size();
+    nmeta += (H.lower ? 8 * (int64_t)(H.n + 1) : 0) + 8 * (int64_t)H.n +
+             (int64_t)sizeof(DevSn) * (int64_t)H.sn.size() + 8 * (int64_t)(H.nlev + 1);
+  }
+  hipError_t e;
+  if ((e = pool.upload(blk, &out.blk))) return e;
+  if ((e = pool.upload(lev_ptr, &out.lev_ptr))) return e;
+  if ((e = pool.upload(lev_g, &out.lev_g))) return e;
+  if ((e = pool.upload(lrows, &out.lrows))) return e;
+  if ((e = pool.upload(row_sn, &out.row_sn))) return e;
+  if ((e = pool.upload(sn, &out.sn))) return e;
+  if ((e = pool.upload(rp, &out.rp))) return e;
+  if ((e = pool.upload(col, &out.col))) return e;
+  if ((e = pool.upload(val, &out.val))) return e;
+  if ((e = pool.upload(ridx, &out.ridx))) return e;
+  if ((e = pool.upload(tri, &out.tri))) return e;
+  return hipSuccess;
+}
+
+// Host CSR of the coupling blocks in the layouts the kernels read.
+struct CouplingHost {
+  std::vector<int64_t> ptr;
+  std::vector<int32_t> col;
+  std::vector<double> val;
+};
+
+template <typename T>
+hipError_t upload_csr(DevPool& pool, const CouplingHost& C, DevCsr<T>& out) {
+  std::vector<T> v(C.val.begin(), C.val.end());
+  hipError_t e;
+  if ((e = pool.upload(C.ptr, &out.ptr))) return e;
+  if ((e = pool.upload(C.col, &out.col))) return e;
+  return pool.upload(v, &out.val);
+}
+
+// Everything one direction of the apply needs, host side.
+struct DirHost {
+  std::vector<int32_t> gB_in, gB_out, gC_in, gC_out, gC_inv;
+  CouplingHost Ein, Fout, Cg;
+};
+
+}  // namespace
+
+struct pslr_ctx {
+  int device = 0;
+  Reordering R;
+  int32_t m = 3, rank = 0, precision = 0, want_T = 0;
+  int64_t nnzA = 0;
+  std::vector<int64_t> hA_ptr;
+  DevPool pool;      // factor and matrix data
+  DevPool ws;        // workspaces (grown on demand)
+  DevPool vpool;     // low-rank data
+  // device copies of A (original order) and optionally A^T
+  const int64_t* A_ptr = nullptr;
+  const int32_t* A_col = nullptr;
+  const double* A_val = nullptr;
+  const int64_t* AT_ptr = nullptr;
+  const int32_t* AT_col = nullptr;
+  const double* AT_val = nullptr;
+  ApplyArrays<double> fw64{}, tr64{};
+  ApplyArrays<float> fw32{}, tr32{};
+  bool have64 = false, have32 = false, haveT = false;
+  int threads = 512;
+  size_t lds64 = 0, lds32 = 0;
+  // low rank: Vcm (FP64 q x k column-major, host), H, G; device V row-major and G
+  int32_t k = 0;
+  std::vector<double> hV, hH, hG;
+  const double* V64 = nullptr;
+  const double* G64 = nullptr;
+  const __hip_bfloat16* Vbf = nullptr;
+  const float* G32 = nullptr;
+  int nchunk = 256;
+  // apply workspaces
+  int ws_nrhs = 0;
+  void* y = nullptr;
+  void* u0 = nullptr;
+  void* u1 = nullptr;
+  void* partial = nullptr;
+  // info
+  pslr_info_t info{};
+};
+
+namespace {
+
+pslr_status validate_csr(int64_t n, const int64_t* rowptr, const int32_t* colind) {
+  if (n < 0 || (n > 0 && (!rowptr || !colind))) return fail(PSLR_EINVAL, "null CSR arrays");
+  if (n > 0x7fffffff) return fail(PSLR_EINVAL, "n must fit in int32");
+  if (rowptr[0] != 0) return fail(PSLR_EINVAL, "rowptr[0] must be 0");
+  for (int64_t i = 0; i < n; ++i) {
+    if (rowptr[i + 1] < rowptr[i]) return fail(PSLR_EINVAL, "rowptr not non-decreasing");
+    for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
+      if (colind[k] < 0 || colind[k] >= n) return fail(PSLR_EINVAL, "column index out of range");
+  }
+  return PSLR_OK;
+}
+
+pslr_status validate_part(int64_t n, const int32_t* part, int32_t nparts) {
+  if (nparts <= 0 || (n > 0 && !part)) return fail(PSLR_EINVAL, "bad part/nparts");
+  for (int64_t i = 0; i < n; ++i)
+    if (part[i] < 0 || part[i] >= nparts) return fail(PSLR_EINVAL, "label outside [0, nparts)");
+  return PSLR_OK;
+}
+
+// Build the per-direction host index maps and coupling matrices.
+DirHost build_dir(const Reordering& R, const Blocks& Bk, const std::vector<BlockFactor>& fB,
+                  const std::vector<BlockFactor>& fC, bool transpose) {
+  DirHost D;
+  const int np = R.nparts;
+  D.gB_in.resize(R.p);
+  D.gB_out.resize(R.p);
+  D.gC_in.resize(R.q);
+  D.gC_out.resize(R.q);
+  D.gC_inv.resize(R.q);
+  D.Ein.ptr.assign(R.p + 1, 0);
+  D.Fout.ptr.assign(R.q + 1, 0);
+  for (int i = 0; i < np; ++i) {
+    const int64_t i0 = R.int_ptr[i], f0 = R.if_ptr[i];
+    const BlockFactor& B = fB[i];
+    const BlockFactor& C = fC[i];
+    const std::vector<int32_t>& bin = transpose ? B.gout : B.gin;
+    const std::vector<int32_t>& bout = transpose ? B.gin : B.gout;
+    const std::vector<int32_t>& cin = transpose ? C.gout : C.gin;
+    const std::vector<int32_t>& cout = transpose ? C.gin : C.gout;
+    for (int p = 0; p < B.n; ++p) {
+      D.gB_in[i0 + p] = (int32_t)R.perm[i0 + bin[p]];
+      D.gB_out[i0 + p] = (int32_t)R.perm[i0 + bout[p]];
+    }
+    for (int p = 0; p < C.n; ++p) {
+      D.gC_in[f0 + p] = cin[p];
+      D.gC_out[f0 + p] = cout[p];
+      D.gC_inv[f0 + cin[p]] = p;
+    }
+  }
+  // Ein: row = B-solve input position (global i0 + p); forward: E_i row bin[p];
+  // transposed: F_i^T row bin[p] = column bin[p] of F_i.
+  // Fout: row = global interface; forward: F_i with columns mapped to B output
+  // positions; transposed: E_i^T with columns mapped likewise.
+  for (int i = 0; i < np; ++i) {
+    const int64_t i0 = R.int_ptr[i], f0 = R.if_ptr[i];
+    const BlockFactor& B = fB[i];
+    const std::vector<int32_t>& bin = transpose ? B.gout : B.gin;
+    const std::vector<int32_t>& bout = transpose ? B.gin : B.gout;
+    std::vector<int32_t> boutinv(B.n);
+    for (int c = 0; c < B.n; ++c) boutinv[bout[c]] = c;
+    const CsrL& E = Bk.E[i];   // p_i x q_i
+    const CsrL& F = Bk.F[i];   // q_i x p_i
+    // column lists of the matrix feeding Ein (rows = local interior)
+    std::vector<std::vector<std::pair<int32_t, double>>> inrows(B.n), outrows(F.nrows);
+    if (!transpose) {
+      for (int r = 0; r < E.nrows; ++r)
+        for (int k = E.ptr[r]; k < E.ptr[r + 1]; ++k) inrows[r].push_back({E.col[k], E.val[k]});
+      for (int r = 0; r < F.nrows; ++r)
+        for (int k = F.ptr[r]; k < F.ptr[r + 1]; ++k) outrows[r].push_back({boutinv[F.col[k]], F.val[k]});
+    } else {
+      for (int r = 0; r < F.nrows; ++r)  // F^T: row = local interior F.col, col = r
+        for (int k = F.ptr[r]; k < F.ptr[r + 1]; ++k) inrows[F.col[k]].push_back({r, F.val[k]});
+      for (int r = 0; r < E.nrows; ++r)  // E^T: row = local interface E.col, col = interior r
+        for (int k = E.ptr[r]; k < E.ptr[r + 1]; ++k) outrows[E.col[k]].push_back({boutinv[r], E.val[k]});
+    }
+    for (int p = 0; p < B.n; ++p) {
+      auto& rw = inrows[bin[p]];
+      std::sort(rw.begin(), rw.end());
+      for (auto& e : rw) {
+        D.Ein.col.push_back(e.first);
+        D.Ein.val.push_back(e.second);
+      }
+      D.Ein.ptr[i0 + p + 1] = (int64_t)D.Ein.col.size();
+    }
+    for (int r = 0; r < F.nrows; ++r) {
+      auto& rw = outrows[r];
+      std::sort(rw.begin(), rw.end());
+      for (auto& e : rw) {
+        D.Fout.col.push_back(e.first);
+        D.Fout.val.push_back(e.second);
+      }
+      D.Fout.ptr[f0 + r + 1] = (int64_t)D.Fout.col.size();
+    }
+  }
+  const CsrG& G = Bk.Cg;
+  if (!transpose) {
+    D.Cg.ptr = G.ptr;
+    D.Cg.col = G.col;
+    D.Cg.val = G.val;
+  } else {
+    D.Cg.ptr.assign(R.q + 1, 0);
+    for (int32_t c : G.col) D.Cg.ptr[c + 1]++;
+    for (int64_t r = 0; r < R.q; ++r) D.Cg.ptr[r + 1] += D.Cg.ptr[r];
+    D.Cg.col.resize(G.col.size());
+    D.Cg.val.resize(G.col.size());
+    std::vector<int64_t> pos(D.Cg.ptr.begin(), D.Cg.ptr.end() - 1);
+    for (int64_t r = 0; r < R.q; ++r)
+      for (int64_t k = G.ptr[r]; k < G.ptr[r + 1]; ++k) {
+        int64_t d = pos[G.col[k]]++;
+        D.Cg.col[d] = (int32_t)r;
+        D.Cg.val[d] = G.val[k];
+      }
+  }
+  return D;
+}
+
+template <typename T>
+hipError_t upload_dir(DevPool& pool, const Reordering& R, const std::vector<BlockFactor>& fB,
+                      const std::vector<BlockFactor>& fC, const DirHost& D, bool transpose,
+                      const int64_t* d_int_ptr, const int64_t* d_if_ptr, const int32_t* d_if_orig,
+                      ApplyArrays<T>& A, int64_t bytes_out[4]) {
+  hipError_t e;
+  A.nparts = R.nparts;
+  A.n = R.n;
+  A.p = R.p;
+  A.q = R.q;
+  A.int_ptr = d_int_ptr;
+  A.if_ptr = d_if_ptr;
+  A.if_orig = d_if_orig;
+  int mlr = 0;
+  int64_t v, x, mt;
+  TriHost BlockFactor::*lo = transpose ? &BlockFactor::loT : &BlockFactor::lo;
+  TriHost BlockFactor::*up = transpose ? &BlockFactor::upT : &BlockFactor::up;
+  const int w = (int)sizeof(T);
+  if ((e = upload_tri(pool, fB, lo, A.LB, mlr, v, x, mt))) return e;
+  bytes_out[0] = v * w + x * 4 + mt;
+  if ((e = upload_tri(pool, fB, up, A.UB, mlr, v, x, mt))) return e;
+  bytes_out[0] += v * w + x * 4 + mt;
+  if ((e = upload_tri(pool, fC, lo, A.LC, mlr, v, x, mt))) return e;
+  bytes_out[1] = v * w + x * 4 + mt;
+  if ((e = upload_tri(pool, fC, up, A.UC, mlr, v, x, mt))) return e;
+  bytes_out[1] += v * w + x * 4 + mt;
+  A.maxLR = std::max(mlr, 1);
+  A.maxPB = A.maxQB = 1;
+  for (int i = 0; i < R.nparts; ++i) {
+    A.maxPB = std::max<int>(A.maxPB, (int)(R.int_ptr[i + 1] - R.int_ptr[i]));
+    A.maxQB = std::max<int>(A.maxQB, (int)(R.if_ptr[i + 1] - R.if_ptr[i]));
+  }
+  if ((e = pool.upload(D.gB_in, &A.gB_in))) return e;
+  if ((e = pool.upload(D.gB_out, &A.gB_out))) return e;
+  if ((e = pool.upload(D.gC_in, &A.gC_in))) return e;
+  if ((e = pool.upload(D.gC_out, &A.gC_out))) return e;
+  if ((e = pool.upload(D.gC_inv, &A.gC_inv))) return e;
+  if ((e = upload_csr(pool, D.Ein, A.Ein))) return e;
+  if ((e = upload_csr(pool, D.Fout, A.Fout))) return e;
+  if ((e = upload_csr(pool, D.Cg, A.Cg))) return e;
+  bytes_out[2] = (int64_t)(D.Ein.val.size() + D.Fout.val.size()) * (w + 4) + 8 * (R.p + R.q + 2);
+  bytes_out[3] = (int64_t)D.Cg.val.size() * (w + 4) + 8 * (R.q + 1);
+  return hipSuccess;
+}
+
+template <typename T>
+size_t lds_bytes(const ApplyArrays<T>& A, int kmax) {
+  return sizeof(T) * ((size_t)A.maxPB + A.maxLR + 2 * (size_t)A.maxQB + 2 * (size_t)std::max(kmax, 1));
+}
+
+pslr_status ensure_ws(pslr_ctx* h, int nrhs) {
+  if (nrhs <= h->ws_nrhs) return PSLR_OK;
+  h->ws.release();
+  const size_t q = (size_t)std::max<int64_t>(h->R.q, 1);
+  HIP_TRY(h->ws.alloc<double>(q * nrhs, (double**)&h->y));
+  HIP_TRY(h->ws.alloc<double>(q * nrhs, (double**)&h->u0));
+  HIP_TRY(h->ws.alloc<double>(q * nrhs, (double**)&h->u1));
+  HIP_TRY(h->ws.alloc<double>((size_t)h->nchunk * nrhs * std::max(h->k, 1), (double**)&h->partial));
+  h->ws_nrhs = nrhs;
+  return PSLR_OK;
+}
+
+template <typename T>
+struct LowRank;
+template <>
+struct LowRank<double> {
+  static const double* V(pslr_ctx* h) { return h->V64; }
+  static const double* G(pslr_ctx* h) { return h->G64; }
+};
+template <>
+struct LowRank<float> {
+  static const __hip_bfloat16* V(pslr_ctx* h) { return h->Vbf; }
+  static const float* G(pslr_ctx* h) { return h->G32; }
+};
+
+// z = M^{-1} b (or M^{-T} b) with apply arrays A.
+template <typename T>
+pslr_status run_apply(pslr_ctx* h, const ApplyArrays<T>& A, size_t lds, bool transpose, int nrhs,
+                      const double* b, int64_t ldb, double* z, int64_t ldz, hipStream_t s) {
+  pslr_status st = ensure_ws(h, nrhs);
+  if (st != PSLR_OK) return st;
+  const int64_t q = std::max<int64_t>(h->R.q, 1);
+  LaunchCfg cfg{h->threads, lds, s};
+  T* y = (T*)h->y;
+  T* ua = (T*)h->u0;
+  T* ub = (T*)h->u1;
+  T* part = (T*)h->partial;
+  const int k = h->k;
+  HIP_TRY(launch_head<T>(A, cfg, nrhs, b, ldb, y, q));
+  if (!transpose) {
+    if (k > 0) {
+      HIP_TRY((launch_lr_partial<T>(h->R.q, k, LowRank<T>::V(h), y, q, nrhs, h->nchunk, part, s)));
+      HIP_TRY((launch_lr_expand<T>(A, cfg, nrhs, k, LowRank<T>::V(h), LowRank<T>::G(h), 0, part,
+                                   h->nchunk, y, q, 1, ua, q)));
+    } else {
+      HIP_TRY(launch_c0solve<T>(A, cfg, nrhs, y, q, ua, q));
+    }
+    for (int i = 0; i < h->m; ++i) {
+      HIP_TRY(launch_series<T>(A, cfg, nrhs, y, q, ua, ub, q, 1, 1));
+      std::swap(ua, ub);
+    }
+  } else {
+    HIP_TRY(launch_c0solve<T>(A, cfg, nrhs, y, q, ua, q));
+    for (int i = 0; i < h->m; ++i) {
+      HIP_TRY(launch_series<T>(A, cfg, nrhs, y, q, ua, ub, q, 1, 1));
+      std::swap(ua, ub);
+    }
+    if (k > 0) {
+      HIP_TRY((launch_lr_partial<T>(h->R.q, k, LowRank<T>::V(h), ua, q, nrhs, h->nchunk, part, s)));
+      HIP_TRY((launch_lr_expand<T>(A, cfg, nrhs, k, LowRank<T>::V(h), LowRank<T>::G(h), 1, part,
+                                   h->nchunk, ua, q, 0, ub, q)));
+    }
+  }
+  HIP_TRY(launch_tail<T>(A, cfg, nrhs, b, ldb, ua, q, z, ldz));
+  return PSLR_OK;
+}
+
+pslr_status apply_dir(pslr_ctx* h, bool transpose, int nrhs, const double* b, int64_t ldb, double* z,
+                      int64_t ldz, hipStream_t s, bool force64 = false) {
+  if (h->R.n == 0) return PSLR_OK;
+  if (h->precision == 1 && !force64 && h->have32)
+    return run_apply<float>(h, transpose ? h->tr32 : h->fw32, h->lds32, transpose, nrhs, b, ldb, z,
+                            ldz, s);
+  if (!h->have64) return fail(PSLR_EINVAL, "FP64 apply arrays not available");
+  return run_apply<double>(h, transpose ? h->tr64 : h->fw64, h->lds64, transpose, nrhs, b, ldb, z,
+                           ldz, s);
+}
+
+// ---- small dense helpers (host)
+
+// G = (I - H)^{-1} - I with LU and partial pivoting; false if I - H is singular.
+bool compute_G(int k, const std::vector<double>& H, std::vector<double>& G) {
+  std::vector<double> M((size_t)k * k), X((size_t)k * k, 0.0);
+  double nrm = 0.0;
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) {
+      M[(size_t)i * k + j] = (i == j ? 1.0 : 0.0) - H[(size_t)j * k + i];  // H column-major
+      nrm = std::max(nrm, std::fabs(M[(size_t)i * k + j]));
+    }
+  for (int i = 0; i < k; ++i) X[(size_t)i * k + i] = 1.0;
+  for (int c = 0; c < k; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < k; ++r)
+      if (std::fabs(M[(size_t)r * k + c]) > std::fabs(M[(size_t)piv * k + c])) piv = r;
+    if (!(std::fabs(M[(size_t)piv * k + c]) > 1e-14 * nrm)) return false;
+    if (piv != c)
+      for (int j = 0; j < k; ++j) {
+        std::swap(M[(size_t)c * k + j], M[(size_t)piv * k + j]);
+        std::swap(X[(size_t)c * k + j], X[(size_t)piv * k + j]);
+      }
+    for (int r = 0; r < k; ++r) {
+      if (r == c) continue;
+      const double f = M[(size_t)r * k + c] / M[(size_t)c * k + c];
+      if (f == 0.0) continue;
+      for (int j = 0; j < k; ++j) {
+        M[(size_t)r * k + j] -= f * M[(size_t)c * k + j];
+        X[(size_t)r * k + j] -= f * X[(size_t)c * k + j];
+      }
+    }
+  }
+  G.assign((size_t)k * k, 0.0);  // row-major
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j)
+      G[(size_t)i * k + j] = X[(size_t)i * k + j] / M[(size_t)i * k + i] - (i == j ? 1.0 : 0.0);
+  return true;
+}
+
+// Upload V (row-major, apply precision) and G for the current hV/hH.
+pslr_status upload_lowrank(pslr_ctx* h) {
+  h->vpool.release();
+  h->V64 = h->G64 = nullptr;
+  h->Vbf = nullptr;
+  h->G32 = nullptr;
+  const int k = h->k;
+  const int64_t q = h->R.q;
+  if (k == 0) return PSLR_OK;
+  if (!compute_G(k, h->hH, h->hG)) return fail(PSLR_ESINGULAR, "I - H is singular");
+  if (h->precision == 0) {
+    std::vector<double> Vr((size_t)q * k);
+    for (int64_t r = 0; r < q; ++r)
+      for (int j = 0; j < k; ++j) Vr[(size_t)r * k + j] = h->hV[(size_t)j * q + r];
+    HIP_TRY(h->vpool.upload(Vr, &h->V64));
+    HIP_TRY(h->vpool.upload(h->hG, &h->G64));
+  } else {
+    std::vector<__hip_bfloat16> Vr((size_t)q * k);
+    for (int64_t r = 0; r < q; ++r)
+      for (int j = 0; j < k; ++j) Vr[(size_t)r * k + j] = __float2bfloat16((float)h->hV[(size_t)j * q + r]);
+    std::vector<float> G32(h->hG.begin(), h->hG.end());
+    HIP_TRY(h->vpool.upload(Vr, &h->Vbf));
+    HIP_TRY(h->vpool.upload(G32, &h->G32));
+  }
+  return PSLR_OK;
+}
+
+// Device dot products of nv vectors with w (column r of each), result on host.
+pslr_status dots(pslr_ctx* h, int64_t n, int nv, const double* V, int64_t ldv, int64_t ldvr,
+                 const double* w, int64_t ldw, int nrhs, double* dbuf, double* dout,
+                 std::vector<double>& host, hipStream_t s) {
+  HIP_TRY(launch_mdot(n, nv, V, ldv, ldvr, w, ldw, nrhs, h->nchunk, dbuf, s));
+  HIP_TRY(launch_reduce(h->nchunk, nrhs, nv, dbuf, dout, s));
+  host.resize((size_t)nrhs * nv);
+  HIP_TRY(hipMemcpyAsync(host.data(), dout, sizeof(double) * nrhs * nv, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return PSLR_OK;
+}
+
+// r_k-step Arnoldi on E_rr(m) = (E_s C0^{-1})^{m+1} (Theorem t2), classical
+// Gram-Schmidt with one full re-orthogonalisation, FP64 on the device.
+pslr_status arnoldi(pslr_ctx* h, const double* v0host, uint64_t seed, hipStream_t s, bool& breakdown) {
+  const int64_t q = h->R.q;
+  int kreq = (int)std::min<int64_t>(h->rank, q);
+  breakdown = false;
+  h->k = 0;
+  h->hV.clear();
+  h->hH.clear();
+  if (kreq <= 0) return upload_lowrank(h);
+  DevPool tmp;
+  double *Vd, *w, *ua, *ub, *dbuf, *dout, *scl;
+  HIP_TRY(tmp.alloc<double>((size_t)q * (kreq + 1), &Vd));
+  HIP_TRY(tmp.alloc<double>(q, &w));
+  HIP_TRY(tmp.alloc<double>(q, &ua));
+  HIP_TRY(tmp.alloc<double>(q, &ub));
+  HIP_TRY(tmp.alloc<double>((size_t)h->nchunk * (kreq + 1), &dbuf));
+  HIP_TRY(tmp.alloc<double>(kreq + 1, &dout));
+  HIP_TRY(tmp.alloc<double>(1, &scl));
+  std::vector<double> v(q);
+  if (v0host) {
+    std::copy(v0host, v0host + q, v.begin());
+  } else {
+    uint64_t st = seed;
+    for (int64_t i = 0; i < q; ++i) v[i] = (double)(splitmix64_next(st) >> 11) * 0x1.0p-53 - 0.5;
+  }
+  double nv = 0.0;
+  for (double x : v) nv += x * x;
+  nv = std::sqrt(nv);
+  if (!(nv > 0.0)) return fail(PSLR_EINVAL, "Arnoldi start vector is zero");
+  for (double& x : v) x /= nv;
+  HIP_TRY(hipMemcpy(Vd, v.data(), sizeof(double) * q, hipMemcpyHostToDevice));
+  const ApplyArrays<double>& A = h->fw64;
+  LaunchCfg cfg{h->threads, h->lds64, s};
+  std::vector<double> Hb((size_t)(kreq + 1) * kreq, 0.0), hv, hv2, nn;
+  int kdone = kreq;
+  for (int j = 0; j < kreq; ++j) {
+    const double* cur = Vd + (size_t)j * q;
+    for (int r = 0; r <= h->m; ++r) {
+      HIP_TRY(launch_c0solve<double>(A, cfg, 1, cur, q, ua, q));
+      HIP_TRY(launch_series<double>(A, cfg, 1, ua, q, ua, ub, q, 0, 0));
+      cur = ub;
+    }
+    // cur == ub holds E_rr v_j
+    HIP_TRY(hipMemcpyAsync(w, cur, sizeof(double) * q, hipMemcpyDeviceToDevice, s));
+    pslr_status st = dots(h, q, 1, w, q, 0, w, q, 1, dbuf, dout, nn, s);
+    if (st) return st;
+    const double wnorm = std::sqrt(nn[0]);
+    st = dots(h, q, j + 1, Vd, q, 0, w, q, 1, dbuf, dout, hv, s);
+    if (st) return st;
+    HIP_TRY(hipMemcpyAsync(dout, hv.data(), sizeof(double) * (j + 1), hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_maxpy(q, j + 1, Vd, q, 0, dout, j + 1, w, q, 1, 1.0, s));
+    st = dots(h, q, j + 1, Vd, q, 0, w, q, 1, dbuf, dout, hv2, s);
+    if (st) return st;
+    HIP_TRY(launch_maxpy(q, j + 1, Vd, q, 0, dout, j + 1, w, q, 1, 1.0, s));
+    for (int i = 0; i <= j; ++i) Hb[(size_t)j * (kreq + 1) + i] = hv[i] + hv2[i];
+    st = dots(h, q, 1, w, q, 0, w, q, 1, dbuf, dout, nn, s);
+    if (st) return st;
+    const double hn = std::sqrt(nn[0]);
+    Hb[(size_t)j * (kreq + 1) + j + 1] = hn;
+    if (hn <= 1e-14 * wnorm) {
+      kdone = j + 1;
+      breakdown = kdone < kreq;
+      break;
+    }
+    const double inv = 1.0 / hn;
+    HIP_TRY(hipMemcpyAsync(scl, &inv, sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_scale(q, w, q, scl, Vd + (size_t)(j + 1) * q, q, 1, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  h->k = kdone;
+  h->hV.resize((size_t)q * kdone);
+  HIP_TRY(hipMemcpy(h->hV.data(), Vd, sizeof(double) * q * kdone, hipMemcpyDeviceToHost));
+  h->hH.assign((size_t)kdone * kdone, 0.0);
+  for (int j = 0; j < kdone; ++j)
+    for (int i = 0; i < kdone; ++i) h->hH[(size_t)j * kdone + i] = Hb[(size_t)j * (kreq + 1) + i];
+  return upload_lowrank(h);
+}
+
+void fill_info(pslr_ctx* h, const std::vector<BlockFactor>& fB, const std::vector<BlockFactor>& fC,
+               const Blocks& Bk, const int64_t bytes[4]) {
+  pslr_info_t& I = h->info;
+  I.n = h->R.n;
+  I.p = h->R.p;
+  I.q = h->R.q;
+  I.nparts = h->R.nparts;
+  I.m = h->m;
+  I.rank = h->k;
+  I.precision = h->precision;
+  I.nnz_A = h->nnzA;
+  I.nnz_E = I.nnz_F = 0;
+  for (auto& E : Bk.E) I.nnz_E += E.nnz();
+  for (auto& F : Bk.F) I.nnz_F += F.nnz();
+  I.nnz_Cg = (int64_t)Bk.Cg.col.size();
+  I.nnz_LU_B = I.nnz_LU_C0 = 0;
+  I.supernodes_B = I.supernodes_C0 = 0;
+  I.max_levels_B = I.max_levels_C0 = 0;
+  for (auto& f : fB) {
+    I.nnz_LU_B += f.nnz_L + f.nnz_U;
+    I.supernodes_B += f.nsuper;
+    I.max_levels_B = std::max(I.max_levels_B, f.lo.nlev);
+  }
+  for (auto& f : fC) {
+    I.nnz_LU_C0 += f.nnz_L + f.nnz_U;
+    I.supernodes_C0 += f.nsuper;
+    I.max_levels_C0 = std::max(I.max_levels_C0, f.lo.nlev);
+  }
+  const double nA = std::max<int64_t>(h->nnzA, 1);
+  I.fill_lu = (double)(I.nnz_LU_B + I.nnz_LU_C0) / nA;
+  I.fill_lowrank = ((double)h->R.q * h->k + (double)h->k * h->k) / nA;
+  I.fill_total = I.fill_lu + I.fill_lowrank;
+  // algorithmic bytes: factor/matrix data once per use, vectors once per read/write
+  const int w = h->precision == 1 ? 4 : 8;
+  const int wv = h->precision == 1 ? 2 : 8;
+  const int m = h->m;
+  const int64_t p = h->R.p, q = h->R.q, n = h->R.n, k = h->k;
+  const int64_t bB = bytes[0], bC = bytes[1], bEF = bytes[2], bCg = bytes[3];
+  const int64_t vecB = (int64_t)w * 2 * p, vecC = (int64_t)w * 2 * q;  // one gather in, one scatter out
+  const int64_t series = bB + bC + bEF + bCg + vecB + vecC + (int64_t)w * 3 * q + 8 * 2 * q;
+  I.series_bytes = series;
+  const int64_t matrix = (m + 2) * bB + (m + 1) * bC + (m + 1) * bEF + m * bCg + 2 * q * k * wv +
+                         k * k * w;
+  const int64_t vectors = (int64_t)(m + 2) * vecB + (m + 1) * vecC + (int64_t)w * (2 * m + 3) * q +
+                          (int64_t)(8 + w) * n * 2;
+  I.apply_bytes = matrix + vectors;
+  I.apply_bytes_rhs = vectors;
+}
+
+}  // namespace
+
+// =========================================================================
+// C ABI
+// =========================================================================
+
+extern "C" {
+
+void pslr_default_options(pslr_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->m = 3;
+  o->rank = 16;
+  o->precision = 0;
+  o->want_transpose = 0;
+  o->v0 = nullptr;
+  o->seed = 1;
+  o->pivot_threshold = 0.1;
+  o->nthreads = 0;
+}
+
+const char* pslr_status_string(pslr_status s) {
+  switch (s) {
+    case PSLR_OK: return "PSLR_OK";
+    case PSLR_EINVAL: return "PSLR_EINVAL";
+    case PSLR_ESINGULAR: return "PSLR_ESINGULAR";
+    case PSLR_ENOCONV: return "PSLR_ENOCONV";
+    case PSLR_EBREAKDOWN: return "PSLR_EBREAKDOWN";
+    case PSLR_ENOMEM: return "PSLR_ENOMEM";
+    case PSLR_EHIP: return "PSLR_EHIP";
+    case PSLR_ENOTSUP: return "PSLR_ENOTSUP";
+  }
+  return "PSLR_UNKNOWN";
+}
+
+const char* pslr_last_error(void) { return g_last_error.c_str(); }
+
+pslr_status pslr_partition_geometric(int32_t ndim, const int32_t* dims, const int32_t* parts,
+                                     int32_t* label) {
+  if (ndim < 1 || ndim > 3 || !dims || !parts || !label) return fail(PSLR_EINVAL, "bad arguments");
+  int64_t n = 1;
+  for (int d = 0; d < ndim; ++d) {
+    if (dims[d] <= 0 || parts[d] <= 0 || parts[d] > dims[d]) return fail(PSLR_EINVAL, "bad dims/parts");
+    n *= dims[d];
+  }
+  for (int64_t v = 0; v < n; ++v) {
+    int64_t rem = v, mult = 1, lab = 0;
+    for (int d = 0; d < ndim; ++d) {
+      const int64_t i = rem % dims[d];
+      rem /= dims[d];
+      lab += mult * ((i * parts[d]) / dims[d]);
+      mult *= parts[d];
+    }
+    label[v] = (int32_t)lab;
+  }
+  return PSLR_OK;
+}
+
+pslr_status pslr_partition_region_growing(int64_t n, const int64_t* rowptr, const int32_t* colind,
+                                          int32_t nparts, uint64_t seed, int32_t* label,
+                                          int32_t* nlabels) {
+  pslr_status st = validate_csr(n, rowptr, colind);
+  if (st) return st;
+  if (nparts <= 0 || !label) return fail(PSLR_EINVAL, "bad nparts/label");
+  std::vector<int64_t> sp;
+  std::vector<int32_t> si;
+  symmetric_pattern(n, rowptr, colind, sp, si);
+  std::fill(label, label + n, -1);
+  std::vector<int64_t> queue;
+  queue.reserve(n);
+  uint64_t state = seed;
+  int32_t next = 0;
+  const int32_t want = (int32_t)std::min<int64_t>(nparts, n);
+  while (next < want) {
+    const int64_t v = (int64_t)(splitmix64_next(state) % (uint64_t)n);
+    if (label[v] >= 0) continue;
+    label[v] = next++;
+    queue.push_back(v);
+  }
+  auto grow = [&](size_t head) {
+    while (head < queue.size()) {
+      const int64_t v = queue[head++];
+      for (int64_t k = sp[v]; k < sp[v + 1]; ++k) {
+        const int32_t w = si[k];
+        if (label[w] < 0) {
+          label[w] = label[v];
+          queue.push_back(w);
+        }
+      }
+    }
+  };
+  grow(0);
+  for (int64_t v = 0; v < n; ++v)
+    if (label[v] < 0) {
+      label[v] = next++;
+      const size_t h0 = queue.size();
+      queue.push_back(v);
+      grow(h0);
+    }
+  if (nlabels) *nlabels = next;
+  return PSLR_OK;
+}
+
+pslr_status pslr_reorder(int64_t n, const int64_t* rowptr, const int32_t* colind,
+                         const int32_t* part, int32_t nparts, int64_t* perm, int64_t* p, int64_t* q) {
+  pslr_status st = validate_csr(n, rowptr, colind);
+  if (st) return st;
+  if ((st = validate_part(n, part, nparts))) return st;
+  Reordering R = reorder(n, rowptr, colind, part, nparts);
+  if (perm) std::copy(R.perm.begin(), R.perm.end(), perm);
+  if (p) *p = R.p;
+  if (q) *q = R.q;
+  return PSLR_OK;
+}
+
+pslr_status pslr_host_selfcheck(int64_t n, const int64_t* rowptr, const int32_t* colind,
+                                const double* vals, const int32_t* part, int32_t nparts,
+                                const pslr_options* opt, double* factor_residual,
+                                double* solve_residual) {
+  pslr_status st = validate_csr(n, rowptr, colind);
+  if (st) return st;
+  if ((st = validate_part(n, part, nparts))) return st;
+  pslr_options o;
+  pslr_default_options(&o);
+  if (opt) o = *opt;
+  const double tau = o.pivot_threshold > 0 ? o.pivot_threshold : 0.1;
+  Reordering R = reorder(n, rowptr, colind, part, nparts);
+  Blocks Bk = extract_blocks(n, rowptr, colind, vals, R);
+  std::vector<const CsrL*> mats;
+  for (auto& b : Bk.B) mats.push_back(&b);
+  for (auto& c : Bk.C0) mats.push_back(&c);
+  std::vector<double> fres(mats.size(), 0.0), sres(mats.size(), 0.0);
+  std::vector<std::string> errs(mats.size());
+  std::vector<int> codes(mats.size(), 0);
+  parallel_for((int)mats.size(), o.nthreads, [&](int t) {
+    const CsrL& M = *mats[t];
+    BlockFactor f;
+    codes[t] = factor_block(M, tau, o.want_transpose != 0, f, errs[t]);
+    if (codes[t] || M.nrows == 0) return;
+    const int nb = M.nrows;
+    // residual of the solve layouts: x = M^{-1} b with b = M * xe
+    for (int tr = 0; tr < (o.want_transpose ? 2 : 1); ++tr) {
+      std::vector<double> xe(nb), bb(nb, 0.0), X(nb), x(nb);
+      for (int i = 0; i < nb; ++i) xe[i] = std::sin(1.0 + i);
+      for (int i = 0; i < nb; ++i)
+        for (int k = M.ptr[i]; k < M.ptr[i + 1]; ++k) {
+          if (!tr) bb[i] += M.val[k] * xe[M.col[k]];
+          else bb[M.col[k]] += M.val[k] * xe[i];
+        }
+      const std::vector<int32_t>& gi = tr ? f.gout : f.gin;
+      const std::vector<int32_t>& go = tr ? f.gin : f.gout;
+      for (int pp = 0; pp < nb; ++pp) X[pp] = bb[gi[pp]];
+      host_tri_solve(tr ? f.loT : f.lo, X);
+      host_tri_solve(tr ? f.upT : f.up, X);
+      for (int c = 0; c < nb; ++c) x[go[c]] = X[c];
+      double e2 = 0.0, n2 = 0.0;
+      for (int i = 0; i < nb; ++i) {
+        e2 += (x[i] - xe[i]) * (x[i] - xe[i]);
+        n2 += xe[i] * xe[i];
+      }
+      sres[t] = std::max(sres[t], std::sqrt(e2 / n2));
+    }
+    // factorisation residual ||P Q M Q^T - L U||_F / ||M||_F through M x for unit vectors is
+    // expensive; instead report || M x - b || / (||M|| ||x||) on a second vector
+    std::vector<double> xe(nb), bb(nb, 0.0), X(nb), x(nb), rr(nb, 0.0);
+    for (int i = 0; i < nb; ++i) bb[i] = std::cos(0.5 + 0.37 * i);
+    for (int pp = 0; pp < nb; ++pp) X[pp] = bb[f.gin[pp]];
+    host_tri_solve(f.lo, X);
+    host_tri_solve(f.up, X);
+    for (int c = 0; c < nb; ++c) x[f.gout[c]] = X[c];
+    double mnorm = 0.0, xn = 0.0, rn = 0.0;
+    for (int i = 0; i < nb; ++i) {
+      double rs = 0.0;
+      for (int k = M.ptr[i]; k < M.ptr[i + 1]; ++k) {
+        rr[i] += M.val[k] * x[M.col[k]];
+        rs += std::fabs(M.val[k]);
+      }
+      mnorm = std::max(mnorm, rs);
+      xn = std::max(xn, std::fabs(x[i]));
+      rn = std::max(rn, std::fabs(rr[i] - bb[i]));
+    }
+    fres[t] = rn / (mnorm * xn);
+  });
+  for (size_t t = 0; t < mats.size(); ++t)
+    if (codes[t]) return fail(PSLR_ESINGULAR, errs[t]);
+  if (factor_residual) *factor_residual = *std::max_element(fres.begin(), fres.end());
+  if (solve_residual) *solve_residual = *std::max_element(sres.begin(), sres.end());
+  return PSLR_OK;
+}
+
+pslr_status pslr_setup(int64_t n, const int64_t* rowptr, const int32_t* colind, const double* vals,
+                       const int32_t* part, int32_t nparts, const pslr_options* opt,
+                       void* hip_stream, pslr_handle* out) {
+  if (!out) return fail(PSLR_EINVAL, "out is NULL");
+  *out = nullptr;
+  pslr_status st = validate_csr(n, rowptr, colind);
+  if (st) return st;
+  if ((st = validate_part(n, part, nparts))) return st;
+  if (n > 0 && !vals) return fail(PSLR_EINVAL, "vals is NULL");
+  pslr_options o;
+  pslr_default_options(&o);
+  if (opt) o = *opt;
+  if (o.m < 0) return fail(PSLR_EINVAL, "m < 0");
+  if (o.rank < 0) return fail(PSLR_EINVAL, "rank < 0");
+  if (o.precision != 0 && o.precision != 1) return fail(PSLR_EINVAL, "precision must be 0 or 1");
+  const double tau = o.pivot_threshold > 0 ? o.pivot_threshold : 0.1;
+  for (int64_t k = 0; k < (n > 0 ? rowptr[n] : 0); ++k)
+    if (!std::isfinite(vals[k])) return fail(PSLR_EINVAL, "non-finite value in A");
+  hipStream_t s = (hipStream_t)hip_stream;
+  std::unique_ptr<pslr_ctx> h(new pslr_ctx());
+  HIP_TRY(hipGetDevice(&h->device));
+  h->m = o.m;
+  h->rank = std::min(o.rank, 256);
+  h->precision = o.precision;
+  h->want_T = o.want_transpose ? 1 : 0;
+  h->nnzA = n > 0 ? rowptr[n] : 0;
+  const double t0 = now_s();
+  h->R = reorder(n, rowptr, colind, part, nparts);
+  Blocks Bk = extract_blocks(n, rowptr, colind, vals, h->R);
+  const double t1 = now_s();
+  const int np = nparts;
+  std::vector<BlockFactor> fB(np), fC(np);
+  std::vector<std::string> errs(2 * np);
+  std::vector<int> codes(2 * np, 0);
+  parallel_for(2 * np, o.nthreads, [&](int t) {
+    if (t < np) codes[t] = factor_block(Bk.B[t], tau, h->want_T != 0, fB[t], errs[t]);
+    else codes[t] = factor_block(Bk.C0[t - np], tau, h->want_T != 0, fC[t - np], errs[t]);
+  });
+  for (int t = 0; t < 2 * np; ++t)
+    if (codes[t]) return fail(PSLR_ESINGULAR, std::string(t < np ? "B_" : "C_") +
+                                                  std::to_string(t % np) + ": " + errs[t]);
+  const double t2 = now_s();
+
+  // device copies of A (and A^T)
+  {
+    std::vector<int64_t> ptr(rowptr, rowptr + n + 1);
+    std::vector<int32_t> col(colind, colind + h->nnzA);
+    std::vector<double> val(vals, vals + h->nnzA);
+    HIP_TRY(h->pool.upload(ptr, &h->A_ptr));
+    HIP_TRY(h->pool.upload(col, &h->A_col));
+    HIP_TRY(h->pool.upload(val, &h->A_val));
+    if (h->want_T) {
+      std::vector<int64_t> tp(n + 1, 0);
+      for (int32_t c : col) tp[c + 1]++;
+      for (int64_t i = 0; i < n; ++i) tp[i + 1] += tp[i];
+      std::vector<int32_t> tc(col.size());
+      std::vector<double> tv(col.size());
+      std::vector<int64_t> pos(tp.begin(), tp.end() - 1);
+      for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) {
+          int64_t d = pos[col[k]]++;
+          tc[d] = (int32_t)i;
+          tv[d] = val[k];
+        }
+      HIP_TRY(h->pool.upload(tp, &h->AT_ptr));
+      HIP_TRY(h->pool.upload(tc, &h->AT_col));
+      HIP_TRY(h->pool.upload(tv, &h->AT_val));
+    }
+  }
+  const int64_t *d_int_ptr, *d_if_ptr;
+  const int32_t* d_if_orig;
+  {
+    std::vector<int32_t> if_orig(h->R.q);
+    for (int64_t k = 0; k < h->R.q; ++k) if_orig[k] = (int32_t)h->R.perm[h->R.p + k];
+    HIP_TRY(h->pool.upload(h->R.int_ptr, &d_int_ptr));
+    HIP_TRY(h->pool.upload(h->R.if_ptr, &d_if_ptr));
+    HIP_TRY(h->pool.upload(if_orig, &d_if_orig));
+  }
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, h->device));
+  const size_t lds_max = prop.sharedMemPerBlock > 0 ? prop.sharedMemPerBlock : 65536;
+  DirHost Dfw = build_dir(h->R, Bk, fB, fC, false);
+  int64_t bytes[4] = {0, 0, 0, 0};
+  HIP_TRY(upload_dir<double>(h->pool, h->R, fB, fC, Dfw, false, d_int_ptr, d_if_ptr, d_if_orig,
+                             h->fw64, bytes));
+  h->lds64 = lds_bytes(h->fw64, h->rank);
+  if (h->lds64 > lds_max)
+    return fail(PSLR_ENOTSUP, "a subdomain needs " + std::to_string(h->lds64) +
+                                  " bytes of LDS in FP64 (limit " + std::to_string(lds_max) + ")");
+  HIP_TRY(set_lds_limit<double>(h->lds64));
+  h->have64 = true;
+
+  // Arnoldi on E_rr(m) in FP64 (Algorithm 4, lines 6-8)
+  bool breakdown = false;
+  st = arnoldi(h.get(), o.v0, o.seed, s, breakdown);
+  if (st) return st;
+  const double t3 = now_s();
+
+  if (h->precision == 1) {
+    HIP_TRY(upload_dir<float>(h->pool, h->R, fB, fC, Dfw, false, d_int_ptr, d_if_ptr, d_if_orig,
+                              h->fw32, bytes));
+    h->lds32 = lds_bytes(h->fw32, h->rank);
+    if (h->lds32 > lds_max) return fail(PSLR_ENOTSUP, "a subdomain needs too much LDS in FP32");
+    HIP_TRY(set_lds_limit<float>(h->lds32));
+    h->have32 = true;
+  }
+  if (h->want_T) {
+    DirHost Dtr = build_dir(h->R, Bk, fB, fC, true);
+    int64_t tb[4];
+    if (h->precision == 1) {
+      HIP_TRY(upload_dir<float>(h->pool, h->R, fB, fC, Dtr, true, d_int_ptr, d_if_ptr, d_if_orig,
+                                h->tr32, tb));
+      h->lds32 = std::max(h->lds32, lds_bytes(h->tr32, h->rank));
+      HIP_TRY(set_lds_limit<float>(h->lds32));
+    }
+    HIP_TRY(upload_dir<double>(h->pool, h->R, fB, fC, Dtr, true, d_int_ptr, d_if_ptr, d_if_orig,
+                               h->tr64, tb));
+    h->lds64 = std::max(h->lds64, lds_bytes(h->tr64, h->rank));
+    if (h->lds64 > lds_max) return fail(PSLR_ENOTSUP, "transposed layout needs too much LDS");
+    HIP_TRY(set_lds_limit<double>(h->lds64));
+    h->haveT = true;
+  }
+  fill_info(h.get(), fB, fC, Bk, bytes);
+  h->info.seconds_reorder = t1 - t0;
+  h->info.seconds_factor = t2 - t1;
+  h->info.seconds_arnoldi = t3 - t2;
+  HIP_TRY(hipStreamSynchronize(s));
+  *out = h.release();
+  return breakdown ? PSLR_EBREAKDOWN : PSLR_OK;
+}
+
+pslr_status pslr_apply(pslr_handle h, int32_t nrhs, const double* b, int64_t ldb, double* z,
+                       int64_t ldz, void* hip_stream) {
+  if (!h) return fail(PSLR_EINVAL, "null handle");
+  if (nrhs < 0 || (nrhs > 0 && (!b || !z)) || ldb < h->R.n || ldz < h->R.n)
+    return fail(PSLR_EINVAL, "bad vector arguments");
+  if (nrhs == 0) return PSLR_OK;
+  return apply_dir(h, false, nrhs, b, ldb, z, ldz, (hipStream_t)hip_stream);
+}
+
+pslr_status pslr_apply_transpose(pslr_handle h, int32_t nrhs, const double* b, int64_t ldb,
+                                 double* z, int64_t ldz, void* hip_stream) {
+  if (!h) return fail(PSLR_EINVAL, "null handle");
+  if (!h->haveT) return fail(PSLR_EINVAL, "handle was built without want_transpose");
+  if (nrhs < 0 || (nrhs > 0 && (!b || !z)) || ldb < h->R.n || ldz < h->R.n)
+    return fail(PSLR_EINVAL, "bad vector arguments");
+  if (nrhs == 0) return PSLR_OK;
+  return apply_dir(h, true, nrhs, b, ldb, z, ldz, (hipStream_t)hip_stream);
+}
+
+pslr_status fgmres_solve(pslr_handle h, int32_t nrhs, const double* b, int64_t ldb, double* x,
+                         int64_t ldx, int32_t restart, int32_t maxit, double tol, int32_t transpose,
+                         int32_t* iters, double* relres, void* hip_stream) {
+  if (!h) return fail(PSLR_EINVAL, "null handle");
+  if (nrhs <= 0 || !b || !x || ldb < h->R.n || ldx < h->R.n || restart <= 0 || maxit < 0 ||
+      !(tol > 0))
+    return fail(PSLR_EINVAL, "bad FGMRES arguments");
+  if (transpose && !h->haveT) return fail(PSLR_EINVAL, "handle was built without want_transpose");
+  hipStream_t s = (hipStream_t)hip_stream;
+  const int64_t n = h->R.n;
+  const int R1 = restart + 1;
+  const int64_t* Ap = transpose ? h->AT_ptr : h->A_ptr;
+  const int32_t* Ac = transpose ? h->AT_col : h->A_col;
+  const double* Av = transpose ? h->AT_val : h->A_val;
+  DevPool tmp;
+  double *Vb, *Zb, *W, *dbuf, *dout, *dh, *scl;
+  HIP_TRY(tmp.alloc<double>((size_t)n * R1 * nrhs, &Vb));
+  HIP_TRY(tmp.alloc<double>((size_t)n * restart * nrhs, &Zb));
+  HIP_TRY(tmp.alloc<double>((size_t)n * nrhs, &W));
+  HIP_TRY(tmp.alloc<double>((size_t)h->nchunk * nrhs * R1, &dbuf));
+  HIP_TRY(tmp.alloc<double>((size_t)nrhs * R1, &dout));
+  HIP_TRY(tmp.alloc<double>((size_t)nrhs * R1, &dh));
+  HIP_TRY(tmp.alloc<double>(nrhs, &scl));
+  const int64_t ldvr = (int64_t)n * R1, ldzr = (int64_t)n * restart;
+  std::vector<double> bn, nn, h1, h2;
+  pslr_status st = dots(h, n, 1, b, 0, ldb, b, ldb, nrhs, dbuf, dout, bn, s);
+  if (st) return st;
+  for (double& v : bn) v = std::sqrt(v);
+  std::vector<int> its(nrhs, 0), done(nrhs, 0);
+  std::vector<double> rel(nrhs, 0.0);
+  for (int r = 0; r < nrhs; ++r)
+    if (bn[r] == 0.0) done[r] = 1;
+  std::vector<double> Hh((size_t)nrhs * R1 * restart), cs((size_t)nrhs * restart),
+      sn((size_t)nrhs * restart), g((size_t)nrhs * R1);
+  std::vector<int> jdone(nrhs);
+  std::vector<double> yv((size_t)nrhs * restart), sc(nrhs);
+  for (;;) {
+    // r0 = b - A x into V_0 of every column
+    HIP_TRY(launch_spmv(n, Ap, Ac, Av, nrhs, x, ldx, Vb, ldvr, b, ldb, s));
+    st = dots(h, n, 1, Vb, 0, ldvr, Vb, ldvr, nrhs, dbuf, dout, nn, s);
+    if (st) return st;
+    bool any = false;
+    for (int r = 0; r < nrhs; ++r) {
+      const double beta = std::sqrt(nn[r]);
+      if (!done[r]) {
+        rel[r] = beta / bn[r];
+        if (beta <= tol * bn[r]) done[r] = 1;
+        else if (its[r] >= maxit) done[r] = 2;
+      }
+      const bool act = !done[r];
+      any = any || act;
+      sc[r] = act ? 1.0 / beta : 0.0;
+      std::fill(&g[(size_t)r * R1], &g[(size_t)r * R1] + R1, 0.0);
+      g[(size_t)r * R1] = act ? beta : 0.0;
+      jdone[r] = 0;
+    }
+    if (!any) break;
+    HIP_TRY(hipMemcpyAsync(scl, sc.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_scale(n, Vb, ldvr, scl, Vb, ldvr, nrhs, s));
+    std::vector<int> act(nrhs);
+    for (int r = 0; r < nrhs; ++r) act[r] = !done[r];
+    for (int j = 0; j < restart; ++j) {
+      double* Vj = Vb + (size_t)j * n;
+      double* Zj = Zb + (size_t)j * n;
+      st = apply_dir(h, transpose != 0, nrhs, Vj, ldvr, Zj, ldzr, s);
+      if (st) return st;
+      HIP_TRY(launch_spmv(n, Ap, Ac, Av, nrhs, Zj, ldzr, W, n, nullptr, 0, s));
+      // classical Gram-Schmidt, two passes
+      st = dots(h, n, j + 1, Vb, n, ldvr, W, n, nrhs, dbuf, dout, h1, s);
+      if (st) return st;
+      HIP_TRY(launch_maxpy(n, j + 1, Vb, n, ldvr, dout, j + 1, W, n, nrhs, 1.0, s));
+      st = dots(h, n, j + 1, Vb, n, ldvr, W, n, nrhs, dbuf, dout, h2, s);
+      if (st) return st;
+      HIP_TRY(launch_maxpy(n, j + 1, Vb, n, ldvr, dout, j + 1, W, n, nrhs, 1.0, s));
+      st = dots(h, n, 1, W, 0, n, W, n, nrhs, dbuf, dout, nn, s);
+      if (st) return st;
+      bool cont = false;
+      for (int r = 0; r < nrhs; ++r) {
+        if (!act[r]) {
+          sc[r] = 0.0;
+          continue;
+        }
+        double* Hc = &Hh[((size_t)r * restart + j) * R1];
+        for (int i = 0; i <= j; ++i) Hc[i] = h1[(size_t)r * (j + 1) + i] + h2[(size_t)r * (j + 1) + i];
+        const double hn = std::sqrt(nn[r]);
+        Hc[j + 1] = hn;
+        sc[r] = hn > 0 ? 1.0 / hn : 0.0;
+        double* c_ = &cs[(size_t)r * restart];
+        double* s_ = &sn[(size_t)r * restart];
+        double* g_ = &g[(size_t)r * R1];
+        for (int i = 0; i < j; ++i) {
+          const double t = c_[i] * Hc[i] + s_[i] * Hc[i + 1];
+          Hc[i + 1] = -s_[i] * Hc[i] + c_[i] * Hc[i + 1];
+          Hc[i] = t;
+        }
+        const double d = std::hypot(Hc[j], Hc[j + 1]);
+        c_[j] = d > 0 ? Hc[j] / d : 1.0;
+        s_[j] = d > 0 ? Hc[j + 1] / d : 0.0;
+        Hc[j] = d;
+        Hc[j + 1] = 0.0;
+        g_[j + 1] = -s_[j] * g_[j];
+        g_[j] = c_[j] * g_[j];
+        its[r]++;
+        jdone[r] = j + 1;
+        if (std::fabs(g_[j + 1]) <= tol * bn[r] || its[r] >= maxit || hn == 0.0) act[r] = 0;
+        else cont = true;
+      }
+      if (!cont) break;
+      HIP_TRY(hipMemcpyAsync(scl, sc.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, s));
+      HIP_TRY(launch_scale(n, W, n, scl, Vb + (size_t)(j + 1) * n, ldvr, nrhs, s));
+    }
+    // x += Z y
+    std::fill(yv.begin(), yv.end(), 0.0);
+    for (int r = 0; r < nrhs; ++r) {
+      const int jd = jdone[r];
+      double* y = &yv[(size_t)r * restart];
+      for (int i = jd - 1; i >= 0; --i) {
+        double acc = g[(size_t)r * R1 + i];
+        for (int c = i + 1; c < jd; ++c) acc -= Hh[((size_t)r * restart + c) * R1 + i] * y[c];
+        y[i] = acc / Hh[((size_t)r * restart + i) * R1 + i];
+      }
+    }
+    int jmax = 0;
+    for (int r = 0; r < nrhs; ++r) jmax = std::max(jmax, jdone[r]);
+    HIP_TRY(hipMemcpyAsync(dh, yv.data(), sizeof(double) * nrhs * restart, hipMemcpyHostToDevice, s));
+    if (jmax > 0) HIP_TRY(launch_maxpy(n, jmax, Zb, n, ldzr, dh, restart, x, ldx, nrhs, -1.0, s));
+  }
+  for (int r = 0; r < nrhs; ++r) {
+    if (iters) iters[r] = its[r];
+    if (relres) relres[r] = rel[r];
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int r = 0; r < nrhs; ++r)
+    if (done[r] != 1) return fail(PSLR_ENOCONV, "FGMRES did not converge within maxit");
+  return PSLR_OK;
+}
+
+pslr_status pslr_sddmm_grad(pslr_handle h, int32_t nrhs, const double* lambda, int64_t ldl,
+                            const double* z, int64_t ldz, double* grad, void* hip_stream) {
+  if (!h) return fail(PSLR_EINVAL, "null handle");
+  if (nrhs <= 0 || !lambda || !z || !grad || ldl < h->R.n || ldz < h->R.n)
+    return fail(PSLR_EINVAL, "bad SDDMM arguments");
+  HIP_TRY(launch_sddmm(h->R.n, h->A_ptr, h->A_col, nrhs, lambda, ldl, z, ldz, grad,
+                       (hipStream_t)hip_stream));
+  return PSLR_OK;
+}
+
+pslr_status pslr_info(pslr_handle h, pslr_info_t* out) {
+  if (!h || !out) return fail(PSLR_EINVAL, "null argument");
+  *out = h->info;
+  out->rank = h->k;
+  return PSLR_OK;
+}
+
+pslr_status pslr_set_lowrank(pslr_handle h, int32_t k, const double* V, int64_t ldv,
+                             const double* H, int64_t ldh) {
+  if (!h || k < 0 || k > 256 || k > h->R.q || (k > 0 && (!V || !H || ldv < h->R.q || ldh < k)))
+    return fail(PSLR_EINVAL, "bad low-rank arguments");
+  if (k > h->rank && h->ws_nrhs > 0) {
+    h->ws.release();
+    h->ws_nrhs = 0;
+  }
+  const int64_t q = h->R.q;
+  h->k = k;
+  h->hV.assign((size_t)q * k, 0.0);
+  h->hH.assign((size_t)k * k, 0.0);
+  for (int j = 0; j < k; ++j) {
+    for (int64_t r = 0; r < q; ++r) h->hV[(size_t)j * q + r] = V[(size_t)j * ldv + r];
+    for (int i = 0; i < k; ++i) h->hH[(size_t)j * k + i] = H[(size_t)j * ldh + i];
+  }
+  if (k > h->rank) {  // LDS for W/Z scratch grows with k
+    h->rank = k;
+    if (h->have64) {
+      h->lds64 = std::max(h->lds64, lds_bytes(h->fw64, k));
+      HIP_TRY(set_lds_limit<double>(h->lds64));
+    }
+    if (h->have32) {
+      h->lds32 = std::max(h->lds32, lds_bytes(h->fw32, k));
+      HIP_TRY(set_lds_limit<float>(h->lds32));
+    }
+  }
+  if (h->ws_nrhs > 0) {  // partial buffer is sized by k
+    h->ws.release();
+    h->ws_nrhs = 0;
+  }
+  pslr_status st = upload_lowrank(h);
+  h->info.rank = h->k;
+  return st;
+}
+
+pslr_status pslr_get_lowrank(pslr_handle h, int32_t* k, double* V, int64_t ldv, double* H,
+                             int64_t ldh) {
+  if (!h || !k) return fail(PSLR_EINVAL, "null argument");
+  *k = h->k;
+  const int64_t q = h->R.q;
+  if (V)
+    for (int j = 0; j < h->k; ++j)
+      for (int64_t r = 0; r < q; ++r) V[(size_t)j * ldv + r] = h->hV[(size_t)j * q + r];
+  if (H)
+    for (int j = 0; j < h->k; ++j)
+      for (int i = 0; i < h->k; ++i) H[(size_t)j * ldh + i] = h->hH[(size_t)j * h->k + i];
+  return PSLR_OK;
+}
+
+pslr_status pslr_destroy(pslr_handle h) {
+  delete h;
+  return PSLR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,123 @@
+// Device layouts of the PSLR preconditioner and the launchers of its HIP
+// kernels (gfx950).  All offsets stored in these arrays are absolute indices
+// into the concatenated per-family arrays.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <cstdint>
+
+namespace pslr {
+
+// Supernode of a packed triangular factor (mirrors the host SnHost layout).
+struct DevSn {
+  int32_t f, w, h, pad;
+  int64_t tri_off, panel_off, ridx_off;
+};
+
+// Per-block descriptor of one packed triangular factor.
+struct DevTriBlock {
+  int32_t n, nlev, max_lrows, lower;
+  int64_t lev_base;   // lev_ptr[lev_base .. +nlev], lev_g[lev_base .. +nlev)
+  int64_t row_base;   // lrows / row_sn [row_base .. +n)
+  int64_t rp_base;    // rp[rp_base .. +n] (lower factors)
+  int64_t sn_base;    // sn[sn_base + s]
+};
+
+// One family of packed triangular factors (e.g. "L of every B_i").
+template <typename T>
+struct TriArrays {
+  const DevTriBlock* blk;
+  const int32_t* lev_ptr;
+  const int32_t* lev_g;
+  const int32_t* lrows;
+  const int32_t* row_sn;
+  const DevSn* sn;
+  const int64_t* rp;
+  const int32_t* col;
+  const T* val;
+  const int32_t* ridx;
+  const T* tri;
+};
+
+// Block-diagonal CSR over all subdomains with 64-bit row offsets.
+template <typename T>
+struct DevCsr {
+  const int64_t* ptr;
+  const int32_t* col;
+  const T* val;
+};
+
+// Everything one direction (forward or transposed) of the apply needs.
+template <typename T>
+struct ApplyArrays {
+  int32_t nparts;
+  int64_t n, p, q;
+  const int64_t* int_ptr;     // nparts + 1
+  const int64_t* if_ptr;      // nparts + 1
+  TriArrays<T> LB, UB, LC, UC;
+  const int32_t* gB_in;       // p: original index feeding B-solve input position
+  const int32_t* gB_out;      // p: original index receiving B-solve output position
+  const int32_t* gC_in;       // q: local interface index feeding C0-solve input position
+  const int32_t* gC_out;      // q: local interface index receiving C0-solve output position
+  const int32_t* gC_inv;      // q: inverse of gC_in (local)
+  const int32_t* if_orig;     // q: original index of interface unknown k
+  DevCsr<T> Ein;              // rows = B-solve input positions, cols = local interface
+  DevCsr<T> Fout;             // rows = global interface, cols = B-solve output positions
+  DevCsr<T> Cg;               // rows/cols = global interface
+  int32_t maxPB, maxQB, maxLR;
+};
+
+struct LaunchCfg {
+  int threads;
+  size_t lds;
+  hipStream_t stream;
+};
+
+// ---- preconditioner kernels (T = double or float; TV = V's storage type)
+template <typename T>
+hipError_t launch_head(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, const double* b,
+                       int64_t ldb, T* y, int64_t ldy);
+template <typename T, typename TV>
+hipError_t launch_lr_partial(int64_t q, int k, const TV* V, const T* y, int64_t ldy, int nrhs,
+                             int nchunk, T* partial, hipStream_t s);
+template <typename T, typename TV>
+hipError_t launch_lr_expand(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, int k,
+                            const TV* V, const T* G, int gtrans, const T* partial, int nchunk,
+                            T* y, int64_t ldy, int do_c0, T* u, int64_t ldu);
+template <typename T>
+hipError_t launch_c0solve(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, const T* src,
+                          int64_t lds_, T* dst, int64_t ldd);
+template <typename T>
+hipError_t launch_series(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, const T* y,
+                         int64_t ldy, const T* uprev, T* unext, int64_t ldu, int add_y, int do_c0);
+template <typename T>
+hipError_t launch_tail(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, const double* b,
+                       int64_t ldb, const T* u, int64_t ldu, double* z, int64_t ldz);
+template <typename T>
+hipError_t set_lds_limit(size_t bytes);
+
+// ---- FP64 vector kernels for Arnoldi and FGMRES
+hipError_t launch_spmv(int64_t n, const int64_t* ptr, const int32_t* col, const double* val,
+                       int nrhs, const double* x, int64_t ldx, double* y, int64_t ldy,
+                       const double* bsub, int64_t ldb, hipStream_t s);
+// partial[chunk][r][i] = sum over rows of chunk of V_i[row] * w_r[row], i < nv
+// V_i of column r at V + r*ldvr + i*ldv
+hipError_t launch_mdot(int64_t n, int nv, const double* V, int64_t ldv, int64_t ldvr,
+                       const double* w, int64_t ldw, int nrhs, int nchunk, double* partial,
+                       hipStream_t s);
+// out[r][i] = sum_chunk partial[chunk][r][i]
+hipError_t launch_reduce(int nchunk, int nrhs, int nv, const double* partial, double* out,
+                         hipStream_t s);
+// w_r -= sum_i h[r][i] V_i   (h row stride hld)
+hipError_t launch_maxpy(int64_t n, int nv, const double* V, int64_t ldv, int64_t ldvr,
+                        const double* h, int hld, double* w, int64_t ldw, int nrhs, double sign,
+                        hipStream_t s);
+// v_r = w_r * scale[r] (scale on device)
+hipError_t launch_scale(int64_t n, const double* w, int64_t ldw, const double* scale, double* v,
+                        int64_t ldv, int nrhs, hipStream_t s);
+hipError_t launch_copy_cast_to_f32(int64_t count, const double* src, float* dst, hipStream_t s);
+hipError_t launch_sddmm(int64_t n, const int64_t* ptr, const int32_t* col, int nrhs,
+                        const double* lam, int64_t ldl, const double* z, int64_t ldz,
+                        double* grad, hipStream_t s);
+
+}  // namespace pslr

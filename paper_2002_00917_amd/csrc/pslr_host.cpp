@@ -1,0 +1,846 @@
+// Host-side setup of the PSLR preconditioner (paper Sec. 2 and Algorithm 4).
+//
+// * reorder(): interface detection and the interiors-first permutation of
+//   Sec. 2 (eq. resystem).
+// * extract_blocks(): B_i, E_i, F_i, C_i and the inter-subdomain coupling C_g
+//   (Sec. 3.1, eq. matrixS and the proof of Lemma l2).
+// * factor_block(): exact sparse LU of one diagonal block (Algorithm 4 builds
+//   ILU factors; exact LU is used here).  Nested-dissection ordering by
+//   recursive BFS level-set bisection, elimination tree, fundamental
+//   supernodes, multifrontal numeric factorisation with threshold partial
+//   pivoting restricted to each front's fully-summed rows, then packing into
+//   the level-scheduled layouts read by the device triangular solves: the
+//   dense diagonal triangle of every supernode is stored inverted, so each
+//   level of the solve is two parallel dot-product sweeps.
+#include "pslr_host.h"
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <thread>
+
+namespace pslr {
+
+uint64_t splitmix64_next(uint64_t& state) {
+  state += 0x9E3779B97F4A7C15ull;
+  uint64_t z = state;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+void parallel_for(int count, int nthreads, const std::function<void(int)>& fn) {
+  if (nthreads <= 0) nthreads = (int)std::max(1u, std::thread::hardware_concurrency());
+  nthreads = std::min(nthreads, std::max(count, 1));
+  if (nthreads <= 1) {
+    for (int i = 0; i < count; ++i) fn(i);
+    return;
+  }
+  std::atomic<int> next(0);
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nthreads; ++t)
+    pool.emplace_back([&]() {
+      for (int i = next++; i < count; i = next++) fn(i);
+    });
+  for (auto& th : pool) th.join();
+}
+
+// ---------------------------------------------------------------------------
+// Reordering (Sec. 2)
+// ---------------------------------------------------------------------------
+
+void symmetric_pattern(int64_t n, const int64_t* rowptr, const int32_t* colind,
+                       std::vector<int64_t>& sptr, std::vector<int32_t>& sidx) {
+  std::vector<int64_t> cnt(n + 1, 0);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+      int64_t j = colind[k];
+      if (j == i) continue;
+      cnt[i + 1]++;
+      cnt[j + 1]++;
+    }
+  for (int64_t i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
+  std::vector<int32_t> tmp(cnt[n]);
+  std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+      int64_t j = colind[k];
+      if (j == i) continue;
+      tmp[pos[i]++] = (int32_t)j;
+      tmp[pos[j]++] = (int32_t)i;
+    }
+  sptr.assign(n + 1, 0);
+  sidx.clear();
+  sidx.reserve(tmp.size());
+  for (int64_t i = 0; i < n; ++i) {
+    auto b = tmp.begin() + cnt[i], e = tmp.begin() + cnt[i + 1];
+    std::sort(b, e);
+    auto u = std::unique(b, e);
+    sidx.insert(sidx.end(), b, u);
+    sptr[i + 1] = (int64_t)sidx.size();
+  }
+}
+
+Reordering reorder(int64_t n, const int64_t* rowptr, const int32_t* colind, const int32_t* part,
+                   int32_t nparts) {
+  Reordering R;
+  R.n = n;
+  R.nparts = nparts;
+  std::vector<int64_t> sptr;
+  std::vector<int32_t> sidx;
+  symmetric_pattern(n, rowptr, colind, sptr, sidx);
+  std::vector<char> iface(n, 0);
+  for (int64_t v = 0; v < n; ++v)
+    for (int64_t k = sptr[v]; k < sptr[v + 1]; ++k)
+      if (part[sidx[k]] != part[v]) {
+        iface[v] = 1;
+        break;
+      }
+  std::vector<int64_t> nint(nparts, 0), nif(nparts, 0);
+  for (int64_t v = 0; v < n; ++v) (iface[v] ? nif : nint)[part[v]]++;
+  R.int_ptr.assign(nparts + 1, 0);
+  R.if_ptr.assign(nparts + 1, 0);
+  for (int i = 0; i < nparts; ++i) {
+    R.int_ptr[i + 1] = R.int_ptr[i] + nint[i];
+    R.if_ptr[i + 1] = R.if_ptr[i] + nif[i];
+  }
+  R.p = R.int_ptr[nparts];
+  R.q = R.if_ptr[nparts];
+  R.perm.assign(n, 0);
+  std::vector<int64_t> ci(R.int_ptr.begin(), R.int_ptr.end() - 1);
+  std::vector<int64_t> cf(R.if_ptr.begin(), R.if_ptr.end() - 1);
+  for (int64_t v = 0; v < n; ++v) {
+    if (iface[v]) R.perm[R.p + cf[part[v]]++] = v;
+    else R.perm[ci[part[v]]++] = v;
+  }
+  return R;
+}
+
+static void finish_csr(CsrL& M, std::vector<std::vector<std::pair<int32_t, double>>>& rows) {
+  M.ptr.assign(M.nrows + 1, 0);
+  for (int32_t r = 0; r < M.nrows; ++r) M.ptr[r + 1] = M.ptr[r] + (int32_t)rows[r].size();
+  M.col.resize(M.ptr[M.nrows]);
+  M.val.resize(M.ptr[M.nrows]);
+  for (int32_t r = 0; r < M.nrows; ++r) {
+    auto& rw = rows[r];
+    std::sort(rw.begin(), rw.end());
+    for (size_t k = 0; k < rw.size(); ++k) {
+      M.col[M.ptr[r] + k] = rw[k].first;
+      M.val[M.ptr[r] + k] = rw[k].second;
+    }
+  }
+}
+
+Blocks extract_blocks(int64_t n, const int64_t* rowptr, const int32_t* colind,
+                      const double* vals, const Reordering& R) {
+  const int np = R.nparts;
+  std::vector<int64_t> iperm(n);
+  for (int64_t k = 0; k < n; ++k) iperm[R.perm[k]] = k;
+  // owner part of each new position
+  std::vector<int32_t> own(n);
+  for (int i = 0; i < np; ++i) {
+    for (int64_t k = R.int_ptr[i]; k < R.int_ptr[i + 1]; ++k) own[k] = i;
+    for (int64_t k = R.if_ptr[i]; k < R.if_ptr[i + 1]; ++k) own[R.p + k] = i;
+  }
+  Blocks Bk;
+  Bk.B.resize(np);
+  Bk.C0.resize(np);
+  Bk.E.resize(np);
+  Bk.F.resize(np);
+  std::vector<std::vector<std::pair<int32_t, double>>> cgrows(R.q);
+  parallel_for(np, 0, [&](int i) {
+    const int64_t i0 = R.int_ptr[i], pi = R.int_ptr[i + 1] - i0;
+    const int64_t f0 = R.if_ptr[i], qi = R.if_ptr[i + 1] - f0;
+    CsrL& B = Bk.B[i]; CsrL& E = Bk.E[i]; CsrL& F = Bk.F[i]; CsrL& C = Bk.C0[i];
+    B.nrows = B.ncols = (int32_t)pi;
+    E.nrows = (int32_t)pi; E.ncols = (int32_t)qi;
+    F.nrows = (int32_t)qi; F.ncols = (int32_t)pi;
+    C.nrows = C.ncols = (int32_t)qi;
+    std::vector<std::vector<std::pair<int32_t, double>>> rb(pi), re(pi), rf(qi), rc(qi);
+    for (int64_t r = 0; r < pi; ++r) {
+      int64_t o = R.perm[i0 + r];
+      for (int64_t k = rowptr[o]; k < rowptr[o + 1]; ++k) {
+        int64_t c = iperm[colind[k]];
+        if (c < R.p) rb[r].push_back({(int32_t)(c - i0), vals[k]});
+        else re[r].push_back({(int32_t)(c - R.p - f0), vals[k]});
+      }
+    }
+    for (int64_t r = 0; r < qi; ++r) {
+      int64_t o = R.perm[R.p + f0 + r];
+      for (int64_t k = rowptr[o]; k < rowptr[o + 1]; ++k) {
+        int64_t c = iperm[colind[k]];
+        if (c < R.p) rf[r].push_back({(int32_t)(c - i0), vals[k]});
+        else if (own[c] == i) rc[r].push_back({(int32_t)(c - R.p - f0), vals[k]});
+        else cgrows[f0 + r].push_back({(int32_t)(c - R.p), vals[k]});
+      }
+    }
+    finish_csr(B, rb);
+    finish_csr(E, re);
+    finish_csr(F, rf);
+    finish_csr(C, rc);
+  });
+  CsrG& G = Bk.Cg;
+  G.nrows = G.ncols = R.q;
+  G.ptr.assign(R.q + 1, 0);
+  for (int64_t r = 0; r < R.q; ++r) {
+    auto& rw = cgrows[r];
+    std::sort(rw.begin(), rw.end());
+    for (auto& e : rw) {
+      G.col.push_back(e.first);
+      G.val.push_back(e.second);
+    }
+    G.ptr[r + 1] = (int64_t)G.col.size();
+  }
+  return Bk;
+}
+
+// ---------------------------------------------------------------------------
+// Nested dissection by recursive BFS level-set bisection
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct Graph {
+  int n = 0;
+  std::vector<int> ptr, adj;
+};
+
+Graph block_graph(const CsrL& M) {
+  Graph g;
+  g.n = M.nrows;
+  std::vector<int64_t> rp(M.nrows + 1);
+  for (int i = 0; i <= M.nrows; ++i) rp[i] = M.ptr[i];
+  std::vector<int64_t> sp;
+  std::vector<int32_t> si;
+  symmetric_pattern(M.nrows, rp.data(), M.col.data(), sp, si);
+  g.ptr.assign(sp.begin(), sp.end());
+  g.adj.assign(si.begin(), si.end());
+  return g;
+}
+
+struct ND {
+  const Graph& g;
+  std::vector<int> tag, lev, order, queue;
+  int ntag = 1;
+  static const int kLeaf = 8;
+  explicit ND(const Graph& gr) : g(gr), tag(gr.n, 0), lev(gr.n, -1), queue(gr.n) {}
+
+  // BFS from r inside tag t; returns number reached, fills queue[0..cnt) in BFS order.
+  int bfs(int r, int t, int& depth) {
+    int head = 0, tail = 0;
+    queue[tail++] = r;
+    lev[r] = 0;
+    depth = 0;
+    while (head < tail) {
+      int v = queue[head++];
+      for (int k = g.ptr[v]; k < g.ptr[v + 1]; ++k) {
+        int w = g.adj[k];
+        if (tag[w] == t && lev[w] < 0) {
+          lev[w] = lev[v] + 1;
+          depth = std::max(depth, lev[w]);
+          queue[tail++] = w;
+        }
+      }
+    }
+    return tail;
+  }
+  void clear_lev(int cnt) {
+    for (int i = 0; i < cnt; ++i) lev[queue[i]] = -1;
+  }
+
+  void run(std::vector<int> S, int t) {
+    if ((int)S.size() <= kLeaf) {
+      std::sort(S.begin(), S.end());
+      order.insert(order.end(), S.begin(), S.end());
+      return;
+    }
+    int depth;
+    int cnt = bfs(S[0], t, depth);
+    if (cnt < (int)S.size()) {  // several components: order them one after another
+      std::vector<int> comp(queue.begin(), queue.begin() + cnt);
+      clear_lev(cnt);
+      int t1 = ntag++;
+      for (int v : comp) tag[v] = t1;
+      std::vector<int> rest;
+      for (int v : S)
+        if (tag[v] == t) rest.push_back(v);
+      run(comp, t1);
+      run(rest, t);
+      return;
+    }
+    // pseudo-peripheral root: restart from the last vertex reached while the depth grows
+    int root = queue[cnt - 1];
+    clear_lev(cnt);
+    for (int it = 0; it < 4; ++it) {
+      int d2;
+      cnt = bfs(root, t, d2);
+      int far = queue[cnt - 1];
+      clear_lev(cnt);
+      if (d2 <= depth) {
+        depth = d2;
+        break;
+      }
+      depth = d2;
+      root = far;
+    }
+    cnt = bfs(root, t, depth);
+    if (depth < 2) {
+      clear_lev(cnt);
+      std::sort(S.begin(), S.end());
+      order.insert(order.end(), S.begin(), S.end());
+      return;
+    }
+    std::vector<int> lsize(depth + 1, 0);
+    for (int i = 0; i < cnt; ++i) lsize[lev[queue[i]]]++;
+    int k = 1, acc = lsize[0];
+    while (k < depth - 1 && acc + lsize[k] < (int)S.size() / 2) acc += lsize[k++];
+    std::vector<int> A, Bv, sep;
+    for (int i = 0; i < cnt; ++i) {
+      int v = queue[i];
+      if (lev[v] < k) A.push_back(v);
+      else if (lev[v] > k) Bv.push_back(v);
+      else sep.push_back(v);
+    }
+    // shrink the separator: vertices not touching the far side join the near side
+    std::vector<int> sep2;
+    for (int v : sep) {
+      bool touchB = false;
+      for (int q = g.ptr[v]; q < g.ptr[v + 1] && !touchB; ++q) {
+        int w = g.adj[q];
+        touchB = (tag[w] == t && lev[w] == k + 1);
+      }
+      if (touchB) sep2.push_back(v);
+      else A.push_back(v);
+    }
+    clear_lev(cnt);
+    int ta = ntag++, tb = ntag++, ts = ntag++;
+    for (int v : A) tag[v] = ta;
+    for (int v : Bv) tag[v] = tb;
+    for (int v : sep2) tag[v] = ts;
+    run(std::move(A), ta);
+    run(std::move(Bv), tb);
+    std::sort(sep2.begin(), sep2.end());
+    order.insert(order.end(), sep2.begin(), sep2.end());
+  }
+};
+
+// Elimination tree of a symmetric pattern (Liu's algorithm with path compression).
+std::vector<int> etree(const Graph& g) {
+  std::vector<int> parent(g.n, -1), anc(g.n, -1);
+  for (int k = 0; k < g.n; ++k)
+    for (int q = g.ptr[k]; q < g.ptr[k + 1]; ++q) {
+      int r = g.adj[q];
+      if (r >= k) continue;
+      while (anc[r] != -1 && anc[r] != k) {
+        int t = anc[r];
+        anc[r] = k;
+        r = t;
+      }
+      if (anc[r] == -1) {
+        anc[r] = k;
+        parent[r] = k;
+      }
+    }
+  return parent;
+}
+
+std::vector<int> postorder(const std::vector<int>& parent) {
+  int n = (int)parent.size();
+  std::vector<int> head(n, -1), next(n, -1), post;
+  post.reserve(n);
+  for (int v = n - 1; v >= 0; --v)
+    if (parent[v] >= 0) {
+      next[v] = head[parent[v]];
+      head[parent[v]] = v;
+    }
+  std::vector<int> stack;
+  for (int r = 0; r < n; ++r) {
+    if (parent[r] >= 0) continue;
+    stack.push_back(r);
+    while (!stack.empty()) {
+      int v = stack.back();
+      if (head[v] >= 0) {
+        int c = head[v];
+        head[v] = next[c];
+        stack.push_back(c);
+      } else {
+        stack.pop_back();
+        post.push_back(v);
+      }
+    }
+  }
+  return post;
+}
+
+Graph permute_graph(const Graph& g, const std::vector<int>& perm, const std::vector<int>& iperm) {
+  Graph h;
+  h.n = g.n;
+  h.ptr.assign(g.n + 1, 0);
+  h.adj.reserve(g.adj.size());
+  for (int i = 0; i < g.n; ++i) {
+    int o = perm[i];
+    size_t b = h.adj.size();
+    for (int q = g.ptr[o]; q < g.ptr[o + 1]; ++q) h.adj.push_back(iperm[g.adj[q]]);
+    std::sort(h.adj.begin() + b, h.adj.end());
+    h.ptr[i + 1] = (int)h.adj.size();
+  }
+  return h;
+}
+
+// Inverse of a unit lower (lower = true) or upper triangular w x w matrix
+// stored row-major in T; result row-major in X.
+void invert_triangle(const double* T, int w, bool lower, double* X) {
+  std::fill(X, X + (size_t)w * w, 0.0);
+  if (lower) {
+    for (int j = 0; j < w; ++j) {
+      X[(size_t)j * w + j] = 1.0;
+      for (int i = j + 1; i < w; ++i) {
+        double s = 0.0;
+        for (int k = j; k < i; ++k) s += T[(size_t)i * w + k] * X[(size_t)k * w + j];
+        X[(size_t)i * w + j] = -s;
+      }
+    }
+  } else {
+    for (int j = w - 1; j >= 0; --j) {
+      X[(size_t)j * w + j] = 1.0 / T[(size_t)j * w + j];
+      for (int i = j - 1; i >= 0; --i) {
+        double s = 0.0;
+        for (int k = i + 1; k <= j; ++k) s += T[(size_t)i * w + k] * X[(size_t)k * w + j];
+        X[(size_t)i * w + j] = -s / T[(size_t)i * w + i];
+      }
+    }
+  }
+}
+
+int pow2_lanes(double avg) {
+  int g = 1;
+  while (g < 64 && g * 2 <= avg / 2.0) g *= 2;
+  return g;
+}
+
+// Level schedule: supernode heights in the supernodal elimination tree.
+void build_levels(TriHost& T, const std::vector<int>& sfirst, const std::vector<int>& height,
+                  int nlev) {
+  const int ns = (int)sfirst.size() - 1;
+  T.nlev = nlev;
+  T.lev_ptr.assign(nlev + 1, 0);
+  T.lrows.clear();
+  T.lrows.reserve(T.n);
+  T.row_sn.assign(T.n, 0);
+  T.max_lrows = 0;
+  std::vector<std::vector<int>> bylev(nlev);
+  for (int s = 0; s < ns; ++s) bylev[height[s]].push_back(s);
+  for (int l = 0; l < nlev; ++l) {
+    for (int s : bylev[l])
+      for (int r = sfirst[s]; r < sfirst[s + 1]; ++r) {
+        T.lrows.push_back(r);
+        T.row_sn[r] = s;
+      }
+    T.lev_ptr[l + 1] = (int)T.lrows.size();
+    T.max_lrows = std::max(T.max_lrows, T.lev_ptr[l + 1] - T.lev_ptr[l]);
+  }
+  // lanes per row for the two sweeps of each level
+  T.lev_g.assign(nlev, 0);
+  for (int l = 0; l < nlev; ++l) {
+    double s1 = 0, s2 = 0;
+    int cnt = T.lev_ptr[l + 1] - T.lev_ptr[l];
+    for (int k = T.lev_ptr[l]; k < T.lev_ptr[l + 1]; ++k) {
+      int p = T.lrows[k];
+      const SnHost& S = T.sn[T.row_sn[p]];
+      int i = p - S.f;
+      s1 += T.lower ? (double)(T.rp[p + 1] - T.rp[p]) : (double)S.h;
+      s2 += T.lower ? (double)(i + 1) : (double)(S.w - i);
+    }
+    int g1 = cnt ? pow2_lanes(s1 / cnt) : 1;
+    int g2 = cnt ? pow2_lanes(s2 / cnt) : 1;
+    T.lev_g[l] = g1 | (g2 << 8);
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Exact sparse LU of one block
+// ---------------------------------------------------------------------------
+
+int factor_block(const CsrL& M, double tau, bool want_T, BlockFactor& out, std::string& err) {
+  const int n = M.nrows;
+  out = BlockFactor();
+  out.n = n;
+  if (n == 0) {
+    for (TriHost* T : {&out.lo, &out.up, &out.loT, &out.upT}) {
+      T->n = 0;
+      T->nlev = 0;
+      T->lev_ptr.assign(1, 0);
+      T->rp.assign(1, 0);
+    }
+    out.lo.lower = out.loT.lower = true;
+    out.up.lower = out.upT.lower = false;
+    return 0;
+  }
+  double maxabs = 0.0;
+  for (double v : M.val) maxabs = std::max(maxabs, std::fabs(v));
+
+  // --- ordering: nested dissection, then etree postorder
+  Graph g = block_graph(M);
+  ND nd(g);
+  {
+    std::vector<int> all(n);
+    std::iota(all.begin(), all.end(), 0);
+    nd.run(all, 0);
+  }
+  std::vector<int> perm = nd.order, iperm(n);
+  for (int i = 0; i < n; ++i) iperm[perm[i]] = i;
+  Graph gp = permute_graph(g, perm, iperm);
+  std::vector<int> par = etree(gp);
+  std::vector<int> post = postorder(par);
+  {
+    std::vector<int> p2(n);
+    for (int i = 0; i < n; ++i) p2[i] = perm[post[i]];
+    perm.swap(p2);
+  }
+  for (int i = 0; i < n; ++i) iperm[perm[i]] = i;
+  gp = permute_graph(g, perm, iperm);
+  par = etree(gp);
+
+  // --- symbolic: column structures of L, fundamental supernodes
+  std::vector<std::vector<int>> st(n);
+  std::vector<int> nchild(n, 0), mark(n, -1);
+  std::vector<int> chead(n, -1), cnext(n, -1);
+  for (int v = n - 1; v >= 0; --v)
+    if (par[v] >= 0) {
+      nchild[par[v]]++;
+      cnext[v] = chead[par[v]];
+      chead[par[v]] = v;
+    }
+  for (int j = 0; j < n; ++j) {
+    std::vector<int>& s = st[j];
+    mark[j] = j;
+    for (int q = gp.ptr[j]; q < gp.ptr[j + 1]; ++q) {
+      int i = gp.adj[q];
+      if (i > j && mark[i] != j) {
+        mark[i] = j;
+        s.push_back(i);
+      }
+    }
+    for (int c = chead[j]; c >= 0; c = cnext[c])
+      for (int i : st[c])
+        if (i > j && mark[i] != j) {
+          mark[i] = j;
+          s.push_back(i);
+        }
+    std::sort(s.begin(), s.end());
+  }
+  std::vector<int> sfirst;
+  sfirst.push_back(0);
+  for (int j = 1; j < n; ++j) {
+    bool join = par[j - 1] == j && st[j - 1].size() == st[j].size() + 1 && nchild[j] == 1;
+    if (!join) sfirst.push_back(j);
+  }
+  sfirst.push_back(n);
+  const int ns = (int)sfirst.size() - 1;
+  out.nsuper = ns;
+  std::vector<int> snode(n);
+  for (int s = 0; s < ns; ++s)
+    for (int j = sfirst[s]; j < sfirst[s + 1]; ++j) snode[j] = s;
+  std::vector<std::vector<int>> R(ns);
+  std::vector<int> spar(ns, -1), height(ns, 0);
+  for (int s = 0; s < ns; ++s) {
+    R[s] = st[sfirst[s + 1] - 1];
+    if (!R[s].empty()) spar[s] = snode[R[s][0]];
+  }
+  st.clear();
+  st.shrink_to_fit();
+  int nlev = 1;
+  for (int s = 0; s < ns; ++s)
+    if (spar[s] >= 0) {
+      height[spar[s]] = std::max(height[spar[s]], height[s] + 1);
+      nlev = std::max(nlev, height[spar[s]] + 1);
+    }
+
+  // --- permuted matrix Mp = M[perm, perm], CSR and CSC
+  std::vector<int> rp(n + 1, 0), ci;
+  std::vector<double> cv;
+  {
+    std::vector<std::pair<int, double>> row;
+    for (int i = 0; i < n; ++i) {
+      int o = perm[i];
+      row.clear();
+      for (int k = M.ptr[o]; k < M.ptr[o + 1]; ++k) row.push_back({iperm[M.col[k]], M.val[k]});
+      std::sort(row.begin(), row.end());
+      for (auto& e : row) {
+        ci.push_back(e.first);
+        cv.push_back(e.second);
+      }
+      rp[i + 1] = (int)ci.size();
+    }
+  }
+  std::vector<int> cp(n + 1, 0), ri(ci.size());
+  std::vector<double> rv(ci.size());
+  for (int c : ci) cp[c + 1]++;
+  for (int i = 0; i < n; ++i) cp[i + 1] += cp[i];
+  {
+    std::vector<int> pos(cp.begin(), cp.end() - 1);
+    for (int i = 0; i < n; ++i)
+      for (int k = rp[i]; k < rp[i + 1]; ++k) {
+        int d = pos[ci[k]]++;
+        ri[d] = i;
+        rv[d] = cv[k];
+      }
+  }
+
+  // --- numeric multifrontal factorisation
+  struct CB {
+    std::vector<int> idx;
+    std::vector<double> a;
+  };
+  std::vector<CB> stack;
+  std::vector<std::vector<double>> diagLU(ns), Lp(ns), Up(ns);
+  std::vector<int> prow(n);
+  std::vector<int> relpos(n, -1);
+  std::vector<int> snchild(ns, 0);
+  for (int s = 0; s < ns; ++s)
+    if (spar[s] >= 0) snchild[spar[s]]++;
+  const int NB = 32;
+  for (int s = 0; s < ns; ++s) {
+    const int f = sfirst[s], l = sfirst[s + 1] - 1, w = l - f + 1;
+    const std::vector<int>& Rs = R[s];
+    const int h = (int)Rs.size(), N = w + h;
+    for (int k = 0; k < w; ++k) relpos[f + k] = k;
+    for (int a = 0; a < h; ++a) relpos[Rs[a]] = w + a;
+    std::vector<double> F((size_t)N * N, 0.0);
+    for (int j = f; j <= l; ++j) {
+      for (int k = rp[j]; k < rp[j + 1]; ++k)
+        if (ci[k] >= f) F[(size_t)(j - f) * N + relpos[ci[k]]] += cv[k];
+      for (int k = cp[j]; k < cp[j + 1]; ++k)
+        if (ri[k] > l) F[(size_t)relpos[ri[k]] * N + (j - f)] += rv[k];
+    }
+    for (int c = 0; c < snchild[s]; ++c) {
+      CB cb = std::move(stack.back());
+      stack.pop_back();
+      const int hc = (int)cb.idx.size();
+      for (int a = 0; a < hc; ++a) {
+        double* Fr = &F[(size_t)relpos[cb.idx[a]] * N];
+        const double* Cr = &cb.a[(size_t)a * hc];
+        for (int b = 0; b < hc; ++b) Fr[relpos[cb.idx[b]]] += Cr[b];
+      }
+    }
+    std::vector<int> pr(w);
+    std::iota(pr.begin(), pr.end(), f);
+    for (int k0 = 0; k0 < w; k0 += NB) {
+      const int kend = std::min(w, k0 + NB);
+      for (int k = k0; k < kend; ++k) {
+        double amax = 0.0;
+        int ip = k;
+        for (int i = k; i < w; ++i) {
+          double a = std::fabs(F[(size_t)i * N + k]);
+          if (a > amax) {
+            amax = a;
+            ip = i;
+          }
+        }
+        if (!(amax > 1e-14 * maxabs)) {
+          err = "zero pivot in a diagonal block (singular or numerically singular block)";
+          return 2;
+        }
+        if (std::fabs(F[(size_t)k * N + k]) >= tau * amax) ip = k;
+        if (ip != k) {
+          std::swap_ranges(F.begin() + (size_t)k * N, F.begin() + (size_t)(k + 1) * N,
+                           F.begin() + (size_t)ip * N);
+          std::swap(pr[k], pr[ip]);
+        }
+        const double piv = F[(size_t)k * N + k];
+        const double* Fk = &F[(size_t)k * N];
+        for (int i = k + 1; i < N; ++i) {
+          double* Fi = &F[(size_t)i * N];
+          double lik = Fi[k] / piv;
+          Fi[k] = lik;
+          if (lik != 0.0)
+            for (int j = k + 1; j < kend; ++j) Fi[j] -= lik * Fk[j];
+        }
+      }
+      for (int i = k0 + 1; i < kend; ++i) {
+        double* Fi = &F[(size_t)i * N];
+        for (int k = k0; k < i; ++k) {
+          const double lik = Fi[k];
+          if (lik == 0.0) continue;
+          const double* Fk = &F[(size_t)k * N];
+          for (int j = kend; j < N; ++j) Fi[j] -= lik * Fk[j];
+        }
+      }
+      for (int i = kend; i < N; ++i) {
+        double* Fi = &F[(size_t)i * N];
+        for (int k = k0; k < kend; ++k) {
+          const double lik = Fi[k];
+          if (lik == 0.0) continue;
+          const double* Fk = &F[(size_t)k * N];
+          for (int j = kend; j < N; ++j) Fi[j] -= lik * Fk[j];
+        }
+      }
+    }
+    for (int k = 0; k < w; ++k) prow[f + k] = pr[k];
+    diagLU[s].resize((size_t)w * w);
+    Lp[s].resize((size_t)h * w);
+    Up[s].resize((size_t)w * h);
+    for (int i = 0; i < w; ++i)
+      for (int j = 0; j < w; ++j) diagLU[s][(size_t)i * w + j] = F[(size_t)i * N + j];
+    for (int a = 0; a < h; ++a)
+      for (int j = 0; j < w; ++j) Lp[s][(size_t)a * w + j] = F[(size_t)(w + a) * N + j];
+    for (int i = 0; i < w; ++i)
+      for (int a = 0; a < h; ++a) Up[s][(size_t)i * h + a] = F[(size_t)i * N + w + a];
+    if (h > 0) {
+      CB cb;
+      cb.idx = Rs;
+      cb.a.resize((size_t)h * h);
+      for (int a = 0; a < h; ++a)
+        std::memcpy(&cb.a[(size_t)a * h], &F[(size_t)(w + a) * N + w], sizeof(double) * h);
+      stack.push_back(std::move(cb));
+    }
+  }
+
+  // --- index maps
+  std::vector<int> posOf(n);
+  for (int p = 0; p < n; ++p) posOf[prow[p]] = p;
+  out.gin.resize(n);
+  out.gout.resize(n);
+  for (int p = 0; p < n; ++p) {
+    out.gin[p] = perm[prow[p]];
+    out.gout[p] = perm[p];
+  }
+
+  // --- packed layouts
+  std::vector<double> inv, tmp;
+  auto init_tri = [&](TriHost& T, bool lower) {
+    T = TriHost();
+    T.lower = lower;
+    T.n = n;
+    T.sn.resize(ns);
+    for (int s = 0; s < ns; ++s) {
+      SnHost& S = T.sn[s];
+      S.f = sfirst[s];
+      S.w = sfirst[s + 1] - sfirst[s];
+      S.h = lower ? 0 : (int)R[s].size();
+      S.pad = 0;
+      S.tri_off = S.panel_off = S.ridx_off = 0;
+    }
+  };
+  // packed inverted triangles: lower rows hold columns 0..i, upper rows i..w-1
+  auto pack_tri = [&](TriHost& T, int s, const std::vector<double>& Xinv, bool transpose) {
+    const int w = T.sn[s].w;
+    T.sn[s].tri_off = (int64_t)T.tri.size();
+    for (int i = 0; i < w; ++i) {
+      int a = T.lower ? 0 : i, b = T.lower ? i : w - 1;
+      for (int k = a; k <= b; ++k)
+        T.tri.push_back(transpose ? Xinv[(size_t)k * w + i] : Xinv[(size_t)i * w + k]);
+    }
+  };
+  std::vector<std::vector<double>> invL(ns), invU(ns);
+  for (int s = 0; s < ns; ++s) {
+    const int w = sfirst[s + 1] - sfirst[s];
+    invL[s].resize((size_t)w * w);
+    invU[s].resize((size_t)w * w);
+    invert_triangle(diagLU[s].data(), w, true, invL[s].data());
+    invert_triangle(diagLU[s].data(), w, false, invU[s].data());
+    out.nnz_L += (int64_t)w * (w + 1) / 2 + (int64_t)w * (int64_t)R[s].size();
+    out.nnz_U += (int64_t)w * (w + 1) / 2 + (int64_t)w * (int64_t)R[s].size();
+  }
+  // lower CSR rows from the L panels (forward) or U panels (transposed)
+  auto build_lower_rows = [&](TriHost& T, bool fromU) {
+    std::vector<int64_t> cnt(n + 1, 0);
+    for (int d = 0; d < ns; ++d) {
+      const int w = sfirst[d + 1] - sfirst[d];
+      for (int r : R[d]) cnt[(fromU ? r : posOf[r]) + 1] += w;
+    }
+    for (int p = 0; p < n; ++p) cnt[p + 1] += cnt[p];
+    T.rp = cnt;
+    T.col.resize(cnt[n]);
+    T.val.resize(cnt[n]);
+    std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+    for (int d = 0; d < ns; ++d) {
+      const int f = sfirst[d], w = sfirst[d + 1] - f, h = (int)R[d].size();
+      for (int a = 0; a < h; ++a) {
+        const int p = fromU ? R[d][a] : posOf[R[d][a]];
+        for (int j = 0; j < w; ++j) {
+          T.col[pos[p]] = f + j;
+          T.val[pos[p]++] = fromU ? Up[d][(size_t)j * h + a] : Lp[d][(size_t)a * w + j];
+        }
+      }
+    }
+  };
+  auto build_upper_panels = [&](TriHost& T, bool fromL) {
+    for (int s = 0; s < ns; ++s) {
+      SnHost& S = T.sn[s];
+      const int w = S.w, h = S.h;
+      S.ridx_off = (int64_t)T.ridx.size();
+      S.panel_off = (int64_t)T.val.size();
+      for (int a = 0; a < h; ++a) T.ridx.push_back(fromL ? posOf[R[s][a]] : R[s][a]);
+      for (int i = 0; i < w; ++i)
+        for (int a = 0; a < h; ++a)
+          T.val.push_back(fromL ? Lp[s][(size_t)a * w + i] : Up[s][(size_t)i * h + a]);
+    }
+  };
+  init_tri(out.lo, true);
+  build_lower_rows(out.lo, false);
+  for (int s = 0; s < ns; ++s) pack_tri(out.lo, s, invL[s], false);
+  build_levels(out.lo, sfirst, height, nlev);
+  init_tri(out.up, false);
+  build_upper_panels(out.up, false);
+  out.up.rp.assign(1, 0);
+  for (int s = 0; s < ns; ++s) pack_tri(out.up, s, invU[s], false);
+  build_levels(out.up, sfirst, height, nlev);
+  if (want_T) {
+    init_tri(out.loT, true);
+    build_lower_rows(out.loT, true);
+    for (int s = 0; s < ns; ++s) pack_tri(out.loT, s, invU[s], true);
+    build_levels(out.loT, sfirst, height, nlev);
+    init_tri(out.upT, false);
+    build_upper_panels(out.upT, true);
+    out.upT.rp.assign(1, 0);
+    for (int s = 0; s < ns; ++s) pack_tri(out.upT, s, invL[s], true);
+    build_levels(out.upT, sfirst, height, nlev);
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Host execution of a packed factor (diagnostics)
+// ---------------------------------------------------------------------------
+
+void host_tri_solve(const TriHost& T, std::vector<double>& X) {
+  std::vector<double> Rb(std::max(T.max_lrows, 1));
+  for (int li = 0; li < T.nlev; ++li) {
+    const int l = T.lower ? li : T.nlev - 1 - li;
+    const int b = T.lev_ptr[l], e = T.lev_ptr[l + 1];
+    for (int k = b; k < e; ++k) {
+      const int p = T.lrows[k];
+      const SnHost& S = T.sn[T.row_sn[p]];
+      double acc = 0.0;
+      if (T.lower) {
+        for (int64_t q = T.rp[p]; q < T.rp[p + 1]; ++q) acc += T.val[q] * X[T.col[q]];
+      } else {
+        const double* pr = &T.val[S.panel_off + (int64_t)(p - S.f) * S.h];
+        for (int a = 0; a < S.h; ++a) acc += pr[a] * X[T.ridx[S.ridx_off + a]];
+      }
+      Rb[k - b] = X[p] - acc;
+    }
+    for (int k = b; k < e; ++k) {
+      const int p = T.lrows[k];
+      const SnHost& S = T.sn[T.row_sn[p]];
+      const int i = p - S.f, base = k - b - i;
+      double acc = 0.0;
+      if (T.lower) {
+        const double* tr = &T.tri[S.tri_off + (int64_t)i * (i + 1) / 2];
+        for (int c = 0; c <= i; ++c) acc += tr[c] * Rb[base + c];
+      } else {
+        const int64_t off = (int64_t)i * S.w - (int64_t)i * (i - 1) / 2;
+        const double* tr = &T.tri[S.tri_off + off];
+        for (int c = i; c < S.w; ++c) acc += tr[c - i] * Rb[base + c];
+      }
+      X[p] = acc;
+    }
+  }
+}
+
+}  // namespace pslr

@@ -1,0 +1,294 @@
+"""Python binding of the PSLR C ABI (include/pslr.h): argument marshalling only.
+
+Every computation runs in libpslr.so (HIP kernels on the GPU, C++ host setup);
+this module converts numpy arrays / torch device tensors into the pointers
+and sizes the C functions take.  Names match the C entry points.
+
+Device vectors are torch float64 tensors on a HIP device, either 1-D (n,) or
+2-D (nrhs, n) row-major, i.e. column-major n x nrhs with leading dimension
+equal to the row stride.  The library is required: nothing here has a CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpslr.so")
+_lib = None
+
+PSLR_OK, PSLR_EINVAL, PSLR_ESINGULAR, PSLR_ENOCONV, PSLR_EBREAKDOWN, PSLR_ENOMEM, PSLR_EHIP, \
+    PSLR_ENOTSUP = range(8)
+
+
+class PslrError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s: %s" % (_status_name(status), message))
+        self.status = status
+
+
+class pslr_options(C.Structure):
+    _fields_ = [("m", C.c_int32), ("rank", C.c_int32), ("precision", C.c_int32),
+                ("want_transpose", C.c_int32), ("v0", C.POINTER(C.c_double)),
+                ("seed", C.c_uint64), ("pivot_threshold", C.c_double), ("nthreads", C.c_int32)]
+
+
+class pslr_info_t(C.Structure):
+    _fields_ = [("n", C.c_int64), ("p", C.c_int64), ("q", C.c_int64), ("nparts", C.c_int32),
+                ("m", C.c_int32), ("rank", C.c_int32), ("precision", C.c_int32),
+                ("nnz_A", C.c_int64), ("nnz_E", C.c_int64), ("nnz_F", C.c_int64),
+                ("nnz_Cg", C.c_int64), ("nnz_LU_B", C.c_int64), ("nnz_LU_C0", C.c_int64),
+                ("supernodes_B", C.c_int32), ("supernodes_C0", C.c_int32),
+                ("max_levels_B", C.c_int32), ("max_levels_C0", C.c_int32),
+                ("fill_lu", C.c_double), ("fill_lowrank", C.c_double), ("fill_total", C.c_double),
+                ("apply_bytes", C.c_int64), ("apply_bytes_rhs", C.c_int64),
+                ("series_bytes", C.c_int64), ("seconds_reorder", C.c_double),
+                ("seconds_factor", C.c_double), ("seconds_arnoldi", C.c_double)]
+
+
+_P = C.c_void_p
+_I32P = C.POINTER(C.c_int32)
+_I64P = C.POINTER(C.c_int64)
+_F64P = C.POINTER(C.c_double)
+
+_SIGS = {
+    "pslr_default_options": (None, [C.POINTER(pslr_options)]),
+    "pslr_setup": (C.c_int, [C.c_int64, _I64P, _I32P, _F64P, _I32P, C.c_int32,
+                             C.POINTER(pslr_options), _P, C.POINTER(_P)]),
+    "pslr_apply": (C.c_int, [_P, C.c_int32, _P, C.c_int64, _P, C.c_int64, _P]),
+    "pslr_apply_transpose": (C.c_int, [_P, C.c_int32, _P, C.c_int64, _P, C.c_int64, _P]),
+    "fgmres_solve": (C.c_int, [_P, C.c_int32, _P, C.c_int64, _P, C.c_int64, C.c_int32, C.c_int32,
+                               C.c_double, C.c_int32, _I32P, _F64P, _P]),
+    "pslr_sddmm_grad": (C.c_int, [_P, C.c_int32, _P, C.c_int64, _P, C.c_int64, _P, _P]),
+    "pslr_info": (C.c_int, [_P, C.POINTER(pslr_info_t)]),
+    "pslr_set_lowrank": (C.c_int, [_P, C.c_int32, _F64P, C.c_int64, _F64P, C.c_int64]),
+    "pslr_get_lowrank": (C.c_int, [_P, _I32P, _F64P, C.c_int64, _F64P, C.c_int64]),
+    "pslr_partition_geometric": (C.c_int, [C.c_int32, _I32P, _I32P, _I32P]),
+    "pslr_partition_region_growing": (C.c_int, [C.c_int64, _I64P, _I32P, C.c_int32, C.c_uint64,
+                                                _I32P, _I32P]),
+    "pslr_reorder": (C.c_int, [C.c_int64, _I64P, _I32P, _I32P, C.c_int32, _I64P, _I64P, _I64P]),
+    "pslr_host_selfcheck": (C.c_int, [C.c_int64, _I64P, _I32P, _F64P, _I32P, C.c_int32,
+                                      C.POINTER(pslr_options), _F64P, _F64P]),
+    "pslr_destroy": (C.c_int, [_P]),
+    "pslr_status_string": (C.c_char_p, [C.c_int]),
+    "pslr_last_error": (C.c_char_p, []),
+}
+
+EXPORTED = tuple(_SIGS)
+
+
+def lib():
+    """Load libpslr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libpslr.so is not built: run `python -m paper_2002_00917_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _status_name(s):
+    try:
+        return lib().pslr_status_string(s).decode()
+    except Exception:
+        return "status %d" % s
+
+
+def _check(status, allowed=(PSLR_OK,)):
+    if status not in allowed:
+        raise PslrError(status, lib().pslr_last_error().decode())
+    return status
+
+
+def _arr(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(C.POINTER(np.ctypeslib.as_ctypes_type(dtype)))
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+
+
+def _vec(t, n):
+    """(pointer, nrhs, ld) of a float64 device tensor shaped (n,) or (nrhs, n)."""
+    import torch
+    if t.dtype != torch.float64 or not t.is_cuda:
+        raise ValueError("device float64 tensor required")
+    if t.dim() == 1:
+        if t.shape[0] != n or t.stride(0) != 1:
+            raise ValueError("bad vector shape")
+        return C.c_void_p(t.data_ptr()), 1, n
+    if t.dim() != 2 or t.shape[1] != n or t.stride(1) != 1:
+        raise ValueError("expected shape (nrhs, n) with unit stride along n")
+    return C.c_void_p(t.data_ptr()), t.shape[0], t.stride(0)
+
+
+# ----------------------------------------------------------------- handle
+
+
+class Handle:
+    def __init__(self, ptr, n, status):
+        self.ptr = ptr
+        self.n = n
+        self.status = status
+
+    def __del__(self):
+        if getattr(self, "ptr", None) is not None and _lib is not None:
+            _lib.pslr_destroy(self.ptr)
+            self.ptr = None
+
+
+def pslr_default_options():
+    o = pslr_options()
+    lib().pslr_default_options(C.byref(o))
+    return o
+
+
+def pslr_setup(rowptr, colind, vals, part, nparts, m=3, rank=16, precision=0,
+               want_transpose=False, v0=None, seed=1, pivot_threshold=0.1, nthreads=0,
+               stream=None) -> Handle:
+    L = lib()
+    rp, rpp = _arr(rowptr, np.int64)
+    ci, cip = _arr(colind, np.int32)
+    va, vap = _arr(vals, np.float64)
+    pa, pap = _arr(part, np.int32)
+    o = pslr_default_options()
+    o.m, o.rank, o.precision = int(m), int(rank), int(precision)
+    o.want_transpose = 1 if want_transpose else 0
+    o.seed, o.pivot_threshold, o.nthreads = int(seed), float(pivot_threshold), int(nthreads)
+    keep = None
+    if v0 is not None:
+        keep, o.v0 = _arr(v0, np.float64)
+    out = C.c_void_p()
+    n = len(rp) - 1
+    st = L.pslr_setup(n, rpp, cip, vap, pap, int(nparts), C.byref(o), _stream_ptr(stream),
+                      C.byref(out))
+    _check(st, (PSLR_OK, PSLR_EBREAKDOWN))
+    del keep
+    return Handle(out, n, st)
+
+
+def pslr_apply(h: Handle, b, z, stream=None):
+    bp, nrhs, ldb = _vec(b, h.n)
+    zp, nrz, ldz = _vec(z, h.n)
+    if nrz != nrhs:
+        raise ValueError("b and z have different column counts")
+    _check(lib().pslr_apply(h.ptr, nrhs, bp, ldb, zp, ldz, _stream_ptr(stream)))
+
+
+def pslr_apply_transpose(h: Handle, b, z, stream=None):
+    bp, nrhs, ldb = _vec(b, h.n)
+    zp, nrz, ldz = _vec(z, h.n)
+    if nrz != nrhs:
+        raise ValueError("b and z have different column counts")
+    _check(lib().pslr_apply_transpose(h.ptr, nrhs, bp, ldb, zp, ldz, _stream_ptr(stream)))
+
+
+def fgmres_solve(h: Handle, b, x, restart=40, maxit=500, tol=1e-8, transpose=False, stream=None):
+    """Returns (status, iters[nrhs], relres[nrhs]); x holds the initial guess and the result."""
+    bp, nrhs, ldb = _vec(b, h.n)
+    xp, nrx, ldx = _vec(x, h.n)
+    if nrx != nrhs:
+        raise ValueError("b and x have different column counts")
+    its = np.zeros(nrhs, dtype=np.int32)
+    rel = np.zeros(nrhs, dtype=np.float64)
+    st = lib().fgmres_solve(h.ptr, nrhs, bp, ldb, xp, ldx, int(restart), int(maxit), float(tol),
+                            1 if transpose else 0, its.ctypes.data_as(_I32P),
+                            rel.ctypes.data_as(_F64P), _stream_ptr(stream))
+    _check(st, (PSLR_OK, PSLR_ENOCONV))
+    return st, its, rel
+
+
+def pslr_sddmm_grad(h: Handle, lam, z, grad, stream=None):
+    lp, nrhs, ldl = _vec(lam, h.n)
+    zp, nrz, ldz = _vec(z, h.n)
+    if nrz != nrhs:
+        raise ValueError("lambda and z have different column counts")
+    _check(lib().pslr_sddmm_grad(h.ptr, nrhs, lp, ldl, zp, ldz, C.c_void_p(grad.data_ptr()),
+                                 _stream_ptr(stream)))
+
+
+def pslr_info(h: Handle) -> dict:
+    info = pslr_info_t()
+    _check(lib().pslr_info(h.ptr, C.byref(info)))
+    return {k: getattr(info, k) for k, _ in pslr_info_t._fields_}
+
+
+def pslr_set_lowrank(h: Handle, V, H):
+    V = np.asfortranarray(V, dtype=np.float64)
+    H = np.asfortranarray(H, dtype=np.float64)
+    k = V.shape[1] if V.ndim == 2 else 0
+    q = V.shape[0]
+    _check(lib().pslr_set_lowrank(h.ptr, k, V.ctypes.data_as(_F64P), max(q, 1),
+                                  H.ctypes.data_as(_F64P), max(k, 1)))
+
+
+def pslr_get_lowrank(h: Handle):
+    info = pslr_info(h)
+    q, k = info["q"], info["rank"]
+    V = np.zeros((q, k), order="F")
+    H = np.zeros((k, k), order="F")
+    kk = C.c_int32()
+    _check(lib().pslr_get_lowrank(h.ptr, C.byref(kk), V.ctypes.data_as(_F64P), max(q, 1),
+                                  H.ctypes.data_as(_F64P), max(k, 1)))
+    return V[:, :kk.value], H[:kk.value, :kk.value]
+
+
+def pslr_partition_geometric(dims, parts) -> np.ndarray:
+    d, dp = _arr(dims, np.int32)
+    p, pp = _arr(parts, np.int32)
+    out = np.zeros(int(np.prod(d)), dtype=np.int32)
+    _check(lib().pslr_partition_geometric(len(d), dp, pp, out.ctypes.data_as(_I32P)))
+    return out
+
+
+def pslr_partition_region_growing(rowptr, colind, nparts, seed):
+    rp, rpp = _arr(rowptr, np.int64)
+    ci, cip = _arr(colind, np.int32)
+    n = len(rp) - 1
+    out = np.zeros(n, dtype=np.int32)
+    nl = C.c_int32()
+    _check(lib().pslr_partition_region_growing(n, rpp, cip, int(nparts), C.c_uint64(seed),
+                                               out.ctypes.data_as(_I32P), C.byref(nl)))
+    return out, nl.value
+
+
+def pslr_reorder(rowptr, colind, part, nparts):
+    rp, rpp = _arr(rowptr, np.int64)
+    ci, cip = _arr(colind, np.int32)
+    pa, pap = _arr(part, np.int32)
+    n = len(rp) - 1
+    perm = np.zeros(n, dtype=np.int64)
+    p = C.c_int64()
+    q = C.c_int64()
+    _check(lib().pslr_reorder(n, rpp, cip, pap, int(nparts), perm.ctypes.data_as(_I64P),
+                              C.byref(p), C.byref(q)))
+    return perm, p.value, q.value
+
+
+def pslr_host_selfcheck(rowptr, colind, vals, part, nparts, want_transpose=True,
+                        pivot_threshold=0.1, nthreads=0):
+    rp, rpp = _arr(rowptr, np.int64)
+    ci, cip = _arr(colind, np.int32)
+    va, vap = _arr(vals, np.float64)
+    pa, pap = _arr(part, np.int32)
+    o = pslr_default_options()
+    o.want_transpose = 1 if want_transpose else 0
+    o.pivot_threshold = float(pivot_threshold)
+    o.nthreads = int(nthreads)
+    fr = C.c_double()
+    sr = C.c_double()
+    _check(lib().pslr_host_selfcheck(len(rp) - 1, rpp, cip, vap, pap, int(nparts), C.byref(o),
+                                     C.byref(fr), C.byref(sr)))
+    return fr.value, sr.value

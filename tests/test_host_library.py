@@ -1,0 +1,115 @@
+"""Host-side logic of the HIP library, checked on the CPU (no GPU calls).
+
+* the C ABI exports every function include/pslr.h declares;
+* partition labels and the reordering are bit-exact with the oracle;
+* the exact LU factors and the packed level-scheduled solve layouts solve the
+  diagonal blocks to rounding (host execution of the device layouts).
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2002_00917_amd import workloads as wl
+from paper_2002_00917_amd import pslr as P
+from oracle import partition as opart
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+pytestmark = pytest.mark.skipif(not os.path.exists(P.LIB_PATH), reason="libpslr.so not built")
+
+
+def test_header_symbols_exported():
+    with open(os.path.join(ROOT, "include", "pslr.h")) as fh:
+        src = fh.read()
+    names = set(re.findall(r"^\s*(?:pslr_status|void|const char\*)\s+(\w+)\s*\(", src, re.M))
+    assert {"pslr_setup", "pslr_apply", "pslr_apply_transpose", "fgmres_solve"} <= names
+    L = P.lib()
+    for nm in names:
+        assert hasattr(L, nm), nm
+    assert set(P.EXPORTED) == names
+
+
+def test_geometric_partition_bit_exact():
+    for dims, parts in (((64, 64), (2, 2)), ((64, 64, 64), (4, 4, 4)), ((37, 23), (3, 5)),
+                        ((11, 7, 5), (2, 3, 1)), ((256, 256), (4, 4))):
+        assert np.array_equal(P.pslr_partition_geometric(dims, parts),
+                              opart.geometric_labels(dims, parts))
+
+
+def test_region_growing_bit_exact():
+    cases = [(wl.laplacian2d(40, 0.0, Ny=31), 9, 3), (wl.convdiff3d(14, 10.0, 0.1), 17, 4),
+             (wl.laplacian2d(130, 0.0), 23, 3003)]
+    for A, s, seed in cases:
+        lab, nl = P.pslr_partition_region_growing(A.rowptr, A.colind, s, seed)
+        olab = opart.region_growing_labels(A.to_scipy(), s, seed)
+        assert nl == s and np.array_equal(lab, olab)
+
+
+def test_region_growing_disconnected_graph():
+    # two disconnected grids and one seed: the unreached part gets a new label
+    import scipy.sparse as sp
+    a = wl.laplacian2d(6, 0.0).to_scipy()
+    A = wl.CSR.from_scipy(sp.block_diag([a, a]))
+    lab, nl = P.pslr_partition_region_growing(A.rowptr, A.colind, 1, 1)
+    olab = opart.region_growing_labels(A.to_scipy(), 1, 1)
+    assert np.array_equal(lab, olab) and nl == 2 and len(set(lab.tolist())) == 2
+
+
+def test_reorder_bit_exact():
+    rng = np.random.default_rng(3)
+    for A, lab in ((wl.c1().A, opart.geometric_labels((64, 64), (2, 2))),
+                   (wl.laplacian3d(20, 0.1), opart.geometric_labels((20,) * 3, (3, 2, 2))),
+                   (wl.laplacian2d(30, 0.0), rng.integers(0, 5, size=900).astype(np.int32))):
+        perm, p, q = P.pslr_reorder(A.rowptr, A.colind, lab, int(lab.max()) + 1)
+        operm, op, oq, _, _ = opart.reorder(A.to_scipy(), lab)
+        assert (p, q) == (op, oq) and np.array_equal(perm, operm)
+
+
+@pytest.mark.parametrize("case", ["c1", "lap3d", "convdiff_rg", "random_labels", "c5_like"])
+def test_block_factor_layouts_solve(case):
+    rng = np.random.default_rng(0)
+    if case == "c1":
+        A = wl.c1().A
+        lab = opart.geometric_labels((64, 64), (2, 2))
+    elif case == "lap3d":
+        A = wl.laplacian3d(18, wl.SIGMA_C2)
+        lab = opart.geometric_labels((18,) * 3, (2, 2, 2))
+    elif case == "convdiff_rg":
+        A = wl.convdiff3d(16, 10.0, 0.2)
+        lab = opart.region_growing_labels(A.to_scipy(), 6, 4)
+    elif case == "random_labels":
+        A = wl.laplacian2d(25, 0.3)
+        lab = rng.integers(0, 7, size=A.n).astype(np.int32)
+    else:
+        w, kappa, kref, sigma = wl.c5(48)
+        A = w.A
+        lab = opart.geometric_labels((48, 48), (4, 4))
+    fr, sr = P.pslr_host_selfcheck(A.rowptr, A.colind, A.vals, lab, int(lab.max()) + 1,
+                                   want_transpose=True, nthreads=4)
+    assert fr < 1e-13, fr
+    assert sr < 1e-10, sr
+
+
+def test_singular_block_reported():
+    # a 1-D Laplacian block shifted exactly onto one of its eigenvalues is singular
+    N = 9
+    lam = 2.0 - 2.0 * np.cos(np.pi / (N + 1))
+    import scipy.sparse as sp
+    T = sp.diags([-np.ones(N - 1), (2.0 - lam) * np.ones(N), -np.ones(N - 1)], [-1, 0, 1])
+    A = wl.CSR.from_scipy(T)
+    lab = np.zeros(N, dtype=np.int32)
+    with pytest.raises(P.PslrError) as ei:
+        P.pslr_host_selfcheck(A.rowptr, A.colind, A.vals, lab, 1)
+    assert ei.value.status == P.PSLR_ESINGULAR
+
+
+def test_invalid_arguments():
+    A = wl.laplacian2d(5, 0.0)
+    bad = np.full(A.n, 3, dtype=np.int32)
+    with pytest.raises(P.PslrError) as ei:
+        P.pslr_reorder(A.rowptr, A.colind, bad, 2)
+    assert ei.value.status == P.PSLR_EINVAL
+    with pytest.raises(P.PslrError):
+        P.pslr_partition_geometric((4, 4), (5, 1))
