@@ -62,7 +62,8 @@ typedef enum {
 typedef struct {
   int32_t m;                /* power-series upper index: sum_{i=0..m}, i.e. m+1 terms (eq. approx1) */
   int32_t rank;             /* r_k, Arnoldi steps (eq. schur); capped at q; 0 disables the correction */
-  int32_t precision;        /* 0: FP64 apply; 1: FP32 apply with BF16 V (FGMRES and Arnoldi stay FP64) */
+  int32_t precision;        /* 0: FP64 apply; 1: FP32 apply (FP32 V); 2: FP32 apply with V stored in
+                               BF16.  FGMRES and Arnoldi stay FP64 in every mode */
   int32_t want_transpose;   /* nonzero: also build the layouts pslr_apply_transpose needs */
   const double* v0;         /* optional host Arnoldi start vector of length q (interface order) */
   uint64_t seed;            /* used when v0 == NULL: SplitMix64 uniform in [-0.5, 0.5) */

@@ -183,6 +183,7 @@ struct pslr_ctx {
   const double* V64 = nullptr;
   const double* G64 = nullptr;
   const __hip_bfloat16* Vbf = nullptr;
+  const float* V32 = nullptr;
   const float* G32 = nullptr;
   int nchunk = 256;
   // apply workspaces
@@ -375,18 +376,42 @@ pslr_status ensure_ws(pslr_ctx* h, int nrhs) {
   return PSLR_OK;
 }
 
+// V^T y partial sums and the expansion y += V G V^T y in the handle's V storage type.
 template <typename T>
-struct LowRank;
+hipError_t lowrank_partial(pslr_ctx* h, const T* y, int64_t ldy, int nrhs, T* part, hipStream_t s);
 template <>
-struct LowRank<double> {
-  static const double* V(pslr_ctx* h) { return h->V64; }
-  static const double* G(pslr_ctx* h) { return h->G64; }
-};
+hipError_t lowrank_partial<double>(pslr_ctx* h, const double* y, int64_t ldy, int nrhs, double* part,
+                                   hipStream_t s) {
+  return launch_lr_partial<double, double>(h->R.q, h->k, h->V64, y, ldy, nrhs, h->nchunk, part, s);
+}
 template <>
-struct LowRank<float> {
-  static const __hip_bfloat16* V(pslr_ctx* h) { return h->Vbf; }
-  static const float* G(pslr_ctx* h) { return h->G32; }
-};
+hipError_t lowrank_partial<float>(pslr_ctx* h, const float* y, int64_t ldy, int nrhs, float* part,
+                                  hipStream_t s) {
+  if (h->Vbf)
+    return launch_lr_partial<float, __hip_bfloat16>(h->R.q, h->k, h->Vbf, y, ldy, nrhs, h->nchunk,
+                                                    part, s);
+  return launch_lr_partial<float, float>(h->R.q, h->k, h->V32, y, ldy, nrhs, h->nchunk, part, s);
+}
+template <typename T>
+hipError_t lowrank_expand(pslr_ctx* h, const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs,
+                          int gtrans, const T* part, T* y, int64_t ldy, int do_c0, T* u, int64_t ldu);
+template <>
+hipError_t lowrank_expand<double>(pslr_ctx* h, const ApplyArrays<double>& A, const LaunchCfg& c,
+                                  int nrhs, int gtrans, const double* part, double* y, int64_t ldy,
+                                  int do_c0, double* u, int64_t ldu) {
+  return launch_lr_expand<double, double>(A, c, nrhs, h->k, h->V64, h->G64, gtrans, part, h->nchunk,
+                                          y, ldy, do_c0, u, ldu);
+}
+template <>
+hipError_t lowrank_expand<float>(pslr_ctx* h, const ApplyArrays<float>& A, const LaunchCfg& c,
+                                 int nrhs, int gtrans, const float* part, float* y, int64_t ldy,
+                                 int do_c0, float* u, int64_t ldu) {
+  if (h->Vbf)
+    return launch_lr_expand<float, __hip_bfloat16>(A, c, nrhs, h->k, h->Vbf, h->G32, gtrans, part,
+                                                   h->nchunk, y, ldy, do_c0, u, ldu);
+  return launch_lr_expand<float, float>(A, c, nrhs, h->k, h->V32, h->G32, gtrans, part, h->nchunk, y,
+                                        ldy, do_c0, u, ldu);
+}
 
 // z = M^{-1} b (or M^{-T} b) with apply arrays A.
 template <typename T>
@@ -404,9 +429,8 @@ pslr_status run_apply(pslr_ctx* h, const ApplyArrays<T>& A, size_t lds, bool tra
   HIP_TRY(launch_head<T>(A, cfg, nrhs, b, ldb, y, q));
   if (!transpose) {
     if (k > 0) {
-      HIP_TRY((launch_lr_partial<T>(h->R.q, k, LowRank<T>::V(h), y, q, nrhs, h->nchunk, part, s)));
-      HIP_TRY((launch_lr_expand<T>(A, cfg, nrhs, k, LowRank<T>::V(h), LowRank<T>::G(h), 0, part,
-                                   h->nchunk, y, q, 1, ua, q)));
+      HIP_TRY(lowrank_partial<T>(h, y, q, nrhs, part, s));
+      HIP_TRY(lowrank_expand<T>(h, A, cfg, nrhs, 0, part, y, q, 1, ua, q));
     } else {
       HIP_TRY(launch_c0solve<T>(A, cfg, nrhs, y, q, ua, q));
     }
@@ -421,9 +445,8 @@ pslr_status run_apply(pslr_ctx* h, const ApplyArrays<T>& A, size_t lds, bool tra
       std::swap(ua, ub);
     }
     if (k > 0) {
-      HIP_TRY((launch_lr_partial<T>(h->R.q, k, LowRank<T>::V(h), ua, q, nrhs, h->nchunk, part, s)));
-      HIP_TRY((launch_lr_expand<T>(A, cfg, nrhs, k, LowRank<T>::V(h), LowRank<T>::G(h), 1, part,
-                                   h->nchunk, ua, q, 0, ub, q)));
+      HIP_TRY(lowrank_partial<T>(h, ua, q, nrhs, part, s));
+      HIP_TRY(lowrank_expand<T>(h, A, cfg, nrhs, 1, part, ua, q, 0, ub, q));
     }
   }
   HIP_TRY(launch_tail<T>(A, cfg, nrhs, b, ldb, ua, q, z, ldz));
@@ -433,7 +456,7 @@ pslr_status run_apply(pslr_ctx* h, const ApplyArrays<T>& A, size_t lds, bool tra
 pslr_status apply_dir(pslr_ctx* h, bool transpose, int nrhs, const double* b, int64_t ldb, double* z,
                       int64_t ldz, hipStream_t s, bool force64 = false) {
   if (h->R.n == 0) return PSLR_OK;
-  if (h->precision == 1 && !force64 && h->have32)
+  if (h->precision >= 1 && !force64 && h->have32)
     return run_apply<float>(h, transpose ? h->tr32 : h->fw32, h->lds32, transpose, nrhs, b, ldb, z,
                             ldz, s);
   if (!h->have64) return fail(PSLR_EINVAL, "FP64 apply arrays not available");
@@ -485,6 +508,7 @@ pslr_status upload_lowrank(pslr_ctx* h) {
   h->vpool.release();
   h->V64 = h->G64 = nullptr;
   h->Vbf = nullptr;
+  h->V32 = nullptr;
   h->G32 = nullptr;
   const int k = h->k;
   const int64_t q = h->R.q;
@@ -497,12 +521,20 @@ pslr_status upload_lowrank(pslr_ctx* h) {
     HIP_TRY(h->vpool.upload(Vr, &h->V64));
     HIP_TRY(h->vpool.upload(h->hG, &h->G64));
   } else {
-    std::vector<__hip_bfloat16> Vr((size_t)q * k);
-    for (int64_t r = 0; r < q; ++r)
-      for (int j = 0; j < k; ++j) Vr[(size_t)r * k + j] = __float2bfloat16((float)h->hV[(size_t)j * q + r]);
     std::vector<float> G32(h->hG.begin(), h->hG.end());
-    HIP_TRY(h->vpool.upload(Vr, &h->Vbf));
     HIP_TRY(h->vpool.upload(G32, &h->G32));
+    if (h->precision == 2) {
+      std::vector<__hip_bfloat16> Vr((size_t)q * k);
+      for (int64_t r = 0; r < q; ++r)
+        for (int j = 0; j < k; ++j)
+          Vr[(size_t)r * k + j] = __float2bfloat16((float)h->hV[(size_t)j * q + r]);
+      HIP_TRY(h->vpool.upload(Vr, &h->Vbf));
+    } else {
+      std::vector<float> Vr((size_t)q * k);
+      for (int64_t r = 0; r < q; ++r)
+        for (int j = 0; j < k; ++j) Vr[(size_t)r * k + j] = (float)h->hV[(size_t)j * q + r];
+      HIP_TRY(h->vpool.upload(Vr, &h->V32));
+    }
   }
   return PSLR_OK;
 }
@@ -631,8 +663,8 @@ void fill_info(pslr_ctx* h, const std::vector<BlockFactor>& fB, const std::vecto
   I.fill_lowrank = ((double)h->R.q * h->k + (double)h->k * h->k) / nA;
   I.fill_total = I.fill_lu + I.fill_lowrank;
   // algorithmic bytes: factor/matrix data once per use, vectors once per read/write
-  const int w = h->precision == 1 ? 4 : 8;
-  const int wv = h->precision == 1 ? 2 : 8;
+  const int w = h->precision >= 1 ? 4 : 8;
+  const int wv = h->precision == 2 ? 2 : w;
   const int m = h->m;
   const int64_t p = h->R.p, q = h->R.q, n = h->R.n, k = h->k;
   const int64_t bB = bytes[0], bC = bytes[1], bEF = bytes[2], bCg = bytes[3];
@@ -851,7 +883,7 @@ pslr_status pslr_setup(int64_t n, const int64_t* rowptr, const int32_t* colind, 
   if (opt) o = *opt;
   if (o.m < 0) return fail(PSLR_EINVAL, "m < 0");
   if (o.rank < 0) return fail(PSLR_EINVAL, "rank < 0");
-  if (o.precision != 0 && o.precision != 1) return fail(PSLR_EINVAL, "precision must be 0 or 1");
+  if (o.precision < 0 || o.precision > 2) return fail(PSLR_EINVAL, "precision must be 0, 1 or 2");
   const double tau = o.pivot_threshold > 0 ? o.pivot_threshold : 0.1;
   for (int64_t k = 0; k < (n > 0 ? rowptr[n] : 0); ++k)
     if (!std::isfinite(vals[k])) return fail(PSLR_EINVAL, "non-finite value in A");
@@ -935,7 +967,7 @@ pslr_status pslr_setup(int64_t n, const int64_t* rowptr, const int32_t* colind, 
   if (st) return st;
   const double t3 = now_s();
 
-  if (h->precision == 1) {
+  if (h->precision >= 1) {
     HIP_TRY(upload_dir<float>(h->pool, h->R, fB, fC, Dfw, false, d_int_ptr, d_if_ptr, d_if_orig,
                               h->fw32, bytes));
     h->lds32 = lds_bytes(h->fw32, h->rank);
@@ -946,7 +978,7 @@ pslr_status pslr_setup(int64_t n, const int64_t* rowptr, const int32_t* colind, 
   if (h->want_T) {
     DirHost Dtr = build_dir(h->R, Bk, fB, fC, true);
     int64_t tb[4];
-    if (h->precision == 1) {
+    if (h->precision >= 1) {
       HIP_TRY(upload_dir<float>(h->pool, h->R, fB, fC, Dtr, true, d_int_ptr, d_if_ptr, d_if_orig,
                                 h->tr32, tb));
       h->lds32 = std::max(h->lds32, lds_bytes(h->tr32, h->rank));

@@ -498,6 +498,12 @@ template hipError_t launch_lr_partial<double, double>(int64_t, int, const double
 template hipError_t launch_lr_partial<float, __hip_bfloat16>(int64_t, int, const __hip_bfloat16*,
                                                              const float*, int64_t, int, int,
                                                              float*, hipStream_t);
+template hipError_t launch_lr_partial<float, float>(int64_t, int, const float*, const float*,
+                                                    int64_t, int, int, float*, hipStream_t);
+template hipError_t launch_lr_expand<float, float>(const ApplyArrays<float>&, const LaunchCfg&, int,
+                                                   int, const float*, const float*, int,
+                                                   const float*, int, float*, int64_t, int, float*,
+                                                   int64_t);
 template hipError_t launch_lr_expand<double, double>(const ApplyArrays<double>&, const LaunchCfg&,
                                                      int, int, const double*, const double*, int,
                                                      const double*, int, double*, int64_t, int,

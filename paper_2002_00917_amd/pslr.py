@@ -129,9 +129,11 @@ def _vec(t, n):
         if t.shape[0] != n or t.stride(0) != 1:
             raise ValueError("bad vector shape")
         return C.c_void_p(t.data_ptr()), 1, n
-    if t.dim() != 2 or t.shape[1] != n or t.stride(1) != 1:
+    if t.dim() != 2 or t.shape[1] != n or (n > 1 and t.stride(1) != 1):
         raise ValueError("expected shape (nrhs, n) with unit stride along n")
-    return C.c_void_p(t.data_ptr()), t.shape[0], t.stride(0)
+    # the stride of a size-1 dimension carries no layout information
+    ld = t.stride(0) if t.shape[0] > 1 else n
+    return C.c_void_p(t.data_ptr()), t.shape[0], ld
 
 
 # ----------------------------------------------------------------- handle
