@@ -133,6 +133,20 @@ pslr_status pslr_sddmm_grad(pslr_handle h, int32_t nrhs, const double* lambda, i
 
 pslr_status pslr_info(pslr_handle h, pslr_info_t* out);
 
+/* Phase timers of the apply.  While enabled, every apply records HIP events on
+ * its stream before and after each of its kernel launches; pslr_trace_read
+ * waits for the recorded events and returns the summed elapsed times per
+ * phase (head: B^{-1} f and g - F t; lowrank: V G V^T and the C0 solve it is
+ * fused with or the plain C0 solve; series: each power-series step launch;
+ * tail: x = B^{-1}(f - E u) and the scatter).  reset != 0 clears the sums. */
+typedef struct {
+  int64_t applies;
+  int64_t series_launches;
+  double ms_head, ms_lowrank, ms_series, ms_tail;
+} pslr_trace_t;
+pslr_status pslr_trace_enable(pslr_handle h, int32_t enable);
+pslr_status pslr_trace_read(pslr_handle h, pslr_trace_t* out, int32_t reset);
+
 /* Replace V and H (host, column-major q x k and k x k) and recompute G; k = 0
  * removes the low-rank correction.  Used to apply an externally computed
  * Arnoldi basis. */

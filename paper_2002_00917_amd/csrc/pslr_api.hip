@@ -8,13 +8,14 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <memory>
 #include <string>
 #include <vector>
 
 #include "../../include/pslr.h"
-#include "pslr_dev.h"
 #include "pslr_host.h"
+#include "pslr_dev.h"
 
 using namespace pslr;
 
@@ -76,57 +77,52 @@ struct TriBytes {
   int64_t val = 0, idx = 0, meta = 0;  // algorithmic bytes split by kind (values counted as entries)
 };
 
-// Concatenate one factor family over all blocks with absolute offsets.
+// Concatenate one factor family over all blocks.
 template <typename T>
-hipError_t upload_tri(DevPool& pool, const std::vector<BlockFactor>& F, TriHost BlockFactor::*mem,
-                      TriArrays<T>& out, int& max_lrows, int64_t& nval, int64_t& nidx,
-                      int64_t& nmeta) {
+hipError_t upload_tri(DevPool& pool, const std::vector<BlockFactor>& F, TriPacked BlockFactor::*mem,
+                      TriArrays<T>& out, int& max_lrows, int64_t& bytes) {
   std::vector<DevTriBlock> blk(F.size());
-  std::vector<int32_t> lev_ptr, lev_g, lrows, row_sn, col, ridx;
-  std::vector<DevSn> sn;
-  std::vector<int64_t> rp;
+  std::vector<int32_t> lev_ptr, lev_g, rec, col, ridx;
   std::vector<T> val, tri;
-  nval = nidx = nmeta = 0;
+  bytes = 0;
   for (size_t i = 0; i < F.size(); ++i) {
-    const TriHost& H = F[i].*mem;
+    const TriPacked& H = F[i].*mem;
     DevTriBlock& B = blk[i];
     B.n = H.n;
     B.nlev = H.nlev;
     B.max_lrows = H.max_lrows;
     B.lower = H.lower ? 1 : 0;
     B.lev_base = (int64_t)lev_ptr.size();
-    B.row_base = (int64_t)lrows.size();
-    B.rp_base = (int64_t)rp.size();
-    B.sn_base = (int64_t)sn.size();
+    B.rec_base = (int64_t)rec.size() / 8;
+    B.val_base = (int64_t)val.size();
+    B.ridx_base = (int64_t)ridx.size();
+    B.tri_base = (int64_t)tri.size();
     max_lrows = std::max(max_lrows, H.max_lrows);
-    const int64_t vb = (int64_t)val.size(), tb = (int64_t)tri.size(), rb = (int64_t)ridx.size();
     lev_ptr.insert(lev_ptr.end(), H.lev_ptr.begin(), H.lev_ptr.end());
     lev_g.insert(lev_g.end(), H.lev_g.begin(), H.lev_g.end());
     lev_g.push_back(0);
-    lrows.insert(lrows.end(), H.lrows.begin(), H.lrows.end());
-    row_sn.insert(row_sn.end(), H.row_sn.begin(), H.row_sn.end());
-    for (int64_t v : H.rp) rp.push_back(v + vb);
-    col.insert(col.end(), H.col.begin(), H.col.end());
+    rec.insert(rec.end(), H.rec.begin(), H.rec.end());
     for (double v : H.val) val.push_back((T)v);
+    if (H.lower) col.insert(col.end(), H.col.begin(), H.col.end());
+    else col.resize(val.size(), 0);
     ridx.insert(ridx.end(), H.ridx.begin(), H.ridx.end());
     for (double v : H.tri) tri.push_back((T)v);
-    for (const SnHost& S : H.sn)
-      sn.push_back(DevSn{S.f, S.w, S.h, 0, S.tri_off + tb, S.panel_off + vb, S.ridx_off + rb});
-    nval += (int64_t)H.val.size() + (int64_t)H.tri.size();
-    nidx += (int64_t)H.col.size() + (int64_t)H.ridx.size();
-    nmeta += (H.lower ? 8 * (int64_t)(H.n + 1) : 0) + 8 * (int64_t)H.n +
-             (int64_t)sizeof(DevSn) * (int64_t)H.sn.size() + 8 * (int64_t)(H.nlev + 1);
+    // algorithmic bytes of one solve: every value once, its index (lower) or the
+    // supernode column list (upper) once, one record per row, the level table
+    bytes += (int64_t)(H.val.size() + H.tri.size()) * (int64_t)sizeof(T) +
+             4 * (int64_t)(H.lower ? H.col.size() : H.ridx.size()) + 32 * (int64_t)H.n +
+             8 * (int64_t)(H.nlev + 1);
   }
+  if (col.size() < val.size()) col.resize(val.size(), 0);
   hipError_t e;
   if ((e = pool.upload(blk, &out.blk))) return e;
   if ((e = pool.upload(lev_ptr, &out.lev_ptr))) return e;
   if ((e = pool.upload(lev_g, &out.lev_g))) return e;
-  if ((e = pool.upload(lrows, &out.lrows))) return e;
-  if ((e = pool.upload(row_sn, &out.row_sn))) return e;
-  if ((e = pool.upload(sn, &out.sn))) return e;
-  if ((e = pool.upload(rp, &out.rp))) return e;
-  if ((e = pool.upload(col, &out.col))) return e;
+  const int32_t* recp = nullptr;
+  if ((e = pool.upload(rec, &recp))) return e;
+  out.rec = reinterpret_cast<const int4*>(recp);
   if ((e = pool.upload(val, &out.val))) return e;
+  if ((e = pool.upload(col, &out.col))) return e;
   if ((e = pool.upload(ridx, &out.ridx))) return e;
   if ((e = pool.upload(tri, &out.tri))) return e;
   return hipSuccess;
@@ -175,7 +171,7 @@ struct pslr_ctx {
   ApplyArrays<double> fw64{}, tr64{};
   ApplyArrays<float> fw32{}, tr32{};
   bool have64 = false, have32 = false, haveT = false;
-  int threads = 512;
+  int threads = kSolveThreads;
   size_t lds64 = 0, lds32 = 0;
   // low rank: Vcm (FP64 q x k column-major, host), H, G; device V row-major and G
   int32_t k = 0;
@@ -194,6 +190,14 @@ struct pslr_ctx {
   void* partial = nullptr;
   // info
   pslr_info_t info{};
+  // phase tracing: each traced apply leaves a list of (phase, event) marks
+  bool trace = false;
+  std::vector<hipEvent_t> ev_free, ev_all;
+  std::deque<std::vector<std::pair<int, hipEvent_t>>> ev_pending;
+  pslr_trace_t tr{};
+  ~pslr_ctx() {
+    for (hipEvent_t e : ev_all) (void)hipEventDestroy(e);
+  }
 };
 
 namespace {
@@ -328,18 +332,18 @@ hipError_t upload_dir(DevPool& pool, const Reordering& R, const std::vector<Bloc
   A.if_ptr = d_if_ptr;
   A.if_orig = d_if_orig;
   int mlr = 0;
-  int64_t v, x, mt;
-  TriHost BlockFactor::*lo = transpose ? &BlockFactor::loT : &BlockFactor::lo;
-  TriHost BlockFactor::*up = transpose ? &BlockFactor::upT : &BlockFactor::up;
+  int64_t by;
+  TriPacked BlockFactor::*lo = transpose ? &BlockFactor::loT : &BlockFactor::lo;
+  TriPacked BlockFactor::*up = transpose ? &BlockFactor::upT : &BlockFactor::up;
   const int w = (int)sizeof(T);
-  if ((e = upload_tri(pool, fB, lo, A.LB, mlr, v, x, mt))) return e;
-  bytes_out[0] = v * w + x * 4 + mt;
-  if ((e = upload_tri(pool, fB, up, A.UB, mlr, v, x, mt))) return e;
-  bytes_out[0] += v * w + x * 4 + mt;
-  if ((e = upload_tri(pool, fC, lo, A.LC, mlr, v, x, mt))) return e;
-  bytes_out[1] = v * w + x * 4 + mt;
-  if ((e = upload_tri(pool, fC, up, A.UC, mlr, v, x, mt))) return e;
-  bytes_out[1] += v * w + x * 4 + mt;
+  if ((e = upload_tri(pool, fB, lo, A.LB, mlr, by))) return e;
+  bytes_out[0] = by;
+  if ((e = upload_tri(pool, fB, up, A.UB, mlr, by))) return e;
+  bytes_out[0] += by;
+  if ((e = upload_tri(pool, fC, lo, A.LC, mlr, by))) return e;
+  bytes_out[1] = by;
+  if ((e = upload_tri(pool, fC, up, A.UC, mlr, by))) return e;
+  bytes_out[1] += by;
   A.maxLR = std::max(mlr, 1);
   A.maxPB = A.maxQB = 1;
   for (int i = 0; i < R.nparts; ++i) {
@@ -413,6 +417,62 @@ hipError_t lowrank_expand<float>(pslr_ctx* h, const ApplyArrays<float>& A, const
                                         ldy, do_c0, u, ldu);
 }
 
+enum { PH_START = -1, PH_HEAD = 0, PH_LOWRANK = 1, PH_SERIES = 2, PH_TAIL = 3 };
+
+// Sum the elapsed times of completed traced applies (all of them if wait).
+hipError_t trace_collect(pslr_ctx* h, bool wait) {
+  while (!h->ev_pending.empty()) {
+    auto& marks = h->ev_pending.front();
+    hipEvent_t last = marks.back().second;
+    if (wait) {
+      hipError_t e = hipEventSynchronize(last);
+      if (e != hipSuccess) return e;
+    } else if (hipEventQuery(last) != hipSuccess) {
+      break;
+    }
+    for (size_t i = 1; i < marks.size(); ++i) {
+      float ms = 0.f;
+      hipError_t e = hipEventElapsedTime(&ms, marks[i - 1].second, marks[i].second);
+      if (e != hipSuccess) return e;
+      switch (marks[i].first) {
+        case PH_HEAD: h->tr.ms_head += ms; break;
+        case PH_LOWRANK: h->tr.ms_lowrank += ms; break;
+        case PH_SERIES: h->tr.ms_series += ms; h->tr.series_launches++; break;
+        case PH_TAIL: h->tr.ms_tail += ms; break;
+      }
+    }
+    h->tr.applies++;
+    for (auto& mk : marks) h->ev_free.push_back(mk.second);
+    h->ev_pending.pop_front();
+  }
+  return hipSuccess;
+}
+
+struct Tracer {
+  pslr_ctx* h;
+  hipStream_t s;
+  std::vector<std::pair<int, hipEvent_t>> marks;
+  hipError_t mark(int phase) {
+    if (!h->trace) return hipSuccess;
+    hipEvent_t e;
+    if (!h->ev_free.empty()) {
+      e = h->ev_free.back();
+      h->ev_free.pop_back();
+    } else {
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return r;
+      h->ev_all.push_back(e);
+    }
+    marks.push_back({phase, e});
+    return hipEventRecord(e, s);
+  }
+  hipError_t finish() {
+    if (!h->trace) return hipSuccess;
+    h->ev_pending.push_back(std::move(marks));
+    return trace_collect(h, h->ev_pending.size() > 512);
+  }
+};
+
 // z = M^{-1} b (or M^{-T} b) with apply arrays A.
 template <typename T>
 pslr_status run_apply(pslr_ctx* h, const ApplyArrays<T>& A, size_t lds, bool transpose, int nrhs,
@@ -426,7 +486,10 @@ pslr_status run_apply(pslr_ctx* h, const ApplyArrays<T>& A, size_t lds, bool tra
   T* ub = (T*)h->u1;
   T* part = (T*)h->partial;
   const int k = h->k;
+  Tracer tr{h, s, {}};
+  HIP_TRY(tr.mark(PH_START));
   HIP_TRY(launch_head<T>(A, cfg, nrhs, b, ldb, y, q));
+  HIP_TRY(tr.mark(PH_HEAD));
   if (!transpose) {
     if (k > 0) {
       HIP_TRY(lowrank_partial<T>(h, y, q, nrhs, part, s));
@@ -434,22 +497,29 @@ pslr_status run_apply(pslr_ctx* h, const ApplyArrays<T>& A, size_t lds, bool tra
     } else {
       HIP_TRY(launch_c0solve<T>(A, cfg, nrhs, y, q, ua, q));
     }
+    HIP_TRY(tr.mark(PH_LOWRANK));
     for (int i = 0; i < h->m; ++i) {
       HIP_TRY(launch_series<T>(A, cfg, nrhs, y, q, ua, ub, q, 1, 1));
+      HIP_TRY(tr.mark(PH_SERIES));
       std::swap(ua, ub);
     }
   } else {
     HIP_TRY(launch_c0solve<T>(A, cfg, nrhs, y, q, ua, q));
+    HIP_TRY(tr.mark(PH_LOWRANK));
     for (int i = 0; i < h->m; ++i) {
       HIP_TRY(launch_series<T>(A, cfg, nrhs, y, q, ua, ub, q, 1, 1));
+      HIP_TRY(tr.mark(PH_SERIES));
       std::swap(ua, ub);
     }
     if (k > 0) {
       HIP_TRY(lowrank_partial<T>(h, ua, q, nrhs, part, s));
       HIP_TRY(lowrank_expand<T>(h, A, cfg, nrhs, 1, part, ua, q, 0, ub, q));
+      HIP_TRY(tr.mark(PH_LOWRANK));
     }
   }
   HIP_TRY(launch_tail<T>(A, cfg, nrhs, b, ldb, ua, q, z, ldz));
+  HIP_TRY(tr.mark(PH_TAIL));
+  HIP_TRY(tr.finish());
   return PSLR_OK;
 }
 
@@ -1170,6 +1240,20 @@ pslr_status pslr_info(pslr_handle h, pslr_info_t* out) {
   if (!h || !out) return fail(PSLR_EINVAL, "null argument");
   *out = h->info;
   out->rank = h->k;
+  return PSLR_OK;
+}
+
+pslr_status pslr_trace_enable(pslr_handle h, int32_t enable) {
+  if (!h) return fail(PSLR_EINVAL, "null handle");
+  h->trace = enable != 0;
+  return PSLR_OK;
+}
+
+pslr_status pslr_trace_read(pslr_handle h, pslr_trace_t* out, int32_t reset) {
+  if (!h) return fail(PSLR_EINVAL, "null handle");
+  HIP_TRY(trace_collect(h, true));
+  if (out) *out = h->tr;
+  if (reset) h->tr = pslr_trace_t{};
   return PSLR_OK;
 }
 

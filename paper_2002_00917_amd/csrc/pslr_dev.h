@@ -8,19 +8,16 @@
 
 namespace pslr {
 
-// Supernode of a packed triangular factor (mirrors the host SnHost layout).
-struct DevSn {
-  int32_t f, w, h, pad;
-  int64_t tri_off, panel_off, ridx_off;
-};
-
-// Per-block descriptor of one packed triangular factor.
+// Per-block descriptor of one packed triangular factor (see TriPacked): rows
+// and factor data are stored level by level; a row record is 8 int32 =
+// {p, off_begin, off_len, ridx_begin, tri_begin, tri_len, rb_first, 0}.
 struct DevTriBlock {
   int32_t n, nlev, max_lrows, lower;
   int64_t lev_base;   // lev_ptr[lev_base .. +nlev], lev_g[lev_base .. +nlev)
-  int64_t row_base;   // lrows / row_sn [row_base .. +n)
-  int64_t rp_base;    // rp[rp_base .. +n] (lower factors)
-  int64_t sn_base;    // sn[sn_base + s]
+  int64_t rec_base;   // row records, in rows
+  int64_t val_base;   // val (and col for lower factors)
+  int64_t ridx_base;  // upper factors: supernode column lists
+  int64_t tri_base;   // inverted diagonal triangles
 };
 
 // One family of packed triangular factors (e.g. "L of every B_i").
@@ -29,12 +26,9 @@ struct TriArrays {
   const DevTriBlock* blk;
   const int32_t* lev_ptr;
   const int32_t* lev_g;
-  const int32_t* lrows;
-  const int32_t* row_sn;
-  const DevSn* sn;
-  const int64_t* rp;
-  const int32_t* col;
+  const int4* rec;
   const T* val;
+  const int32_t* col;
   const int32_t* ridx;
   const T* tri;
 };

@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <thread>
@@ -224,7 +225,7 @@ struct ND {
   const Graph& g;
   std::vector<int> tag, lev, order, queue;
   int ntag = 1;
-  static const int kLeaf = 8;
+  int kLeaf = 8;
   explicit ND(const Graph& gr) : g(gr), tag(gr.n, 0), lev(gr.n, -1), queue(gr.n) {}
 
   // BFS from r inside tag t; returns number reached, fills queue[0..cnt) in BFS order.
@@ -470,11 +471,10 @@ int factor_block(const CsrL& M, double tau, bool want_T, BlockFactor& out, std::
   out = BlockFactor();
   out.n = n;
   if (n == 0) {
-    for (TriHost* T : {&out.lo, &out.up, &out.loT, &out.upT}) {
+    for (TriPacked* T : {&out.lo, &out.up, &out.loT, &out.upT}) {
       T->n = 0;
       T->nlev = 0;
       T->lev_ptr.assign(1, 0);
-      T->rp.assign(1, 0);
     }
     out.lo.lower = out.loT.lower = true;
     out.up.lower = out.upT.lower = false;
@@ -486,6 +486,7 @@ int factor_block(const CsrL& M, double tau, bool want_T, BlockFactor& out, std::
   // --- ordering: nested dissection, then etree postorder
   Graph g = block_graph(M);
   ND nd(g);
+  if (const char* e = getenv("PSLR_ND_LEAF")) nd.kLeaf = atoi(e);
   {
     std::vector<int> all(n);
     std::iota(all.begin(), all.end(), 0);
@@ -540,6 +541,47 @@ int factor_block(const CsrL& M, double tau, bool want_T, BlockFactor& out, std::
     if (!join) sfirst.push_back(j);
   }
   sfirst.push_back(n);
+  // relaxed amalgamation of single-child chains: a supernode whose parent has
+  // no other child is merged into it when the explicit zeros this adds stay
+  // small, which shortens the level schedule of the triangular solves
+  {
+    const int ns0 = (int)sfirst.size() - 1;
+    std::vector<int> snode0(n), par0(ns0, -1), nch(ns0, 0);
+    for (int s = 0; s < ns0; ++s)
+      for (int j = sfirst[s]; j < sfirst[s + 1]; ++j) snode0[j] = s;
+    for (int s = 0; s < ns0; ++s) {
+      const std::vector<int>& Rs = st[sfirst[s + 1] - 1];
+      if (!Rs.empty()) {
+        par0[s] = snode0[Rs[0]];
+        nch[par0[s]]++;
+      }
+    }
+    std::vector<int> gfirst(sfirst.begin(), sfirst.end() - 1);
+    std::vector<double> truenz(ns0);
+    std::vector<char> absorbed(ns0, 0);
+    for (int s = 0; s < ns0; ++s) {
+      const double w = sfirst[s + 1] - sfirst[s], h = (double)st[sfirst[s + 1] - 1].size();
+      truenz[s] = w * (w - 1) / 2 + w * h;
+    }
+    for (int s = 1; s < ns0; ++s) {
+      if (par0[s - 1] != s) continue;
+      const int c = s - 1;
+      const double mw = (double)(sfirst[s + 1] - gfirst[c]);
+      const double hp = (double)st[sfirst[s + 1] - 1].size();
+      const double dense = mw * (mw - 1) / 2 + mw * hp;
+      const double tnz = truenz[c] + truenz[s];
+      if (mw <= 512 && (mw <= 16 || dense - tnz <= 0.3 * dense)) {
+        gfirst[s] = gfirst[c];
+        truenz[s] = tnz;
+        absorbed[c] = 1;
+      }
+    }
+    std::vector<int> sf2;
+    for (int s = 0; s < ns0; ++s)
+      if (!absorbed[s]) sf2.push_back(gfirst[s]);
+    sf2.push_back(n);
+    sfirst.swap(sf2);
+  }
   const int ns = (int)sfirst.size() - 1;
   out.nsuper = ns;
   std::vector<int> snode(n);
@@ -727,7 +769,7 @@ int factor_block(const CsrL& M, double tau, bool want_T, BlockFactor& out, std::
     }
   };
   // packed inverted triangles: lower rows hold columns 0..i, upper rows i..w-1
-  auto pack_tri = [&](TriHost& T, int s, const std::vector<double>& Xinv, bool transpose) {
+  auto pack_inv = [&](TriHost& T, int s, const std::vector<double>& Xinv, bool transpose) {
     const int w = T.sn[s].w;
     T.sn[s].tri_off = (int64_t)T.tri.size();
     for (int i = 0; i < w; ++i) {
@@ -781,64 +823,138 @@ int factor_block(const CsrL& M, double tau, bool want_T, BlockFactor& out, std::
           T.val.push_back(fromL ? Lp[s][(size_t)a * w + i] : Up[s][(size_t)i * h + a]);
     }
   };
-  init_tri(out.lo, true);
-  build_lower_rows(out.lo, false);
-  for (int s = 0; s < ns; ++s) pack_tri(out.lo, s, invL[s], false);
-  build_levels(out.lo, sfirst, height, nlev);
-  init_tri(out.up, false);
-  build_upper_panels(out.up, false);
-  out.up.rp.assign(1, 0);
-  for (int s = 0; s < ns; ++s) pack_tri(out.up, s, invU[s], false);
-  build_levels(out.up, sfirst, height, nlev);
+  {
+    TriHost T;
+    init_tri(T, true);
+    build_lower_rows(T, false);
+    for (int s = 0; s < ns; ++s) pack_inv(T, s, invL[s], false);
+    build_levels(T, sfirst, height, nlev);
+    pack_tri(T, out.lo);
+  }
+  {
+    TriHost T;
+    init_tri(T, false);
+    build_upper_panels(T, false);
+    T.rp.assign(1, 0);
+    for (int s = 0; s < ns; ++s) pack_inv(T, s, invU[s], false);
+    build_levels(T, sfirst, height, nlev);
+    pack_tri(T, out.up);
+  }
   if (want_T) {
-    init_tri(out.loT, true);
-    build_lower_rows(out.loT, true);
-    for (int s = 0; s < ns; ++s) pack_tri(out.loT, s, invU[s], true);
-    build_levels(out.loT, sfirst, height, nlev);
-    init_tri(out.upT, false);
-    build_upper_panels(out.upT, true);
-    out.upT.rp.assign(1, 0);
-    for (int s = 0; s < ns; ++s) pack_tri(out.upT, s, invL[s], true);
-    build_levels(out.upT, sfirst, height, nlev);
+    {
+      TriHost T;
+      init_tri(T, true);
+      build_lower_rows(T, true);
+      for (int s = 0; s < ns; ++s) pack_inv(T, s, invU[s], true);
+      build_levels(T, sfirst, height, nlev);
+      pack_tri(T, out.loT);
+    }
+    {
+      TriHost T;
+      init_tri(T, false);
+      build_upper_panels(T, true);
+      T.rp.assign(1, 0);
+      for (int s = 0; s < ns; ++s) pack_inv(T, s, invL[s], true);
+      build_levels(T, sfirst, height, nlev);
+      pack_tri(T, out.upT);
+    }
   }
   return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Device layout
+// ---------------------------------------------------------------------------
+
+namespace {
+// Lanes per row: enough that one unrolled batch of 8 entries per lane covers
+// the average row, widened while the level leaves threads idle.
+int lanes_for(double avg, int rows) {
+  int g = 1;
+  while (g < 64 && g * 8 < avg) g *= 2;
+  while (g < 64 && (int64_t)rows * g * 2 <= kSolveThreads && g < avg) g *= 2;
+  return g;
+}
+}  // namespace
+
+void pack_tri(const TriHost& T, TriPacked& P) {
+  P = TriPacked();
+  P.lower = T.lower;
+  P.n = T.n;
+  P.nlev = T.nlev;
+  P.max_lrows = T.max_lrows;
+  P.lev_ptr = T.lev_ptr;
+  P.lev_g.assign(T.nlev, 0);
+  P.rec.assign((size_t)8 * T.n, 0);
+  std::vector<int32_t> ridx_at(T.sn.size(), -1);
+  for (int l = 0; l < T.nlev; ++l) {
+    double s1 = 0, s2 = 0;
+    const int b = T.lev_ptr[l], e = T.lev_ptr[l + 1];
+    for (int k = b; k < e; ++k) {
+      const int p = T.lrows[k];
+      const int sidx = T.row_sn[p];
+      const SnHost& S = T.sn[sidx];
+      const int i = p - S.f;
+      int32_t* r = &P.rec[(size_t)8 * k];
+      r[0] = p;
+      r[1] = (int32_t)P.val.size();
+      if (T.lower) {
+        for (int64_t q = T.rp[p]; q < T.rp[p + 1]; ++q) {
+          P.val.push_back(T.val[q]);
+          P.col.push_back(T.col[q]);
+        }
+        r[2] = (int32_t)(T.rp[p + 1] - T.rp[p]);
+        r[3] = 0;
+      } else {
+        const double* pr = &T.val[S.panel_off + (int64_t)i * S.h];
+        P.val.insert(P.val.end(), pr, pr + S.h);
+        r[2] = S.h;
+        if (ridx_at[sidx] < 0) {
+          ridx_at[sidx] = (int32_t)P.ridx.size();
+          P.ridx.insert(P.ridx.end(), T.ridx.begin() + S.ridx_off, T.ridx.begin() + S.ridx_off + S.h);
+        }
+        r[3] = ridx_at[sidx];
+      }
+      const int64_t toff = T.lower ? (int64_t)i * (i + 1) / 2
+                                   : (int64_t)i * S.w - (int64_t)i * (i - 1) / 2;
+      const int tlen = T.lower ? i + 1 : S.w - i;
+      r[4] = (int32_t)P.tri.size();
+      P.tri.insert(P.tri.end(), T.tri.begin() + S.tri_off + toff,
+                   T.tri.begin() + S.tri_off + toff + tlen);
+      r[5] = tlen;
+      r[6] = T.lower ? (k - b) - i : (k - b);
+      r[7] = 0;
+      s1 += r[2];
+      s2 += tlen;
+    }
+    const int cnt = e - b;
+    const int g1 = cnt ? lanes_for(s1 / cnt, cnt) : 1;
+    const int g2 = cnt ? lanes_for(s2 / cnt, cnt) : 1;
+    P.lev_g[l] = g1 | (g2 << 8);
+  }
 }
 
 // ---------------------------------------------------------------------------
 // Host execution of a packed factor (diagnostics)
 // ---------------------------------------------------------------------------
 
-void host_tri_solve(const TriHost& T, std::vector<double>& X) {
+void host_tri_solve(const TriPacked& T, std::vector<double>& X) {
   std::vector<double> Rb(std::max(T.max_lrows, 1));
   for (int li = 0; li < T.nlev; ++li) {
     const int l = T.lower ? li : T.nlev - 1 - li;
     const int b = T.lev_ptr[l], e = T.lev_ptr[l + 1];
     for (int k = b; k < e; ++k) {
-      const int p = T.lrows[k];
-      const SnHost& S = T.sn[T.row_sn[p]];
+      const int32_t* r = &T.rec[(size_t)8 * k];
       double acc = 0.0;
-      if (T.lower) {
-        for (int64_t q = T.rp[p]; q < T.rp[p + 1]; ++q) acc += T.val[q] * X[T.col[q]];
-      } else {
-        const double* pr = &T.val[S.panel_off + (int64_t)(p - S.f) * S.h];
-        for (int a = 0; a < S.h; ++a) acc += pr[a] * X[T.ridx[S.ridx_off + a]];
-      }
-      Rb[k - b] = X[p] - acc;
+      for (int j = 0; j < r[2]; ++j)
+        acc += T.val[r[1] + j] * X[T.lower ? T.col[r[1] + j] : T.ridx[r[3] + j]];
+      Rb[k - b] = X[r[0]] - acc;
     }
     for (int k = b; k < e; ++k) {
-      const int p = T.lrows[k];
-      const SnHost& S = T.sn[T.row_sn[p]];
-      const int i = p - S.f, base = k - b - i;
+      const int32_t* r = &T.rec[(size_t)8 * k];
       double acc = 0.0;
-      if (T.lower) {
-        const double* tr = &T.tri[S.tri_off + (int64_t)i * (i + 1) / 2];
-        for (int c = 0; c <= i; ++c) acc += tr[c] * Rb[base + c];
-      } else {
-        const int64_t off = (int64_t)i * S.w - (int64_t)i * (i - 1) / 2;
-        const double* tr = &T.tri[S.tri_off + off];
-        for (int c = i; c < S.w; ++c) acc += tr[c - i] * Rb[base + c];
-      }
-      X[p] = acc;
+      for (int j = 0; j < r[5]; ++j) acc += T.tri[r[4] + j] * Rb[r[6] + j];
+      X[r[0]] = acc;
     }
   }
 }

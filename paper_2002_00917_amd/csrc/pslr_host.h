@@ -57,6 +57,29 @@ struct TriHost {
   int64_t off_nnz() const { return (int64_t)val.size(); }
 };
 
+// Threads of the workgroup that solves one block; lane-group widths are sized for it.
+constexpr int kSolveThreads = 1024;
+
+// Device layout of one packed triangular factor of one block.  Rows are stored
+// level by level (the order of TriHost::lrows) and so is all factor data, so
+// every level reads one contiguous stretch of memory.  Each row has one record
+// of 8 int32 (offsets relative to the block's arrays):
+//   [0] position p             [1] off-diagonal start (val/col or panel val)
+//   [2] off-diagonal length    [3] upper: start of the supernode's column list
+//   [4] triangle-row start     [5] triangle-row length
+//   [6] first scratch index of the triangle row (level-local)   [7] unused
+// Solving level l: r_k = X[p] - sum_j off[j] * X[col_j] for all rows k of the
+// level, then X[p] = sum_j tri[j] * r_{rec[6] + j}.
+struct TriPacked {
+  bool lower = true;
+  int32_t n = 0, nlev = 0, max_lrows = 0;
+  std::vector<int32_t> lev_ptr;   // nlev + 1
+  std::vector<int32_t> lev_g;     // nlev: lanes per row, sweep 1 | (sweep 2 << 8)
+  std::vector<int32_t> rec;       // 8 per row
+  std::vector<double> val, tri;
+  std::vector<int32_t> col, ridx;
+};
+
 // Factorisation of one block M: P (Q M Q^T) = L U with Q a nested-dissection
 // ordering (postordered) and P a row permutation that only permutes rows
 // inside each supernode (restricted threshold partial pivoting).
@@ -65,7 +88,7 @@ struct TriHost {
 struct BlockFactor {
   int32_t n = 0;
   std::vector<int32_t> gin, gout;
-  TriHost lo, up, loT, upT;
+  TriPacked lo, up, loT, upT;
   int64_t nnz_L = 0, nnz_U = 0;   // entries of L and U (diagonal blocks included)
   int32_t nsuper = 0;
 };
@@ -98,8 +121,11 @@ Blocks extract_blocks(int64_t n, const int64_t* rowptr, const int32_t* colind,
 // Apply `fn(i)` for i in [0, count) on `nthreads` host threads.
 void parallel_for(int count, int nthreads, const std::function<void(int)>& fn);
 
-// Host execution of a packed factor pair on one vector (diagnostics only).
-void host_tri_solve(const TriHost& T, std::vector<double>& X);
+// Pack a TriHost into the device layout.
+void pack_tri(const TriHost& T, TriPacked& P);
+
+// Host execution of a packed factor on one vector (diagnostics only).
+void host_tri_solve(const TriPacked& T, std::vector<double>& X);
 
 uint64_t splitmix64_next(uint64_t& state);
 

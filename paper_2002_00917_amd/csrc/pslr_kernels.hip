@@ -28,6 +28,52 @@ __device__ __forceinline__ float tv_to_float(__hip_bfloat16 v) { return __bfloat
 __device__ __forceinline__ float tv_to_float(float v) { return v; }
 __device__ __forceinline__ double tv_to_float(double v) { return v; }
 
+// sum_j v[j] * X[idx[j]] over this lane's share (j = lane, lane+G, ...), with
+// eight independent loads in flight per lane.
+template <typename T>
+__device__ __forceinline__ T dot_gather(const T* __restrict__ v, const int32_t* __restrict__ idx,
+                                        int len, const T* X, int lane, int G) {
+  T a0 = 0, a1 = 0;
+  int j = lane;
+  for (; j + 7 * G < len; j += 8 * G) {
+    T v0 = v[j], v1 = v[j + G], v2 = v[j + 2 * G], v3 = v[j + 3 * G];
+    T v4 = v[j + 4 * G], v5 = v[j + 5 * G], v6 = v[j + 6 * G], v7 = v[j + 7 * G];
+    int c0 = idx[j], c1 = idx[j + G], c2 = idx[j + 2 * G], c3 = idx[j + 3 * G];
+    int c4 = idx[j + 4 * G], c5 = idx[j + 5 * G], c6 = idx[j + 6 * G], c7 = idx[j + 7 * G];
+    a0 += v0 * X[c0];
+    a1 += v1 * X[c1];
+    a0 += v2 * X[c2];
+    a1 += v3 * X[c3];
+    a0 += v4 * X[c4];
+    a1 += v5 * X[c5];
+    a0 += v6 * X[c6];
+    a1 += v7 * X[c7];
+  }
+  for (; j < len; j += G) a0 += v[j] * X[idx[j]];
+  return a0 + a1;
+}
+
+// sum_j v[j] * R[j] over this lane's share, eight loads in flight per lane.
+template <typename T>
+__device__ __forceinline__ T dot_dense(const T* __restrict__ v, int len, const T* R, int lane, int G) {
+  T a0 = 0, a1 = 0;
+  int j = lane;
+  for (; j + 7 * G < len; j += 8 * G) {
+    T v0 = v[j], v1 = v[j + G], v2 = v[j + 2 * G], v3 = v[j + 3 * G];
+    T v4 = v[j + 4 * G], v5 = v[j + 5 * G], v6 = v[j + 6 * G], v7 = v[j + 7 * G];
+    a0 += v0 * R[j];
+    a1 += v1 * R[j + G];
+    a0 += v2 * R[j + 2 * G];
+    a1 += v3 * R[j + 3 * G];
+    a0 += v4 * R[j + 4 * G];
+    a1 += v5 * R[j + 5 * G];
+    a0 += v6 * R[j + 6 * G];
+    a1 += v7 * R[j + 7 * G];
+  }
+  for (; j < len; j += G) a0 += v[j] * R[j];
+  return a0 + a1;
+}
+
 // Solve one packed triangular factor of block `bi` in place on the LDS vector X
 // (positions 0..n-1); Rb is LDS scratch of max_lrows entries.  All threads of
 // the workgroup must call it.  Ends with a barrier.
@@ -35,49 +81,37 @@ template <typename T>
 __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb) {
   const DevTriBlock B = A.blk[bi];
   const int tid = threadIdx.x, nthr = blockDim.x;
+  const int4* rec = A.rec + 2 * B.rec_base;
+  const T* val = A.val + B.val_base;
+  const int32_t* col = A.col + B.val_base;
+  const int32_t* ridx = A.ridx + B.ridx_base;
+  const T* tri = A.tri + B.tri_base;
+  const int32_t* lev_ptr = A.lev_ptr + B.lev_base;
+  const int32_t* lev_g = A.lev_g + B.lev_base;
   for (int li = 0; li < B.nlev; ++li) {
     const int l = B.lower ? li : B.nlev - 1 - li;
-    const int b = A.lev_ptr[B.lev_base + l];
-    const int cnt = A.lev_ptr[B.lev_base + l + 1] - b;
-    const int g = A.lev_g[B.lev_base + l];
+    const int b = lev_ptr[l];
+    const int cnt = lev_ptr[l + 1] - b;
+    const int g = lev_g[l];
     const int G1 = g & 0xff, G2 = (g >> 8) & 0xff;
-    const int32_t* lrows = A.lrows + B.row_base + b;
-    // sweep 1: r_p = x_p - (off-diagonal row p) . x
+    // sweep 1: r_k = x_p - (off-diagonal part of row p) . x
     {
       const int grp = tid / G1, lane = tid - grp * G1, ngrp = nthr / G1;
       for (int k = grp; k < cnt; k += ngrp) {
-        const int p = lrows[k];
-        T acc = 0;
-        if (B.lower) {
-          const int64_t e = A.rp[B.rp_base + p + 1];
-          for (int64_t q = A.rp[B.rp_base + p] + lane; q < e; q += G1) acc += A.val[q] * X[A.col[q]];
-        } else {
-          const DevSn S = A.sn[B.sn_base + A.row_sn[B.row_base + p]];
-          const T* pr = A.val + S.panel_off + (int64_t)(p - S.f) * S.h;
-          const int32_t* ri = A.ridx + S.ridx_off;
-          for (int a = lane; a < S.h; a += G1) acc += pr[a] * X[ri[a]];
-        }
+        const int4 r = rec[2 * (b + k)];
+        T acc = dot_gather(val + r.y, B.lower ? col + r.y : ridx + r.w, r.z, X, lane, G1);
         acc = group_sum(acc, G1);
-        if (lane == 0) Rb[k] = X[p] - acc;
+        if (lane == 0) Rb[k] = X[r.x] - acc;
       }
     }
     __syncthreads();
-    // sweep 2: x_s = inv(T_ss) r_s per supernode
+    // sweep 2: x_s = inv(T_ss) r_s for every supernode of the level
     {
       const int grp = tid / G2, lane = tid - grp * G2, ngrp = nthr / G2;
       for (int k = grp; k < cnt; k += ngrp) {
-        const int p = lrows[k];
-        const DevSn S = A.sn[B.sn_base + A.row_sn[B.row_base + p]];
-        const int i = p - S.f;
-        const T* rb = Rb + (k - i);
-        T acc = 0;
-        if (B.lower) {
-          const T* tr = A.tri + S.tri_off + (int64_t)i * (i + 1) / 2;
-          for (int c = lane; c <= i; c += G2) acc += tr[c] * rb[c];
-        } else {
-          const T* tr = A.tri + S.tri_off + (int64_t)i * S.w - (int64_t)i * (i - 1) / 2 - i;
-          for (int c = i + lane; c < S.w; c += G2) acc += tr[c] * rb[c];
-        }
+        const int p = rec[2 * (b + k)].x;
+        const int4 r = rec[2 * (b + k) + 1];
+        T acc = dot_dense(tri + r.x, r.y, Rb + r.z, lane, G2);
         acc = group_sum(acc, G2);
         if (lane == 0) X[p] = acc;
       }
@@ -105,7 +139,7 @@ __device__ Lds<T> carve(const ApplyArrays<T>& A) {
 
 // t = B^{-1} f;  y = g - F t   (Algorithm 3, line 2)
 template <typename T>
-__global__ void k_head(ApplyArrays<T> A, const double* __restrict__ b, int64_t ldb, T* y,
+__global__ void __launch_bounds__(1024) k_head(ApplyArrays<T> A, const double* __restrict__ b, int64_t ldb, T* y,
                        int64_t ldy) {
   Lds<T> L = carve(A);
   const int i = blockIdx.x, r = blockIdx.y, tid = threadIdx.x, nt = blockDim.x;
@@ -152,7 +186,7 @@ __global__ void k_lr_partial(int64_t q, int k, const TV* __restrict__ V, const T
 
 // y += V (G (V^T y)) on the rows of block i; optionally u = C0^{-1} y (line 3, line 4 start)
 template <typename T, typename TV>
-__global__ void k_lr_expand(ApplyArrays<T> A, int k, const TV* __restrict__ V,
+__global__ void __launch_bounds__(1024) k_lr_expand(ApplyArrays<T> A, int k, const TV* __restrict__ V,
                             const T* __restrict__ G, int gtrans, const T* __restrict__ partial,
                             int nchunk, T* y, int64_t ldy, int do_c0, T* u, int64_t ldu) {
   Lds<T> L = carve(A);
@@ -197,7 +231,7 @@ __global__ void k_lr_expand(ApplyArrays<T> A, int k, const TV* __restrict__ V,
 
 // dst = C0^{-1} src
 template <typename T>
-__global__ void k_c0solve(ApplyArrays<T> A, const T* __restrict__ src, int64_t lds_, T* dst,
+__global__ void __launch_bounds__(1024) k_c0solve(ApplyArrays<T> A, const T* __restrict__ src, int64_t lds_, T* dst,
                           int64_t ldd) {
   Lds<T> L = carve(A);
   const int i = blockIdx.x, r = blockIdx.y, tid = threadIdx.x, nt = blockDim.x;
@@ -214,7 +248,7 @@ __global__ void k_c0solve(ApplyArrays<T> A, const T* __restrict__ src, int64_t l
 // One power-series step (eq. approx1 by its recurrence):
 //   w = E_s u = -C_g u + F B^{-1} E u;  r = [y +] w;  u_next = [C0^{-1}] r
 template <typename T>
-__global__ void k_series(ApplyArrays<T> A, const T* __restrict__ y, int64_t ldy,
+__global__ void __launch_bounds__(1024) k_series(ApplyArrays<T> A, const T* __restrict__ y, int64_t ldy,
                          const T* __restrict__ uprev, T* unext, int64_t ldu, int add_y, int do_c0) {
   Lds<T> L = carve(A);
   const int i = blockIdx.x, r = blockIdx.y, tid = threadIdx.x, nt = blockDim.x;
@@ -251,7 +285,7 @@ __global__ void k_series(ApplyArrays<T> A, const T* __restrict__ y, int64_t ldy,
 
 // x = B^{-1}(f - E u);  z = P^T (x; u)   (Algorithm 3, lines 5-6)
 template <typename T>
-__global__ void k_tail(ApplyArrays<T> A, const double* __restrict__ b, int64_t ldb,
+__global__ void __launch_bounds__(1024) k_tail(ApplyArrays<T> A, const double* __restrict__ b, int64_t ldb,
                        const T* __restrict__ u, int64_t ldu, double* z, int64_t ldz) {
   Lds<T> L = carve(A);
   const int i = blockIdx.x, r = blockIdx.y, tid = threadIdx.x, nt = blockDim.x;

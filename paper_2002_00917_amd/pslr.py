@@ -49,6 +49,11 @@ class pslr_info_t(C.Structure):
                 ("seconds_factor", C.c_double), ("seconds_arnoldi", C.c_double)]
 
 
+class pslr_trace_t(C.Structure):
+    _fields_ = [("applies", C.c_int64), ("series_launches", C.c_int64), ("ms_head", C.c_double),
+                ("ms_lowrank", C.c_double), ("ms_series", C.c_double), ("ms_tail", C.c_double)]
+
+
 _P = C.c_void_p
 _I32P = C.POINTER(C.c_int32)
 _I64P = C.POINTER(C.c_int64)
@@ -64,6 +69,8 @@ _SIGS = {
                                C.c_double, C.c_int32, _I32P, _F64P, _P]),
     "pslr_sddmm_grad": (C.c_int, [_P, C.c_int32, _P, C.c_int64, _P, C.c_int64, _P, _P]),
     "pslr_info": (C.c_int, [_P, C.POINTER(pslr_info_t)]),
+    "pslr_trace_enable": (C.c_int, [_P, C.c_int32]),
+    "pslr_trace_read": (C.c_int, [_P, C.POINTER(pslr_trace_t), C.c_int32]),
     "pslr_set_lowrank": (C.c_int, [_P, C.c_int32, _F64P, C.c_int64, _F64P, C.c_int64]),
     "pslr_get_lowrank": (C.c_int, [_P, _I32P, _F64P, C.c_int64, _F64P, C.c_int64]),
     "pslr_partition_geometric": (C.c_int, [C.c_int32, _I32P, _I32P, _I32P]),
@@ -225,6 +232,16 @@ def pslr_info(h: Handle) -> dict:
     info = pslr_info_t()
     _check(lib().pslr_info(h.ptr, C.byref(info)))
     return {k: getattr(info, k) for k, _ in pslr_info_t._fields_}
+
+
+def pslr_trace_enable(h: Handle, enable=True):
+    _check(lib().pslr_trace_enable(h.ptr, 1 if enable else 0))
+
+
+def pslr_trace_read(h: Handle, reset=False) -> dict:
+    t = pslr_trace_t()
+    _check(lib().pslr_trace_read(h.ptr, C.byref(t), 1 if reset else 0))
+    return {k: getattr(t, k) for k, _ in pslr_trace_t._fields_}
 
 
 def pslr_set_lowrank(h: Handle, V, H):
