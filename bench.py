@@ -34,7 +34,7 @@ sys.path.insert(0, ROOT)
 METRIC = "PSLR-FGMRES solves/s to rel-res 1e-8 (FP64 vs mixed/batched); apply HBM GB/s"
 HBM_PEAK_GBS = 8000.0
 KERNEL_SRC = os.path.join(ROOT, "paper_2002_00917_amd", "csrc", "pslr_kernels.hip")
-PMC_FILE = os.path.join(ROOT, "profiles", "k_series_lap3d64_pmc.json")
+PMC_FILE = os.path.join(ROOT, "profiles", "k_series_lap3d64_pmc.txt")
 
 
 def log(*a):
@@ -47,15 +47,15 @@ def kernel_hash():
 
 
 def measured_traffic():
-    """HBM bytes per k_series launch from committed rocprofv3 counter runs, if current."""
+    """HBM bytes per k_series launch from the committed rocprofv3 counter summary, if current."""
     try:
         with open(PMC_FILE) as fh:
-            d = json.load(fh)
-    except (OSError, ValueError):
+            kv = dict(line.split(" = ", 1) for line in fh.read().splitlines() if " = " in line)
+    except OSError:
         return None
-    if d.get("kernel_source_sha256_16") != kernel_hash():
+    if kv.get("kernel_source_sha256_16", "").strip() != kernel_hash():
         return None
-    return d.get("bytes_per_launch")
+    return float(kv["bytes_per_launch"])
 
 
 def run_form(P, torch, A, lab, b, precision, steps, warmup, m, rank, restart, tol):

@@ -1112,6 +1112,11 @@ pslr_status fgmres_solve(pslr_handle h, int32_t nrhs, const double* b, int64_t l
   HIP_TRY(tmp.alloc<double>((size_t)nrhs * R1, &dout));
   HIP_TRY(tmp.alloc<double>((size_t)nrhs * R1, &dh));
   HIP_TRY(tmp.alloc<double>(nrhs, &scl));
+  double *dh1, *dh2, *dnn;
+  HIP_TRY(tmp.alloc<double>((size_t)nrhs * (2 * R1 + 1), &dh1));
+  dh2 = dh1 + (size_t)nrhs * R1;
+  dnn = dh2 + (size_t)nrhs * R1;
+  std::vector<double> hbuf((size_t)nrhs * (2 * R1 + 1));
   const int64_t ldvr = (int64_t)n * R1, ldzr = (int64_t)n * restart;
   std::vector<double> bn, nn, h1, h2;
   pslr_status st = dots(h, n, 1, b, 0, ldb, b, ldb, nrhs, dbuf, dout, bn, s);
@@ -1156,15 +1161,22 @@ pslr_status fgmres_solve(pslr_handle h, int32_t nrhs, const double* b, int64_t l
       st = apply_dir(h, transpose != 0, nrhs, Vj, ldvr, Zj, ldzr, s);
       if (st) return st;
       HIP_TRY(launch_spmv(n, Ap, Ac, Av, nrhs, Zj, ldzr, W, n, nullptr, 0, s));
-      // classical Gram-Schmidt, two passes
-      st = dots(h, n, j + 1, Vb, n, ldvr, W, n, nrhs, dbuf, dout, h1, s);
-      if (st) return st;
-      HIP_TRY(launch_maxpy(n, j + 1, Vb, n, ldvr, dout, j + 1, W, n, nrhs, 1.0, s));
-      st = dots(h, n, j + 1, Vb, n, ldvr, W, n, nrhs, dbuf, dout, h2, s);
-      if (st) return st;
-      HIP_TRY(launch_maxpy(n, j + 1, Vb, n, ldvr, dout, j + 1, W, n, nrhs, 1.0, s));
-      st = dots(h, n, 1, W, 0, n, W, n, nrhs, dbuf, dout, nn, s);
-      if (st) return st;
+      // classical Gram-Schmidt, two passes, then ||w||; one host synchronisation
+      const int nv = j + 1;
+      HIP_TRY(launch_mdot(n, nv, Vb, n, ldvr, W, n, nrhs, h->nchunk, dbuf, s));
+      HIP_TRY(launch_reduce(h->nchunk, nrhs, nv, dbuf, dh1, s));
+      HIP_TRY(launch_maxpy(n, nv, Vb, n, ldvr, dh1, nv, W, n, nrhs, 1.0, s));
+      HIP_TRY(launch_mdot(n, nv, Vb, n, ldvr, W, n, nrhs, h->nchunk, dbuf, s));
+      HIP_TRY(launch_reduce(h->nchunk, nrhs, nv, dbuf, dh2, s));
+      HIP_TRY(launch_maxpy(n, nv, Vb, n, ldvr, dh2, nv, W, n, nrhs, 1.0, s));
+      HIP_TRY(launch_mdot(n, 1, W, 0, n, W, n, nrhs, h->nchunk, dbuf, s));
+      HIP_TRY(launch_reduce(h->nchunk, nrhs, 1, dbuf, dnn, s));
+      HIP_TRY(hipMemcpyAsync(hbuf.data(), dh1, sizeof(double) * nrhs * (2 * R1 + 1),
+                             hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      h1.assign(hbuf.begin(), hbuf.begin() + (size_t)nrhs * nv);
+      h2.assign(hbuf.begin() + (size_t)nrhs * R1, hbuf.begin() + (size_t)nrhs * R1 + (size_t)nrhs * nv);
+      nn.assign(hbuf.begin() + 2 * (size_t)nrhs * R1, hbuf.begin() + 2 * (size_t)nrhs * R1 + nrhs);
       bool cont = false;
       for (int r = 0; r < nrhs; ++r) {
         if (!act[r]) {

@@ -349,12 +349,19 @@ __global__ void k_mdot(int64_t n, int nv, const double* __restrict__ V, int64_t 
   }
 }
 
+// out[r][i] = sum over chunks of partial[c][r][i]: one workgroup per (i, r)
 __global__ void k_reduce(int nchunk, int nrhs, int nv, const double* __restrict__ partial, double* out) {
-  const int r = blockIdx.x;
-  for (int i = threadIdx.x; i < nv; i += blockDim.x) {
-    double s = 0.0;
-    for (int c = 0; c < nchunk; ++c) s += partial[((int64_t)c * nrhs + r) * nv + i];
-    out[(int64_t)r * nv + i] = s;
+  __shared__ double red[4];
+  const int i = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
+  double s = 0.0;
+  for (int c = tid; c < nchunk; c += blockDim.x) s += partial[((int64_t)c * nrhs + r) * nv + i];
+  s = group_sum(s, 64);
+  if ((tid & 63) == 0) red[tid >> 6] = s;
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+    out[(int64_t)r * nv + i] = t;
   }
 }
 
@@ -481,7 +488,7 @@ hipError_t launch_mdot(int64_t n, int nv, const double* V, int64_t ldv, int64_t 
 
 hipError_t launch_reduce(int nchunk, int nrhs, int nv, const double* partial, double* out,
                          hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce, dim3(nrhs), dim3(64), 0, s, nchunk, nrhs, nv, partial, out);
+  hipLaunchKernelGGL(k_reduce, dim3(nv, nrhs), dim3(256), 0, s, nchunk, nrhs, nv, partial, out);
   return hipGetLastError();
 }
 
