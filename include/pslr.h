@@ -69,6 +69,8 @@ typedef struct {
   uint64_t seed;            /* used when v0 == NULL: SplitMix64 uniform in [-0.5, 0.5) */
   double pivot_threshold;   /* tau of restricted threshold partial pivoting; <= 0 means 0.1 */
   int32_t nthreads;         /* host threads for the factorisation; 0 = hardware concurrency */
+  int32_t working_vectors;  /* 0: subdomain working vectors in LDS when they fit (default);
+                               1: always in a global-memory workspace */
 } pslr_options;
 
 typedef struct {
@@ -84,6 +86,8 @@ typedef struct {
   int64_t apply_bytes_rhs;  /* vector bytes added by each further right-hand side */
   int64_t series_bytes;     /* algorithmic bytes of one power-series step launch, single rhs */
   double seconds_reorder, seconds_factor, seconds_arnoldi;
+  int32_t nsys;             /* systems of a batched handle (1 otherwise) */
+  int32_t global_vectors;   /* 1 when the working vectors live in global memory */
 } pslr_info_t;
 
 /* Fill *opt with defaults: m = 3, rank = 16, FP64, no transpose, seed 1, tau 0.1. */
@@ -101,6 +105,21 @@ void pslr_default_options(pslr_options* opt);
 pslr_status pslr_setup(int64_t n, const int64_t* rowptr, const int32_t* colind, const double* vals,
                        const int32_t* part, int32_t nparts, const pslr_options* opt,
                        void* hip_stream, pslr_handle* out);
+
+/* Batched setup over nsys independent systems stored as one block-diagonal
+ * matrix: system s owns rows sys_ptr[s] .. sys_ptr[s+1]-1 (sys_ptr[0] = 0,
+ * sys_ptr[nsys] = n), no stored entry couples two systems, every subdomain
+ * label belongs to one system and the labels of system s are smaller than
+ * those of system s + 1.  Every stage of an apply then runs one launch over
+ * the subdomains of all systems; each system gets its own r_k-step Arnoldi
+ * basis and G (the processes run together).  fgmres_solve on such a handle
+ * runs one Krylov space per (system, right-hand side) pair and reports
+ * iters/relres for nsys * nrhs pairs, index r * nsys + s.  v0, when given, is
+ * the concatenation of the per-system start vectors (interface order). */
+pslr_status pslr_setup_batched(int64_t n, const int64_t* rowptr, const int32_t* colind,
+                               const double* vals, const int32_t* part, int32_t nparts,
+                               int32_t nsys, const int64_t* sys_ptr, const pslr_options* opt,
+                               void* hip_stream, pslr_handle* out);
 
 /* z = M^{-1} b, the preconditioner of Algorithm 3 (eq. application):
  *   y = g - F B^{-1} f;  y <- y + V G V^T y;  y <- P_m y;  x = B^{-1}(f - E y).
@@ -120,7 +139,8 @@ pslr_status pslr_apply_transpose(pslr_handle h, int32_t nrhs, const double* b, i
  * Givens residual estimate reaches tol * ||b||, confirms with the true FP64
  * residual and restarts if needed; at most maxit inner iterations (the paper's
  * "its" and its 500-iteration failure rule, Sec. 4).  iters[nrhs], relres[nrhs]:
- * host outputs (true relative residuals).  Synchronises the stream. */
+ * host outputs (true relative residuals); nsys * nrhs entries on a batched
+ * handle.  Synchronises the stream. */
 pslr_status fgmres_solve(pslr_handle h, int32_t nrhs, const double* b, int64_t ldb, double* x,
                          int64_t ldx, int32_t restart, int32_t maxit, double tol, int32_t transpose,
                          int32_t* iters, double* relres, void* hip_stream);

@@ -182,12 +182,33 @@ struct pslr_ctx {
   const float* V32 = nullptr;
   const float* G32 = nullptr;
   int nchunk = 256;
+  // systems of a batched handle (one system otherwise): row ranges in the
+  // original ordering, interface ranges, achieved ranks
+  int32_t nsys = 1;
+  std::vector<int64_t> sys_n, sys_q;
+  std::vector<int32_t> sys_k;
+  const int32_t* d_part_sys = nullptr;
+  const LrChunk* d_chunks = nullptr;
+  const int32_t* d_sys_chunk = nullptr;
+  int nchunk_lr = 1;
+  const Seg* d_qcols = nullptr;
+  // global working vectors when a subdomain does not fit in LDS
+  bool gx = false;
+  int64_t gws_stride = 0;
+  const int64_t* d_rb_off = nullptr;
   // apply workspaces
   int ws_nrhs = 0;
   void* y = nullptr;
   void* u0 = nullptr;
   void* u1 = nullptr;
   void* partial = nullptr;
+  void* gws = nullptr;
+  // FGMRES workspace (kept between calls)
+  DevPool fpool;
+  int f_nrhs = 0, f_restart = 0;
+  double *fVb = nullptr, *fZb = nullptr, *fW = nullptr, *fdbuf = nullptr, *fh = nullptr,
+         *fscl = nullptr, *fy = nullptr;
+  Seg *fcolsV = nullptr, *fcolsB = nullptr, *fcolsX = nullptr;
   // info
   pslr_info_t info{};
   // phase tracing: each traced apply leaves a list of (phase, event) marks
@@ -375,7 +396,11 @@ pslr_status ensure_ws(pslr_ctx* h, int nrhs) {
   HIP_TRY(h->ws.alloc<double>(q * nrhs, (double**)&h->y));
   HIP_TRY(h->ws.alloc<double>(q * nrhs, (double**)&h->u0));
   HIP_TRY(h->ws.alloc<double>(q * nrhs, (double**)&h->u1));
-  HIP_TRY(h->ws.alloc<double>((size_t)h->nchunk * nrhs * std::max(h->k, 1), (double**)&h->partial));
+  HIP_TRY(h->ws.alloc<double>((size_t)h->nchunk_lr * nrhs * std::max(h->k, 1), (double**)&h->partial));
+  h->gws = nullptr;
+  if (h->gx) HIP_TRY(h->ws.alloc<double>((size_t)h->gws_stride * nrhs, (double**)&h->gws));
+  for (ApplyArrays<double>* A : {&h->fw64, &h->tr64}) A->gws = h->gws;
+  for (ApplyArrays<float>* A : {&h->fw32, &h->tr32}) A->gws = h->gws;
   h->ws_nrhs = nrhs;
   return PSLR_OK;
 }
@@ -386,15 +411,17 @@ hipError_t lowrank_partial(pslr_ctx* h, const T* y, int64_t ldy, int nrhs, T* pa
 template <>
 hipError_t lowrank_partial<double>(pslr_ctx* h, const double* y, int64_t ldy, int nrhs, double* part,
                                    hipStream_t s) {
-  return launch_lr_partial<double, double>(h->R.q, h->k, h->V64, y, ldy, nrhs, h->nchunk, part, s);
+  return launch_lr_partial<double, double>(h->nchunk_lr, h->d_chunks, h->k, h->V64, y, ldy, nrhs,
+                                           part, s);
 }
 template <>
 hipError_t lowrank_partial<float>(pslr_ctx* h, const float* y, int64_t ldy, int nrhs, float* part,
                                   hipStream_t s) {
   if (h->Vbf)
-    return launch_lr_partial<float, __hip_bfloat16>(h->R.q, h->k, h->Vbf, y, ldy, nrhs, h->nchunk,
-                                                    part, s);
-  return launch_lr_partial<float, float>(h->R.q, h->k, h->V32, y, ldy, nrhs, h->nchunk, part, s);
+    return launch_lr_partial<float, __hip_bfloat16>(h->nchunk_lr, h->d_chunks, h->k, h->Vbf, y, ldy,
+                                                    nrhs, part, s);
+  return launch_lr_partial<float, float>(h->nchunk_lr, h->d_chunks, h->k, h->V32, y, ldy, nrhs, part,
+                                         s);
 }
 template <typename T>
 hipError_t lowrank_expand(pslr_ctx* h, const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs,
@@ -403,8 +430,8 @@ template <>
 hipError_t lowrank_expand<double>(pslr_ctx* h, const ApplyArrays<double>& A, const LaunchCfg& c,
                                   int nrhs, int gtrans, const double* part, double* y, int64_t ldy,
                                   int do_c0, double* u, int64_t ldu) {
-  return launch_lr_expand<double, double>(A, c, nrhs, h->k, h->V64, h->G64, gtrans, part, h->nchunk,
-                                          y, ldy, do_c0, u, ldu);
+  return launch_lr_expand<double, double>(A, c, nrhs, h->k, h->V64, h->G64, gtrans, part,
+                                          h->nchunk_lr, h->d_sys_chunk, y, ldy, do_c0, u, ldu);
 }
 template <>
 hipError_t lowrank_expand<float>(pslr_ctx* h, const ApplyArrays<float>& A, const LaunchCfg& c,
@@ -412,9 +439,10 @@ hipError_t lowrank_expand<float>(pslr_ctx* h, const ApplyArrays<float>& A, const
                                  int do_c0, float* u, int64_t ldu) {
   if (h->Vbf)
     return launch_lr_expand<float, __hip_bfloat16>(A, c, nrhs, h->k, h->Vbf, h->G32, gtrans, part,
-                                                   h->nchunk, y, ldy, do_c0, u, ldu);
-  return launch_lr_expand<float, float>(A, c, nrhs, h->k, h->V32, h->G32, gtrans, part, h->nchunk, y,
-                                        ldy, do_c0, u, ldu);
+                                                   h->nchunk_lr, h->d_sys_chunk, y, ldy, do_c0, u,
+                                                   ldu);
+  return launch_lr_expand<float, float>(A, c, nrhs, h->k, h->V32, h->G32, gtrans, part, h->nchunk_lr,
+                                        h->d_sys_chunk, y, ldy, do_c0, u, ldu);
 }
 
 enum { PH_START = -1, PH_HEAD = 0, PH_LOWRANK = 1, PH_SERIES = 2, PH_TAIL = 3 };
@@ -526,6 +554,8 @@ pslr_status run_apply(pslr_ctx* h, const ApplyArrays<T>& A, size_t lds, bool tra
 pslr_status apply_dir(pslr_ctx* h, bool transpose, int nrhs, const double* b, int64_t ldb, double* z,
                       int64_t ldz, hipStream_t s, bool force64 = false) {
   if (h->R.n == 0) return PSLR_OK;
+  pslr_status st = ensure_ws(h, nrhs);
+  if (st != PSLR_OK) return st;
   if (h->precision >= 1 && !force64 && h->have32)
     return run_apply<float>(h, transpose ? h->tr32 : h->fw32, h->lds32, transpose, nrhs, b, ldb, z,
                             ldz, s);
@@ -573,7 +603,8 @@ bool compute_G(int k, const std::vector<double>& H, std::vector<double>& G) {
   return true;
 }
 
-// Upload V (row-major, apply precision) and G for the current hV/hH.
+// Upload V (union q x k row-major, apply precision) and one G per system for
+// the current hV (q x k column-major) and hH (nsys blocks of k x k column-major).
 pslr_status upload_lowrank(pslr_ctx* h) {
   h->vpool.release();
   h->V64 = h->G64 = nullptr;
@@ -583,7 +614,17 @@ pslr_status upload_lowrank(pslr_ctx* h) {
   const int k = h->k;
   const int64_t q = h->R.q;
   if (k == 0) return PSLR_OK;
-  if (!compute_G(k, h->hH, h->hG)) return fail(PSLR_ESINGULAR, "I - H is singular");
+  h->hG.assign((size_t)h->nsys * k * k, 0.0);
+  for (int s = 0; s < h->nsys; ++s) {
+    const int ks = h->sys_k[s];
+    if (ks == 0) continue;
+    std::vector<double> Hs((size_t)ks * ks), Gs;
+    for (int j = 0; j < ks; ++j)
+      for (int i = 0; i < ks; ++i) Hs[(size_t)j * ks + i] = h->hH[(size_t)s * k * k + (size_t)j * k + i];
+    if (!compute_G(ks, Hs, Gs)) return fail(PSLR_ESINGULAR, "I - H is singular");
+    for (int i = 0; i < ks; ++i)
+      for (int j = 0; j < ks; ++j) h->hG[(size_t)s * k * k + (size_t)i * k + j] = Gs[(size_t)i * ks + j];
+  }
   if (h->precision == 0) {
     std::vector<double> Vr((size_t)q * k);
     for (int64_t r = 0; r < q; ++r)
@@ -622,24 +663,34 @@ pslr_status dots(pslr_ctx* h, int64_t n, int nv, const double* V, int64_t ldv, i
 }
 
 // r_k-step Arnoldi on E_rr(m) = (E_s C0^{-1})^{m+1} (Theorem t2), classical
-// Gram-Schmidt with one full re-orthogonalisation, FP64 on the device.
+// Gram-Schmidt with one full re-orthogonalisation, FP64 on the device.  The
+// systems of a batched handle run their Arnoldi processes together: E_rr is
+// block diagonal by system, and the Gram-Schmidt sums are taken per system.
 pslr_status arnoldi(pslr_ctx* h, const double* v0host, uint64_t seed, hipStream_t s, bool& breakdown) {
   const int64_t q = h->R.q;
-  int kreq = (int)std::min<int64_t>(h->rank, q);
+  const int ns = h->nsys;
+  int64_t qmax = 0;
+  for (int c = 0; c < ns; ++c) qmax = std::max(qmax, h->sys_q[c + 1] - h->sys_q[c]);
+  int kreq = (int)std::min<int64_t>(h->rank, qmax);
   breakdown = false;
   h->k = 0;
+  h->sys_k.assign(ns, 0);
   h->hV.clear();
   h->hH.clear();
   if (kreq <= 0) return upload_lowrank(h);
   DevPool tmp;
-  double *Vd, *w, *ua, *ub, *dbuf, *dout, *scl;
+  double *Vd, *w, *ua, *ub, *dbuf, *dhh, *scl;
   HIP_TRY(tmp.alloc<double>((size_t)q * (kreq + 1), &Vd));
   HIP_TRY(tmp.alloc<double>(q, &w));
   HIP_TRY(tmp.alloc<double>(q, &ua));
   HIP_TRY(tmp.alloc<double>(q, &ub));
-  HIP_TRY(tmp.alloc<double>((size_t)h->nchunk * (kreq + 1), &dbuf));
-  HIP_TRY(tmp.alloc<double>(kreq + 1, &dout));
-  HIP_TRY(tmp.alloc<double>(1, &scl));
+  HIP_TRY(tmp.alloc<double>((size_t)h->nchunk * ns * (kreq + 1), &dbuf));
+  HIP_TRY(tmp.alloc<double>((size_t)ns * (2 * (kreq + 1) + 2), &dhh));
+  HIP_TRY(tmp.alloc<double>(ns, &scl));
+  double* dh1 = dhh;
+  double* dh2 = dhh + (size_t)ns * (kreq + 1);
+  double* dnn = dh2 + (size_t)ns * (kreq + 1);
+  double* dwn = dnn + ns;
   std::vector<double> v(q);
   if (v0host) {
     std::copy(v0host, v0host + q, v.begin());
@@ -647,16 +698,26 @@ pslr_status arnoldi(pslr_ctx* h, const double* v0host, uint64_t seed, hipStream_
     uint64_t st = seed;
     for (int64_t i = 0; i < q; ++i) v[i] = (double)(splitmix64_next(st) >> 11) * 0x1.0p-53 - 0.5;
   }
-  double nv = 0.0;
-  for (double x : v) nv += x * x;
-  nv = std::sqrt(nv);
-  if (!(nv > 0.0)) return fail(PSLR_EINVAL, "Arnoldi start vector is zero");
-  for (double& x : v) x /= nv;
+  std::vector<int> active(ns, 0);
+  for (int c = 0; c < ns; ++c) {
+    double nv = 0.0;
+    for (int64_t i = h->sys_q[c]; i < h->sys_q[c + 1]; ++i) nv += v[i] * v[i];
+    nv = std::sqrt(nv);
+    const int64_t qc = h->sys_q[c + 1] - h->sys_q[c];
+    if (nv > 0.0 && qc > 0) {
+      active[c] = 1;
+      for (int64_t i = h->sys_q[c]; i < h->sys_q[c + 1]; ++i) v[i] /= nv;
+    } else {
+      for (int64_t i = h->sys_q[c]; i < h->sys_q[c + 1]; ++i) v[i] = 0.0;
+    }
+  }
   HIP_TRY(hipMemcpy(Vd, v.data(), sizeof(double) * q, hipMemcpyHostToDevice));
   const ApplyArrays<double>& A = h->fw64;
   LaunchCfg cfg{h->threads, h->lds64, s};
-  std::vector<double> Hb((size_t)(kreq + 1) * kreq, 0.0), hv, hv2, nn;
-  int kdone = kreq;
+  std::vector<double> Hb((size_t)ns * (kreq + 1) * kreq, 0.0), hb((size_t)ns * (2 * (kreq + 1) + 2)),
+      sc(ns);
+  std::vector<int> kdone(ns, 0);
+  const Seg* cols = h->d_qcols;
   for (int j = 0; j < kreq; ++j) {
     const double* cur = Vd + (size_t)j * q;
     for (int r = 0; r <= h->m; ++r) {
@@ -664,39 +725,61 @@ pslr_status arnoldi(pslr_ctx* h, const double* v0host, uint64_t seed, hipStream_
       HIP_TRY(launch_series<double>(A, cfg, 1, ua, q, ua, ub, q, 0, 0));
       cur = ub;
     }
-    // cur == ub holds E_rr v_j
-    HIP_TRY(hipMemcpyAsync(w, cur, sizeof(double) * q, hipMemcpyDeviceToDevice, s));
-    pslr_status st = dots(h, q, 1, w, q, 0, w, q, 1, dbuf, dout, nn, s);
-    if (st) return st;
-    const double wnorm = std::sqrt(nn[0]);
-    st = dots(h, q, j + 1, Vd, q, 0, w, q, 1, dbuf, dout, hv, s);
-    if (st) return st;
-    HIP_TRY(hipMemcpyAsync(dout, hv.data(), sizeof(double) * (j + 1), hipMemcpyHostToDevice, s));
-    HIP_TRY(launch_maxpy(q, j + 1, Vd, q, 0, dout, j + 1, w, q, 1, 1.0, s));
-    st = dots(h, q, j + 1, Vd, q, 0, w, q, 1, dbuf, dout, hv2, s);
-    if (st) return st;
-    HIP_TRY(launch_maxpy(q, j + 1, Vd, q, 0, dout, j + 1, w, q, 1, 1.0, s));
-    for (int i = 0; i <= j; ++i) Hb[(size_t)j * (kreq + 1) + i] = hv[i] + hv2[i];
-    st = dots(h, q, 1, w, q, 0, w, q, 1, dbuf, dout, nn, s);
-    if (st) return st;
-    const double hn = std::sqrt(nn[0]);
-    Hb[(size_t)j * (kreq + 1) + j + 1] = hn;
-    if (hn <= 1e-14 * wnorm) {
-      kdone = j + 1;
-      breakdown = kdone < kreq;
-      break;
-    }
-    const double inv = 1.0 / hn;
-    HIP_TRY(hipMemcpyAsync(scl, &inv, sizeof(double), hipMemcpyHostToDevice, s));
-    HIP_TRY(launch_scale(q, w, q, scl, Vd + (size_t)(j + 1) * q, q, 1, s));
+    HIP_TRY(hipMemcpyAsync(w, ub, sizeof(double) * q, hipMemcpyDeviceToDevice, s));
+    const int nv = j + 1;
+    HIP_TRY(launch_mdot_seg(ns, cols, cols, 1, w, 0, w, h->nchunk, dbuf, s));
+    HIP_TRY(launch_reduce(h->nchunk, ns, 1, dbuf, dwn, s));
+    HIP_TRY(launch_mdot_seg(ns, cols, cols, nv, Vd, q, w, h->nchunk, dbuf, s));
+    HIP_TRY(launch_reduce(h->nchunk, ns, nv, dbuf, dh1, s));
+    HIP_TRY(launch_maxpy_seg(ns, cols, cols, qmax, nv, Vd, q, dh1, nv, w, 1.0, s));
+    HIP_TRY(launch_mdot_seg(ns, cols, cols, nv, Vd, q, w, h->nchunk, dbuf, s));
+    HIP_TRY(launch_reduce(h->nchunk, ns, nv, dbuf, dh2, s));
+    HIP_TRY(launch_maxpy_seg(ns, cols, cols, qmax, nv, Vd, q, dh2, nv, w, 1.0, s));
+    HIP_TRY(launch_mdot_seg(ns, cols, cols, 1, w, 0, w, h->nchunk, dbuf, s));
+    HIP_TRY(launch_reduce(h->nchunk, ns, 1, dbuf, dnn, s));
+    HIP_TRY(hipMemcpyAsync(hb.data(), dhh, sizeof(double) * hb.size(), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    const double* h1 = hb.data();
+    const double* h2 = h1 + (size_t)ns * (kreq + 1);
+    const double* nn = h2 + (size_t)ns * (kreq + 1);
+    const double* wn = nn + ns;
+    bool any = false;
+    for (int c = 0; c < ns; ++c) {
+      sc[c] = 0.0;
+      if (!active[c]) continue;
+      double* Hc = &Hb[((size_t)c * kreq + j) * (kreq + 1)];
+      for (int i = 0; i <= j; ++i) Hc[i] = h1[(size_t)c * nv + i] + h2[(size_t)c * nv + i];
+      const double hn = std::sqrt(nn[c]);
+      Hc[j + 1] = hn;
+      const int64_t qc = h->sys_q[c + 1] - h->sys_q[c];
+      if (hn <= 1e-14 * std::sqrt(wn[c]) || j + 1 >= qc) {
+        kdone[c] = j + 1;
+        active[c] = 0;
+        if (j + 1 < kreq && j + 1 < qc) breakdown = true;
+        continue;
+      }
+      kdone[c] = j + 1;
+      sc[c] = 1.0 / hn;
+      any = true;
+    }
+    if (!any) break;
+    HIP_TRY(hipMemcpyAsync(scl, sc.data(), sizeof(double) * ns, hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_scale_seg(ns, cols, cols, qmax, w, scl, Vd + (size_t)(j + 1) * q, s));
   }
-  h->k = kdone;
-  h->hV.resize((size_t)q * kdone);
-  HIP_TRY(hipMemcpy(h->hV.data(), Vd, sizeof(double) * q * kdone, hipMemcpyDeviceToHost));
-  h->hH.assign((size_t)kdone * kdone, 0.0);
-  for (int j = 0; j < kdone; ++j)
-    for (int i = 0; i < kdone; ++i) h->hH[(size_t)j * kdone + i] = Hb[(size_t)j * (kreq + 1) + i];
+  int kmax = 0;
+  for (int c = 0; c < ns; ++c) kmax = std::max(kmax, kdone[c]);
+  h->k = kmax;
+  h->sys_k = kdone;
+  h->hV.assign((size_t)q * kmax, 0.0);
+  if (kmax > 0) HIP_TRY(hipMemcpy(h->hV.data(), Vd, sizeof(double) * q * kmax, hipMemcpyDeviceToHost));
+  for (int c = 0; c < ns; ++c)  // columns beyond a system's rank are zero on its rows
+    for (int j = kdone[c]; j < kmax; ++j)
+      for (int64_t r = h->sys_q[c]; r < h->sys_q[c + 1]; ++r) h->hV[(size_t)j * q + r] = 0.0;
+  h->hH.assign((size_t)ns * kmax * kmax, 0.0);
+  for (int c = 0; c < ns; ++c)
+    for (int j = 0; j < kdone[c]; ++j)
+      for (int i = 0; i < kdone[c]; ++i)
+        h->hH[(size_t)c * kmax * kmax + (size_t)j * kmax + i] = Hb[((size_t)c * kreq + j) * (kreq + 1) + i];
   return upload_lowrank(h);
 }
 
@@ -747,6 +830,8 @@ void fill_info(pslr_ctx* h, const std::vector<BlockFactor>& fB, const std::vecto
                           (int64_t)(8 + w) * n * 2;
   I.apply_bytes = matrix + vectors;
   I.apply_bytes_rhs = vectors;
+  I.nsys = h->nsys;
+  I.global_vectors = h->gx ? 1 : 0;
 }
 
 }  // namespace
@@ -768,6 +853,7 @@ void pslr_default_options(pslr_options* o) {
   o->seed = 1;
   o->pivot_threshold = 0.1;
   o->nthreads = 0;
+  o->working_vectors = 0;
 }
 
 const char* pslr_status_string(pslr_status s) {
@@ -939,9 +1025,15 @@ pslr_status pslr_host_selfcheck(int64_t n, const int64_t* rowptr, const int32_t*
   return PSLR_OK;
 }
 
-pslr_status pslr_setup(int64_t n, const int64_t* rowptr, const int32_t* colind, const double* vals,
-                       const int32_t* part, int32_t nparts, const pslr_options* opt,
-                       void* hip_stream, pslr_handle* out) {
+}  // extern "C"
+
+namespace {
+
+// Setup of a handle over nsys independent systems (rows sys_ptr[s] ..
+// sys_ptr[s+1]); a plain handle is the case nsys = 1.
+pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, const double* vals,
+                       const int32_t* part, int32_t nparts, int32_t nsys, const int64_t* sys_ptr,
+                       const pslr_options* opt, void* hip_stream, pslr_handle* out) {
   if (!out) return fail(PSLR_EINVAL, "out is NULL");
   *out = nullptr;
   pslr_status st = validate_csr(n, rowptr, colind);
@@ -965,8 +1057,39 @@ pslr_status pslr_setup(int64_t n, const int64_t* rowptr, const int32_t* colind, 
   h->precision = o.precision;
   h->want_T = o.want_transpose ? 1 : 0;
   h->nnzA = n > 0 ? rowptr[n] : 0;
+  // systems: rows, subdomain labels and couplings must not straddle two systems,
+  // and the labels of system s must precede those of system s + 1
+  h->nsys = nsys;
+  h->sys_n.assign(sys_ptr, sys_ptr + nsys + 1);
+  if (h->sys_n[0] != 0 || h->sys_n[nsys] != n) return fail(PSLR_EINVAL, "sys_ptr must span 0..n");
+  std::vector<int32_t> lab_sys(nparts, -1), row_sys(n);
+  for (int s = 0; s < nsys; ++s) {
+    if (h->sys_n[s + 1] < h->sys_n[s]) return fail(PSLR_EINVAL, "sys_ptr not non-decreasing");
+    for (int64_t i = h->sys_n[s]; i < h->sys_n[s + 1]; ++i) {
+      row_sys[i] = s;
+      if (lab_sys[part[i]] >= 0 && lab_sys[part[i]] != s)
+        return fail(PSLR_EINVAL, "a subdomain label is used by two systems");
+      lab_sys[part[i]] = s;
+    }
+  }
+  for (int l = 0, last = 0; l < nparts; ++l) {
+    if (lab_sys[l] < 0) lab_sys[l] = last;
+    if (lab_sys[l] < last) return fail(PSLR_EINVAL, "subdomain labels must be ordered by system");
+    last = lab_sys[l];
+  }
+  if (nsys > 1)
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
+        if (row_sys[colind[k]] != row_sys[i]) return fail(PSLR_EINVAL, "A couples two systems");
   const double t0 = now_s();
   h->R = reorder(n, rowptr, colind, part, nparts);
+  h->sys_q.assign(nsys + 1, h->R.q);
+  h->sys_q[0] = 0;
+  {
+    std::vector<int64_t> qs(nsys, 0);
+    for (int l = 0; l < nparts; ++l) qs[lab_sys[l]] += h->R.if_ptr[l + 1] - h->R.if_ptr[l];
+    for (int s = 0; s < nsys; ++s) h->sys_q[s + 1] = h->sys_q[s] + qs[s];
+  }
   Blocks Bk = extract_blocks(n, rowptr, colind, vals, h->R);
   const double t1 = now_s();
   const int np = nparts;
@@ -1017,6 +1140,34 @@ pslr_status pslr_setup(int64_t n, const int64_t* rowptr, const int32_t* colind, 
     HIP_TRY(h->pool.upload(h->R.if_ptr, &d_if_ptr));
     HIP_TRY(h->pool.upload(if_orig, &d_if_orig));
   }
+  // per-system tables: subdomain -> system, V^T y row chunks, interface segments
+  {
+    std::vector<int32_t> ps(nparts);
+    for (int l = 0; l < nparts; ++l) ps[l] = lab_sys[l];
+    HIP_TRY(h->pool.upload(ps, &h->d_part_sys));
+    std::vector<LrChunk> ch;
+    std::vector<int32_t> sc(nsys + 1, 0);
+    const int64_t qtot = std::max<int64_t>(h->R.q, 1);
+    for (int s = 0; s < nsys; ++s) {
+      const int64_t q0 = h->sys_q[s], qs = h->sys_q[s + 1] - q0;
+      if (qs > 0) {
+        const int64_t c = std::max<int64_t>(1, (int64_t)std::llround((double)h->nchunk * qs / qtot));
+        const int64_t rows = (qs + c - 1) / c;
+        for (int64_t r0 = 0; r0 < qs; r0 += rows)
+          ch.push_back(LrChunk{q0 + r0, q0 + std::min(qs, r0 + rows), s, 0});
+      }
+      sc[s + 1] = (int32_t)ch.size();
+    }
+    if (ch.empty()) ch.push_back(LrChunk{0, 0, 0, 0});
+    h->nchunk_lr = (int)ch.size();
+    HIP_TRY(h->pool.upload(ch, &h->d_chunks));
+    HIP_TRY(h->pool.upload(sc, &h->d_sys_chunk));
+    std::vector<Seg> qc(nsys);
+    for (int s = 0; s < nsys; ++s) qc[s] = Seg{h->sys_q[s], h->sys_q[s + 1] - h->sys_q[s]};
+    const Seg* dq = nullptr;
+    HIP_TRY(h->pool.upload(qc, &dq));
+    h->d_qcols = dq;
+  }
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, h->device));
   const size_t lds_max = prop.sharedMemPerBlock > 0 ? prop.sharedMemPerBlock : 65536;
@@ -1025,24 +1176,59 @@ pslr_status pslr_setup(int64_t n, const int64_t* rowptr, const int32_t* colind, 
   HIP_TRY(upload_dir<double>(h->pool, h->R, fB, fC, Dfw, false, d_int_ptr, d_if_ptr, d_if_orig,
                              h->fw64, bytes));
   h->lds64 = lds_bytes(h->fw64, h->rank);
-  if (h->lds64 > lds_max)
-    return fail(PSLR_ENOTSUP, "a subdomain needs " + std::to_string(h->lds64) +
-                                  " bytes of LDS in FP64 (limit " + std::to_string(lds_max) + ")");
-  HIP_TRY(set_lds_limit<double>(h->lds64));
+  // subdomains too large for LDS: working vectors in a global workspace
+  {
+    const size_t need32 = lds_bytes(h->fw64, h->rank) / 2;
+    const bool need_gx = (h->precision == 0 ? h->lds64 : need32) > lds_max ||
+                         (h->want_T && h->precision == 0 && h->lds64 > lds_max);
+    h->gx = need_gx || o.working_vectors == 1;
+    if (h->gx) {
+      std::vector<int64_t> rb(nparts + 1, 0);
+      for (int i = 0; i < nparts; ++i) {
+        int mx = 1;
+        for (const BlockFactor* f : {&fB[i], &fC[i]})
+          for (const TriPacked* T : {&f->lo, &f->up, &f->loT, &f->upT}) mx = std::max(mx, T->max_lrows);
+        rb[i + 1] = rb[i] + mx;
+      }
+      HIP_TRY(h->pool.upload(rb, &h->d_rb_off));
+      h->gws_stride = h->R.p + 2 * h->R.q + rb[nparts] + (int64_t)nparts * 2 * std::max(h->rank, 1);
+      h->lds64 = 0;
+    }
+  }
+  auto set_gx = [&](auto& A) {
+    A.part_sys = h->d_part_sys;
+    A.gshift = 0;
+    A.gws = nullptr;
+    A.gws_stride = h->gws_stride;
+    A.rb_off = h->d_rb_off;
+    A.kmax = std::max(h->rank, 1);
+  };
+  set_gx(h->fw64);
+  if (!h->gx) HIP_TRY(set_lds_limit<double>(h->lds64));
   h->have64 = true;
+  if (h->gx) {
+    st = ensure_ws(h.get(), 1);
+    if (st) return st;
+  }
 
   // Arnoldi on E_rr(m) in FP64 (Algorithm 4, lines 6-8)
   bool breakdown = false;
+  h->ws.release();
+  h->ws_nrhs = 0;
+  st = ensure_ws(h.get(), 1);
+  if (st) return st;
   st = arnoldi(h.get(), o.v0, o.seed, s, breakdown);
   if (st) return st;
+  h->ws.release();  // the V^T y partial sums are sized by the achieved rank
+  h->ws_nrhs = 0;
   const double t3 = now_s();
 
   if (h->precision >= 1) {
     HIP_TRY(upload_dir<float>(h->pool, h->R, fB, fC, Dfw, false, d_int_ptr, d_if_ptr, d_if_orig,
                               h->fw32, bytes));
-    h->lds32 = lds_bytes(h->fw32, h->rank);
-    if (h->lds32 > lds_max) return fail(PSLR_ENOTSUP, "a subdomain needs too much LDS in FP32");
-    HIP_TRY(set_lds_limit<float>(h->lds32));
+    set_gx(h->fw32);
+    h->lds32 = h->gx ? 0 : lds_bytes(h->fw32, h->rank);
+    if (!h->gx) HIP_TRY(set_lds_limit<float>(h->lds32));
     h->have32 = true;
   }
   if (h->want_T) {
@@ -1051,15 +1237,22 @@ pslr_status pslr_setup(int64_t n, const int64_t* rowptr, const int32_t* colind, 
     if (h->precision >= 1) {
       HIP_TRY(upload_dir<float>(h->pool, h->R, fB, fC, Dtr, true, d_int_ptr, d_if_ptr, d_if_orig,
                                 h->tr32, tb));
-      h->lds32 = std::max(h->lds32, lds_bytes(h->tr32, h->rank));
-      HIP_TRY(set_lds_limit<float>(h->lds32));
+      set_gx(h->tr32);
+      if (!h->gx) {
+        h->lds32 = std::max(h->lds32, lds_bytes(h->tr32, h->rank));
+        HIP_TRY(set_lds_limit<float>(h->lds32));
+      }
     }
     HIP_TRY(upload_dir<double>(h->pool, h->R, fB, fC, Dtr, true, d_int_ptr, d_if_ptr, d_if_orig,
                                h->tr64, tb));
-    h->lds64 = std::max(h->lds64, lds_bytes(h->tr64, h->rank));
-    if (h->lds64 > lds_max) return fail(PSLR_ENOTSUP, "transposed layout needs too much LDS");
-    HIP_TRY(set_lds_limit<double>(h->lds64));
+    set_gx(h->tr64);
+    if (!h->gx) {
+      h->lds64 = std::max(h->lds64, lds_bytes(h->tr64, h->rank));
+      HIP_TRY(set_lds_limit<double>(h->lds64));
+    }
     h->haveT = true;
+    h->ws.release();
+    h->ws_nrhs = 0;
   }
   fill_info(h.get(), fB, fC, Bk, bytes);
   h->info.seconds_reorder = t1 - t0;
@@ -1068,6 +1261,25 @@ pslr_status pslr_setup(int64_t n, const int64_t* rowptr, const int32_t* colind, 
   HIP_TRY(hipStreamSynchronize(s));
   *out = h.release();
   return breakdown ? PSLR_EBREAKDOWN : PSLR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pslr_status pslr_setup(int64_t n, const int64_t* rowptr, const int32_t* colind, const double* vals,
+                       const int32_t* part, int32_t nparts, const pslr_options* opt,
+                       void* hip_stream, pslr_handle* out) {
+  const int64_t sp[2] = {0, n};
+  return setup_impl(n, rowptr, colind, vals, part, nparts, 1, sp, opt, hip_stream, out);
+}
+
+pslr_status pslr_setup_batched(int64_t n, const int64_t* rowptr, const int32_t* colind,
+                               const double* vals, const int32_t* part, int32_t nparts,
+                               int32_t nsys, const int64_t* sys_ptr, const pslr_options* opt,
+                               void* hip_stream, pslr_handle* out) {
+  if (nsys < 1 || !sys_ptr) return fail(PSLR_EINVAL, "bad system table");
+  return setup_impl(n, rowptr, colind, vals, part, nparts, nsys, sys_ptr, opt, hip_stream, out);
 }
 
 pslr_status pslr_apply(pslr_handle h, int32_t nrhs, const double* b, int64_t ldb, double* z,
@@ -1099,98 +1311,119 @@ pslr_status fgmres_solve(pslr_handle h, int32_t nrhs, const double* b, int64_t l
   if (transpose && !h->haveT) return fail(PSLR_EINVAL, "handle was built without want_transpose");
   hipStream_t s = (hipStream_t)hip_stream;
   const int64_t n = h->R.n;
+  const int ns = h->nsys;
+  const int ncol = ns * nrhs;  // column c = r * nsys + sys: one Krylov space per (system, rhs)
   const int R1 = restart + 1;
   const int64_t* Ap = transpose ? h->AT_ptr : h->A_ptr;
   const int32_t* Ac = transpose ? h->AT_col : h->A_col;
   const double* Av = transpose ? h->AT_val : h->A_val;
-  DevPool tmp;
-  double *Vb, *Zb, *W, *dbuf, *dout, *dh, *scl;
-  HIP_TRY(tmp.alloc<double>((size_t)n * R1 * nrhs, &Vb));
-  HIP_TRY(tmp.alloc<double>((size_t)n * restart * nrhs, &Zb));
-  HIP_TRY(tmp.alloc<double>((size_t)n * nrhs, &W));
-  HIP_TRY(tmp.alloc<double>((size_t)h->nchunk * nrhs * R1, &dbuf));
-  HIP_TRY(tmp.alloc<double>((size_t)nrhs * R1, &dout));
-  HIP_TRY(tmp.alloc<double>((size_t)nrhs * R1, &dh));
-  HIP_TRY(tmp.alloc<double>(nrhs, &scl));
-  double *dh1, *dh2, *dnn;
-  HIP_TRY(tmp.alloc<double>((size_t)nrhs * (2 * R1 + 1), &dh1));
-  dh2 = dh1 + (size_t)nrhs * R1;
-  dnn = dh2 + (size_t)nrhs * R1;
-  std::vector<double> hbuf((size_t)nrhs * (2 * R1 + 1));
-  const int64_t ldvr = (int64_t)n * R1, ldzr = (int64_t)n * restart;
-  std::vector<double> bn, nn, h1, h2;
-  pslr_status st = dots(h, n, 1, b, 0, ldb, b, ldb, nrhs, dbuf, dout, bn, s);
-  if (st) return st;
-  for (double& v : bn) v = std::sqrt(v);
-  std::vector<int> its(nrhs, 0), done(nrhs, 0);
-  std::vector<double> rel(nrhs, 0.0);
+  const int64_t blk = n * nrhs;  // one basis vector of every column: n x nrhs, leading dimension n
+  int64_t maxlen = 0;
+  for (int c = 0; c < ns; ++c) maxlen = std::max(maxlen, h->sys_n[c + 1] - h->sys_n[c]);
+  if (h->f_nrhs != nrhs || h->f_restart != restart) {
+    h->fpool.release();
+    HIP_TRY(h->fpool.alloc<double>((size_t)blk * R1, &h->fVb));
+    HIP_TRY(h->fpool.alloc<double>((size_t)blk * restart, &h->fZb));
+    HIP_TRY(h->fpool.alloc<double>((size_t)blk, &h->fW));
+    HIP_TRY(h->fpool.alloc<double>((size_t)h->nchunk * ncol * R1, &h->fdbuf));
+    HIP_TRY(h->fpool.alloc<double>((size_t)ncol * (2 * R1 + 1), &h->fh));
+    HIP_TRY(h->fpool.alloc<double>(ncol, &h->fscl));
+    HIP_TRY(h->fpool.alloc<double>((size_t)ncol * restart, &h->fy));
+    HIP_TRY(h->fpool.alloc<Seg>((size_t)3 * ncol, &h->fcolsV));
+    h->fcolsB = h->fcolsV + ncol;
+    h->fcolsX = h->fcolsB + ncol;
+    h->f_nrhs = nrhs;
+    h->f_restart = restart;
+  }
+  std::vector<Seg> cols((size_t)3 * ncol);
   for (int r = 0; r < nrhs; ++r)
-    if (bn[r] == 0.0) done[r] = 1;
-  std::vector<double> Hh((size_t)nrhs * R1 * restart), cs((size_t)nrhs * restart),
-      sn((size_t)nrhs * restart), g((size_t)nrhs * R1);
-  std::vector<int> jdone(nrhs);
-  std::vector<double> yv((size_t)nrhs * restart), sc(nrhs);
+    for (int c = 0; c < ns; ++c) {
+      const int64_t o = h->sys_n[c], len = h->sys_n[c + 1] - o;
+      cols[r * ns + c] = Seg{r * n + o, len};
+      cols[ncol + r * ns + c] = Seg{r * ldb + o, len};
+      cols[2 * ncol + r * ns + c] = Seg{r * ldx + o, len};
+    }
+  HIP_TRY(hipMemcpyAsync(h->fcolsV, cols.data(), sizeof(Seg) * cols.size(), hipMemcpyHostToDevice, s));
+  const Seg *cV = h->fcolsV, *cB = h->fcolsB, *cX = h->fcolsX;
+  double* Vb = h->fVb;
+  double* Zb = h->fZb;
+  double* W = h->fW;
+  double* dh1 = h->fh;
+  double* dh2 = dh1 + (size_t)ncol * R1;
+  double* dnn = dh2 + (size_t)ncol * R1;
+  std::vector<double> hbuf((size_t)ncol * (2 * R1 + 1)), sc(ncol), bn(ncol);
+  // ||b|| per column
+  HIP_TRY(launch_mdot_seg(ncol, cB, cB, 1, b, 0, b, h->nchunk, h->fdbuf, s));
+  HIP_TRY(launch_reduce(h->nchunk, ncol, 1, h->fdbuf, dnn, s));
+  HIP_TRY(hipMemcpyAsync(bn.data(), dnn, sizeof(double) * ncol, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (double& v : bn) v = std::sqrt(v);
+  std::vector<int> its(ncol, 0), done(ncol, 0), jdone(ncol, 0), act(ncol, 0);
+  std::vector<double> rel(ncol, 0.0);
+  for (int c = 0; c < ncol; ++c)
+    if (bn[c] == 0.0) done[c] = 1;
+  std::vector<double> Hh((size_t)ncol * R1 * restart), cs((size_t)ncol * restart),
+      sn((size_t)ncol * restart), g((size_t)ncol * R1), yv((size_t)ncol * restart);
   for (;;) {
     // r0 = b - A x into V_0 of every column
-    HIP_TRY(launch_spmv(n, Ap, Ac, Av, nrhs, x, ldx, Vb, ldvr, b, ldb, s));
-    st = dots(h, n, 1, Vb, 0, ldvr, Vb, ldvr, nrhs, dbuf, dout, nn, s);
-    if (st) return st;
+    HIP_TRY(launch_spmv(n, Ap, Ac, Av, nrhs, x, ldx, Vb, n, b, ldb, s));
+    HIP_TRY(launch_mdot_seg(ncol, cV, cV, 1, Vb, 0, Vb, h->nchunk, h->fdbuf, s));
+    HIP_TRY(launch_reduce(h->nchunk, ncol, 1, h->fdbuf, dnn, s));
+    HIP_TRY(hipMemcpyAsync(hbuf.data(), dnn, sizeof(double) * ncol, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
     bool any = false;
-    for (int r = 0; r < nrhs; ++r) {
-      const double beta = std::sqrt(nn[r]);
-      if (!done[r]) {
-        rel[r] = beta / bn[r];
-        if (beta <= tol * bn[r]) done[r] = 1;
-        else if (its[r] >= maxit) done[r] = 2;
+    for (int c = 0; c < ncol; ++c) {
+      const double beta = std::sqrt(hbuf[c]);
+      if (!done[c]) {
+        rel[c] = beta / bn[c];
+        if (beta <= tol * bn[c]) done[c] = 1;
+        else if (its[c] >= maxit) done[c] = 2;
       }
-      const bool act = !done[r];
-      any = any || act;
-      sc[r] = act ? 1.0 / beta : 0.0;
-      std::fill(&g[(size_t)r * R1], &g[(size_t)r * R1] + R1, 0.0);
-      g[(size_t)r * R1] = act ? beta : 0.0;
-      jdone[r] = 0;
+      act[c] = !done[c];
+      any = any || act[c];
+      sc[c] = act[c] ? 1.0 / beta : 0.0;
+      std::fill(&g[(size_t)c * R1], &g[(size_t)c * R1] + R1, 0.0);
+      g[(size_t)c * R1] = act[c] ? beta : 0.0;
+      jdone[c] = 0;
     }
     if (!any) break;
-    HIP_TRY(hipMemcpyAsync(scl, sc.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, s));
-    HIP_TRY(launch_scale(n, Vb, ldvr, scl, Vb, ldvr, nrhs, s));
-    std::vector<int> act(nrhs);
-    for (int r = 0; r < nrhs; ++r) act[r] = !done[r];
+    HIP_TRY(hipMemcpyAsync(h->fscl, sc.data(), sizeof(double) * ncol, hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_scale_seg(ncol, cV, cV, maxlen, Vb, h->fscl, Vb, s));
     for (int j = 0; j < restart; ++j) {
-      double* Vj = Vb + (size_t)j * n;
-      double* Zj = Zb + (size_t)j * n;
-      st = apply_dir(h, transpose != 0, nrhs, Vj, ldvr, Zj, ldzr, s);
+      double* Vj = Vb + (size_t)j * blk;
+      double* Zj = Zb + (size_t)j * blk;
+      pslr_status st = apply_dir(h, transpose != 0, nrhs, Vj, n, Zj, n, s);
       if (st) return st;
-      HIP_TRY(launch_spmv(n, Ap, Ac, Av, nrhs, Zj, ldzr, W, n, nullptr, 0, s));
+      HIP_TRY(launch_spmv(n, Ap, Ac, Av, nrhs, Zj, n, W, n, nullptr, 0, s));
       // classical Gram-Schmidt, two passes, then ||w||; one host synchronisation
       const int nv = j + 1;
-      HIP_TRY(launch_mdot(n, nv, Vb, n, ldvr, W, n, nrhs, h->nchunk, dbuf, s));
-      HIP_TRY(launch_reduce(h->nchunk, nrhs, nv, dbuf, dh1, s));
-      HIP_TRY(launch_maxpy(n, nv, Vb, n, ldvr, dh1, nv, W, n, nrhs, 1.0, s));
-      HIP_TRY(launch_mdot(n, nv, Vb, n, ldvr, W, n, nrhs, h->nchunk, dbuf, s));
-      HIP_TRY(launch_reduce(h->nchunk, nrhs, nv, dbuf, dh2, s));
-      HIP_TRY(launch_maxpy(n, nv, Vb, n, ldvr, dh2, nv, W, n, nrhs, 1.0, s));
-      HIP_TRY(launch_mdot(n, 1, W, 0, n, W, n, nrhs, h->nchunk, dbuf, s));
-      HIP_TRY(launch_reduce(h->nchunk, nrhs, 1, dbuf, dnn, s));
-      HIP_TRY(hipMemcpyAsync(hbuf.data(), dh1, sizeof(double) * nrhs * (2 * R1 + 1),
-                             hipMemcpyDeviceToHost, s));
+      HIP_TRY(launch_mdot_seg(ncol, cV, cV, nv, Vb, blk, W, h->nchunk, h->fdbuf, s));
+      HIP_TRY(launch_reduce(h->nchunk, ncol, nv, h->fdbuf, dh1, s));
+      HIP_TRY(launch_maxpy_seg(ncol, cV, cV, maxlen, nv, Vb, blk, dh1, nv, W, 1.0, s));
+      HIP_TRY(launch_mdot_seg(ncol, cV, cV, nv, Vb, blk, W, h->nchunk, h->fdbuf, s));
+      HIP_TRY(launch_reduce(h->nchunk, ncol, nv, h->fdbuf, dh2, s));
+      HIP_TRY(launch_maxpy_seg(ncol, cV, cV, maxlen, nv, Vb, blk, dh2, nv, W, 1.0, s));
+      HIP_TRY(launch_mdot_seg(ncol, cV, cV, 1, W, 0, W, h->nchunk, h->fdbuf, s));
+      HIP_TRY(launch_reduce(h->nchunk, ncol, 1, h->fdbuf, dnn, s));
+      HIP_TRY(hipMemcpyAsync(hbuf.data(), dh1, sizeof(double) * hbuf.size(), hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
-      h1.assign(hbuf.begin(), hbuf.begin() + (size_t)nrhs * nv);
-      h2.assign(hbuf.begin() + (size_t)nrhs * R1, hbuf.begin() + (size_t)nrhs * R1 + (size_t)nrhs * nv);
-      nn.assign(hbuf.begin() + 2 * (size_t)nrhs * R1, hbuf.begin() + 2 * (size_t)nrhs * R1 + nrhs);
+      const double* h1 = hbuf.data();
+      const double* h2 = h1 + (size_t)ncol * R1;
+      const double* nn = h2 + (size_t)ncol * R1;
       bool cont = false;
-      for (int r = 0; r < nrhs; ++r) {
-        if (!act[r]) {
-          sc[r] = 0.0;
+      for (int c = 0; c < ncol; ++c) {
+        if (!act[c]) {
+          sc[c] = 0.0;
           continue;
         }
-        double* Hc = &Hh[((size_t)r * restart + j) * R1];
-        for (int i = 0; i <= j; ++i) Hc[i] = h1[(size_t)r * (j + 1) + i] + h2[(size_t)r * (j + 1) + i];
-        const double hn = std::sqrt(nn[r]);
+        double* Hc = &Hh[((size_t)c * restart + j) * R1];
+        for (int i = 0; i <= j; ++i) Hc[i] = h1[(size_t)c * nv + i] + h2[(size_t)c * nv + i];
+        const double hn = std::sqrt(nn[c]);
         Hc[j + 1] = hn;
-        sc[r] = hn > 0 ? 1.0 / hn : 0.0;
-        double* c_ = &cs[(size_t)r * restart];
-        double* s_ = &sn[(size_t)r * restart];
-        double* g_ = &g[(size_t)r * R1];
+        sc[c] = hn > 0 ? 1.0 / hn : 0.0;
+        double* c_ = &cs[(size_t)c * restart];
+        double* s_ = &sn[(size_t)c * restart];
+        double* g_ = &g[(size_t)c * R1];
         for (int i = 0; i < j; ++i) {
           const double t = c_[i] * Hc[i] + s_[i] * Hc[i + 1];
           Hc[i + 1] = -s_[i] * Hc[i] + c_[i] * Hc[i + 1];
@@ -1203,38 +1436,39 @@ pslr_status fgmres_solve(pslr_handle h, int32_t nrhs, const double* b, int64_t l
         Hc[j + 1] = 0.0;
         g_[j + 1] = -s_[j] * g_[j];
         g_[j] = c_[j] * g_[j];
-        its[r]++;
-        jdone[r] = j + 1;
-        if (std::fabs(g_[j + 1]) <= tol * bn[r] || its[r] >= maxit || hn == 0.0) act[r] = 0;
+        its[c]++;
+        jdone[c] = j + 1;
+        if (std::fabs(g_[j + 1]) <= tol * bn[c] || its[c] >= maxit || hn == 0.0) act[c] = 0;
         else cont = true;
       }
       if (!cont) break;
-      HIP_TRY(hipMemcpyAsync(scl, sc.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, s));
-      HIP_TRY(launch_scale(n, W, n, scl, Vb + (size_t)(j + 1) * n, ldvr, nrhs, s));
+      HIP_TRY(hipMemcpyAsync(h->fscl, sc.data(), sizeof(double) * ncol, hipMemcpyHostToDevice, s));
+      HIP_TRY(launch_scale_seg(ncol, cV, cV, maxlen, W, h->fscl, Vb + (size_t)(j + 1) * blk, s));
     }
     // x += Z y
     std::fill(yv.begin(), yv.end(), 0.0);
-    for (int r = 0; r < nrhs; ++r) {
-      const int jd = jdone[r];
-      double* y = &yv[(size_t)r * restart];
+    int jmax = 0;
+    for (int c = 0; c < ncol; ++c) {
+      const int jd = jdone[c];
+      jmax = std::max(jmax, jd);
+      double* y = &yv[(size_t)c * restart];
       for (int i = jd - 1; i >= 0; --i) {
-        double acc = g[(size_t)r * R1 + i];
-        for (int c = i + 1; c < jd; ++c) acc -= Hh[((size_t)r * restart + c) * R1 + i] * y[c];
-        y[i] = acc / Hh[((size_t)r * restart + i) * R1 + i];
+        double acc = g[(size_t)c * R1 + i];
+        for (int cc = i + 1; cc < jd; ++cc) acc -= Hh[((size_t)c * restart + cc) * R1 + i] * y[cc];
+        y[i] = acc / Hh[((size_t)c * restart + i) * R1 + i];
       }
     }
-    int jmax = 0;
-    for (int r = 0; r < nrhs; ++r) jmax = std::max(jmax, jdone[r]);
-    HIP_TRY(hipMemcpyAsync(dh, yv.data(), sizeof(double) * nrhs * restart, hipMemcpyHostToDevice, s));
-    if (jmax > 0) HIP_TRY(launch_maxpy(n, jmax, Zb, n, ldzr, dh, restart, x, ldx, nrhs, -1.0, s));
+    HIP_TRY(hipMemcpyAsync(h->fy, yv.data(), sizeof(double) * yv.size(), hipMemcpyHostToDevice, s));
+    if (jmax > 0)
+      HIP_TRY(launch_maxpy_seg(ncol, cV, cX, maxlen, jmax, Zb, blk, h->fy, restart, x, -1.0, s));
   }
-  for (int r = 0; r < nrhs; ++r) {
-    if (iters) iters[r] = its[r];
-    if (relres) relres[r] = rel[r];
+  for (int c = 0; c < ncol; ++c) {
+    if (iters) iters[c] = its[c];
+    if (relres) relres[c] = rel[c];
   }
   HIP_TRY(hipStreamSynchronize(s));
-  for (int r = 0; r < nrhs; ++r)
-    if (done[r] != 1) return fail(PSLR_ENOCONV, "FGMRES did not converge within maxit");
+  for (int c = 0; c < ncol; ++c)
+    if (done[c] != 1) return fail(PSLR_ENOCONV, "FGMRES did not converge within maxit");
   return PSLR_OK;
 }
 
@@ -1273,12 +1507,25 @@ pslr_status pslr_set_lowrank(pslr_handle h, int32_t k, const double* V, int64_t 
                              const double* H, int64_t ldh) {
   if (!h || k < 0 || k > 256 || k > h->R.q || (k > 0 && (!V || !H || ldv < h->R.q || ldh < k)))
     return fail(PSLR_EINVAL, "bad low-rank arguments");
+  if (h->nsys != 1) return fail(PSLR_EINVAL, "pslr_set_lowrank needs a single-system handle");
   if (k > h->rank && h->ws_nrhs > 0) {
     h->ws.release();
     h->ws_nrhs = 0;
   }
   const int64_t q = h->R.q;
   h->k = k;
+  h->sys_k.assign(1, k);
+  if (h->gx && k > h->fw64.kmax) {  // global workspace holds 2k scratch per block
+    h->gws_stride += (int64_t)h->R.nparts * 2 * (k - h->fw64.kmax);
+    for (ApplyArrays<double>* A : {&h->fw64, &h->tr64}) {
+      A->kmax = k;
+      A->gws_stride = h->gws_stride;
+    }
+    for (ApplyArrays<float>* A : {&h->fw32, &h->tr32}) {
+      A->kmax = k;
+      A->gws_stride = h->gws_stride;
+    }
+  }
   h->hV.assign((size_t)q * k, 0.0);
   h->hH.assign((size_t)k * k, 0.0);
   for (int j = 0; j < k; ++j) {
@@ -1287,11 +1534,11 @@ pslr_status pslr_set_lowrank(pslr_handle h, int32_t k, const double* V, int64_t 
   }
   if (k > h->rank) {  // LDS for W/Z scratch grows with k
     h->rank = k;
-    if (h->have64) {
+    if (h->have64 && !h->gx) {
       h->lds64 = std::max(h->lds64, lds_bytes(h->fw64, k));
       HIP_TRY(set_lds_limit<double>(h->lds64));
     }
-    if (h->have32) {
+    if (h->have32 && !h->gx) {
       h->lds32 = std::max(h->lds32, lds_bytes(h->fw32, k));
       HIP_TRY(set_lds_limit<float>(h->lds32));
     }
@@ -1308,6 +1555,7 @@ pslr_status pslr_set_lowrank(pslr_handle h, int32_t k, const double* V, int64_t 
 pslr_status pslr_get_lowrank(pslr_handle h, int32_t* k, double* V, int64_t ldv, double* H,
                              int64_t ldh) {
   if (!h || !k) return fail(PSLR_EINVAL, "null argument");
+  if (h->nsys != 1) return fail(PSLR_EINVAL, "pslr_get_lowrank needs a single-system handle");
   *k = h->k;
   const int64_t q = h->R.q;
   if (V)

@@ -58,7 +58,26 @@ struct ApplyArrays {
   DevCsr<T> Ein;              // rows = B-solve input positions, cols = local interface
   DevCsr<T> Fout;             // rows = global interface, cols = B-solve output positions
   DevCsr<T> Cg;               // rows/cols = global interface
+  const int32_t* part_sys;    // nparts: system (batched handles) owning each subdomain
   int32_t maxPB, maxQB, maxLR;
+  int32_t gshift;             // lane-group widths are scaled by 2^gshift (autotuned)
+  // global working vectors (used instead of LDS when a subdomain does not fit)
+  void* gws;                  // null: working vectors in LDS
+  int64_t gws_stride;         // elements per right-hand side
+  const int64_t* rb_off;      // nparts + 1: per-block level-scratch offsets
+  int32_t kmax;
+};
+
+// A row chunk of the interface vectors for the V^T y partial sums; chunks never
+// straddle two systems.
+struct LrChunk {
+  int64_t r0, r1;
+  int32_t sys, pad;
+};
+
+// One column of a segmented vector operation: elements [base, base + len).
+struct Seg {
+  int64_t base, len;
 };
 
 struct LaunchCfg {
@@ -72,12 +91,15 @@ template <typename T>
 hipError_t launch_head(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, const double* b,
                        int64_t ldb, T* y, int64_t ldy);
 template <typename T, typename TV>
-hipError_t launch_lr_partial(int64_t q, int k, const TV* V, const T* y, int64_t ldy, int nrhs,
-                             int nchunk, T* partial, hipStream_t s);
+hipError_t launch_lr_partial(int nchunk, const LrChunk* chunks, int k, const TV* V, const T* y,
+                             int64_t ldy, int nrhs, T* partial, hipStream_t s);
+// G holds one k x k row-major matrix per system; block i uses system part_sys[i]
+// and the partial sums of chunks sys_chunk[s] .. sys_chunk[s+1].
 template <typename T, typename TV>
 hipError_t launch_lr_expand(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, int k,
                             const TV* V, const T* G, int gtrans, const T* partial, int nchunk,
-                            T* y, int64_t ldy, int do_c0, T* u, int64_t ldu);
+                            const int32_t* sys_chunk, T* y, int64_t ldy, int do_c0, T* u,
+                            int64_t ldu);
 template <typename T>
 hipError_t launch_c0solve(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, const T* src,
                           int64_t lds_, T* dst, int64_t ldd);
@@ -109,6 +131,17 @@ hipError_t launch_maxpy(int64_t n, int nv, const double* V, int64_t ldv, int64_t
 // v_r = w_r * scale[r] (scale on device)
 hipError_t launch_scale(int64_t n, const double* w, int64_t ldw, const double* scale, double* v,
                         int64_t ldv, int nrhs, hipStream_t s);
+// Segmented forms over ncol columns (column c: vcols[c] in V / wcols[c] in W):
+// partial[chunk][c][i] = sum_rows V_i[vbase + row] * W[wbase + row], V_i = V + i*ldv
+hipError_t launch_mdot_seg(int ncol, const Seg* vcols, const Seg* wcols, int nv, const double* V,
+                           int64_t ldv, const double* W, int nchunk, double* partial, hipStream_t s);
+// W[wbase + row] -= sign * sum_i h[c*hld + i] * V_i[vbase + row]
+hipError_t launch_maxpy_seg(int ncol, const Seg* vcols, const Seg* wcols, int64_t maxlen, int nv,
+                            const double* V, int64_t ldv, const double* h, int hld, double* W,
+                            double sign, hipStream_t s);
+// D[dbase + row] = S[sbase + row] * scale[c]
+hipError_t launch_scale_seg(int ncol, const Seg* scols, const Seg* dcols, int64_t maxlen,
+                            const double* S, const double* scale, double* D, hipStream_t s);
 hipError_t launch_copy_cast_to_f32(int64_t count, const double* src, float* dst, hipStream_t s);
 hipError_t launch_sddmm(int64_t n, const int64_t* ptr, const int32_t* col, int nrhs,
                         const double* lam, int64_t ldl, const double* z, int64_t ldz,

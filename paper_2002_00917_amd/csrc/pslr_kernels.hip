@@ -78,7 +78,7 @@ __device__ __forceinline__ T dot_dense(const T* __restrict__ v, int len, const T
 // (positions 0..n-1); Rb is LDS scratch of max_lrows entries.  All threads of
 // the workgroup must call it.  Ends with a barrier.
 template <typename T>
-__device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb) {
+__device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift) {
   const DevTriBlock B = A.blk[bi];
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int4* rec = A.rec + 2 * B.rec_base;
@@ -93,7 +93,14 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb) {
     const int b = lev_ptr[l];
     const int cnt = lev_ptr[l + 1] - b;
     const int g = lev_g[l];
-    const int G1 = g & 0xff, G2 = (g >> 8) & 0xff;
+    int G1 = g & 0xff, G2 = (g >> 8) & 0xff;
+    if (gshift > 0) {
+      G1 = min(64, G1 << gshift);
+      G2 = min(64, G2 << gshift);
+    } else if (gshift < 0) {
+      G1 = max(1, G1 >> -gshift);
+      G2 = max(1, G2 >> -gshift);
+    }
     // sweep 1: r_k = x_p - (off-diagonal part of row p) . x
     {
       const int grp = tid / G1, lane = tid - grp * G1, ngrp = nthr / G1;
@@ -125,31 +132,45 @@ struct Lds {
   T *XB, *Rb, *XC, *U, *W;
 };
 
-template <typename T>
+// Working vectors of block blockIdx.x for right-hand side blockIdx.y: in LDS,
+// or (GX) in the handle's global workspace when a subdomain is too large for
+// LDS.  The global layout per right-hand side is [X_B: p][X_C: q][U: q]
+// [scratch: sum of per-block level sizes][W: 2k per block].
+template <typename T, bool GX>
 __device__ Lds<T> carve(const ApplyArrays<T>& A) {
-  extern __shared__ __align__(16) unsigned char smem[];
   Lds<T> L;
-  L.XB = reinterpret_cast<T*>(smem);
-  L.Rb = L.XB + A.maxPB;
-  L.XC = L.Rb + A.maxLR;
-  L.U = L.XC + A.maxQB;
-  L.W = L.U + A.maxQB;
+  if (GX) {
+    const int i = blockIdx.x, r = blockIdx.y;
+    T* base = reinterpret_cast<T*>(A.gws) + (int64_t)r * A.gws_stride;
+    L.XB = base + A.int_ptr[i];
+    L.XC = base + A.p + A.if_ptr[i];
+    L.U = base + A.p + A.q + A.if_ptr[i];
+    L.Rb = base + A.p + 2 * A.q + A.rb_off[i];
+    L.W = base + A.p + 2 * A.q + A.rb_off[A.nparts] + (int64_t)i * 2 * A.kmax;
+  } else {
+    extern __shared__ __align__(16) unsigned char smem[];
+    L.XB = reinterpret_cast<T*>(smem);
+    L.Rb = L.XB + A.maxPB;
+    L.XC = L.Rb + A.maxLR;
+    L.U = L.XC + A.maxQB;
+    L.W = L.U + A.maxQB;
+  }
   return L;
 }
 
 // t = B^{-1} f;  y = g - F t   (Algorithm 3, line 2)
-template <typename T>
+template <typename T, bool GX>
 __global__ void __launch_bounds__(1024) k_head(ApplyArrays<T> A, const double* __restrict__ b, int64_t ldb, T* y,
                        int64_t ldy) {
-  Lds<T> L = carve(A);
+  Lds<T> L = carve<T, GX>(A);
   const int i = blockIdx.x, r = blockIdx.y, tid = threadIdx.x, nt = blockDim.x;
   const int64_t i0 = A.int_ptr[i], pi = A.int_ptr[i + 1] - i0;
   const int64_t f0 = A.if_ptr[i], qi = A.if_ptr[i + 1] - f0;
   const double* br = b + r * ldb;
   for (int64_t p = tid; p < pi; p += nt) L.XB[p] = (T)br[A.gB_in[i0 + p]];
   __syncthreads();
-  tri_solve(A.LB, i, L.XB, L.Rb);
-  tri_solve(A.UB, i, L.XB, L.Rb);
+  tri_solve(A.LB, i, L.XB, L.Rb, A.gshift);
+  tri_solve(A.UB, i, L.XB, L.Rb, A.gshift);
   T* yr = y + r * ldy;
   for (int64_t k = tid; k < qi; k += nt) {
     const int64_t row = f0 + k;
@@ -161,19 +182,18 @@ __global__ void __launch_bounds__(1024) k_head(ApplyArrays<T> A, const double* _
 
 // partial[chunk][r][j] = sum_{rows in chunk} V[row][j] y_r[row]   (V^T y, line 3)
 template <typename T, typename TV>
-__global__ void k_lr_partial(int64_t q, int k, const TV* __restrict__ V, const T* __restrict__ y,
-                             int64_t ldy, int nchunk, T* partial) {
+__global__ void k_lr_partial(const LrChunk* __restrict__ chunks, int k, const TV* __restrict__ V,
+                             const T* __restrict__ y, int64_t ldy, T* partial) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* red = reinterpret_cast<T*>(smem);
   const int chunk = blockIdx.x, r = blockIdx.y, tid = threadIdx.x, nt = blockDim.x;
-  const int64_t rows = (q + nchunk - 1) / nchunk;
-  const int64_t r0 = chunk * rows, r1 = min(q, r0 + rows);
+  const LrChunk C = chunks[chunk];
   const int ng = nt / k;
   const int g = tid / k, j = tid - g * k;
   T acc = 0;
   if (g < ng) {
     const T* yr = y + r * ldy;
-    for (int64_t row = r0 + g; row < r1; row += ng) acc += (T)tv_to_float(V[row * k + j]) * yr[row];
+    for (int64_t row = C.r0 + g; row < C.r1; row += ng) acc += (T)tv_to_float(V[row * k + j]) * yr[row];
     red[g * k + j] = acc;
   }
   __syncthreads();
@@ -185,19 +205,23 @@ __global__ void k_lr_partial(int64_t q, int k, const TV* __restrict__ V, const T
 }
 
 // y += V (G (V^T y)) on the rows of block i; optionally u = C0^{-1} y (line 3, line 4 start)
-template <typename T, typename TV>
+template <typename T, typename TV, bool GX>
 __global__ void __launch_bounds__(1024) k_lr_expand(ApplyArrays<T> A, int k, const TV* __restrict__ V,
-                            const T* __restrict__ G, int gtrans, const T* __restrict__ partial,
-                            int nchunk, T* y, int64_t ldy, int do_c0, T* u, int64_t ldu) {
-  Lds<T> L = carve(A);
+                            const T* __restrict__ Gall, int gtrans, const T* __restrict__ partial,
+                            const int32_t* __restrict__ sys_chunk, T* y, int64_t ldy, int do_c0,
+                            T* u, int64_t ldu) {
+  Lds<T> L = carve<T, GX>(A);
   T* Wv = L.W;
   T* Zv = L.W + k;
   const int i = blockIdx.x, r = blockIdx.y, tid = threadIdx.x, nt = blockDim.x;
   const int nrhs = gridDim.y;
   const int64_t f0 = A.if_ptr[i], qi = A.if_ptr[i + 1] - f0;
+  const int sys = A.part_sys[i];
+  const T* G = Gall + (int64_t)sys * k * k;
+  const int c0 = sys_chunk[sys], c1 = sys_chunk[sys + 1];
   for (int j = tid; j < k; j += nt) {
     T s = 0;
-    for (int c = 0; c < nchunk; ++c) s += partial[((int64_t)c * nrhs + r) * k + j];
+    for (int c = c0; c < c1; ++c) s += partial[((int64_t)c * nrhs + r) * k + j];
     Wv[j] = s;
   }
   __syncthreads();
@@ -223,34 +247,34 @@ __global__ void __launch_bounds__(1024) k_lr_expand(ApplyArrays<T> A, int k, con
   }
   if (!do_c0) return;
   __syncthreads();
-  tri_solve(A.LC, i, L.XC, L.Rb);
-  tri_solve(A.UC, i, L.XC, L.Rb);
+  tri_solve(A.LC, i, L.XC, L.Rb, A.gshift);
+  tri_solve(A.UC, i, L.XC, L.Rb, A.gshift);
   T* ur = u + r * ldu;
   for (int64_t c = tid; c < qi; c += nt) ur[f0 + A.gC_out[f0 + c]] = L.XC[c];
 }
 
 // dst = C0^{-1} src
-template <typename T>
+template <typename T, bool GX>
 __global__ void __launch_bounds__(1024) k_c0solve(ApplyArrays<T> A, const T* __restrict__ src, int64_t lds_, T* dst,
                           int64_t ldd) {
-  Lds<T> L = carve(A);
+  Lds<T> L = carve<T, GX>(A);
   const int i = blockIdx.x, r = blockIdx.y, tid = threadIdx.x, nt = blockDim.x;
   const int64_t f0 = A.if_ptr[i], qi = A.if_ptr[i + 1] - f0;
   const T* sr = src + r * lds_;
   for (int64_t p = tid; p < qi; p += nt) L.XC[p] = sr[f0 + A.gC_in[f0 + p]];
   __syncthreads();
-  tri_solve(A.LC, i, L.XC, L.Rb);
-  tri_solve(A.UC, i, L.XC, L.Rb);
+  tri_solve(A.LC, i, L.XC, L.Rb, A.gshift);
+  tri_solve(A.UC, i, L.XC, L.Rb, A.gshift);
   T* dr = dst + r * ldd;
   for (int64_t c = tid; c < qi; c += nt) dr[f0 + A.gC_out[f0 + c]] = L.XC[c];
 }
 
 // One power-series step (eq. approx1 by its recurrence):
 //   w = E_s u = -C_g u + F B^{-1} E u;  r = [y +] w;  u_next = [C0^{-1}] r
-template <typename T>
+template <typename T, bool GX>
 __global__ void __launch_bounds__(1024) k_series(ApplyArrays<T> A, const T* __restrict__ y, int64_t ldy,
                          const T* __restrict__ uprev, T* unext, int64_t ldu, int add_y, int do_c0) {
-  Lds<T> L = carve(A);
+  Lds<T> L = carve<T, GX>(A);
   const int i = blockIdx.x, r = blockIdx.y, tid = threadIdx.x, nt = blockDim.x;
   const int64_t i0 = A.int_ptr[i], pi = A.int_ptr[i + 1] - i0;
   const int64_t f0 = A.if_ptr[i], qi = A.if_ptr[i + 1] - f0;
@@ -264,8 +288,8 @@ __global__ void __launch_bounds__(1024) k_series(ApplyArrays<T> A, const T* __re
     L.XB[p] = acc;
   }
   __syncthreads();
-  tri_solve(A.LB, i, L.XB, L.Rb);
-  tri_solve(A.UB, i, L.XB, L.Rb);
+  tri_solve(A.LB, i, L.XB, L.Rb, A.gshift);
+  tri_solve(A.UB, i, L.XB, L.Rb, A.gshift);
   const T* yr = y + r * ldy;
   T* vr = unext + r * ldu;
   for (int64_t k = tid; k < qi; k += nt) {
@@ -278,16 +302,16 @@ __global__ void __launch_bounds__(1024) k_series(ApplyArrays<T> A, const T* __re
   }
   if (!do_c0) return;
   __syncthreads();
-  tri_solve(A.LC, i, L.XC, L.Rb);
-  tri_solve(A.UC, i, L.XC, L.Rb);
+  tri_solve(A.LC, i, L.XC, L.Rb, A.gshift);
+  tri_solve(A.UC, i, L.XC, L.Rb, A.gshift);
   for (int64_t c = tid; c < qi; c += nt) vr[f0 + A.gC_out[f0 + c]] = L.XC[c];
 }
 
 // x = B^{-1}(f - E u);  z = P^T (x; u)   (Algorithm 3, lines 5-6)
-template <typename T>
+template <typename T, bool GX>
 __global__ void __launch_bounds__(1024) k_tail(ApplyArrays<T> A, const double* __restrict__ b, int64_t ldb,
                        const T* __restrict__ u, int64_t ldu, double* z, int64_t ldz) {
-  Lds<T> L = carve(A);
+  Lds<T> L = carve<T, GX>(A);
   const int i = blockIdx.x, r = blockIdx.y, tid = threadIdx.x, nt = blockDim.x;
   const int64_t i0 = A.int_ptr[i], pi = A.int_ptr[i + 1] - i0;
   const int64_t f0 = A.if_ptr[i], qi = A.if_ptr[i + 1] - f0;
@@ -307,8 +331,8 @@ __global__ void __launch_bounds__(1024) k_tail(ApplyArrays<T> A, const double* _
     L.XB[p] = acc;
   }
   __syncthreads();
-  tri_solve(A.LB, i, L.XB, L.Rb);
-  tri_solve(A.UB, i, L.XB, L.Rb);
+  tri_solve(A.LB, i, L.XB, L.Rb, A.gshift);
+  tri_solve(A.UB, i, L.XB, L.Rb, A.gshift);
   for (int64_t c = tid; c < pi; c += nt) zr[A.gB_out[i0 + c]] = (double)L.XB[c];
 }
 
@@ -384,6 +408,53 @@ __global__ void k_scale(int64_t n, const double* __restrict__ w, int64_t ldw,
   v[r * ldv + row] = w[r * ldw + row] * scale[r];
 }
 
+__global__ void k_mdot_seg(const Seg* __restrict__ vcols, const Seg* __restrict__ wcols, int nv,
+                           const double* __restrict__ V, int64_t ldv, const double* __restrict__ W,
+                           int nchunk, double* partial) {
+  __shared__ double red[8];
+  const int chunk = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
+  const Seg sv = vcols[c], sw = wcols[c];
+  const int64_t rows = (sw.len + nchunk - 1) / nchunk;
+  const int64_t r0 = chunk * rows, r1 = min(sw.len, r0 + rows);
+  const double* wr = W + sw.base;
+  for (int i = 0; i < nv; ++i) {
+    const double* vi = V + sv.base + i * ldv;
+    double acc = 0.0;
+    for (int64_t row = r0 + tid; row < r1; row += blockDim.x) acc += vi[row] * wr[row];
+    acc = group_sum(acc, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) {
+      double s = 0.0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+      partial[((int64_t)chunk * gridDim.y + c) * nv + i] = s;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_maxpy_seg(const Seg* __restrict__ vcols, const Seg* __restrict__ wcols, int nv,
+                            const double* __restrict__ V, int64_t ldv, const double* __restrict__ h,
+                            int hld, double* W, double sign) {
+  const int c = blockIdx.y;
+  const Seg sv = vcols[c], sw = wcols[c];
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= sw.len) return;
+  const double* hr = h + (int64_t)c * hld;
+  double acc = 0.0;
+  for (int i = 0; i < nv; ++i) acc += hr[i] * V[sv.base + i * ldv + row];
+  W[sw.base + row] -= sign * acc;
+}
+
+__global__ void k_scale_seg(const Seg* __restrict__ scols, const Seg* __restrict__ dcols,
+                            const double* __restrict__ S, const double* __restrict__ scale, double* D) {
+  const int c = blockIdx.y;
+  const Seg ss = scols[c], sd = dcols[c];
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= sd.len) return;
+  D[sd.base + row] = S[ss.base + row] * scale[c];
+}
+
 __global__ void k_cast(int64_t count, const double* __restrict__ s, float* d) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) d[i] = (float)s[i];
@@ -411,62 +482,81 @@ template <typename T>
 hipError_t set_lds_limit(size_t bytes) {
   hipError_t e;
   const int b = (int)bytes;
-  if ((e = hipFuncSetAttribute((const void*)k_head<T>, hipFuncAttributeMaxDynamicSharedMemorySize, b))) return e;
-  if ((e = hipFuncSetAttribute((const void*)k_c0solve<T>, hipFuncAttributeMaxDynamicSharedMemorySize, b))) return e;
-  if ((e = hipFuncSetAttribute((const void*)k_series<T>, hipFuncAttributeMaxDynamicSharedMemorySize, b))) return e;
-  if ((e = hipFuncSetAttribute((const void*)k_tail<T>, hipFuncAttributeMaxDynamicSharedMemorySize, b))) return e;
-  if ((e = hipFuncSetAttribute((const void*)k_lr_expand<T, T>, hipFuncAttributeMaxDynamicSharedMemorySize, b))) return e;
-  if ((e = hipFuncSetAttribute((const void*)k_lr_expand<T, __hip_bfloat16>, hipFuncAttributeMaxDynamicSharedMemorySize, b))) return e;
+  if ((e = hipFuncSetAttribute((const void*)k_head<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b))) return e;
+  if ((e = hipFuncSetAttribute((const void*)k_c0solve<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b))) return e;
+  if ((e = hipFuncSetAttribute((const void*)k_series<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b))) return e;
+  if ((e = hipFuncSetAttribute((const void*)k_tail<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b))) return e;
+  if ((e = hipFuncSetAttribute((const void*)k_lr_expand<T, T, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b))) return e;
+  if ((e = hipFuncSetAttribute((const void*)k_lr_expand<T, __hip_bfloat16, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b))) return e;
   return hipSuccess;
 }
 
 template <typename T>
 hipError_t launch_head(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, const double* b,
                        int64_t ldb, T* y, int64_t ldy) {
-  hipLaunchKernelGGL(k_head<T>, dim3(A.nparts, nrhs), dim3(c.threads), c.lds, c.stream, A, b, ldb, y, ldy);
+  if (A.gws) hipLaunchKernelGGL((k_head<T, true>), dim3(A.nparts, nrhs), dim3(c.threads), 0, c.stream, A, b, ldb, y, ldy);
+  else hipLaunchKernelGGL((k_head<T, false>), dim3(A.nparts, nrhs), dim3(c.threads), c.lds, c.stream, A, b, ldb, y, ldy);
   return hipGetLastError();
 }
 
 template <typename T, typename TV>
-hipError_t launch_lr_partial(int64_t q, int k, const TV* V, const T* y, int64_t ldy, int nrhs,
-                             int nchunk, T* partial, hipStream_t s) {
+hipError_t launch_lr_partial(int nchunk, const LrChunk* chunks, int k, const TV* V, const T* y,
+                             int64_t ldy, int nrhs, T* partial, hipStream_t s) {
   const int threads = 256;
   size_t lds = sizeof(T) * threads;
-  hipLaunchKernelGGL((k_lr_partial<T, TV>), dim3(nchunk, nrhs), dim3(threads), lds, s, q, k, V, y,
-                     ldy, nchunk, partial);
+  hipLaunchKernelGGL((k_lr_partial<T, TV>), dim3(nchunk, nrhs), dim3(threads), lds, s, chunks, k, V,
+                     y, ldy, partial);
   return hipGetLastError();
 }
 
 template <typename T, typename TV>
 hipError_t launch_lr_expand(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, int k,
                             const TV* V, const T* G, int gtrans, const T* partial, int nchunk,
-                            T* y, int64_t ldy, int do_c0, T* u, int64_t ldu) {
-  hipLaunchKernelGGL((k_lr_expand<T, TV>), dim3(A.nparts, nrhs), dim3(c.threads), c.lds, c.stream,
-                     A, k, V, G, gtrans, partial, nchunk, y, ldy, do_c0, u, ldu);
+                            const int32_t* sys_chunk, T* y, int64_t ldy, int do_c0, T* u,
+                            int64_t ldu) {
+  (void)nchunk;
+  if (A.gws)
+    hipLaunchKernelGGL((k_lr_expand<T, TV, true>), dim3(A.nparts, nrhs), dim3(c.threads), 0, c.stream,
+                       A, k, V, G, gtrans, partial, sys_chunk, y, ldy, do_c0, u, ldu);
+  else
+    hipLaunchKernelGGL((k_lr_expand<T, TV, false>), dim3(A.nparts, nrhs), dim3(c.threads), c.lds,
+                       c.stream, A, k, V, G, gtrans, partial, sys_chunk, y, ldy, do_c0, u, ldu);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_c0solve(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, const T* src,
                           int64_t lds_, T* dst, int64_t ldd) {
-  hipLaunchKernelGGL(k_c0solve<T>, dim3(A.nparts, nrhs), dim3(c.threads), c.lds, c.stream, A, src,
-                     lds_, dst, ldd);
+  if (A.gws)
+    hipLaunchKernelGGL((k_c0solve<T, true>), dim3(A.nparts, nrhs), dim3(c.threads), 0, c.stream, A,
+                       src, lds_, dst, ldd);
+  else
+    hipLaunchKernelGGL((k_c0solve<T, false>), dim3(A.nparts, nrhs), dim3(c.threads), c.lds, c.stream,
+                       A, src, lds_, dst, ldd);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_series(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, const T* y,
                          int64_t ldy, const T* uprev, T* unext, int64_t ldu, int add_y, int do_c0) {
-  hipLaunchKernelGGL(k_series<T>, dim3(A.nparts, nrhs), dim3(c.threads), c.lds, c.stream, A, y,
-                     ldy, uprev, unext, ldu, add_y, do_c0);
+  if (A.gws)
+    hipLaunchKernelGGL((k_series<T, true>), dim3(A.nparts, nrhs), dim3(c.threads), 0, c.stream, A, y,
+                       ldy, uprev, unext, ldu, add_y, do_c0);
+  else
+    hipLaunchKernelGGL((k_series<T, false>), dim3(A.nparts, nrhs), dim3(c.threads), c.lds, c.stream,
+                       A, y, ldy, uprev, unext, ldu, add_y, do_c0);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_tail(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, const double* b,
                        int64_t ldb, const T* u, int64_t ldu, double* z, int64_t ldz) {
-  hipLaunchKernelGGL(k_tail<T>, dim3(A.nparts, nrhs), dim3(c.threads), c.lds, c.stream, A, b, ldb,
-                     u, ldu, z, ldz);
+  if (A.gws)
+    hipLaunchKernelGGL((k_tail<T, true>), dim3(A.nparts, nrhs), dim3(c.threads), 0, c.stream, A, b,
+                       ldb, u, ldu, z, ldz);
+  else
+    hipLaunchKernelGGL((k_tail<T, false>), dim3(A.nparts, nrhs), dim3(c.threads), c.lds, c.stream, A,
+                       b, ldb, u, ldu, z, ldz);
   return hipGetLastError();
 }
 
@@ -506,6 +596,30 @@ hipError_t launch_scale(int64_t n, const double* w, int64_t ldw, const double* s
   return hipGetLastError();
 }
 
+hipError_t launch_mdot_seg(int ncol, const Seg* vcols, const Seg* wcols, int nv, const double* V,
+                           int64_t ldv, const double* W, int nchunk, double* partial, hipStream_t s) {
+  hipLaunchKernelGGL(k_mdot_seg, dim3(nchunk, ncol), dim3(512), 0, s, vcols, wcols, nv, V, ldv, W,
+                     nchunk, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_maxpy_seg(int ncol, const Seg* vcols, const Seg* wcols, int64_t maxlen, int nv,
+                            const double* V, int64_t ldv, const double* h, int hld, double* W,
+                            double sign, hipStream_t s) {
+  if (maxlen <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_maxpy_seg, dim3(nblk(maxlen, 256), ncol), dim3(256), 0, s, vcols, wcols, nv,
+                     V, ldv, h, hld, W, sign);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_seg(int ncol, const Seg* scols, const Seg* dcols, int64_t maxlen,
+                            const double* S, const double* scale, double* D, hipStream_t s) {
+  if (maxlen <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale_seg, dim3(nblk(maxlen, 256), ncol), dim3(256), 0, s, scols, dcols, S,
+                     scale, D);
+  return hipGetLastError();
+}
+
 hipError_t launch_copy_cast_to_f32(int64_t count, const double* src, float* dst, hipStream_t s) {
   if (count == 0) return hipSuccess;
   hipLaunchKernelGGL(k_cast, dim3(nblk(count, 256)), dim3(256), 0, s, count, src, dst);
@@ -534,23 +648,24 @@ hipError_t launch_sddmm(int64_t n, const int64_t* ptr, const int32_t* col, int n
 PSLR_INST(double)
 PSLR_INST(float)
 
-template hipError_t launch_lr_partial<double, double>(int64_t, int, const double*, const double*,
-                                                      int64_t, int, int, double*, hipStream_t);
-template hipError_t launch_lr_partial<float, __hip_bfloat16>(int64_t, int, const __hip_bfloat16*,
-                                                             const float*, int64_t, int, int,
-                                                             float*, hipStream_t);
-template hipError_t launch_lr_partial<float, float>(int64_t, int, const float*, const float*,
-                                                    int64_t, int, int, float*, hipStream_t);
-template hipError_t launch_lr_expand<float, float>(const ApplyArrays<float>&, const LaunchCfg&, int,
-                                                   int, const float*, const float*, int,
-                                                   const float*, int, float*, int64_t, int, float*,
-                                                   int64_t);
+template hipError_t launch_lr_partial<double, double>(int, const LrChunk*, int, const double*,
+                                                      const double*, int64_t, int, double*,
+                                                      hipStream_t);
+template hipError_t launch_lr_partial<float, float>(int, const LrChunk*, int, const float*,
+                                                    const float*, int64_t, int, float*, hipStream_t);
+template hipError_t launch_lr_partial<float, __hip_bfloat16>(int, const LrChunk*, int,
+                                                             const __hip_bfloat16*, const float*,
+                                                             int64_t, int, float*, hipStream_t);
 template hipError_t launch_lr_expand<double, double>(const ApplyArrays<double>&, const LaunchCfg&,
                                                      int, int, const double*, const double*, int,
-                                                     const double*, int, double*, int64_t, int,
-                                                     double*, int64_t);
+                                                     const double*, int, const int32_t*, double*,
+                                                     int64_t, int, double*, int64_t);
+template hipError_t launch_lr_expand<float, float>(const ApplyArrays<float>&, const LaunchCfg&, int,
+                                                   int, const float*, const float*, int,
+                                                   const float*, int, const int32_t*, float*,
+                                                   int64_t, int, float*, int64_t);
 template hipError_t launch_lr_expand<float, __hip_bfloat16>(
-    const ApplyArrays<float>&, const LaunchCfg&, int, int, const __hip_bfloat16*, const float*,
-    int, const float*, int, float*, int64_t, int, float*, int64_t);
+    const ApplyArrays<float>&, const LaunchCfg&, int, int, const __hip_bfloat16*, const float*, int,
+    const float*, int, const int32_t*, float*, int64_t, int, float*, int64_t);
 
 }  // namespace pslr

@@ -33,7 +33,8 @@ class PslrError(RuntimeError):
 class pslr_options(C.Structure):
     _fields_ = [("m", C.c_int32), ("rank", C.c_int32), ("precision", C.c_int32),
                 ("want_transpose", C.c_int32), ("v0", C.POINTER(C.c_double)),
-                ("seed", C.c_uint64), ("pivot_threshold", C.c_double), ("nthreads", C.c_int32)]
+                ("seed", C.c_uint64), ("pivot_threshold", C.c_double), ("nthreads", C.c_int32),
+                ("working_vectors", C.c_int32)]
 
 
 class pslr_info_t(C.Structure):
@@ -46,7 +47,8 @@ class pslr_info_t(C.Structure):
                 ("fill_lu", C.c_double), ("fill_lowrank", C.c_double), ("fill_total", C.c_double),
                 ("apply_bytes", C.c_int64), ("apply_bytes_rhs", C.c_int64),
                 ("series_bytes", C.c_int64), ("seconds_reorder", C.c_double),
-                ("seconds_factor", C.c_double), ("seconds_arnoldi", C.c_double)]
+                ("seconds_factor", C.c_double), ("seconds_arnoldi", C.c_double),
+                ("nsys", C.c_int32), ("global_vectors", C.c_int32)]
 
 
 class pslr_trace_t(C.Structure):
@@ -63,6 +65,8 @@ _SIGS = {
     "pslr_default_options": (None, [C.POINTER(pslr_options)]),
     "pslr_setup": (C.c_int, [C.c_int64, _I64P, _I32P, _F64P, _I32P, C.c_int32,
                              C.POINTER(pslr_options), _P, C.POINTER(_P)]),
+    "pslr_setup_batched": (C.c_int, [C.c_int64, _I64P, _I32P, _F64P, _I32P, C.c_int32, C.c_int32,
+                                     _I64P, C.POINTER(pslr_options), _P, C.POINTER(_P)]),
     "pslr_apply": (C.c_int, [_P, C.c_int32, _P, C.c_int64, _P, C.c_int64, _P]),
     "pslr_apply_transpose": (C.c_int, [_P, C.c_int32, _P, C.c_int64, _P, C.c_int64, _P]),
     "fgmres_solve": (C.c_int, [_P, C.c_int32, _P, C.c_int64, _P, C.c_int64, C.c_int32, C.c_int32,
@@ -147,10 +151,11 @@ def _vec(t, n):
 
 
 class Handle:
-    def __init__(self, ptr, n, status):
+    def __init__(self, ptr, n, status, nsys=1):
         self.ptr = ptr
         self.n = n
         self.status = status
+        self.nsys = nsys
 
     def __del__(self):
         if getattr(self, "ptr", None) is not None and _lib is not None:
@@ -164,21 +169,29 @@ def pslr_default_options():
     return o
 
 
+def _options(m, rank, precision, want_transpose, v0, seed, pivot_threshold, nthreads,
+             working_vectors):
+    o = pslr_default_options()
+    o.m, o.rank, o.precision = int(m), int(rank), int(precision)
+    o.want_transpose = 1 if want_transpose else 0
+    o.seed, o.pivot_threshold, o.nthreads = int(seed), float(pivot_threshold), int(nthreads)
+    o.working_vectors = int(working_vectors)
+    keep = None
+    if v0 is not None:
+        keep, o.v0 = _arr(v0, np.float64)
+    return o, keep
+
+
 def pslr_setup(rowptr, colind, vals, part, nparts, m=3, rank=16, precision=0,
                want_transpose=False, v0=None, seed=1, pivot_threshold=0.1, nthreads=0,
-               stream=None) -> Handle:
+               working_vectors=0, stream=None) -> Handle:
     L = lib()
     rp, rpp = _arr(rowptr, np.int64)
     ci, cip = _arr(colind, np.int32)
     va, vap = _arr(vals, np.float64)
     pa, pap = _arr(part, np.int32)
-    o = pslr_default_options()
-    o.m, o.rank, o.precision = int(m), int(rank), int(precision)
-    o.want_transpose = 1 if want_transpose else 0
-    o.seed, o.pivot_threshold, o.nthreads = int(seed), float(pivot_threshold), int(nthreads)
-    keep = None
-    if v0 is not None:
-        keep, o.v0 = _arr(v0, np.float64)
+    o, keep = _options(m, rank, precision, want_transpose, v0, seed, pivot_threshold, nthreads,
+                       working_vectors)
     out = C.c_void_p()
     n = len(rp) - 1
     st = L.pslr_setup(n, rpp, cip, vap, pap, int(nparts), C.byref(o), _stream_ptr(stream),
@@ -186,6 +199,26 @@ def pslr_setup(rowptr, colind, vals, part, nparts, m=3, rank=16, precision=0,
     _check(st, (PSLR_OK, PSLR_EBREAKDOWN))
     del keep
     return Handle(out, n, st)
+
+
+def pslr_setup_batched(rowptr, colind, vals, part, nparts, sys_ptr, m=3, rank=16, precision=0,
+                       want_transpose=False, v0=None, seed=1, pivot_threshold=0.1, nthreads=0,
+                       working_vectors=0, stream=None) -> Handle:
+    L = lib()
+    rp, rpp = _arr(rowptr, np.int64)
+    ci, cip = _arr(colind, np.int32)
+    va, vap = _arr(vals, np.float64)
+    pa, pap = _arr(part, np.int32)
+    sp, spp = _arr(sys_ptr, np.int64)
+    o, keep = _options(m, rank, precision, want_transpose, v0, seed, pivot_threshold, nthreads,
+                       working_vectors)
+    out = C.c_void_p()
+    n = len(rp) - 1
+    st = L.pslr_setup_batched(n, rpp, cip, vap, pap, int(nparts), len(sp) - 1, spp, C.byref(o),
+                              _stream_ptr(stream), C.byref(out))
+    _check(st, (PSLR_OK, PSLR_EBREAKDOWN))
+    del keep
+    return Handle(out, n, st, nsys=len(sp) - 1)
 
 
 def pslr_apply(h: Handle, b, z, stream=None):
@@ -205,13 +238,16 @@ def pslr_apply_transpose(h: Handle, b, z, stream=None):
 
 
 def fgmres_solve(h: Handle, b, x, restart=40, maxit=500, tol=1e-8, transpose=False, stream=None):
-    """Returns (status, iters[nrhs], relres[nrhs]); x holds the initial guess and the result."""
+    """Returns (status, iters, relres); x holds the initial guess and the result.
+
+    iters/relres have nrhs entries, or nrhs * nsys (index r * nsys + s) on a
+    batched handle."""
     bp, nrhs, ldb = _vec(b, h.n)
     xp, nrx, ldx = _vec(x, h.n)
     if nrx != nrhs:
         raise ValueError("b and x have different column counts")
-    its = np.zeros(nrhs, dtype=np.int32)
-    rel = np.zeros(nrhs, dtype=np.float64)
+    its = np.zeros(nrhs * h.nsys, dtype=np.int32)
+    rel = np.zeros(nrhs * h.nsys, dtype=np.float64)
     st = lib().fgmres_solve(h.ptr, nrhs, bp, ldb, xp, ldx, int(restart), int(maxit), float(tol),
                             1 if transpose else 0, its.ctypes.data_as(_I32P),
                             rel.ctypes.data_as(_F64P), _stream_ptr(stream))

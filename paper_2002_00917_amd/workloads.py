@@ -270,6 +270,17 @@ def c3_systems(count: int = 48, side_lo: int = 32, side_hi: int = 512, seed: int
     return out
 
 
+def union(systems):
+    """Block-diagonal union of several workloads' matrices.
+
+    Returns (CSR, sys_ptr) with system s on rows sys_ptr[s] .. sys_ptr[s+1]-1.
+    """
+    mats = [w.A.to_scipy() for w in systems]
+    U = CSR.from_scipy(sp.block_diag(mats, format="csr"))
+    sys_ptr = np.concatenate([[0], np.cumsum([m.shape[0] for m in mats])]).astype(np.int64)
+    return U, sys_ptr
+
+
 def c5(N: int = 256, kappa_seed: int = 5, ref_seed: int = 6):
     """2D variable-coefficient Helmholtz-type problem for the gradient check.
 
