@@ -107,6 +107,68 @@ def run_form(P, torch, A, lab, b, precision, steps, warmup, m, rank, restart, to
                 relres=rels, trace=tr, apply_ms=apply_ms, series_ms=series_ms)
 
 
+def run_batched(P, torch, wl, steps, warmup, restart=120, rank=64, tol=1e-8):
+    """48 uneven 2D shifted Laplacians in one batched handle, 8 rhs each."""
+    dev = torch.device("cuda:0")
+    systems = wl.c3_systems()
+    labels, off = [], 0
+    for w in systems:
+        lab, nl = P.pslr_partition_region_growing(w.A.rowptr, w.A.colind, w.region_parts,
+                                                  w.region_seed)
+        labels.append(lab + off)
+        off += nl
+    U, sys_ptr = wl.union(systems)
+    lab = np.concatenate(labels).astype(np.int32)
+    b = np.concatenate([w.b for w in systems], axis=0)
+    nrhs = b.shape[1]
+    t0 = time.perf_counter()
+    h = P.pslr_setup_batched(U.rowptr, U.colind, U.vals, lab, off, sys_ptr, m=3, rank=rank, seed=3,
+                             autotune=True)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    info = P.pslr_info(h)
+    bt = torch.tensor(np.ascontiguousarray(b.T), dtype=torch.float64, device=dev)
+    x = torch.zeros_like(bt)
+    for _ in range(warmup):
+        x.zero_()
+        P.fgmres_solve(h, bt, x, restart=restart, maxit=500, tol=tol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = rels = None
+    for _ in range(steps):
+        x.zero_()
+        st, its, rels = P.fgmres_solve(h, bt, x, restart=restart, maxit=500, tol=tol)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    z = torch.zeros_like(bt)
+    times = []
+    for _ in range(12):
+        a0 = torch.cuda.Event(enable_timing=True)
+        a1 = torch.cuda.Event(enable_timing=True)
+        a0.record()
+        P.pslr_apply(h, bt, z)
+        a1.record()
+        torch.cuda.synchronize()
+        times.append(a0.elapsed_time(a1))
+    apply_ms = float(np.median(times[2:]))
+    pairs = len(systems) * nrhs
+    ok = bool(np.all(rels <= tol))
+    return {
+        "workload": "48 2D 5-point shifted Laplacians, sides U{32..512}, sigma = U[0.5,1.5] * "
+                    "sigma_20neg(N), 4-32 region-grown subdomains each, 8 rhs N(0,1), seed 3; "
+                    "m=3, r_k=%d per system, FGMRES(%d) per (system, rhs) to 1e-8" % (rank, restart),
+        "n_total": int(U.n), "systems": len(systems), "subdomains": int(off), "nrhs": nrhs,
+        "solves_per_s": pairs * steps / wall if ok else 0.0,
+        "all_converged": ok, "max_relres": float(np.max(rels)),
+        "iterations_max": int(np.max(its)), "iterations_mean": float(np.mean(its)),
+        "seconds_per_batch": wall / steps, "setup_s": setup_s,
+        "apply_ms_all_systems_8rhs": apply_ms,
+        "apply_GBps": (info["apply_bytes"] + (nrhs - 1) * info["apply_bytes_rhs"]) / (apply_ms * 1e-3) / 1e9,
+        "global_vectors": info["global_vectors"], "threads": info["threads"],
+        "lane_shift": info["lane_shift"],
+    }
+
+
 def cpu_baseline(A, b, m, rank, restart, its_gpu, target_s=12.0):
     """The oracle timed on a bounded number of FGMRES iterations on the host cores."""
     from oracle import pslr as opslr
@@ -152,6 +214,7 @@ def main():
     ap.add_argument("--restart", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--forms", default="fp64,fp32_apply")
+    ap.add_argument("--batched-steps", type=int, default=1)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device-to-device (counter calibration run)")
     args = ap.parse_args()
@@ -233,6 +296,10 @@ def main():
             "levels_B": inf["max_levels_B"], "fill_total": inf["fill_total"],
             "seconds_factor": inf["seconds_factor"], "seconds_arnoldi": inf["seconds_arnoldi"],
         }
+    if args.batched_steps > 0:
+        log("batched systems ...")
+        out["batched"] = run_batched(P, torch, wl, args.batched_steps, 0)
+        log("batched: %s" % json.dumps(out["batched"]))
     if not args.no_cpu:
         log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(A, w.b, m, rank, restart, f64["its"][0])

@@ -193,8 +193,10 @@ struct pslr_ctx {
   int nchunk_lr = 1;
   const Seg* d_qcols = nullptr;
   // global working vectors when a subdomain does not fit in LDS
-  bool gx = false;
+  bool gx = false;          // working vectors forced to global memory
+  size_t lds_max = 65536;   // LDS bytes a workgroup may use
   int64_t gws_stride = 0;
+  int tuned_threads = 0, tuned_gshift = 0;
   const int64_t* d_rb_off = nullptr;
   // apply workspaces
   int ws_nrhs = 0;
@@ -208,7 +210,9 @@ struct pslr_ctx {
   int f_nrhs = 0, f_restart = 0;
   double *fVb = nullptr, *fZb = nullptr, *fW = nullptr, *fdbuf = nullptr, *fh = nullptr,
          *fscl = nullptr, *fy = nullptr;
-  Seg *fcolsV = nullptr, *fcolsB = nullptr, *fcolsX = nullptr;
+  Seg *fcolsV = nullptr, *fcolsB = nullptr, *fcolsX = nullptr, *fcolsM = nullptr;
+  uint8_t* factive = nullptr;
+  const uint8_t* cur_active = nullptr;  // mask of (system, rhs) columns the apply works on
   // info
   pslr_info_t info{};
   // phase tracing: each traced apply leaves a list of (phase, event) marks
@@ -385,8 +389,9 @@ hipError_t upload_dir(DevPool& pool, const Reordering& R, const std::vector<Bloc
 }
 
 template <typename T>
-size_t lds_bytes(const ApplyArrays<T>& A, int kmax) {
-  return sizeof(T) * ((size_t)A.maxPB + A.maxLR + 2 * (size_t)A.maxQB + 2 * (size_t)std::max(kmax, 1));
+size_t lds_bytes(const ApplyArrays<T>& A, int kmax, int R = 1) {
+  return sizeof(T) * (size_t)R *
+         ((size_t)A.maxPB + A.maxLR + 2 * (size_t)A.maxQB + 2 * (size_t)std::max(kmax, 1));
 }
 
 pslr_status ensure_ws(pslr_ctx* h, int nrhs) {
@@ -398,7 +403,8 @@ pslr_status ensure_ws(pslr_ctx* h, int nrhs) {
   HIP_TRY(h->ws.alloc<double>(q * nrhs, (double**)&h->u1));
   HIP_TRY(h->ws.alloc<double>((size_t)h->nchunk_lr * nrhs * std::max(h->k, 1), (double**)&h->partial));
   h->gws = nullptr;
-  if (h->gx) HIP_TRY(h->ws.alloc<double>((size_t)h->gws_stride * nrhs, (double**)&h->gws));
+  if (h->gws_stride > 0)
+    HIP_TRY(h->ws.alloc<double>((size_t)h->gws_stride * ((nrhs + 7) / 8 * 8), (double**)&h->gws));
   for (ApplyArrays<double>* A : {&h->fw64, &h->tr64}) A->gws = h->gws;
   for (ApplyArrays<float>* A : {&h->fw32, &h->tr32}) A->gws = h->gws;
   h->ws_nrhs = nrhs;
@@ -412,16 +418,16 @@ template <>
 hipError_t lowrank_partial<double>(pslr_ctx* h, const double* y, int64_t ldy, int nrhs, double* part,
                                    hipStream_t s) {
   return launch_lr_partial<double, double>(h->nchunk_lr, h->d_chunks, h->k, h->V64, y, ldy, nrhs,
-                                           part, s);
+                                           part, h->cur_active, h->nsys, s);
 }
 template <>
 hipError_t lowrank_partial<float>(pslr_ctx* h, const float* y, int64_t ldy, int nrhs, float* part,
                                   hipStream_t s) {
   if (h->Vbf)
     return launch_lr_partial<float, __hip_bfloat16>(h->nchunk_lr, h->d_chunks, h->k, h->Vbf, y, ldy,
-                                                    nrhs, part, s);
+                                                    nrhs, part, h->cur_active, h->nsys, s);
   return launch_lr_partial<float, float>(h->nchunk_lr, h->d_chunks, h->k, h->V32, y, ldy, nrhs, part,
-                                         s);
+                                         h->cur_active, h->nsys, s);
 }
 template <typename T>
 hipError_t lowrank_expand(pslr_ctx* h, const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs,
@@ -501,14 +507,43 @@ struct Tracer {
   }
 };
 
+// Right-hand-side tile width and working-vector placement of an apply: LDS with
+// the widest tile that fits, unless several right-hand sides would then be
+// solved one or two at a time (each tile re-reads every factor entry), in
+// which case the global workspace with tiles of up to 8.
+template <typename T>
+LaunchCfg choose_launch(pslr_ctx* h, const ApplyArrays<T>& A, int nrhs, hipStream_t s) {
+  LaunchCfg c{h->threads, 0, s, 1, false};
+  int want = 1;
+  while (want < 8 && want < nrhs) want *= 2;
+  int Rl = 0;
+  if (!h->gx)
+    for (int R = want; R >= 1; R /= 2)
+      if (lds_bytes(A, A.kmax, R) <= h->lds_max) {
+        Rl = R;
+        break;
+      }
+  if (Rl == 0 || (nrhs >= 4 && Rl < 4)) {
+    c.gx = true;
+    c.R = want;
+  } else {
+    c.R = Rl;
+    c.lds = lds_bytes(A, A.kmax, Rl);
+  }
+  return c;
+}
+
 // z = M^{-1} b (or M^{-T} b) with apply arrays A.
 template <typename T>
-pslr_status run_apply(pslr_ctx* h, const ApplyArrays<T>& A, size_t lds, bool transpose, int nrhs,
+pslr_status run_apply(pslr_ctx* h, const ApplyArrays<T>& Ah, size_t lds, bool transpose, int nrhs,
                       const double* b, int64_t ldb, double* z, int64_t ldz, hipStream_t s) {
+  ApplyArrays<T> A = Ah;
+  A.active = h->cur_active;
+  (void)lds;
   pslr_status st = ensure_ws(h, nrhs);
   if (st != PSLR_OK) return st;
   const int64_t q = std::max<int64_t>(h->R.q, 1);
-  LaunchCfg cfg{h->threads, lds, s};
+  LaunchCfg cfg = choose_launch(h, A, nrhs, s);
   T* y = (T*)h->y;
   T* ua = (T*)h->u0;
   T* ub = (T*)h->u1;
@@ -713,7 +748,7 @@ pslr_status arnoldi(pslr_ctx* h, const double* v0host, uint64_t seed, hipStream_
   }
   HIP_TRY(hipMemcpy(Vd, v.data(), sizeof(double) * q, hipMemcpyHostToDevice));
   const ApplyArrays<double>& A = h->fw64;
-  LaunchCfg cfg{h->threads, h->lds64, s};
+  LaunchCfg cfg = choose_launch(h, A, 1, s);
   std::vector<double> Hb((size_t)ns * (kreq + 1) * kreq, 0.0), hb((size_t)ns * (2 * (kreq + 1) + 2)),
       sc(ns);
   std::vector<int> kdone(ns, 0);
@@ -783,6 +818,61 @@ pslr_status arnoldi(pslr_ctx* h, const double* v0host, uint64_t seed, hipStream_
   return upload_lowrank(h);
 }
 
+// Pick the workgroup size and the lane-group scaling of the triangular solves by
+// timing applies (one right-hand side, HIP events) over a small grid of choices.
+pslr_status autotune(pslr_ctx* h, hipStream_t s) {
+  const int64_t n = h->R.n;
+  if (n == 0) return PSLR_OK;
+  DevPool tmp;
+  double *b, *z;
+  HIP_TRY(tmp.alloc<double>(n, &b));
+  HIP_TRY(tmp.alloc<double>(n, &z));
+  {
+    std::vector<double> hb(n);
+    uint64_t st = 12345;
+    for (int64_t i = 0; i < n; ++i) hb[i] = (double)(splitmix64_next(st) >> 11) * 0x1.0p-53 - 0.5;
+    HIP_TRY(hipMemcpy(b, hb.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+  }
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  const bool tr = h->trace;
+  h->trace = false;
+  float best = 1e30f;
+  int bt = h->threads, bg = 0;
+  for (int threads : {512, 1024})
+    for (int gs : {-1, 0, 1}) {
+      h->threads = threads;
+      for (auto* A : {&h->fw64, &h->tr64}) A->gshift = gs;
+      for (auto* A : {&h->fw32, &h->tr32}) A->gshift = gs;
+      float tmin = 1e30f;
+      for (int rep = 0; rep < 3; ++rep) {
+        HIP_TRY(hipEventRecord(e0, s));
+        pslr_status st = apply_dir(h, false, 1, b, n, z, n, s);
+        if (st) return st;
+        HIP_TRY(hipEventRecord(e1, s));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (rep > 0) tmin = std::min(tmin, ms);
+      }
+      if (tmin < best) {
+        best = tmin;
+        bt = threads;
+        bg = gs;
+      }
+    }
+  h->threads = bt;
+  for (auto* A : {&h->fw64, &h->tr64}) A->gshift = bg;
+  for (auto* A : {&h->fw32, &h->tr32}) A->gshift = bg;
+  h->trace = tr;
+  h->tuned_threads = bt;
+  h->tuned_gshift = bg;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return PSLR_OK;
+}
+
 void fill_info(pslr_ctx* h, const std::vector<BlockFactor>& fB, const std::vector<BlockFactor>& fC,
                const Blocks& Bk, const int64_t bytes[4]) {
   pslr_info_t& I = h->info;
@@ -832,6 +922,8 @@ void fill_info(pslr_ctx* h, const std::vector<BlockFactor>& fB, const std::vecto
   I.apply_bytes_rhs = vectors;
   I.nsys = h->nsys;
   I.global_vectors = h->gx ? 1 : 0;
+  I.threads = h->threads;
+  I.lane_shift = h->fw64.gshift;
 }
 
 }  // namespace
@@ -854,6 +946,7 @@ void pslr_default_options(pslr_options* o) {
   o->pivot_threshold = 0.1;
   o->nthreads = 0;
   o->working_vectors = 0;
+  o->autotune = 0;
 }
 
 const char* pslr_status_string(pslr_status s) {
@@ -1170,31 +1263,25 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
   }
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, h->device));
-  const size_t lds_max = prop.sharedMemPerBlock > 0 ? prop.sharedMemPerBlock : 65536;
+  h->lds_max = prop.sharedMemPerBlock > 0 ? prop.sharedMemPerBlock : 65536;
   DirHost Dfw = build_dir(h->R, Bk, fB, fC, false);
   int64_t bytes[4] = {0, 0, 0, 0};
   HIP_TRY(upload_dir<double>(h->pool, h->R, fB, fC, Dfw, false, d_int_ptr, d_if_ptr, d_if_orig,
                              h->fw64, bytes));
-  h->lds64 = lds_bytes(h->fw64, h->rank);
-  // subdomains too large for LDS: working vectors in a global workspace
+  // global workspace layout, used by applies whose subdomains do not fit in
+  // LDS or that solve wide right-hand-side tiles
   {
-    const size_t need32 = lds_bytes(h->fw64, h->rank) / 2;
-    const bool need_gx = (h->precision == 0 ? h->lds64 : need32) > lds_max ||
-                         (h->want_T && h->precision == 0 && h->lds64 > lds_max);
-    h->gx = need_gx || o.working_vectors == 1;
-    if (h->gx) {
-      std::vector<int64_t> rb(nparts + 1, 0);
-      for (int i = 0; i < nparts; ++i) {
-        int mx = 1;
-        for (const BlockFactor* f : {&fB[i], &fC[i]})
-          for (const TriPacked* T : {&f->lo, &f->up, &f->loT, &f->upT}) mx = std::max(mx, T->max_lrows);
-        rb[i + 1] = rb[i] + mx;
-      }
-      HIP_TRY(h->pool.upload(rb, &h->d_rb_off));
-      h->gws_stride = h->R.p + 2 * h->R.q + rb[nparts] + (int64_t)nparts * 2 * std::max(h->rank, 1);
-      h->lds64 = 0;
+    std::vector<int64_t> rb(nparts + 1, 0);
+    for (int i = 0; i < nparts; ++i) {
+      int mx = 1;
+      for (const BlockFactor* f : {&fB[i], &fC[i]})
+        for (const TriPacked* T : {&f->lo, &f->up, &f->loT, &f->upT}) mx = std::max(mx, T->max_lrows);
+      rb[i + 1] = rb[i] + mx;
     }
+    HIP_TRY(h->pool.upload(rb, &h->d_rb_off));
+    h->gws_stride = h->R.p + 2 * h->R.q + rb[nparts] + (int64_t)nparts * 2 * std::max(h->rank, 1);
   }
+  h->gx = o.working_vectors == 1;
   auto set_gx = [&](auto& A) {
     A.part_sys = h->d_part_sys;
     A.gshift = 0;
@@ -1202,14 +1289,13 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
     A.gws_stride = h->gws_stride;
     A.rb_off = h->d_rb_off;
     A.kmax = std::max(h->rank, 1);
+    A.nsys = h->nsys;
+    A.active = nullptr;
   };
   set_gx(h->fw64);
-  if (!h->gx) HIP_TRY(set_lds_limit<double>(h->lds64));
+  HIP_TRY(set_lds_limit<double>(h->lds_max));
+  HIP_TRY(set_lds_limit<float>(h->lds_max));
   h->have64 = true;
-  if (h->gx) {
-    st = ensure_ws(h.get(), 1);
-    if (st) return st;
-  }
 
   // Arnoldi on E_rr(m) in FP64 (Algorithm 4, lines 6-8)
   bool breakdown = false;
@@ -1227,8 +1313,6 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
     HIP_TRY(upload_dir<float>(h->pool, h->R, fB, fC, Dfw, false, d_int_ptr, d_if_ptr, d_if_orig,
                               h->fw32, bytes));
     set_gx(h->fw32);
-    h->lds32 = h->gx ? 0 : lds_bytes(h->fw32, h->rank);
-    if (!h->gx) HIP_TRY(set_lds_limit<float>(h->lds32));
     h->have32 = true;
   }
   if (h->want_T) {
@@ -1238,21 +1322,15 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
       HIP_TRY(upload_dir<float>(h->pool, h->R, fB, fC, Dtr, true, d_int_ptr, d_if_ptr, d_if_orig,
                                 h->tr32, tb));
       set_gx(h->tr32);
-      if (!h->gx) {
-        h->lds32 = std::max(h->lds32, lds_bytes(h->tr32, h->rank));
-        HIP_TRY(set_lds_limit<float>(h->lds32));
-      }
     }
     HIP_TRY(upload_dir<double>(h->pool, h->R, fB, fC, Dtr, true, d_int_ptr, d_if_ptr, d_if_orig,
                                h->tr64, tb));
     set_gx(h->tr64);
-    if (!h->gx) {
-      h->lds64 = std::max(h->lds64, lds_bytes(h->tr64, h->rank));
-      HIP_TRY(set_lds_limit<double>(h->lds64));
-    }
     h->haveT = true;
-    h->ws.release();
-    h->ws_nrhs = 0;
+  }
+  if (o.autotune) {
+    st = autotune(h.get(), s);
+    if (st) return st;
   }
   fill_info(h.get(), fB, fC, Bk, bytes);
   h->info.seconds_reorder = t1 - t0;
@@ -1329,9 +1407,13 @@ pslr_status fgmres_solve(pslr_handle h, int32_t nrhs, const double* b, int64_t l
     HIP_TRY(h->fpool.alloc<double>((size_t)ncol * (2 * R1 + 1), &h->fh));
     HIP_TRY(h->fpool.alloc<double>(ncol, &h->fscl));
     HIP_TRY(h->fpool.alloc<double>((size_t)ncol * restart, &h->fy));
-    HIP_TRY(h->fpool.alloc<Seg>((size_t)3 * ncol, &h->fcolsV));
+    HIP_TRY(h->fpool.alloc<Seg>((size_t)4 * ncol, &h->fcolsV));
     h->fcolsB = h->fcolsV + ncol;
     h->fcolsX = h->fcolsB + ncol;
+    h->fcolsM = h->fcolsX + ncol;
+    HIP_TRY(h->fpool.alloc<uint8_t>(ncol, &h->factive));
+    // columns a masked apply leaves unwritten must hold finite values
+    HIP_TRY(hipMemsetAsync(h->fZb, 0, sizeof(double) * (size_t)blk * restart, s));
     h->f_nrhs = nrhs;
     h->f_restart = restart;
   }
@@ -1344,7 +1426,9 @@ pslr_status fgmres_solve(pslr_handle h, int32_t nrhs, const double* b, int64_t l
       cols[2 * ncol + r * ns + c] = Seg{r * ldx + o, len};
     }
   HIP_TRY(hipMemcpyAsync(h->fcolsV, cols.data(), sizeof(Seg) * cols.size(), hipMemcpyHostToDevice, s));
-  const Seg *cV = h->fcolsV, *cB = h->fcolsB, *cX = h->fcolsX;
+  const Seg *cV = h->fcolsV, *cB = h->fcolsB, *cX = h->fcolsX, *cM = h->fcolsM;
+  std::vector<Seg> mcols(cols.begin(), cols.begin() + ncol);
+  std::vector<uint8_t> amask(ncol);
   double* Vb = h->fVb;
   double* Zb = h->fZb;
   double* W = h->fW;
@@ -1392,18 +1476,27 @@ pslr_status fgmres_solve(pslr_handle h, int32_t nrhs, const double* b, int64_t l
     for (int j = 0; j < restart; ++j) {
       double* Vj = Vb + (size_t)j * blk;
       double* Zj = Zb + (size_t)j * blk;
+      // converged columns skip the apply and the vector work of this iteration
+      for (int c = 0; c < ncol; ++c) {
+        amask[c] = act[c] ? 1 : 0;
+        mcols[c].len = act[c] ? cols[c].len : 0;
+      }
+      HIP_TRY(hipMemcpyAsync(h->factive, amask.data(), ncol, hipMemcpyHostToDevice, s));
+      HIP_TRY(hipMemcpyAsync(h->fcolsM, mcols.data(), sizeof(Seg) * ncol, hipMemcpyHostToDevice, s));
+      h->cur_active = h->factive;
       pslr_status st = apply_dir(h, transpose != 0, nrhs, Vj, n, Zj, n, s);
+      h->cur_active = nullptr;
       if (st) return st;
       HIP_TRY(launch_spmv(n, Ap, Ac, Av, nrhs, Zj, n, W, n, nullptr, 0, s));
       // classical Gram-Schmidt, two passes, then ||w||; one host synchronisation
       const int nv = j + 1;
-      HIP_TRY(launch_mdot_seg(ncol, cV, cV, nv, Vb, blk, W, h->nchunk, h->fdbuf, s));
+      HIP_TRY(launch_mdot_seg(ncol, cM, cM, nv, Vb, blk, W, h->nchunk, h->fdbuf, s));
       HIP_TRY(launch_reduce(h->nchunk, ncol, nv, h->fdbuf, dh1, s));
-      HIP_TRY(launch_maxpy_seg(ncol, cV, cV, maxlen, nv, Vb, blk, dh1, nv, W, 1.0, s));
-      HIP_TRY(launch_mdot_seg(ncol, cV, cV, nv, Vb, blk, W, h->nchunk, h->fdbuf, s));
+      HIP_TRY(launch_maxpy_seg(ncol, cM, cM, maxlen, nv, Vb, blk, dh1, nv, W, 1.0, s));
+      HIP_TRY(launch_mdot_seg(ncol, cM, cM, nv, Vb, blk, W, h->nchunk, h->fdbuf, s));
       HIP_TRY(launch_reduce(h->nchunk, ncol, nv, h->fdbuf, dh2, s));
-      HIP_TRY(launch_maxpy_seg(ncol, cV, cV, maxlen, nv, Vb, blk, dh2, nv, W, 1.0, s));
-      HIP_TRY(launch_mdot_seg(ncol, cV, cV, 1, W, 0, W, h->nchunk, h->fdbuf, s));
+      HIP_TRY(launch_maxpy_seg(ncol, cM, cM, maxlen, nv, Vb, blk, dh2, nv, W, 1.0, s));
+      HIP_TRY(launch_mdot_seg(ncol, cM, cM, 1, W, 0, W, h->nchunk, h->fdbuf, s));
       HIP_TRY(launch_reduce(h->nchunk, ncol, 1, h->fdbuf, dnn, s));
       HIP_TRY(hipMemcpyAsync(hbuf.data(), dh1, sizeof(double) * hbuf.size(), hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
@@ -1515,7 +1608,7 @@ pslr_status pslr_set_lowrank(pslr_handle h, int32_t k, const double* V, int64_t 
   const int64_t q = h->R.q;
   h->k = k;
   h->sys_k.assign(1, k);
-  if (h->gx && k > h->fw64.kmax) {  // global workspace holds 2k scratch per block
+  if (k > h->fw64.kmax) {  // global workspace holds 2k scratch per block
     h->gws_stride += (int64_t)h->R.nparts * 2 * (k - h->fw64.kmax);
     for (ApplyArrays<double>* A : {&h->fw64, &h->tr64}) {
       A->kmax = k;
@@ -1532,17 +1625,7 @@ pslr_status pslr_set_lowrank(pslr_handle h, int32_t k, const double* V, int64_t 
     for (int64_t r = 0; r < q; ++r) h->hV[(size_t)j * q + r] = V[(size_t)j * ldv + r];
     for (int i = 0; i < k; ++i) h->hH[(size_t)j * k + i] = H[(size_t)j * ldh + i];
   }
-  if (k > h->rank) {  // LDS for W/Z scratch grows with k
-    h->rank = k;
-    if (h->have64 && !h->gx) {
-      h->lds64 = std::max(h->lds64, lds_bytes(h->fw64, k));
-      HIP_TRY(set_lds_limit<double>(h->lds64));
-    }
-    if (h->have32 && !h->gx) {
-      h->lds32 = std::max(h->lds32, lds_bytes(h->fw32, k));
-      HIP_TRY(set_lds_limit<float>(h->lds32));
-    }
-  }
+  if (k > h->rank) h->rank = k;
   if (h->ws_nrhs > 0) {  // partial buffer is sized by k
     h->ws.release();
     h->ws_nrhs = 0;

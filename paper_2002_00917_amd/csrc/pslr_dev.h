@@ -66,6 +66,10 @@ struct ApplyArrays {
   int64_t gws_stride;         // elements per right-hand side
   const int64_t* rb_off;      // nparts + 1: per-block level-scratch offsets
   int32_t kmax;
+  int32_t nsys;
+  // optional (system, rhs) mask, index r * nsys + s: a block skips its work for
+  // right-hand side r when its system's entry is 0 (converged FGMRES columns)
+  const uint8_t* active;
 };
 
 // A row chunk of the interface vectors for the V^T y partial sums; chunks never
@@ -82,8 +86,10 @@ struct Seg {
 
 struct LaunchCfg {
   int threads;
-  size_t lds;
+  size_t lds;          // dynamic LDS bytes (LDS working vectors)
   hipStream_t stream;
+  int R;               // right-hand sides per workgroup tile: 1, 2, 4 or 8
+  bool gx;             // working vectors in the global workspace
 };
 
 // ---- preconditioner kernels (T = double or float; TV = V's storage type)
@@ -92,7 +98,8 @@ hipError_t launch_head(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, co
                        int64_t ldb, T* y, int64_t ldy);
 template <typename T, typename TV>
 hipError_t launch_lr_partial(int nchunk, const LrChunk* chunks, int k, const TV* V, const T* y,
-                             int64_t ldy, int nrhs, T* partial, hipStream_t s);
+                             int64_t ldy, int nrhs, T* partial, const uint8_t* active, int nsys,
+                             hipStream_t s);
 // G holds one k x k row-major matrix per system; block i uses system part_sys[i]
 // and the partial sums of chunks sys_chunk[s] .. sys_chunk[s+1].
 template <typename T, typename TV>

@@ -28,56 +28,70 @@ __device__ __forceinline__ float tv_to_float(__hip_bfloat16 v) { return __bfloat
 __device__ __forceinline__ float tv_to_float(float v) { return v; }
 __device__ __forceinline__ double tv_to_float(double v) { return v; }
 
-// sum_j v[j] * X[idx[j]] over this lane's share (j = lane, lane+G, ...), with
-// eight independent loads in flight per lane.
-template <typename T>
-__device__ __forceinline__ T dot_gather(const T* __restrict__ v, const int32_t* __restrict__ idx,
-                                        int len, const T* X, int lane, int G) {
-  T a0 = 0, a1 = 0;
+// Vectors of a workgroup hold a tile of R right-hand sides interleaved:
+// element (position p, rhs r) at X[p * R + r].  Each factor entry is loaded
+// once and applied to all R of them.
+
+// acc[r] += sum_j v[j] * X[idx[j] * R + r] over this lane's share (j = lane,
+// lane + G, ...), several independent loads in flight per lane.
+template <typename T, int R>
+__device__ __forceinline__ void dot_gather(const T* __restrict__ v, const int32_t* __restrict__ idx,
+                                           int len, const T* X, int lane, int G, T (&acc)[R]) {
+  constexpr int U = R == 1 ? 8 : 4;
   int j = lane;
-  for (; j + 7 * G < len; j += 8 * G) {
-    T v0 = v[j], v1 = v[j + G], v2 = v[j + 2 * G], v3 = v[j + 3 * G];
-    T v4 = v[j + 4 * G], v5 = v[j + 5 * G], v6 = v[j + 6 * G], v7 = v[j + 7 * G];
-    int c0 = idx[j], c1 = idx[j + G], c2 = idx[j + 2 * G], c3 = idx[j + 3 * G];
-    int c4 = idx[j + 4 * G], c5 = idx[j + 5 * G], c6 = idx[j + 6 * G], c7 = idx[j + 7 * G];
-    a0 += v0 * X[c0];
-    a1 += v1 * X[c1];
-    a0 += v2 * X[c2];
-    a1 += v3 * X[c3];
-    a0 += v4 * X[c4];
-    a1 += v5 * X[c5];
-    a0 += v6 * X[c6];
-    a1 += v7 * X[c7];
+  for (; j + (U - 1) * G < len; j += U * G) {
+    T vv[U];
+    int cc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      vv[u] = v[j + u * G];
+      cc[u] = idx[j + u * G];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] += vv[u] * X[cc[u] * R + r];
   }
-  for (; j < len; j += G) a0 += v[j] * X[idx[j]];
-  return a0 + a1;
+  for (; j < len; j += G) {
+    const T vv = v[j];
+    const int c = idx[j];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] += vv * X[c * R + r];
+  }
 }
 
-// sum_j v[j] * R[j] over this lane's share, eight loads in flight per lane.
-template <typename T>
-__device__ __forceinline__ T dot_dense(const T* __restrict__ v, int len, const T* R, int lane, int G) {
-  T a0 = 0, a1 = 0;
+// acc[r] += sum_j v[j] * Y[j * R + r] over this lane's share.
+template <typename T, int R>
+__device__ __forceinline__ void dot_dense(const T* __restrict__ v, int len, const T* Y, int lane,
+                                          int G, T (&acc)[R]) {
+  constexpr int U = R == 1 ? 8 : 4;
   int j = lane;
-  for (; j + 7 * G < len; j += 8 * G) {
-    T v0 = v[j], v1 = v[j + G], v2 = v[j + 2 * G], v3 = v[j + 3 * G];
-    T v4 = v[j + 4 * G], v5 = v[j + 5 * G], v6 = v[j + 6 * G], v7 = v[j + 7 * G];
-    a0 += v0 * R[j];
-    a1 += v1 * R[j + G];
-    a0 += v2 * R[j + 2 * G];
-    a1 += v3 * R[j + 3 * G];
-    a0 += v4 * R[j + 4 * G];
-    a1 += v5 * R[j + 5 * G];
-    a0 += v6 * R[j + 6 * G];
-    a1 += v7 * R[j + 7 * G];
+  for (; j + (U - 1) * G < len; j += U * G) {
+    T vv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) vv[u] = v[j + u * G];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] += vv[u] * Y[(j + u * G) * R + r];
   }
-  for (; j < len; j += G) a0 += v[j] * R[j];
-  return a0 + a1;
+  for (; j < len; j += G) {
+    const T vv = v[j];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] += vv * Y[j * R + r];
+  }
 }
 
-// Solve one packed triangular factor of block `bi` in place on the LDS vector X
-// (positions 0..n-1); Rb is LDS scratch of max_lrows entries.  All threads of
-// the workgroup must call it.  Ends with a barrier.
-template <typename T>
+template <typename T, int R>
+__device__ __forceinline__ void group_sum_r(T (&acc)[R], int G) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = group_sum(acc[r], G);
+}
+
+// Solve one packed triangular factor of block `bi` in place on the vector tile
+// X (positions 0..n-1, R right-hand sides); Rb is scratch of max_lrows * R
+// entries.  All threads of the workgroup must call it.  Ends with a barrier.
+template <typename T, int R>
 __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift) {
   const DevTriBlock B = A.blk[bi];
   const int tid = threadIdx.x, nthr = blockDim.x;
@@ -105,10 +119,15 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
     {
       const int grp = tid / G1, lane = tid - grp * G1, ngrp = nthr / G1;
       for (int k = grp; k < cnt; k += ngrp) {
-        const int4 r = rec[2 * (b + k)];
-        T acc = dot_gather(val + r.y, B.lower ? col + r.y : ridx + r.w, r.z, X, lane, G1);
-        acc = group_sum(acc, G1);
-        if (lane == 0) Rb[k] = X[r.x] - acc;
+        const int4 rr = rec[2 * (b + k)];
+        T acc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = 0;
+        dot_gather<T, R>(val + rr.y, B.lower ? col + rr.y : ridx + rr.w, rr.z, X, lane, G1, acc);
+        group_sum_r<T, R>(acc, G1);
+        if (lane == 0)
+#pragma unroll
+          for (int r = 0; r < R; ++r) Rb[k * R + r] = X[rr.x * R + r] - acc[r];
       }
     }
     __syncthreads();
@@ -117,10 +136,15 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
       const int grp = tid / G2, lane = tid - grp * G2, ngrp = nthr / G2;
       for (int k = grp; k < cnt; k += ngrp) {
         const int p = rec[2 * (b + k)].x;
-        const int4 r = rec[2 * (b + k) + 1];
-        T acc = dot_dense(tri + r.x, r.y, Rb + r.z, lane, G2);
-        acc = group_sum(acc, G2);
-        if (lane == 0) X[p] = acc;
+        const int4 rr = rec[2 * (b + k) + 1];
+        T acc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = 0;
+        dot_dense<T, R>(tri + rr.x, rr.y, Rb + rr.z * R, lane, G2, acc);
+        group_sum_r<T, R>(acc, G2);
+        if (lane == 0)
+#pragma unroll
+          for (int r = 0; r < R; ++r) X[p * R + r] = acc[r];
       }
     }
     __syncthreads();
@@ -132,62 +156,90 @@ struct Lds {
   T *XB, *Rb, *XC, *U, *W;
 };
 
-// Working vectors of block blockIdx.x for right-hand side blockIdx.y: in LDS,
-// or (GX) in the handle's global workspace when a subdomain is too large for
-// LDS.  The global layout per right-hand side is [X_B: p][X_C: q][U: q]
-// [scratch: sum of per-block level sizes][W: 2k per block].
-template <typename T, bool GX>
+// Working vectors of block blockIdx.x for the right-hand-side tile blockIdx.y:
+// in LDS, or (GX) in the handle's global workspace when a subdomain does not
+// fit.  Global layout of one tile: [X_B: p][X_C: q][U: q][scratch: sum of
+// per-block level sizes][W: 2k per block], every element an R-vector.
+template <typename T, int R, bool GX>
 __device__ Lds<T> carve(const ApplyArrays<T>& A) {
   Lds<T> L;
   if (GX) {
-    const int i = blockIdx.x, r = blockIdx.y;
-    T* base = reinterpret_cast<T*>(A.gws) + (int64_t)r * A.gws_stride;
-    L.XB = base + A.int_ptr[i];
-    L.XC = base + A.p + A.if_ptr[i];
-    L.U = base + A.p + A.q + A.if_ptr[i];
-    L.Rb = base + A.p + 2 * A.q + A.rb_off[i];
-    L.W = base + A.p + 2 * A.q + A.rb_off[A.nparts] + (int64_t)i * 2 * A.kmax;
+    const int i = blockIdx.x, t = blockIdx.y;
+    T* base = reinterpret_cast<T*>(A.gws) + (int64_t)t * R * A.gws_stride;
+    L.XB = base + R * A.int_ptr[i];
+    L.XC = base + R * (A.p + A.if_ptr[i]);
+    L.U = base + R * (A.p + A.q + A.if_ptr[i]);
+    L.Rb = base + R * (A.p + 2 * A.q + A.rb_off[i]);
+    L.W = base + R * (A.p + 2 * A.q + A.rb_off[A.nparts] + (int64_t)i * 2 * A.kmax);
   } else {
     extern __shared__ __align__(16) unsigned char smem[];
     L.XB = reinterpret_cast<T*>(smem);
-    L.Rb = L.XB + A.maxPB;
-    L.XC = L.Rb + A.maxLR;
-    L.U = L.XC + A.maxQB;
-    L.W = L.U + A.maxQB;
+    L.Rb = L.XB + R * A.maxPB;
+    L.XC = L.Rb + R * A.maxLR;
+    L.U = L.XC + R * A.maxQB;
+    L.W = L.U + R * A.maxQB;
   }
   return L;
 }
 
+// right-hand sides r0 .. r0 + nr - 1 of this workgroup's tile; false when the
+// whole tile is masked out (converged FGMRES columns)
+template <typename T, int R>
+__device__ __forceinline__ bool tile_rhs(const ApplyArrays<T>& A, int nrhs, int i, int& r0, int& nr) {
+  r0 = blockIdx.y * R;
+  nr = min(R, nrhs - r0);
+  if (!A.active) return true;
+  const int s = A.part_sys[i];
+  for (int r = 0; r < nr; ++r)
+    if (A.active[(r0 + r) * A.nsys + s]) return true;
+  return false;
+}
+
 // t = B^{-1} f;  y = g - F t   (Algorithm 3, line 2)
-template <typename T, bool GX>
-__global__ void __launch_bounds__(1024) k_head(ApplyArrays<T> A, const double* __restrict__ b, int64_t ldb, T* y,
-                       int64_t ldy) {
-  Lds<T> L = carve<T, GX>(A);
-  const int i = blockIdx.x, r = blockIdx.y, tid = threadIdx.x, nt = blockDim.x;
+template <typename T, int R, bool GX>
+__global__ void __launch_bounds__(1024) k_head(ApplyArrays<T> A, int nrhs, const double* __restrict__ b,
+                                               int64_t ldb, T* y, int64_t ldy) {
+  const int i = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  int r0, nr;
+  if (!tile_rhs<T, R>(A, nrhs, i, r0, nr)) return;
+  Lds<T> L = carve<T, R, GX>(A);
   const int64_t i0 = A.int_ptr[i], pi = A.int_ptr[i + 1] - i0;
   const int64_t f0 = A.if_ptr[i], qi = A.if_ptr[i + 1] - f0;
-  const double* br = b + r * ldb;
-  for (int64_t p = tid; p < pi; p += nt) L.XB[p] = (T)br[A.gB_in[i0 + p]];
+  for (int64_t e = tid; e < pi * R; e += nt) {
+    const int64_t p = e / R;
+    const int r = (int)(e - p * R);
+    L.XB[e] = r < nr ? (T)b[(r0 + r) * ldb + A.gB_in[i0 + p]] : (T)0;
+  }
   __syncthreads();
-  tri_solve(A.LB, i, L.XB, L.Rb, A.gshift);
-  tri_solve(A.UB, i, L.XB, L.Rb, A.gshift);
-  T* yr = y + r * ldy;
+  tri_solve<T, R>(A.LB, i, L.XB, L.Rb, A.gshift);
+  tri_solve<T, R>(A.UB, i, L.XB, L.Rb, A.gshift);
   for (int64_t k = tid; k < qi; k += nt) {
     const int64_t row = f0 + k;
-    T acc = (T)br[A.if_orig[row]];
-    for (int64_t q = A.Fout.ptr[row]; q < A.Fout.ptr[row + 1]; ++q) acc -= A.Fout.val[q] * L.XB[A.Fout.col[q]];
-    yr[row] = acc;
+    T acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = r < nr ? (T)b[(r0 + r) * ldb + A.if_orig[row]] : (T)0;
+    for (int64_t q = A.Fout.ptr[row]; q < A.Fout.ptr[row + 1]; ++q) {
+      const T v = A.Fout.val[q];
+      const int c = A.Fout.col[q];
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] -= v * L.XB[c * R + r];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (r < nr) y[(r0 + r) * ldy + row] = acc[r];
   }
 }
 
 // partial[chunk][r][j] = sum_{rows in chunk} V[row][j] y_r[row]   (V^T y, line 3)
 template <typename T, typename TV>
 __global__ void k_lr_partial(const LrChunk* __restrict__ chunks, int k, const TV* __restrict__ V,
-                             const T* __restrict__ y, int64_t ldy, T* partial) {
+                             const T* __restrict__ y, int64_t ldy, T* partial,
+                             const uint8_t* __restrict__ active, int nsys) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* red = reinterpret_cast<T*>(smem);
   const int chunk = blockIdx.x, r = blockIdx.y, tid = threadIdx.x, nt = blockDim.x;
   const LrChunk C = chunks[chunk];
+  if (active && !active[r * nsys + C.sys]) return;
   const int ng = nt / k;
   const int g = tid / k, j = tid - g * k;
   T acc = 0;
@@ -205,135 +257,209 @@ __global__ void k_lr_partial(const LrChunk* __restrict__ chunks, int k, const TV
 }
 
 // y += V (G (V^T y)) on the rows of block i; optionally u = C0^{-1} y (line 3, line 4 start)
-template <typename T, typename TV, bool GX>
-__global__ void __launch_bounds__(1024) k_lr_expand(ApplyArrays<T> A, int k, const TV* __restrict__ V,
-                            const T* __restrict__ Gall, int gtrans, const T* __restrict__ partial,
-                            const int32_t* __restrict__ sys_chunk, T* y, int64_t ldy, int do_c0,
-                            T* u, int64_t ldu) {
-  Lds<T> L = carve<T, GX>(A);
+template <typename T, typename TV, int R, bool GX>
+__global__ void __launch_bounds__(1024) k_lr_expand(ApplyArrays<T> A, int nrhs, int k,
+                            const TV* __restrict__ V, const T* __restrict__ Gall, int gtrans,
+                            const T* __restrict__ partial, const int32_t* __restrict__ sys_chunk,
+                            T* y, int64_t ldy, int do_c0, T* u, int64_t ldu) {
+  const int i = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  int r0, nr;
+  if (!tile_rhs<T, R>(A, nrhs, i, r0, nr)) return;
+  Lds<T> L = carve<T, R, GX>(A);
   T* Wv = L.W;
-  T* Zv = L.W + k;
-  const int i = blockIdx.x, r = blockIdx.y, tid = threadIdx.x, nt = blockDim.x;
-  const int nrhs = gridDim.y;
+  T* Zv = L.W + k * R;
   const int64_t f0 = A.if_ptr[i], qi = A.if_ptr[i + 1] - f0;
   const int sys = A.part_sys[i];
   const T* G = Gall + (int64_t)sys * k * k;
   const int c0 = sys_chunk[sys], c1 = sys_chunk[sys + 1];
-  for (int j = tid; j < k; j += nt) {
+  for (int e = tid; e < k * R; e += nt) {
+    const int j = e / R, r = e - j * R;
     T s = 0;
-    for (int c = c0; c < c1; ++c) s += partial[((int64_t)c * nrhs + r) * k + j];
-    Wv[j] = s;
+    if (r < nr)
+      for (int c = c0; c < c1; ++c) s += partial[((int64_t)c * nrhs + r0 + r) * k + j];
+    Wv[e] = s;
   }
   __syncthreads();
-  for (int j = tid; j < k; j += nt) {
+  for (int e = tid; e < k * R; e += nt) {
+    const int j = e / R, r = e - j * R;
     T s = 0;
-    for (int l = 0; l < k; ++l) s += (gtrans ? G[(int64_t)l * k + j] : G[(int64_t)j * k + l]) * Wv[l];
-    Zv[j] = s;
+    for (int l = 0; l < k; ++l) s += (gtrans ? G[(int64_t)l * k + j] : G[(int64_t)j * k + l]) * Wv[l * R + r];
+    Zv[e] = s;
   }
   __syncthreads();
-  T* yr = y + r * ldy;
   const int GL = k >= 64 ? 64 : (k >= 32 ? 32 : (k >= 16 ? 16 : (k >= 8 ? 8 : (k >= 4 ? 4 : (k >= 2 ? 2 : 1)))));
   const int grp = tid / GL, lane = tid - grp * GL, ngrp = nt / GL;
   for (int64_t kr = grp; kr < qi; kr += ngrp) {
     const int64_t row = f0 + kr;
-    T acc = 0;
-    for (int j = lane; j < k; j += GL) acc += (T)tv_to_float(V[row * k + j]) * Zv[j];
-    acc = group_sum(acc, GL);
+    T acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = 0;
+    for (int j = lane; j < k; j += GL) {
+      const T v = (T)tv_to_float(V[row * k + j]);
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] += v * Zv[j * R + r];
+    }
+    group_sum_r<T, R>(acc, GL);
     if (lane == 0) {
-      const T v = yr[row] + acc;
-      yr[row] = v;
-      if (do_c0) L.XC[A.gC_inv[row]] = v;
+      const int64_t pos = A.gC_inv[row];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const T v = r < nr ? y[(r0 + r) * ldy + row] + acc[r] : (T)0;
+        if (r < nr) y[(r0 + r) * ldy + row] = v;
+        if (do_c0) L.XC[pos * R + r] = v;
+      }
     }
   }
   if (!do_c0) return;
   __syncthreads();
-  tri_solve(A.LC, i, L.XC, L.Rb, A.gshift);
-  tri_solve(A.UC, i, L.XC, L.Rb, A.gshift);
-  T* ur = u + r * ldu;
-  for (int64_t c = tid; c < qi; c += nt) ur[f0 + A.gC_out[f0 + c]] = L.XC[c];
+  tri_solve<T, R>(A.LC, i, L.XC, L.Rb, A.gshift);
+  tri_solve<T, R>(A.UC, i, L.XC, L.Rb, A.gshift);
+  for (int64_t e = tid; e < qi * R; e += nt) {
+    const int64_t c = e / R;
+    const int r = (int)(e - c * R);
+    if (r < nr) u[(r0 + r) * ldu + f0 + A.gC_out[f0 + c]] = L.XC[e];
+  }
 }
 
 // dst = C0^{-1} src
-template <typename T, bool GX>
-__global__ void __launch_bounds__(1024) k_c0solve(ApplyArrays<T> A, const T* __restrict__ src, int64_t lds_, T* dst,
-                          int64_t ldd) {
-  Lds<T> L = carve<T, GX>(A);
-  const int i = blockIdx.x, r = blockIdx.y, tid = threadIdx.x, nt = blockDim.x;
+template <typename T, int R, bool GX>
+__global__ void __launch_bounds__(1024) k_c0solve(ApplyArrays<T> A, int nrhs, const T* __restrict__ src,
+                                                  int64_t lds_, T* dst, int64_t ldd) {
+  const int i = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  int r0, nr;
+  if (!tile_rhs<T, R>(A, nrhs, i, r0, nr)) return;
+  Lds<T> L = carve<T, R, GX>(A);
   const int64_t f0 = A.if_ptr[i], qi = A.if_ptr[i + 1] - f0;
-  const T* sr = src + r * lds_;
-  for (int64_t p = tid; p < qi; p += nt) L.XC[p] = sr[f0 + A.gC_in[f0 + p]];
+  for (int64_t e = tid; e < qi * R; e += nt) {
+    const int64_t p = e / R;
+    const int r = (int)(e - p * R);
+    L.XC[e] = r < nr ? src[(r0 + r) * lds_ + f0 + A.gC_in[f0 + p]] : (T)0;
+  }
   __syncthreads();
-  tri_solve(A.LC, i, L.XC, L.Rb, A.gshift);
-  tri_solve(A.UC, i, L.XC, L.Rb, A.gshift);
-  T* dr = dst + r * ldd;
-  for (int64_t c = tid; c < qi; c += nt) dr[f0 + A.gC_out[f0 + c]] = L.XC[c];
+  tri_solve<T, R>(A.LC, i, L.XC, L.Rb, A.gshift);
+  tri_solve<T, R>(A.UC, i, L.XC, L.Rb, A.gshift);
+  for (int64_t e = tid; e < qi * R; e += nt) {
+    const int64_t c = e / R;
+    const int r = (int)(e - c * R);
+    if (r < nr) dst[(r0 + r) * ldd + f0 + A.gC_out[f0 + c]] = L.XC[e];
+  }
 }
 
 // One power-series step (eq. approx1 by its recurrence):
 //   w = E_s u = -C_g u + F B^{-1} E u;  r = [y +] w;  u_next = [C0^{-1}] r
-template <typename T, bool GX>
-__global__ void __launch_bounds__(1024) k_series(ApplyArrays<T> A, const T* __restrict__ y, int64_t ldy,
-                         const T* __restrict__ uprev, T* unext, int64_t ldu, int add_y, int do_c0) {
-  Lds<T> L = carve<T, GX>(A);
-  const int i = blockIdx.x, r = blockIdx.y, tid = threadIdx.x, nt = blockDim.x;
+template <typename T, int R, bool GX>
+__global__ void __launch_bounds__(1024) k_series(ApplyArrays<T> A, int nrhs, const T* __restrict__ y,
+                                                 int64_t ldy, const T* __restrict__ uprev, T* unext,
+                                                 int64_t ldu, int add_y, int do_c0) {
+  const int i = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  int r0, nr;
+  if (!tile_rhs<T, R>(A, nrhs, i, r0, nr)) return;
+  Lds<T> L = carve<T, R, GX>(A);
   const int64_t i0 = A.int_ptr[i], pi = A.int_ptr[i + 1] - i0;
   const int64_t f0 = A.if_ptr[i], qi = A.if_ptr[i + 1] - f0;
-  const T* ur = uprev + r * ldu;
-  for (int64_t k = tid; k < qi; k += nt) L.U[k] = ur[f0 + k];
+  for (int64_t e = tid; e < qi * R; e += nt) {
+    const int64_t kk = e / R;
+    const int r = (int)(e - kk * R);
+    L.U[e] = r < nr ? uprev[(r0 + r) * ldu + f0 + kk] : (T)0;
+  }
   __syncthreads();
   for (int64_t p = tid; p < pi; p += nt) {
     const int64_t row = i0 + p;
-    T acc = 0;
-    for (int64_t q = A.Ein.ptr[row]; q < A.Ein.ptr[row + 1]; ++q) acc += A.Ein.val[q] * L.U[A.Ein.col[q]];
-    L.XB[p] = acc;
+    T acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = 0;
+    for (int64_t q = A.Ein.ptr[row]; q < A.Ein.ptr[row + 1]; ++q) {
+      const T v = A.Ein.val[q];
+      const int c = A.Ein.col[q];
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] += v * L.U[c * R + r];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) L.XB[p * R + r] = acc[r];
   }
   __syncthreads();
-  tri_solve(A.LB, i, L.XB, L.Rb, A.gshift);
-  tri_solve(A.UB, i, L.XB, L.Rb, A.gshift);
-  const T* yr = y + r * ldy;
-  T* vr = unext + r * ldu;
-  for (int64_t k = tid; k < qi; k += nt) {
-    const int64_t row = f0 + k;
-    T acc = add_y ? yr[row] : (T)0;
-    for (int64_t q = A.Cg.ptr[row]; q < A.Cg.ptr[row + 1]; ++q) acc -= A.Cg.val[q] * ur[A.Cg.col[q]];
-    for (int64_t q = A.Fout.ptr[row]; q < A.Fout.ptr[row + 1]; ++q) acc += A.Fout.val[q] * L.XB[A.Fout.col[q]];
-    if (do_c0) L.XC[A.gC_inv[row]] = acc;
-    else vr[row] = acc;
+  tri_solve<T, R>(A.LB, i, L.XB, L.Rb, A.gshift);
+  tri_solve<T, R>(A.UB, i, L.XB, L.Rb, A.gshift);
+  for (int64_t kk = tid; kk < qi; kk += nt) {
+    const int64_t row = f0 + kk;
+    T acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = (add_y && r < nr) ? y[(r0 + r) * ldy + row] : (T)0;
+    for (int64_t q = A.Cg.ptr[row]; q < A.Cg.ptr[row + 1]; ++q) {
+      const T v = A.Cg.val[q];
+      const int64_t c = A.Cg.col[q];
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (r < nr) acc[r] -= v * uprev[(r0 + r) * ldu + c];
+    }
+    for (int64_t q = A.Fout.ptr[row]; q < A.Fout.ptr[row + 1]; ++q) {
+      const T v = A.Fout.val[q];
+      const int c = A.Fout.col[q];
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] += v * L.XB[c * R + r];
+    }
+    if (do_c0) {
+      const int64_t pos = A.gC_inv[row];
+#pragma unroll
+      for (int r = 0; r < R; ++r) L.XC[pos * R + r] = acc[r];
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (r < nr) unext[(r0 + r) * ldu + row] = acc[r];
+    }
   }
   if (!do_c0) return;
   __syncthreads();
-  tri_solve(A.LC, i, L.XC, L.Rb, A.gshift);
-  tri_solve(A.UC, i, L.XC, L.Rb, A.gshift);
-  for (int64_t c = tid; c < qi; c += nt) vr[f0 + A.gC_out[f0 + c]] = L.XC[c];
+  tri_solve<T, R>(A.LC, i, L.XC, L.Rb, A.gshift);
+  tri_solve<T, R>(A.UC, i, L.XC, L.Rb, A.gshift);
+  for (int64_t e = tid; e < qi * R; e += nt) {
+    const int64_t c = e / R;
+    const int r = (int)(e - c * R);
+    if (r < nr) unext[(r0 + r) * ldu + f0 + A.gC_out[f0 + c]] = L.XC[e];
+  }
 }
 
 // x = B^{-1}(f - E u);  z = P^T (x; u)   (Algorithm 3, lines 5-6)
-template <typename T, bool GX>
-__global__ void __launch_bounds__(1024) k_tail(ApplyArrays<T> A, const double* __restrict__ b, int64_t ldb,
-                       const T* __restrict__ u, int64_t ldu, double* z, int64_t ldz) {
-  Lds<T> L = carve<T, GX>(A);
-  const int i = blockIdx.x, r = blockIdx.y, tid = threadIdx.x, nt = blockDim.x;
+template <typename T, int R, bool GX>
+__global__ void __launch_bounds__(1024) k_tail(ApplyArrays<T> A, int nrhs, const double* __restrict__ b,
+                                               int64_t ldb, const T* __restrict__ u, int64_t ldu,
+                                               double* z, int64_t ldz) {
+  const int i = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  int r0, nr;
+  if (!tile_rhs<T, R>(A, nrhs, i, r0, nr)) return;
+  Lds<T> L = carve<T, R, GX>(A);
   const int64_t i0 = A.int_ptr[i], pi = A.int_ptr[i + 1] - i0;
   const int64_t f0 = A.if_ptr[i], qi = A.if_ptr[i + 1] - f0;
-  const T* ur = u + r * ldu;
-  const double* br = b + r * ldb;
-  double* zr = z + r * ldz;
-  for (int64_t k = tid; k < qi; k += nt) {
-    const T v = ur[f0 + k];
-    L.U[k] = v;
-    zr[A.if_orig[f0 + k]] = (double)v;
+  for (int64_t e = tid; e < qi * R; e += nt) {
+    const int64_t kk = e / R;
+    const int r = (int)(e - kk * R);
+    const T v = r < nr ? u[(r0 + r) * ldu + f0 + kk] : (T)0;
+    L.U[e] = v;
+    if (r < nr) z[(r0 + r) * ldz + A.if_orig[f0 + kk]] = (double)v;
   }
   __syncthreads();
   for (int64_t p = tid; p < pi; p += nt) {
     const int64_t row = i0 + p;
-    T acc = (T)br[A.gB_in[row]];
-    for (int64_t q = A.Ein.ptr[row]; q < A.Ein.ptr[row + 1]; ++q) acc -= A.Ein.val[q] * L.U[A.Ein.col[q]];
-    L.XB[p] = acc;
+    T acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = r < nr ? (T)b[(r0 + r) * ldb + A.gB_in[row]] : (T)0;
+    for (int64_t q = A.Ein.ptr[row]; q < A.Ein.ptr[row + 1]; ++q) {
+      const T v = A.Ein.val[q];
+      const int c = A.Ein.col[q];
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] -= v * L.U[c * R + r];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) L.XB[p * R + r] = acc[r];
   }
   __syncthreads();
-  tri_solve(A.LB, i, L.XB, L.Rb, A.gshift);
-  tri_solve(A.UB, i, L.XB, L.Rb, A.gshift);
-  for (int64_t c = tid; c < pi; c += nt) zr[A.gB_out[i0 + c]] = (double)L.XB[c];
+  tri_solve<T, R>(A.LB, i, L.XB, L.Rb, A.gshift);
+  tri_solve<T, R>(A.UB, i, L.XB, L.Rb, A.gshift);
+  for (int64_t e = tid; e < pi * R; e += nt) {
+    const int64_t c = e / R;
+    const int r = (int)(e - c * R);
+    if (r < nr) z[(r0 + r) * ldz + A.gB_out[i0 + c]] = (double)L.XB[e];
+  }
 }
 
 // ---------------------------------------------------------------- FP64 vector kernels
@@ -442,7 +568,10 @@ __global__ void k_maxpy_seg(const Seg* __restrict__ vcols, const Seg* __restrict
   if (row >= sw.len) return;
   const double* hr = h + (int64_t)c * hld;
   double acc = 0.0;
-  for (int i = 0; i < nv; ++i) acc += hr[i] * V[sv.base + i * ldv + row];
+  for (int i = 0; i < nv; ++i) {
+    const double hi = hr[i];
+    if (hi != 0.0) acc += hi * V[sv.base + i * ldv + row];
+  }
   W[sw.base + row] -= sign * acc;
 }
 
@@ -478,34 +607,59 @@ inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 // ---------------------------------------------------------------- launchers
 
+// dispatch a block kernel over the rhs-tile width R (1, 2, 4, 8) and the
+// working-vector placement (LDS or global)
+#define PSLR_DISPATCH(c, BODY)                        \
+  do {                                                \
+    switch ((c).R) {                                  \
+      case 1: { constexpr int RR = 1; BODY; } break;  \
+      case 2: { constexpr int RR = 2; BODY; } break;  \
+      case 4: { constexpr int RR = 4; BODY; } break;  \
+      case 8: { constexpr int RR = 8; BODY; } break;  \
+      default: return hipErrorInvalidValue;           \
+    }                                                 \
+  } while (0)
+
+inline unsigned ntiles(int nrhs, int R) { return (unsigned)((nrhs + R - 1) / R); }
+
 template <typename T>
 hipError_t set_lds_limit(size_t bytes) {
   hipError_t e;
   const int b = (int)bytes;
-  if ((e = hipFuncSetAttribute((const void*)k_head<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b))) return e;
-  if ((e = hipFuncSetAttribute((const void*)k_c0solve<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b))) return e;
-  if ((e = hipFuncSetAttribute((const void*)k_series<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b))) return e;
-  if ((e = hipFuncSetAttribute((const void*)k_tail<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b))) return e;
-  if ((e = hipFuncSetAttribute((const void*)k_lr_expand<T, T, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b))) return e;
-  if ((e = hipFuncSetAttribute((const void*)k_lr_expand<T, __hip_bfloat16, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b))) return e;
+#define PSLR_SETATTR(RR)                                                                              \
+  if ((e = hipFuncSetAttribute((const void*)k_head<T, RR, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b))) return e; \
+  if ((e = hipFuncSetAttribute((const void*)k_c0solve<T, RR, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b))) return e; \
+  if ((e = hipFuncSetAttribute((const void*)k_series<T, RR, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b))) return e; \
+  if ((e = hipFuncSetAttribute((const void*)k_tail<T, RR, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b))) return e; \
+  if ((e = hipFuncSetAttribute((const void*)k_lr_expand<T, T, RR, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b))) return e; \
+  if ((e = hipFuncSetAttribute((const void*)k_lr_expand<T, __hip_bfloat16, RR, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b))) return e;
+  PSLR_SETATTR(1)
+  PSLR_SETATTR(2)
+  PSLR_SETATTR(4)
+  PSLR_SETATTR(8)
+#undef PSLR_SETATTR
   return hipSuccess;
 }
 
 template <typename T>
 hipError_t launch_head(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, const double* b,
                        int64_t ldb, T* y, int64_t ldy) {
-  if (A.gws) hipLaunchKernelGGL((k_head<T, true>), dim3(A.nparts, nrhs), dim3(c.threads), 0, c.stream, A, b, ldb, y, ldy);
-  else hipLaunchKernelGGL((k_head<T, false>), dim3(A.nparts, nrhs), dim3(c.threads), c.lds, c.stream, A, b, ldb, y, ldy);
+  PSLR_DISPATCH(c, {
+    const dim3 grid(A.nparts, ntiles(nrhs, RR));
+    if (c.gx) hipLaunchKernelGGL((k_head<T, RR, true>), grid, dim3(c.threads), 0, c.stream, A, nrhs, b, ldb, y, ldy);
+    else hipLaunchKernelGGL((k_head<T, RR, false>), grid, dim3(c.threads), c.lds, c.stream, A, nrhs, b, ldb, y, ldy);
+  });
   return hipGetLastError();
 }
 
 template <typename T, typename TV>
 hipError_t launch_lr_partial(int nchunk, const LrChunk* chunks, int k, const TV* V, const T* y,
-                             int64_t ldy, int nrhs, T* partial, hipStream_t s) {
+                             int64_t ldy, int nrhs, T* partial, const uint8_t* active, int nsys,
+                             hipStream_t s) {
   const int threads = 256;
   size_t lds = sizeof(T) * threads;
   hipLaunchKernelGGL((k_lr_partial<T, TV>), dim3(nchunk, nrhs), dim3(threads), lds, s, chunks, k, V,
-                     y, ldy, partial);
+                     y, ldy, partial, active, nsys);
   return hipGetLastError();
 }
 
@@ -515,48 +669,56 @@ hipError_t launch_lr_expand(const ApplyArrays<T>& A, const LaunchCfg& c, int nrh
                             const int32_t* sys_chunk, T* y, int64_t ldy, int do_c0, T* u,
                             int64_t ldu) {
   (void)nchunk;
-  if (A.gws)
-    hipLaunchKernelGGL((k_lr_expand<T, TV, true>), dim3(A.nparts, nrhs), dim3(c.threads), 0, c.stream,
-                       A, k, V, G, gtrans, partial, sys_chunk, y, ldy, do_c0, u, ldu);
-  else
-    hipLaunchKernelGGL((k_lr_expand<T, TV, false>), dim3(A.nparts, nrhs), dim3(c.threads), c.lds,
-                       c.stream, A, k, V, G, gtrans, partial, sys_chunk, y, ldy, do_c0, u, ldu);
+  PSLR_DISPATCH(c, {
+    const dim3 grid(A.nparts, ntiles(nrhs, RR));
+    if (c.gx)
+      hipLaunchKernelGGL((k_lr_expand<T, TV, RR, true>), grid, dim3(c.threads), 0, c.stream, A, nrhs,
+                         k, V, G, gtrans, partial, sys_chunk, y, ldy, do_c0, u, ldu);
+    else
+      hipLaunchKernelGGL((k_lr_expand<T, TV, RR, false>), grid, dim3(c.threads), c.lds, c.stream, A,
+                         nrhs, k, V, G, gtrans, partial, sys_chunk, y, ldy, do_c0, u, ldu);
+  });
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_c0solve(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, const T* src,
                           int64_t lds_, T* dst, int64_t ldd) {
-  if (A.gws)
-    hipLaunchKernelGGL((k_c0solve<T, true>), dim3(A.nparts, nrhs), dim3(c.threads), 0, c.stream, A,
-                       src, lds_, dst, ldd);
-  else
-    hipLaunchKernelGGL((k_c0solve<T, false>), dim3(A.nparts, nrhs), dim3(c.threads), c.lds, c.stream,
-                       A, src, lds_, dst, ldd);
+  PSLR_DISPATCH(c, {
+    const dim3 grid(A.nparts, ntiles(nrhs, RR));
+    if (c.gx) hipLaunchKernelGGL((k_c0solve<T, RR, true>), grid, dim3(c.threads), 0, c.stream, A, nrhs, src, lds_, dst, ldd);
+    else hipLaunchKernelGGL((k_c0solve<T, RR, false>), grid, dim3(c.threads), c.lds, c.stream, A, nrhs, src, lds_, dst, ldd);
+  });
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_series(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, const T* y,
                          int64_t ldy, const T* uprev, T* unext, int64_t ldu, int add_y, int do_c0) {
-  if (A.gws)
-    hipLaunchKernelGGL((k_series<T, true>), dim3(A.nparts, nrhs), dim3(c.threads), 0, c.stream, A, y,
-                       ldy, uprev, unext, ldu, add_y, do_c0);
-  else
-    hipLaunchKernelGGL((k_series<T, false>), dim3(A.nparts, nrhs), dim3(c.threads), c.lds, c.stream,
-                       A, y, ldy, uprev, unext, ldu, add_y, do_c0);
+  PSLR_DISPATCH(c, {
+    const dim3 grid(A.nparts, ntiles(nrhs, RR));
+    if (c.gx)
+      hipLaunchKernelGGL((k_series<T, RR, true>), grid, dim3(c.threads), 0, c.stream, A, nrhs, y, ldy,
+                         uprev, unext, ldu, add_y, do_c0);
+    else
+      hipLaunchKernelGGL((k_series<T, RR, false>), grid, dim3(c.threads), c.lds, c.stream, A, nrhs, y,
+                         ldy, uprev, unext, ldu, add_y, do_c0);
+  });
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_tail(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, const double* b,
                        int64_t ldb, const T* u, int64_t ldu, double* z, int64_t ldz) {
-  if (A.gws)
-    hipLaunchKernelGGL((k_tail<T, true>), dim3(A.nparts, nrhs), dim3(c.threads), 0, c.stream, A, b,
-                       ldb, u, ldu, z, ldz);
-  else
-    hipLaunchKernelGGL((k_tail<T, false>), dim3(A.nparts, nrhs), dim3(c.threads), c.lds, c.stream, A,
-                       b, ldb, u, ldu, z, ldz);
+  PSLR_DISPATCH(c, {
+    const dim3 grid(A.nparts, ntiles(nrhs, RR));
+    if (c.gx)
+      hipLaunchKernelGGL((k_tail<T, RR, true>), grid, dim3(c.threads), 0, c.stream, A, nrhs, b, ldb, u,
+                         ldu, z, ldz);
+    else
+      hipLaunchKernelGGL((k_tail<T, RR, false>), grid, dim3(c.threads), c.lds, c.stream, A, nrhs, b,
+                         ldb, u, ldu, z, ldz);
+  });
   return hipGetLastError();
 }
 
@@ -650,12 +812,14 @@ PSLR_INST(float)
 
 template hipError_t launch_lr_partial<double, double>(int, const LrChunk*, int, const double*,
                                                       const double*, int64_t, int, double*,
-                                                      hipStream_t);
+                                                      const uint8_t*, int, hipStream_t);
 template hipError_t launch_lr_partial<float, float>(int, const LrChunk*, int, const float*,
-                                                    const float*, int64_t, int, float*, hipStream_t);
+                                                    const float*, int64_t, int, float*,
+                                                    const uint8_t*, int, hipStream_t);
 template hipError_t launch_lr_partial<float, __hip_bfloat16>(int, const LrChunk*, int,
                                                              const __hip_bfloat16*, const float*,
-                                                             int64_t, int, float*, hipStream_t);
+                                                             int64_t, int, float*, const uint8_t*,
+                                                             int, hipStream_t);
 template hipError_t launch_lr_expand<double, double>(const ApplyArrays<double>&, const LaunchCfg&,
                                                      int, int, const double*, const double*, int,
                                                      const double*, int, const int32_t*, double*,

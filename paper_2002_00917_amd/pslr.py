@@ -34,7 +34,7 @@ class pslr_options(C.Structure):
     _fields_ = [("m", C.c_int32), ("rank", C.c_int32), ("precision", C.c_int32),
                 ("want_transpose", C.c_int32), ("v0", C.POINTER(C.c_double)),
                 ("seed", C.c_uint64), ("pivot_threshold", C.c_double), ("nthreads", C.c_int32),
-                ("working_vectors", C.c_int32)]
+                ("working_vectors", C.c_int32), ("autotune", C.c_int32)]
 
 
 class pslr_info_t(C.Structure):
@@ -48,7 +48,8 @@ class pslr_info_t(C.Structure):
                 ("apply_bytes", C.c_int64), ("apply_bytes_rhs", C.c_int64),
                 ("series_bytes", C.c_int64), ("seconds_reorder", C.c_double),
                 ("seconds_factor", C.c_double), ("seconds_arnoldi", C.c_double),
-                ("nsys", C.c_int32), ("global_vectors", C.c_int32)]
+                ("nsys", C.c_int32), ("global_vectors", C.c_int32), ("threads", C.c_int32),
+                ("lane_shift", C.c_int32)]
 
 
 class pslr_trace_t(C.Structure):
@@ -170,12 +171,13 @@ def pslr_default_options():
 
 
 def _options(m, rank, precision, want_transpose, v0, seed, pivot_threshold, nthreads,
-             working_vectors):
+             working_vectors, autotune=False):
     o = pslr_default_options()
     o.m, o.rank, o.precision = int(m), int(rank), int(precision)
     o.want_transpose = 1 if want_transpose else 0
     o.seed, o.pivot_threshold, o.nthreads = int(seed), float(pivot_threshold), int(nthreads)
     o.working_vectors = int(working_vectors)
+    o.autotune = 1 if autotune else 0
     keep = None
     if v0 is not None:
         keep, o.v0 = _arr(v0, np.float64)
@@ -184,14 +186,14 @@ def _options(m, rank, precision, want_transpose, v0, seed, pivot_threshold, nthr
 
 def pslr_setup(rowptr, colind, vals, part, nparts, m=3, rank=16, precision=0,
                want_transpose=False, v0=None, seed=1, pivot_threshold=0.1, nthreads=0,
-               working_vectors=0, stream=None) -> Handle:
+               working_vectors=0, autotune=False, stream=None) -> Handle:
     L = lib()
     rp, rpp = _arr(rowptr, np.int64)
     ci, cip = _arr(colind, np.int32)
     va, vap = _arr(vals, np.float64)
     pa, pap = _arr(part, np.int32)
     o, keep = _options(m, rank, precision, want_transpose, v0, seed, pivot_threshold, nthreads,
-                       working_vectors)
+                       working_vectors, autotune)
     out = C.c_void_p()
     n = len(rp) - 1
     st = L.pslr_setup(n, rpp, cip, vap, pap, int(nparts), C.byref(o), _stream_ptr(stream),
@@ -203,7 +205,7 @@ def pslr_setup(rowptr, colind, vals, part, nparts, m=3, rank=16, precision=0,
 
 def pslr_setup_batched(rowptr, colind, vals, part, nparts, sys_ptr, m=3, rank=16, precision=0,
                        want_transpose=False, v0=None, seed=1, pivot_threshold=0.1, nthreads=0,
-                       working_vectors=0, stream=None) -> Handle:
+                       working_vectors=0, autotune=False, stream=None) -> Handle:
     L = lib()
     rp, rpp = _arr(rowptr, np.int64)
     ci, cip = _arr(colind, np.int32)
@@ -211,7 +213,7 @@ def pslr_setup_batched(rowptr, colind, vals, part, nparts, sys_ptr, m=3, rank=16
     pa, pap = _arr(part, np.int32)
     sp, spp = _arr(sys_ptr, np.int64)
     o, keep = _options(m, rank, precision, want_transpose, v0, seed, pivot_threshold, nthreads,
-                       working_vectors)
+                       working_vectors, autotune)
     out = C.c_void_p()
     n = len(rp) - 1
     st = L.pslr_setup_batched(n, rpp, cip, vap, pap, int(nparts), len(sp) - 1, spp, C.byref(o),
