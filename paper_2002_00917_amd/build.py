@@ -45,7 +45,7 @@ def build(verbose: bool = False) -> str:
     o = os.path.join(BUILD, "pslr_host.o")
     _run([cxx] + CXX_FLAGS + ["-c", os.path.join(CSRC, "pslr_host.cpp"), "-o", o], verbose)
     objs.append(o)
-    for src in ("pslr_kernels.hip", "pslr_api.hip"):
+    for src in ("pslr_kernels.hip", "pslr_vec.hip", "pslr_api.hip"):
         o = os.path.join(BUILD, src.replace(".hip", ".o"))
         _run([hipcc] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", o], verbose)
         objs.append(o)

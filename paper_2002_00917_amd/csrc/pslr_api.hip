@@ -211,6 +211,9 @@ struct pslr_ctx {
   double *fVb = nullptr, *fZb = nullptr, *fW = nullptr, *fdbuf = nullptr, *fh = nullptr,
          *fscl = nullptr, *fy = nullptr;
   Seg *fcolsV = nullptr, *fcolsB = nullptr, *fcolsX = nullptr, *fcolsM = nullptr;
+  Chunk *fchF = nullptr, *fchM = nullptr;
+  int32_t *fcpF = nullptr, *fcpM = nullptr;
+  int64_t f_maxch = 0;
   uint8_t* factive = nullptr;
   const uint8_t* cur_active = nullptr;  // mask of (system, rhs) columns the apply works on
   // info
@@ -507,6 +510,36 @@ struct Tracer {
   }
 };
 
+// Rows per chunk for columns cols: at least ~1024 chunks over all columns so
+// that every CU holds several, between 256 and kChunkRows rows each.
+int64_t chunk_rows(const std::vector<Seg>& cols) {
+  int64_t tot = 0;
+  for (const Seg& s : cols) tot += s.len;
+  const int64_t r = ((tot + 1023) / 1024 + 255) / 256 * 256;
+  return std::min<int64_t>(kChunkRows, std::max<int64_t>(256, r));
+}
+
+// Split columns into row chunks of at most rows rows; columns with
+// active[c] == 0 get no chunks.  cptr[c] .. cptr[c+1] are column c's chunks.
+int make_chunks(const std::vector<Seg>& cols, int64_t rows, const std::vector<uint8_t>* active,
+                std::vector<Chunk>& ch, std::vector<int32_t>& cptr) {
+  ch.clear();
+  cptr.assign(cols.size() + 1, 0);
+  for (size_t c = 0; c < cols.size(); ++c) {
+    if (!active || (*active)[c])
+      for (int64_t r0 = 0; r0 < cols[c].len; r0 += rows)
+        ch.push_back(Chunk{(int32_t)c, 0, r0, std::min(cols[c].len, r0 + rows)});
+    cptr[c + 1] = (int32_t)ch.size();
+  }
+  return (int)ch.size();
+}
+
+int64_t count_chunks(const std::vector<Seg>& cols, int64_t rows) {
+  int64_t t = 0;
+  for (const Seg& s : cols) t += (s.len + rows - 1) / rows;
+  return std::max<int64_t>(t, 1);
+}
+
 // Right-hand-side tile width and working-vector placement of an apply: LDS with
 // the widest tile that fits, unless several right-hand sides would then be
 // solved one or two at a time (each tile re-reads every factor entry), in
@@ -719,7 +752,18 @@ pslr_status arnoldi(pslr_ctx* h, const double* v0host, uint64_t seed, hipStream_
   HIP_TRY(tmp.alloc<double>(q, &w));
   HIP_TRY(tmp.alloc<double>(q, &ua));
   HIP_TRY(tmp.alloc<double>(q, &ub));
-  HIP_TRY(tmp.alloc<double>((size_t)h->nchunk * ns * (kreq + 1), &dbuf));
+  std::vector<Seg> qcols(ns);
+  for (int c = 0; c < ns; ++c) qcols[c] = Seg{h->sys_q[c], h->sys_q[c + 1] - h->sys_q[c]};
+  std::vector<Chunk> chv;
+  std::vector<int32_t> cpv;
+  const int nch = make_chunks(qcols, chunk_rows(qcols), nullptr, chv, cpv);
+  Chunk* dch;
+  int32_t* dcp;
+  HIP_TRY(tmp.alloc<Chunk>(std::max(nch, 1), &dch));
+  HIP_TRY(tmp.alloc<int32_t>(ns + 1, &dcp));
+  if (nch > 0) HIP_TRY(hipMemcpy(dch, chv.data(), sizeof(Chunk) * nch, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(dcp, cpv.data(), sizeof(int32_t) * (ns + 1), hipMemcpyHostToDevice));
+  HIP_TRY(tmp.alloc<double>((size_t)std::max(nch, 1) * (kreq + 1), &dbuf));
   HIP_TRY(tmp.alloc<double>((size_t)ns * (2 * (kreq + 1) + 2), &dhh));
   HIP_TRY(tmp.alloc<double>(ns, &scl));
   double* dh1 = dhh;
@@ -762,16 +806,16 @@ pslr_status arnoldi(pslr_ctx* h, const double* v0host, uint64_t seed, hipStream_
     }
     HIP_TRY(hipMemcpyAsync(w, ub, sizeof(double) * q, hipMemcpyDeviceToDevice, s));
     const int nv = j + 1;
-    HIP_TRY(launch_mdot_seg(ns, cols, cols, 1, w, 0, w, h->nchunk, dbuf, s));
-    HIP_TRY(launch_reduce(h->nchunk, ns, 1, dbuf, dwn, s));
-    HIP_TRY(launch_mdot_seg(ns, cols, cols, nv, Vd, q, w, h->nchunk, dbuf, s));
-    HIP_TRY(launch_reduce(h->nchunk, ns, nv, dbuf, dh1, s));
-    HIP_TRY(launch_maxpy_seg(ns, cols, cols, qmax, nv, Vd, q, dh1, nv, w, 1.0, s));
-    HIP_TRY(launch_mdot_seg(ns, cols, cols, nv, Vd, q, w, h->nchunk, dbuf, s));
-    HIP_TRY(launch_reduce(h->nchunk, ns, nv, dbuf, dh2, s));
-    HIP_TRY(launch_maxpy_seg(ns, cols, cols, qmax, nv, Vd, q, dh2, nv, w, 1.0, s));
-    HIP_TRY(launch_mdot_seg(ns, cols, cols, 1, w, 0, w, h->nchunk, dbuf, s));
-    HIP_TRY(launch_reduce(h->nchunk, ns, 1, dbuf, dnn, s));
+    HIP_TRY(launch_mdot_chunk(nch, dch, cols, cols, 1, w, 0, w, dbuf, s));
+    HIP_TRY(launch_reduce_chunk(ns, dcp, 1, nch, dbuf, dwn, s));
+    HIP_TRY(launch_mdot_chunk(nch, dch, cols, cols, nv, Vd, q, w, dbuf, s));
+    HIP_TRY(launch_reduce_chunk(ns, dcp, nv, nch, dbuf, dh1, s));
+    HIP_TRY(launch_maxpy_chunk(nch, dch, cols, cols, nv, Vd, q, dh1, nv, w, 1.0, s));
+    HIP_TRY(launch_mdot_chunk(nch, dch, cols, cols, nv, Vd, q, w, dbuf, s));
+    HIP_TRY(launch_reduce_chunk(ns, dcp, nv, nch, dbuf, dh2, s));
+    HIP_TRY(launch_maxpy_chunk(nch, dch, cols, cols, nv, Vd, q, dh2, nv, w, 1.0, s));
+    HIP_TRY(launch_mdot_chunk(nch, dch, cols, cols, 1, w, 0, w, dbuf, s));
+    HIP_TRY(launch_reduce_chunk(ns, dcp, 1, nch, dbuf, dnn, s));
     HIP_TRY(hipMemcpyAsync(hb.data(), dhh, sizeof(double) * hb.size(), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     const double* h1 = hb.data();
@@ -799,7 +843,7 @@ pslr_status arnoldi(pslr_ctx* h, const double* v0host, uint64_t seed, hipStream_
     }
     if (!any) break;
     HIP_TRY(hipMemcpyAsync(scl, sc.data(), sizeof(double) * ns, hipMemcpyHostToDevice, s));
-    HIP_TRY(launch_scale_seg(ns, cols, cols, qmax, w, scl, Vd + (size_t)(j + 1) * q, s));
+    HIP_TRY(launch_scale_chunk(nch, dch, cols, cols, w, scl, Vd + (size_t)(j + 1) * q, s));
   }
   int kmax = 0;
   for (int c = 0; c < ns; ++c) kmax = std::max(kmax, kdone[c]);
@@ -1398,12 +1442,28 @@ pslr_status fgmres_solve(pslr_handle h, int32_t nrhs, const double* b, int64_t l
   const int64_t blk = n * nrhs;  // one basis vector of every column: n x nrhs, leading dimension n
   int64_t maxlen = 0;
   for (int c = 0; c < ns; ++c) maxlen = std::max(maxlen, h->sys_n[c + 1] - h->sys_n[c]);
-  if (h->f_nrhs != nrhs || h->f_restart != restart) {
+  std::vector<Seg> cols((size_t)3 * ncol);
+  for (int r = 0; r < nrhs; ++r)
+    for (int c = 0; c < ns; ++c) {
+      const int64_t o = h->sys_n[c], len = h->sys_n[c + 1] - o;
+      cols[r * ns + c] = Seg{r * n + o, len};
+      cols[ncol + r * ns + c] = Seg{r * ldb + o, len};
+      cols[2 * ncol + r * ns + c] = Seg{r * ldx + o, len};
+    }
+  const std::vector<Seg> vcols(cols.begin(), cols.begin() + ncol);
+  const int64_t crows = chunk_rows(vcols);
+  const int64_t maxch = count_chunks(vcols, crows);
+  if (h->f_nrhs != nrhs || h->f_restart != restart || h->f_maxch != maxch) {
     h->fpool.release();
     HIP_TRY(h->fpool.alloc<double>((size_t)blk * R1, &h->fVb));
     HIP_TRY(h->fpool.alloc<double>((size_t)blk * restart, &h->fZb));
     HIP_TRY(h->fpool.alloc<double>((size_t)blk, &h->fW));
-    HIP_TRY(h->fpool.alloc<double>((size_t)h->nchunk * ncol * R1, &h->fdbuf));
+    HIP_TRY(h->fpool.alloc<double>((size_t)maxch * R1, &h->fdbuf));
+    HIP_TRY(h->fpool.alloc<Chunk>((size_t)2 * maxch, &h->fchF));
+    h->fchM = h->fchF + maxch;
+    HIP_TRY(h->fpool.alloc<int32_t>((size_t)2 * (ncol + 1), &h->fcpF));
+    h->fcpM = h->fcpF + ncol + 1;
+    h->f_maxch = maxch;
     HIP_TRY(h->fpool.alloc<double>((size_t)ncol * (2 * R1 + 1), &h->fh));
     HIP_TRY(h->fpool.alloc<double>(ncol, &h->fscl));
     HIP_TRY(h->fpool.alloc<double>((size_t)ncol * restart, &h->fy));
@@ -1417,18 +1477,15 @@ pslr_status fgmres_solve(pslr_handle h, int32_t nrhs, const double* b, int64_t l
     h->f_nrhs = nrhs;
     h->f_restart = restart;
   }
-  std::vector<Seg> cols((size_t)3 * ncol);
-  for (int r = 0; r < nrhs; ++r)
-    for (int c = 0; c < ns; ++c) {
-      const int64_t o = h->sys_n[c], len = h->sys_n[c + 1] - o;
-      cols[r * ns + c] = Seg{r * n + o, len};
-      cols[ncol + r * ns + c] = Seg{r * ldb + o, len};
-      cols[2 * ncol + r * ns + c] = Seg{r * ldx + o, len};
-    }
   HIP_TRY(hipMemcpyAsync(h->fcolsV, cols.data(), sizeof(Seg) * cols.size(), hipMemcpyHostToDevice, s));
-  const Seg *cV = h->fcolsV, *cB = h->fcolsB, *cX = h->fcolsX, *cM = h->fcolsM;
-  std::vector<Seg> mcols(cols.begin(), cols.begin() + ncol);
-  std::vector<uint8_t> amask(ncol);
+  std::vector<Chunk> chF, chM;
+  std::vector<int32_t> cpF, cpM;
+  const int nchF = make_chunks(vcols, crows, nullptr, chF, cpF);
+  HIP_TRY(hipMemcpyAsync(h->fchF, chF.data(), sizeof(Chunk) * std::max(nchF, 1), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(h->fcpF, cpF.data(), sizeof(int32_t) * (ncol + 1), hipMemcpyHostToDevice, s));
+  const Seg *cV = h->fcolsV, *cB = h->fcolsB, *cX = h->fcolsX;
+  std::vector<uint8_t> amask(ncol, 0);
+  int nchM = 0;
   double* Vb = h->fVb;
   double* Zb = h->fZb;
   double* W = h->fW;
@@ -1437,8 +1494,8 @@ pslr_status fgmres_solve(pslr_handle h, int32_t nrhs, const double* b, int64_t l
   double* dnn = dh2 + (size_t)ncol * R1;
   std::vector<double> hbuf((size_t)ncol * (2 * R1 + 1)), sc(ncol), bn(ncol);
   // ||b|| per column
-  HIP_TRY(launch_mdot_seg(ncol, cB, cB, 1, b, 0, b, h->nchunk, h->fdbuf, s));
-  HIP_TRY(launch_reduce(h->nchunk, ncol, 1, h->fdbuf, dnn, s));
+  HIP_TRY(launch_mdot_chunk(nchF, h->fchF, cB, cB, 1, b, 0, b, h->fdbuf, s));
+  HIP_TRY(launch_reduce_chunk(ncol, h->fcpF, 1, nchF, h->fdbuf, dnn, s));
   HIP_TRY(hipMemcpyAsync(bn.data(), dnn, sizeof(double) * ncol, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   for (double& v : bn) v = std::sqrt(v);
@@ -1451,8 +1508,8 @@ pslr_status fgmres_solve(pslr_handle h, int32_t nrhs, const double* b, int64_t l
   for (;;) {
     // r0 = b - A x into V_0 of every column
     HIP_TRY(launch_spmv(n, Ap, Ac, Av, nrhs, x, ldx, Vb, n, b, ldb, s));
-    HIP_TRY(launch_mdot_seg(ncol, cV, cV, 1, Vb, 0, Vb, h->nchunk, h->fdbuf, s));
-    HIP_TRY(launch_reduce(h->nchunk, ncol, 1, h->fdbuf, dnn, s));
+    HIP_TRY(launch_mdot_chunk(nchF, h->fchF, cV, cV, 1, Vb, 0, Vb, h->fdbuf, s));
+    HIP_TRY(launch_reduce_chunk(ncol, h->fcpF, 1, nchF, h->fdbuf, dnn, s));
     HIP_TRY(hipMemcpyAsync(hbuf.data(), dnn, sizeof(double) * ncol, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     bool any = false;
@@ -1472,17 +1529,23 @@ pslr_status fgmres_solve(pslr_handle h, int32_t nrhs, const double* b, int64_t l
     }
     if (!any) break;
     HIP_TRY(hipMemcpyAsync(h->fscl, sc.data(), sizeof(double) * ncol, hipMemcpyHostToDevice, s));
-    HIP_TRY(launch_scale_seg(ncol, cV, cV, maxlen, Vb, h->fscl, Vb, s));
+    HIP_TRY(launch_scale_chunk(nchF, h->fchF, cV, cV, Vb, h->fscl, Vb, s));
     for (int j = 0; j < restart; ++j) {
       double* Vj = Vb + (size_t)j * blk;
       double* Zj = Zb + (size_t)j * blk;
       // converged columns skip the apply and the vector work of this iteration
+      bool changed = j == 0;
       for (int c = 0; c < ncol; ++c) {
+        changed = changed || amask[c] != (act[c] ? 1 : 0);
         amask[c] = act[c] ? 1 : 0;
-        mcols[c].len = act[c] ? cols[c].len : 0;
       }
-      HIP_TRY(hipMemcpyAsync(h->factive, amask.data(), ncol, hipMemcpyHostToDevice, s));
-      HIP_TRY(hipMemcpyAsync(h->fcolsM, mcols.data(), sizeof(Seg) * ncol, hipMemcpyHostToDevice, s));
+      if (changed) {  // the previous upload finished at the last synchronisation
+        nchM = make_chunks(vcols, crows, &amask, chM, cpM);
+        HIP_TRY(hipMemcpyAsync(h->factive, amask.data(), ncol, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(h->fchM, chM.data(), sizeof(Chunk) * std::max(nchM, 1),
+                               hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(h->fcpM, cpM.data(), sizeof(int32_t) * (ncol + 1), hipMemcpyHostToDevice, s));
+      }
       h->cur_active = h->factive;
       pslr_status st = apply_dir(h, transpose != 0, nrhs, Vj, n, Zj, n, s);
       h->cur_active = nullptr;
@@ -1490,14 +1553,14 @@ pslr_status fgmres_solve(pslr_handle h, int32_t nrhs, const double* b, int64_t l
       HIP_TRY(launch_spmv(n, Ap, Ac, Av, nrhs, Zj, n, W, n, nullptr, 0, s));
       // classical Gram-Schmidt, two passes, then ||w||; one host synchronisation
       const int nv = j + 1;
-      HIP_TRY(launch_mdot_seg(ncol, cM, cM, nv, Vb, blk, W, h->nchunk, h->fdbuf, s));
-      HIP_TRY(launch_reduce(h->nchunk, ncol, nv, h->fdbuf, dh1, s));
-      HIP_TRY(launch_maxpy_seg(ncol, cM, cM, maxlen, nv, Vb, blk, dh1, nv, W, 1.0, s));
-      HIP_TRY(launch_mdot_seg(ncol, cM, cM, nv, Vb, blk, W, h->nchunk, h->fdbuf, s));
-      HIP_TRY(launch_reduce(h->nchunk, ncol, nv, h->fdbuf, dh2, s));
-      HIP_TRY(launch_maxpy_seg(ncol, cM, cM, maxlen, nv, Vb, blk, dh2, nv, W, 1.0, s));
-      HIP_TRY(launch_mdot_seg(ncol, cM, cM, 1, W, 0, W, h->nchunk, h->fdbuf, s));
-      HIP_TRY(launch_reduce(h->nchunk, ncol, 1, h->fdbuf, dnn, s));
+      HIP_TRY(launch_mdot_chunk(nchM, h->fchM, cV, cV, nv, Vb, blk, W, h->fdbuf, s));
+      HIP_TRY(launch_reduce_chunk(ncol, h->fcpM, nv, nchM, h->fdbuf, dh1, s));
+      HIP_TRY(launch_maxpy_chunk(nchM, h->fchM, cV, cV, nv, Vb, blk, dh1, nv, W, 1.0, s));
+      HIP_TRY(launch_mdot_chunk(nchM, h->fchM, cV, cV, nv, Vb, blk, W, h->fdbuf, s));
+      HIP_TRY(launch_reduce_chunk(ncol, h->fcpM, nv, nchM, h->fdbuf, dh2, s));
+      HIP_TRY(launch_maxpy_chunk(nchM, h->fchM, cV, cV, nv, Vb, blk, dh2, nv, W, 1.0, s));
+      HIP_TRY(launch_mdot_chunk(nchM, h->fchM, cV, cV, 1, W, 0, W, h->fdbuf, s));
+      HIP_TRY(launch_reduce_chunk(ncol, h->fcpM, 1, nchM, h->fdbuf, dnn, s));
       HIP_TRY(hipMemcpyAsync(hbuf.data(), dh1, sizeof(double) * hbuf.size(), hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
       const double* h1 = hbuf.data();
@@ -1536,7 +1599,7 @@ pslr_status fgmres_solve(pslr_handle h, int32_t nrhs, const double* b, int64_t l
       }
       if (!cont) break;
       HIP_TRY(hipMemcpyAsync(h->fscl, sc.data(), sizeof(double) * ncol, hipMemcpyHostToDevice, s));
-      HIP_TRY(launch_scale_seg(ncol, cV, cV, maxlen, W, h->fscl, Vb + (size_t)(j + 1) * blk, s));
+      HIP_TRY(launch_scale_chunk(nchF, h->fchF, cV, cV, W, h->fscl, Vb + (size_t)(j + 1) * blk, s));
     }
     // x += Z y
     std::fill(yv.begin(), yv.end(), 0.0);
@@ -1553,7 +1616,7 @@ pslr_status fgmres_solve(pslr_handle h, int32_t nrhs, const double* b, int64_t l
     }
     HIP_TRY(hipMemcpyAsync(h->fy, yv.data(), sizeof(double) * yv.size(), hipMemcpyHostToDevice, s));
     if (jmax > 0)
-      HIP_TRY(launch_maxpy_seg(ncol, cV, cX, maxlen, jmax, Zb, blk, h->fy, restart, x, -1.0, s));
+      HIP_TRY(launch_maxpy_chunk(nchF, h->fchF, cV, cX, jmax, Zb, blk, h->fy, restart, x, -1.0, s));
   }
   for (int c = 0; c < ncol; ++c) {
     if (iters) iters[c] = its[c];

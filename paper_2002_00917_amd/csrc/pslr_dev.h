@@ -84,6 +84,14 @@ struct Seg {
   int64_t base, len;
 };
 
+// A row range of one column of a segmented vector operation.
+struct Chunk {
+  int32_t col, pad;
+  int64_t r0, r1;
+};
+// longest row chunk of the chunked vector kernels (16 rows per thread at 256 threads)
+constexpr int64_t kChunkRows = 4096;
+
 struct LaunchCfg {
   int threads;
   size_t lds;          // dynamic LDS bytes (LDS working vectors)
@@ -149,6 +157,19 @@ hipError_t launch_maxpy_seg(int ncol, const Seg* vcols, const Seg* wcols, int64_
 // D[dbase + row] = S[sbase + row] * scale[c]
 hipError_t launch_scale_seg(int ncol, const Seg* scols, const Seg* dcols, int64_t maxlen,
                             const double* S, const double* scale, double* D, hipStream_t s);
+// Chunked forms: chunk c covers rows r0..r1 (at most kChunkRows) of column
+// ch[c].col; the chunks of column j are cptr[j] .. cptr[j+1].  Dot products:
+// partial[i * nchunk + c] per chunk, then out[j * nv + i] per column.
+hipError_t launch_mdot_chunk(int nchunk, const Chunk* ch, const Seg* vcols, const Seg* wcols, int nv,
+                             const double* V, int64_t ldv, const double* W, double* partial,
+                             hipStream_t s);
+hipError_t launch_reduce_chunk(int ncol, const int32_t* cptr, int nv, int nchunk,
+                               const double* partial, double* out, hipStream_t s);
+hipError_t launch_maxpy_chunk(int nchunk, const Chunk* ch, const Seg* vcols, const Seg* wcols,
+                              int nv, const double* V, int64_t ldv, const double* h, int hld,
+                              double* W, double sign, hipStream_t s);
+hipError_t launch_scale_chunk(int nchunk, const Chunk* ch, const Seg* scols, const Seg* dcols,
+                              const double* S, const double* scale, double* D, hipStream_t s);
 hipError_t launch_copy_cast_to_f32(int64_t count, const double* src, float* dst, hipStream_t s);
 hipError_t launch_sddmm(int64_t n, const int64_t* ptr, const int32_t* col, int nrhs,
                         const double* lam, int64_t ldl, const double* z, int64_t ldz,
