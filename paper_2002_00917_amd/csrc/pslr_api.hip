@@ -73,16 +73,15 @@ struct DevPool {
   }
 };
 
-struct TriBytes {
-  int64_t val = 0, idx = 0, meta = 0;  // algorithmic bytes split by kind (values counted as entries)
-};
-
-// Concatenate one factor family over all blocks.
+// Concatenate one factor family over all blocks.  `bytes` receives the
+// algorithmic bytes of one solve of every block: each value once (triangles and
+// panels), each panel position list once, one record per row and per push
+// item, the level tables.
 template <typename T>
 hipError_t upload_tri(DevPool& pool, const std::vector<BlockFactor>& F, TriPacked BlockFactor::*mem,
                       TriArrays<T>& out, int& max_lrows, int64_t& bytes) {
   std::vector<DevTriBlock> blk(F.size());
-  std::vector<int32_t> lev_ptr, lev_g, rec, col, ridx;
+  std::vector<int32_t> lev_ptr, push_ptr, lev_c, rec, prec, ridx;
   std::vector<T> val, tri;
   bytes = 0;
   for (size_t i = 0; i < F.size(); ++i) {
@@ -94,35 +93,35 @@ hipError_t upload_tri(DevPool& pool, const std::vector<BlockFactor>& F, TriPacke
     B.lower = H.lower ? 1 : 0;
     B.lev_base = (int64_t)lev_ptr.size();
     B.rec_base = (int64_t)rec.size() / 8;
+    B.prec_base = (int64_t)prec.size() / 4;
     B.val_base = (int64_t)val.size();
     B.ridx_base = (int64_t)ridx.size();
     B.tri_base = (int64_t)tri.size();
     max_lrows = std::max(max_lrows, H.max_lrows);
     lev_ptr.insert(lev_ptr.end(), H.lev_ptr.begin(), H.lev_ptr.end());
-    lev_g.insert(lev_g.end(), H.lev_g.begin(), H.lev_g.end());
-    lev_g.push_back(0);
+    push_ptr.insert(push_ptr.end(), H.push_ptr.begin(), H.push_ptr.end());
+    if (H.push_ptr.size() < H.lev_ptr.size()) push_ptr.resize(lev_ptr.size(), 0);
+    lev_c.insert(lev_c.end(), H.lev_c.begin(), H.lev_c.end());
+    lev_c.resize(lev_ptr.size(), 0);
     rec.insert(rec.end(), H.rec.begin(), H.rec.end());
+    prec.insert(prec.end(), H.prec.begin(), H.prec.end());
     for (double v : H.val) val.push_back((T)v);
-    if (H.lower) col.insert(col.end(), H.col.begin(), H.col.end());
-    else col.resize(val.size(), 0);
     ridx.insert(ridx.end(), H.ridx.begin(), H.ridx.end());
     for (double v : H.tri) tri.push_back((T)v);
-    // algorithmic bytes of one solve: every value once, its index (lower) or the
-    // supernode column list (upper) once, one record per row, the level table
-    bytes += (int64_t)(H.val.size() + H.tri.size()) * (int64_t)sizeof(T) +
-             4 * (int64_t)(H.lower ? H.col.size() : H.ridx.size()) + 32 * (int64_t)H.n +
-             8 * (int64_t)(H.nlev + 1);
+    bytes += (int64_t)(H.val.size() + H.tri.size()) * (int64_t)sizeof(T) + 4 * (int64_t)H.ridx.size() +
+             4 * (int64_t)H.rec.size() + 4 * (int64_t)H.prec.size() + 12 * (int64_t)(H.nlev + 1);
   }
-  if (col.size() < val.size()) col.resize(val.size(), 0);
   hipError_t e;
   if ((e = pool.upload(blk, &out.blk))) return e;
   if ((e = pool.upload(lev_ptr, &out.lev_ptr))) return e;
-  if ((e = pool.upload(lev_g, &out.lev_g))) return e;
-  const int32_t* recp = nullptr;
-  if ((e = pool.upload(rec, &recp))) return e;
-  out.rec = reinterpret_cast<const int4*>(recp);
+  if ((e = pool.upload(push_ptr, &out.push_ptr))) return e;
+  if ((e = pool.upload(lev_c, &out.lev_c))) return e;
+  const int32_t* p = nullptr;
+  if ((e = pool.upload(rec, &p))) return e;
+  out.rec = reinterpret_cast<const int4*>(p);
+  if ((e = pool.upload(prec, &p))) return e;
+  out.prec = reinterpret_cast<const int4*>(p);
   if ((e = pool.upload(val, &out.val))) return e;
-  if ((e = pool.upload(col, &out.col))) return e;
   if ((e = pool.upload(ridx, &out.ridx))) return e;
   if ((e = pool.upload(tri, &out.tri))) return e;
   return hipSuccess;
@@ -394,7 +393,7 @@ hipError_t upload_dir(DevPool& pool, const Reordering& R, const std::vector<Bloc
 template <typename T>
 size_t lds_bytes(const ApplyArrays<T>& A, int kmax, int R = 1) {
   return sizeof(T) * (size_t)R *
-         ((size_t)A.maxPB + A.maxLR + 2 * (size_t)A.maxQB + 2 * (size_t)std::max(kmax, 1));
+         ((size_t)A.maxPB + 2 * (size_t)A.maxLR + 2 * (size_t)A.maxQB + 2 * (size_t)std::max(kmax, 1));
 }
 
 pslr_status ensure_ws(pslr_ctx* h, int nrhs) {
@@ -1238,8 +1237,8 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
     else codes[t] = factor_block(Bk.C0[t - np], tau, h->want_T != 0, fC[t - np], errs[t]);
   });
   for (int t = 0; t < 2 * np; ++t)
-    if (codes[t]) return fail(PSLR_ESINGULAR, std::string(t < np ? "B_" : "C_") +
-                                                  std::to_string(t % np) + ": " + errs[t]);
+    if (codes[t]) return fail(codes[t] == 3 ? PSLR_ENOTSUP : PSLR_ESINGULAR,
+                              std::string(t < np ? "B_" : "C_") + std::to_string(t % np) + ": " + errs[t]);
   const double t2 = now_s();
 
   // device copies of A (and A^T)
@@ -1320,7 +1319,7 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
       int mx = 1;
       for (const BlockFactor* f : {&fB[i], &fC[i]})
         for (const TriPacked* T : {&f->lo, &f->up, &f->loT, &f->upT}) mx = std::max(mx, T->max_lrows);
-      rb[i + 1] = rb[i] + mx;
+      rb[i + 1] = rb[i] + 2 * mx;  // two halves for alternate levels
     }
     HIP_TRY(h->pool.upload(rb, &h->d_rb_off));
     h->gws_stride = h->R.p + 2 * h->R.q + rb[nparts] + (int64_t)nparts * 2 * std::max(h->rank, 1);

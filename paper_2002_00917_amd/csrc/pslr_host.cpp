@@ -15,6 +15,7 @@
 #include "pslr_host.h"
 
 #include <algorithm>
+#include <climits>
 #include <atomic>
 #include <cmath>
 #include <cstdlib>
@@ -415,12 +416,6 @@ void invert_triangle(const double* T, int w, bool lower, double* X) {
   }
 }
 
-int pow2_lanes(double avg) {
-  int g = 1;
-  while (g < 64 && g * 2 <= avg / 2.0) g *= 2;
-  return g;
-}
-
 // Level schedule: supernode heights in the supernodal elimination tree.
 void build_levels(TriHost& T, const std::vector<int>& sfirst, const std::vector<int>& height,
                   int nlev) {
@@ -441,22 +436,6 @@ void build_levels(TriHost& T, const std::vector<int>& sfirst, const std::vector<
       }
     T.lev_ptr[l + 1] = (int)T.lrows.size();
     T.max_lrows = std::max(T.max_lrows, T.lev_ptr[l + 1] - T.lev_ptr[l]);
-  }
-  // lanes per row for the two sweeps of each level
-  T.lev_g.assign(nlev, 0);
-  for (int l = 0; l < nlev; ++l) {
-    double s1 = 0, s2 = 0;
-    int cnt = T.lev_ptr[l + 1] - T.lev_ptr[l];
-    for (int k = T.lev_ptr[l]; k < T.lev_ptr[l + 1]; ++k) {
-      int p = T.lrows[k];
-      const SnHost& S = T.sn[T.row_sn[p]];
-      int i = p - S.f;
-      s1 += T.lower ? (double)(T.rp[p + 1] - T.rp[p]) : (double)S.h;
-      s2 += T.lower ? (double)(i + 1) : (double)(S.w - i);
-    }
-    int g1 = cnt ? pow2_lanes(s1 / cnt) : 1;
-    int g2 = cnt ? pow2_lanes(s2 / cnt) : 1;
-    T.lev_g[l] = g1 | (g2 << 8);
   }
 }
 
@@ -788,27 +767,19 @@ int factor_block(const CsrL& M, double tau, bool want_T, BlockFactor& out, std::
     out.nnz_L += (int64_t)w * (w + 1) / 2 + (int64_t)w * (int64_t)R[s].size();
     out.nnz_U += (int64_t)w * (w + 1) / 2 + (int64_t)w * (int64_t)R[s].size();
   }
-  // lower CSR rows from the L panels (forward) or U panels (transposed)
-  auto build_lower_rows = [&](TriHost& T, bool fromU) {
-    std::vector<int64_t> cnt(n + 1, 0);
-    for (int d = 0; d < ns; ++d) {
-      const int w = sfirst[d + 1] - sfirst[d];
-      for (int r : R[d]) cnt[(fromU ? r : posOf[r]) + 1] += w;
-    }
-    for (int p = 0; p < n; ++p) cnt[p + 1] += cnt[p];
-    T.rp = cnt;
-    T.col.resize(cnt[n]);
-    T.val.resize(cnt[n]);
-    std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
-    for (int d = 0; d < ns; ++d) {
-      const int f = sfirst[d], w = sfirst[d + 1] - f, h = (int)R[d].size();
-      for (int a = 0; a < h; ++a) {
-        const int p = fromU ? R[d][a] : posOf[R[d][a]];
-        for (int j = 0; j < w; ++j) {
-          T.col[pos[p]] = f + j;
-          T.val[pos[p]++] = fromU ? Up[d][(size_t)j * h + a] : Lp[d][(size_t)a * w + j];
-        }
-      }
+  // lower column panels from the L panels (forward) or U panels (transposed):
+  // entry (a, j) = factor[ridx[a], f + j], row-major h x w
+  auto build_lower_panels = [&](TriHost& T, bool fromU) {
+    for (int s = 0; s < ns; ++s) {
+      SnHost& S = T.sn[s];
+      const int w = S.w, h = (int)R[s].size();
+      S.h = h;
+      S.ridx_off = (int64_t)T.ridx.size();
+      S.panel_off = (int64_t)T.val.size();
+      for (int a = 0; a < h; ++a) T.ridx.push_back(fromU ? R[s][a] : posOf[R[s][a]]);
+      for (int a = 0; a < h; ++a)
+        for (int j = 0; j < w; ++j)
+          T.val.push_back(fromU ? Up[s][(size_t)j * h + a] : Lp[s][(size_t)a * w + j]);
     }
   };
   auto build_upper_panels = [&](TriHost& T, bool fromL) {
@@ -826,37 +797,47 @@ int factor_block(const CsrL& M, double tau, bool want_T, BlockFactor& out, std::
   {
     TriHost T;
     init_tri(T, true);
-    build_lower_rows(T, false);
+    build_lower_panels(T, false);
     for (int s = 0; s < ns; ++s) pack_inv(T, s, invL[s], false);
     build_levels(T, sfirst, height, nlev);
-    pack_tri(T, out.lo);
+    if (!pack_tri(T, out.lo)) {
+      err = "supernode wider than 32767 rows, panel taller than 32767 rows or block factor beyond 2^31 entries";
+      return 3;
+    }
   }
   {
     TriHost T;
     init_tri(T, false);
     build_upper_panels(T, false);
-    T.rp.assign(1, 0);
     for (int s = 0; s < ns; ++s) pack_inv(T, s, invU[s], false);
     build_levels(T, sfirst, height, nlev);
-    pack_tri(T, out.up);
+    if (!pack_tri(T, out.up)) {
+      err = "supernode wider than 32767 rows, panel taller than 32767 rows or block factor beyond 2^31 entries";
+      return 3;
+    }
   }
   if (want_T) {
     {
       TriHost T;
       init_tri(T, true);
-      build_lower_rows(T, true);
+      build_lower_panels(T, true);
       for (int s = 0; s < ns; ++s) pack_inv(T, s, invU[s], true);
       build_levels(T, sfirst, height, nlev);
-      pack_tri(T, out.loT);
+      if (!pack_tri(T, out.loT)) {
+      err = "supernode wider than 32767 rows, panel taller than 32767 rows or block factor beyond 2^31 entries";
+      return 3;
+    }
     }
     {
       TriHost T;
       init_tri(T, false);
       build_upper_panels(T, true);
-      T.rp.assign(1, 0);
       for (int s = 0; s < ns; ++s) pack_inv(T, s, invL[s], true);
       build_levels(T, sfirst, height, nlev);
-      pack_tri(T, out.upT);
+      if (!pack_tri(T, out.upT)) {
+      err = "supernode wider than 32767 rows, panel taller than 32767 rows or block factor beyond 2^31 entries";
+      return 3;
+    }
     }
   }
   return 0;
@@ -867,75 +848,93 @@ int factor_block(const CsrL& M, double tau, bool want_T, BlockFactor& out, std::
 // ---------------------------------------------------------------------------
 
 namespace {
-// Lanes per row: enough that one unrolled batch of 8 entries per lane covers
-// the average row, widened while the level leaves threads idle.
-int lanes_for(double avg, int rows) {
-  int g = 1;
-  while (g < 64 && g * 8 < avg) g *= 2;
-  while (g < 64 && (int64_t)rows * g * 2 <= kSolveThreads && g < avg) g *= 2;
-  return g;
+// Chunks per item: enough items x chunks to cover the workgroup, each chunk
+// still a few unrolled batches long.
+int chunks_for(int64_t items, double avg_len) {
+  if (items <= 0) return 1;
+  int c = (int)std::min<int64_t>(255, std::max<int64_t>(1, kSolveThreads / items));
+  const int by_len = std::max(1, (int)(avg_len / 16.0));
+  return std::max(1, std::min(c, by_len));
 }
 }  // namespace
 
-void pack_tri(const TriHost& T, TriPacked& P) {
+bool pack_tri(const TriHost& T, TriPacked& P) {
   P = TriPacked();
   P.lower = T.lower;
   P.n = T.n;
   P.nlev = T.nlev;
   P.max_lrows = T.max_lrows;
   P.lev_ptr = T.lev_ptr;
-  P.lev_g.assign(T.nlev, 0);
+  P.push_ptr.assign(T.nlev + 1, 0);
+  P.lev_c.assign(T.nlev, 0);
   P.rec.assign((size_t)8 * T.n, 0);
-  std::vector<int32_t> ridx_at(T.sn.size(), -1);
   for (int l = 0; l < T.nlev; ++l) {
-    double s1 = 0, s2 = 0;
     const int b = T.lev_ptr[l], e = T.lev_ptr[l + 1];
-    for (int k = b; k < e; ++k) {
-      const int p = T.lrows[k];
-      const int sidx = T.row_sn[p];
+    double tri_len = 0, panel_len = 0, push_len = 0;
+    int64_t npush = 0;
+    for (int k = b; k < e;) {
+      const int sidx = T.row_sn[T.lrows[k]];
       const SnHost& S = T.sn[sidx];
-      const int i = p - S.f;
-      int32_t* r = &P.rec[(size_t)8 * k];
-      r[0] = p;
-      r[1] = (int32_t)P.val.size();
-      if (T.lower) {
-        for (int64_t q = T.rp[p]; q < T.rp[p + 1]; ++q) {
-          P.val.push_back(T.val[q]);
-          P.col.push_back(T.col[q]);
-        }
-        r[2] = (int32_t)(T.rp[p + 1] - T.rp[p]);
-        r[3] = 0;
-      } else {
-        const double* pr = &T.val[S.panel_off + (int64_t)i * S.h];
-        P.val.insert(P.val.end(), pr, pr + S.h);
-        r[2] = S.h;
-        if (ridx_at[sidx] < 0) {
-          ridx_at[sidx] = (int32_t)P.ridx.size();
-          P.ridx.insert(P.ridx.end(), T.ridx.begin() + S.ridx_off, T.ridx.begin() + S.ridx_off + S.h);
-        }
-        r[3] = ridx_at[sidx];
+      const int w = S.w, h = S.h;
+      if (w > 32767 || h > 32767) return false;
+      const int32_t toff = (int32_t)P.tri.size(), poff = (int32_t)P.val.size();
+      const int32_t roff = (int32_t)P.ridx.size();
+      // inverted triangle, column-major packed
+      for (int j = 0; j < w; ++j) {
+        const int i0 = T.lower ? j : 0, i1 = T.lower ? w - 1 : j;
+        for (int i = i0; i <= i1; ++i)
+          P.tri.push_back(T.lower ? T.tri[S.tri_off + (int64_t)i * (i + 1) / 2 + j]
+                                  : T.tri[S.tri_off + (int64_t)i * w - (int64_t)i * (i - 1) / 2 + (j - i)]);
       }
-      const int64_t toff = T.lower ? (int64_t)i * (i + 1) / 2
-                                   : (int64_t)i * S.w - (int64_t)i * (i - 1) / 2;
-      const int tlen = T.lower ? i + 1 : S.w - i;
-      r[4] = (int32_t)P.tri.size();
-      P.tri.insert(P.tri.end(), T.tri.begin() + S.tri_off + toff,
-                   T.tri.begin() + S.tri_off + toff + tlen);
-      r[5] = tlen;
-      r[6] = T.lower ? (k - b) - i : (k - b);
-      r[7] = 0;
-      s1 += r[2];
-      s2 += tlen;
+      // panel, column-major
+      if (T.lower) {
+        for (int j = 0; j < w; ++j)
+          for (int q = 0; q < h; ++q) P.val.push_back(T.val[S.panel_off + (int64_t)q * w + j]);
+      } else {
+        for (int q = 0; q < h; ++q)
+          for (int i = 0; i < w; ++i) P.val.push_back(T.val[S.panel_off + (int64_t)i * h + q]);
+      }
+      P.ridx.insert(P.ridx.end(), T.ridx.begin() + S.ridx_off, T.ridx.begin() + S.ridx_off + h);
+      for (int i = 0; i < w; ++i) {
+        int32_t* r = &P.rec[(size_t)8 * (k + i)];
+        r[0] = S.f + i;
+        r[1] = i;
+        r[2] = w;
+        r[3] = h;
+        r[4] = toff;
+        r[5] = poff;
+        r[6] = roff;
+        r[7] = k - b;
+        tri_len += T.lower ? i + 1 : w - i;
+        panel_len += T.lower ? 0 : h;
+      }
+      if (T.lower) {
+        for (int q = 0; q < h; ++q) {
+          P.prec.push_back(T.ridx[S.ridx_off + q]);
+          P.prec.push_back(poff + q);
+          P.prec.push_back(w | (h << 16));
+          P.prec.push_back(k - b);
+        }
+        npush += h;
+        push_len += (double)h * w;
+      }
+      k += w;
     }
+    P.push_ptr[l + 1] = P.push_ptr[l] + (int32_t)npush;
     const int cnt = e - b;
-    const int g1 = cnt ? lanes_for(s1 / cnt, cnt) : 1;
-    const int g2 = cnt ? lanes_for(s2 / cnt, cnt) : 1;
-    P.lev_g[l] = g1 | (g2 << 8);
+    const int ct = chunks_for(cnt, cnt ? tri_len / cnt : 0.0);
+    const int cp = T.lower ? chunks_for(npush, npush ? push_len / npush : 0.0)
+                           : chunks_for(cnt, cnt ? panel_len / cnt : 0.0);
+    P.lev_c[l] = ct | (cp << 8);
   }
+  // record fields are int32 offsets into the block's arrays
+  return P.val.size() < (size_t)INT32_MAX && P.tri.size() < (size_t)INT32_MAX &&
+         P.ridx.size() < (size_t)INT32_MAX;
 }
 
 // ---------------------------------------------------------------------------
-// Host execution of a packed factor (diagnostics)
+// Host execution of a packed factor (diagnostics): the device algorithm in
+// sequential order
 // ---------------------------------------------------------------------------
 
 void host_tri_solve(const TriPacked& T, std::vector<double>& X) {
@@ -943,18 +942,38 @@ void host_tri_solve(const TriPacked& T, std::vector<double>& X) {
   for (int li = 0; li < T.nlev; ++li) {
     const int l = T.lower ? li : T.nlev - 1 - li;
     const int b = T.lev_ptr[l], e = T.lev_ptr[l + 1];
-    for (int k = b; k < e; ++k) {
-      const int32_t* r = &T.rec[(size_t)8 * k];
-      double acc = 0.0;
-      for (int j = 0; j < r[2]; ++j)
-        acc += T.val[r[1] + j] * X[T.lower ? T.col[r[1] + j] : T.ridx[r[3] + j]];
-      Rb[k - b] = X[r[0]] - acc;
-    }
-    for (int k = b; k < e; ++k) {
-      const int32_t* r = &T.rec[(size_t)8 * k];
-      double acc = 0.0;
-      for (int j = 0; j < r[5]; ++j) acc += T.tri[r[4] + j] * Rb[r[6] + j];
-      X[r[0]] = acc;
+    if (T.lower) {
+      for (int k = b; k < e; ++k) {
+        const int32_t* r = &T.rec[(size_t)8 * k];
+        const int p = r[0], i = r[1], w = r[2];
+        double acc = 0.0;
+        for (int j = 0; j <= i; ++j)
+          acc += T.tri[r[4] + (int64_t)j * w - (int64_t)j * (j - 1) / 2 + (i - j)] * X[p - i + j];
+        Rb[k - b] = acc;
+      }
+      for (int k = b; k < e; ++k) X[T.rec[(size_t)8 * k]] = Rb[k - b];
+      for (int m = T.push_ptr[l]; m < T.push_ptr[l + 1]; ++m) {
+        const int32_t* q = &T.prec[(size_t)4 * m];
+        const int w = q[2] & 0xffff, h = q[2] >> 16;
+        double acc = 0.0;
+        for (int j = 0; j < w; ++j) acc += T.val[q[1] + (int64_t)j * h] * Rb[q[3] + j];
+        X[q[0]] -= acc;
+      }
+    } else {
+      for (int k = b; k < e; ++k) {
+        const int32_t* r = &T.rec[(size_t)8 * k];
+        const int p = r[0], i = r[1], w = r[2], h = r[3];
+        double acc = 0.0;
+        for (int a = 0; a < h; ++a) acc += T.val[r[5] + (int64_t)a * w + i] * X[T.ridx[r[6] + a]];
+        Rb[k - b] = X[p] - acc;
+      }
+      for (int k = b; k < e; ++k) {
+        const int32_t* r = &T.rec[(size_t)8 * k];
+        const int p = r[0], i = r[1], w = r[2];
+        double acc = 0.0;
+        for (int j = i; j < w; ++j) acc += T.tri[r[4] + (int64_t)j * (j + 1) / 2 + i] * Rb[r[7] + j];
+        X[p] = acc;
+      }
     }
   }
 }

@@ -26,58 +26,74 @@ struct CsrG {
   std::vector<double> val;
 };
 
-// One supernode of a packed triangular factor.  Rows f..f+w-1 (positions)
-// form a dense w x w diagonal triangle stored INVERTED and packed by rows at
-// tri_off; for an upper factor the off-diagonal part is a dense w x h panel
-// (row-major, panel_off) over the shared column list ridx[ridx_off .. +h).
+// One supernode of a triangular factor.  Rows f..f+w-1 (positions) form a
+// dense w x w diagonal triangle, stored INVERTED and packed by rows at
+// tri_off (lower: row i holds columns 0..i; upper: columns i..w-1).  The
+// off-diagonal part is a dense panel over the position list
+// ridx[ridx_off .. +h), row-major at panel_off:
+//   lower factor: h x w, entry (a, j) = L[ridx[a], f + j]  (column panel:
+//                 the rows that column block f..f+w-1 updates)
+//   upper factor: w x h, entry (i, a) = U[f + i, ridx[a]]  (row panel)
 struct SnHost {
   int32_t f, w, h, pad;
   int64_t tri_off, panel_off, ridx_off;
 };
 
-// A packed triangular factor of one block, solved level by level: level l
-// holds whole supernodes (rows lrows[lev_ptr[l] .. lev_ptr[l+1]), supernode
-// by supernode, rows ascending).  A lower factor is solved for l = 0..nlev-1
-// and pulls its off-diagonal part from CSR rows (rp/col/val) whose columns are
-// all in earlier levels; an upper factor is solved for l = nlev-1..0 and pulls
-// from the dense panels.
+// A triangular factor of one block, solved level by level: level l holds
+// whole supernodes (rows lrows[lev_ptr[l] .. lev_ptr[l+1]), supernode by
+// supernode, rows ascending).  Lower factors run l = 0..nlev-1, upper ones
+// l = nlev-1..0.
 struct TriHost {
   bool lower = true;
   int32_t n = 0, nlev = 0, max_lrows = 0;
   std::vector<int32_t> lev_ptr;   // nlev + 1
-  std::vector<int32_t> lev_g;     // nlev: lanes per row, phase 1 | (phase 2 << 8)
   std::vector<int32_t> lrows;     // n: positions in level order
   std::vector<int32_t> row_sn;    // n: supernode of each position
   std::vector<SnHost> sn;
-  std::vector<int64_t> rp;        // lower: n + 1
-  std::vector<int32_t> col;       // lower: off-diagonal columns
-  std::vector<double> val;        // lower: CSR values; upper: panel values
-  std::vector<int32_t> ridx;      // upper: panel column lists
+  std::vector<double> val;        // panels
+  std::vector<int32_t> ridx;      // panel position lists
   std::vector<double> tri;        // inverted diagonal triangles, packed by rows
-  int64_t off_nnz() const { return (int64_t)val.size(); }
 };
 
-// Threads of the workgroup that solves one block; lane-group widths are sized for it.
+// Threads of the workgroup that solves one block; chunk counts are sized for it.
 constexpr int kSolveThreads = 1024;
 
-// Device layout of one packed triangular factor of one block.  Rows are stored
-// level by level (the order of TriHost::lrows) and so is all factor data, so
-// every level reads one contiguous stretch of memory.  Each row has one record
-// of 8 int32 (offsets relative to the block's arrays):
-//   [0] position p             [1] off-diagonal start (val/col or panel val)
-//   [2] off-diagonal length    [3] upper: start of the supernode's column list
-//   [4] triangle-row start     [5] triangle-row length
-//   [6] first scratch index of the triangle row (level-local)   [7] unused
-// Solving level l: r_k = X[p] - sum_j off[j] * X[col_j] for all rows k of the
-// level, then X[p] = sum_j tri[j] * r_{rec[6] + j}.
+// Device layout of one packed triangular factor of one block.  All data is
+// stored level by level, so every level reads one contiguous stretch of each
+// array.  Per level l: row items lev_ptr[l] .. lev_ptr[l+1] (one per row) and,
+// for a lower factor, push items push_ptr[l] .. push_ptr[l+1] (one per panel
+// row of each supernode of the level); lev_c[l] = C_T | (C_P << 8) splits the
+// inner loop of every triangle item into C_T chunks and of every panel item
+// into C_P chunks (chunks are combined with atomic adds).
+//
+// Row record, 8 int32 (offsets relative to the block's arrays):
+//   [0] position p   [1] row i in its supernode   [2] w   [3] h
+//   [4] triangle start (column-major packed)       [5] panel start
+//   [6] ridx start   [7] level-local index of the supernode's first row
+// Push record (lower only), 4 int32:
+//   [0] target position ridx[a]   [1] panel start + a   [2] w | (h << 16)
+//   [3] level-local index of the supernode's first row
+//
+// Inverted triangles are column-major packed: lower entry (i, j), j <= i, at
+// j*w - j*(j-1)/2 + (i - j); upper entry (i, j), j >= i, at j*(j+1)/2 + i.
+// Panels are column-major: lower (a, j) at j*h + a, upper (i, a) at a*w + i,
+// so consecutive lanes (consecutive a or i) read consecutive entries.
+//
+// Lower solve (right-looking), per level: s_k = sum_j Tinv(i, j) x[f + j]
+// for every row item (x holds b minus the pushed updates), then x[p] = s_k and
+// x[ridx[a]] -= sum_j Lpanel(a, j) s_{first + j} for every push item.
+// Upper solve (left-looking), per level: r_k = x[p] - sum_a Upanel(i, a)
+// x[ridx[a]], then x[p] = sum_j Tinv(i, j) r_{first + j}.
 struct TriPacked {
   bool lower = true;
   int32_t n = 0, nlev = 0, max_lrows = 0;
   std::vector<int32_t> lev_ptr;   // nlev + 1
-  std::vector<int32_t> lev_g;     // nlev: lanes per row, sweep 1 | (sweep 2 << 8)
+  std::vector<int32_t> push_ptr;  // nlev + 1 (all zero for an upper factor)
+  std::vector<int32_t> lev_c;     // nlev
   std::vector<int32_t> rec;       // 8 per row
+  std::vector<int32_t> prec;      // 4 per push item
   std::vector<double> val, tri;
-  std::vector<int32_t> col, ridx;
+  std::vector<int32_t> ridx;
 };
 
 // Factorisation of one block M: P (Q M Q^T) = L U with Q a nested-dissection
@@ -93,7 +109,8 @@ struct BlockFactor {
   int32_t nsuper = 0;
 };
 
-// Fill `out` for block M.  Returns 0 on success, 2 on a zero pivot (message in err).
+// Fill `out` for block M.  Returns 0 on success, 2 on a zero pivot, 3 on a
+// supernode too large for the device layout (message in err).
 int factor_block(const CsrL& M, double tau, bool want_transpose, BlockFactor& out,
                  std::string& err);
 
@@ -121,8 +138,9 @@ Blocks extract_blocks(int64_t n, const int64_t* rowptr, const int32_t* colind,
 // Apply `fn(i)` for i in [0, count) on `nthreads` host threads.
 void parallel_for(int count, int nthreads, const std::function<void(int)>& fn);
 
-// Pack a TriHost into the device layout.
-void pack_tri(const TriHost& T, TriPacked& P);
+// Pack a TriHost into the device layout; false if a supernode exceeds the
+// record field widths (w or h above 32767) or a block's arrays exceed 2^31.
+bool pack_tri(const TriHost& T, TriPacked& P);
 
 // Host execution of a packed factor on one vector (diagnostics only).
 void host_tri_solve(const TriPacked& T, std::vector<double>& X);

@@ -32,122 +32,288 @@ __device__ __forceinline__ double tv_to_float(double v) { return v; }
 // element (position p, rhs r) at X[p * R + r].  Each factor entry is loaded
 // once and applied to all R of them.
 
-// acc[r] += sum_j v[j] * X[idx[j] * R + r] over this lane's share (j = lane,
-// lane + G, ...), several independent loads in flight per lane.
-template <typename T, int R>
-__device__ __forceinline__ void dot_gather(const T* __restrict__ v, const int32_t* __restrict__ idx,
-                                           int len, const T* X, int lane, int G, T (&acc)[R]) {
-  constexpr int U = R == 1 ? 8 : 4;
-  int j = lane;
-  for (; j + (U - 1) * G < len; j += U * G) {
-    T vv[U];
-    int cc[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      vv[u] = v[j + u * G];
-      cc[u] = idx[j + u * G];
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int r = 0; r < R; ++r) acc[r] += vv[u] * X[cc[u] * R + r];
-  }
-  for (; j < len; j += G) {
-    const T vv = v[j];
-    const int c = idx[j];
-#pragma unroll
-    for (int r = 0; r < R; ++r) acc[r] += vv * X[c * R + r];
-  }
-}
-
-// acc[r] += sum_j v[j] * Y[j * R + r] over this lane's share.
-template <typename T, int R>
-__device__ __forceinline__ void dot_dense(const T* __restrict__ v, int len, const T* Y, int lane,
-                                          int G, T (&acc)[R]) {
-  constexpr int U = R == 1 ? 8 : 4;
-  int j = lane;
-  for (; j + (U - 1) * G < len; j += U * G) {
-    T vv[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) vv[u] = v[j + u * G];
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int r = 0; r < R; ++r) acc[r] += vv[u] * Y[(j + u * G) * R + r];
-  }
-  for (; j < len; j += G) {
-    const T vv = v[j];
-#pragma unroll
-    for (int r = 0; r < R; ++r) acc[r] += vv * Y[j * R + r];
-  }
-}
-
 template <typename T, int R>
 __device__ __forceinline__ void group_sum_r(T (&acc)[R], int G) {
 #pragma unroll
   for (int r = 0; r < R; ++r) acc[r] = group_sum(acc[r], G);
 }
 
+template <typename T>
+__device__ __forceinline__ void atomic_add(T* addr, T v) {
+  unsafeAtomicAdd(addr, v);
+}
+
+// Chunk counts of a level, scaled by 2^gshift (the setup autotuner's knob).
+__device__ __forceinline__ void level_chunks(int c, int gshift, int& CT, int& CP) {
+  CT = c & 0xff;
+  CP = (c >> 8) & 0xff;
+  if (gshift > 0) {
+    CT = min(255, CT << gshift);
+    CP = min(255, CP << gshift);
+  } else if (gshift < 0) {
+    CT = max(1, CT >> -gshift);
+    CP = max(1, CP >> -gshift);
+  }
+}
+
+// acc[r] += sum_{0 <= t < n} M[off(jt)] * S[jt * R + r] with jt = j0 + d * t
+// (d = +1 or -1): one lane's share of a dense column-major product.  Lanes of
+// a supernode start at the same j and walk it in step, so consecutive lanes
+// (consecutive rows) read consecutive entries while their counts n differ; S
+// is the same for all of them.
+template <typename T, int R, typename Off>
+__device__ __forceinline__ void panel_dot(const T* __restrict__ M, Off off, int j0, int d, int n,
+                                          const T* S, T (&acc)[R]) {
+  constexpr int U = R == 1 ? 8 : 4;
+  int t = 0;
+  for (; t + U <= n; t += U) {
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = M[off(j0 + d * (t + u))];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] += v[u] * S[(j0 + d * (t + u)) * R + r];
+  }
+  for (; t < n; ++t) {
+    const T v = M[off(j0 + d * t)];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] += v * S[(j0 + d * t) * R + r];
+  }
+}
+
 // Solve one packed triangular factor of block `bi` in place on the vector tile
-// X (positions 0..n-1, R right-hand sides); Rb is scratch of max_lrows * R
-// entries.  All threads of the workgroup must call it.  Ends with a barrier.
+// X (positions 0..n-1, R right-hand sides).  Rb is scratch of 2 * max_lrows * R
+// entries (two halves used by alternate levels, so that one level's chunk sums
+// can be cleared while the other's are read).  All threads of the workgroup
+// must call it; it ends with a barrier.
+//
+// Lower factors run right-looking: per level, every row item forms
+// s_k = sum_j Tinv(i, j) x[f + j] (x already holds b minus all pushed updates),
+// then x[p] = s_k and every push item subtracts its panel row times s from
+// x[ridx[a]] (atomic adds: supernodes of a level may update the same rows).
+// Upper factors run left-looking: r_k = x[p] - sum_a Upanel(i, a) x[ridx[a]],
+// then x[p] = sum_j Tinv(i, j) r_j.  Inner loops are split into CT / CP chunks
+// whose partial sums meet through atomic adds into cleared scratch.
+//
+// Records do not depend on x, so each thread's first record of a sweep is
+// loaded before the barrier that precedes the sweep, and the record of its
+// next task while it works on the current one.
 template <typename T, int R>
 __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift) {
   const DevTriBlock B = A.blk[bi];
+  if (B.nlev <= 0) return;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int4* rec = A.rec + 2 * B.rec_base;
-  const T* val = A.val + B.val_base;
-  const int32_t* col = A.col + B.val_base;
+  const int4* prec = A.prec + B.prec_base;
+  const T* pan = A.val + B.val_base;
   const int32_t* ridx = A.ridx + B.ridx_base;
   const T* tri = A.tri + B.tri_base;
   const int32_t* lev_ptr = A.lev_ptr + B.lev_base;
-  const int32_t* lev_g = A.lev_g + B.lev_base;
+  const int32_t* push_ptr = A.push_ptr + B.lev_base;
+  const int32_t* lev_c = A.lev_c + B.lev_base;
+  const int4 z4 = make_int4(0, 0, 0, 0);
+  T* const Rh0 = Rb;
+  T* const Rh1 = Rb + (int64_t)R * B.max_lrows;
+  // first row record of this thread in the coming sweep: row tid % cnt
+  int4 f0 = z4, f1 = z4;
+  {
+    const int l0 = B.lower ? 0 : B.nlev - 1;
+    const int b0 = lev_ptr[l0], c0 = lev_ptr[l0 + 1] - b0;
+    if (c0 > 0) {
+      f0 = rec[2 * (b0 + tid % c0)];
+      f1 = rec[2 * (b0 + tid % c0) + 1];
+    }
+  }
   for (int li = 0; li < B.nlev; ++li) {
     const int l = B.lower ? li : B.nlev - 1 - li;
     const int b = lev_ptr[l];
     const int cnt = lev_ptr[l + 1] - b;
-    const int g = lev_g[l];
-    int G1 = g & 0xff, G2 = (g >> 8) & 0xff;
-    if (gshift > 0) {
-      G1 = min(64, G1 << gshift);
-      G2 = min(64, G2 << gshift);
-    } else if (gshift < 0) {
-      G1 = max(1, G1 >> -gshift);
-      G2 = max(1, G2 >> -gshift);
+    int CT, CP;
+    level_chunks(lev_c[l], gshift, CT, CP);
+    T* Rc = (li & 1) ? Rh1 : Rh0;
+    T* Rn = (li & 1) ? Rh0 : Rh1;
+    int bn = 0, cntn = 0, CTn = 1, CPn = 1;
+    if (li + 1 < B.nlev) {
+      const int ln = B.lower ? l + 1 : l - 1;
+      bn = lev_ptr[ln];
+      cntn = lev_ptr[ln + 1] - bn;
+      level_chunks(lev_c[ln], gshift, CTn, CPn);
     }
-    // sweep 1: r_k = x_p - (off-diagonal part of row p) . x
-    {
-      const int grp = tid / G1, lane = tid - grp * G1, ngrp = nthr / G1;
-      for (int k = grp; k < cnt; k += ngrp) {
-        const int4 rr = rec[2 * (b + k)];
-        T acc[R];
+    if (li == 0 && (B.lower ? CT : CP) > 1) {
+      for (int e = tid; e < cnt * R; e += nthr) Rc[e] = (T)0;
+      __syncthreads();
+    }
+    if (B.lower) {
+      const int pb = push_ptr[l], np = push_ptr[l + 1] - pb;
+      int4 fq = np > 0 ? prec[pb + tid % np] : z4;
+      // s_k = Tinv(i, 0..i) x[f .. f+i]
+      {
+        int4 r0 = f0, r1 = f1;
+        for (int t = tid; t < cnt * CT; t += nthr) {
+          const int tn = t + nthr;
+          int4 n0 = z4, n1 = z4;
+          if (tn < cnt * CT) {
+            n0 = rec[2 * (b + tn % cnt)];
+            n1 = rec[2 * (b + tn % cnt) + 1];
+          }
+          const int c = t / cnt, k = t - c * cnt;
+          const int i = r0.y, w = r0.z;
+          const int Lc = (w + CT - 1) / CT;
+          const int j0 = c * Lc, j1 = min(w, j0 + Lc);
+          T acc[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) acc[r] = 0;
-        dot_gather<T, R>(val + rr.y, B.lower ? col + rr.y : ridx + rr.w, rr.z, X, lane, G1, acc);
-        group_sum_r<T, R>(acc, G1);
-        if (lane == 0)
+          for (int r = 0; r < R; ++r) acc[r] = 0;
+          panel_dot<T, R>(tri + r1.x, [=](int j) { return j * w - (j * (j - 1) >> 1) + (i - j); }, j0, 1,
+                          min(j1, i + 1) - j0, X + (int64_t)(r0.x - i) * R, acc);
+          if (CT == 1) {
 #pragma unroll
-          for (int r = 0; r < R; ++r) Rb[k * R + r] = X[rr.x * R + r] - acc[r];
+            for (int r = 0; r < R; ++r) Rc[k * R + r] = acc[r];
+          } else if (j0 <= i) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) atomic_add(&Rc[k * R + r], acc[r]);
+          }
+          r0 = n0;
+          r1 = n1;
+        }
       }
-    }
-    __syncthreads();
-    // sweep 2: x_s = inv(T_ss) r_s for every supernode of the level
-    {
-      const int grp = tid / G2, lane = tid - grp * G2, ngrp = nthr / G2;
-      for (int k = grp; k < cnt; k += ngrp) {
-        const int p = rec[2 * (b + k)].x;
-        const int4 rr = rec[2 * (b + k) + 1];
-        T acc[R];
+      __syncthreads();
+      // x[p] = s_k
+      for (int k = tid; k < cnt; k += nthr) {
+        const int p = k == tid ? f0.x : rec[2 * (b + k)].x;
 #pragma unroll
-        for (int r = 0; r < R; ++r) acc[r] = 0;
-        dot_dense<T, R>(tri + rr.x, rr.y, Rb + rr.z * R, lane, G2, acc);
-        group_sum_r<T, R>(acc, G2);
-        if (lane == 0)
-#pragma unroll
-          for (int r = 0; r < R; ++r) X[p * R + r] = acc[r];
+        for (int r = 0; r < R; ++r) X[p * R + r] = Rc[k * R + r];
       }
+      // x[ridx[a]] -= Lpanel(a, :) s
+      {
+        int4 q = fq;
+        for (int t = tid; t < np * CP; t += nthr) {
+          const int tn = t + nthr;
+          const int4 qn = tn < np * CP ? prec[pb + tn % np] : z4;
+          const int c = t / np;
+          const int w = q.z & 0xffff, h = q.z >> 16;
+          const int Lc = (w + CP - 1) / CP;
+          const int j0 = c * Lc, j1 = min(w, j0 + Lc);
+          if (j0 < j1) {
+            T acc[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] = 0;
+            panel_dot<T, R>(pan + q.y, [=](int j) { return j * h; }, j0, 1, j1 - j0, Rc + (int64_t)q.w * R, acc);
+#pragma unroll
+            for (int r = 0; r < R; ++r) atomic_add(&X[q.x * R + r], -acc[r]);
+          }
+          q = qn;
+        }
+      }
+      if (CTn > 1)
+        for (int e = tid; e < cntn * R; e += nthr) Rn[e] = (T)0;
+      if (cntn > 0) {
+        f0 = rec[2 * (bn + tid % cntn)];
+        f1 = rec[2 * (bn + tid % cntn) + 1];
+      }
+      __syncthreads();
+    } else {
+      // r_k = x[p] - Upanel(i, :) x[ridx]
+      {
+        int4 r0 = f0, r1 = f1;
+        for (int t = tid; t < cnt * CP; t += nthr) {
+          const int tn = t + nthr;
+          int4 n0 = z4, n1 = z4;
+          if (tn < cnt * CP) {
+            n0 = rec[2 * (b + tn % cnt)];
+            n1 = rec[2 * (b + tn % cnt) + 1];
+          }
+          const int c = t / cnt, k = t - c * cnt;
+          const int p = r0.x, i = r0.y, w = r0.z, h = r0.w;
+          const int Lc = (h + CP - 1) / CP;
+          const int a0 = c * Lc, a1 = min(h, a0 + Lc);
+          const T* pc = pan + r1.y + i;
+          const int32_t* rc = ridx + r1.z;
+          T acc[R];
+#pragma unroll
+          for (int r = 0; r < R; ++r) acc[r] = 0;
+          constexpr int U = R == 1 ? 8 : 4;
+          int a = a0;
+          for (; a + U <= a1; a += U) {
+            T v[U];
+            int cc[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+              v[u] = pc[(a + u) * w];
+              cc[u] = rc[a + u];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+              for (int r = 0; r < R; ++r) acc[r] += v[u] * X[cc[u] * R + r];
+          }
+          for (; a < a1; ++a) {
+            const T v = pc[a * w];
+            const int cc = rc[a];
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] += v * X[cc * R + r];
+          }
+          if (CP == 1) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+              Rc[k * R + r] = X[p * R + r] - acc[r];
+              if (CT > 1) X[p * R + r] = (T)0;
+            }
+          } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+              T v = -acc[r];
+              if (c == 0) {
+                v += X[p * R + r];
+                if (CT > 1) X[p * R + r] = (T)0;
+              }
+              if (c == 0 || a0 < a1) atomic_add(&Rc[k * R + r], v);
+            }
+          }
+          r0 = n0;
+          r1 = n1;
+        }
+      }
+      if (CPn > 1)
+        for (int e = tid; e < cntn * R; e += nthr) Rn[e] = (T)0;
+      __syncthreads();
+      // x[p] = Tinv(i, i..w-1) r
+      {
+        int4 r0 = f0, r1 = f1;
+        for (int t = tid; t < cnt * CT; t += nthr) {
+          const int tn = t + nthr;
+          int4 n0 = z4, n1 = z4;
+          if (tn < cnt * CT) {
+            n0 = rec[2 * (b + tn % cnt)];
+            n1 = rec[2 * (b + tn % cnt) + 1];
+          }
+          const int c = t / cnt;
+          const int p = r0.x, i = r0.y, w = r0.z;
+          const int Lc = (w + CT - 1) / CT;
+          const int j0 = c * Lc, j1 = min(w, j0 + Lc);
+          T acc[R];
+#pragma unroll
+          for (int r = 0; r < R; ++r) acc[r] = 0;
+          // columns j1-1 down to max(j0, i): a common start for the lanes
+          panel_dot<T, R>(tri + r1.x, [=](int j) { return ((j * (j + 1)) >> 1) + i; }, j1 - 1, -1,
+                          j1 - max(j0, i), Rc + (int64_t)r1.w * R, acc);
+          if (CT == 1) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) X[p * R + r] = acc[r];
+          } else if (j1 > i) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) atomic_add(&X[p * R + r], acc[r]);
+          }
+          r0 = n0;
+          r1 = n1;
+        }
+      }
+      if (cntn > 0) {
+        f0 = rec[2 * (bn + tid % cntn)];
+        f1 = rec[2 * (bn + tid % cntn) + 1];
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 
@@ -175,7 +341,7 @@ __device__ Lds<T> carve(const ApplyArrays<T>& A) {
     extern __shared__ __align__(16) unsigned char smem[];
     L.XB = reinterpret_cast<T*>(smem);
     L.Rb = L.XB + R * A.maxPB;
-    L.XC = L.Rb + R * A.maxLR;
+    L.XC = L.Rb + 2 * R * A.maxLR;
     L.U = L.XC + R * A.maxQB;
     L.W = L.U + R * A.maxQB;
   }
