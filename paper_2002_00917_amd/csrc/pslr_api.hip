@@ -74,15 +74,15 @@ struct DevPool {
 };
 
 // Concatenate one factor family over all blocks.  `bytes` receives the
-// algorithmic bytes of one solve of every block: each value once (triangles and
-// panels), each panel position list once, one record per row and per push
-// item, the level tables.
+// algorithmic bytes of one single-right-hand-side solve of every block (LDS
+// working vectors): each value it reads once (triangles, panels or entries),
+// the indices and records it reads once, the level tables.
 template <typename T>
 hipError_t upload_tri(DevPool& pool, const std::vector<BlockFactor>& F, TriPacked BlockFactor::*mem,
                       TriArrays<T>& out, int& max_lrows, int64_t& bytes) {
   std::vector<DevTriBlock> blk(F.size());
-  std::vector<int32_t> lev_ptr, push_ptr, lev_c, rec, prec, ridx;
-  std::vector<T> val, tri;
+  std::vector<int32_t> lev_ptr, push_ptr, ent_ptr, lev_c, rec, prec, ridx, eidx, eloc;
+  std::vector<T> val, tri, eval;
   bytes = 0;
   for (size_t i = 0; i < F.size(); ++i) {
     const TriPacked& H = F[i].*mem;
@@ -94,6 +94,7 @@ hipError_t upload_tri(DevPool& pool, const std::vector<BlockFactor>& F, TriPacke
     B.lev_base = (int64_t)lev_ptr.size();
     B.rec_base = (int64_t)rec.size() / 8;
     B.prec_base = (int64_t)prec.size() / 4;
+    B.ent_base = (int64_t)eval.size();
     B.val_base = (int64_t)val.size();
     B.ridx_base = (int64_t)ridx.size();
     B.tri_base = (int64_t)tri.size();
@@ -101,6 +102,8 @@ hipError_t upload_tri(DevPool& pool, const std::vector<BlockFactor>& F, TriPacke
     lev_ptr.insert(lev_ptr.end(), H.lev_ptr.begin(), H.lev_ptr.end());
     push_ptr.insert(push_ptr.end(), H.push_ptr.begin(), H.push_ptr.end());
     if (H.push_ptr.size() < H.lev_ptr.size()) push_ptr.resize(lev_ptr.size(), 0);
+    ent_ptr.insert(ent_ptr.end(), H.ent_ptr.begin(), H.ent_ptr.end());
+    if (H.ent_ptr.size() < H.lev_ptr.size()) ent_ptr.resize(lev_ptr.size(), 0);
     lev_c.insert(lev_c.end(), H.lev_c.begin(), H.lev_c.end());
     lev_c.resize(lev_ptr.size(), 0);
     rec.insert(rec.end(), H.rec.begin(), H.rec.end());
@@ -108,13 +111,17 @@ hipError_t upload_tri(DevPool& pool, const std::vector<BlockFactor>& F, TriPacke
     for (double v : H.val) val.push_back((T)v);
     ridx.insert(ridx.end(), H.ridx.begin(), H.ridx.end());
     for (double v : H.tri) tri.push_back((T)v);
-    bytes += (int64_t)(H.val.size() + H.tri.size()) * (int64_t)sizeof(T) + 4 * (int64_t)H.ridx.size() +
-             4 * (int64_t)H.rec.size() + 4 * (int64_t)H.prec.size() + 12 * (int64_t)(H.nlev + 1);
+    for (double v : H.eval) eval.push_back((T)v);
+    eidx.insert(eidx.end(), H.eidx.begin(), H.eidx.end());
+    eloc.insert(eloc.end(), H.eloc.begin(), H.eloc.end());
+    const int path = sizeof(T) == 8 ? 0 : 1;  // entry form only in FP64
+    bytes += H.read_vals[path] * (int64_t)sizeof(T) + 4 * H.read_ints[path];
   }
   hipError_t e;
   if ((e = pool.upload(blk, &out.blk))) return e;
   if ((e = pool.upload(lev_ptr, &out.lev_ptr))) return e;
   if ((e = pool.upload(push_ptr, &out.push_ptr))) return e;
+  if ((e = pool.upload(ent_ptr, &out.ent_ptr))) return e;
   if ((e = pool.upload(lev_c, &out.lev_c))) return e;
   const int32_t* p = nullptr;
   if ((e = pool.upload(rec, &p))) return e;
@@ -124,6 +131,9 @@ hipError_t upload_tri(DevPool& pool, const std::vector<BlockFactor>& F, TriPacke
   if ((e = pool.upload(val, &out.val))) return e;
   if ((e = pool.upload(ridx, &out.ridx))) return e;
   if ((e = pool.upload(tri, &out.tri))) return e;
+  if ((e = pool.upload(eval, &out.eval))) return e;
+  if ((e = pool.upload(eidx, &out.eidx))) return e;
+  if ((e = pool.upload(eloc, &out.eloc))) return e;
   return hipSuccess;
 }
 

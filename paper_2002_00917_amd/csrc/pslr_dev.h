@@ -13,9 +13,10 @@ namespace pslr {
 // {p, off_begin, off_len, ridx_begin, tri_begin, tri_len, rb_first, 0}.
 struct DevTriBlock {
   int32_t n, nlev, max_lrows, lower;
-  int64_t lev_base;   // lev_ptr/push_ptr[lev_base .. +nlev], lev_c[lev_base .. +nlev)
+  int64_t lev_base;   // lev_ptr/push_ptr/ent_ptr[lev_base .. +nlev], lev_c[lev_base .. +nlev)
   int64_t rec_base;   // row records, in rows
   int64_t prec_base;  // push records, in items
+  int64_t ent_base;   // entry-form values and indices
   int64_t val_base;   // panels
   int64_t ridx_base;  // panel position lists
   int64_t tri_base;   // inverted diagonal triangles
@@ -27,12 +28,16 @@ struct TriArrays {
   const DevTriBlock* blk;
   const int32_t* lev_ptr;
   const int32_t* push_ptr;
+  const int32_t* ent_ptr;
   const int32_t* lev_c;
   const int4* rec;
   const int4* prec;
   const T* val;
   const int32_t* ridx;
   const T* tri;
+  const T* eval;
+  const int32_t* eidx;
+  const int32_t* eloc;
 };
 
 // Block-diagonal CSR over all subdomains with 64-bit row offsets.

@@ -866,10 +866,16 @@ bool pack_tri(const TriHost& T, TriPacked& P) {
   P.max_lrows = T.max_lrows;
   P.lev_ptr = T.lev_ptr;
   P.push_ptr.assign(T.nlev + 1, 0);
+  P.ent_ptr.assign(T.nlev + 1, 0);
   P.lev_c.assign(T.nlev, 0);
   P.rec.assign((size_t)8 * T.n, 0);
   for (int l = 0; l < T.nlev; ++l) {
     const int b = T.lev_ptr[l], e = T.lev_ptr[l + 1];
+    const int cnt = e - b;
+    int nsn = 0;
+    for (int k = b; k < e; k += T.sn[T.row_sn[T.lrows[k]]].w) ++nsn;
+    // narrow supernodes: entry form for the off-diagonal part
+    const bool ent = nsn > 0 && cnt < kNarrowWidth * nsn;
     double tri_len = 0, panel_len = 0, push_len = 0;
     int64_t npush = 0;
     for (int k = b; k < e;) {
@@ -886,15 +892,46 @@ bool pack_tri(const TriHost& T, TriPacked& P) {
           P.tri.push_back(T.lower ? T.tri[S.tri_off + (int64_t)i * (i + 1) / 2 + j]
                                   : T.tri[S.tri_off + (int64_t)i * w - (int64_t)i * (i - 1) / 2 + (j - i)]);
       }
-      // panel, column-major
-      if (T.lower) {
-        for (int j = 0; j < w; ++j)
-          for (int q = 0; q < h; ++q) P.val.push_back(T.val[S.panel_off + (int64_t)q * w + j]);
-      } else {
-        for (int q = 0; q < h; ++q)
-          for (int i = 0; i < w; ++i) P.val.push_back(T.val[S.panel_off + (int64_t)i * h + q]);
+      if (ent) {
+        // entry form (kept besides the panels; the solve picks one):
+        // lower: (a, j) -> x[ridx[a]] -= v * s_{k0 + j};  upper: (i, a) -> r_{k0 + i} -= v * x[ridx[a]]
+        if (T.lower) {
+          for (int j = 0; j < w; ++j)
+            for (int q = 0; q < h; ++q) {
+              P.eval.push_back(T.val[S.panel_off + (int64_t)q * w + j]);
+              P.eidx.push_back(T.ridx[S.ridx_off + q]);
+              P.eloc.push_back(k - b + j);
+            }
+        } else {
+          for (int q = 0; q < h; ++q)
+            for (int i = 0; i < w; ++i) {
+              P.eval.push_back(T.val[S.panel_off + (int64_t)i * h + q]);
+              P.eidx.push_back(T.ridx[S.ridx_off + q]);
+              P.eloc.push_back(k - b + i);
+            }
+        }
       }
-      P.ridx.insert(P.ridx.end(), T.ridx.begin() + S.ridx_off, T.ridx.begin() + S.ridx_off + h);
+      {
+        // panel, column-major
+        if (T.lower) {
+          for (int j = 0; j < w; ++j)
+            for (int q = 0; q < h; ++q) P.val.push_back(T.val[S.panel_off + (int64_t)q * w + j]);
+        } else {
+          for (int q = 0; q < h; ++q)
+            for (int i = 0; i < w; ++i) P.val.push_back(T.val[S.panel_off + (int64_t)i * h + q]);
+        }
+        P.ridx.insert(P.ridx.end(), T.ridx.begin() + S.ridx_off, T.ridx.begin() + S.ridx_off + h);
+        if (T.lower) {
+          for (int q = 0; q < h; ++q) {
+            P.prec.push_back(T.ridx[S.ridx_off + q]);
+            P.prec.push_back(poff + q);
+            P.prec.push_back(w | (h << 16));
+            P.prec.push_back(k - b);
+          }
+          npush += h;
+          push_len += (double)h * w;
+        }
+      }
       for (int i = 0; i < w; ++i) {
         int32_t* r = &P.rec[(size_t)8 * (k + i)];
         r[0] = S.f + i;
@@ -908,28 +945,37 @@ bool pack_tri(const TriHost& T, TriPacked& P) {
         tri_len += T.lower ? i + 1 : w - i;
         panel_len += T.lower ? 0 : h;
       }
-      if (T.lower) {
-        for (int q = 0; q < h; ++q) {
-          P.prec.push_back(T.ridx[S.ridx_off + q]);
-          P.prec.push_back(poff + q);
-          P.prec.push_back(w | (h << 16));
-          P.prec.push_back(k - b);
-        }
-        npush += h;
-        push_len += (double)h * w;
-      }
       k += w;
     }
     P.push_ptr[l + 1] = P.push_ptr[l] + (int32_t)npush;
-    const int cnt = e - b;
+    const int64_t nent = (int64_t)P.eval.size() - P.ent_ptr[l];
+    P.ent_ptr[l + 1] = (int32_t)P.eval.size();
+    {
+      // what each path reads at this level besides triangles and row records
+      int64_t pv = 0, pi = 0;
+      for (int k = b; k < e;) {
+        const SnHost& S = T.sn[T.row_sn[T.lrows[k]]];
+        pv += (int64_t)S.w * S.h;
+        pi += T.lower ? 4 * (int64_t)S.h : S.h;  // push records / position list
+        k += S.w;
+      }
+      P.read_vals[1] += pv;
+      P.read_ints[1] += pi;
+      P.read_vals[0] += ent ? nent : pv;
+      P.read_ints[0] += ent ? 2 * nent : pi;
+    }
     const int ct = chunks_for(cnt, cnt ? tri_len / cnt : 0.0);
     const int cp = T.lower ? chunks_for(npush, npush ? push_len / npush : 0.0)
                            : chunks_for(cnt, cnt ? panel_len / cnt : 0.0);
-    P.lev_c[l] = ct | (cp << 8);
+    P.lev_c[l] = ct | (cp << 8) | ((ent ? 1 : 0) << 16);
+  }
+  for (int q = 0; q < 2; ++q) {
+    P.read_vals[q] += (int64_t)P.tri.size();
+    P.read_ints[q] += (int64_t)P.rec.size() + 4 * (int64_t)(T.nlev + 1);
   }
   // record fields are int32 offsets into the block's arrays
   return P.val.size() < (size_t)INT32_MAX && P.tri.size() < (size_t)INT32_MAX &&
-         P.ridx.size() < (size_t)INT32_MAX;
+         P.ridx.size() < (size_t)INT32_MAX && P.eval.size() < (size_t)INT32_MAX;
 }
 
 // ---------------------------------------------------------------------------
@@ -942,6 +988,7 @@ void host_tri_solve(const TriPacked& T, std::vector<double>& X) {
   for (int li = 0; li < T.nlev; ++li) {
     const int l = T.lower ? li : T.nlev - 1 - li;
     const int b = T.lev_ptr[l], e = T.lev_ptr[l + 1];
+    const bool ent = (T.lev_c[l] >> 16) & 1;
     if (T.lower) {
       for (int k = b; k < e; ++k) {
         const int32_t* r = &T.rec[(size_t)8 * k];
@@ -952,21 +999,27 @@ void host_tri_solve(const TriPacked& T, std::vector<double>& X) {
         Rb[k - b] = acc;
       }
       for (int k = b; k < e; ++k) X[T.rec[(size_t)8 * k]] = Rb[k - b];
-      for (int m = T.push_ptr[l]; m < T.push_ptr[l + 1]; ++m) {
-        const int32_t* q = &T.prec[(size_t)4 * m];
-        const int w = q[2] & 0xffff, h = q[2] >> 16;
-        double acc = 0.0;
-        for (int j = 0; j < w; ++j) acc += T.val[q[1] + (int64_t)j * h] * Rb[q[3] + j];
-        X[q[0]] -= acc;
+      if (ent) {
+        for (int q = T.ent_ptr[l]; q < T.ent_ptr[l + 1]; ++q) X[T.eidx[q]] -= T.eval[q] * Rb[T.eloc[q]];
+      } else {
+        for (int m = T.push_ptr[l]; m < T.push_ptr[l + 1]; ++m) {
+          const int32_t* q = &T.prec[(size_t)4 * m];
+          const int w = q[2] & 0xffff, h = q[2] >> 16;
+          double acc = 0.0;
+          for (int j = 0; j < w; ++j) acc += T.val[q[1] + (int64_t)j * h] * Rb[q[3] + j];
+          X[q[0]] -= acc;
+        }
       }
     } else {
       for (int k = b; k < e; ++k) {
         const int32_t* r = &T.rec[(size_t)8 * k];
-        const int p = r[0], i = r[1], w = r[2], h = r[3];
+        const int i = r[1], w = r[2], h = ent ? 0 : r[3];
         double acc = 0.0;
         for (int a = 0; a < h; ++a) acc += T.val[r[5] + (int64_t)a * w + i] * X[T.ridx[r[6] + a]];
-        Rb[k - b] = X[p] - acc;
+        Rb[k - b] = X[r[0]] - acc;
       }
+      if (ent)
+        for (int q = T.ent_ptr[l]; q < T.ent_ptr[l + 1]; ++q) Rb[T.eloc[q]] -= T.eval[q] * X[T.eidx[q]];
       for (int k = b; k < e; ++k) {
         const int32_t* r = &T.rec[(size_t)8 * k];
         const int p = r[0], i = r[1], w = r[2];

@@ -57,20 +57,30 @@ struct TriHost {
 
 // Threads of the workgroup that solves one block; chunk counts are sized for it.
 constexpr int kSolveThreads = 1024;
+// Levels whose supernodes average fewer rows than this store their
+// off-diagonal part as entries rather than panels.
+constexpr int kNarrowWidth = 8;
 
 // Device layout of one packed triangular factor of one block.  All data is
 // stored level by level, so every level reads one contiguous stretch of each
-// array.  Per level l: row items lev_ptr[l] .. lev_ptr[l+1] (one per row) and,
-// for a lower factor, push items push_ptr[l] .. push_ptr[l+1] (one per panel
-// row of each supernode of the level); lev_c[l] = C_T | (C_P << 8) splits the
-// inner loop of every triangle item into C_T chunks and of every panel item
-// into C_P chunks (chunks are combined with atomic adds).
+// array.  Per level l: row items lev_ptr[l] .. lev_ptr[l+1] (one per row);
+// lev_c[l] = C_T | (C_P << 8) | (E << 16) splits the inner loop of every
+// triangle item into C_T chunks and of every panel item into C_P chunks
+// (chunks meet through atomic adds).  The off-diagonal part of a level is
+// stored as panels and, for levels of narrow supernodes (E = 1), also as
+// entries ent_ptr[l] .. ent_ptr[l+1] with one value and two indices each, so
+// that every thread streams independent loads:
+//   lower: x[eidx] -= eval * s_{eloc}        upper: r_{eloc} -= eval * x[eidx]
+// FP64 single-right-hand-side solves with working vectors in LDS use the
+// entries (one atomic add per entry is cheap there); other solves use the panels.  A
+// lower factor has push items push_ptr[l] .. push_ptr[l+1], one per panel row
+// of each supernode.
 //
 // Row record, 8 int32 (offsets relative to the block's arrays):
 //   [0] position p   [1] row i in its supernode   [2] w   [3] h
 //   [4] triangle start (column-major packed)       [5] panel start
 //   [6] ridx start   [7] level-local index of the supernode's first row
-// Push record (lower only), 4 int32:
+// Push record (lower panel levels), 4 int32:
 //   [0] target position ridx[a]   [1] panel start + a   [2] w | (h << 16)
 //   [3] level-local index of the supernode's first row
 //
@@ -78,22 +88,27 @@ constexpr int kSolveThreads = 1024;
 // j*w - j*(j-1)/2 + (i - j); upper entry (i, j), j >= i, at j*(j+1)/2 + i.
 // Panels are column-major: lower (a, j) at j*h + a, upper (i, a) at a*w + i,
 // so consecutive lanes (consecutive a or i) read consecutive entries.
+// Entries follow the same order within each supernode.
 //
 // Lower solve (right-looking), per level: s_k = sum_j Tinv(i, j) x[f + j]
 // for every row item (x holds b minus the pushed updates), then x[p] = s_k and
-// x[ridx[a]] -= sum_j Lpanel(a, j) s_{first + j} for every push item.
+// x[ridx[a]] -= sum_j Lpanel(a, j) s_{first + j}.
 // Upper solve (left-looking), per level: r_k = x[p] - sum_a Upanel(i, a)
 // x[ridx[a]], then x[p] = sum_j Tinv(i, j) r_{first + j}.
 struct TriPacked {
   bool lower = true;
   int32_t n = 0, nlev = 0, max_lrows = 0;
   std::vector<int32_t> lev_ptr;   // nlev + 1
-  std::vector<int32_t> push_ptr;  // nlev + 1 (all zero for an upper factor)
+  std::vector<int32_t> push_ptr;  // nlev + 1
+  std::vector<int32_t> ent_ptr;   // nlev + 1
   std::vector<int32_t> lev_c;     // nlev
   std::vector<int32_t> rec;       // 8 per row
   std::vector<int32_t> prec;      // 4 per push item
-  std::vector<double> val, tri;
-  std::vector<int32_t> ridx;
+  std::vector<double> val, tri, eval;
+  std::vector<int32_t> ridx, eidx, eloc;
+  // entries a solve reads: values and int32 indices/record words, [0] on the
+  // single-right-hand-side path (entry form where present), [1] on the panel path
+  int64_t read_vals[2] = {0, 0}, read_ints[2] = {0, 0};
 };
 
 // Factorisation of one block M: P (Q M Q^T) = L U with Q a nested-dissection

@@ -82,6 +82,38 @@ __device__ __forceinline__ void panel_dot(const T* __restrict__ M, Off off, int 
   }
 }
 
+// Entry-form off-diagonal part of a level: for e in [e0, e1),
+// D[dst(e)] -= v[e] * S[src(e)] with atomic adds, unrolled so that every thread
+// keeps several independent loads in flight.
+template <typename T, int R>
+__device__ __forceinline__ void entry_sweep(const T* __restrict__ v, const int32_t* __restrict__ to,
+                                            const int32_t* __restrict__ from, int e0, int e1, T* D,
+                                            const T* S, bool lower) {
+  constexpr int U = R == 1 ? 8 : 4;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  for (int e = e0 + tid; e < e1; e += U * nthr) {
+    T vv[U];
+    int it[U], il[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int q = e + u * nthr;
+      const bool ok = q < e1;
+      vv[u] = ok ? v[q] : (T)0;
+      it[u] = ok ? to[q] : 0;
+      il[u] = ok ? from[q] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (e + u * nthr < e1) {
+        // lower: to = target position, from = level-local source row;
+        // upper: to = source position, from = level-local target row
+        const int d = lower ? it[u] : il[u], s = lower ? il[u] : it[u];
+#pragma unroll
+        for (int r = 0; r < R; ++r) atomic_add(&D[d * R + r], -vv[u] * S[s * R + r]);
+      }
+  }
+}
+
 // Solve one packed triangular factor of block `bi` in place on the vector tile
 // X (positions 0..n-1, R right-hand sides).  Rb is scratch of 2 * max_lrows * R
 // entries (two halves used by alternate levels, so that one level's chunk sums
@@ -93,13 +125,16 @@ __device__ __forceinline__ void panel_dot(const T* __restrict__ M, Off off, int 
 // then x[p] = s_k and every push item subtracts its panel row times s from
 // x[ridx[a]] (atomic adds: supernodes of a level may update the same rows).
 // Upper factors run left-looking: r_k = x[p] - sum_a Upanel(i, a) x[ridx[a]],
-// then x[p] = sum_j Tinv(i, j) r_j.  Inner loops are split into CT / CP chunks
-// whose partial sums meet through atomic adds into cleared scratch.
+// then x[p] = sum_j Tinv(i, j) r_j; r_k starts as x[p], copied one level ahead
+// (rows of later levels keep their input values until their own level).
+// Inner loops are split into CT / CP chunks whose partial sums meet through
+// atomic adds; levels of narrow supernodes use the entry form instead of
+// panels.
 //
 // Records do not depend on x, so each thread's first record of a sweep is
 // loaded before the barrier that precedes the sweep, and the record of its
 // next task while it works on the current one.
-template <typename T, int R>
+template <typename T, int R, bool GX>
 __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift) {
   const DevTriBlock B = A.blk[bi];
   if (B.nlev <= 0) return;
@@ -111,6 +146,10 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
   const T* tri = A.tri + B.tri_base;
   const int32_t* lev_ptr = A.lev_ptr + B.lev_base;
   const int32_t* push_ptr = A.push_ptr + B.lev_base;
+  const int32_t* ent_ptr = A.ent_ptr + B.lev_base;
+  const T* eval = A.eval + B.ent_base;
+  const int32_t* eidx = A.eidx + B.ent_base;
+  const int32_t* eloc = A.eloc + B.ent_base;
   const int32_t* lev_c = A.lev_c + B.lev_base;
   const int4 z4 = make_int4(0, 0, 0, 0);
   T* const Rh0 = Rb;
@@ -131,6 +170,9 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
     const int cnt = lev_ptr[l + 1] - b;
     int CT, CP;
     level_chunks(lev_c[l], gshift, CT, CP);
+    // entry form for FP64 single right-hand sides in LDS (one atomic add per
+    // entry; in FP32 the two indices per value cost more than they save)
+    const bool ent = sizeof(T) == 8 && R == 1 && !GX && ((lev_c[l] >> 16) & 1);
     T* Rc = (li & 1) ? Rh1 : Rh0;
     T* Rn = (li & 1) ? Rh0 : Rh1;
     int bn = 0, cntn = 0, CTn = 1, CPn = 1;
@@ -140,12 +182,23 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
       cntn = lev_ptr[ln + 1] - bn;
       level_chunks(lev_c[ln], gshift, CTn, CPn);
     }
-    if (li == 0 && (B.lower ? CT : CP) > 1) {
-      for (int e = tid; e < cnt * R; e += nthr) Rc[e] = (T)0;
-      __syncthreads();
+    if (li == 0) {
+      if (B.lower) {
+        if (CT > 1) {
+          for (int e = tid; e < cnt * R; e += nthr) Rc[e] = (T)0;
+          __syncthreads();
+        }
+      } else {
+        for (int k = tid; k < cnt; k += nthr) {
+          const int p = k == tid ? f0.x : rec[2 * (b + k)].x;
+#pragma unroll
+          for (int r = 0; r < R; ++r) Rc[k * R + r] = X[p * R + r];
+        }
+        __syncthreads();
+      }
     }
     if (B.lower) {
-      const int pb = push_ptr[l], np = push_ptr[l + 1] - pb;
+      const int pb = push_ptr[l], np = ent ? 0 : push_ptr[l + 1] - pb;
       int4 fq = np > 0 ? prec[pb + tid % np] : z4;
       // s_k = Tinv(i, 0..i) x[f .. f+i]
       {
@@ -185,6 +238,7 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
         for (int r = 0; r < R; ++r) X[p * R + r] = Rc[k * R + r];
       }
       // x[ridx[a]] -= Lpanel(a, :) s
+      if (ent) entry_sweep<T, R>(eval, eidx, eloc, ent_ptr[l], ent_ptr[l + 1], X, Rc, true);
       {
         int4 q = fq;
         for (int t = tid; t < np * CP; t += nthr) {
@@ -216,7 +270,7 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
       // r_k = x[p] - Upanel(i, :) x[ridx]
       {
         int4 r0 = f0, r1 = f1;
-        for (int t = tid; t < cnt * CP; t += nthr) {
+        for (int t = tid; t < (ent ? 0 : cnt * CP); t += nthr) {
           const int tn = t + nthr;
           int4 n0 = z4, n1 = z4;
           if (tn < cnt * CP) {
@@ -224,7 +278,7 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
             n1 = rec[2 * (b + tn % cnt) + 1];
           }
           const int c = t / cnt, k = t - c * cnt;
-          const int p = r0.x, i = r0.y, w = r0.z, h = r0.w;
+          const int i = r0.y, w = r0.z, h = r0.w;
           const int Lc = (h + CP - 1) / CP;
           const int a0 = c * Lc, a1 = min(h, a0 + Lc);
           const T* pc = pan + r1.y + i;
@@ -255,27 +309,23 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
           }
           if (CP == 1) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-              Rc[k * R + r] = X[p * R + r] - acc[r];
-              if (CT > 1) X[p * R + r] = (T)0;
-            }
-          } else {
+            for (int r = 0; r < R; ++r) Rc[k * R + r] -= acc[r];
+          } else if (a0 < a1) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-              T v = -acc[r];
-              if (c == 0) {
-                v += X[p * R + r];
-                if (CT > 1) X[p * R + r] = (T)0;
-              }
-              if (c == 0 || a0 < a1) atomic_add(&Rc[k * R + r], v);
-            }
+            for (int r = 0; r < R; ++r) atomic_add(&Rc[k * R + r], -acc[r]);
           }
           r0 = n0;
           r1 = n1;
         }
       }
-      if (CPn > 1)
-        for (int e = tid; e < cntn * R; e += nthr) Rn[e] = (T)0;
+      if (ent) entry_sweep<T, R>(eval, eidx, eloc, ent_ptr[l], ent_ptr[l + 1], Rc, X, false);
+      // rows whose triangle products are chunked accumulate into x[p]
+      if (CT > 1)
+        for (int k = tid; k < cnt; k += nthr) {
+          const int p = k == tid ? f0.x : rec[2 * (b + k)].x;
+#pragma unroll
+          for (int r = 0; r < R; ++r) X[p * R + r] = (T)0;
+        }
       __syncthreads();
       // x[p] = Tinv(i, i..w-1) r
       {
@@ -311,6 +361,12 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
       if (cntn > 0) {
         f0 = rec[2 * (bn + tid % cntn)];
         f1 = rec[2 * (bn + tid % cntn) + 1];
+      }
+      // r of the next level starts as its rows' (untouched) x values
+      for (int k = tid; k < cntn; k += nthr) {
+        const int p = k == tid ? f0.x : rec[2 * (bn + k)].x;
+#pragma unroll
+        for (int r = 0; r < R; ++r) Rn[k * R + r] = X[p * R + r];
       }
       __syncthreads();
     }
@@ -377,8 +433,8 @@ __global__ void __launch_bounds__(1024) k_head(ApplyArrays<T> A, int nrhs, const
     L.XB[e] = r < nr ? (T)b[(r0 + r) * ldb + A.gB_in[i0 + p]] : (T)0;
   }
   __syncthreads();
-  tri_solve<T, R>(A.LB, i, L.XB, L.Rb, A.gshift);
-  tri_solve<T, R>(A.UB, i, L.XB, L.Rb, A.gshift);
+  tri_solve<T, R, GX>(A.LB, i, L.XB, L.Rb, A.gshift);
+  tri_solve<T, R, GX>(A.UB, i, L.XB, L.Rb, A.gshift);
   for (int64_t k = tid; k < qi; k += nt) {
     const int64_t row = f0 + k;
     T acc[R];
@@ -478,8 +534,8 @@ __global__ void __launch_bounds__(1024) k_lr_expand(ApplyArrays<T> A, int nrhs, 
   }
   if (!do_c0) return;
   __syncthreads();
-  tri_solve<T, R>(A.LC, i, L.XC, L.Rb, A.gshift);
-  tri_solve<T, R>(A.UC, i, L.XC, L.Rb, A.gshift);
+  tri_solve<T, R, GX>(A.LC, i, L.XC, L.Rb, A.gshift);
+  tri_solve<T, R, GX>(A.UC, i, L.XC, L.Rb, A.gshift);
   for (int64_t e = tid; e < qi * R; e += nt) {
     const int64_t c = e / R;
     const int r = (int)(e - c * R);
@@ -502,8 +558,8 @@ __global__ void __launch_bounds__(1024) k_c0solve(ApplyArrays<T> A, int nrhs, co
     L.XC[e] = r < nr ? src[(r0 + r) * lds_ + f0 + A.gC_in[f0 + p]] : (T)0;
   }
   __syncthreads();
-  tri_solve<T, R>(A.LC, i, L.XC, L.Rb, A.gshift);
-  tri_solve<T, R>(A.UC, i, L.XC, L.Rb, A.gshift);
+  tri_solve<T, R, GX>(A.LC, i, L.XC, L.Rb, A.gshift);
+  tri_solve<T, R, GX>(A.UC, i, L.XC, L.Rb, A.gshift);
   for (int64_t e = tid; e < qi * R; e += nt) {
     const int64_t c = e / R;
     const int r = (int)(e - c * R);
@@ -544,8 +600,8 @@ __global__ void __launch_bounds__(1024) k_series(ApplyArrays<T> A, int nrhs, con
     for (int r = 0; r < R; ++r) L.XB[p * R + r] = acc[r];
   }
   __syncthreads();
-  tri_solve<T, R>(A.LB, i, L.XB, L.Rb, A.gshift);
-  tri_solve<T, R>(A.UB, i, L.XB, L.Rb, A.gshift);
+  tri_solve<T, R, GX>(A.LB, i, L.XB, L.Rb, A.gshift);
+  tri_solve<T, R, GX>(A.UB, i, L.XB, L.Rb, A.gshift);
   for (int64_t kk = tid; kk < qi; kk += nt) {
     const int64_t row = f0 + kk;
     T acc[R];
@@ -576,8 +632,8 @@ __global__ void __launch_bounds__(1024) k_series(ApplyArrays<T> A, int nrhs, con
   }
   if (!do_c0) return;
   __syncthreads();
-  tri_solve<T, R>(A.LC, i, L.XC, L.Rb, A.gshift);
-  tri_solve<T, R>(A.UC, i, L.XC, L.Rb, A.gshift);
+  tri_solve<T, R, GX>(A.LC, i, L.XC, L.Rb, A.gshift);
+  tri_solve<T, R, GX>(A.UC, i, L.XC, L.Rb, A.gshift);
   for (int64_t e = tid; e < qi * R; e += nt) {
     const int64_t c = e / R;
     const int r = (int)(e - c * R);
@@ -619,8 +675,8 @@ __global__ void __launch_bounds__(1024) k_tail(ApplyArrays<T> A, int nrhs, const
     for (int r = 0; r < R; ++r) L.XB[p * R + r] = acc[r];
   }
   __syncthreads();
-  tri_solve<T, R>(A.LB, i, L.XB, L.Rb, A.gshift);
-  tri_solve<T, R>(A.UB, i, L.XB, L.Rb, A.gshift);
+  tri_solve<T, R, GX>(A.LB, i, L.XB, L.Rb, A.gshift);
+  tri_solve<T, R, GX>(A.UB, i, L.XB, L.Rb, A.gshift);
   for (int64_t e = tid; e < pi * R; e += nt) {
     const int64_t c = e / R;
     const int r = (int)(e - c * R);
