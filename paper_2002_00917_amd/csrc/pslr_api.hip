@@ -871,7 +871,7 @@ pslr_status arnoldi(pslr_ctx* h, const double* v0host, uint64_t seed, hipStream_
   return upload_lowrank(h);
 }
 
-// Pick the workgroup size and the lane-group scaling of the triangular solves by
+// Pick the workgroup size and the chunk-count scaling of the triangular solves by
 // timing applies (one right-hand side, HIP events) over a small grid of choices.
 pslr_status autotune(pslr_ctx* h, hipStream_t s) {
   const int64_t n = h->R.n;

@@ -67,7 +67,7 @@ struct ApplyArrays {
   DevCsr<T> Cg;               // rows/cols = global interface
   const int32_t* part_sys;    // nparts: system (batched handles) owning each subdomain
   int32_t maxPB, maxQB, maxLR;
-  int32_t gshift;             // lane-group widths are scaled by 2^gshift (autotuned)
+  int32_t gshift;             // per-level chunk counts are scaled by 2^gshift (autotuned)
   // global working vectors (used instead of LDS when a subdomain does not fit)
   void* gws;                  // null: working vectors in LDS
   int64_t gws_stride;         // elements per right-hand side

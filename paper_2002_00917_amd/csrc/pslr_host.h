@@ -59,7 +59,7 @@ struct TriHost {
 constexpr int kSolveThreads = 1024;
 // Levels whose supernodes average fewer rows than this store their
 // off-diagonal part as entries rather than panels.
-constexpr int kNarrowWidth = 8;
+constexpr int kNarrowWidth = 24;
 
 // Device layout of one packed triangular factor of one block.  All data is
 // stored level by level, so every level reads one contiguous stretch of each

@@ -1,17 +1,16 @@
-// HIP kernels of the PSLR preconditioner apply (paper Algorithm 3) and of the
-// FP64 vector work of Arnoldi (Algorithm 4) and flexible GMRES, for gfx950.
+// HIP kernels of the PSLR preconditioner apply (paper Algorithm 3), for gfx950.
 //
-// Design: one workgroup owns one subdomain (and one right-hand side) and keeps
-// that subdomain's working vectors in LDS.  The B_i and C_i solves are
-// level-scheduled over the supernodal elimination tree of an exact LU
-// factorisation: each level is (1) a sweep of independent dot products that
-// pulls the already-solved unknowns (CSR rows for lower factors, dense panels
-// over a shared column list for upper factors) and (2) a sweep of dense
-// products with the level's inverted diagonal triangles.  Both sweeps stream
-// the factor entries from HBM exactly once, coalesced, with lane groups sized
-// per level to the average row length; gathers hit LDS only.  The coupling
-// SpMVs with E, F and C_g are fused into the kernels that produce or consume
-// their operands, so one power-series step of eq. approx1 is one launch.
+// Design: one workgroup owns one subdomain and one tile of right-hand sides
+// and keeps that subdomain's working vectors in LDS (or, when they do not fit,
+// in a global workspace).  The B_i and C_i solves are level-scheduled over the
+// supernodal elimination tree of an exact LU factorisation; every level is two
+// sweeps of lane-per-row dense products: L right-looking (inverted diagonal
+// triangles, then column panels pushed into the ancestor rows), U left-looking
+// (row panels pulled from the ancestor rows, then the inverted triangles).
+// Factor data streams from HBM once, coalesced; vector operands are LDS
+// broadcasts.  The coupling SpMVs with E, F and C_g are fused into the kernels
+// that produce or consume their operands, so one power-series step of
+// eq. approx1 is one launch.
 #include "pslr_dev.h"
 
 namespace pslr {
