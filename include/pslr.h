@@ -158,11 +158,13 @@ pslr_status pslr_sddmm_grad(pslr_handle h, int32_t nrhs, const double* lambda, i
 pslr_status pslr_info(pslr_handle h, pslr_info_t* out);
 
 /* Phase timers of the apply.  While enabled, every apply records HIP events on
- * its stream before and after each of its kernel launches; pslr_trace_read
- * waits for the recorded events and returns the summed elapsed times per
- * phase (head: B^{-1} f and g - F t; lowrank: V G V^T and the C0 solve it is
- * fused with or the plain C0 solve; series: each power-series step launch;
- * tail: x = B^{-1}(f - E u) and the scatter).  reset != 0 clears the sums. */
+ * its stream between its kernel launches, and each power-series step launch
+ * stamps events at its own start and end; pslr_trace_read waits for the
+ * recorded events and returns the summed elapsed times per phase (head:
+ * B^{-1} f and g - F t; lowrank: V G V^T and the C0 solve it is fused with or
+ * the plain C0 solve; series: the execution time of each power-series step
+ * kernel, launch gaps excluded; tail: x = B^{-1}(f - E u) and the scatter).
+ * reset != 0 clears the sums. */
 typedef struct {
   int64_t applies;
   int64_t series_launches;

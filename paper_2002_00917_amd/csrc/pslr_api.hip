@@ -463,7 +463,8 @@ hipError_t lowrank_expand<float>(pslr_ctx* h, const ApplyArrays<float>& A, const
                                         h->d_sys_chunk, y, ldy, do_c0, u, ldu);
 }
 
-enum { PH_START = -1, PH_HEAD = 0, PH_LOWRANK = 1, PH_SERIES = 2, PH_TAIL = 3 };
+// PH_GAP ends the interval before a kernel-stamped span (not attributed)
+enum { PH_START = -1, PH_HEAD = 0, PH_LOWRANK = 1, PH_SERIES = 2, PH_TAIL = 3, PH_GAP = 4 };
 
 // Sum the elapsed times of completed traced applies (all of them if wait).
 hipError_t trace_collect(pslr_ctx* h, bool wait) {
@@ -511,6 +512,27 @@ struct Tracer {
     }
     marks.push_back({phase, e});
     return hipEventRecord(e, s);
+  }
+  // Events for a launch that stamps its own start and end: the interval up to
+  // the start is not attributed, the kernel's duration goes to `phase`.
+  hipError_t span(int phase, LaunchCfg& c) {
+    if (!h->trace) return hipSuccess;
+    hipEvent_t e[2];
+    for (hipEvent_t& x : e) {
+      if (!h->ev_free.empty()) {
+        x = h->ev_free.back();
+        h->ev_free.pop_back();
+      } else {
+        hipError_t r = hipEventCreate(&x);
+        if (r != hipSuccess) return r;
+        h->ev_all.push_back(x);
+      }
+    }
+    marks.push_back({PH_GAP, e[0]});
+    marks.push_back({phase, e[1]});
+    c.ev_start = e[0];
+    c.ev_stop = e[1];
+    return hipSuccess;
   }
   hipError_t finish() {
     if (!h->trace) return hipSuccess;
@@ -604,16 +626,18 @@ pslr_status run_apply(pslr_ctx* h, const ApplyArrays<T>& Ah, size_t lds, bool tr
     }
     HIP_TRY(tr.mark(PH_LOWRANK));
     for (int i = 0; i < h->m; ++i) {
-      HIP_TRY(launch_series<T>(A, cfg, nrhs, y, q, ua, ub, q, 1, 1));
-      HIP_TRY(tr.mark(PH_SERIES));
+      LaunchCfg c1 = cfg;
+      HIP_TRY(tr.span(PH_SERIES, c1));
+      HIP_TRY(launch_series<T>(A, c1, nrhs, y, q, ua, ub, q, 1, 1));
       std::swap(ua, ub);
     }
   } else {
     HIP_TRY(launch_c0solve<T>(A, cfg, nrhs, y, q, ua, q));
     HIP_TRY(tr.mark(PH_LOWRANK));
     for (int i = 0; i < h->m; ++i) {
-      HIP_TRY(launch_series<T>(A, cfg, nrhs, y, q, ua, ub, q, 1, 1));
-      HIP_TRY(tr.mark(PH_SERIES));
+      LaunchCfg c1 = cfg;
+      HIP_TRY(tr.span(PH_SERIES, c1));
+      HIP_TRY(launch_series<T>(A, c1, nrhs, y, q, ua, ub, q, 1, 1));
       std::swap(ua, ub);
     }
     if (k > 0) {

@@ -105,6 +105,9 @@ struct LaunchCfg {
   hipStream_t stream;
   int R;               // right-hand sides per workgroup tile: 1, 2, 4 or 8
   bool gx;             // working vectors in the global workspace
+  // optional events stamped at the start and end of the kernel itself
+  // (launch_series only; used by the phase tracer)
+  hipEvent_t ev_start = nullptr, ev_stop = nullptr;
 };
 
 // ---- preconditioner kernels (T = double or float; TV = V's storage type)

@@ -13,6 +13,8 @@
 // eq. approx1 is one launch.
 #include "pslr_dev.h"
 
+#include <hip/hip_ext.h>
+
 namespace pslr {
 
 namespace {
@@ -779,12 +781,20 @@ hipError_t launch_series(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, 
                          int64_t ldy, const T* uprev, T* unext, int64_t ldu, int add_y, int do_c0) {
   PSLR_DISPATCH(c, {
     const dim3 grid(A.nparts, ntiles(nrhs, RR));
-    if (c.gx)
+    if (c.ev_start || c.ev_stop) {
+      if (c.gx)
+        hipExtLaunchKernelGGL((k_series<T, RR, true>), grid, dim3(c.threads), 0, c.stream, c.ev_start,
+                              c.ev_stop, 0, A, nrhs, y, ldy, uprev, unext, ldu, add_y, do_c0);
+      else
+        hipExtLaunchKernelGGL((k_series<T, RR, false>), grid, dim3(c.threads), (uint32_t)c.lds, c.stream,
+                              c.ev_start, c.ev_stop, 0, A, nrhs, y, ldy, uprev, unext, ldu, add_y, do_c0);
+    } else if (c.gx) {
       hipLaunchKernelGGL((k_series<T, RR, true>), grid, dim3(c.threads), 0, c.stream, A, nrhs, y, ldy,
                          uprev, unext, ldu, add_y, do_c0);
-    else
+    } else {
       hipLaunchKernelGGL((k_series<T, RR, false>), grid, dim3(c.threads), c.lds, c.stream, A, nrhs, y,
                          ldy, uprev, unext, ldu, add_y, do_c0);
+    }
   });
   return hipGetLastError();
 }
