@@ -429,16 +429,16 @@ hipError_t lowrank_partial(pslr_ctx* h, const T* y, int64_t ldy, int nrhs, T* pa
 template <>
 hipError_t lowrank_partial<double>(pslr_ctx* h, const double* y, int64_t ldy, int nrhs, double* part,
                                    hipStream_t s) {
-  return launch_lr_partial<double, double>(h->nchunk_lr, h->d_chunks, h->k, h->V64, y, ldy, nrhs,
+  return launch_lr_partial<double, double>(h->nchunk_lr, h->d_chunks, h->k, h->V64, h->R.q, y, ldy, nrhs,
                                            part, h->cur_active, h->nsys, s);
 }
 template <>
 hipError_t lowrank_partial<float>(pslr_ctx* h, const float* y, int64_t ldy, int nrhs, float* part,
                                   hipStream_t s) {
   if (h->Vbf)
-    return launch_lr_partial<float, __hip_bfloat16>(h->nchunk_lr, h->d_chunks, h->k, h->Vbf, y, ldy,
+    return launch_lr_partial<float, __hip_bfloat16>(h->nchunk_lr, h->d_chunks, h->k, h->Vbf, h->R.q, y, ldy,
                                                     nrhs, part, h->cur_active, h->nsys, s);
-  return launch_lr_partial<float, float>(h->nchunk_lr, h->d_chunks, h->k, h->V32, y, ldy, nrhs, part,
+  return launch_lr_partial<float, float>(h->nchunk_lr, h->d_chunks, h->k, h->V32, h->R.q, y, ldy, nrhs, part,
                                          h->cur_active, h->nsys, s);
 }
 template <typename T>
@@ -726,25 +726,19 @@ pslr_status upload_lowrank(pslr_ctx* h) {
     for (int i = 0; i < ks; ++i)
       for (int j = 0; j < ks; ++j) h->hG[(size_t)s * k * k + (size_t)i * k + j] = Gs[(size_t)i * ks + j];
   }
+  // V is kept column-major (column j at V + j*q), as the Arnoldi process builds it
   if (h->precision == 0) {
-    std::vector<double> Vr((size_t)q * k);
-    for (int64_t r = 0; r < q; ++r)
-      for (int j = 0; j < k; ++j) Vr[(size_t)r * k + j] = h->hV[(size_t)j * q + r];
-    HIP_TRY(h->vpool.upload(Vr, &h->V64));
+    HIP_TRY(h->vpool.upload(h->hV, &h->V64));
     HIP_TRY(h->vpool.upload(h->hG, &h->G64));
   } else {
     std::vector<float> G32(h->hG.begin(), h->hG.end());
     HIP_TRY(h->vpool.upload(G32, &h->G32));
     if (h->precision == 2) {
       std::vector<__hip_bfloat16> Vr((size_t)q * k);
-      for (int64_t r = 0; r < q; ++r)
-        for (int j = 0; j < k; ++j)
-          Vr[(size_t)r * k + j] = __float2bfloat16((float)h->hV[(size_t)j * q + r]);
+      for (size_t e = 0; e < Vr.size(); ++e) Vr[e] = __float2bfloat16((float)h->hV[e]);
       HIP_TRY(h->vpool.upload(Vr, &h->Vbf));
     } else {
-      std::vector<float> Vr((size_t)q * k);
-      for (int64_t r = 0; r < q; ++r)
-        for (int j = 0; j < k; ++j) Vr[(size_t)r * k + j] = (float)h->hV[(size_t)j * q + r];
+      std::vector<float> Vr(h->hV.begin(), h->hV.end());
       HIP_TRY(h->vpool.upload(Vr, &h->V32));
     }
   }
@@ -1322,7 +1316,7 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
       const int64_t q0 = h->sys_q[s], qs = h->sys_q[s + 1] - q0;
       if (qs > 0) {
         const int64_t c = std::max<int64_t>(1, (int64_t)std::llround((double)h->nchunk * qs / qtot));
-        const int64_t rows = (qs + c - 1) / c;
+        const int64_t rows = std::min<int64_t>((qs + c - 1) / c, kLrChunkRows);
         for (int64_t r0 = 0; r0 < qs; r0 += rows)
           ch.push_back(LrChunk{q0 + r0, q0 + std::min(qs, r0 + rows), s, 0});
       }

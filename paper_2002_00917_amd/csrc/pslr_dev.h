@@ -85,6 +85,8 @@ struct LrChunk {
   int64_t r0, r1;
   int32_t sys, pad;
 };
+// longest row chunk of the V^T y partial sums (8 rows per thread at 256 threads)
+constexpr int64_t kLrChunkRows = 2048;
 
 // One column of a segmented vector operation: elements [base, base + len).
 struct Seg {
@@ -115,9 +117,10 @@ template <typename T>
 hipError_t launch_head(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, const double* b,
                        int64_t ldb, T* y, int64_t ldy);
 template <typename T, typename TV>
-hipError_t launch_lr_partial(int nchunk, const LrChunk* chunks, int k, const TV* V, const T* y,
-                             int64_t ldy, int nrhs, T* partial, const uint8_t* active, int nsys,
-                             hipStream_t s);
+// V is column-major (column j at V + j*ldv); chunks hold at most kLrChunkRows rows
+hipError_t launch_lr_partial(int nchunk, const LrChunk* chunks, int k, const TV* V, int64_t ldv,
+                             const T* y, int64_t ldy, int nrhs, T* partial, const uint8_t* active,
+                             int nsys, hipStream_t s);
 // G holds one k x k row-major matrix per system; block i uses system part_sys[i]
 // and the partial sums of chunks sys_chunk[s] .. sys_chunk[s+1].
 template <typename T, typename TV>

@@ -453,29 +453,64 @@ __global__ void __launch_bounds__(1024) k_head(ApplyArrays<T> A, int nrhs, const
   }
 }
 
-// partial[chunk][r][j] = sum_{rows in chunk} V[row][j] y_r[row]   (V^T y, line 3)
+template <typename T>
+__device__ __forceinline__ T wave_reduce(T v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// partial[(chunk * nrhs + r) * k + j] = sum over the chunk's rows of V[j][row] y_r[row]
+// (V^T y, Algorithm 3 line 3).  V is column-major; each thread keeps its rows
+// of y in registers and walks the columns four at a time.
+constexpr int kLrThreads = 256, kLrRows = (int)(kLrChunkRows / kLrThreads);
+
 template <typename T, typename TV>
-__global__ void k_lr_partial(const LrChunk* __restrict__ chunks, int k, const TV* __restrict__ V,
-                             const T* __restrict__ y, int64_t ldy, T* partial,
-                             const uint8_t* __restrict__ active, int nsys) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  T* red = reinterpret_cast<T*>(smem);
-  const int chunk = blockIdx.x, r = blockIdx.y, tid = threadIdx.x, nt = blockDim.x;
+__global__ void __launch_bounds__(kLrThreads)
+k_lr_partial(const LrChunk* __restrict__ chunks, int k, const TV* __restrict__ V, int64_t ldv,
+             const T* __restrict__ y, int64_t ldy, T* partial, const uint8_t* __restrict__ active,
+             int nsys) {
+  __shared__ T red[kLrThreads / 64][64];
+  const int chunk = blockIdx.x, r = blockIdx.y, tid = threadIdx.x, wave = tid >> 6;
   const LrChunk C = chunks[chunk];
   if (active && !active[r * nsys + C.sys]) return;
-  const int ng = nt / k;
-  const int g = tid / k, j = tid - g * k;
-  T acc = 0;
-  if (g < ng) {
-    const T* yr = y + r * ldy;
-    for (int64_t row = C.r0 + g; row < C.r1; row += ng) acc += (T)tv_to_float(V[row * k + j]) * yr[row];
-    red[g * k + j] = acc;
+  const int64_t nrow = C.r1 - C.r0;
+  T yr[kLrRows];
+#pragma unroll
+  for (int t = 0; t < kLrRows; ++t) {
+    const int64_t row = tid + (int64_t)t * kLrThreads;
+    yr[t] = row < nrow ? y[r * ldy + C.r0 + row] : (T)0;
   }
-  __syncthreads();
-  if (tid < k) {
-    T s = 0;
-    for (int gg = 0; gg < ng; ++gg) s += red[gg * k + tid];
-    partial[((int64_t)chunk * gridDim.y + r) * k + tid] = s;
+  const TV* vb = V + C.r0;
+  for (int j0 = 0; j0 < k; j0 += 64) {
+    const int nj = min(64, k - j0);
+    for (int jj = 0; jj < nj; jj += 4) {
+      T acc[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        acc[u] = 0;
+        if (jj + u < nj) {
+          const TV* vj = vb + (int64_t)(j0 + jj + u) * ldv;
+#pragma unroll
+          for (int t = 0; t < kLrRows; ++t) {
+            const int64_t row = tid + (int64_t)t * kLrThreads;
+            if (row < nrow) acc[u] += (T)tv_to_float(vj[row]) * yr[t];
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const T v = wave_reduce(acc[u]);
+        if ((tid & 63) == 0 && jj + u < nj) red[wave][jj + u] = v;
+      }
+    }
+    __syncthreads();
+    if (tid < nj) {
+      T s = 0;
+#pragma unroll
+      for (int w = 0; w < kLrThreads / 64; ++w) s += red[w][tid];
+      partial[((int64_t)chunk * gridDim.y + r) * k + j0 + tid] = s;
+    }
+    __syncthreads();
   }
 }
 
@@ -510,27 +545,36 @@ __global__ void __launch_bounds__(1024) k_lr_expand(ApplyArrays<T> A, int nrhs, 
     Zv[e] = s;
   }
   __syncthreads();
-  const int GL = k >= 64 ? 64 : (k >= 32 ? 32 : (k >= 16 ? 16 : (k >= 8 ? 8 : (k >= 4 ? 4 : (k >= 2 ? 2 : 1)))));
-  const int grp = tid / GL, lane = tid - grp * GL, ngrp = nt / GL;
-  for (int64_t kr = grp; kr < qi; kr += ngrp) {
+  // lane per interface row: acc = V[row, :] . Z with V column-major, Z broadcast from LDS
+  const int64_t ldv = A.q;
+  for (int64_t kr = tid; kr < qi; kr += nt) {
     const int64_t row = f0 + kr;
+    const TV* vr = V + row;
     T acc[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[r] = 0;
-    for (int j = lane; j < k; j += GL) {
-      const T v = (T)tv_to_float(V[row * k + j]);
+    constexpr int U = 8;
+    int j = 0;
+    for (; j + U <= k; j += U) {
+      T v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = (T)tv_to_float(vr[(int64_t)(j + u) * ldv]);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] += v[u] * Zv[(j + u) * R + r];
+    }
+    for (; j < k; ++j) {
+      const T v = (T)tv_to_float(vr[(int64_t)j * ldv]);
 #pragma unroll
       for (int r = 0; r < R; ++r) acc[r] += v * Zv[j * R + r];
     }
-    group_sum_r<T, R>(acc, GL);
-    if (lane == 0) {
-      const int64_t pos = A.gC_inv[row];
+    const int64_t pos = A.gC_inv[row];
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const T v = r < nr ? y[(r0 + r) * ldy + row] + acc[r] : (T)0;
-        if (r < nr) y[(r0 + r) * ldy + row] = v;
-        if (do_c0) L.XC[pos * R + r] = v;
-      }
+    for (int r = 0; r < R; ++r) {
+      const T v = r < nr ? y[(r0 + r) * ldy + row] + acc[r] : (T)0;
+      if (r < nr) y[(r0 + r) * ldy + row] = v;
+      if (do_c0) L.XC[pos * R + r] = v;
     }
   }
   if (!do_c0) return;
@@ -737,13 +781,12 @@ hipError_t launch_head(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, co
 }
 
 template <typename T, typename TV>
-hipError_t launch_lr_partial(int nchunk, const LrChunk* chunks, int k, const TV* V, const T* y,
-                             int64_t ldy, int nrhs, T* partial, const uint8_t* active, int nsys,
-                             hipStream_t s) {
-  const int threads = 256;
-  size_t lds = sizeof(T) * threads;
-  hipLaunchKernelGGL((k_lr_partial<T, TV>), dim3(nchunk, nrhs), dim3(threads), lds, s, chunks, k, V,
-                     y, ldy, partial, active, nsys);
+hipError_t launch_lr_partial(int nchunk, const LrChunk* chunks, int k, const TV* V, int64_t ldv,
+                             const T* y, int64_t ldy, int nrhs, T* partial, const uint8_t* active,
+                             int nsys, hipStream_t s) {
+  if (nchunk <= 0 || k <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_lr_partial<T, TV>), dim3(nchunk, nrhs), dim3(kLrThreads), 0, s, chunks, k, V,
+                     ldv, y, ldy, partial, active, nsys);
   return hipGetLastError();
 }
 
@@ -829,15 +872,15 @@ PSLR_INST(double)
 PSLR_INST(float)
 
 template hipError_t launch_lr_partial<double, double>(int, const LrChunk*, int, const double*,
-                                                      const double*, int64_t, int, double*,
+                                                      int64_t, const double*, int64_t, int, double*,
                                                       const uint8_t*, int, hipStream_t);
-template hipError_t launch_lr_partial<float, float>(int, const LrChunk*, int, const float*,
+template hipError_t launch_lr_partial<float, float>(int, const LrChunk*, int, const float*, int64_t,
                                                     const float*, int64_t, int, float*,
                                                     const uint8_t*, int, hipStream_t);
 template hipError_t launch_lr_partial<float, __hip_bfloat16>(int, const LrChunk*, int,
-                                                             const __hip_bfloat16*, const float*,
-                                                             int64_t, int, float*, const uint8_t*,
-                                                             int, hipStream_t);
+                                                             const __hip_bfloat16*, int64_t,
+                                                             const float*, int64_t, int, float*,
+                                                             const uint8_t*, int, hipStream_t);
 template hipError_t launch_lr_expand<double, double>(const ApplyArrays<double>&, const LaunchCfg&,
                                                      int, int, const double*, const double*, int,
                                                      const double*, int, const int32_t*, double*,
