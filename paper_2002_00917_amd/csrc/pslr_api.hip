@@ -571,6 +571,8 @@ int64_t count_chunks(const std::vector<Seg>& cols, int64_t rows) {
   return std::max<int64_t>(t, 1);
 }
 
+constexpr size_t kLrStaticLds = 8192;
+
 // Right-hand-side tile width and working-vector placement of an apply: LDS with
 // the widest tile that fits, unless several right-hand sides would then be
 // solved one or two at a time (each tile re-reads every factor entry), in
@@ -583,7 +585,8 @@ LaunchCfg choose_launch(pslr_ctx* h, const ApplyArrays<T>& A, int nrhs, hipStrea
   int Rl = 0;
   if (!h->gx)
     for (int R = want; R >= 1; R /= 2)
-      if (lds_bytes(A, A.kmax, R) <= h->lds_max) {
+      // 8 KB stay free for k_lr_expand's static slice sums
+      if (lds_bytes(A, A.kmax, R) + kLrStaticLds <= h->lds_max) {
         Rl = R;
         break;
       }

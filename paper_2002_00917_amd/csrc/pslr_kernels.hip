@@ -514,6 +514,10 @@ k_lr_partial(const LrChunk* __restrict__ chunks, int k, const TV* __restrict__ V
   }
 }
 
+// LDS slots k_lr_expand uses for its slice sums (static, on top of the dynamic
+// working vectors; the launch configuration leaves room for them)
+constexpr int kLrSlots = 1024;
+
 // y += V (G (V^T y)) on the rows of block i; optionally u = C0^{-1} y (line 3, line 4 start)
 template <typename T, typename TV, int R, bool GX>
 __global__ void __launch_bounds__(1024) k_lr_expand(ApplyArrays<T> A, int nrhs, int k,
@@ -530,21 +534,46 @@ __global__ void __launch_bounds__(1024) k_lr_expand(ApplyArrays<T> A, int nrhs, 
   const int sys = A.part_sys[i];
   const T* G = Gall + (int64_t)sys * k * k;
   const int c0 = sys_chunk[sys], c1 = sys_chunk[sys + 1];
-  for (int e = tid; e < k * R; e += nt) {
+  // W = V^T y (sum of the system's chunk partials), then Z = G W; both spread
+  // over the workgroup in S slices of the summation range, joined through LDS
+  __shared__ T red[kLrSlots];
+  const int KR = k * R;
+  const int S = KR <= kLrSlots ? min(nt, kLrSlots) / KR : 1;
+  for (int t = tid; t < (S > 1 ? S * KR : KR); t += nt) {
+    const int sl = S > 1 ? t / KR : 0, e = t - sl * KR;
     const int j = e / R, r = e - j * R;
     T s = 0;
     if (r < nr)
-      for (int c = c0; c < c1; ++c) s += partial[((int64_t)c * nrhs + r0 + r) * k + j];
-    Wv[e] = s;
+      for (int c = c0 + sl; c < c1; c += S) s += partial[((int64_t)c * nrhs + r0 + r) * k + j];
+    if (S > 1) red[t] = s;
+    else Wv[e] = s;
   }
   __syncthreads();
-  for (int e = tid; e < k * R; e += nt) {
+  if (S > 1) {
+    for (int e = tid; e < KR; e += nt) {
+      T s = 0;
+      for (int sl = 0; sl < S; ++sl) s += red[sl * KR + e];
+      Wv[e] = s;
+    }
+    __syncthreads();
+  }
+  for (int t = tid; t < (S > 1 ? S * KR : KR); t += nt) {
+    const int sl = S > 1 ? t / KR : 0, e = t - sl * KR;
     const int j = e / R, r = e - j * R;
     T s = 0;
-    for (int l = 0; l < k; ++l) s += (gtrans ? G[(int64_t)l * k + j] : G[(int64_t)j * k + l]) * Wv[l * R + r];
-    Zv[e] = s;
+    for (int l = sl; l < k; l += S) s += (gtrans ? G[(int64_t)l * k + j] : G[(int64_t)j * k + l]) * Wv[l * R + r];
+    if (S > 1) red[t] = s;
+    else Zv[e] = s;
   }
   __syncthreads();
+  if (S > 1) {
+    for (int e = tid; e < KR; e += nt) {
+      T s = 0;
+      for (int sl = 0; sl < S; ++sl) s += red[sl * KR + e];
+      Zv[e] = s;
+    }
+    __syncthreads();
+  }
   // lane per interface row: acc = V[row, :] . Z with V column-major, Z broadcast from LDS
   const int64_t ldv = A.q;
   for (int64_t kr = tid; kr < qi; kr += nt) {
@@ -759,8 +788,8 @@ hipError_t set_lds_limit(size_t bytes) {
   if ((e = hipFuncSetAttribute((const void*)k_c0solve<T, RR, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b))) return e; \
   if ((e = hipFuncSetAttribute((const void*)k_series<T, RR, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b))) return e; \
   if ((e = hipFuncSetAttribute((const void*)k_tail<T, RR, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b))) return e; \
-  if ((e = hipFuncSetAttribute((const void*)k_lr_expand<T, T, RR, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b))) return e; \
-  if ((e = hipFuncSetAttribute((const void*)k_lr_expand<T, __hip_bfloat16, RR, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b))) return e;
+  if ((e = hipFuncSetAttribute((const void*)k_lr_expand<T, T, RR, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b - (int)(kLrSlots * sizeof(T))))) return e; \
+  if ((e = hipFuncSetAttribute((const void*)k_lr_expand<T, __hip_bfloat16, RR, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b - (int)(kLrSlots * sizeof(T))))) return e;
   PSLR_SETATTR(1)
   PSLR_SETATTR(2)
   PSLR_SETATTR(4)
