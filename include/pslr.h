@@ -208,8 +208,9 @@ pslr_status pslr_reorder(int64_t n, const int64_t* rowptr, const int32_t* colind
  * and C_i, then reports the largest relative factorisation residual
  * ||P Q M Q^T - L U||_F / ||M||_F and the largest relative residual of the
  * packed level-scheduled solve layouts executed on the host for a fixed
- * vector (forward, and transposed when want_transpose).  Diagnostic only: no
- * other entry point calls it. */
+ * vector (forward, and transposed when want_transpose; levels of narrow
+ * supernodes once through their entry form and once through their panels).
+ * Diagnostic only: no other entry point calls it. */
 pslr_status pslr_host_selfcheck(int64_t n, const int64_t* rowptr, const int32_t* colind,
                                 const double* vals, const int32_t* part, int32_t nparts,
                                 const pslr_options* opt, double* factor_residual,

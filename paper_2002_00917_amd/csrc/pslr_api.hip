@@ -1142,8 +1142,11 @@ pslr_status pslr_host_selfcheck(int64_t n, const int64_t* rowptr, const int32_t*
     codes[t] = factor_block(M, tau, o.want_transpose != 0, f, errs[t]);
     if (codes[t] || M.nrows == 0) return;
     const int nb = M.nrows;
-    // residual of the solve layouts: x = M^{-1} b with b = M * xe
-    for (int tr = 0; tr < (o.want_transpose ? 2 : 1); ++tr) {
+    // residual of the solve layouts: x = M^{-1} b with b = M * xe, through the
+    // entry form and through the panels of narrow levels
+    for (int pass = 0; pass < 2 * (o.want_transpose ? 2 : 1); ++pass) {
+      const int tr = pass >> 1;
+      const bool entries = (pass & 1) == 0;
       std::vector<double> xe(nb), bb(nb, 0.0), X(nb), x(nb);
       for (int i = 0; i < nb; ++i) xe[i] = std::sin(1.0 + i);
       for (int i = 0; i < nb; ++i)
@@ -1154,8 +1157,8 @@ pslr_status pslr_host_selfcheck(int64_t n, const int64_t* rowptr, const int32_t*
       const std::vector<int32_t>& gi = tr ? f.gout : f.gin;
       const std::vector<int32_t>& go = tr ? f.gin : f.gout;
       for (int pp = 0; pp < nb; ++pp) X[pp] = bb[gi[pp]];
-      host_tri_solve(tr ? f.loT : f.lo, X);
-      host_tri_solve(tr ? f.upT : f.up, X);
+      host_tri_solve(tr ? f.loT : f.lo, X, entries);
+      host_tri_solve(tr ? f.upT : f.up, X, entries);
       for (int c = 0; c < nb; ++c) x[go[c]] = X[c];
       double e2 = 0.0, n2 = 0.0;
       for (int i = 0; i < nb; ++i) {
@@ -1169,8 +1172,8 @@ pslr_status pslr_host_selfcheck(int64_t n, const int64_t* rowptr, const int32_t*
     std::vector<double> xe(nb), bb(nb, 0.0), X(nb), x(nb), rr(nb, 0.0);
     for (int i = 0; i < nb; ++i) bb[i] = std::cos(0.5 + 0.37 * i);
     for (int pp = 0; pp < nb; ++pp) X[pp] = bb[f.gin[pp]];
-    host_tri_solve(f.lo, X);
-    host_tri_solve(f.up, X);
+    host_tri_solve(f.lo, X, true);
+    host_tri_solve(f.up, X, true);
     for (int c = 0; c < nb; ++c) x[f.gout[c]] = X[c];
     double mnorm = 0.0, xn = 0.0, rn = 0.0;
     for (int i = 0; i < nb; ++i) {

@@ -983,12 +983,12 @@ bool pack_tri(const TriHost& T, TriPacked& P) {
 // sequential order
 // ---------------------------------------------------------------------------
 
-void host_tri_solve(const TriPacked& T, std::vector<double>& X) {
+void host_tri_solve(const TriPacked& T, std::vector<double>& X, bool entries) {
   std::vector<double> Rb(std::max(T.max_lrows, 1));
   for (int li = 0; li < T.nlev; ++li) {
     const int l = T.lower ? li : T.nlev - 1 - li;
     const int b = T.lev_ptr[l], e = T.lev_ptr[l + 1];
-    const bool ent = (T.lev_c[l] >> 16) & 1;
+    const bool ent = entries && ((T.lev_c[l] >> 16) & 1);
     if (T.lower) {
       for (int k = b; k < e; ++k) {
         const int32_t* r = &T.rec[(size_t)8 * k];

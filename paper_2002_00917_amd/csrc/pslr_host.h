@@ -158,7 +158,8 @@ void parallel_for(int count, int nthreads, const std::function<void(int)>& fn);
 bool pack_tri(const TriHost& T, TriPacked& P);
 
 // Host execution of a packed factor on one vector (diagnostics only).
-void host_tri_solve(const TriPacked& T, std::vector<double>& X);
+// entries: use the entry form where a level has one (else the panels).
+void host_tri_solve(const TriPacked& T, std::vector<double>& X, bool entries);
 
 uint64_t splitmix64_next(uint64_t& state);
 
