@@ -85,7 +85,7 @@ struct LrChunk {
   int64_t r0, r1;
   int32_t sys, pad;
 };
-// longest row chunk of the V^T y partial sums (8 rows per thread at 256 threads)
+// longest row chunk of the V^T y partial sums (keeps several chunks per system)
 constexpr int64_t kLrChunkRows = 2048;
 
 // One column of a segmented vector operation: elements [base, base + len).

@@ -453,62 +453,48 @@ __global__ void __launch_bounds__(1024) k_head(ApplyArrays<T> A, int nrhs, const
   }
 }
 
-template <typename T>
-__device__ __forceinline__ T wave_reduce(T v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
 // partial[(chunk * nrhs + r) * k + j] = sum over the chunk's rows of V[j][row] y_r[row]
-// (V^T y, Algorithm 3 line 3).  V is column-major; each thread keeps its rows
-// of y in registers and walks the columns four at a time.
-constexpr int kLrThreads = 256, kLrRows = (int)(kLrChunkRows / kLrThreads);
+// (V^T y, Algorithm 3 line 3).  V is column-major.  Tiles of 64 rows x 64
+// columns are staged through LDS (loads coalesced along the rows, rows padded
+// to 65 entries so that column reads are conflict free); thread (g, j) then
+// sums 16 rows of column j, and the four row groups meet in LDS at the end.
+constexpr int kLrThreads = 256, kLrTile = 64;
 
 template <typename T, typename TV>
 __global__ void __launch_bounds__(kLrThreads)
 k_lr_partial(const LrChunk* __restrict__ chunks, int k, const TV* __restrict__ V, int64_t ldv,
              const T* __restrict__ y, int64_t ldy, T* partial, const uint8_t* __restrict__ active,
              int nsys) {
-  __shared__ T red[kLrThreads / 64][64];
-  const int chunk = blockIdx.x, r = blockIdx.y, tid = threadIdx.x, wave = tid >> 6;
+  __shared__ T tile[kLrTile * (kLrTile + 1)];
+  __shared__ T ys[kLrTile];
+  const int chunk = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
   const LrChunk C = chunks[chunk];
   if (active && !active[r * nsys + C.sys]) return;
-  const int64_t nrow = C.r1 - C.r0;
-  T yr[kLrRows];
+  const int jl = tid & (kLrTile - 1), g = tid >> 6;  // column in block, row group (0..3)
+  for (int jb = 0; jb < k; jb += kLrTile) {
+    const int nj = min(kLrTile, k - jb);
+    T acc = 0;
+    for (int64_t t0 = C.r0; t0 < C.r1; t0 += kLrTile) {
+      const int nr = (int)min<int64_t>(kLrTile, C.r1 - t0);
+      // load: lane = row of the tile, 16 columns per thread
 #pragma unroll
-  for (int t = 0; t < kLrRows; ++t) {
-    const int64_t row = tid + (int64_t)t * kLrThreads;
-    yr[t] = row < nrow ? y[r * ldy + C.r0 + row] : (T)0;
-  }
-  const TV* vb = V + C.r0;
-  for (int j0 = 0; j0 < k; j0 += 64) {
-    const int nj = min(64, k - j0);
-    for (int jj = 0; jj < nj; jj += 4) {
-      T acc[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        acc[u] = 0;
-        if (jj + u < nj) {
-          const TV* vj = vb + (int64_t)(j0 + jj + u) * ldv;
-#pragma unroll
-          for (int t = 0; t < kLrRows; ++t) {
-            const int64_t row = tid + (int64_t)t * kLrThreads;
-            if (row < nrow) acc[u] += (T)tv_to_float(vj[row]) * yr[t];
-          }
-        }
+      for (int m = 0; m < kLrTile / 4; ++m) {
+        const int j = g + 4 * m;
+        tile[j * (kLrTile + 1) + jl] =
+            (j < nj && jl < nr) ? (T)tv_to_float(V[(int64_t)(jb + j) * ldv + t0 + jl]) : (T)0;
       }
+      if (tid < kLrTile) ys[tid] = tid < nr ? y[r * ldy + t0 + tid] : (T)0;
+      __syncthreads();
+      const T* tj = tile + jl * (kLrTile + 1) + g * 16;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const T v = wave_reduce(acc[u]);
-        if ((tid & 63) == 0 && jj + u < nj) red[wave][jj + u] = v;
-      }
+      for (int q = 0; q < 16; ++q) acc += tj[q] * ys[g * 16 + q];
+      __syncthreads();
     }
+    tile[g * kLrTile + jl] = acc;
     __syncthreads();
     if (tid < nj) {
-      T s = 0;
-#pragma unroll
-      for (int w = 0; w < kLrThreads / 64; ++w) s += red[w][tid];
-      partial[((int64_t)chunk * gridDim.y + r) * k + j0 + tid] = s;
+      const T s = tile[tid] + tile[kLrTile + tid] + tile[2 * kLrTile + tid] + tile[3 * kLrTile + tid];
+      partial[((int64_t)chunk * gridDim.y + r) * k + jb + tid] = s;
     }
     __syncthreads();
   }
