@@ -224,6 +224,8 @@ struct pslr_ctx {
   int32_t *fcpF = nullptr, *fcpM = nullptr;
   int64_t f_maxch = 0;
   uint8_t* factive = nullptr;
+  double* fpin = nullptr;  // pinned host staging of the Hessenberg columns (two slots)
+  size_t fpin_n = 0;
   const uint8_t* cur_active = nullptr;  // mask of (system, rhs) columns the apply works on
   // info
   pslr_info_t info{};
@@ -234,6 +236,7 @@ struct pslr_ctx {
   pslr_trace_t tr{};
   ~pslr_ctx() {
     for (hipEvent_t e : ev_all) (void)hipEventDestroy(e);
+    if (fpin) (void)hipHostFree(fpin);
   }
 };
 
@@ -1526,6 +1529,22 @@ pslr_status fgmres_solve(pslr_handle h, int32_t nrhs, const double* b, int64_t l
   double* dh2 = dh1 + (size_t)ncol * R1;
   double* dnn = dh2 + (size_t)ncol * R1;
   std::vector<double> hbuf((size_t)ncol * (2 * R1 + 1)), sc(ncol), bn(ncol);
+  const size_t hsz = (size_t)ncol * (2 * R1 + 1);
+  if (h->fpin_n < 2 * hsz) {
+    if (h->fpin) (void)hipHostFree(h->fpin);
+    h->fpin = nullptr;
+    h->fpin_n = 0;
+    HIP_TRY(hipHostMalloc((void**)&h->fpin, sizeof(double) * 2 * hsz, hipHostMallocDefault));
+    h->fpin_n = 2 * hsz;
+  }
+  struct Events {
+    hipEvent_t e[2] = {nullptr, nullptr};
+    ~Events() {
+      for (hipEvent_t x : e)
+        if (x) (void)hipEventDestroy(x);
+    }
+  } hev;
+  for (hipEvent_t& x : hev.e) HIP_TRY(hipEventCreateWithFlags(&x, hipEventDisableTiming));
   // ||b|| per column
   HIP_TRY(launch_mdot_chunk(nchF, h->fchF, cB, cB, 1, b, 0, b, h->fdbuf, s));
   HIP_TRY(launch_reduce_chunk(ncol, h->fcpF, 1, nchF, h->fdbuf, dnn, s));
@@ -1563,16 +1582,20 @@ pslr_status fgmres_solve(pslr_handle h, int32_t nrhs, const double* b, int64_t l
     if (!any) break;
     HIP_TRY(hipMemcpyAsync(h->fscl, sc.data(), sizeof(double) * ncol, hipMemcpyHostToDevice, s));
     HIP_TRY(launch_scale_chunk(nchF, h->fchF, cV, cV, Vb, h->fscl, Vb, s));
-    for (int j = 0; j < restart; ++j) {
+    // Iteration j+1 is enqueued before the host reads iteration j's Hessenberg
+    // column: V_{j+1} is normalised on the device from its norm, the column
+    // travels to pinned host memory behind an event, and the host's Givens
+    // update of column j overlaps the device's iteration j+1.  Convergence is
+    // seen one iteration late; the extra iteration's results are not used.
+    auto enqueue = [&](int j) -> pslr_status {
       double* Vj = Vb + (size_t)j * blk;
       double* Zj = Zb + (size_t)j * blk;
       // converged columns skip the apply and the vector work of this iteration
       bool changed = j == 0;
-      for (int c = 0; c < ncol; ++c) {
-        changed = changed || amask[c] != (act[c] ? 1 : 0);
-        amask[c] = act[c] ? 1 : 0;
-      }
-      if (changed) {  // the previous upload finished at the last synchronisation
+      for (int c = 0; c < ncol; ++c) changed = changed || amask[c] != (act[c] ? 1 : 0);
+      if (changed) {
+        HIP_TRY(hipStreamSynchronize(s));  // earlier uploads may still read these host arrays
+        for (int c = 0; c < ncol; ++c) amask[c] = act[c] ? 1 : 0;
         nchM = make_chunks(vcols, crows, &amask, chM, cpM);
         HIP_TRY(hipMemcpyAsync(h->factive, amask.data(), ncol, hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(h->fchM, chM.data(), sizeof(Chunk) * std::max(nchM, 1),
@@ -1584,7 +1607,7 @@ pslr_status fgmres_solve(pslr_handle h, int32_t nrhs, const double* b, int64_t l
       h->cur_active = nullptr;
       if (st) return st;
       HIP_TRY(launch_spmv(n, Ap, Ac, Av, nrhs, Zj, n, W, n, nullptr, 0, s));
-      // classical Gram-Schmidt, two passes, then ||w||; one host synchronisation
+      // classical Gram-Schmidt, two passes, then ||w|| and V_{j+1} = w / ||w||
       const int nv = j + 1;
       HIP_TRY(launch_mdot_chunk(nchM, h->fchM, cV, cV, nv, Vb, blk, W, h->fdbuf, s));
       HIP_TRY(launch_reduce_chunk(ncol, h->fcpM, nv, nchM, h->fdbuf, dh1, s));
@@ -1594,22 +1617,33 @@ pslr_status fgmres_solve(pslr_handle h, int32_t nrhs, const double* b, int64_t l
       HIP_TRY(launch_maxpy_chunk(nchM, h->fchM, cV, cV, nv, Vb, blk, dh2, nv, W, 1.0, s));
       HIP_TRY(launch_mdot_chunk(nchM, h->fchM, cV, cV, 1, W, 0, W, h->fdbuf, s));
       HIP_TRY(launch_reduce_chunk(ncol, h->fcpM, 1, nchM, h->fdbuf, dnn, s));
-      HIP_TRY(hipMemcpyAsync(hbuf.data(), dh1, sizeof(double) * hbuf.size(), hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipStreamSynchronize(s));
-      const double* h1 = hbuf.data();
+      HIP_TRY(launch_inv_sqrt(ncol, dnn, h->factive, h->fscl, s));
+      HIP_TRY(launch_scale_chunk(nchF, h->fchF, cV, cV, W, h->fscl, Vb + (size_t)(j + 1) * blk, s));
+      double* slot = h->fpin + (size_t)(j & 1) * hsz;
+      HIP_TRY(hipMemcpyAsync(slot, dh1, sizeof(double) * ncol * nv, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipMemcpyAsync(slot + (size_t)ncol * R1, dh2, sizeof(double) * ncol * nv,
+                             hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipMemcpyAsync(slot + (size_t)2 * ncol * R1, dnn, sizeof(double) * ncol,
+                             hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipEventRecord(hev.e[j & 1], s));
+      return PSLR_OK;
+    };
+    if (pslr_status st = enqueue(0)) return st;
+    for (int j = 0; j < restart; ++j) {
+      if (j + 1 < restart)
+        if (pslr_status st = enqueue(j + 1)) return st;
+      HIP_TRY(hipEventSynchronize(hev.e[j & 1]));
+      const int nv = j + 1;
+      const double* h1 = h->fpin + (size_t)(j & 1) * hsz;
       const double* h2 = h1 + (size_t)ncol * R1;
       const double* nn = h2 + (size_t)ncol * R1;
       bool cont = false;
       for (int c = 0; c < ncol; ++c) {
-        if (!act[c]) {
-          sc[c] = 0.0;
-          continue;
-        }
+        if (!act[c]) continue;
         double* Hc = &Hh[((size_t)c * restart + j) * R1];
         for (int i = 0; i <= j; ++i) Hc[i] = h1[(size_t)c * nv + i] + h2[(size_t)c * nv + i];
         const double hn = std::sqrt(nn[c]);
         Hc[j + 1] = hn;
-        sc[c] = hn > 0 ? 1.0 / hn : 0.0;
         double* c_ = &cs[(size_t)c * restart];
         double* s_ = &sn[(size_t)c * restart];
         double* g_ = &g[(size_t)c * R1];
@@ -1631,8 +1665,6 @@ pslr_status fgmres_solve(pslr_handle h, int32_t nrhs, const double* b, int64_t l
         else cont = true;
       }
       if (!cont) break;
-      HIP_TRY(hipMemcpyAsync(h->fscl, sc.data(), sizeof(double) * ncol, hipMemcpyHostToDevice, s));
-      HIP_TRY(launch_scale_chunk(nchF, h->fchF, cV, cV, W, h->fscl, Vb + (size_t)(j + 1) * blk, s));
     }
     // x += Z y
     std::fill(yv.begin(), yv.end(), 0.0);

@@ -181,6 +181,9 @@ hipError_t launch_reduce_chunk(int ncol, const int32_t* cptr, int nv, int nchunk
 hipError_t launch_maxpy_chunk(int nchunk, const Chunk* ch, const Seg* vcols, const Seg* wcols,
                               int nv, const double* V, int64_t ldv, const double* h, int hld,
                               double* W, double sign, hipStream_t s);
+// scl[c] = 1 / sqrt(nn[c]) where active[c] and nn[c] > 0, else 0
+hipError_t launch_inv_sqrt(int ncol, const double* nn, const uint8_t* active, double* scl,
+                           hipStream_t s);
 hipError_t launch_scale_chunk(int nchunk, const Chunk* ch, const Seg* scols, const Seg* dcols,
                               const double* S, const double* scale, double* D, hipStream_t s);
 hipError_t launch_copy_cast_to_f32(int64_t count, const double* src, float* dst, hipStream_t s);

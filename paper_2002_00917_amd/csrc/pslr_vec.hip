@@ -279,6 +279,15 @@ __global__ void k_scale_chunk(const Chunk* __restrict__ ch, const Seg* __restric
   for (int64_t row = C.r0 + threadIdx.x; row < C.r1; row += blockDim.x) D[sd.base + row] = S[ss.base + row] * f;
 }
 
+// scl[c] = 1 / sqrt(nn[c]) for active columns with nn[c] > 0, else 0
+__global__ void k_inv_sqrt(int ncol, const double* __restrict__ nn, const uint8_t* __restrict__ active,
+                           double* scl) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncol) return;
+  const double v = nn[c];
+  scl[c] = (active[c] && v > 0.0) ? 1.0 / sqrt(v) : 0.0;
+}
+
 inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
@@ -305,6 +314,13 @@ hipError_t launch_maxpy_chunk(int nchunk, const Chunk* ch, const Seg* vcols, con
   if (nchunk <= 0 || nv <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_maxpy_chunk, dim3(nchunk), dim3(kChunkThreads), 0, s, ch, vcols, wcols, nv, V,
                      ldv, h, hld, W, sign);
+  return hipGetLastError();
+}
+
+hipError_t launch_inv_sqrt(int ncol, const double* nn, const uint8_t* active, double* scl,
+                           hipStream_t s) {
+  if (ncol <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_inv_sqrt, dim3(nblk(ncol, 256)), dim3(256), 0, s, ncol, nn, active, scl);
   return hipGetLastError();
 }
 
