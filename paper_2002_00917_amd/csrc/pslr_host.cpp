@@ -445,6 +445,10 @@ void build_levels(TriHost& T, const std::vector<int>& sfirst, const std::vector<
 // Exact sparse LU of one block
 // ---------------------------------------------------------------------------
 
+// Bottom-up amalgamation: merged supernodes of at most kMergeWidth rows, at
+// most kMergePasses rounds (each removes one level at the bottom).
+constexpr int kMergeWidth = 16, kMergePasses = 3;
+
 int factor_block(const CsrL& M, double tau, bool want_T, BlockFactor& out, std::string& err) {
   const int n = M.nrows;
   out = BlockFactor();
@@ -558,6 +562,46 @@ int factor_block(const CsrL& M, double tau, bool want_T, BlockFactor& out, std::
     std::vector<int> sf2;
     for (int s = 0; s < ns0; ++s)
       if (!absorbed[s]) sf2.push_back(gfirst[s]);
+    sf2.push_back(n);
+    sfirst.swap(sf2);
+  }
+  // bottom-up amalgamation: a supernode whose children are all leaves absorbs
+  // them when the merged block stays narrow (postorder keeps the subtree
+  // contiguous); every pass removes one level at the bottom of the schedule
+  for (int pass = 0; pass < kMergePasses; ++pass) {
+    const int ns0 = (int)sfirst.size() - 1;
+    std::vector<int> snode0(n), par0(ns0, -1), nch(ns0, 0), wsum(ns0, 0), lfirst(ns0);
+    std::vector<char> allleaf(ns0, 1);
+    for (int s = 0; s < ns0; ++s)
+      for (int j = sfirst[s]; j < sfirst[s + 1]; ++j) snode0[j] = s;
+    for (int s = 0; s < ns0; ++s) {
+      const std::vector<int>& Rs = st[sfirst[s + 1] - 1];
+      if (!Rs.empty()) par0[s] = snode0[Rs[0]];
+      lfirst[s] = sfirst[s];
+    }
+    for (int s = 0; s < ns0; ++s)
+      if (par0[s] >= 0) {
+        nch[par0[s]]++;
+        wsum[par0[s]] += sfirst[s + 1] - sfirst[s];
+      }
+    for (int s = 0; s < ns0; ++s)
+      if (par0[s] >= 0) {
+        if (nch[s] > 0) allleaf[par0[s]] = 0;
+        lfirst[par0[s]] = std::min(lfirst[par0[s]], sfirst[s]);
+      }
+    std::vector<char> absorbed(ns0, 0), merge(ns0, 0);
+    bool any = false;
+    for (int s = 0; s < ns0; ++s)
+      if (nch[s] > 0 && allleaf[s] && wsum[s] + (sfirst[s + 1] - sfirst[s]) <= kMergeWidth) {
+        merge[s] = 1;
+        any = true;
+      }
+    if (!any) break;
+    for (int s = 0; s < ns0; ++s)
+      if (par0[s] >= 0 && merge[par0[s]]) absorbed[s] = 1;
+    std::vector<int> sf2;
+    for (int s = 0; s < ns0; ++s)
+      if (!absorbed[s]) sf2.push_back(merge[s] ? lfirst[s] : sfirst[s]);
     sf2.push_back(n);
     sfirst.swap(sf2);
   }
