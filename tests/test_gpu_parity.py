@@ -317,22 +317,23 @@ def test_c2_full_size_apply_parity():
 @pytest.mark.parametrize("precision", [0, 1])
 def test_tile_paths_agree(precision):
     """Right-hand sides applied one at a time (single-rhs path: entry form on
-    narrow levels in FP64, chunked products) and in tiles of 2, 4 and 8 (panel
-    form, one task per row) give the same preconditioned vectors."""
+    narrow levels in FP64, chunked products) and together in tiles of 2, 4 and
+    8, including ragged counts that leave a tile partly empty (3, 5, 11), give
+    the same preconditioned vectors."""
     A = wl.laplacian3d(14, 0.3)
     lab = opart.geometric_labels((14, 14, 14), (2, 2, 2))
     h = P.pslr_setup(A.rowptr, A.colind, A.vals, lab, 8, m=3, rank=8, precision=precision,
                      want_transpose=True, seed=11)
-    b = wl.normal_rhs(A.n, 8, 21)
+    b = wl.normal_rhs(A.n, 11, 21)
     tol = 1e-13 if precision == 0 else 1e-5
     for apply in (P.pslr_apply, P.pslr_apply_transpose):
         single = np.empty_like(b)
-        for j in range(8):
+        for j in range(b.shape[1]):
             z1 = torch.zeros((1, A.n), dtype=torch.float64, device=_dev())
             apply(h, _tens(b[:, j:j + 1]), z1)
             torch.cuda.synchronize()
             single[:, j] = _cols(z1)[:, 0]
-        for nr in (2, 4, 8):
+        for nr in (2, 3, 4, 5, 8, 11):
             z = torch.zeros((nr, A.n), dtype=torch.float64, device=_dev())
             apply(h, _tens(b[:, :nr]), z)
             torch.cuda.synchronize()
