@@ -751,18 +751,6 @@ pslr_status upload_lowrank(pslr_ctx* h) {
   return PSLR_OK;
 }
 
-// Device dot products of nv vectors with w (column r of each), result on host.
-pslr_status dots(pslr_ctx* h, int64_t n, int nv, const double* V, int64_t ldv, int64_t ldvr,
-                 const double* w, int64_t ldw, int nrhs, double* dbuf, double* dout,
-                 std::vector<double>& host, hipStream_t s) {
-  HIP_TRY(launch_mdot(n, nv, V, ldv, ldvr, w, ldw, nrhs, h->nchunk, dbuf, s));
-  HIP_TRY(launch_reduce(h->nchunk, nrhs, nv, dbuf, dout, s));
-  host.resize((size_t)nrhs * nv);
-  HIP_TRY(hipMemcpyAsync(host.data(), dout, sizeof(double) * nrhs * nv, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  return PSLR_OK;
-}
-
 // r_k-step Arnoldi on E_rr(m) = (E_s C0^{-1})^{m+1} (Theorem t2), classical
 // Gram-Schmidt with one full re-orthogonalisation, FP64 on the device.  The
 // systems of a batched handle run their Arnoldi processes together: E_rr is

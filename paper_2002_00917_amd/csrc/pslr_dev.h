@@ -144,32 +144,6 @@ hipError_t set_lds_limit(size_t bytes);
 hipError_t launch_spmv(int64_t n, const int64_t* ptr, const int32_t* col, const double* val,
                        int nrhs, const double* x, int64_t ldx, double* y, int64_t ldy,
                        const double* bsub, int64_t ldb, hipStream_t s);
-// partial[chunk][r][i] = sum over rows of chunk of V_i[row] * w_r[row], i < nv
-// V_i of column r at V + r*ldvr + i*ldv
-hipError_t launch_mdot(int64_t n, int nv, const double* V, int64_t ldv, int64_t ldvr,
-                       const double* w, int64_t ldw, int nrhs, int nchunk, double* partial,
-                       hipStream_t s);
-// out[r][i] = sum_chunk partial[chunk][r][i]
-hipError_t launch_reduce(int nchunk, int nrhs, int nv, const double* partial, double* out,
-                         hipStream_t s);
-// w_r -= sum_i h[r][i] V_i   (h row stride hld)
-hipError_t launch_maxpy(int64_t n, int nv, const double* V, int64_t ldv, int64_t ldvr,
-                        const double* h, int hld, double* w, int64_t ldw, int nrhs, double sign,
-                        hipStream_t s);
-// v_r = w_r * scale[r] (scale on device)
-hipError_t launch_scale(int64_t n, const double* w, int64_t ldw, const double* scale, double* v,
-                        int64_t ldv, int nrhs, hipStream_t s);
-// Segmented forms over ncol columns (column c: vcols[c] in V / wcols[c] in W):
-// partial[chunk][c][i] = sum_rows V_i[vbase + row] * W[wbase + row], V_i = V + i*ldv
-hipError_t launch_mdot_seg(int ncol, const Seg* vcols, const Seg* wcols, int nv, const double* V,
-                           int64_t ldv, const double* W, int nchunk, double* partial, hipStream_t s);
-// W[wbase + row] -= sign * sum_i h[c*hld + i] * V_i[vbase + row]
-hipError_t launch_maxpy_seg(int ncol, const Seg* vcols, const Seg* wcols, int64_t maxlen, int nv,
-                            const double* V, int64_t ldv, const double* h, int hld, double* W,
-                            double sign, hipStream_t s);
-// D[dbase + row] = S[sbase + row] * scale[c]
-hipError_t launch_scale_seg(int ncol, const Seg* scols, const Seg* dcols, int64_t maxlen,
-                            const double* S, const double* scale, double* D, hipStream_t s);
 // Chunked forms: chunk c covers rows r0..r1 (at most kChunkRows) of column
 // ch[c].col; the chunks of column j are cptr[j] .. cptr[j+1].  Dot products:
 // partial[i * nchunk + c] per chunk, then out[j * nv + i] per column.
@@ -186,7 +160,6 @@ hipError_t launch_inv_sqrt(int ncol, const double* nn, const uint8_t* active, do
                            hipStream_t s);
 hipError_t launch_scale_chunk(int nchunk, const Chunk* ch, const Seg* scols, const Seg* dcols,
                               const double* S, const double* scale, double* D, hipStream_t s);
-hipError_t launch_copy_cast_to_f32(int64_t count, const double* src, float* dst, hipStream_t s);
 hipError_t launch_sddmm(int64_t n, const int64_t* ptr, const int32_t* col, int nrhs,
                         const double* lam, int64_t ldl, const double* z, int64_t ldz,
                         double* grad, hipStream_t s);

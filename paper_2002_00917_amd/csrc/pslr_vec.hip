@@ -25,119 +25,6 @@ __global__ void k_spmv(int64_t n, const int64_t* __restrict__ ptr, const int32_t
   y[r * ldy + row] = bsub ? bsub[r * ldb + row] - acc : acc;
 }
 
-__global__ void k_mdot(int64_t n, int nv, const double* __restrict__ V, int64_t ldv, int64_t ldvr,
-                       const double* __restrict__ w, int64_t ldw, int nchunk, double* partial) {
-  __shared__ double red[8];
-  const int chunk = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
-  const int64_t rows = (n + nchunk - 1) / nchunk;
-  const int64_t r0 = chunk * rows, r1 = min(n, r0 + rows);
-  const double* wr = w + r * ldw;
-  for (int i = 0; i < nv; ++i) {
-    const double* vi = V + r * ldvr + i * ldv;
-    double acc = 0.0;
-    for (int64_t row = r0 + tid; row < r1; row += blockDim.x) acc += vi[row] * wr[row];
-    acc = wave_sum(acc);
-    if ((tid & 63) == 0) red[tid >> 6] = acc;
-    __syncthreads();
-    if (tid == 0) {
-      double s = 0.0;
-      for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += red[k];
-      partial[((int64_t)chunk * gridDim.y + r) * nv + i] = s;
-    }
-    __syncthreads();
-  }
-}
-
-// out[r][i] = sum over chunks of partial[c][r][i]: one workgroup per (i, r)
-__global__ void k_reduce(int nchunk, int nrhs, int nv, const double* __restrict__ partial, double* out) {
-  __shared__ double red[4];
-  const int i = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
-  double s = 0.0;
-  for (int c = tid; c < nchunk; c += blockDim.x) s += partial[((int64_t)c * nrhs + r) * nv + i];
-  s = wave_sum(s);
-  if ((tid & 63) == 0) red[tid >> 6] = s;
-  __syncthreads();
-  if (tid == 0) {
-    double t = 0.0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
-    out[(int64_t)r * nv + i] = t;
-  }
-}
-
-__global__ void k_maxpy(int64_t n, int nv, const double* __restrict__ V, int64_t ldv, int64_t ldvr,
-                        const double* __restrict__ h, int hld, double* w, int64_t ldw, double sign) {
-  const int r = blockIdx.y;
-  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= n) return;
-  const double* hr = h + (int64_t)r * hld;
-  double acc = 0.0;
-  for (int i = 0; i < nv; ++i) acc += hr[i] * V[r * ldvr + i * ldv + row];
-  w[r * ldw + row] -= sign * acc;
-}
-
-__global__ void k_scale(int64_t n, const double* __restrict__ w, int64_t ldw,
-                        const double* __restrict__ scale, double* v, int64_t ldv) {
-  const int r = blockIdx.y;
-  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= n) return;
-  v[r * ldv + row] = w[r * ldw + row] * scale[r];
-}
-
-__global__ void k_mdot_seg(const Seg* __restrict__ vcols, const Seg* __restrict__ wcols, int nv,
-                           const double* __restrict__ V, int64_t ldv, const double* __restrict__ W,
-                           int nchunk, double* partial) {
-  __shared__ double red[8];
-  const int chunk = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
-  const Seg sv = vcols[c], sw = wcols[c];
-  const int64_t rows = (sw.len + nchunk - 1) / nchunk;
-  const int64_t r0 = chunk * rows, r1 = min(sw.len, r0 + rows);
-  const double* wr = W + sw.base;
-  for (int i = 0; i < nv; ++i) {
-    const double* vi = V + sv.base + i * ldv;
-    double acc = 0.0;
-    for (int64_t row = r0 + tid; row < r1; row += blockDim.x) acc += vi[row] * wr[row];
-    acc = wave_sum(acc);
-    if ((tid & 63) == 0) red[tid >> 6] = acc;
-    __syncthreads();
-    if (tid == 0) {
-      double s = 0.0;
-      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
-      partial[((int64_t)chunk * gridDim.y + c) * nv + i] = s;
-    }
-    __syncthreads();
-  }
-}
-
-__global__ void k_maxpy_seg(const Seg* __restrict__ vcols, const Seg* __restrict__ wcols, int nv,
-                            const double* __restrict__ V, int64_t ldv, const double* __restrict__ h,
-                            int hld, double* W, double sign) {
-  const int c = blockIdx.y;
-  const Seg sv = vcols[c], sw = wcols[c];
-  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= sw.len) return;
-  const double* hr = h + (int64_t)c * hld;
-  double acc = 0.0;
-  for (int i = 0; i < nv; ++i) {
-    const double hi = hr[i];
-    if (hi != 0.0) acc += hi * V[sv.base + i * ldv + row];
-  }
-  W[sw.base + row] -= sign * acc;
-}
-
-__global__ void k_scale_seg(const Seg* __restrict__ scols, const Seg* __restrict__ dcols,
-                            const double* __restrict__ S, const double* __restrict__ scale, double* D) {
-  const int c = blockIdx.y;
-  const Seg ss = scols[c], sd = dcols[c];
-  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= sd.len) return;
-  D[sd.base + row] = S[ss.base + row] * scale[c];
-}
-
-__global__ void k_cast(int64_t count, const double* __restrict__ s, float* d) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) d[i] = (float)s[i];
-}
-
 __global__ void k_sddmm(int64_t n, const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
                         int nrhs, const double* __restrict__ lam, int64_t ldl,
                         const double* __restrict__ z, int64_t ldz, double* grad) {
@@ -150,8 +37,6 @@ __global__ void k_sddmm(int64_t n, const int64_t* __restrict__ ptr, const int32_
   }
 }
 
-// partial[c][i] = sum over the chunk's rows of V_i[vbase + row] * W[wbase + row];
-// per-wave partial sums stay in LDS, one barrier per chunk
 // Chunked vector kernels: 256 threads per chunk, each thread owns rows
 // r0 + tid + t*256 (t < kRows) of its chunk; vectors go in groups of kUnroll so
 // that kUnroll * kRows independent loads are in flight per thread.
@@ -337,64 +222,6 @@ hipError_t launch_spmv(int64_t n, const int64_t* ptr, const int32_t* col, const 
                        const double* bsub, int64_t ldb, hipStream_t s) {
   hipLaunchKernelGGL(k_spmv, dim3(nblk(n, 256), nrhs), dim3(256), 0, s, n, ptr, col, val, x, ldx, y,
                      ldy, bsub, ldb);
-  return hipGetLastError();
-}
-
-hipError_t launch_mdot(int64_t n, int nv, const double* V, int64_t ldv, int64_t ldvr,
-                       const double* w, int64_t ldw, int nrhs, int nchunk, double* partial,
-                       hipStream_t s) {
-  hipLaunchKernelGGL(k_mdot, dim3(nchunk, nrhs), dim3(512), 0, s, n, nv, V, ldv, ldvr, w, ldw,
-                     nchunk, partial);
-  return hipGetLastError();
-}
-
-hipError_t launch_reduce(int nchunk, int nrhs, int nv, const double* partial, double* out,
-                         hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce, dim3(nv, nrhs), dim3(256), 0, s, nchunk, nrhs, nv, partial, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_maxpy(int64_t n, int nv, const double* V, int64_t ldv, int64_t ldvr,
-                        const double* h, int hld, double* w, int64_t ldw, int nrhs, double sign,
-                        hipStream_t s) {
-  hipLaunchKernelGGL(k_maxpy, dim3(nblk(n, 256), nrhs), dim3(256), 0, s, n, nv, V, ldv, ldvr, h,
-                     hld, w, ldw, sign);
-  return hipGetLastError();
-}
-
-hipError_t launch_scale(int64_t n, const double* w, int64_t ldw, const double* scale, double* v,
-                        int64_t ldv, int nrhs, hipStream_t s) {
-  hipLaunchKernelGGL(k_scale, dim3(nblk(n, 256), nrhs), dim3(256), 0, s, n, w, ldw, scale, v, ldv);
-  return hipGetLastError();
-}
-
-hipError_t launch_mdot_seg(int ncol, const Seg* vcols, const Seg* wcols, int nv, const double* V,
-                           int64_t ldv, const double* W, int nchunk, double* partial, hipStream_t s) {
-  hipLaunchKernelGGL(k_mdot_seg, dim3(nchunk, ncol), dim3(512), 0, s, vcols, wcols, nv, V, ldv, W,
-                     nchunk, partial);
-  return hipGetLastError();
-}
-
-hipError_t launch_maxpy_seg(int ncol, const Seg* vcols, const Seg* wcols, int64_t maxlen, int nv,
-                            const double* V, int64_t ldv, const double* h, int hld, double* W,
-                            double sign, hipStream_t s) {
-  if (maxlen <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_maxpy_seg, dim3(nblk(maxlen, 256), ncol), dim3(256), 0, s, vcols, wcols, nv,
-                     V, ldv, h, hld, W, sign);
-  return hipGetLastError();
-}
-
-hipError_t launch_scale_seg(int ncol, const Seg* scols, const Seg* dcols, int64_t maxlen,
-                            const double* S, const double* scale, double* D, hipStream_t s) {
-  if (maxlen <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_scale_seg, dim3(nblk(maxlen, 256), ncol), dim3(256), 0, s, scols, dcols, S,
-                     scale, D);
-  return hipGetLastError();
-}
-
-hipError_t launch_copy_cast_to_f32(int64_t count, const double* src, float* dst, hipStream_t s) {
-  if (count == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_cast, dim3(nblk(count, 256)), dim3(256), 0, s, count, src, dst);
   return hipGetLastError();
 }
 
