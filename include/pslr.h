@@ -34,6 +34,12 @@
  *   - A handle owns every device buffer it allocates; it holds one workspace,
  *     so concurrent calls on one handle from different streams race.
  *   - hip_stream may be NULL (the default stream).
+ *   - The triangular solves combine partial sums with atomic adds, so two
+ *     applies of the same vector can differ in the last bits (the summation
+ *     order varies); every result stays within the rounding of the method.
+ *   - pslr_apply and pslr_apply_transpose launch kernels only (no allocation,
+ *     memset or host synchronisation once the handle's workspace for that
+ *     many right-hand sides exists), so they can be captured in a HIP graph.
  */
 #ifndef PSLR_H
 #define PSLR_H
@@ -144,7 +150,9 @@ pslr_status pslr_apply_transpose(pslr_handle h, int32_t nrhs, const double* b, i
  * residual and restarts if needed; at most maxit inner iterations (the paper's
  * "its" and its 500-iteration failure rule, Sec. 4).  iters[nrhs], relres[nrhs]:
  * host outputs (true relative residuals); nsys * nrhs entries on a batched
- * handle.  Synchronises the stream. */
+ * handle.  The device runs one iteration ahead of the host's Givens updates,
+ * so a cycle that stops computes one iteration it does not use.  Synchronises
+ * the stream. */
 pslr_status fgmres_solve(pslr_handle h, int32_t nrhs, const double* b, int64_t ldb, double* x,
                          int64_t ldx, int32_t restart, int32_t maxit, double tol, int32_t transpose,
                          int32_t* iters, double* relres, void* hip_stream);
