@@ -213,7 +213,7 @@ def main():
     ap.add_argument("--grid", type=int, default=64)
     ap.add_argument("--restart", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--forms", default="fp64,fp32_apply")
+    ap.add_argument("--forms", default="fp64,fp32_apply,fp32_apply_bf16_v")
     ap.add_argument("--batched-steps", type=int, default=1)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device-to-device (counter calibration run)")
@@ -242,7 +242,7 @@ def main():
     log("workload n=%d nnz=%d" % (A.n, A.nnz))
     forms = {}
     wanted = args.forms.split(",")
-    for name, prec in (("fp64", 0), ("fp32_apply", 1)):
+    for name, prec in (("fp64", 0), ("fp32_apply", 1), ("fp32_apply_bf16_v", 2)):
         if name not in wanted:
             continue
         r = run_form(P, torch, A, lab, w.b, prec, args.steps, args.warmup, m, rank, restart, tol)
