@@ -81,8 +81,11 @@ template <typename T>
 hipError_t upload_tri(DevPool& pool, const std::vector<BlockFactor>& F, TriPacked BlockFactor::*mem,
                       TriArrays<T>& out, int& max_lrows, int64_t& bytes) {
   std::vector<DevTriBlock> blk(F.size());
-  std::vector<int32_t> lev_ptr, push_ptr, ent_ptr, lev_c, rec, prec, ridx, eidx, eloc;
-  std::vector<T> val, tri, eval;
+  std::vector<int32_t> lev_ptr, push_ptr, ent_ptr, lev_c, rec, prec, ridx, ent;
+  std::vector<T> val, tri;
+  // the entry form is read by FP64 solves only
+  const bool want_ent = sizeof(T) == 8;
+  int64_t nent = 0;
   bytes = 0;
   for (size_t i = 0; i < F.size(); ++i) {
     const TriPacked& H = F[i].*mem;
@@ -94,7 +97,7 @@ hipError_t upload_tri(DevPool& pool, const std::vector<BlockFactor>& F, TriPacke
     B.lev_base = (int64_t)lev_ptr.size();
     B.rec_base = (int64_t)rec.size() / 8;
     B.prec_base = (int64_t)prec.size() / 4;
-    B.ent_base = (int64_t)eval.size();
+    B.ent_base = nent;
     B.val_base = (int64_t)val.size();
     B.ridx_base = (int64_t)ridx.size();
     B.tri_base = (int64_t)tri.size();
@@ -111,9 +114,13 @@ hipError_t upload_tri(DevPool& pool, const std::vector<BlockFactor>& F, TriPacke
     for (double v : H.val) val.push_back((T)v);
     ridx.insert(ridx.end(), H.ridx.begin(), H.ridx.end());
     for (double v : H.tri) tri.push_back((T)v);
-    for (double v : H.eval) eval.push_back((T)v);
-    eidx.insert(eidx.end(), H.eidx.begin(), H.eidx.end());
-    eloc.insert(eloc.end(), H.eloc.begin(), H.eloc.end());
+    if (want_ent)
+      for (size_t q = 0; q < H.eval.size(); ++q) {
+        int32_t bits[2];
+        std::memcpy(bits, &H.eval[q], sizeof(double));
+        ent.insert(ent.end(), {bits[0], bits[1], H.eidx[q], H.eloc[q]});
+      }
+    nent += want_ent ? (int64_t)H.eval.size() : 0;
     const int path = sizeof(T) == 8 ? 0 : 1;  // entry form only in FP64
     bytes += H.read_vals[path] * (int64_t)sizeof(T) + 4 * H.read_ints[path];
   }
@@ -131,9 +138,8 @@ hipError_t upload_tri(DevPool& pool, const std::vector<BlockFactor>& F, TriPacke
   if ((e = pool.upload(val, &out.val))) return e;
   if ((e = pool.upload(ridx, &out.ridx))) return e;
   if ((e = pool.upload(tri, &out.tri))) return e;
-  if ((e = pool.upload(eval, &out.eval))) return e;
-  if ((e = pool.upload(eidx, &out.eidx))) return e;
-  if ((e = pool.upload(eloc, &out.eloc))) return e;
+  if ((e = pool.upload(ent, &p))) return e;
+  out.ent = reinterpret_cast<const double2*>(p);
   return hipSuccess;
 }
 

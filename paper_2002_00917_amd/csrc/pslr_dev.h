@@ -35,9 +35,9 @@ struct TriArrays {
   const T* val;
   const int32_t* ridx;
   const T* tri;
-  const T* eval;
-  const int32_t* eidx;
-  const int32_t* eloc;
+  // entry form, one 16-byte record per entry: x = value, y = the bits of
+  // {eidx (low word), eloc (high word)}; FP64 factors only
+  const double2* ent;
 };
 
 // Block-diagonal CSR over all subdomains with 64-bit row offsets.

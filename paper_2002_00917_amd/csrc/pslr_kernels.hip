@@ -84,34 +84,32 @@ __device__ __forceinline__ void panel_dot(const T* __restrict__ M, Off off, int 
 }
 
 // Entry-form off-diagonal part of a level: for e in [e0, e1),
-// D[dst(e)] -= v[e] * S[src(e)] with atomic adds, unrolled so that every thread
-// keeps several independent loads in flight.
+// D[dst(e)] -= v[e] * S[src(e)] with atomic adds.  Every entry is one 16-byte
+// record (value, target/source position, level-local row), loaded with one
+// instruction; each thread keeps U of them in flight.
 template <typename T, int R>
-__device__ __forceinline__ void entry_sweep(const T* __restrict__ v, const int32_t* __restrict__ to,
-                                            const int32_t* __restrict__ from, int e0, int e1, T* D,
+__device__ __forceinline__ void entry_sweep(const double2* __restrict__ er, int e0, int e1, T* D,
                                             const T* S, bool lower) {
-  constexpr int U = R == 1 ? 8 : 4;
+  constexpr int U = 4;
   const int tid = threadIdx.x, nthr = blockDim.x;
   for (int e = e0 + tid; e < e1; e += U * nthr) {
-    T vv[U];
-    int it[U], il[U];
+    // unconditional loads and adds, so that the compiler keeps all U loads in
+    // flight together instead of sinking each into a branch of its own: a
+    // slot past e1 re-reads the thread's own entry e and adds zero (to the
+    // target of that entry, so that such slots do not all meet on one address)
+    double2 q[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) q[u] = er[e + u * nthr < e1 ? e + u * nthr : e];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int q = e + u * nthr;
-      const bool ok = q < e1;
-      vv[u] = ok ? v[q] : (T)0;
-      it[u] = ok ? to[q] : 0;
-      il[u] = ok ? from[q] : 0;
+      const T v = e + u * nthr < e1 ? (T)q[u].x : (T)0;
+      // second half: lower: (target position, level-local source row);
+      // upper: (source position, level-local target row)
+      const int a = __double2loint(q[u].y), c = __double2hiint(q[u].y);
+      const int d = lower ? a : c, s = lower ? c : a;
+#pragma unroll
+      for (int r = 0; r < R; ++r) atomic_add(&D[d * R + r], -v * S[s * R + r]);
     }
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (e + u * nthr < e1) {
-        // lower: to = target position, from = level-local source row;
-        // upper: to = source position, from = level-local target row
-        const int d = lower ? it[u] : il[u], s = lower ? il[u] : it[u];
-#pragma unroll
-        for (int r = 0; r < R; ++r) atomic_add(&D[d * R + r], -vv[u] * S[s * R + r]);
-      }
   }
 }
 
@@ -148,9 +146,7 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
   const int32_t* lev_ptr = A.lev_ptr + B.lev_base;
   const int32_t* push_ptr = A.push_ptr + B.lev_base;
   const int32_t* ent_ptr = A.ent_ptr + B.lev_base;
-  const T* eval = A.eval + B.ent_base;
-  const int32_t* eidx = A.eidx + B.ent_base;
-  const int32_t* eloc = A.eloc + B.ent_base;
+  const double2* ent_rec = A.ent + B.ent_base;
   const int32_t* lev_c = A.lev_c + B.lev_base;
   const int4 z4 = make_int4(0, 0, 0, 0);
   T* const Rh0 = Rb;
@@ -239,7 +235,7 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
         for (int r = 0; r < R; ++r) X[p * R + r] = Rc[k * R + r];
       }
       // x[ridx[a]] -= Lpanel(a, :) s
-      if (ent) entry_sweep<T, R>(eval, eidx, eloc, ent_ptr[l], ent_ptr[l + 1], X, Rc, true);
+      if (ent) entry_sweep<T, R>(ent_rec, ent_ptr[l], ent_ptr[l + 1], X, Rc, true);
       {
         int4 q = fq;
         for (int t = tid; t < np * CP; t += nthr) {
@@ -319,7 +315,7 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
           r1 = n1;
         }
       }
-      if (ent) entry_sweep<T, R>(eval, eidx, eloc, ent_ptr[l], ent_ptr[l + 1], Rc, X, false);
+      if (ent) entry_sweep<T, R>(ent_rec, ent_ptr[l], ent_ptr[l + 1], Rc, X, false);
       // rows whose triangle products are chunked accumulate into x[p]
       if (CT > 1)
         for (int k = tid; k < cnt; k += nthr) {
