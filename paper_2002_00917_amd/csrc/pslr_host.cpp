@@ -929,12 +929,20 @@ bool pack_tri(const TriHost& T, TriPacked& P) {
       if (w > 32767 || h > 32767) return false;
       const int32_t toff = (int32_t)P.tri.size(), poff = (int32_t)P.val.size();
       const int32_t roff = (int32_t)P.ridx.size();
-      // inverted triangle, column-major packed
-      for (int j = 0; j < w; ++j) {
-        const int i0 = T.lower ? j : 0, i1 = T.lower ? w - 1 : j;
-        for (int i = i0; i <= i1; ++i)
-          P.tri.push_back(T.lower ? T.tri[S.tri_off + (int64_t)i * (i + 1) / 2 + j]
-                                  : T.tri[S.tri_off + (int64_t)i * w - (int64_t)i * (i - 1) / 2 + (j - i)]);
+      // inverted triangle entry (i, j) of the host layout (0 outside the triangle)
+      auto tinv = [&](int i, int j) -> double {
+        if (i >= w || j >= w || (T.lower ? j > i : j < i)) return 0.0;
+        return T.lower ? T.tri[S.tri_off + (int64_t)i * (i + 1) / 2 + j]
+                       : T.tri[S.tri_off + (int64_t)i * w - (int64_t)i * (i - 1) / 2 + (j - i)];
+      };
+      // inverted triangle, column pairs (2c, 2c+1) interleaved: lower pair c
+      // holds rows 2c..w-1, upper pair c rows 0..2c+1 (zeros outside the triangle)
+      for (int c = 0; c < (w + 1) / 2; ++c) {
+        const int i0 = T.lower ? 2 * c : 0, i1 = T.lower ? w - 1 : 2 * c + 1;
+        for (int i = i0; i <= i1; ++i) {
+          P.tri.push_back(tinv(i, 2 * c));
+          P.tri.push_back(tinv(i, 2 * c + 1));
+        }
       }
       if (ent) {
         // entry form (kept besides the panels; the solve picks one):
@@ -956,19 +964,26 @@ bool pack_tri(const TriHost& T, TriPacked& P) {
         }
       }
       {
-        // panel, column-major
+        // panel, column pairs interleaved: lower (a, 2c + t) at 2(c h + a) + t,
+        // upper (i, 2c + t) at 2(c w + i) + t; an odd last column pairs with zeros
         if (T.lower) {
-          for (int j = 0; j < w; ++j)
-            for (int q = 0; q < h; ++q) P.val.push_back(T.val[S.panel_off + (int64_t)q * w + j]);
+          for (int c = 0; c < (w + 1) / 2; ++c)
+            for (int q = 0; q < h; ++q)
+              for (int t = 0; t < 2; ++t)
+                P.val.push_back(2 * c + t < w ? T.val[S.panel_off + (int64_t)q * w + 2 * c + t] : 0.0);
         } else {
-          for (int q = 0; q < h; ++q)
-            for (int i = 0; i < w; ++i) P.val.push_back(T.val[S.panel_off + (int64_t)i * h + q]);
+          for (int c = 0; c < (h + 1) / 2; ++c)
+            for (int i = 0; i < w; ++i)
+              for (int t = 0; t < 2; ++t)
+                P.val.push_back(2 * c + t < h ? T.val[S.panel_off + (int64_t)i * h + 2 * c + t] : 0.0);
         }
+        // position list padded to even length with its last position (paired with zeros)
         P.ridx.insert(P.ridx.end(), T.ridx.begin() + S.ridx_off, T.ridx.begin() + S.ridx_off + h);
+        if (h & 1) P.ridx.push_back(T.ridx[S.ridx_off + h - 1]);
         if (T.lower) {
           for (int q = 0; q < h; ++q) {
             P.prec.push_back(T.ridx[S.ridx_off + q]);
-            P.prec.push_back(poff + q);
+            P.prec.push_back(poff / 2 + q);
             P.prec.push_back(w | (h << 16));
             P.prec.push_back(k - b);
           }
@@ -1013,8 +1028,10 @@ bool pack_tri(const TriHost& T, TriPacked& P) {
                            : chunks_for(cnt, cnt ? panel_len / cnt : 0.0);
     P.lev_c[l] = ct | (cp << 8) | ((ent ? 1 : 0) << 16);
   }
+  int64_t tri_vals = 0;  // triangle entries without the pair padding
+  for (const SnHost& S : T.sn) tri_vals += (int64_t)S.w * (S.w + 1) / 2;
   for (int q = 0; q < 2; ++q) {
-    P.read_vals[q] += (int64_t)P.tri.size();
+    P.read_vals[q] += tri_vals;
     P.read_ints[q] += (int64_t)P.rec.size() + 4 * (int64_t)(T.nlev + 1);
   }
   // record fields are int32 offsets into the block's arrays
@@ -1026,6 +1043,18 @@ bool pack_tri(const TriHost& T, TriPacked& P) {
 // Host execution of a packed factor (diagnostics): the device algorithm in
 // sequential order
 // ---------------------------------------------------------------------------
+
+namespace {
+// pair index of triangle entry (i, j) in the column-pair layouts of pack_tri
+int64_t tri_pair_lower(int i, int j, int w) {
+  const int64_t c = j >> 1;
+  return c * (w - c + 1) + (i - 2 * c);
+}
+int64_t tri_pair_upper(int i, int j) {
+  const int64_t c = j >> 1;
+  return c * (c + 1) + i;
+}
+}  // namespace
 
 void host_tri_solve(const TriPacked& T, std::vector<double>& X, bool entries) {
   std::vector<double> Rb(std::max(T.max_lrows, 1));
@@ -1039,7 +1068,7 @@ void host_tri_solve(const TriPacked& T, std::vector<double>& X, bool entries) {
         const int p = r[0], i = r[1], w = r[2];
         double acc = 0.0;
         for (int j = 0; j <= i; ++j)
-          acc += T.tri[r[4] + (int64_t)j * w - (int64_t)j * (j - 1) / 2 + (i - j)] * X[p - i + j];
+          acc += T.tri[r[4] + 2 * tri_pair_lower(i, j, w) + (j & 1)] * X[p - i + j];
         Rb[k - b] = acc;
       }
       for (int k = b; k < e; ++k) X[T.rec[(size_t)8 * k]] = Rb[k - b];
@@ -1050,7 +1079,7 @@ void host_tri_solve(const TriPacked& T, std::vector<double>& X, bool entries) {
           const int32_t* q = &T.prec[(size_t)4 * m];
           const int w = q[2] & 0xffff, h = q[2] >> 16;
           double acc = 0.0;
-          for (int j = 0; j < w; ++j) acc += T.val[q[1] + (int64_t)j * h] * Rb[q[3] + j];
+          for (int j = 0; j < w; ++j) acc += T.val[2 * (q[1] + (int64_t)(j >> 1) * h) + (j & 1)] * Rb[q[3] + j];
           X[q[0]] -= acc;
         }
       }
@@ -1059,7 +1088,8 @@ void host_tri_solve(const TriPacked& T, std::vector<double>& X, bool entries) {
         const int32_t* r = &T.rec[(size_t)8 * k];
         const int i = r[1], w = r[2], h = ent ? 0 : r[3];
         double acc = 0.0;
-        for (int a = 0; a < h; ++a) acc += T.val[r[5] + (int64_t)a * w + i] * X[T.ridx[r[6] + a]];
+        for (int a = 0; a < h; ++a)
+          acc += T.val[r[5] + 2 * ((int64_t)(a >> 1) * w + i) + (a & 1)] * X[T.ridx[r[6] + a]];
         Rb[k - b] = X[r[0]] - acc;
       }
       if (ent)
@@ -1068,7 +1098,7 @@ void host_tri_solve(const TriPacked& T, std::vector<double>& X, bool entries) {
         const int32_t* r = &T.rec[(size_t)8 * k];
         const int p = r[0], i = r[1], w = r[2];
         double acc = 0.0;
-        for (int j = i; j < w; ++j) acc += T.tri[r[4] + (int64_t)j * (j + 1) / 2 + i] * Rb[r[7] + j];
+        for (int j = i; j < w; ++j) acc += T.tri[r[4] + 2 * tri_pair_upper(i, j) + (j & 1)] * Rb[r[7] + j];
         X[p] = acc;
       }
     }

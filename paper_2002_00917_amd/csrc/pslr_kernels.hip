@@ -57,31 +57,64 @@ __device__ __forceinline__ void level_chunks(int c, int gshift, int& CT, int& CP
   }
 }
 
-// acc[r] += sum_{0 <= t < n} M[off(jt)] * S[jt * R + r] with jt = j0 + d * t
-// (d = +1 or -1): one lane's share of a dense column-major product.  Lanes of
-// a supernode start at the same j and walk it in step, so consecutive lanes
-// (consecutive rows) read consecutive entries while their counts n differ; S
-// is the same for all of them.
+// Dense factor blocks store their columns in interleaved pairs (2c, 2c + 1),
+// so that one 16-byte (FP64) or 8-byte (FP32) load brings a lane two columns.
+template <typename T>
+struct Pair;
+template <>
+struct Pair<double> {
+  using type = double2;
+};
+template <>
+struct Pair<float> {
+  using type = float2;
+};
+
+#ifndef PSLR_PAIR_U
+#define PSLR_PAIR_U 4
+#endif
+
+// acc[r] += sum over the columns of pairs c = c0 + d * t, 0 <= t < np (d = +1
+// or -1), of M(j) * S[j * R + r]: one lane's share of a dense product.  Lanes
+// of a supernode start at the same pair and walk in step, so consecutive lanes
+// (consecutive rows) read consecutive pairs while their counts np differ; S is
+// the same for all of them.
 template <typename T, int R, typename Off>
-__device__ __forceinline__ void panel_dot(const T* __restrict__ M, Off off, int j0, int d, int n,
-                                          const T* S, T (&acc)[R]) {
-  constexpr int U = R == 1 ? 8 : 4;
+__device__ __forceinline__ void pair_dot(const typename Pair<T>::type* __restrict__ M, Off off, int c0,
+                                         int d, int np, const T* S, T (&acc)[R]) {
+  constexpr int U = R == 1 ? PSLR_PAIR_U : 2;
   int t = 0;
-  for (; t + U <= n; t += U) {
-    T v[U];
+  for (; t + U <= np; t += U) {
+    typename Pair<T>::type v[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) v[u] = M[off(j0 + d * (t + u))];
+    for (int u = 0; u < U; ++u) v[u] = M[off(c0 + d * (t + u))];
 #pragma unroll
-    for (int u = 0; u < U; ++u)
+    for (int u = 0; u < U; ++u) {
+      const int j = 2 * (c0 + d * (t + u));
 #pragma unroll
-      for (int r = 0; r < R; ++r) acc[r] += v[u] * S[(j0 + d * (t + u)) * R + r];
+      for (int r = 0; r < R; ++r) acc[r] += v[u].x * S[j * R + r] + v[u].y * S[(j + 1) * R + r];
+    }
   }
-  for (; t < n; ++t) {
-    const T v = M[off(j0 + d * t)];
+  for (; t < np; ++t) {
+    const typename Pair<T>::type v = M[off(c0 + d * t)];
+    const int j = 2 * (c0 + d * t);
 #pragma unroll
-    for (int r = 0; r < R; ++r) acc[r] += v * S[(j0 + d * t) * R + r];
+    for (int r = 0; r < R; ++r) acc[r] += v.x * S[j * R + r] + v.y * S[(j + 1) * R + r];
   }
 }
+
+// acc[r] += M(2c) * S[2c * R + r]: the first column of pair c alone (an odd
+// column count; the second column is not read from S).
+template <typename T, int R>
+__device__ __forceinline__ void half_pair(const typename Pair<T>::type* __restrict__ M, int64_t at, int c,
+                                          const T* S, T (&acc)[R]) {
+  const T v = M[at].x;
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] += v * S[2 * c * R + r];
+}
+
+// even chunk length covering len in C chunks
+__device__ __forceinline__ int pair_chunk(int len, int C) { return (((len + C - 1) / C) + 1) & ~1; }
 
 // Entry-form off-diagonal part of a level: for e in [e0, e1),
 // D[dst(e)] -= v[e] * S[src(e)] with atomic adds.  Every entry is one 16-byte
@@ -209,13 +242,24 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
           }
           const int c = t / cnt, k = t - c * cnt;
           const int i = r0.y, w = r0.z;
-          const int Lc = (w + CT - 1) / CT;
+          const int Lc = pair_chunk(w, CT);
           const int j0 = c * Lc, j1 = min(w, j0 + Lc);
           T acc[R];
 #pragma unroll
           for (int r = 0; r < R; ++r) acc[r] = 0;
-          panel_dot<T, R>(tri + r1.x, [=](int j) { return j * w - (j * (j - 1) >> 1) + (i - j); }, j0, 1,
-                          min(j1, i + 1) - j0, X + (int64_t)(r0.x - i) * R, acc);
+          // columns j0 .. min(j1, i + 1) - 1; pair c of a lower triangle holds
+          // rows 2c .. w-1 at pair index c (w - c + 1) + (i - 2c)
+          const int ncol = min(j1, i + 1) - j0;
+          if (ncol > 0) {
+            const auto* M = reinterpret_cast<const typename Pair<T>::type*>(tri + r1.x);
+            auto off = [=](int cc) { return cc * (w - cc + 1) + (i - 2 * cc); };
+            const T* S = X + (int64_t)(r0.x - i) * R;
+            pair_dot<T, R>(M, off, j0 >> 1, 1, ncol >> 1, S, acc);
+            if (ncol & 1) {
+              const int ch = (j0 >> 1) + (ncol >> 1);
+              half_pair<T, R>(M, off(ch), ch, S, acc);
+            }
+          }
           if (CT == 1) {
 #pragma unroll
             for (int r = 0; r < R; ++r) Rc[k * R + r] = acc[r];
@@ -243,13 +287,22 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
           const int4 qn = tn < np * CP ? prec[pb + tn % np] : z4;
           const int c = t / np;
           const int w = q.z & 0xffff, h = q.z >> 16;
-          const int Lc = (w + CP - 1) / CP;
+          const int Lc = pair_chunk(w, CP);
           const int j0 = c * Lc, j1 = min(w, j0 + Lc);
           if (j0 < j1) {
             T acc[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) acc[r] = 0;
-            panel_dot<T, R>(pan + q.y, [=](int j) { return j * h; }, j0, 1, j1 - j0, Rc + (int64_t)q.w * R, acc);
+            // panel row a: pair c at pair index q.y + c h
+            const auto* M = reinterpret_cast<const typename Pair<T>::type*>(pan) + q.y;
+            auto off = [=](int cc) { return cc * h; };
+            const T* S = Rc + (int64_t)q.w * R;
+            const int ncol = j1 - j0;
+            pair_dot<T, R>(M, off, j0 >> 1, 1, ncol >> 1, S, acc);
+            if (ncol & 1) {
+              const int ch = (j0 >> 1) + (ncol >> 1);
+              half_pair<T, R>(M, off(ch), ch, S, acc);
+            }
 #pragma unroll
             for (int r = 0; r < R; ++r) atomic_add(&X[q.x * R + r], -acc[r]);
           }
@@ -276,33 +329,37 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
           }
           const int c = t / cnt, k = t - c * cnt;
           const int i = r0.y, w = r0.z, h = r0.w;
-          const int Lc = (h + CP - 1) / CP;
+          const int Lc = pair_chunk(h, CP);
           const int a0 = c * Lc, a1 = min(h, a0 + Lc);
-          const T* pc = pan + r1.y + i;
-          const int32_t* rc = ridx + r1.z;
+          // row i: pair g (columns 2g, 2g + 1) at pair index g w + i, positions
+          // ridx[2g], ridx[2g + 1] (an odd last column pairs with a zero value
+          // and a repeated position)
+          const auto* pc = reinterpret_cast<const typename Pair<T>::type*>(pan + r1.y) + i;
+          const int2* rc = reinterpret_cast<const int2*>(ridx + r1.z);
           T acc[R];
 #pragma unroll
           for (int r = 0; r < R; ++r) acc[r] = 0;
-          constexpr int U = R == 1 ? 8 : 4;
-          int a = a0;
-          for (; a + U <= a1; a += U) {
-            T v[U];
-            int cc[U];
+          constexpr int U = R == 1 ? PSLR_PAIR_U : 2;
+          int g = a0 >> 1;
+          const int g1 = (a1 + 1) >> 1;
+          for (; g + U <= g1; g += U) {
+            typename Pair<T>::type v[U];
+            int2 cc[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-              v[u] = pc[(a + u) * w];
-              cc[u] = rc[a + u];
+              v[u] = pc[(g + u) * w];
+              cc[u] = rc[g + u];
             }
 #pragma unroll
             for (int u = 0; u < U; ++u)
 #pragma unroll
-              for (int r = 0; r < R; ++r) acc[r] += v[u] * X[cc[u] * R + r];
+              for (int r = 0; r < R; ++r) acc[r] += v[u].x * X[cc[u].x * R + r] + v[u].y * X[cc[u].y * R + r];
           }
-          for (; a < a1; ++a) {
-            const T v = pc[a * w];
-            const int cc = rc[a];
+          for (; g < g1; ++g) {
+            const typename Pair<T>::type v = pc[g * w];
+            const int2 cc = rc[g];
 #pragma unroll
-            for (int r = 0; r < R; ++r) acc[r] += v * X[cc * R + r];
+            for (int r = 0; r < R; ++r) acc[r] += v.x * X[cc.x * R + r] + v.y * X[cc.y * R + r];
           }
           if (CP == 1) {
 #pragma unroll
@@ -336,14 +393,24 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
           }
           const int c = t / cnt;
           const int p = r0.x, i = r0.y, w = r0.z;
-          const int Lc = (w + CT - 1) / CT;
+          const int Lc = pair_chunk(w, CT);
           const int j0 = c * Lc, j1 = min(w, j0 + Lc);
           T acc[R];
 #pragma unroll
           for (int r = 0; r < R; ++r) acc[r] = 0;
-          // columns j1-1 down to max(j0, i): a common start for the lanes
-          panel_dot<T, R>(tri + r1.x, [=](int j) { return ((j * (j + 1)) >> 1) + i; }, j1 - 1, -1,
-                          j1 - max(j0, i), Rc + (int64_t)r1.w * R, acc);
+          // columns j1-1 down to jlo = max(j0, i), a common start for the
+          // lanes; pair c of an upper triangle holds rows 0 .. 2c+1 at pair
+          // index c (c + 1) + i (entries left of the diagonal are zeros).  An
+          // odd j1 (= w) leaves the top pair with one column.
+          {
+            const int jlo = max(j0, i);
+            const auto* M = reinterpret_cast<const typename Pair<T>::type*>(tri + r1.x);
+            auto off = [=](int cc) { return cc * (cc + 1) + i; };
+            const T* S = Rc + (int64_t)r1.w * R;
+            if ((j1 & 1) && j1 - 1 >= jlo) half_pair<T, R>(M, off(j1 >> 1), j1 >> 1, S, acc);
+            const int npair = (j1 >> 1) - (jlo >> 1);
+            if (npair > 0) pair_dot<T, R>(M, off, (j1 >> 1) - 1, -1, npair, S, acc);
+          }
           if (CT == 1) {
 #pragma unroll
             for (int r = 0; r < R; ++r) X[p * R + r] = acc[r];
