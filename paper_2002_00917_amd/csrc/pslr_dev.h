@@ -10,7 +10,8 @@ namespace pslr {
 
 // Per-block descriptor of one packed triangular factor (see TriPacked): rows
 // and factor data are stored level by level; a row record is 8 int32 =
-// {p, off_begin, off_len, ridx_begin, tri_begin, tri_len, rb_first, 0}.
+// {p, row in supernode, w, h, triangle start, panel start, ridx start,
+// level-local index of the supernode's first row}.
 struct DevTriBlock {
   int32_t n, nlev, max_lrows, lower;
   int64_t lev_base;   // lev_ptr/push_ptr/ent_ptr[lev_base .. +nlev], lev_c[lev_base .. +nlev)

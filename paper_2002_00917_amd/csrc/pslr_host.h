@@ -84,11 +84,19 @@ constexpr int kNarrowWidth = 24;
 //   [0] target position ridx[a]   [1] panel start + a   [2] w | (h << 16)
 //   [3] level-local index of the supernode's first row
 //
-// Inverted triangles are column-major packed: lower entry (i, j), j <= i, at
-// j*w - j*(j-1)/2 + (i - j); upper entry (i, j), j >= i, at j*(j+1)/2 + i.
-// Panels are column-major: lower (a, j) at j*h + a, upper (i, a) at a*w + i,
-// so consecutive lanes (consecutive a or i) read consecutive entries.
-// Entries follow the same order within each supernode.
+// Triangles and panels store their columns in interleaved pairs (2c, 2c+1),
+// so that one load brings a lane two columns, and consecutive lanes
+// (consecutive rows) read consecutive pairs:
+//   inverted lower triangle: pair c holds rows 2c..w-1; entry (i, 2c+t) at
+//     2 (c (w - c + 1) + i - 2c) + t
+//   inverted upper triangle: pair c holds rows 0..2c+1; entry (i, 2c+t) at
+//     2 (c (c + 1) + i) + t
+//   lower panel (a, 2c+t) at 2 (c h + a) + t; upper panel (i, 2c+t) at 2 (c w + i) + t
+// Entries outside a triangle, and the partner of an odd last column, are
+// stored zeros; each upper position list is padded to even length by
+// repeating its last position.  Every supernode's arrays start at an even
+// offset.  Entries follow the panel order within each supernode.
+// The push record's panel start [1] is a pair index (panel start / 2 + a).
 //
 // Lower solve (right-looking), per level: s_k = sum_j Tinv(i, j) x[f + j]
 // for every row item (x holds b minus the pushed updates), then x[p] = s_k and
