@@ -33,7 +33,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "PSLR-FGMRES solves/s to rel-res 1e-8 (FP64 vs mixed/batched); apply HBM GB/s"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_2002_00917_amd", "csrc", "pslr_kernels.hip")
+# what decides the data a k_series launch reads: the kernels and the host
+# packing of the factors (layouts, entry-form thresholds)
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2002_00917_amd", "csrc", f)
+               for f in ("pslr_kernels.hip", "pslr_host.cpp", "pslr_host.h")]
 PMC_FILE = os.path.join(ROOT, "profiles", "k_series_lap3d64_pmc.txt")
 
 
@@ -42,8 +45,11 @@ def log(*a):
 
 
 def kernel_hash():
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic():
@@ -53,7 +59,7 @@ def measured_traffic():
             kv = dict(line.split(" = ", 1) for line in fh.read().splitlines() if " = " in line)
     except OSError:
         return None
-    if kv.get("kernel_source_sha256_16", "").strip() != kernel_hash():
+    if kv.get("source_sha256_16", "").strip() != kernel_hash():
         return None
     return float(kv["bytes_per_launch"])
 

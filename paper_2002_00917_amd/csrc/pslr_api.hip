@@ -1136,7 +1136,8 @@ pslr_status pslr_host_selfcheck(int64_t n, const int64_t* rowptr, const int32_t*
   parallel_for((int)mats.size(), o.nthreads, [&](int t) {
     const CsrL& M = *mats[t];
     BlockFactor f;
-    codes[t] = factor_block(M, tau, o.want_transpose != 0, f, errs[t]);
+    codes[t] = factor_block(M, tau, o.want_transpose != 0,
+                            t < (int)Bk.B.size() ? kNarrowWidthB : kNarrowWidthC, f, errs[t]);
     if (codes[t] || M.nrows == 0) return;
     const int nb = M.nrows;
     // residual of the solve layouts: x = M^{-1} b with b = M * xe, through the
@@ -1264,8 +1265,8 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
   std::vector<std::string> errs(2 * np);
   std::vector<int> codes(2 * np, 0);
   parallel_for(2 * np, o.nthreads, [&](int t) {
-    if (t < np) codes[t] = factor_block(Bk.B[t], tau, h->want_T != 0, fB[t], errs[t]);
-    else codes[t] = factor_block(Bk.C0[t - np], tau, h->want_T != 0, fC[t - np], errs[t]);
+    if (t < np) codes[t] = factor_block(Bk.B[t], tau, h->want_T != 0, kNarrowWidthB, fB[t], errs[t]);
+    else codes[t] = factor_block(Bk.C0[t - np], tau, h->want_T != 0, kNarrowWidthC, fC[t - np], errs[t]);
   });
   for (int t = 0; t < 2 * np; ++t)
     if (codes[t]) return fail(codes[t] == 3 ? PSLR_ENOTSUP : PSLR_ESINGULAR,

@@ -449,7 +449,8 @@ void build_levels(TriHost& T, const std::vector<int>& sfirst, const std::vector<
 // most kMergePasses rounds (each removes one level at the bottom).
 constexpr int kMergeWidth = 16, kMergePasses = 3;
 
-int factor_block(const CsrL& M, double tau, bool want_T, BlockFactor& out, std::string& err) {
+int factor_block(const CsrL& M, double tau, bool want_T, int narrow_width, BlockFactor& out,
+                 std::string& err) {
   const int n = M.nrows;
   out = BlockFactor();
   out.n = n;
@@ -844,7 +845,7 @@ int factor_block(const CsrL& M, double tau, bool want_T, BlockFactor& out, std::
     build_lower_panels(T, false);
     for (int s = 0; s < ns; ++s) pack_inv(T, s, invL[s], false);
     build_levels(T, sfirst, height, nlev);
-    if (!pack_tri(T, out.lo)) {
+    if (!pack_tri(T, out.lo, narrow_width)) {
       err = "supernode wider than 32767 rows, panel taller than 32767 rows or block factor beyond 2^31 entries";
       return 3;
     }
@@ -855,7 +856,7 @@ int factor_block(const CsrL& M, double tau, bool want_T, BlockFactor& out, std::
     build_upper_panels(T, false);
     for (int s = 0; s < ns; ++s) pack_inv(T, s, invU[s], false);
     build_levels(T, sfirst, height, nlev);
-    if (!pack_tri(T, out.up)) {
+    if (!pack_tri(T, out.up, narrow_width)) {
       err = "supernode wider than 32767 rows, panel taller than 32767 rows or block factor beyond 2^31 entries";
       return 3;
     }
@@ -867,7 +868,7 @@ int factor_block(const CsrL& M, double tau, bool want_T, BlockFactor& out, std::
       build_lower_panels(T, true);
       for (int s = 0; s < ns; ++s) pack_inv(T, s, invU[s], true);
       build_levels(T, sfirst, height, nlev);
-      if (!pack_tri(T, out.loT)) {
+      if (!pack_tri(T, out.loT, narrow_width)) {
       err = "supernode wider than 32767 rows, panel taller than 32767 rows or block factor beyond 2^31 entries";
       return 3;
     }
@@ -878,7 +879,7 @@ int factor_block(const CsrL& M, double tau, bool want_T, BlockFactor& out, std::
       build_upper_panels(T, true);
       for (int s = 0; s < ns; ++s) pack_inv(T, s, invL[s], true);
       build_levels(T, sfirst, height, nlev);
-      if (!pack_tri(T, out.upT)) {
+      if (!pack_tri(T, out.upT, narrow_width)) {
       err = "supernode wider than 32767 rows, panel taller than 32767 rows or block factor beyond 2^31 entries";
       return 3;
     }
@@ -902,7 +903,7 @@ int chunks_for(int64_t items, double avg_len) {
 }
 }  // namespace
 
-bool pack_tri(const TriHost& T, TriPacked& P) {
+bool pack_tri(const TriHost& T, TriPacked& P, int narrow_width) {
   P = TriPacked();
   P.lower = T.lower;
   P.n = T.n;
@@ -919,7 +920,7 @@ bool pack_tri(const TriHost& T, TriPacked& P) {
     int nsn = 0;
     for (int k = b; k < e; k += T.sn[T.row_sn[T.lrows[k]]].w) ++nsn;
     // narrow supernodes: entry form for the off-diagonal part
-    const bool ent = nsn > 0 && cnt < kNarrowWidth * nsn;
+    const bool ent = nsn > 0 && cnt < narrow_width * nsn;
     double tri_len = 0, panel_len = 0, push_len = 0;
     int64_t npush = 0;
     for (int k = b; k < e;) {

@@ -58,8 +58,17 @@ struct TriHost {
 // Threads of the workgroup that solves one block; chunk counts are sized for it.
 constexpr int kSolveThreads = 1024;
 // Levels whose supernodes average fewer rows than this store their
-// off-diagonal part as entries rather than panels.
-constexpr int kNarrowWidth = 24;
+// off-diagonal part as entries rather than panels (measured on the 64^3
+// workload: the interior blocks B_i gain from panels down to 8-row supernodes,
+// the interface blocks C_i keep entries up to 24).
+#ifndef PSLR_NARROW_B
+#define PSLR_NARROW_B 8
+#endif
+#ifndef PSLR_NARROW_C
+#define PSLR_NARROW_C 24
+#endif
+constexpr int kNarrowWidthB = PSLR_NARROW_B;
+constexpr int kNarrowWidthC = PSLR_NARROW_C;
 
 // Device layout of one packed triangular factor of one block.  All data is
 // stored level by level, so every level reads one contiguous stretch of each
@@ -134,7 +143,9 @@ struct BlockFactor {
 
 // Fill `out` for block M.  Returns 0 on success, 2 on a zero pivot, 3 on a
 // supernode too large for the device layout (message in err).
-int factor_block(const CsrL& M, double tau, bool want_transpose, BlockFactor& out,
+// narrow_width: the entry-form threshold of pack_tri (kNarrowWidthB for
+// interior blocks, kNarrowWidthC for interface blocks).
+int factor_block(const CsrL& M, double tau, bool want_transpose, int narrow_width, BlockFactor& out,
                  std::string& err);
 
 // Reordering of Sec. 2 (interface rule and interiors-first permutation).
@@ -161,9 +172,10 @@ Blocks extract_blocks(int64_t n, const int64_t* rowptr, const int32_t* colind,
 // Apply `fn(i)` for i in [0, count) on `nthreads` host threads.
 void parallel_for(int count, int nthreads, const std::function<void(int)>& fn);
 
-// Pack a TriHost into the device layout; false if a supernode exceeds the
+// Pack a TriHost into the device layout (levels whose supernodes average
+// fewer than narrow_width rows also get the entry form); false if a supernode exceeds the
 // record field widths (w or h above 32767) or a block's arrays exceed 2^31.
-bool pack_tri(const TriHost& T, TriPacked& P);
+bool pack_tri(const TriHost& T, TriPacked& P, int narrow_width);
 
 // Host execution of a packed factor on one vector (diagnostics only).
 // entries: use the entry form where a level has one (else the panels).
