@@ -171,7 +171,7 @@ def run_batched(P, torch, wl, steps, warmup, restart=120, rank=64, tol=1e-8):
         "apply_ms_all_systems_8rhs": apply_ms,
         "apply_GBps": (info["apply_bytes"] + (nrhs - 1) * info["apply_bytes_rhs"]) / (apply_ms * 1e-3) / 1e9,
         "global_vectors": info["global_vectors"], "threads": info["threads"],
-        "lane_shift": info["lane_shift"],
+        "lane_shift": info["lane_shift"], "max_tile": info["max_tile"],
     }
 
 

@@ -78,7 +78,9 @@ typedef struct {
   int32_t working_vectors;  /* 0: subdomain working vectors in LDS when they fit (default);
                                1: always in a global-memory workspace */
   int32_t autotune;         /* nonzero: at the end of setup, time applies over workgroup sizes
-                               {512, 1024} x chunk-count scalings {1/2, 1, 2} and keep the fastest */
+                               {512, 1024} x chunk-count scalings {1/2, 1, 2} and keep the fastest,
+                               then applies of 8 right-hand sides with tiles of at most
+                               {8, 4, 2, 1} right-hand sides per workgroup and keep the fastest */
 } pslr_options;
 
 typedef struct {
@@ -98,6 +100,7 @@ typedef struct {
   int32_t global_vectors;   /* 1 when the working vectors live in global memory */
   int32_t threads;          /* workgroup size of the subdomain kernels */
   int32_t lane_shift;       /* per-level chunk counts of the solves scaled by 2^lane_shift */
+  int32_t max_tile;         /* widest right-hand-side tile of one workgroup (8 unless autotuned) */
 } pslr_info_t;
 
 /* Fill *opt with defaults: m = 3, rank = 16, FP64, no transpose, seed 1, tau 0.1. */

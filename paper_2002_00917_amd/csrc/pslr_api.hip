@@ -212,6 +212,7 @@ struct pslr_ctx {
   size_t lds_max = 65536;   // LDS bytes a workgroup may use
   int64_t gws_stride = 0;
   int tuned_threads = 0, tuned_gshift = 0;
+  int rmax = 8;      // widest right-hand-side tile of a launch (autotuned)
   const int64_t* d_rb_off = nullptr;
   // apply workspaces
   int ws_nrhs = 0;
@@ -590,7 +591,7 @@ template <typename T>
 LaunchCfg choose_launch(pslr_ctx* h, const ApplyArrays<T>& A, int nrhs, hipStream_t s) {
   LaunchCfg c{h->threads, 0, s, 1, false};
   int want = 1;
-  while (want < 8 && want < nrhs) want *= 2;
+  while (want < h->rmax && want < nrhs) want *= 2;
   int Rl = 0;
   if (!h->gx)
     for (int R = want; R >= 1; R /= 2)
@@ -890,7 +891,8 @@ pslr_status arnoldi(pslr_ctx* h, const double* v0host, uint64_t seed, hipStream_
 }
 
 // Pick the workgroup size and the chunk-count scaling of the triangular solves by
-// timing applies (one right-hand side, HIP events) over a small grid of choices.
+// timing applies (one right-hand side, HIP events) over a small grid of choices,
+// then the widest right-hand-side tile (applies of 8 right-hand sides).
 pslr_status autotune(pslr_ctx* h, hipStream_t s) {
   const int64_t n = h->R.n;
   if (n == 0) return PSLR_OK;
@@ -936,6 +938,38 @@ pslr_status autotune(pslr_ctx* h, hipStream_t s) {
   h->threads = bt;
   for (auto* A : {&h->fw64, &h->tr64}) A->gshift = bg;
   for (auto* A : {&h->fw32, &h->tr32}) A->gshift = bg;
+  // widest right-hand-side tile: applies of 8 right-hand sides with tiles of at
+  // most 8, 4, 2 and 1.  Narrower tiles read each factor more often but spread
+  // the largest subdomains over more workgroups.
+  {
+    const int nr = 8;
+    double *b8, *z8;
+    HIP_TRY(tmp.alloc<double>(n * nr, &b8));
+    HIP_TRY(tmp.alloc<double>(n * nr, &z8));
+    for (int r = 0; r < nr; ++r)
+      HIP_TRY(hipMemcpyAsync(b8 + (int64_t)r * n, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    float bestr = 1e30f;
+    int br = h->rmax;
+    for (int rm : {8, 4, 2, 1}) {
+      h->rmax = rm;
+      float tmin = 1e30f;
+      for (int rep = 0; rep < 3; ++rep) {
+        HIP_TRY(hipEventRecord(e0, s));
+        pslr_status st = apply_dir(h, false, nr, b8, n, z8, n, s);
+        if (st) return st;
+        HIP_TRY(hipEventRecord(e1, s));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (rep > 0) tmin = std::min(tmin, ms);
+      }
+      if (tmin < bestr) {
+        bestr = tmin;
+        br = rm;
+      }
+    }
+    h->rmax = br;
+  }
   h->trace = tr;
   h->tuned_threads = bt;
   h->tuned_gshift = bg;
@@ -995,6 +1029,7 @@ void fill_info(pslr_ctx* h, const std::vector<BlockFactor>& fB, const std::vecto
   I.global_vectors = h->gx ? 1 : 0;
   I.threads = h->threads;
   I.lane_shift = h->fw64.gshift;
+  I.max_tile = h->rmax;
 }
 
 }  // namespace

@@ -49,7 +49,7 @@ class pslr_info_t(C.Structure):
                 ("series_bytes", C.c_int64), ("seconds_reorder", C.c_double),
                 ("seconds_factor", C.c_double), ("seconds_arnoldi", C.c_double),
                 ("nsys", C.c_int32), ("global_vectors", C.c_int32), ("threads", C.c_int32),
-                ("lane_shift", C.c_int32)]
+                ("lane_shift", C.c_int32), ("max_tile", C.c_int32)]
 
 
 class pslr_trace_t(C.Structure):

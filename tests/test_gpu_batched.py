@@ -162,3 +162,25 @@ def test_global_working_vectors_match_lds(precision):
     ref = pre.apply(b)
     e = np.linalg.norm(out[1][0] - ref, axis=0) / np.linalg.norm(ref, axis=0)
     assert np.all(e <= (1e-12 if precision == 0 else 1e-5))
+
+
+def test_autotuned_tile_width_gives_the_same_apply():
+    """The setup autotuner may narrow the right-hand-side tiles; the apply is unchanged."""
+    systems = small_systems()
+    U, sys_ptr, lab, nparts = build_union(systems)
+    h8 = P.pslr_setup_batched(U.rowptr, U.colind, U.vals, lab, nparts, sys_ptr, m=3, rank=0)
+    ht = P.pslr_setup_batched(U.rowptr, U.colind, U.vals, lab, nparts, sys_ptr, m=3, rank=0,
+                              autotune=True)
+    assert P.pslr_info(h8)["max_tile"] == 8
+    assert P.pslr_info(ht)["max_tile"] in (1, 2, 4, 8)
+    print("autotuned tile width", P.pslr_info(ht)["max_tile"])
+    for nr in (8, 3):
+        b = wl.normal_rhs(U.n, nr, 40 + nr)
+        out = []
+        for h in (h8, ht):
+            z = torch.zeros((nr, U.n), dtype=torch.float64, device=_dev())
+            P.pslr_apply(h, _t(b), z)
+            torch.cuda.synchronize()
+            out.append(_cols(z))
+        e = np.linalg.norm(out[0] - out[1], axis=0) / np.linalg.norm(out[0], axis=0)
+        assert np.all(e <= 1e-12), e
