@@ -95,11 +95,21 @@ __device__ __forceinline__ void pair_dot(const typename Pair<T>::type* __restric
       for (int r = 0; r < R; ++r) acc[r] += v[u].x * S[j * R + r] + v[u].y * S[(j + 1) * R + r];
     }
   }
-  for (; t < np; ++t) {
-    const typename Pair<T>::type v = M[off(c0 + d * t)];
-    const int j = 2 * (c0 + d * t);
+  if (t < np) {
+    // last round masked rather than one pair at a time: every slot loads
+    // (slots past np re-read pair np - 1) and the extra products are dropped
+    typename Pair<T>::type v[U];
 #pragma unroll
-    for (int r = 0; r < R; ++r) acc[r] += v.x * S[j * R + r] + v.y * S[(j + 1) * R + r];
+    for (int u = 0; u < U; ++u) v[u] = M[off(c0 + d * min(t + u, np - 1))];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = 2 * (c0 + d * min(t + u, np - 1));
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const T a = v[u].x * S[j * R + r] + v[u].y * S[(j + 1) * R + r];
+        acc[r] += t + u < np ? a : (T)0;
+      }
+    }
   }
 }
 
@@ -355,11 +365,22 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
 #pragma unroll
               for (int r = 0; r < R; ++r) acc[r] += v[u].x * X[cc[u].x * R + r] + v[u].y * X[cc[u].y * R + r];
           }
-          for (; g < g1; ++g) {
-            const typename Pair<T>::type v = pc[g * w];
-            const int2 cc = rc[g];
+          if (g < g1) {
+            // last round masked (slots past g1 re-read pair g1 - 1, products dropped)
+            typename Pair<T>::type v[U];
+            int2 cc[U];
 #pragma unroll
-            for (int r = 0; r < R; ++r) acc[r] += v.x * X[cc.x * R + r] + v.y * X[cc.y * R + r];
+            for (int u = 0; u < U; ++u) {
+              v[u] = pc[min(g + u, g1 - 1) * w];
+              cc[u] = rc[min(g + u, g1 - 1)];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+              for (int r = 0; r < R; ++r) {
+                const T a = v[u].x * X[cc[u].x * R + r] + v[u].y * X[cc[u].y * R + r];
+                acc[r] += g + u < g1 ? a : (T)0;
+              }
           }
           if (CP == 1) {
 #pragma unroll
