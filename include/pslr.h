@@ -80,7 +80,8 @@ typedef struct {
   int32_t autotune;         /* nonzero: at the end of setup, time applies over workgroup sizes
                                {512, 1024} x chunk-count scalings {1/2, 1, 2} and keep the fastest,
                                then applies of 8 right-hand sides with tiles of at most
-                               {8, 4, 2, 1} right-hand sides per workgroup and keep the fastest */
+                               {8, 4, 2, 1} right-hand sides per workgroup and keep the
+                               narrowest within 5% of the fastest */
 } pslr_options;
 
 typedef struct {

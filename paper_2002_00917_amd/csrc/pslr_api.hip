@@ -948,9 +948,12 @@ pslr_status autotune(pslr_ctx* h, hipStream_t s) {
     HIP_TRY(tmp.alloc<double>(n * nr, &z8));
     for (int r = 0; r < nr; ++r)
       HIP_TRY(hipMemcpyAsync(b8 + (int64_t)r * n, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-    float bestr = 1e30f;
-    int br = h->rmax;
-    for (int rm : {8, 4, 2, 1}) {
+    // the narrowest cap within 5% of the fastest: inside FGMRES, tiles whose
+    // columns have all converged are skipped, which favours narrow tiles
+    float tr_ms[4];
+    const int caps[4] = {8, 4, 2, 1};
+    for (int ci = 0; ci < 4; ++ci) {
+      const int rm = caps[ci];
       h->rmax = rm;
       float tmin = 1e30f;
       for (int rep = 0; rep < 3; ++rep) {
@@ -963,11 +966,12 @@ pslr_status autotune(pslr_ctx* h, hipStream_t s) {
         HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
         if (rep > 0) tmin = std::min(tmin, ms);
       }
-      if (tmin < bestr) {
-        bestr = tmin;
-        br = rm;
-      }
+      tr_ms[ci] = tmin;
     }
+    const float bestr = *std::min_element(tr_ms, tr_ms + 4);
+    int br = 8;
+    for (int ci = 0; ci < 4; ++ci)
+      if (tr_ms[ci] <= 1.05f * bestr) br = caps[ci];
     h->rmax = br;
   }
   h->trace = tr;
