@@ -78,10 +78,13 @@ struct Pair<float> {
 // or -1), of M(j) * S[j * R + r]: one lane's share of a dense product.  Lanes
 // of a supernode start at the same pair and walk in step, so consecutive lanes
 // (consecutive rows) read consecutive pairs while their counts np differ; S is
-// the same for all of them.
+// the same for all of them.  The pair at walk index half_t (-1: none) holds one
+// column only: its second stored value is a zero (across the diagonal, or
+// padding), and S is read at its first column instead of the second, which
+// the lane does not own.
 template <typename T, int R, typename Off>
 __device__ __forceinline__ void pair_dot(const typename Pair<T>::type* __restrict__ M, Off off, int c0,
-                                         int d, int np, const T* S, T (&acc)[R]) {
+                                         int d, int np, int half_t, const T* S, T (&acc)[R]) {
   constexpr int U = R == 1 ? PSLR_PAIR_U : 2;
   int t = 0;
   for (; t + U <= np; t += U) {
@@ -91,8 +94,9 @@ __device__ __forceinline__ void pair_dot(const typename Pair<T>::type* __restric
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int j = 2 * (c0 + d * (t + u));
+      const int j2 = t + u == half_t ? j : j + 1;
 #pragma unroll
-      for (int r = 0; r < R; ++r) acc[r] += v[u].x * S[j * R + r] + v[u].y * S[(j + 1) * R + r];
+      for (int r = 0; r < R; ++r) acc[r] += v[u].x * S[j * R + r] + v[u].y * S[j2 * R + r];
     }
   }
   if (t < np) {
@@ -103,24 +107,16 @@ __device__ __forceinline__ void pair_dot(const typename Pair<T>::type* __restric
     for (int u = 0; u < U; ++u) v[u] = M[off(c0 + d * min(t + u, np - 1))];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int j = 2 * (c0 + d * min(t + u, np - 1));
+      const int tu = min(t + u, np - 1);
+      const int j = 2 * (c0 + d * tu);
+      const int j2 = tu == half_t ? j : j + 1;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const T a = v[u].x * S[j * R + r] + v[u].y * S[(j + 1) * R + r];
+        const T a = v[u].x * S[j * R + r] + v[u].y * S[j2 * R + r];
         acc[r] += t + u < np ? a : (T)0;
       }
     }
   }
-}
-
-// acc[r] += M(2c) * S[2c * R + r]: the first column of pair c alone (an odd
-// column count; the second column is not read from S).
-template <typename T, int R>
-__device__ __forceinline__ void half_pair(const typename Pair<T>::type* __restrict__ M, int64_t at, int c,
-                                          const T* S, T (&acc)[R]) {
-  const T v = M[at].x;
-#pragma unroll
-  for (int r = 0; r < R; ++r) acc[r] += v * S[2 * c * R + r];
 }
 
 // even chunk length covering len in C chunks
@@ -264,11 +260,8 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
             const auto* M = reinterpret_cast<const typename Pair<T>::type*>(tri + r1.x);
             auto off = [=](int cc) { return cc * (w - cc + 1) + (i - 2 * cc); };
             const T* S = X + (int64_t)(r0.x - i) * R;
-            pair_dot<T, R>(M, off, j0 >> 1, 1, ncol >> 1, S, acc);
-            if (ncol & 1) {
-              const int ch = (j0 >> 1) + (ncol >> 1);
-              half_pair<T, R>(M, off(ch), ch, S, acc);
-            }
+            const int np = (ncol + 1) >> 1;
+            pair_dot<T, R>(M, off, j0 >> 1, 1, np, (ncol & 1) ? np - 1 : -1, S, acc);
           }
           if (CT == 1) {
 #pragma unroll
@@ -308,11 +301,8 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
             auto off = [=](int cc) { return cc * h; };
             const T* S = Rc + (int64_t)q.w * R;
             const int ncol = j1 - j0;
-            pair_dot<T, R>(M, off, j0 >> 1, 1, ncol >> 1, S, acc);
-            if (ncol & 1) {
-              const int ch = (j0 >> 1) + (ncol >> 1);
-              half_pair<T, R>(M, off(ch), ch, S, acc);
-            }
+            const int np = (ncol + 1) >> 1;
+            pair_dot<T, R>(M, off, j0 >> 1, 1, np, (ncol & 1) ? np - 1 : -1, S, acc);
 #pragma unroll
             for (int r = 0; r < R; ++r) atomic_add(&X[q.x * R + r], -acc[r]);
           }
@@ -428,9 +418,10 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
             const auto* M = reinterpret_cast<const typename Pair<T>::type*>(tri + r1.x);
             auto off = [=](int cc) { return cc * (cc + 1) + i; };
             const T* S = Rc + (int64_t)r1.w * R;
-            if ((j1 & 1) && j1 - 1 >= jlo) half_pair<T, R>(M, off(j1 >> 1), j1 >> 1, S, acc);
-            const int npair = (j1 >> 1) - (jlo >> 1);
-            if (npair > 0) pair_dot<T, R>(M, off, (j1 >> 1) - 1, -1, npair, S, acc);
+            // from the top pair (one column when j1 is odd) down to pair jlo / 2
+            const int top = (j1 & 1) ? (j1 >> 1) : (j1 >> 1) - 1;
+            const int np = jlo < j1 ? top - (jlo >> 1) + 1 : 0;
+            if (np > 0) pair_dot<T, R>(M, off, top, -1, np, (j1 & 1) ? 0 : -1, S, acc);
           }
           if (CT == 1) {
 #pragma unroll
