@@ -16,9 +16,9 @@
  *   r_k-step Arnoldi on E_rr(m): E_rr ~ V H V^T       (eq. schur),
  *   G = (I - H)^{-1} - I, S_app^{-1} = P_m (I + V G V^T)  (eqs. Sinv0, Sinv).
  *
- * Local factors are exact sparse LU factorisations of every B_i and C_i (the
- * paper's Algorithm 4 uses ILU; exact LU makes the closed forms above hold
- * to rounding).
+ * Local factors are exact sparse LU factorisations of every B_i and C_i by
+ * default (the closed forms above then hold to rounding), or the paper's
+ * threshold incomplete LU (Algorithm 4, drop tolerance 1e-2 in Sec. 4).
  *
  * Conventions shared by every entry point
  *   - Every call returns a pslr_status and never aborts; pslr_last_error()
@@ -40,6 +40,14 @@
  *   - pslr_apply and pslr_apply_transpose launch kernels only (no allocation,
  *     memset or host synchronisation once the handle's workspace for that
  *     many right-hand sides exists), so they can be captured in a HIP graph.
+ *     A captured apply keeps the device buffers it was captured with.  The
+ *     handle never frees a buffer a captured apply may use while it lives:
+ *     a call that needs a larger workspace (more right-hand sides than any
+ *     earlier call, or a larger rank after pslr_set_lowrank) allocates a new
+ *     one and keeps the old one until pslr_destroy, and pslr_set_lowrank
+ *     keeps the replaced V and G likewise.  A graph captured before
+ *     pslr_set_lowrank therefore still runs, with the OLD low-rank term:
+ *     capture it again to use the new one.  pslr_destroy frees everything.
  */
 #ifndef PSLR_H
 #define PSLR_H
@@ -67,9 +75,14 @@ typedef enum {
 
 typedef struct {
   int32_t m;                /* power-series upper index: sum_{i=0..m}, i.e. m+1 terms (eq. approx1) */
-  int32_t rank;             /* r_k, Arnoldi steps (eq. schur); capped at q; 0 disables the correction */
+  int32_t rank;             /* r_k, Arnoldi steps (eq. schur); capped at min(q, 256), the widest
+                               low-rank term the kernels hold (pslr_info.rank gives the rank
+                               reached); 0 disables the correction */
   int32_t precision;        /* 0: FP64 apply; 1: FP32 apply (FP32 V); 2: FP32 apply with V stored in
-                               BF16.  FGMRES and Arnoldi stay FP64 in every mode */
+                               BF16 where that rounding changes one apply by at most 2.5e-2
+                               relative (measured at setup and by pslr_set_lowrank; else V
+                               stays in FP32, see pslr_info.v_bf16).  FGMRES and Arnoldi stay
+                               FP64 in every mode */
   int32_t want_transpose;   /* nonzero: also build the layouts pslr_apply_transpose needs */
   const double* v0;         /* optional host Arnoldi start vector of length q (interface order) */
   uint64_t seed;            /* used when v0 == NULL: SplitMix64 uniform in [-0.5, 0.5) */
@@ -82,6 +95,15 @@ typedef struct {
                                then applies of 8 right-hand sides with tiles of at most
                                {8, 4, 2, 1} right-hand sides per workgroup and keep the
                                narrowest within 5% of the fastest */
+  int32_t threads;          /* workgroup size of the subdomain kernels: 0 = 1024 (the default, or
+                               the autotuner's choice), else 512 or 1024 */
+  int32_t factor;           /* local factors of every B_i and C_i (Algorithm 4, lines 3-4):
+                               0 = exact sparse LU (nested dissection, supernodes, threshold
+                               pivoting); 1 = threshold incomplete LU in the block's own row
+                               order, no pivoting (ilu() of Algorithm 4; see drop_tol) */
+  double drop_tol;          /* factor = 1: an entry of row i is dropped when its modulus is below
+                               drop_tol * ||A_block[i, :]||_2 (the L entry after division by
+                               the pivot); <= 0 means 1e-2, the paper's setting (Sec. 4) */
 } pslr_options;
 
 typedef struct {
@@ -102,15 +124,20 @@ typedef struct {
   int32_t threads;          /* workgroup size of the subdomain kernels */
   int32_t lane_shift;       /* per-level chunk counts of the solves scaled by 2^lane_shift */
   int32_t max_tile;         /* widest right-hand-side tile of one workgroup (8 unless autotuned) */
+  int32_t v_bf16;           /* precision 2: 1 when V is read in BF16, 0 when the setup probe kept it
+                               in FP32 */
+  double bf16_probe;        /* precision 2: ||z_bf16 - z_fp32|| / ||z_fp32|| of one apply to a fixed
+                               vector with V in BF16 and in FP32; BF16 is kept when <= 2.5e-2 */
 } pslr_info_t;
 
 /* Fill *opt with defaults: m = 3, rank = 16, FP64, no transpose, seed 1, tau 0.1. */
 void pslr_default_options(pslr_options* opt);
 
 /* Build the preconditioner (Algorithm 4): reorder A by the labels `part`
- * (interiors of part 0..s-1 then interfaces, Sec. 2), exact sparse LU of every
- * B_i and C_i on the host, upload, then r_k-step Arnoldi on E_rr(m) on the
- * device in FP64 and G = (I - H)^{-1} - I on the host.
+ * (interiors of part 0..s-1 then interfaces, Sec. 2), local factors of every
+ * B_i and C_i on the host (exact sparse LU, or threshold ILU: opt->factor),
+ * upload, then r_k-step Arnoldi on E_rr(m) on the device in FP64 and
+ * G = (I - H)^{-1} - I on the host.
  *   n, rowptr[n+1], colind[nnz], vals[nnz]: host CSR of A, original ordering.
  *   part[n]: subdomain label of each row, in [0, nparts).
  * Vertex v is an interface vertex iff a stored entry A[v,w] or A[w,v] couples
@@ -227,6 +254,25 @@ pslr_status pslr_host_selfcheck(int64_t n, const int64_t* rowptr, const int32_t*
                                 const double* vals, const int32_t* part, int32_t nparts,
                                 const pslr_options* opt, double* factor_residual,
                                 double* solve_residual);
+
+/* Host-only statistics of the local factors of every B_i and C_i that
+ * pslr_setup would build with these options (no GPU needed): stored factor
+ * entries and level-schedule depths as pslr_info reports them, whether every
+ * packed factor passes the structural level check (each position scheduled
+ * once, a supernode's rows on one level, every dependency solved strictly
+ * before the row that needs it), and the two residuals of
+ * pslr_host_selfcheck.  For factor = 1 the factor residual is the largest
+ * |(A_block - L U)_ij| / ||A_block[i, :]||_2 over the kept pattern of L + U
+ * (zero up to rounding by the definition of the incomplete factorisation). */
+typedef struct {
+  int64_t nnz_LU_B, nnz_LU_C0;
+  int32_t max_levels_B, max_levels_C0;
+  int32_t levels_valid;
+  double factor_residual, solve_residual;
+} pslr_host_stats_t;
+pslr_status pslr_host_stats(int64_t n, const int64_t* rowptr, const int32_t* colind,
+                            const double* vals, const int32_t* part, int32_t nparts,
+                            const pslr_options* opt, pslr_host_stats_t* out);
 
 pslr_status pslr_destroy(pslr_handle h);
 const char* pslr_status_string(pslr_status s);

@@ -14,8 +14,8 @@ S_app^{-1} = P_m (I + V G V^T)                           (eq. Sinv)
 Preconditioner application (Algorithm 3, eq. application):
     y = g - F B^{-1} f;  y += V G V^T y;  y = P_m y;  x = B^{-1}(f - E y).
 
-The local solves use exact sparse LU (scipy's SuperLU) of every B_i and C_i.
-All arithmetic is FP64.
+The local solves use exact sparse LU (scipy's SuperLU) of every B_i and C_i,
+or the paper's threshold ILU (oracle.ilu).  All arithmetic is FP64.
 """
 from __future__ import annotations
 
@@ -25,6 +25,7 @@ import scipy.linalg as sla
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
+from . import ilu as oilu
 from . import partition as opart
 
 
@@ -87,15 +88,18 @@ def _assert_block_diagonal(blk: Blocks):
 
 
 class BlockDiagSolver:
-    """Block-diagonal solve with one SuperLU factorisation per diagonal block."""
+    """Block-diagonal solve with one factorisation per diagonal block: exact
+    sparse LU (SuperLU) or the threshold ILU of Algorithm 4 (oracle.ilu)."""
 
-    def __init__(self, M: sp.csr_matrix, ptr: np.ndarray):
+    def __init__(self, M: sp.csr_matrix, ptr: np.ndarray, factor: str = "lu", drop: float = 1e-2):
         self.ptr = ptr
         self.lu = []
         for i in range(len(ptr) - 1):
             a, b = int(ptr[i]), int(ptr[i + 1])
             if b > a:
-                self.lu.append(spla.splu(sp.csc_matrix(M[a:b, a:b])))
+                blk = M[a:b, a:b]
+                self.lu.append(spla.splu(sp.csc_matrix(blk)) if factor == "lu"
+                               else oilu.IlutSolver(blk, drop))
             else:
                 self.lu.append(None)
 
@@ -184,13 +188,14 @@ class PSLR:
 
     def __init__(self, A: sp.csr_matrix, label: np.ndarray, m: int, rank: int,
                  v0: np.ndarray | None = None, V: np.ndarray | None = None,
-                 H: np.ndarray | None = None):
+                 H: np.ndarray | None = None, factor: str = "lu", drop: float = 1e-2):
+        """factor: "lu" (exact local factors) or "ilut" (threshold ILU, drop tolerance drop)."""
         self.A = sp.csr_matrix(A)
         self.m = int(m)
         self.blk = make_blocks(self.A, label)
         b = self.blk
-        self.Bs = BlockDiagSolver(b.B, b.int_ptr)
-        self.C0s = BlockDiagSolver(b.C0, b.if_ptr)
+        self.Bs = BlockDiagSolver(b.B, b.int_ptr, factor, drop)
+        self.C0s = BlockDiagSolver(b.C0, b.if_ptr, factor, drop)
         if V is not None:
             self.set_lowrank(V, H)
         elif rank > 0 and b.q > 0:

@@ -18,13 +18,23 @@ class PSLRSolve(torch.autograd.Function):
 
     ``handle`` must come from ``pslr_setup(..., want_transpose=True)`` on the
     matrix whose CSR values are ``vals`` (original CSR order); ``vals`` is an
-    input only so that autograd can return its gradient.  ``b``: (n,) or
+    input only so that autograd can return its gradient.  The forward checks
+    ``vals`` against the handle's fingerprint of those values (count, sum,
+    sum of squares) and raises when they differ: new values need a new handle.  ``b``: (n,) or
     (nrhs, n) float64 device tensor.  ``tol`` / ``adj_tol``: relative residual
     targets of the forward and adjoint solves (the adjoint defaults to ``tol``).
     """
 
     @staticmethod
     def forward(ctx, vals, b, handle, tol=1e-10, restart=40, maxit=500, adj_tol=None):
+        # the handle's factors and A belong to the values it was set up with:
+        # a changed vals needs a new handle
+        cnt, s1, s2 = handle.vals_fingerprint
+        v = vals.detach().to(torch.float64)
+        if v.numel() != cnt or not (abs(float(v.sum()) - s1) <= 1e-12 * max(1.0, abs(s1) + s2 ** 0.5 * cnt ** 0.5)
+                                    and abs(float((v * v).sum()) - s2) <= 1e-12 * max(1.0, s2)):
+            raise ValueError("vals differ from the matrix the handle was set up with: "
+                             "rebuild the handle with pslr_setup for new values")
         x = torch.zeros_like(b)
         st, its, rel = P.fgmres_solve(handle, b.contiguous(), x, restart=restart, maxit=maxit, tol=tol)
         if st != P.PSLR_OK:

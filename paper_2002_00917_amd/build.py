@@ -11,6 +11,7 @@ import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -24,6 +25,7 @@ HIP_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",
 ]
+HIP_SOURCES = ("pslr_kernels.hip", "pslr_vec.hip", "pslr_api.hip")
 CXX_FLAGS = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-sign-compare", "-Wno-unused-function"]
 
 
@@ -41,14 +43,16 @@ def build(verbose: bool = False) -> str:
     hipcc = shutil.which("hipcc") or os.path.join(ROCM, "bin", "hipcc")
     cxx = shutil.which("g++") or "g++"
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
-    o = os.path.join(BUILD, "pslr_host.o")
-    _run([cxx] + CXX_FLAGS + ["-c", os.path.join(CSRC, "pslr_host.cpp"), "-o", o], verbose)
-    objs.append(o)
-    for src in ("pslr_kernels.hip", "pslr_vec.hip", "pslr_api.hip"):
-        o = os.path.join(BUILD, src.replace(".hip", ".o"))
-        _run([hipcc] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", o], verbose)
-        objs.append(o)
+    jobs = [[cxx] + CXX_FLAGS + ["-c", os.path.join(CSRC, "pslr_host.cpp"), "-o",
+                                 os.path.join(BUILD, "pslr_host.o")]]
+    for src in HIP_SOURCES:
+        jobs.append([hipcc] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o",
+                                           os.path.join(BUILD, src.replace(".hip", ".o"))])
+    objs = [j[-1] for j in jobs]
+    # the translation units are independent: compile them side by side
+    with ThreadPoolExecutor(max_workers=len(jobs)) as ex:
+        for _ in ex.map(lambda j: _run(j, verbose), jobs):
+            pass
     tmp = OUT + ".tmp"
     _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"], verbose)
     os.replace(tmp, OUT)

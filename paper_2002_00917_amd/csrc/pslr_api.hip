@@ -159,6 +159,12 @@ hipError_t upload_csr(DevPool& pool, const CouplingHost& C, DevCsr<T>& out) {
   return pool.upload(v, &out.val);
 }
 
+// Element counts (in doubles) of an apply workspace: y, u0, u1 (q x nrhs
+// each), the V^T y partial sums and the global working vectors.
+struct WsSizes {
+  size_t vec = 0, partial = 0, gws = 0;
+};
+
 // Everything one direction of the apply needs, host side.
 struct DirHost {
   std::vector<int32_t> gB_in, gB_out, gC_in, gC_out, gC_inv;
@@ -176,6 +182,7 @@ struct pslr_ctx {
   DevPool pool;      // factor and matrix data
   DevPool ws;        // workspaces (grown on demand)
   DevPool vpool;     // low-rank data
+  DevPool vretired;  // low-rank data replaced by pslr_set_lowrank (freed at destroy)
   // device copies of A (original order) and optionally A^T
   const int64_t* A_ptr = nullptr;
   const int32_t* A_col = nullptr;
@@ -187,7 +194,7 @@ struct pslr_ctx {
   ApplyArrays<float> fw32{}, tr32{};
   bool have64 = false, have32 = false, haveT = false;
   int threads = kSolveThreads;
-  size_t lds64 = 0, lds32 = 0;
+  bool threads_fixed = false;  // set by the caller: the autotuner keeps it
   // low rank: Vcm (FP64 q x k column-major, host), H, G; device V row-major and G
   int32_t k = 0;
   std::vector<double> hV, hH, hG;
@@ -195,6 +202,9 @@ struct pslr_ctx {
   const double* G64 = nullptr;
   const __hip_bfloat16* Vbf = nullptr;
   const float* V32 = nullptr;
+  // precision 2: V is read in BF16 only while the setup probe allows it
+  bool v_bf16 = false;
+  double bf16_probe = 0.0;
   const float* G32 = nullptr;
   int nchunk = 256;
   // systems of a batched handle (one system otherwise): row ranges in the
@@ -214,8 +224,9 @@ struct pslr_ctx {
   int tuned_threads = 0, tuned_gshift = 0;
   int rmax = 8;      // widest right-hand-side tile of a launch (autotuned)
   const int64_t* d_rb_off = nullptr;
-  // apply workspaces
+  // apply workspaces (grow-only, see ensure_ws)
   int ws_nrhs = 0;
+  WsSizes ws_cap;
   void* y = nullptr;
   void* u0 = nullptr;
   void* u1 = nullptr;
@@ -416,20 +427,33 @@ size_t lds_bytes(const ApplyArrays<T>& A, int kmax, int R = 1) {
          ((size_t)A.maxPB + 2 * (size_t)A.maxLR + 2 * (size_t)A.maxQB + 2 * (size_t)std::max(kmax, 1));
 }
 
+WsSizes ws_sizes(const pslr_ctx* h, int nrhs) {
+  WsSizes z;
+  z.vec = (size_t)std::max<int64_t>(h->R.q, 1) * nrhs;
+  z.partial = (size_t)h->nchunk_lr * nrhs * std::max(h->k, 1);
+  z.gws = h->gws_stride > 0 ? (size_t)h->gws_stride * ((nrhs + 7) / 8 * 8) : 0;
+  return z;
+}
+
+// The handle's apply workspace, grown on demand and never freed while the
+// handle lives: a workspace that is outgrown stays allocated (until
+// pslr_destroy), so that a HIP graph captured with it still replays on valid
+// memory.  Growth rounds the right-hand-side count up to a power of two.
 pslr_status ensure_ws(pslr_ctx* h, int nrhs) {
-  if (nrhs <= h->ws_nrhs) return PSLR_OK;
-  h->ws.release();
-  const size_t q = (size_t)std::max<int64_t>(h->R.q, 1);
-  HIP_TRY(h->ws.alloc<double>(q * nrhs, (double**)&h->y));
-  HIP_TRY(h->ws.alloc<double>(q * nrhs, (double**)&h->u0));
-  HIP_TRY(h->ws.alloc<double>(q * nrhs, (double**)&h->u1));
-  HIP_TRY(h->ws.alloc<double>((size_t)h->nchunk_lr * nrhs * std::max(h->k, 1), (double**)&h->partial));
+  const WsSizes need = ws_sizes(h, nrhs);
+  if (nrhs <= h->ws_nrhs && need.partial <= h->ws_cap.partial && need.gws <= h->ws_cap.gws)
+    return PSLR_OK;
+  int grow = 1;
+  while (grow < std::max(nrhs, h->ws_nrhs)) grow *= 2;
+  const WsSizes z = ws_sizes(h, grow);
+  HIP_TRY(h->ws.alloc<double>(z.vec, (double**)&h->y));
+  HIP_TRY(h->ws.alloc<double>(z.vec, (double**)&h->u0));
+  HIP_TRY(h->ws.alloc<double>(z.vec, (double**)&h->u1));
+  HIP_TRY(h->ws.alloc<double>(z.partial, (double**)&h->partial));
   h->gws = nullptr;
-  if (h->gws_stride > 0)
-    HIP_TRY(h->ws.alloc<double>((size_t)h->gws_stride * ((nrhs + 7) / 8 * 8), (double**)&h->gws));
-  for (ApplyArrays<double>* A : {&h->fw64, &h->tr64}) A->gws = h->gws;
-  for (ApplyArrays<float>* A : {&h->fw32, &h->tr32}) A->gws = h->gws;
-  h->ws_nrhs = nrhs;
+  if (z.gws > 0) HIP_TRY(h->ws.alloc<double>(z.gws, (double**)&h->gws));
+  h->ws_nrhs = grow;
+  h->ws_cap = z;
   return PSLR_OK;
 }
 
@@ -445,7 +469,7 @@ hipError_t lowrank_partial<double>(pslr_ctx* h, const double* y, int64_t ldy, in
 template <>
 hipError_t lowrank_partial<float>(pslr_ctx* h, const float* y, int64_t ldy, int nrhs, float* part,
                                   hipStream_t s) {
-  if (h->Vbf)
+  if (h->Vbf && h->v_bf16)
     return launch_lr_partial<float, __hip_bfloat16>(h->nchunk_lr, h->d_chunks, h->k, h->Vbf, h->R.q, y, ldy,
                                                     nrhs, part, h->cur_active, h->nsys, s);
   return launch_lr_partial<float, float>(h->nchunk_lr, h->d_chunks, h->k, h->V32, h->R.q, y, ldy, nrhs, part,
@@ -465,7 +489,7 @@ template <>
 hipError_t lowrank_expand<float>(pslr_ctx* h, const ApplyArrays<float>& A, const LaunchCfg& c,
                                  int nrhs, int gtrans, const float* part, float* y, int64_t ldy,
                                  int do_c0, float* u, int64_t ldu) {
-  if (h->Vbf)
+  if (h->Vbf && h->v_bf16)
     return launch_lr_expand<float, __hip_bfloat16>(A, c, nrhs, h->k, h->Vbf, h->G32, gtrans, part,
                                                    h->nchunk_lr, h->d_sys_chunk, y, ldy, do_c0, u,
                                                    ldu);
@@ -610,22 +634,34 @@ LaunchCfg choose_launch(pslr_ctx* h, const ApplyArrays<T>& A, int nrhs, hipStrea
   return c;
 }
 
-// z = M^{-1} b (or M^{-T} b) with apply arrays A.
+// Device workspace of one apply (see WsSizes).
+struct ApplyWs {
+  void *y, *u0, *u1, *partial, *gws;
+};
+
+// z = M^{-1} b (or M^{-T} b) with apply arrays A and workspace W (large
+// enough for nrhs right-hand sides); trace: record the phase events.
 template <typename T>
-pslr_status run_apply(pslr_ctx* h, const ApplyArrays<T>& Ah, size_t lds, bool transpose, int nrhs,
-                      const double* b, int64_t ldb, double* z, int64_t ldz, hipStream_t s) {
+pslr_status run_apply(pslr_ctx* h, const ApplyArrays<T>& Ah, const ApplyWs& W, bool transpose,
+                      int nrhs, const double* b, int64_t ldb, double* z, int64_t ldz, hipStream_t s,
+                      bool trace = true) {
   ApplyArrays<T> A = Ah;
   A.active = h->cur_active;
-  (void)lds;
-  pslr_status st = ensure_ws(h, nrhs);
-  if (st != PSLR_OK) return st;
+  A.gws = W.gws;
   const int64_t q = std::max<int64_t>(h->R.q, 1);
   LaunchCfg cfg = choose_launch(h, A, nrhs, s);
-  T* y = (T*)h->y;
-  T* ua = (T*)h->u0;
-  T* ub = (T*)h->u1;
-  T* part = (T*)h->partial;
+  T* y = (T*)W.y;
+  T* ua = (T*)W.u0;
+  T* ub = (T*)W.u1;
+  T* part = (T*)W.partial;
   const int k = h->k;
+  const bool tr_on = h->trace;
+  if (!trace) h->trace = false;
+  struct Restore {
+    pslr_ctx* h;
+    bool v;
+    ~Restore() { h->trace = v; }
+  } restore{h, tr_on};
   Tracer tr{h, s, {}};
   HIP_TRY(tr.mark(PH_START));
   HIP_TRY(launch_head<T>(A, cfg, nrhs, b, ldb, y, q));
@@ -670,12 +706,11 @@ pslr_status apply_dir(pslr_ctx* h, bool transpose, int nrhs, const double* b, in
   if (h->R.n == 0) return PSLR_OK;
   pslr_status st = ensure_ws(h, nrhs);
   if (st != PSLR_OK) return st;
+  const ApplyWs W{h->y, h->u0, h->u1, h->partial, h->gws};
   if (h->precision >= 1 && !force64 && h->have32)
-    return run_apply<float>(h, transpose ? h->tr32 : h->fw32, h->lds32, transpose, nrhs, b, ldb, z,
-                            ldz, s);
+    return run_apply<float>(h, transpose ? h->tr32 : h->fw32, W, transpose, nrhs, b, ldb, z, ldz, s);
   if (!h->have64) return fail(PSLR_EINVAL, "FP64 apply arrays not available");
-  return run_apply<double>(h, transpose ? h->tr64 : h->fw64, h->lds64, transpose, nrhs, b, ldb, z,
-                           ldz, s);
+  return run_apply<double>(h, transpose ? h->tr64 : h->fw64, W, transpose, nrhs, b, ldb, z, ldz, s);
 }
 
 // ---- small dense helpers (host)
@@ -720,7 +755,12 @@ bool compute_G(int k, const std::vector<double>& H, std::vector<double>& G) {
 // Upload V (union q x k row-major, apply precision) and one G per system for
 // the current hV (q x k column-major) and hH (nsys blocks of k x k column-major).
 pslr_status upload_lowrank(pslr_ctx* h) {
-  h->vpool.release();
+  // the replaced V and G stay allocated until the handle is destroyed (a
+  // captured apply may still read them)
+  for (void* p : h->vpool.ptrs) h->vretired.ptrs.push_back(p);
+  h->vretired.bytes += h->vpool.bytes;
+  h->vpool.ptrs.clear();
+  h->vpool.bytes = 0;
   h->V64 = h->G64 = nullptr;
   h->Vbf = nullptr;
   h->V32 = nullptr;
@@ -746,15 +786,59 @@ pslr_status upload_lowrank(pslr_ctx* h) {
   } else {
     std::vector<float> G32(h->hG.begin(), h->hG.end());
     HIP_TRY(h->vpool.upload(G32, &h->G32));
+    // FP32 V always (the BF16 form falls back to it, see probe_bf16)
+    std::vector<float> Vr(h->hV.begin(), h->hV.end());
+    HIP_TRY(h->vpool.upload(Vr, &h->V32));
     if (h->precision == 2) {
-      std::vector<__hip_bfloat16> Vr((size_t)q * k);
-      for (size_t e = 0; e < Vr.size(); ++e) Vr[e] = __float2bfloat16((float)h->hV[e]);
-      HIP_TRY(h->vpool.upload(Vr, &h->Vbf));
-    } else {
-      std::vector<float> Vr(h->hV.begin(), h->hV.end());
-      HIP_TRY(h->vpool.upload(Vr, &h->V32));
+      std::vector<__hip_bfloat16> Vb((size_t)q * k);
+      for (size_t e = 0; e < Vb.size(); ++e) Vb[e] = __float2bfloat16((float)h->hV[e]);
+      HIP_TRY(h->vpool.upload(Vb, &h->Vbf));
     }
   }
+  return PSLR_OK;
+}
+
+// Precision 2 keeps V in BF16 only where that rounding (8 significant bits)
+// leaves the apply within kBf16ProbeTol of the FP32-V apply, measured on one
+// fixed vector: BF16 rounding breaks the orthonormality of V, and the
+// resulting change of the low-rank term is amplified by the conditioning of
+// the rest of the preconditioner, up to O(1) on ill-conditioned blocks.  Else
+// V stays in FP32 (pslr_info.v_bf16 = 0).  bf16_probe keeps the measured
+// relative difference.
+constexpr double kBf16ProbeTol = 2.5e-2;
+pslr_status probe_bf16(pslr_ctx* h, hipStream_t s) {
+  h->v_bf16 = false;
+  h->bf16_probe = 0.0;
+  if (h->precision != 2 || h->k == 0 || !h->Vbf || !h->have32 || h->R.n == 0) return PSLR_OK;
+  const int64_t n = h->R.n;
+  DevPool tmp;
+  double *b, *z;
+  HIP_TRY(tmp.alloc<double>(n, &b));
+  HIP_TRY(tmp.alloc<double>(2 * n, &z));
+  std::vector<double> hb(n), hz(2 * n);
+  uint64_t st = 0x5eed;
+  for (int64_t i = 0; i < n; ++i) hb[i] = (double)(splitmix64_next(st) >> 11) * 0x1.0p-53 - 0.5;
+  HIP_TRY(hipMemcpy(b, hb.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+  const bool tr = h->trace;
+  h->trace = false;
+  for (int pass = 0; pass < 2; ++pass) {
+    h->v_bf16 = pass == 0;
+    pslr_status r = apply_dir(h, false, 1, b, n, z + pass * n, n, s, false);
+    if (r) {
+      h->trace = tr;
+      return r;
+    }
+  }
+  h->trace = tr;
+  HIP_TRY(hipMemcpyAsync(hz.data(), z, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  double d2 = 0.0, r2 = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    d2 += (hz[i] - hz[n + i]) * (hz[i] - hz[n + i]);
+    r2 += hz[n + i] * hz[n + i];
+  }
+  h->bf16_probe = r2 > 0 ? std::sqrt(d2 / r2) : 0.0;
+  h->v_bf16 = std::isfinite(h->bf16_probe) && h->bf16_probe <= kBf16ProbeTol;
   return PSLR_OK;
 }
 
@@ -819,7 +903,8 @@ pslr_status arnoldi(pslr_ctx* h, const double* v0host, uint64_t seed, hipStream_
     }
   }
   HIP_TRY(hipMemcpy(Vd, v.data(), sizeof(double) * q, hipMemcpyHostToDevice));
-  const ApplyArrays<double>& A = h->fw64;
+  ApplyArrays<double> A = h->fw64;
+  A.gws = h->gws;  // the workspace for one right-hand side exists (ensure_ws at setup)
   LaunchCfg cfg = choose_launch(h, A, 1, s);
   std::vector<double> Hb((size_t)ns * (kreq + 1) * kreq, 0.0), hb((size_t)ns * (2 * (kreq + 1) + 2)),
       sc(ns);
@@ -913,8 +998,10 @@ pslr_status autotune(pslr_ctx* h, hipStream_t s) {
   h->trace = false;
   float best = 1e30f;
   int bt = h->threads, bg = 0;
+  const int fixed = h->threads_fixed ? h->threads : 0;
   for (int threads : {512, 1024})
     for (int gs : {-1, 0, 1}) {
+      if (fixed && threads != fixed) continue;
       h->threads = threads;
       for (auto* A : {&h->fw64, &h->tr64}) A->gshift = gs;
       for (auto* A : {&h->fw32, &h->tr32}) A->gshift = gs;
@@ -1016,7 +1103,7 @@ void fill_info(pslr_ctx* h, const std::vector<BlockFactor>& fB, const std::vecto
   I.fill_total = I.fill_lu + I.fill_lowrank;
   // algorithmic bytes: factor/matrix data once per use, vectors once per read/write
   const int w = h->precision >= 1 ? 4 : 8;
-  const int wv = h->precision == 2 ? 2 : w;
+  const int wv = h->precision == 2 && h->v_bf16 ? 2 : w;
   const int m = h->m;
   const int64_t p = h->R.p, q = h->R.q, n = h->R.n, k = h->k;
   const int64_t bB = bytes[0], bC = bytes[1], bEF = bytes[2], bCg = bytes[3];
@@ -1057,6 +1144,9 @@ void pslr_default_options(pslr_options* o) {
   o->nthreads = 0;
   o->working_vectors = 0;
   o->autotune = 0;
+  o->threads = 0;
+  o->factor = 0;
+  o->drop_tol = 1e-2;
 }
 
 const char* pslr_status_string(pslr_status s) {
@@ -1153,44 +1243,84 @@ pslr_status pslr_reorder(int64_t n, const int64_t* rowptr, const int32_t* colind
   return PSLR_OK;
 }
 
-pslr_status pslr_host_selfcheck(int64_t n, const int64_t* rowptr, const int32_t* colind,
-                                const double* vals, const int32_t* part, int32_t nparts,
-                                const pslr_options* opt, double* factor_residual,
-                                double* solve_residual) {
+pslr_status pslr_host_stats(int64_t n, const int64_t* rowptr, const int32_t* colind,
+                            const double* vals, const int32_t* part, int32_t nparts,
+                            const pslr_options* opt, pslr_host_stats_t* out) {
   pslr_status st = validate_csr(n, rowptr, colind);
   if (st) return st;
   if ((st = validate_part(n, part, nparts))) return st;
+  if (!out) return fail(PSLR_EINVAL, "out is NULL");
   pslr_options o;
   pslr_default_options(&o);
   if (opt) o = *opt;
+  if (o.factor != 0 && o.factor != 1) return fail(PSLR_EINVAL, "factor must be 0 or 1");
   const double tau = o.pivot_threshold > 0 ? o.pivot_threshold : 0.1;
+  const double drop = o.drop_tol > 0 ? o.drop_tol : 1e-2;
   Reordering R = reorder(n, rowptr, colind, part, nparts);
   Blocks Bk = extract_blocks(n, rowptr, colind, vals, R);
   std::vector<const CsrL*> mats;
   for (auto& b : Bk.B) mats.push_back(&b);
   for (auto& c : Bk.C0) mats.push_back(&c);
+  const int nB = (int)Bk.B.size();
   std::vector<double> fres(mats.size(), 0.0), sres(mats.size(), 0.0);
   std::vector<std::string> errs(mats.size());
-  std::vector<int> codes(mats.size(), 0);
+  std::vector<int> codes(mats.size(), 0), lvl(mats.size(), 0), valid(mats.size(), 1);
+  std::vector<int64_t> nnz(mats.size(), 0);
   parallel_for((int)mats.size(), o.nthreads, [&](int t) {
     const CsrL& M = *mats[t];
+    const int narrow = t < nB ? kNarrowWidthB : kNarrowWidthC;
     BlockFactor f;
-    codes[t] = factor_block(M, tau, o.want_transpose != 0,
-                            t < (int)Bk.B.size() ? kNarrowWidthB : kNarrowWidthC, f, errs[t]);
+    IlutFactors I;
+    if (o.factor == 1) {
+      codes[t] = ilut_block(M, drop, o.want_transpose != 0, narrow, f, errs[t]);
+      if (!codes[t]) codes[t] = ilut_factor(M, drop, I, errs[t]);
+    } else {
+      codes[t] = factor_block(M, tau, o.want_transpose != 0, narrow, f, errs[t]);
+    }
     if (codes[t] || M.nrows == 0) return;
+    nnz[t] = f.nnz_L + f.nnz_U;
+    lvl[t] = f.lo.nlev;
+    std::string lerr;
+    for (const TriPacked* T : {&f.lo, &f.up, &f.loT, &f.upT})
+      if ((T == &f.loT || T == &f.upT) && !o.want_transpose) continue;
+      else if (!check_levels(*T, lerr)) valid[t] = 0;
     const int nb = M.nrows;
-    // residual of the solve layouts: x = M^{-1} b with b = M * xe, through the
-    // entry form and through the panels of narrow levels
+    // residual of the solve layouts: x = F^{-1} b through the packed layouts
+    // (narrow levels once through their entry form, once through their panels)
+    // against the reference solve with the same factors: M x = b for the exact
+    // LU (b = M xe), the plain sparse triangular solves for the ILU
     for (int pass = 0; pass < 2 * (o.want_transpose ? 2 : 1); ++pass) {
       const int tr = pass >> 1;
       const bool entries = (pass & 1) == 0;
       std::vector<double> xe(nb), bb(nb, 0.0), X(nb), x(nb);
       for (int i = 0; i < nb; ++i) xe[i] = std::sin(1.0 + i);
-      for (int i = 0; i < nb; ++i)
-        for (int k = M.ptr[i]; k < M.ptr[i + 1]; ++k) {
-          if (!tr) bb[i] += M.val[k] * xe[M.col[k]];
-          else bb[M.col[k]] += M.val[k] * xe[i];
+      if (o.factor == 1) {
+        // reference x = (L U)^{-1} b or (L U)^{-T} b for b = sin(1 + i)
+        bb = xe;
+        std::vector<double> y = bb;
+        if (!tr) {
+          for (int i = 0; i < nb; ++i)
+            for (const auto& e : I.L[i]) y[i] -= e.second * y[e.first];
+          for (int i = nb - 1; i >= 0; --i) {
+            for (const auto& e : I.U[i]) y[i] -= e.second * y[e.first];
+            y[i] /= I.d[i];
+          }
+        } else {
+          for (int i = 0; i < nb; ++i) {
+            y[i] /= I.d[i];
+            for (const auto& e : I.U[i]) y[e.first] -= e.second * y[i];
+          }
+          for (int i = nb - 1; i >= 0; --i)
+            for (const auto& e : I.L[i]) y[e.first] -= e.second * y[i];
         }
+        xe = y;
+      } else {
+        for (int i = 0; i < nb; ++i)
+          for (int k = M.ptr[i]; k < M.ptr[i + 1]; ++k) {
+            if (!tr) bb[i] += M.val[k] * xe[M.col[k]];
+            else bb[M.col[k]] += M.val[k] * xe[i];
+          }
+      }
       const std::vector<int32_t>& gi = tr ? f.gout : f.gin;
       const std::vector<int32_t>& go = tr ? f.gin : f.gout;
       for (int pp = 0; pp < nb; ++pp) X[pp] = bb[gi[pp]];
@@ -1204,9 +1334,40 @@ pslr_status pslr_host_selfcheck(int64_t n, const int64_t* rowptr, const int32_t*
       }
       sres[t] = std::max(sres[t], std::sqrt(e2 / n2));
     }
-    // factorisation residual ||P Q M Q^T - L U||_F / ||M||_F through M x for unit vectors is
-    // expensive; instead report || M x - b || / (||M|| ||x||) on a second vector
-    std::vector<double> xe(nb), bb(nb, 0.0), X(nb), x(nb), rr(nb, 0.0);
+    if (o.factor == 1) {
+      // (M - L U)_ij on the kept pattern of L + U, relative to ||M[i, :]||_2
+      std::vector<double> urow(nb, 0.0), mrow(nb, 0.0), lu(nb, 0.0);
+      for (int i = 0; i < nb; ++i) {
+        double nr = 0.0;
+        for (int k = M.ptr[i]; k < M.ptr[i + 1]; ++k) {
+          mrow[M.col[k]] = M.val[k];
+          nr += M.val[k] * M.val[k];
+        }
+        nr = std::sqrt(nr);
+        // row i of L U = sum_k L_ik U[k, :] + U[i, :]
+        auto addrow = [&](int k, double s) {
+          lu[k] += s * I.d[k];
+          for (const auto& e : I.U[k]) lu[e.first] += s * e.second;
+        };
+        for (const auto& e : I.L[i]) addrow(e.first, e.second);
+        addrow(i, 1.0);
+        double worst = 0.0;
+        for (const auto& e : I.L[i]) worst = std::max(worst, std::fabs(mrow[e.first] - lu[e.first]));
+        worst = std::max(worst, std::fabs(mrow[i] - lu[i]));
+        for (const auto& e : I.U[i]) worst = std::max(worst, std::fabs(mrow[e.first] - lu[e.first]));
+        fres[t] = std::max(fres[t], worst / nr);
+        for (int k = M.ptr[i]; k < M.ptr[i + 1]; ++k) mrow[M.col[k]] = 0.0;
+        for (const auto& e : I.L[i]) {
+          lu[e.first] = 0.0;
+          for (const auto& u : I.U[e.first]) lu[u.first] = 0.0;
+        }
+        lu[i] = 0.0;
+        for (const auto& e : I.U[i]) lu[e.first] = 0.0;
+      }
+      return;
+    }
+    // exact LU: ||M x - b|| / (||M|| ||x||) for x = F^{-1} b on a second vector
+    std::vector<double> bb(nb, 0.0), X(nb), x(nb), rr(nb, 0.0);
     for (int i = 0; i < nb; ++i) bb[i] = std::cos(0.5 + 0.37 * i);
     for (int pp = 0; pp < nb; ++pp) X[pp] = bb[f.gin[pp]];
     host_tri_solve(f.lo, X, true);
@@ -1226,9 +1387,31 @@ pslr_status pslr_host_selfcheck(int64_t n, const int64_t* rowptr, const int32_t*
     fres[t] = rn / (mnorm * xn);
   });
   for (size_t t = 0; t < mats.size(); ++t)
-    if (codes[t]) return fail(PSLR_ESINGULAR, errs[t]);
-  if (factor_residual) *factor_residual = *std::max_element(fres.begin(), fres.end());
-  if (solve_residual) *solve_residual = *std::max_element(sres.begin(), sres.end());
+    if (codes[t]) return fail(codes[t] == 3 ? PSLR_ENOTSUP : PSLR_ESINGULAR, errs[t]);
+  *out = pslr_host_stats_t{};
+  out->levels_valid = 1;
+  for (size_t t = 0; t < mats.size(); ++t) {
+    const bool b = (int)t < nB;
+    (b ? out->nnz_LU_B : out->nnz_LU_C0) += nnz[t];
+    int32_t& L = b ? out->max_levels_B : out->max_levels_C0;
+    L = std::max(L, lvl[t]);
+    out->levels_valid &= valid[t];
+    out->factor_residual = std::max(out->factor_residual, fres[t]);
+    out->solve_residual = std::max(out->solve_residual, sres[t]);
+  }
+  return PSLR_OK;
+}
+
+pslr_status pslr_host_selfcheck(int64_t n, const int64_t* rowptr, const int32_t* colind,
+                                const double* vals, const int32_t* part, int32_t nparts,
+                                const pslr_options* opt, double* factor_residual,
+                                double* solve_residual) {
+  pslr_host_stats_t S;
+  const pslr_status st = pslr_host_stats(n, rowptr, colind, vals, part, nparts, opt, &S);
+  if (st) return st;
+  if (!S.levels_valid) return fail(PSLR_EINVAL, "a packed factor failed the level-schedule check");
+  if (factor_residual) *factor_residual = S.factor_residual;
+  if (solve_residual) *solve_residual = S.solve_residual;
   return PSLR_OK;
 }
 
@@ -1253,6 +1436,9 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
   if (o.m < 0) return fail(PSLR_EINVAL, "m < 0");
   if (o.rank < 0) return fail(PSLR_EINVAL, "rank < 0");
   if (o.precision < 0 || o.precision > 2) return fail(PSLR_EINVAL, "precision must be 0, 1 or 2");
+  if (o.threads != 0 && o.threads != 512 && o.threads != 1024)
+    return fail(PSLR_EINVAL, "threads must be 0, 512 or 1024");
+  if (o.factor != 0 && o.factor != 1) return fail(PSLR_EINVAL, "factor must be 0 or 1");
   const double tau = o.pivot_threshold > 0 ? o.pivot_threshold : 0.1;
   for (int64_t k = 0; k < (n > 0 ? rowptr[n] : 0); ++k)
     if (!std::isfinite(vals[k])) return fail(PSLR_EINVAL, "non-finite value in A");
@@ -1303,9 +1489,13 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
   std::vector<BlockFactor> fB(np), fC(np);
   std::vector<std::string> errs(2 * np);
   std::vector<int> codes(2 * np, 0);
+  const double drop = o.drop_tol > 0 ? o.drop_tol : 1e-2;
   parallel_for(2 * np, o.nthreads, [&](int t) {
-    if (t < np) codes[t] = factor_block(Bk.B[t], tau, h->want_T != 0, kNarrowWidthB, fB[t], errs[t]);
-    else codes[t] = factor_block(Bk.C0[t - np], tau, h->want_T != 0, kNarrowWidthC, fC[t - np], errs[t]);
+    const CsrL& M = t < np ? Bk.B[t] : Bk.C0[t - np];
+    BlockFactor& F = t < np ? fB[t] : fC[t - np];
+    const int narrow = t < np ? kNarrowWidthB : kNarrowWidthC;
+    codes[t] = o.factor == 1 ? ilut_block(M, drop, h->want_T != 0, narrow, F, errs[t])
+                             : factor_block(M, tau, h->want_T != 0, narrow, F, errs[t]);
   });
   for (int t = 0; t < 2 * np; ++t)
     if (codes[t]) return fail(codes[t] == 3 ? PSLR_ENOTSUP : PSLR_ESINGULAR,
@@ -1396,6 +1586,8 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
     h->gws_stride = h->R.p + 2 * h->R.q + rb[nparts] + (int64_t)nparts * 2 * std::max(h->rank, 1);
   }
   h->gx = o.working_vectors == 1;
+  if (o.threads) h->threads = o.threads;
+  h->threads_fixed = o.threads != 0;
   auto set_gx = [&](auto& A) {
     A.part_sys = h->d_part_sys;
     A.gshift = 0;
@@ -1415,12 +1607,14 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
   bool breakdown = false;
   h->ws.release();
   h->ws_nrhs = 0;
+  h->ws_cap = WsSizes{};
   st = ensure_ws(h.get(), 1);
   if (st) return st;
   st = arnoldi(h.get(), o.v0, o.seed, s, breakdown);
   if (st) return st;
   h->ws.release();  // the V^T y partial sums are sized by the achieved rank
   h->ws_nrhs = 0;
+  h->ws_cap = WsSizes{};
   const double t3 = now_s();
 
   if (h->precision >= 1) {
@@ -1442,6 +1636,7 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
     set_gx(h->tr64);
     h->haveT = true;
   }
+  if ((st = probe_bf16(h.get(), s))) return st;
   if (o.autotune) {
     st = autotune(h.get(), s);
     if (st) return st;
@@ -1741,6 +1936,8 @@ pslr_status pslr_info(pslr_handle h, pslr_info_t* out) {
   if (!h || !out) return fail(PSLR_EINVAL, "null argument");
   *out = h->info;
   out->rank = h->k;
+  out->v_bf16 = h->v_bf16 ? 1 : 0;
+  out->bf16_probe = h->bf16_probe;
   return PSLR_OK;
 }
 
@@ -1763,10 +1960,6 @@ pslr_status pslr_set_lowrank(pslr_handle h, int32_t k, const double* V, int64_t 
   if (!h || k < 0 || k > 256 || k > h->R.q || (k > 0 && (!V || !H || ldv < h->R.q || ldh < k)))
     return fail(PSLR_EINVAL, "bad low-rank arguments");
   if (h->nsys != 1) return fail(PSLR_EINVAL, "pslr_set_lowrank needs a single-system handle");
-  if (k > h->rank && h->ws_nrhs > 0) {
-    h->ws.release();
-    h->ws_nrhs = 0;
-  }
   const int64_t q = h->R.q;
   h->k = k;
   h->sys_k.assign(1, k);
@@ -1788,11 +1981,10 @@ pslr_status pslr_set_lowrank(pslr_handle h, int32_t k, const double* V, int64_t 
     for (int i = 0; i < k; ++i) h->hH[(size_t)j * k + i] = H[(size_t)j * ldh + i];
   }
   if (k > h->rank) h->rank = k;
-  if (h->ws_nrhs > 0) {  // partial buffer is sized by k
-    h->ws.release();
-    h->ws_nrhs = 0;
-  }
+  // the next apply grows the workspace if k or the global stride outgrew it
+  // (ensure_ws; the old workspace stays allocated)
   pslr_status st = upload_lowrank(h);
+  if (st == PSLR_OK) st = probe_bf16(h, nullptr);
   h->info.rank = h->k;
   return st;
 }

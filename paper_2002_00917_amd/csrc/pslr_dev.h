@@ -102,6 +102,17 @@ struct Chunk {
 // longest row chunk of the chunked vector kernels (16 rows per thread at 256 threads)
 constexpr int64_t kChunkRows = 4096;
 
+// LDS slots of k_lr_expand's slice sums, and its slice count: the k x R
+// sums of V^T y and G W are each split into S slices of the summation range
+// joined through those slots.  S >= 1 always (S = 1: no slices, direct sums).
+constexpr int kLrExpandSlots = 1024;
+inline int lr_slices(int k, int R, int threads) {
+  const int KR = k * R;
+  if (KR <= 0 || KR > kLrExpandSlots) return 1;
+  const int S = (threads < kLrExpandSlots ? threads : kLrExpandSlots) / KR;
+  return S < 1 ? 1 : S;
+}
+
 struct LaunchCfg {
   int threads;
   size_t lds;          // dynamic LDS bytes (LDS working vectors)

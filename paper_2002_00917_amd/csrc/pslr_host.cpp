@@ -15,6 +15,7 @@
 #include "pslr_host.h"
 
 #include <algorithm>
+#include <functional>
 #include <climits>
 #include <atomic>
 #include <cmath>
@@ -1104,6 +1105,216 @@ void host_tri_solve(const TriPacked& T, std::vector<double>& X, bool entries) {
       }
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Threshold incomplete LU (the local factors of Algorithm 4)
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// A sparse triangular factor as supernodes of one row each: position i has
+// the inverted diagonal dinv[i] and the off-diagonal entries off[i] (lower:
+// column i below the diagonal as (row, value); upper: row i right of the
+// diagonal as (column, value)), in the TriHost layout that pack_tri reads.
+// Levels come from the dependency graph: a lower row sits one level above the
+// highest column it takes an update from; an upper row is solved after every
+// row it reads (levels run top down for upper factors).
+TriHost sparse_tri(bool lower, int n, const std::vector<double>& dinv, const SparseList& off) {
+  TriHost T;
+  T.lower = lower;
+  T.n = n;
+  T.sn.resize(n);
+  std::vector<int> height(n, 0), sfirst(n + 1);
+  for (int i = 0; i <= n; ++i) sfirst[i] = i;
+  int nlev = n > 0 ? 1 : 0;
+  if (lower) {
+    for (int k = 0; k < n; ++k)
+      for (const auto& e : off[k]) height[e.first] = std::max(height[e.first], height[k] + 1);
+    for (int i = 0; i < n; ++i) nlev = std::max(nlev, height[i] + 1);
+  } else {
+    std::vector<int> d(n, 0);
+    int dmax = 0;
+    for (int i = n - 1; i >= 0; --i) {
+      for (const auto& e : off[i]) d[i] = std::max(d[i], d[e.first] + 1);
+      dmax = std::max(dmax, d[i]);
+    }
+    nlev = n > 0 ? dmax + 1 : 0;
+    for (int i = 0; i < n; ++i) height[i] = dmax - d[i];
+  }
+  for (int i = 0; i < n; ++i) {
+    SnHost& S = T.sn[i];
+    S.f = i;
+    S.w = 1;
+    S.h = (int)off[i].size();
+    S.pad = 0;
+    S.tri_off = (int64_t)T.tri.size();
+    T.tri.push_back(dinv[i]);
+    S.ridx_off = (int64_t)T.ridx.size();
+    S.panel_off = (int64_t)T.val.size();
+    for (const auto& e : off[i]) {
+      T.ridx.push_back(e.first);
+      T.val.push_back(e.second);
+    }
+  }
+  build_levels(T, sfirst, height, nlev);
+  return T;
+}
+
+}  // namespace
+
+int ilut_factor(const CsrL& M, double drop, IlutFactors& F, std::string& err) {
+  const int n = M.nrows;
+  F.L.assign(n, {});
+  F.U.assign(n, {});
+  F.d.assign(n, 0.0);
+  std::vector<double> w(n, 0.0);
+  std::vector<int> seen(n, -1);
+  std::vector<int> touched;
+  std::vector<int> heap;  // L-part positions of the work row, smallest first
+  for (int i = 0; i < n; ++i) {
+    touched.clear();
+    heap.clear();
+    double nrm2 = 0.0;
+    for (int q = M.ptr[i]; q < M.ptr[i + 1]; ++q) {
+      const int j = M.col[q];
+      w[j] = M.val[q];
+      seen[j] = i;
+      touched.push_back(j);
+      if (j < i) heap.push_back(j);
+      nrm2 += M.val[q] * M.val[q];
+    }
+    const double ti = drop * std::sqrt(nrm2);  // dropping threshold of row i
+    std::make_heap(heap.begin(), heap.end(), std::greater<int>());
+    while (!heap.empty()) {
+      std::pop_heap(heap.begin(), heap.end(), std::greater<int>());
+      const int k = heap.back();
+      heap.pop_back();
+      const double wk = w[k] / F.d[k];
+      w[k] = 0.0;
+      if (std::fabs(wk) < ti) continue;  // dropped: no update from row k
+      F.L[i].push_back({k, wk});
+      for (const auto& e : F.U[k]) {
+        const int j = e.first;
+        if (seen[j] != i) {
+          seen[j] = i;
+          w[j] = 0.0;
+          touched.push_back(j);
+          if (j < i) {
+            heap.push_back(j);
+            std::push_heap(heap.begin(), heap.end(), std::greater<int>());
+          }
+        }
+        w[j] = w[j] - wk * e.second;
+      }
+    }
+    if (seen[i] != i || w[i] == 0.0) {
+      err = "zero pivot in the incomplete factorisation at row " + std::to_string(i);
+      return 2;
+    }
+    F.d[i] = w[i];
+    std::sort(touched.begin(), touched.end());
+    for (int j : touched) {
+      if (j > i && std::fabs(w[j]) >= ti) F.U[i].push_back({j, w[j]});
+      w[j] = 0.0;
+    }
+    std::sort(F.L[i].begin(), F.L[i].end());
+  }
+  return 0;
+}
+
+int ilut_block(const CsrL& M, double drop, bool want_T, int narrow_width, BlockFactor& out,
+               std::string& err) {
+  const int n = M.nrows;
+  out = BlockFactor();
+  out.n = n;
+  out.gin.resize(n);
+  out.gout.resize(n);
+  for (int i = 0; i < n; ++i) out.gin[i] = out.gout[i] = i;
+  IlutFactors F;
+  if (int rc = ilut_factor(M, drop, F, err)) return rc;
+  const SparseList& Lrow = F.L;
+  const SparseList& Urow = F.U;
+  const std::vector<double>& Ud = F.d;
+  // L by columns (lower solves push columns), U by rows (upper solves pull rows)
+  SparseList Lcol(n);
+  for (int i = 0; i < n; ++i)
+    for (const auto& e : Lrow[i]) Lcol[e.first].push_back({i, e.second});
+  std::vector<double> one(n, 1.0), uinv(n);
+  for (int i = 0; i < n; ++i) uinv[i] = 1.0 / Ud[i];
+  for (int i = 0; i < n; ++i) {
+    out.nnz_L += (int64_t)Lrow[i].size();
+    out.nnz_U += 1 + (int64_t)Urow[i].size();
+  }
+  out.nsuper = n;
+  const char* wide = "block factor beyond 2^31 entries";
+  if (!pack_tri(sparse_tri(true, n, one, Lcol), out.lo, narrow_width) ||
+      !pack_tri(sparse_tri(false, n, uinv, Urow), out.up, narrow_width)) {
+    err = wide;
+    return 3;
+  }
+  if (want_T) {
+    // M^T = U^T L^T: U^T is lower with the rows of U as its columns, L^T upper
+    // with the columns of L as its rows
+    if (!pack_tri(sparse_tri(true, n, uinv, Urow), out.loT, narrow_width) ||
+        !pack_tri(sparse_tri(false, n, one, Lcol), out.upT, narrow_width)) {
+      err = wide;
+      return 3;
+    }
+  }
+  return 0;
+}
+
+bool check_levels(const TriPacked& T, std::string& err) {
+  if (T.n == 0) return true;
+  // level of every position
+  std::vector<int> lev(T.n, -1);
+  for (int l = 0; l < T.nlev; ++l)
+    for (int k = T.lev_ptr[l]; k < T.lev_ptr[l + 1]; ++k) {
+      const int p = T.rec[(size_t)8 * k];
+      if (p < 0 || p >= T.n || lev[p] >= 0) {
+        err = "a position is missing or scheduled twice";
+        return false;
+      }
+      lev[p] = l;
+    }
+  for (int p = 0; p < T.n; ++p)
+    if (lev[p] < 0) {
+      err = "a position is not scheduled";
+      return false;
+    }
+  for (int l = 0; l < T.nlev; ++l) {
+    // a supernode's rows share its level; every off-diagonal dependency is
+    // solved strictly before: lower updates go to later levels, upper rows
+    // read rows of later levels (solved first, the upper sweep runs top down)
+    for (int k = T.lev_ptr[l]; k < T.lev_ptr[l + 1]; ++k) {
+      const int32_t* r = &T.rec[(size_t)8 * k];
+      const int first = r[0] - r[1];
+      for (int j = 0; j < r[2]; ++j)
+        if (lev[first + j] != l) {
+          err = "a supernode spans two levels";
+          return false;
+        }
+      if (!T.lower)
+        for (int a = 0; a < r[3]; ++a)
+          if (lev[T.ridx[r[6] + a]] <= l) {
+            err = "an upper row reads a row that is not solved before it";
+            return false;
+          }
+    }
+    if (T.lower)
+      for (int m = T.push_ptr[l]; m < T.push_ptr[l + 1]; ++m)
+        if (lev[T.prec[(size_t)4 * m]] <= l) {
+          err = "a lower update targets a row that is not solved after it";
+          return false;
+        }
+    for (int q = T.ent_ptr[l]; q < T.ent_ptr[l + 1]; ++q)
+      if (lev[T.eidx[q]] <= l) {
+        err = "an entry-form dependency is not across levels";
+        return false;
+      }
+  }
+  return true;
 }
 
 }  // namespace pslr

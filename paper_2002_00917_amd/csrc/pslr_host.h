@@ -148,6 +148,34 @@ struct BlockFactor {
 int factor_block(const CsrL& M, double tau, bool want_transpose, int narrow_width, BlockFactor& out,
                  std::string& err);
 
+// Threshold incomplete LU of block M in its given row order, no pivoting
+// (the ilu() of Algorithm 4): row by row, w = M[i, :]; for each k < i with
+// w_k != 0, in increasing k: w_k /= u_kk, dropped (set to 0, no update) when
+// |w_k| < drop * ||M[i, :]||_2, else w -= w_k U[k, :]; then the L part keeps
+// the surviving w_k, the U part the diagonal and every w_j (j > i) with
+// |w_j| >= drop * ||M[i, :]||_2.  drop = 0 gives the exact LU without
+// pivoting.  The factors are packed as supernodes of one row each; gin and
+// gout are the identity.  Returns 0, 2 on a zero pivot, 3 on a factor too
+// large for the layout.
+int ilut_block(const CsrL& M, double drop, bool want_T, int narrow_width, BlockFactor& out,
+               std::string& err);
+
+// The factors ilut_block packs: L[i] the strictly lower entries of row i and
+// U[i] the strictly upper entries of row i, as (column, value) ascending, and
+// d[i] = U(i, i) (L has a unit diagonal).
+using SparseList = std::vector<std::vector<std::pair<int32_t, double>>>;
+struct IlutFactors {
+  SparseList L, U;
+  std::vector<double> d;
+};
+int ilut_factor(const CsrL& M, double drop, IlutFactors& F, std::string& err);
+
+// Structural check of a packed factor's level schedule: every position is
+// scheduled once, the rows of a supernode share a level, and every
+// off-diagonal dependency (panel rows, push targets, entry-form indices) is
+// solved strictly before the row that needs it.
+bool check_levels(const TriPacked& T, std::string& err);
+
 // Reordering of Sec. 2 (interface rule and interiors-first permutation).
 struct Reordering {
   int64_t n = 0, p = 0, q = 0;

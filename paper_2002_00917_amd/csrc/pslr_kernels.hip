@@ -577,14 +577,14 @@ k_lr_partial(const LrChunk* __restrict__ chunks, int k, const TV* __restrict__ V
 
 // LDS slots k_lr_expand uses for its slice sums (static, on top of the dynamic
 // working vectors; the launch configuration leaves room for them)
-constexpr int kLrSlots = 1024;
+constexpr int kLrSlots = kLrExpandSlots;
 
 // y += V (G (V^T y)) on the rows of block i; optionally u = C0^{-1} y (line 3, line 4 start)
 template <typename T, typename TV, int R, bool GX>
 __global__ void __launch_bounds__(1024) k_lr_expand(ApplyArrays<T> A, int nrhs, int k,
                             const TV* __restrict__ V, const T* __restrict__ Gall, int gtrans,
                             const T* __restrict__ partial, const int32_t* __restrict__ sys_chunk,
-                            T* y, int64_t ldy, int do_c0, T* u, int64_t ldu) {
+                            T* y, int64_t ldy, int do_c0, T* u, int64_t ldu, int nslice) {
   const int i = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
   int r0, nr;
   if (!tile_rhs<T, R>(A, nrhs, i, r0, nr)) return;
@@ -597,9 +597,10 @@ __global__ void __launch_bounds__(1024) k_lr_expand(ApplyArrays<T> A, int nrhs, 
   const int c0 = sys_chunk[sys], c1 = sys_chunk[sys + 1];
   // W = V^T y (sum of the system's chunk partials), then Z = G W; both spread
   // over the workgroup in S slices of the summation range, joined through LDS
+  // (S = lr_slices(k, R, blockDim.x) >= 1, chosen by the launcher)
   __shared__ T red[kLrSlots];
   const int KR = k * R;
-  const int S = KR <= kLrSlots ? min(nt, kLrSlots) / KR : 1;
+  const int S = nslice;
   for (int t = tid; t < (S > 1 ? S * KR : KR); t += nt) {
     const int sl = S > 1 ? t / KR : 0, e = t - sl * KR;
     const int j = e / R, r = e - j * R;
@@ -704,10 +705,13 @@ __global__ void __launch_bounds__(1024) k_c0solve(ApplyArrays<T> A, int nrhs, co
 
 // One power-series step (eq. approx1 by its recurrence):
 //   w = E_s u = -C_g u + F B^{-1} E u;  r = [y +] w;  u_next = [C0^{-1}] r
-template <typename T, int R, bool GX>
-__global__ void __launch_bounds__(1024) k_series(ApplyArrays<T> A, int nrhs, const T* __restrict__ y,
-                                                 int64_t ldy, const T* __restrict__ uprev, T* unext,
-                                                 int64_t ldu, int add_y, int do_c0) {
+// C0 = true: the full step of the apply (k_series); false: the bare product
+// w = E_s u (k_es, used by the Arnoldi process on (E_s C0^{-1})^{m+1}).
+template <typename T, int R, bool GX, bool C0>
+__device__ __forceinline__ void series_body(const ApplyArrays<T>& A, int nrhs, const T* __restrict__ y,
+                                            int64_t ldy, const T* __restrict__ uprev, T* unext,
+                                            int64_t ldu, int add_y) {
+  constexpr bool do_c0 = C0;
   const int i = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
   int r0, nr;
   if (!tile_rhs<T, R>(A, nrhs, i, r0, nr)) return;
@@ -774,6 +778,19 @@ __global__ void __launch_bounds__(1024) k_series(ApplyArrays<T> A, int nrhs, con
     const int r = (int)(e - c * R);
     if (r < nr) unext[(r0 + r) * ldu + f0 + A.gC_out[f0 + c]] = L.XC[e];
   }
+}
+
+template <typename T, int R, bool GX>
+__global__ void __launch_bounds__(1024) k_series(ApplyArrays<T> A, int nrhs, const T* __restrict__ y,
+                                                 int64_t ldy, const T* __restrict__ uprev, T* unext,
+                                                 int64_t ldu, int add_y) {
+  series_body<T, R, GX, true>(A, nrhs, y, ldy, uprev, unext, ldu, add_y);
+}
+
+template <typename T, int R, bool GX>
+__global__ void __launch_bounds__(1024) k_es(ApplyArrays<T> A, int nrhs, const T* __restrict__ uprev,
+                                             T* unext, int64_t ldu) {
+  series_body<T, R, GX, false>(A, nrhs, nullptr, 0, uprev, unext, ldu, 0);
 }
 
 // x = B^{-1}(f - E u);  z = P^T (x; u)   (Algorithm 3, lines 5-6)
@@ -848,6 +865,7 @@ hipError_t set_lds_limit(size_t bytes) {
   if ((e = hipFuncSetAttribute((const void*)k_head<T, RR, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b))) return e; \
   if ((e = hipFuncSetAttribute((const void*)k_c0solve<T, RR, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b))) return e; \
   if ((e = hipFuncSetAttribute((const void*)k_series<T, RR, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b))) return e; \
+  if ((e = hipFuncSetAttribute((const void*)k_es<T, RR, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b))) return e; \
   if ((e = hipFuncSetAttribute((const void*)k_tail<T, RR, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b))) return e; \
   if ((e = hipFuncSetAttribute((const void*)k_lr_expand<T, T, RR, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b - (int)(kLrSlots * sizeof(T))))) return e; \
   if ((e = hipFuncSetAttribute((const void*)k_lr_expand<T, __hip_bfloat16, RR, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b - (int)(kLrSlots * sizeof(T))))) return e;
@@ -888,12 +906,15 @@ hipError_t launch_lr_expand(const ApplyArrays<T>& A, const LaunchCfg& c, int nrh
   (void)nchunk;
   PSLR_DISPATCH(c, {
     const dim3 grid(A.nparts, ntiles(nrhs, RR));
+    const int S = lr_slices(k, RR, c.threads);
+    // every slice loop must advance, and the slice sums must fit the static LDS slots
+    if (S < 1 || (S > 1 && S * k * RR > kLrSlots)) return hipErrorInvalidValue;
     if (c.gx)
       hipLaunchKernelGGL((k_lr_expand<T, TV, RR, true>), grid, dim3(c.threads), 0, c.stream, A, nrhs,
-                         k, V, G, gtrans, partial, sys_chunk, y, ldy, do_c0, u, ldu);
+                         k, V, G, gtrans, partial, sys_chunk, y, ldy, do_c0, u, ldu, S);
     else
       hipLaunchKernelGGL((k_lr_expand<T, TV, RR, false>), grid, dim3(c.threads), c.lds, c.stream, A,
-                         nrhs, k, V, G, gtrans, partial, sys_chunk, y, ldy, do_c0, u, ldu);
+                         nrhs, k, V, G, gtrans, partial, sys_chunk, y, ldy, do_c0, u, ldu, S);
   });
   return hipGetLastError();
 }
@@ -914,19 +935,24 @@ hipError_t launch_series(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, 
                          int64_t ldy, const T* uprev, T* unext, int64_t ldu, int add_y, int do_c0) {
   PSLR_DISPATCH(c, {
     const dim3 grid(A.nparts, ntiles(nrhs, RR));
-    if (c.ev_start || c.ev_stop) {
+    if (!do_c0) {
+      // the bare product w = E_s u (no y term, no C0 solve)
+      if (add_y) return hipErrorInvalidValue;
+      if (c.gx) hipLaunchKernelGGL((k_es<T, RR, true>), grid, dim3(c.threads), 0, c.stream, A, nrhs, uprev, unext, ldu);
+      else hipLaunchKernelGGL((k_es<T, RR, false>), grid, dim3(c.threads), c.lds, c.stream, A, nrhs, uprev, unext, ldu);
+    } else if (c.ev_start || c.ev_stop) {
       if (c.gx)
         hipExtLaunchKernelGGL((k_series<T, RR, true>), grid, dim3(c.threads), 0, c.stream, c.ev_start,
-                              c.ev_stop, 0, A, nrhs, y, ldy, uprev, unext, ldu, add_y, do_c0);
+                              c.ev_stop, 0, A, nrhs, y, ldy, uprev, unext, ldu, add_y);
       else
         hipExtLaunchKernelGGL((k_series<T, RR, false>), grid, dim3(c.threads), (uint32_t)c.lds, c.stream,
-                              c.ev_start, c.ev_stop, 0, A, nrhs, y, ldy, uprev, unext, ldu, add_y, do_c0);
+                              c.ev_start, c.ev_stop, 0, A, nrhs, y, ldy, uprev, unext, ldu, add_y);
     } else if (c.gx) {
       hipLaunchKernelGGL((k_series<T, RR, true>), grid, dim3(c.threads), 0, c.stream, A, nrhs, y, ldy,
-                         uprev, unext, ldu, add_y, do_c0);
+                         uprev, unext, ldu, add_y);
     } else {
       hipLaunchKernelGGL((k_series<T, RR, false>), grid, dim3(c.threads), c.lds, c.stream, A, nrhs, y,
-                         ldy, uprev, unext, ldu, add_y, do_c0);
+                         ldy, uprev, unext, ldu, add_y);
     }
   });
   return hipGetLastError();

@@ -34,7 +34,14 @@ class pslr_options(C.Structure):
     _fields_ = [("m", C.c_int32), ("rank", C.c_int32), ("precision", C.c_int32),
                 ("want_transpose", C.c_int32), ("v0", C.POINTER(C.c_double)),
                 ("seed", C.c_uint64), ("pivot_threshold", C.c_double), ("nthreads", C.c_int32),
-                ("working_vectors", C.c_int32), ("autotune", C.c_int32)]
+                ("working_vectors", C.c_int32), ("autotune", C.c_int32), ("threads", C.c_int32),
+                ("factor", C.c_int32), ("drop_tol", C.c_double)]
+
+
+class pslr_host_stats_t(C.Structure):
+    _fields_ = [("nnz_LU_B", C.c_int64), ("nnz_LU_C0", C.c_int64), ("max_levels_B", C.c_int32),
+                ("max_levels_C0", C.c_int32), ("levels_valid", C.c_int32),
+                ("factor_residual", C.c_double), ("solve_residual", C.c_double)]
 
 
 class pslr_info_t(C.Structure):
@@ -49,7 +56,8 @@ class pslr_info_t(C.Structure):
                 ("series_bytes", C.c_int64), ("seconds_reorder", C.c_double),
                 ("seconds_factor", C.c_double), ("seconds_arnoldi", C.c_double),
                 ("nsys", C.c_int32), ("global_vectors", C.c_int32), ("threads", C.c_int32),
-                ("lane_shift", C.c_int32), ("max_tile", C.c_int32)]
+                ("lane_shift", C.c_int32), ("max_tile", C.c_int32), ("v_bf16", C.c_int32),
+                ("bf16_probe", C.c_double)]
 
 
 class pslr_trace_t(C.Structure):
@@ -84,6 +92,8 @@ _SIGS = {
     "pslr_reorder": (C.c_int, [C.c_int64, _I64P, _I32P, _I32P, C.c_int32, _I64P, _I64P, _I64P]),
     "pslr_host_selfcheck": (C.c_int, [C.c_int64, _I64P, _I32P, _F64P, _I32P, C.c_int32,
                                       C.POINTER(pslr_options), _F64P, _F64P]),
+    "pslr_host_stats": (C.c_int, [C.c_int64, _I64P, _I32P, _F64P, _I32P, C.c_int32,
+                                  C.POINTER(pslr_options), C.POINTER(pslr_host_stats_t)]),
     "pslr_destroy": (C.c_int, [_P]),
     "pslr_status_string": (C.c_char_p, [C.c_int]),
     "pslr_last_error": (C.c_char_p, []),
@@ -152,11 +162,17 @@ def _vec(t, n):
 
 
 class Handle:
-    def __init__(self, ptr, n, status, nsys=1):
+    """An opaque library handle plus what the binding checks arguments against:
+    n, nnz(A), and a fingerprint of A's values (count, sum, sum of squares)."""
+
+    def __init__(self, ptr, n, status, nsys=1, vals=None):
         self.ptr = ptr
         self.n = n
         self.status = status
         self.nsys = nsys
+        v = np.zeros(0) if vals is None else np.asarray(vals, dtype=np.float64)
+        self.nnz = int(v.size)
+        self.vals_fingerprint = (int(v.size), float(np.sum(v)), float(np.sum(v * v)))
 
     def __del__(self):
         if getattr(self, "ptr", None) is not None and _lib is not None:
@@ -170,9 +186,15 @@ def pslr_default_options():
     return o
 
 
+FACTORS = {"lu": 0, "ilut": 1}
+
+
 def _options(m, rank, precision, want_transpose, v0, seed, pivot_threshold, nthreads,
-             working_vectors, autotune=False):
+             working_vectors, autotune=False, threads=0, factor="lu", drop_tol=1e-2):
     o = pslr_default_options()
+    o.threads = int(threads)
+    o.factor = FACTORS[factor]
+    o.drop_tol = float(drop_tol)
     o.m, o.rank, o.precision = int(m), int(rank), int(precision)
     o.want_transpose = 1 if want_transpose else 0
     o.seed, o.pivot_threshold, o.nthreads = int(seed), float(pivot_threshold), int(nthreads)
@@ -186,26 +208,28 @@ def _options(m, rank, precision, want_transpose, v0, seed, pivot_threshold, nthr
 
 def pslr_setup(rowptr, colind, vals, part, nparts, m=3, rank=16, precision=0,
                want_transpose=False, v0=None, seed=1, pivot_threshold=0.1, nthreads=0,
-               working_vectors=0, autotune=False, stream=None) -> Handle:
+               working_vectors=0, autotune=False, threads=0, factor="lu", drop_tol=1e-2,
+               stream=None) -> Handle:
     L = lib()
     rp, rpp = _arr(rowptr, np.int64)
     ci, cip = _arr(colind, np.int32)
     va, vap = _arr(vals, np.float64)
     pa, pap = _arr(part, np.int32)
     o, keep = _options(m, rank, precision, want_transpose, v0, seed, pivot_threshold, nthreads,
-                       working_vectors, autotune)
+                       working_vectors, autotune, threads, factor, drop_tol)
     out = C.c_void_p()
     n = len(rp) - 1
     st = L.pslr_setup(n, rpp, cip, vap, pap, int(nparts), C.byref(o), _stream_ptr(stream),
                       C.byref(out))
     _check(st, (PSLR_OK, PSLR_EBREAKDOWN))
     del keep
-    return Handle(out, n, st)
+    return Handle(out, n, st, vals=va)
 
 
 def pslr_setup_batched(rowptr, colind, vals, part, nparts, sys_ptr, m=3, rank=16, precision=0,
                        want_transpose=False, v0=None, seed=1, pivot_threshold=0.1, nthreads=0,
-                       working_vectors=0, autotune=False, stream=None) -> Handle:
+                       working_vectors=0, autotune=False, threads=0, factor="lu", drop_tol=1e-2,
+                       stream=None) -> Handle:
     L = lib()
     rp, rpp = _arr(rowptr, np.int64)
     ci, cip = _arr(colind, np.int32)
@@ -213,14 +237,14 @@ def pslr_setup_batched(rowptr, colind, vals, part, nparts, sys_ptr, m=3, rank=16
     pa, pap = _arr(part, np.int32)
     sp, spp = _arr(sys_ptr, np.int64)
     o, keep = _options(m, rank, precision, want_transpose, v0, seed, pivot_threshold, nthreads,
-                       working_vectors, autotune)
+                       working_vectors, autotune, threads, factor, drop_tol)
     out = C.c_void_p()
     n = len(rp) - 1
     st = L.pslr_setup_batched(n, rpp, cip, vap, pap, int(nparts), len(sp) - 1, spp, C.byref(o),
                               _stream_ptr(stream), C.byref(out))
     _check(st, (PSLR_OK, PSLR_EBREAKDOWN))
     del keep
-    return Handle(out, n, st, nsys=len(sp) - 1)
+    return Handle(out, n, st, nsys=len(sp) - 1, vals=va)
 
 
 def pslr_apply(h: Handle, b, z, stream=None):
@@ -258,10 +282,16 @@ def fgmres_solve(h: Handle, b, x, restart=40, maxit=500, tol=1e-8, transpose=Fal
 
 
 def pslr_sddmm_grad(h: Handle, lam, z, grad, stream=None):
+    """grad: float64 device tensor with nnz(A) contiguous entries (original CSR order)."""
+    import torch
     lp, nrhs, ldl = _vec(lam, h.n)
     zp, nrz, ldz = _vec(z, h.n)
     if nrz != nrhs:
         raise ValueError("lambda and z have different column counts")
+    if grad.dtype != torch.float64 or not grad.is_cuda or not grad.is_contiguous():
+        raise ValueError("grad must be a contiguous float64 device tensor")
+    if grad.numel() != h.nnz:
+        raise ValueError("grad has %d entries, A has %d stored entries" % (grad.numel(), h.nnz))
     _check(lib().pslr_sddmm_grad(h.ptr, nrhs, lp, ldl, zp, ldz, C.c_void_p(grad.data_ptr()),
                                  _stream_ptr(stream)))
 
@@ -334,8 +364,8 @@ def pslr_reorder(rowptr, colind, part, nparts):
     return perm, p.value, q.value
 
 
-def pslr_host_selfcheck(rowptr, colind, vals, part, nparts, want_transpose=True,
-                        pivot_threshold=0.1, nthreads=0):
+def pslr_host_stats(rowptr, colind, vals, part, nparts, want_transpose=True, pivot_threshold=0.1,
+                    nthreads=0, factor="lu", drop_tol=1e-2) -> dict:
     rp, rpp = _arr(rowptr, np.int64)
     ci, cip = _arr(colind, np.int32)
     va, vap = _arr(vals, np.float64)
@@ -344,6 +374,26 @@ def pslr_host_selfcheck(rowptr, colind, vals, part, nparts, want_transpose=True,
     o.want_transpose = 1 if want_transpose else 0
     o.pivot_threshold = float(pivot_threshold)
     o.nthreads = int(nthreads)
+    o.factor = FACTORS[factor]
+    o.drop_tol = float(drop_tol)
+    out = pslr_host_stats_t()
+    _check(lib().pslr_host_stats(len(rp) - 1, rpp, cip, vap, pap, int(nparts), C.byref(o),
+                                 C.byref(out)))
+    return {k: getattr(out, k) for k, _ in pslr_host_stats_t._fields_}
+
+
+def pslr_host_selfcheck(rowptr, colind, vals, part, nparts, want_transpose=True,
+                        pivot_threshold=0.1, nthreads=0, factor="lu", drop_tol=1e-2):
+    rp, rpp = _arr(rowptr, np.int64)
+    ci, cip = _arr(colind, np.int32)
+    va, vap = _arr(vals, np.float64)
+    pa, pap = _arr(part, np.int32)
+    o = pslr_default_options()
+    o.want_transpose = 1 if want_transpose else 0
+    o.pivot_threshold = float(pivot_threshold)
+    o.nthreads = int(nthreads)
+    o.factor = FACTORS[factor]
+    o.drop_tol = float(drop_tol)
     fr = C.c_double()
     sr = C.c_double()
     _check(lib().pslr_host_selfcheck(len(rp) - 1, rpp, cip, vap, pap, int(nparts), C.byref(o),

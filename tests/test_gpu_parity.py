@@ -1,20 +1,28 @@
 """Parity of the HIP library (through the C ABI) with the CPU oracle, on the GPU.
 
-Tolerances (normwise relative, per right-hand side):
-  FP64 apply / transposed apply  <= max(1e-12, 20 kappa eps64)
-  FP32 apply (FP32 V)            <= max(1e-5,  20 kappa eps32)
-  FP32 apply with BF16 V         same bound, against the oracle run with the
-                                 same BF16-rounded V (the rounding itself is
-                                 reported, not bounded: BF16 keeps 8 bits)
-  FGMRES                         true relative residual <= 1e-8, iteration
-                                 count within 2 of the oracle's with the same V, H
-where kappa is the largest 2-norm condition number of the diagonal blocks B_i
-and C_i.  Both sides are backward stable, so they can differ by the standard
-forward-error bound kappa * eps; the 2D 64^2 workload's shift lies 4.7e-5
-from an eigenvalue of its 31 x 31 subdomain operator (kappa(B_i) = 1.7e5).
-"""
-import os
+Every comparison imports the oracle's V and H into the library (never the
+other way), so both sides apply the same operator of Algorithm 3.
 
+Bounds, checked per right-hand side both normwise (||z - z_o|| / ||z_o||) and
+elementwise (max_i |z_i - z_o,i| / max_i |z_o,i|):
+  FP64 apply and transposed apply   1e-12
+  FP32 apply (FP32 V)               1e-5
+  FP32 apply with BF16 V            1e-5 against the oracle run with the same
+                                    BF16-rounded V; against the exact-V oracle
+                                    a per-case bound (BF16_VS_EXACT)
+  FGMRES                            true relative residual <= tol
+except the cases in TOL64 / TOL32, whose diagonal blocks are ill conditioned:
+there both sides are backward stable and may differ by the forward-error
+bound kappa * eps (kappa = largest 2-norm condition number of the B_i, C_i),
+and the bound is at most three times the error measured on the MI355X:
+  2D 64^2, sigma 4.7e-5 from an eigenvalue of the 31 x 31 subdomain operator,
+    kappa(B_i) = 1.7e5: kappa * eps64 = 3.7e-11 (measured up to 4.9e-11),
+    kappa * eps32 = 1.0e-2 (measured up to 1.1e-2);
+  3D 9^3, kappa = 1.6e2: kappa * eps32 = 9.2e-6 (measured up to 4.4e-5; the
+    FP32 solves also round the factors, so a few times kappa * eps32);
+  the 24^3 upwind case (C4-shaped), kappa = 2.6e3: kappa * eps32 = 1.5e-4
+    (measured up to 2.6e-5).
+"""
 import numpy as np
 import pytest
 
@@ -28,6 +36,19 @@ from oracle import adjoint as oadj
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
+
+# per-case bounds where kappa * eps exceeds the benchmark spec's 1e-12 / 1e-5
+TOL64 = {"c1": 1.5e-10}
+TOL32 = {"c1": 3.3e-2, "lap3d_9_2x2x2": 8.4e-5, "c4_shaped": 1.5e-4}
+# BF16 storage of V (8 significant bits) against the exact-V preconditioner,
+# where the library keeps it (pslr_info.v_bf16): the rounding breaks V's
+# orthonormality, and the change of the low-rank term is amplified by the
+# conditioning of the rest of the preconditioner.  Three times the measured
+# difference.  On the 2D 64^2 workload (kappa(B_i) = 1.7e5) the difference is
+# O(10): the setup probe withdraws BF16 there and V stays in FP32.
+BF16_VS_EXACT = {"lap2d_10_2x2": 2.1e-2, "lap2d_37x23_3x5": 2.4e-3, "lap3d_9_2x2x2": 2.7e-2,
+                 "convdiff_11_rg7": 7.5e-4}
+BF16_WITHDRAWN = {"c1"}
 
 
 def _dev():
@@ -45,28 +66,26 @@ def _tens(x):
     return torch.tensor(np.ascontiguousarray(x.T), dtype=torch.float64, device=_dev())
 
 
-def block_kappa(A, lab):
-    """Largest 2-norm condition number of the diagonal blocks B_i and C_i."""
-    blk = opslr.make_blocks(A.to_scipy(), lab)
-    kap = 1.0
-    for M, ptr in ((blk.B, blk.int_ptr), (blk.C0, blk.if_ptr)):
-        for i in range(len(ptr) - 1):
-            a, b = int(ptr[i]), int(ptr[i + 1])
-            if b > a:
-                kap = max(kap, np.linalg.cond(M[a:b, a:b].toarray()))
-    return kap
-
-
-def tol64(A, lab):
-    return max(1e-12, 20.0 * block_kappa(A, lab) * np.finfo(np.float64).eps)
-
-
-def tol32(A, lab):
-    return max(1e-5, 20.0 * block_kappa(A, lab) * np.finfo(np.float32).eps)
-
-
 def relerr(a, b):
+    """Normwise relative error per column."""
     return np.linalg.norm(a - b, axis=0) / np.linalg.norm(b, axis=0)
+
+
+def maxerr(a, b):
+    """Elementwise error per column: max |a - b| over max |b|."""
+    return np.abs(a - b).max(axis=0) / np.abs(b).max(axis=0)
+
+
+def _fmt(a):
+    return "[" + " ".join("%.2e" % v for v in np.ravel(a)) + "]"
+
+
+def check(name, what, z, ref, tol):
+    e2, ei = relerr(z, ref), maxerr(z, ref)
+    print("%s %s: normwise %s elementwise %s (max %.2e / %.2e) bound %.1e"
+          % (name, what, _fmt(e2), _fmt(ei), e2.max(), ei.max(), tol), flush=True)
+    assert np.all(e2 <= tol), (what, e2, tol)
+    assert np.all(ei <= tol), (what, ei, tol)
 
 
 def tiny_cases():
@@ -88,14 +107,14 @@ CASES = tiny_cases()
 IDS = [c[0] for c in CASES]
 
 
-def _pair(A, lab, m, rank, precision=0, want_T=True):
+def _pair(A, lab, m, rank, precision=0, want_T=True, **kw):
     """Library handle with the oracle's Arnoldi V, H imported, and the oracle preconditioner."""
     nparts = int(lab.max()) + 1
     blk = opslr.make_blocks(A.to_scipy(), lab)
     v0 = wl.start_vector(blk.q, 17)
     pre = opslr.PSLR(A.to_scipy(), lab, m, rank, v0=v0)
-    h = P.pslr_setup(A.rowptr, A.colind, A.vals, lab, nparts, m=m, rank=rank, precision=precision,
-                     want_transpose=want_T, v0=v0)
+    h = P.pslr_setup(A.rowptr, A.colind, A.vals, lab, nparts, m=m, rank=0, precision=precision,
+                     want_transpose=want_T, **kw)
     P.pslr_set_lowrank(h, pre.V, pre.H)
     return h, pre
 
@@ -107,17 +126,12 @@ def test_apply_fp64_matches_oracle(name, A, lab, m, rank):
     b = wl.normal_rhs(A.n, 3, 5)
     z = torch.zeros((3, A.n), dtype=torch.float64, device=_dev())
     P.pslr_apply(h, _tens(b), z)
-    torch.cuda.synchronize()
-    err = relerr(_cols(z), pre.apply(b))
-    tol = tol64(A, lab)
-    print(name, "fp64 apply relerr", err, "tol", tol)
-    assert np.all(err <= tol)
     zt = torch.zeros_like(z)
     P.pslr_apply_transpose(h, _tens(b), zt)
     torch.cuda.synchronize()
-    errt = relerr(_cols(zt), pre.apply_transpose(b))
-    print(name, "fp64 apply_transpose relerr", errt)
-    assert np.all(errt <= tol)
+    tol = TOL64.get(name, 1e-12)
+    check(name, "fp64 apply", _cols(z), pre.apply(b), tol)
+    check(name, "fp64 apply_transpose", _cols(zt), pre.apply_transpose(b), tol)
 
 
 @pytest.mark.parametrize("name,A,lab,m,rank", CASES, ids=IDS)
@@ -130,11 +144,9 @@ def test_apply_fp32_matches_oracle(name, A, lab, m, rank):
     zt = torch.zeros_like(z)
     P.pslr_apply_transpose(h, _tens(b), zt)
     torch.cuda.synchronize()
-    err = relerr(_cols(z), pre.apply(b))
-    errt = relerr(_cols(zt), pre.apply_transpose(b))
-    tol = tol32(A, lab)
-    print(name, "fp32 apply relerr", err, "transpose", errt, "tol", tol)
-    assert np.all(err <= tol) and np.all(errt <= tol)
+    tol = TOL32.get(name, 1e-5)
+    check(name, "fp32 apply", _cols(z), pre.apply(b), tol)
+    check(name, "fp32 apply_transpose", _cols(zt), pre.apply_transpose(b), tol)
 
 
 def bf16_round(x):
@@ -149,17 +161,22 @@ def bf16_round(x):
 def test_apply_bf16_lowrank_matches_oracle(name, A, lab, m, rank):
     print("case", name, flush=True)
     h, pre = _pair(A, lab, m, rank, precision=2)
+    info = P.pslr_info(h)
+    print(name, "v_bf16", info["v_bf16"], "bf16_probe %.2e" % info["bf16_probe"], flush=True)
     b = wl.normal_rhs(A.n, 2, 7)
     z = torch.zeros((2, A.n), dtype=torch.float64, device=_dev())
     P.pslr_apply(h, _tens(b), z)
     torch.cuda.synchronize()
     exact = pre.apply(b)
+    if name in BF16_WITHDRAWN:
+        assert info["v_bf16"] == 0 and info["bf16_probe"] > 2.5e-2
+        check(name, "precision-2 apply (V kept in FP32) vs exact-V oracle", _cols(z), exact,
+              TOL32.get(name, 1e-5))
+        return
+    assert info["v_bf16"] == 1 and info["bf16_probe"] <= 2.5e-2
     pre.set_lowrank(bf16_round(pre.V), pre.H)
-    err = relerr(_cols(z), pre.apply(b))
-    tol = tol32(A, lab)
-    print(name, "bf16-V apply relerr vs rounded-V oracle", err, "vs exact-V oracle",
-          relerr(_cols(z), exact), "tol", tol)
-    assert np.all(err <= tol)
+    check(name, "bf16-V apply vs rounded-V oracle", _cols(z), pre.apply(b), TOL32.get(name, 1e-5))
+    check(name, "bf16-V apply vs exact-V oracle", _cols(z), exact, BF16_VS_EXACT[name])
 
 
 @pytest.mark.parametrize("name,A,lab,m,rank", CASES, ids=IDS)
@@ -182,7 +199,7 @@ def test_library_arnoldi_invariants(name, A, lab, m, rank):
     Vo, Ho, _, _ = opslr.arnoldi(pre.err_op, v0, k)
     Pl, Po = V @ V.T, Vo @ Vo.T
     print(name, "projector difference", np.abs(Pl - Po).max())
-    assert np.abs(Pl - Po).max() < 1e-4
+    assert np.abs(Pl - Po).max() < 1e-6
 
 
 def test_fgmres_c1_converges_like_oracle():
@@ -218,6 +235,9 @@ def test_fgmres_multi_rhs_and_transpose():
     xr = _cols(x)
     for j in range(4):
         assert np.linalg.norm(b[:, j] - As @ xr[:, j]) <= 1.01e-10 * np.linalg.norm(b[:, j])
+        _, ito, _, _ = okry.fgmres(As, b[:, j], pre.apply, restart=20, tol=1e-10)
+        print("multi-rhs column", j, "its lib", its[j], "oracle", ito)
+        assert abs(int(its[j]) - ito) <= 1
     xt = torch.zeros_like(x)
     st, its, rel = P.fgmres_solve(h, _tens(b), xt, restart=20, maxit=500, tol=1e-10, transpose=True)
     assert st == P.PSLR_OK and np.all(rel <= 1e-10)
@@ -248,6 +268,11 @@ def test_sddmm_gradient_matches_oracle():
     torch.cuda.synchronize()
     go = oadj.pattern_grad(A.to_scipy(), lam, zz)
     assert np.abs(g.cpu().numpy() - go).max() <= 1e-14 * np.abs(go).max()
+    # a gradient buffer of the wrong length or type is rejected before any launch
+    with pytest.raises(ValueError):
+        P.pslr_sddmm_grad(h, _tens(lam), _tens(zz), torch.zeros(A.nnz - 1, dtype=torch.float64, device=_dev()))
+    with pytest.raises(ValueError):
+        P.pslr_sddmm_grad(h, _tens(lam), _tens(zz), torch.zeros(A.nnz, dtype=torch.float32, device=_dev()))
 
 
 def test_edge_cases():
@@ -267,26 +292,87 @@ def test_edge_cases():
     P.pslr_apply(h, torch.zeros((2, A.n), dtype=torch.float64, device=_dev()), z0)
     torch.cuda.synchronize()
     assert float(z0.abs().max()) == 0.0
-    # many small parts, some without interior unknowns, rank above q is capped
+    # many small parts, some without interior unknowns; a rank above q is capped
     A = wl.laplacian2d(9, 0.1)
     lab = opart.geometric_labels((9, 9), (4, 4))
     nparts = 16
     blk = opslr.make_blocks(A.to_scipy(), lab)
-    h = P.pslr_setup(A.rowptr, A.colind, A.vals, lab, nparts, m=2, rank=500,
-                     v0=wl.start_vector(blk.q, 3))
+    v0 = wl.start_vector(blk.q, 3)
+    h = P.pslr_setup(A.rowptr, A.colind, A.vals, lab, nparts, m=2, rank=500, v0=v0)
     assert P.pslr_info(h)["rank"] <= min(blk.q, 256)
-    pre = opslr.PSLR(A.to_scipy(), lab, 2, 0)
-    V, H = P.pslr_get_lowrank(h)
-    pre.set_lowrank(V, H)
+    # parity there with the oracle's own Arnoldi basis imported
+    pre = opslr.PSLR(A.to_scipy(), lab, 2, 500, v0=v0)
+    P.pslr_set_lowrank(h, pre.V, pre.H)
     b = wl.normal_rhs(A.n, 2, 9)
     z = torch.zeros((2, A.n), dtype=torch.float64, device=_dev())
     P.pslr_apply(h, _tens(b), z)
     torch.cuda.synchronize()
-    assert np.all(relerr(_cols(z), pre.apply(b)) < 1e-10)
+    check("lap2d_9_4x4", "fp64 apply, full rank", _cols(z), pre.apply(b), 1e-12)
     # invalid arguments are rejected
     with pytest.raises(P.PslrError) as ei:
         P.pslr_setup(A.rowptr, A.colind, A.vals, lab, nparts, m=-1, rank=2)
     assert ei.value.status == P.PSLR_EINVAL
+    with pytest.raises(P.PslrError) as ei:
+        P.pslr_setup(A.rowptr, A.colind, A.vals, lab, nparts, m=2, rank=2, threads=256)
+    assert ei.value.status == P.PSLR_EINVAL
+
+
+def test_lr_expand_slices_512_threads_rank96_8rhs():
+    """Regression: with 512-thread workgroups and k x R between 513 and 1024
+    (rank 96, tiles of 8 right-hand sides) the low-rank expansion once had
+    zero slices; it must match the oracle like any other launch shape."""
+    A = wl.laplacian3d(9, wl.sigma_for_negatives(wl.laplacian_eigs((9, 9, 9)), 10))
+    lab = opart.geometric_labels((9, 9, 9), (2, 2, 2))
+    blk = opslr.make_blocks(A.to_scipy(), lab)
+    assert blk.q >= 96
+    pre = opslr.PSLR(A.to_scipy(), lab, 2, 96, v0=wl.start_vector(blk.q, 5))
+    assert pre.V.shape[1] == 96
+    h = P.pslr_setup(A.rowptr, A.colind, A.vals, lab, 8, m=2, rank=0, threads=512)
+    P.pslr_set_lowrank(h, pre.V, pre.H)
+    assert P.pslr_info(h)["threads"] == 512
+    b = wl.normal_rhs(A.n, 8, 31)
+    z = torch.zeros((8, A.n), dtype=torch.float64, device=_dev())
+    P.pslr_apply(h, _tens(b), z)
+    torch.cuda.synchronize()
+    check("lap3d_9 rank 96, 512 threads", "fp64 apply, 8 rhs", _cols(z), pre.apply(b), 1e-12)
+
+
+def c4_shaped():
+    """A small instance of the 3D upwind workload: region-grown uneven parts."""
+    N = 24
+    sigma = wl.sigma_for_negatives(wl.convdiff_eigs(N, 10.0), 20)
+    A = wl.convdiff3d(N, 10.0, sigma)
+    lab = opart.region_growing_labels(A.to_scipy(), 16, 4)
+    return A, lab
+
+
+@pytest.mark.parametrize("working_vectors", [0, 1], ids=["lds", "global"])
+def test_c4_shaped_32rhs_parity(working_vectors):
+    """Upwind convection-diffusion on 24^3 (20 negative eigenvalues), 16
+    region-grown uneven parts, m = 4, r_k = 16, 32 right-hand sides: FP64,
+    FP32 and BF16-V applies in tiles of 8 right-hand sides, with working
+    vectors in LDS and in the global workspace."""
+    A, lab = c4_shaped()
+    sizes = np.bincount(lab)
+    print("c4-shaped part sizes", sizes.min(), "..", sizes.max(), flush=True)
+    b = wl.normal_rhs(A.n, 32, 40)
+    pre = None
+    for prec, tol in ((0, 1e-12), (1, TOL32["c4_shaped"]), (2, TOL32["c4_shaped"])):
+        h, pre = _pair(A, lab, 4, 16, precision=prec, want_T=True, working_vectors=working_vectors)
+        info = P.pslr_info(h)
+        if prec == 2:
+            print("c4-shaped v_bf16", info["v_bf16"], "bf16_probe %.2e" % info["bf16_probe"])
+            if info["v_bf16"]:
+                pre.set_lowrank(bf16_round(pre.V), pre.H)
+        z = torch.zeros((32, A.n), dtype=torch.float64, device=_dev())
+        P.pslr_apply(h, _tens(b), z)
+        zt = torch.zeros_like(z)
+        P.pslr_apply_transpose(h, _tens(b), zt)
+        torch.cuda.synchronize()
+        name = "c4-shaped %s precision %d (max tile %d, global vectors %d)" % (
+            ["lds", "global"][working_vectors], prec, info["max_tile"], info["global_vectors"])
+        check(name, "apply 32 rhs", _cols(z), pre.apply(b), tol)
+        check(name, "apply_transpose 32 rhs", _cols(zt), pre.apply_transpose(b), tol)
 
 
 def test_c2_full_size_apply_parity():
@@ -309,9 +395,28 @@ def test_c2_full_size_apply_parity():
         z = torch.zeros((1, A.n), dtype=torch.float64, device=_dev())
         P.pslr_apply(h, _tens(b), z)
         torch.cuda.synchronize()
-        err = relerr(_cols(z), ref)
-        print("c2 precision", prec, "relerr", err, flush=True)
-        assert err[0] <= tol
+        check("c2", "precision %d apply" % prec, _cols(z), ref, tol)
+
+
+@pytest.mark.timeout(900)
+def test_c2_fgmres_iterations_match_oracle():
+    """64^3 workload: FGMRES(200) to 1e-8 with the oracle's own 64-step
+    Arnoldi basis imported into the library; the oracle's FGMRES with its
+    own preconditioner needs the same number of iterations (within one)."""
+    w = wl.c2()
+    A = w.A
+    lab = opart.geometric_labels((64, 64, 64), (4, 4, 4))
+    blk = opslr.make_blocks(A.to_scipy(), lab)
+    pre = opslr.PSLR(A.to_scipy(), lab, 4, 64, v0=wl.start_vector(blk.q, 2))
+    h = P.pslr_setup(A.rowptr, A.colind, A.vals, lab, 64, m=4, rank=0)
+    P.pslr_set_lowrank(h, pre.V, pre.H)
+    x = torch.zeros((1, A.n), dtype=torch.float64, device=_dev())
+    st, its, rel = P.fgmres_solve(h, _tens(w.b), x, restart=200, maxit=500, tol=1e-8)
+    print("c2 library FGMRES(200): its", its, "relres", rel, flush=True)
+    xo, ito, relo, oko = okry.fgmres(A.to_scipy(), w.b[:, 0], pre.apply, restart=200, tol=1e-8)
+    print("c2 oracle FGMRES(200): its", ito, "relres", relo, flush=True)
+    assert st == P.PSLR_OK and rel[0] <= 1e-8 and oko
+    assert abs(int(its[0]) - ito) <= 1
 
 
 @pytest.mark.parametrize("precision", [0, 1])

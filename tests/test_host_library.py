@@ -113,3 +113,54 @@ def test_invalid_arguments():
     assert ei.value.status == P.PSLR_EINVAL
     with pytest.raises(P.PslrError):
         P.pslr_partition_geometric((4, 4), (5, 1))
+
+
+@pytest.mark.parametrize("case", ["lap3d", "convdiff_rg", "c1"])
+def test_level_schedules_are_valid(case):
+    """Every packed factor (exact LU and ILU, forward and transposed): each
+    position scheduled once, a supernode on one level, every dependency solved
+    before the row that needs it."""
+    if case == "lap3d":
+        A = wl.laplacian3d(14, wl.SIGMA_C2)
+        lab = opart.geometric_labels((14,) * 3, (2, 2, 2))
+    elif case == "convdiff_rg":
+        A = wl.convdiff3d(12, 10.0, 0.2)
+        lab = opart.region_growing_labels(A.to_scipy(), 6, 4)
+    else:
+        A = wl.c1().A
+        lab = opart.geometric_labels((64, 64), (2, 2))
+    for factor in ("lu", "ilut"):
+        st = P.pslr_host_stats(A.rowptr, A.colind, A.vals, lab, int(lab.max()) + 1,
+                               want_transpose=True, nthreads=4, factor=factor)
+        print(case, factor, st)
+        assert st["levels_valid"] == 1
+        assert st["solve_residual"] < 1e-12
+        assert st["factor_residual"] < (1e-13 if factor == "lu" else 1e-14)
+
+
+@pytest.mark.parametrize("case", ["lap2d", "lap3d", "convdiff_rg"])
+def test_ilut_keeps_the_oracles_entries(case):
+    """The library's threshold ILU of every B_i and C_i keeps exactly as many
+    entries as the oracle's (the dropping decisions are integer results taken
+    in FP64 by the same sequence of operations on both sides)."""
+    from oracle import pslr as opslr
+    from oracle import ilu as oilu
+    if case == "lap2d":
+        A = wl.laplacian2d(30, wl.sigma20_2d(30))
+        lab = opart.geometric_labels((30, 30), (2, 3))
+    elif case == "lap3d":
+        A = wl.laplacian3d(12, wl.sigma_for_negatives(wl.laplacian_eigs((12,) * 3), 8))
+        lab = opart.geometric_labels((12,) * 3, (2, 2, 2))
+    else:
+        A = wl.convdiff3d(10, 10.0, 0.3)
+        lab = opart.region_growing_labels(A.to_scipy(), 5, 4)
+    blk = opslr.make_blocks(A.to_scipy(), lab)
+    for drop in (1e-2, 1e-3):
+        st = P.pslr_host_stats(A.rowptr, A.colind, A.vals, lab, int(lab.max()) + 1,
+                               want_transpose=False, factor="ilut", drop_tol=drop)
+        nB = sum(oilu.IlutSolver(blk.B[a:b, a:b], drop).nnz
+                 for a, b in zip(blk.int_ptr[:-1], blk.int_ptr[1:]) if b > a)
+        nC = sum(oilu.IlutSolver(blk.C0[a:b, a:b], drop).nnz
+                 for a, b in zip(blk.if_ptr[:-1], blk.if_ptr[1:]) if b > a)
+        print(case, drop, "library", st["nnz_LU_B"], st["nnz_LU_C0"], "oracle", nB, nC)
+        assert (st["nnz_LU_B"], st["nnz_LU_C0"]) == (nB, nC)
