@@ -168,6 +168,23 @@ pslr_status pslr_setup_batched(int64_t n, const int64_t* rowptr, const int32_t* 
 pslr_status pslr_apply(pslr_handle h, int32_t nrhs, const double* b, int64_t ldb, double* z,
                        int64_t ldz, void* hip_stream);
 
+/* pslr_apply without any allocation, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments and result as pslr_apply (z = M^{-1} b,
+ * forward direction only, the handle's precision).  The apply's workspace
+ * (y, u0, u1, the V^T y partial sums and, when a subdomain does not fit in
+ * LDS, the global working vectors) is carved from one library-owned 64 MiB
+ * device array per GPU instead of the handle's workspace; the call makes no
+ * hipMalloc/hipFree, memset or host synchronisation and records no trace
+ * events.  Its address is resolved once per device when the first handle is
+ * set up there.  A call whose workspace would exceed 64 MiB returns
+ * PSLR_EINVAL and launches nothing (about 3 q nrhs doubles plus the partial
+ * sums: e.g. q = 67032 allows 32 right-hand sides).  All calls on one GPU share
+ * that array and every apply rewrites what it uses, so calls that overlap on
+ * one GPU (other streams, other threads, other handles) race: serialise them. */
+pslr_status pslr_apply_noalloc(pslr_handle h, int32_t nrhs, const double* b, int64_t ldb, double* z,
+                               int64_t ldz, void* hip_stream);
+
 /* z = M^{-T} b, the transpose of the operator of Algorithm 3:
  *   y = g - E^T B^{-T} f;  y <- P_m^T y;  y <- y + V G^T V^T y;  x = B^{-T}(f - F^T y).
  * Needs a handle built with want_transpose != 0 (else PSLR_EINVAL). */

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <deque>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -157,6 +158,30 @@ hipError_t upload_csr(DevPool& pool, const CouplingHost& C, DevCsr<T>& out) {
   if ((e = pool.upload(C.ptr, &out.ptr))) return e;
   if ((e = pool.upload(C.col, &out.col))) return e;
   return pool.upload(v, &out.val);
+}
+
+// Apply workspace of pslr_apply_noalloc: one file-scope device array per GPU
+// (each device that loads the library holds its own copy until the process
+// ends).  Host code never uses the array's name as an address: its device
+// address is looked up once per device at setup (scratch_attach) and kept in
+// g_scratch_ptr.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Resolve the scratch array's address on `device` (which must be current).
+pslr_status scratch_attach(int device) {
+  if (device < 0 || device >= kMaxDevices) return fail(PSLR_ENOTSUP, "device index above 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return PSLR_OK;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p)
+    return fail(PSLR_EHIP, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+  g_scratch_ptr[device] = p;
+  return PSLR_OK;
 }
 
 // Element counts (in doubles) of an apply workspace: y, u0, u1 (q x nrhs
@@ -1445,6 +1470,10 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
   hipStream_t s = (hipStream_t)hip_stream;
   std::unique_ptr<pslr_ctx> h(new pslr_ctx());
   HIP_TRY(hipGetDevice(&h->device));
+  {
+    const pslr_status sa = scratch_attach(h->device);
+    if (sa != PSLR_OK) return sa;
+  }
   h->m = o.m;
   h->rank = std::min(o.rank, 256);
   h->precision = o.precision;
@@ -1676,6 +1705,42 @@ pslr_status pslr_apply(pslr_handle h, int32_t nrhs, const double* b, int64_t ldb
     return fail(PSLR_EINVAL, "bad vector arguments");
   if (nrhs == 0) return PSLR_OK;
   return apply_dir(h, false, nrhs, b, ldb, z, ldz, (hipStream_t)hip_stream);
+}
+
+pslr_status pslr_apply_noalloc(pslr_handle h, int32_t nrhs, const double* b, int64_t ldb, double* z,
+                               int64_t ldz, void* hip_stream) {
+  if (!h) return fail(PSLR_EINVAL, "null handle");
+  if (nrhs < 0 || (nrhs > 0 && (!b || !z)) || ldb < h->R.n || ldz < h->R.n)
+    return fail(PSLR_EINVAL, "bad vector arguments");
+  if (nrhs == 0 || h->R.n == 0) return PSLR_OK;
+  void* base = (h->device >= 0 && h->device < kMaxDevices) ? g_scratch_ptr[h->device] : nullptr;
+  if (!base) return fail(PSLR_EINVAL, "scratch array not attached on the handle's device");
+  // carve y, u0, u1, the V^T y partial sums and the global working vectors
+  // out of the array, each 256-byte aligned
+  const WsSizes z0 = ws_sizes(h, nrhs);
+  auto up = [](size_t d) { return (d * sizeof(double) + 255) / 256 * 256; };
+  const size_t need = 3 * up(z0.vec) + up(z0.partial) + up(z0.gws);
+  if (need > kScratchBytes)
+    return fail(PSLR_EINVAL, "pslr_apply_noalloc needs " + std::to_string(need) +
+                                 " bytes of scratch for " + std::to_string(nrhs) +
+                                 " right-hand sides; the maximum is " + std::to_string(kScratchBytes));
+  char* c = (char*)base;
+  ApplyWs W{};
+  W.y = c;
+  c += up(z0.vec);
+  W.u0 = c;
+  c += up(z0.vec);
+  W.u1 = c;
+  c += up(z0.vec);
+  W.partial = c;
+  c += up(z0.partial);
+  W.gws = z0.gws > 0 ? (void*)c : nullptr;
+  hipStream_t s = (hipStream_t)hip_stream;
+  // no phase tracing here: the tracer creates events on demand
+  if (h->precision >= 1 && h->have32)
+    return run_apply<float>(h, h->fw32, W, false, nrhs, b, ldb, z, ldz, s, false);
+  if (!h->have64) return fail(PSLR_EINVAL, "FP64 apply arrays not available");
+  return run_apply<double>(h, h->fw64, W, false, nrhs, b, ldb, z, ldz, s, false);
 }
 
 pslr_status pslr_apply_transpose(pslr_handle h, int32_t nrhs, const double* b, int64_t ldb,

@@ -77,6 +77,7 @@ _SIGS = {
     "pslr_setup_batched": (C.c_int, [C.c_int64, _I64P, _I32P, _F64P, _I32P, C.c_int32, C.c_int32,
                                      _I64P, C.POINTER(pslr_options), _P, C.POINTER(_P)]),
     "pslr_apply": (C.c_int, [_P, C.c_int32, _P, C.c_int64, _P, C.c_int64, _P]),
+    "pslr_apply_noalloc": (C.c_int, [_P, C.c_int32, _P, C.c_int64, _P, C.c_int64, _P]),
     "pslr_apply_transpose": (C.c_int, [_P, C.c_int32, _P, C.c_int64, _P, C.c_int64, _P]),
     "fgmres_solve": (C.c_int, [_P, C.c_int32, _P, C.c_int64, _P, C.c_int64, C.c_int32, C.c_int32,
                                C.c_double, C.c_int32, _I32P, _F64P, _P]),
@@ -253,6 +254,14 @@ def pslr_apply(h: Handle, b, z, stream=None):
     if nrz != nrhs:
         raise ValueError("b and z have different column counts")
     _check(lib().pslr_apply(h.ptr, nrhs, bp, ldb, zp, ldz, _stream_ptr(stream)))
+
+
+def pslr_apply_noalloc(h: Handle, b, z, stream=None):
+    bp, nrhs, ldb = _vec(b, h.n)
+    zp, nrz, ldz = _vec(z, h.n)
+    if nrz != nrhs:
+        raise ValueError("b and z have different column counts")
+    _check(lib().pslr_apply_noalloc(h.ptr, nrhs, bp, ldb, zp, ldz, _stream_ptr(stream)))
 
 
 def pslr_apply_transpose(h: Handle, b, z, stream=None):
