@@ -104,6 +104,19 @@ typedef struct {
   double drop_tol;          /* factor = 1: an entry of row i is dropped when its modulus is below
                                drop_tol * ||A_block[i, :]||_2 (the L entry after division by
                                the pivot); <= 0 means 1e-2, the paper's setting (Sec. 4) */
+  int32_t lowrank;          /* how V and H are built (Algorithm 4, lines 6-8):
+                               0 = the paper's r_k-step Arnoldi on E_rr(m) (eq. schur);
+                               1 = Krylov-Schur restarting of that Arnoldi process (Stewart 2001):
+                                   V spans the converged invariant subspace of E_rr(m) for its
+                                   r_k eigenvalues of largest modulus (a complex pair the cut
+                                   would split is dropped), H = V^T E_rr V; bases of r_k + max(r_k,
+                                   16) vectors, at most 60 restarts, converged when the coupling
+                                   to the rest is below 1e-9 times the smallest kept modulus;
+                               2 = as 1, and while every kept eigenvalue has modulus above 1 the
+                                   kept count grows (to 16 more than the Ritz values above 1, up
+                                   to 256), so that all eigenvalues of E_rr(m) outside the unit
+                                   circle are deflated (Sec. 3.2.2); pslr_info.rank gives the
+                                   count reached, which may exceed r_k */
 } pslr_options;
 
 typedef struct {
@@ -128,9 +141,17 @@ typedef struct {
                                in FP32 */
   double bf16_probe;        /* precision 2: ||z_bf16 - z_fp32|| / ||z_fp32|| of one apply to a fixed
                                vector with V in BF16 and in FP32; BF16 is kept when <= 2.5e-2 */
+  int32_t lowrank;          /* pslr_options.lowrank of the setup */
+  int32_t ks_restarts;      /* lowrank 1, 2: Krylov-Schur restarts (largest over systems) */
+  int64_t ks_applies;       /* lowrank 1, 2: applications of E_rr(m) to a basis column */
+  double ks_residual;       /* lowrank 1, 2: largest ||coupling|| / (smallest kept modulus) */
+  int32_t ritz_above_one;   /* lowrank 1, 2: kept eigenvalues of E_rr(m) of modulus above 1
+                               (summed over systems) */
+  int32_t pad0;
 } pslr_info_t;
 
-/* Fill *opt with defaults: m = 3, rank = 16, FP64, no transpose, seed 1, tau 0.1. */
+/* Fill *opt with defaults: m = 3, rank = 16, FP64, no transpose, seed 1, tau 0.1,
+ * exact LU, the paper's Arnoldi (lowrank = 0). */
 void pslr_default_options(pslr_options* opt);
 
 /* Build the preconditioner (Algorithm 4): reorder A by the labels `part`
@@ -290,6 +311,21 @@ typedef struct {
 pslr_status pslr_host_stats(int64_t n, const int64_t* rowptr, const int32_t* colind,
                             const double* vals, const int32_t* part, int32_t nparts,
                             const pslr_options* opt, pslr_host_stats_t* out);
+
+/* Host-only step of the deflated low-rank setup (lowrank = 1, 2), exposed
+ * for checking without a GPU: for a real n x n matrix Hm (column-major,
+ * leading dimension ldh), an orthonormal basis W (n x *kept, column-major,
+ * leading dimension ldw >= n, at least k columns of room) of its invariant
+ * subspace for the k eigenvalues of largest modulus (a complex eigenvalue
+ * whose conjugate would be cut off is dropped, so *kept is k or k - 1), and
+ * Hk = W^T Hm W (*kept x *kept, leading dimension ldk >= k).  ritz_re/ritz_im
+ * (n each, may be NULL) receive all eigenvalues by decreasing modulus.  This
+ * is the Krylov-Schur truncation of Stewart (2001) in its real form: the
+ * complex Schur form from the shifted QR algorithm, reordered, then a real
+ * basis of the leading Schur vectors. */
+pslr_status pslr_host_schur_select(int32_t n, const double* Hm, int64_t ldh, int32_t k, double* W,
+                                   int64_t ldw, double* Hk, int64_t ldk, double* ritz_re,
+                                   double* ritz_im, int32_t* kept);
 
 pslr_status pslr_destroy(pslr_handle h);
 const char* pslr_status_string(pslr_status s);

@@ -62,23 +62,32 @@ def sorted_schur(Hm: np.ndarray, k: int):
 
 
 def krylov_schur(op, v0: np.ndarray, k: int, p: int | None = None, tol: float = 1e-9,
-                 max_restarts: int = 60):
+                 max_restarts: int = 60, grow: bool = False, kmax: int = 256):
     """Converged r_k-dimensional invariant subspace of op for its largest-modulus eigenvalues.
 
     op: v -> E_rr(m) v on the interface (length q).  Returns (V, H, info) with
     V (q x kept) orthonormal, H = V^T op(V) and info = dict(restarts,
     applies, residual) where residual = ||op(V) - V H||_2 bound from the
     Krylov-Schur coupling row.
+
+    grow: the paper's case for the correction is the deflation of every
+    eigenvalue of modulus above 1 (Sec. 3.2.2; Prop. l3 needs r_k above their
+    count).  When a cycle has converged with every kept Ritz value outside the
+    unit circle, k is raised to 16 more than the number of Ritz values of the
+    whole projected matrix outside it (at least k + 16, at most kmax) and the
+    iteration continues from the kept space, with p = max(k, 16) again.
     """
     q = v0.shape[0]
     k = min(k, q)
+    kmax = min(kmax, q)
     if p is None:
         p = max(k, 16)
     m = min(k + p, q)
     if m <= k:  # the whole space: one Arnoldi pass is exact
         m = k
-    V = np.zeros((q, m + 1))
-    H = np.zeros((m + 1, m))
+    width = max(m, min(kmax + max(kmax, 16), q)) if grow else m
+    V = np.zeros((q, width + 1))
+    H = np.zeros((width + 1, width))
     V[:, 0] = v0 / np.linalg.norm(v0)
     j0 = 0
     applies = 0
@@ -109,7 +118,14 @@ def krylov_schur(op, v0: np.ndarray, k: int, p: int | None = None, tol: float = 
         b = H[m_eff, :m_eff] @ Z[:, :kept] if not breakdown else np.zeros(kept)
         scale = np.abs(np.diag(T)[:kept]).min() if kept else 1.0
         res = float(np.linalg.norm(b))
-        if breakdown or m_eff == q or res <= tol * max(scale, 1e-300) or restart == max_restarts:
+        done = breakdown or m_eff == q or res <= tol * max(scale, 1e-300) or restart == max_restarts
+        if (done and grow and not breakdown and m_eff < q and restart < max_restarts and kept
+                and kept_min_modulus(T, kept) > 1.0 and k < kmax):
+            above = int(np.sum(np.abs(np.linalg.eigvals(Hm)) > 1.0))
+            k = min(kmax, max(k + 16, above + 16))
+            p = max(k, 16)
+            done = False
+        if done:
             Vk = V[:, :m_eff] @ Z[:, :kept]
             Hk = T[:kept, :kept].copy()
             return Vk, Hk, dict(restarts=restart, applies=applies, residual=res)
@@ -124,4 +140,11 @@ def krylov_schur(op, v0: np.ndarray, k: int, p: int | None = None, tol: float = 
         Hn[kept, :kept] = b
         H = Hn
         j0 = kept
+        m = min(max(kept, k) + p, q, width)
     raise AssertionError("unreachable")
+
+
+def kept_min_modulus(T: np.ndarray, kept: int) -> float:
+    """Smallest modulus among the eigenvalues of the leading kept x kept block
+    of a real Schur form."""
+    return float(np.abs(np.linalg.eigvals(T[:kept, :kept])).min())

@@ -26,6 +26,7 @@ HIP_FLAGS = [
     "-Wno-unused-result",
 ]
 HIP_SOURCES = ("pslr_kernels.hip", "pslr_vec.hip", "pslr_api.hip")
+CXX_SOURCES = ("pslr_host.cpp", "pslr_schur.cpp")
 CXX_FLAGS = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-sign-compare", "-Wno-unused-function"]
 
 
@@ -43,8 +44,9 @@ def build(verbose: bool = False) -> str:
     hipcc = shutil.which("hipcc") or os.path.join(ROCM, "bin", "hipcc")
     cxx = shutil.which("g++") or "g++"
     os.makedirs(BUILD, exist_ok=True)
-    jobs = [[cxx] + CXX_FLAGS + ["-c", os.path.join(CSRC, "pslr_host.cpp"), "-o",
-                                 os.path.join(BUILD, "pslr_host.o")]]
+    jobs = [[cxx] + CXX_FLAGS + ["-c", os.path.join(CSRC, src), "-o",
+                                 os.path.join(BUILD, src.replace(".cpp", ".o"))]
+            for src in CXX_SOURCES]
     for src in HIP_SOURCES:
         jobs.append([hipcc] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o",
                                            os.path.join(BUILD, src.replace(".hip", ".o"))])

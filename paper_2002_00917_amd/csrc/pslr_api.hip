@@ -1000,6 +1000,332 @@ pslr_status arnoldi(pslr_ctx* h, const double* v0host, uint64_t seed, hipStream_
   return upload_lowrank(h);
 }
 
+// Widen the apply layouts for a low-rank term of k columns: the global
+// workspace holds 2k scratch values per block, the LDS working set 2k.
+void grow_kmax(pslr_ctx* h, int k) {
+  if (k <= h->fw64.kmax) return;
+  h->gws_stride += (int64_t)h->R.nparts * 2 * (k - h->fw64.kmax);
+  for (ApplyArrays<double>* A : {&h->fw64, &h->tr64}) {
+    A->kmax = k;
+    A->gws_stride = h->gws_stride;
+  }
+  for (ApplyArrays<float>* A : {&h->fw32, &h->tr32}) {
+    A->kmax = k;
+    A->gws_stride = h->gws_stride;
+  }
+  if (k > h->rank) h->rank = k;
+}
+
+// Deflated low-rank correction (lowrank = 1, 2): Krylov-Schur restarting
+// (Stewart, SIAM J. Matrix Anal. Appl. 23, 2001) of the Arnoldi process on
+// E_rr(m) = (E_s C0^{-1})^{m+1} (Thm. t2).  The paper motivates the low-rank
+// term as a deflation of the eigenvalues of modulus above 1 (Sec. 3.2.2); a
+// raw r_k-step Arnoldi basis only approximates that invariant subspace, this
+// converges it.  Each cycle expands the basis to k + p vectors (FP64 CGS2 on
+// the device, as in arnoldi()), then on the host keeps the invariant subspace
+// of the projected matrix for its k Ritz values of largest modulus
+// (schur_select), rotates the basis on the device and continues from the
+// coupling vector, until the coupling is below kKsTol times the smallest kept
+// modulus.  lowrank = 2 also raises k (up to 256) while every kept Ritz value
+// lies outside the unit circle, so that all of modulus above 1 are kept.
+// The result keeps the paper's form: V orthonormal, H = V^T E_rr V, G from H.
+//
+// Systems of a batched handle run together: every apply acts on one global
+// basis column for all systems.  Each system's basis occupies positions
+// 0..k_s-1 after a restart (zero columns up to the common continuation
+// position K, the largest k_s) and its own rows of V.
+constexpr double kKsTol = 1e-9;
+constexpr int kKsMaxRestarts = 60;
+constexpr int kKsMaxRank = 256;
+
+pslr_status krylov_schur(pslr_ctx* h, const double* v0host, uint64_t seed, int mode, hipStream_t s,
+                         bool& breakdown) {
+  const int64_t q = h->R.q;
+  const int ns = h->nsys;
+  std::vector<int64_t> qs(ns);
+  int64_t qmax = 0;
+  for (int c = 0; c < ns; ++c) {
+    qs[c] = h->sys_q[c + 1] - h->sys_q[c];
+    qmax = std::max(qmax, qs[c]);
+  }
+  const int kreq = (int)std::min<int64_t>(h->rank, qmax);
+  breakdown = false;
+  h->k = 0;
+  h->sys_k.assign(ns, 0);
+  h->hV.clear();
+  h->hH.clear();
+  h->info.ks_restarts = 0;
+  h->info.ks_applies = 0;
+  h->info.ks_residual = 0.0;
+  h->info.ritz_above_one = 0;
+  if (kreq <= 0) return upload_lowrank(h);
+  const int kcap = mode == 2 ? (int)std::min<int64_t>(kKsMaxRank, qmax) : kreq;
+  // global basis positions: at most kcap kept + p expansion vectors + 1
+  const int Mc = (int)std::min<int64_t>(qmax + 1, (int64_t)kcap + std::max(kcap, 16) + 1);
+  DevPool tmp;
+  double *Vd, *Vn, *w, *ua, *ub, *dbuf, *dhh, *scl, *dW;
+  HIP_TRY(tmp.alloc<double>((size_t)q * (Mc + 1), &Vd));
+  HIP_TRY(tmp.alloc<double>((size_t)q * (kcap + 1), &Vn));
+  HIP_TRY(tmp.alloc<double>(q, &w));
+  HIP_TRY(tmp.alloc<double>(q, &ua));
+  HIP_TRY(tmp.alloc<double>(q, &ub));
+  std::vector<Seg> qcols(ns);
+  for (int c = 0; c < ns; ++c) qcols[c] = Seg{h->sys_q[c], qs[c]};
+  std::vector<Chunk> chv;
+  std::vector<int32_t> cpv;
+  const int nch = make_chunks(qcols, chunk_rows(qcols), nullptr, chv, cpv);
+  Chunk *dch, *dchr;
+  int32_t* dcp;
+  HIP_TRY(tmp.alloc<Chunk>(std::max(nch, 1), &dch));
+  HIP_TRY(tmp.alloc<Chunk>(std::max(nch, 1), &dchr));
+  HIP_TRY(tmp.alloc<int32_t>(ns + 1, &dcp));
+  if (nch > 0) HIP_TRY(hipMemcpy(dch, chv.data(), sizeof(Chunk) * nch, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(dcp, cpv.data(), sizeof(int32_t) * (ns + 1), hipMemcpyHostToDevice));
+  HIP_TRY(tmp.alloc<double>((size_t)std::max(nch, 1) * (Mc + 1), &dbuf));
+  HIP_TRY(tmp.alloc<double>((size_t)ns * (2 * (Mc + 1) + 2), &dhh));
+  HIP_TRY(tmp.alloc<double>(ns, &scl));
+  HIP_TRY(tmp.alloc<double>((size_t)ns * (Mc + 1) * (kcap + 1), &dW));
+  double* dh1 = dhh;
+  double* dh2 = dhh + (size_t)ns * (Mc + 1);
+  double* dnn = dh2 + (size_t)ns * (Mc + 1);
+  double* dwn = dnn + ns;
+  // start vector (the same rule as arnoldi())
+  std::vector<double> v(q);
+  if (v0host) {
+    std::copy(v0host, v0host + q, v.begin());
+  } else {
+    uint64_t st = seed;
+    for (int64_t i = 0; i < q; ++i) v[i] = (double)(splitmix64_next(st) >> 11) * 0x1.0p-53 - 0.5;
+  }
+  struct Sys {
+    bool active = false;  // still expanding in this cycle
+    bool done = false;    // final basis at positions 0..kept-1
+    bool broke = false;   // invariant subspace found in this cycle
+    int ktarget = 0, kept = 0;
+    std::vector<int> pos;  // basis positions (the continuation vector last, when present)
+    std::vector<double> Hk;
+    double res = 0.0;
+    int restarts = 0;
+  };
+  std::vector<Sys> S(ns);
+  for (int c = 0; c < ns; ++c) {
+    double nv = 0.0;
+    for (int64_t i = h->sys_q[c]; i < h->sys_q[c + 1]; ++i) nv += v[i] * v[i];
+    nv = std::sqrt(nv);
+    S[c].ktarget = (int)std::min<int64_t>(kreq, qs[c]);
+    if (nv > 0.0 && qs[c] > 0 && S[c].ktarget > 0) {
+      S[c].active = true;
+      S[c].pos = {0};
+      for (int64_t i = h->sys_q[c]; i < h->sys_q[c + 1]; ++i) v[i] /= nv;
+    } else {
+      S[c].done = true;
+      for (int64_t i = h->sys_q[c]; i < h->sys_q[c + 1]; ++i) v[i] = 0.0;
+    }
+  }
+  HIP_TRY(hipMemcpy(Vd, v.data(), sizeof(double) * q, hipMemcpyHostToDevice));
+  // per-system projected matrix in global positions, (Mc + 1) x Mc column-major
+  const size_t ldH = (size_t)Mc + 1;
+  std::vector<double> Hs((size_t)ns * ldH * Mc, 0.0);
+  auto Hat = [&](int c, int i, int j) -> double& { return Hs[((size_t)c * Mc + j) * ldH + i]; };
+  ApplyArrays<double> A = h->fw64;
+  A.gws = h->gws;
+  LaunchCfg cfg = choose_launch(h, A, 1, s);
+  std::vector<double> hb((size_t)ns * (2 * (Mc + 1) + 2)), sc(ns);
+  const Seg* cols = h->d_qcols;
+  int K = 0;  // continuation position of this cycle
+  int64_t applies = 0;
+  for (int cycle = 0;; ++cycle) {
+    // basis of k + p vectors (p = max(k, 16)): the kept ones (positions below
+    // K) and the new ones from the continuation position K on
+    int kt = 0;
+    for (int c = 0; c < ns; ++c)
+      if (!S[c].done) kt = std::max(kt, S[c].ktarget);
+    const int mend = std::min(std::max(K, kt) + std::max(kt, 16), Mc - 1);
+    for (int c = 0; c < ns; ++c) S[c].broke = false;
+    // ---- expansion: columns K .. mend-1 produce positions K+1 .. mend
+    for (int j = K; j < mend; ++j) {
+      bool any = false;
+      for (int c = 0; c < ns; ++c) any = any || S[c].active;
+      if (!any) break;
+      const double* cur = Vd + (size_t)j * q;
+      for (int r = 0; r <= h->m; ++r) {
+        HIP_TRY(launch_c0solve<double>(A, cfg, 1, cur, q, ua, q));
+        HIP_TRY(launch_series<double>(A, cfg, 1, ua, q, ua, ub, q, 0, 0));
+        cur = ub;
+      }
+      ++applies;
+      HIP_TRY(hipMemcpyAsync(w, ub, sizeof(double) * q, hipMemcpyDeviceToDevice, s));
+      const int nv = j + 1;
+      HIP_TRY(launch_mdot_chunk(nch, dch, cols, cols, 1, w, 0, w, dbuf, s));
+      HIP_TRY(launch_reduce_chunk(ns, dcp, 1, nch, dbuf, dwn, s));
+      HIP_TRY(launch_mdot_chunk(nch, dch, cols, cols, nv, Vd, q, w, dbuf, s));
+      HIP_TRY(launch_reduce_chunk(ns, dcp, nv, nch, dbuf, dh1, s));
+      HIP_TRY(launch_maxpy_chunk(nch, dch, cols, cols, nv, Vd, q, dh1, nv, w, 1.0, s));
+      HIP_TRY(launch_mdot_chunk(nch, dch, cols, cols, nv, Vd, q, w, dbuf, s));
+      HIP_TRY(launch_reduce_chunk(ns, dcp, nv, nch, dbuf, dh2, s));
+      HIP_TRY(launch_maxpy_chunk(nch, dch, cols, cols, nv, Vd, q, dh2, nv, w, 1.0, s));
+      HIP_TRY(launch_mdot_chunk(nch, dch, cols, cols, 1, w, 0, w, dbuf, s));
+      HIP_TRY(launch_reduce_chunk(ns, dcp, 1, nch, dbuf, dnn, s));
+      HIP_TRY(hipMemcpyAsync(hb.data(), dhh, sizeof(double) * hb.size(), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      const double* h1 = hb.data();
+      const double* h2 = h1 + (size_t)ns * (Mc + 1);
+      const double* nn = h2 + (size_t)ns * (Mc + 1);
+      const double* wn = nn + ns;
+      for (int c = 0; c < ns; ++c) {
+        sc[c] = 0.0;
+        if (!S[c].active) continue;
+        for (int i = 0; i <= j; ++i) Hat(c, i, j) = h1[(size_t)c * nv + i] + h2[(size_t)c * nv + i];
+        const double hn = std::sqrt(nn[c]);
+        Hat(c, j + 1, j) = hn;
+        if (hn <= 1e-14 * std::sqrt(wn[c]) || (int64_t)S[c].pos.size() >= qs[c]) {
+          // invariant subspace, or the whole space of this system
+          S[c].active = false;
+          S[c].broke = true;
+          Hat(c, j + 1, j) = 0.0;
+          continue;
+        }
+        S[c].pos.push_back(j + 1);
+        sc[c] = 1.0 / hn;
+      }
+      HIP_TRY(hipMemcpyAsync(scl, sc.data(), sizeof(double) * ns, hipMemcpyHostToDevice, s));
+      HIP_TRY(launch_scale_chunk(nch, dch, cols, cols, w, scl, Vd + (size_t)(j + 1) * q, s));
+    }
+    // ---- host: sorted Schur truncation per system
+    std::vector<char> rot(ns, 0);
+    for (int c = 0; c < ns; ++c) rot[c] = !S[c].done;
+    std::vector<std::vector<double>> Wsel(ns);
+    std::vector<std::vector<double>> bcoup(ns);
+    int Knext = 0, ncols = 0;
+    bool cont_any = false;
+    for (int c = 0; c < ns; ++c) {
+      Sys& y = S[c];
+      if (y.done) continue;
+      const bool has_cont = !y.broke;  // the last position is the continuation vector
+      const int mb = (int)y.pos.size() - (has_cont ? 1 : 0);
+      std::vector<double> Hm((size_t)mb * mb);
+      for (int b = 0; b < mb; ++b)
+        for (int a = 0; a < mb; ++a) Hm[(size_t)b * mb + a] = Hat(c, y.pos[a], y.pos[b]);
+      const double hlast = has_cont ? Hat(c, y.pos[mb], y.pos[mb - 1]) : 0.0;
+      std::vector<double> W, Hk, rr, ri;
+      std::string err;
+      const int kept = schur_select(mb, Hm.data(), mb, std::min(y.ktarget, mb), W, Hk, rr, ri, err);
+      if (kept < 0) return fail(PSLR_ESINGULAR, "Krylov-Schur: " + err);
+      std::vector<double> b(kept);
+      double bn = 0.0;
+      for (int t = 0; t < kept; ++t) {
+        b[t] = hlast * W[(size_t)t * mb + (mb - 1)];
+        bn += b[t] * b[t];
+      }
+      bn = std::sqrt(bn);
+      const double minmod = kept > 0 ? std::hypot(rr[kept - 1], ri[kept - 1]) : 1.0;
+      y.res = kept > 0 ? bn / std::max(minmod, 1e-300) : 0.0;
+      y.restarts = cycle;
+      const bool full = !has_cont || (int64_t)mb >= qs[c];
+      bool conv = full || bn <= kKsTol * std::max(minmod, 1e-300) || cycle >= kKsMaxRestarts;
+      if (conv && mode == 2 && !full && kept > 0 && minmod > 1.0 && y.ktarget < kcap &&
+          cycle < kKsMaxRestarts) {
+        // every kept Ritz value lies outside the unit circle: keep more
+        int above = 0;
+        for (int t = 0; t < mb; ++t) above += std::hypot(rr[t], ri[t]) > 1.0;
+        y.ktarget = std::min(kcap, std::max(y.ktarget + 16, above + 16));
+        conv = false;
+      }
+      if (kept == 0) conv = true;
+      y.kept = kept;
+      y.Hk = Hk;
+      bcoup[c] = b;
+      if (conv) {
+        y.done = true;
+        y.active = false;
+      } else {
+        cont_any = true;
+        Knext = std::max(Knext, kept);
+      }
+      Wsel[c] = std::move(W);
+      ncols = std::max(ncols, kept);
+    }
+    // ---- device: rotate the basis of every system that restarted or finished
+    // in this cycle; continuing systems get their continuation vector at Knext
+    if (cont_any) ncols = std::max(ncols, Knext + 1);
+    if (ncols > 0) {
+      const int mcols = mend + 1;
+      std::vector<double> Wall((size_t)ns * mcols * ncols, 0.0);
+      std::vector<Chunk> chr;
+      for (int c = 0; c < ns; ++c) {
+        if (!rot[c]) continue;
+        const Sys& y = S[c];
+        const int mb = (int)y.pos.size() - (y.broke ? 0 : 1);
+        double* Wc = &Wall[(size_t)c * mcols * ncols];
+        for (int t = 0; t < y.kept; ++t)
+          for (int a = 0; a < mb; ++a) Wc[(size_t)t * mcols + y.pos[a]] = Wsel[c][(size_t)t * mb + a];
+        if (!y.done) Wc[(size_t)Knext * mcols + y.pos.back()] = 1.0;  // continuation vector
+        for (int e = cpv[c]; e < cpv[c + 1]; ++e) chr.push_back(chv[e]);
+      }
+      if (!chr.empty()) {
+        HIP_TRY(hipMemcpyAsync(dW, Wall.data(), sizeof(double) * Wall.size(), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(dchr, chr.data(), sizeof(Chunk) * chr.size(), hipMemcpyHostToDevice, s));
+        HIP_TRY(launch_basis_rotate((int)chr.size(), dchr, cols, mcols, ncols, Vd, q, dW, Vn, q, s));
+        // copy the rotated columns back (rows of the rotated systems only)
+        for (int c = 0; c < ns; ++c) sc[c] = 1.0;
+        HIP_TRY(hipMemcpyAsync(scl, sc.data(), sizeof(double) * ns, hipMemcpyHostToDevice, s));
+        for (int t = 0; t < ncols; ++t)
+          HIP_TRY(launch_scale_chunk((int)chr.size(), dchr, cols, cols, Vn + (size_t)t * q, scl,
+                                     Vd + (size_t)t * q, s));
+        HIP_TRY(hipStreamSynchronize(s));
+      }
+    }
+    // ---- projected matrices of the continuing systems
+    for (int c = 0; c < ns; ++c) {
+      Sys& y = S[c];
+      if (y.done) continue;
+      std::fill(&Hat(c, 0, 0), &Hat(c, 0, 0) + ldH * Mc, 0.0);
+      for (int jj = 0; jj < y.kept; ++jj)
+        for (int i = 0; i < y.kept; ++i) Hat(c, i, jj) = y.Hk[(size_t)jj * y.kept + i];
+      for (int t = 0; t < y.kept; ++t) Hat(c, Knext, t) = bcoup[c][t];
+      y.pos.clear();
+      for (int t = 0; t < y.kept; ++t) y.pos.push_back(t);
+      y.pos.push_back(Knext);
+      y.active = true;
+    }
+    if (!cont_any) break;
+    K = Knext;
+  }
+  // ---- results: V (union q x kmax, zero beyond each system's rank) and H per system
+  int kmax = 0;
+  for (int c = 0; c < ns; ++c) kmax = std::max(kmax, S[c].kept);
+  h->k = kmax;
+  for (int c = 0; c < ns; ++c) h->sys_k[c] = S[c].kept;
+  h->hV.assign((size_t)q * kmax, 0.0);
+  if (kmax > 0) HIP_TRY(hipMemcpy(h->hV.data(), Vd, sizeof(double) * q * kmax, hipMemcpyDeviceToHost));
+  for (int c = 0; c < ns; ++c)
+    for (int j = S[c].kept; j < kmax; ++j)
+      for (int64_t r = h->sys_q[c]; r < h->sys_q[c + 1]; ++r) h->hV[(size_t)j * q + r] = 0.0;
+  h->hH.assign((size_t)ns * kmax * kmax, 0.0);
+  int above = 0, rmax = 0;
+  double resmax = 0.0;
+  for (int c = 0; c < ns; ++c) {
+    const int kc = S[c].kept;
+    for (int j = 0; j < kc; ++j)
+      for (int i = 0; i < kc; ++i) h->hH[(size_t)c * kmax * kmax + (size_t)j * kmax + i] = S[c].Hk[(size_t)j * kc + i];
+    if (kc > 0) {
+      std::vector<double> W, Hk, rr, ri;
+      std::string err;
+      if (schur_select(kc, S[c].Hk.data(), kc, kc, W, Hk, rr, ri, err) >= 0)
+        for (int t = 0; t < kc; ++t) above += std::hypot(rr[t], ri[t]) > 1.0;
+    }
+    resmax = std::max(resmax, S[c].res);
+    rmax = std::max(rmax, S[c].restarts);
+    if (S[c].kept < std::min<int64_t>(kreq, qs[c])) breakdown = true;
+  }
+  h->info.ks_restarts = rmax;
+  h->info.ks_applies = applies;
+  h->info.ks_residual = resmax;
+  h->info.ritz_above_one = above;
+  if (kmax > h->fw64.kmax) grow_kmax(h, kmax);
+  return upload_lowrank(h);
+}
+
 // Pick the workgroup size and the chunk-count scaling of the triangular solves by
 // timing applies (one right-hand side, HIP events) over a small grid of choices,
 // then the widest right-hand-side tile (applies of 8 right-hand sides).
@@ -1172,6 +1498,7 @@ void pslr_default_options(pslr_options* o) {
   o->threads = 0;
   o->factor = 0;
   o->drop_tol = 1e-2;
+  o->lowrank = 0;
 }
 
 const char* pslr_status_string(pslr_status s) {
@@ -1279,6 +1606,7 @@ pslr_status pslr_host_stats(int64_t n, const int64_t* rowptr, const int32_t* col
   pslr_default_options(&o);
   if (opt) o = *opt;
   if (o.factor != 0 && o.factor != 1) return fail(PSLR_EINVAL, "factor must be 0 or 1");
+  if (o.lowrank < 0 || o.lowrank > 2) return fail(PSLR_EINVAL, "lowrank must be 0, 1 or 2");
   const double tau = o.pivot_threshold > 0 ? o.pivot_threshold : 0.1;
   const double drop = o.drop_tol > 0 ? o.drop_tol : 1e-2;
   Reordering R = reorder(n, rowptr, colind, part, nparts);
@@ -1424,6 +1752,28 @@ pslr_status pslr_host_stats(int64_t n, const int64_t* rowptr, const int32_t* col
     out->factor_residual = std::max(out->factor_residual, fres[t]);
     out->solve_residual = std::max(out->solve_residual, sres[t]);
   }
+  return PSLR_OK;
+}
+
+pslr_status pslr_host_schur_select(int32_t n, const double* Hm, int64_t ldh, int32_t k, double* W,
+                                   int64_t ldw, double* Hk, int64_t ldk, double* ritz_re,
+                                   double* ritz_im, int32_t* kept) {
+  if (n < 0 || k < 0 || !kept || (n > 0 && (!Hm || ldh < n)) || (k > 0 && n > 0 && (!W || !Hk)) ||
+      ldw < n || ldk < std::min(k, n))
+    return fail(PSLR_EINVAL, "bad arguments");
+  std::vector<double> w, hk, rr, ri;
+  std::string err;
+  const int kp = schur_select(n, Hm, ldh, k, w, hk, rr, ri, err);
+  if (kp < 0) return fail(PSLR_ESINGULAR, err);
+  for (int j = 0; j < kp; ++j) {
+    for (int i = 0; i < n; ++i) W[(size_t)j * ldw + i] = w[(size_t)j * n + i];
+    for (int i = 0; i < kp; ++i) Hk[(size_t)j * ldk + i] = hk[(size_t)j * kp + i];
+  }
+  for (int i = 0; i < n; ++i) {
+    if (ritz_re) ritz_re[i] = rr[i];
+    if (ritz_im) ritz_im[i] = ri[i];
+  }
+  *kept = kp;
   return PSLR_OK;
 }
 
@@ -1639,7 +1989,9 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
   h->ws_cap = WsSizes{};
   st = ensure_ws(h.get(), 1);
   if (st) return st;
-  st = arnoldi(h.get(), o.v0, o.seed, s, breakdown);
+  h->info.lowrank = o.lowrank;
+  st = o.lowrank == 0 ? arnoldi(h.get(), o.v0, o.seed, s, breakdown)
+                      : krylov_schur(h.get(), o.v0, o.seed, o.lowrank, s, breakdown);
   if (st) return st;
   h->ws.release();  // the V^T y partial sums are sized by the achieved rank
   h->ws_nrhs = 0;
@@ -2028,17 +2380,7 @@ pslr_status pslr_set_lowrank(pslr_handle h, int32_t k, const double* V, int64_t 
   const int64_t q = h->R.q;
   h->k = k;
   h->sys_k.assign(1, k);
-  if (k > h->fw64.kmax) {  // global workspace holds 2k scratch per block
-    h->gws_stride += (int64_t)h->R.nparts * 2 * (k - h->fw64.kmax);
-    for (ApplyArrays<double>* A : {&h->fw64, &h->tr64}) {
-      A->kmax = k;
-      A->gws_stride = h->gws_stride;
-    }
-    for (ApplyArrays<float>* A : {&h->fw32, &h->tr32}) {
-      A->kmax = k;
-      A->gws_stride = h->gws_stride;
-    }
-  }
+  grow_kmax(h, k);
   h->hV.assign((size_t)q * k, 0.0);
   h->hH.assign((size_t)k * k, 0.0);
   for (int j = 0; j < k; ++j) {

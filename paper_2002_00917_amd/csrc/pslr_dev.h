@@ -172,6 +172,11 @@ hipError_t launch_inv_sqrt(int ncol, const double* nn, const uint8_t* active, do
                            hipStream_t s);
 hipError_t launch_scale_chunk(int nchunk, const Chunk* ch, const Seg* scols, const Seg* dcols,
                               const double* S, const double* scale, double* D, hipStream_t s);
+// Vn[:, c] = sum_{j < mcols} V[:, j] W_s[j, c] for c < ncols on the rows of the
+// chunks (chunk column = system s; W: per system mcols x ncols column-major)
+hipError_t launch_basis_rotate(int nchunk, const Chunk* ch, const Seg* cols, int mcols, int ncols,
+                               const double* V, int64_t ldv, const double* W, double* Vn, int64_t ldn,
+                               hipStream_t s);
 hipError_t launch_sddmm(int64_t n, const int64_t* ptr, const int32_t* col, int nrhs,
                         const double* lam, int64_t ldl, const double* z, int64_t ldz,
                         double* grad, hipStream_t s);

@@ -209,6 +209,17 @@ bool pack_tri(const TriHost& T, TriPacked& P, int narrow_width);
 // entries: use the entry form where a level has one (else the panels).
 void host_tri_solve(const TriPacked& T, std::vector<double>& X, bool entries);
 
+// Invariant subspace of a small real matrix H_m (n x n, column-major, leading
+// dimension ldh) for its Ritz values of largest modulus (the Krylov-Schur
+// restart of the deflated low-rank setup; pslr_schur.cpp).  Keeps the k of
+// largest modulus, dropping a complex value whose conjugate falls outside.
+// Outputs: W (n x kept, column-major, orthonormal columns spanning the
+// subspace), Hk = W^T H_m W (kept x kept, column-major), and all n Ritz values
+// by decreasing modulus.  Returns kept (>= 0), or -1 with err set.
+int schur_select(int n, const double* Hm, int64_t ldh, int k, std::vector<double>& W,
+                 std::vector<double>& Hk, std::vector<double>& ritz_re, std::vector<double>& ritz_im,
+                 std::string& err);
+
 uint64_t splitmix64_next(uint64_t& state);
 
 }  // namespace pslr

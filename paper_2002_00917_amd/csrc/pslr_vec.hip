@@ -173,6 +173,35 @@ __global__ void k_inv_sqrt(int ncol, const double* __restrict__ nn, const uint8_
   scl[c] = (active[c] && v > 0.0) ? 1.0 / sqrt(v) : 0.0;
 }
 
+// Vn[:, c] = sum_j V[:, j] W_s[j, c] (c < ncols) on the rows of the listed
+// chunks, whose column index is the system s; W holds one mcols x ncols
+// column-major matrix per system.  The basis change of a Krylov-Schur restart.
+constexpr int kRotTile = 8;
+__global__ void k_basis_rotate(const Chunk* __restrict__ ch, const Seg* __restrict__ cols, int mcols,
+                               int ncols, const double* __restrict__ V, int64_t ldv,
+                               const double* __restrict__ W, double* Vn, int64_t ldn) {
+  const Chunk C = ch[blockIdx.x];
+  const Seg sg = cols[C.col];
+  const double* Ws = W + (int64_t)C.col * mcols * ncols;
+  for (int64_t r = C.r0 + threadIdx.x; r < C.r1; r += blockDim.x) {
+    const int64_t row = sg.base + r;
+    for (int c0 = 0; c0 < ncols; c0 += kRotTile) {
+      double acc[kRotTile];
+#pragma unroll
+      for (int t = 0; t < kRotTile; ++t) acc[t] = 0.0;
+      for (int j = 0; j < mcols; ++j) {
+        const double v = V[(int64_t)j * ldv + row];
+#pragma unroll
+        for (int t = 0; t < kRotTile; ++t)
+          if (c0 + t < ncols) acc[t] += v * Ws[(int64_t)(c0 + t) * mcols + j];
+      }
+#pragma unroll
+      for (int t = 0; t < kRotTile; ++t)
+        if (c0 + t < ncols) Vn[(int64_t)(c0 + t) * ldn + row] = acc[t];
+    }
+  }
+}
+
 inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
@@ -214,6 +243,15 @@ hipError_t launch_scale_chunk(int nchunk, const Chunk* ch, const Seg* scols, con
   if (nchunk <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_scale_chunk, dim3(nchunk), dim3(kChunkThreads), 0, s, ch, scols, dcols, S,
                      scale, D);
+  return hipGetLastError();
+}
+
+hipError_t launch_basis_rotate(int nchunk, const Chunk* ch, const Seg* cols, int mcols, int ncols,
+                               const double* V, int64_t ldv, const double* W, double* Vn, int64_t ldn,
+                               hipStream_t s) {
+  if (nchunk <= 0 || ncols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_basis_rotate, dim3(nchunk), dim3(kChunkThreads), 0, s, ch, cols, mcols, ncols, V,
+                     ldv, W, Vn, ldn);
   return hipGetLastError();
 }
 

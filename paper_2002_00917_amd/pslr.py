@@ -35,7 +35,7 @@ class pslr_options(C.Structure):
                 ("want_transpose", C.c_int32), ("v0", C.POINTER(C.c_double)),
                 ("seed", C.c_uint64), ("pivot_threshold", C.c_double), ("nthreads", C.c_int32),
                 ("working_vectors", C.c_int32), ("autotune", C.c_int32), ("threads", C.c_int32),
-                ("factor", C.c_int32), ("drop_tol", C.c_double)]
+                ("factor", C.c_int32), ("drop_tol", C.c_double), ("lowrank", C.c_int32)]
 
 
 class pslr_host_stats_t(C.Structure):
@@ -57,7 +57,9 @@ class pslr_info_t(C.Structure):
                 ("seconds_factor", C.c_double), ("seconds_arnoldi", C.c_double),
                 ("nsys", C.c_int32), ("global_vectors", C.c_int32), ("threads", C.c_int32),
                 ("lane_shift", C.c_int32), ("max_tile", C.c_int32), ("v_bf16", C.c_int32),
-                ("bf16_probe", C.c_double)]
+                ("bf16_probe", C.c_double), ("lowrank", C.c_int32), ("ks_restarts", C.c_int32),
+                ("ks_applies", C.c_int64), ("ks_residual", C.c_double),
+                ("ritz_above_one", C.c_int32), ("pad0", C.c_int32)]
 
 
 class pslr_trace_t(C.Structure):
@@ -95,6 +97,8 @@ _SIGS = {
                                       C.POINTER(pslr_options), _F64P, _F64P]),
     "pslr_host_stats": (C.c_int, [C.c_int64, _I64P, _I32P, _F64P, _I32P, C.c_int32,
                                   C.POINTER(pslr_options), C.POINTER(pslr_host_stats_t)]),
+    "pslr_host_schur_select": (C.c_int, [C.c_int32, _F64P, C.c_int64, C.c_int32, _F64P, C.c_int64,
+                                         _F64P, C.c_int64, _F64P, _F64P, _I32P]),
     "pslr_destroy": (C.c_int, [_P]),
     "pslr_status_string": (C.c_char_p, [C.c_int]),
     "pslr_last_error": (C.c_char_p, []),
@@ -190,9 +194,14 @@ def pslr_default_options():
 FACTORS = {"lu": 0, "ilut": 1}
 
 
+LOWRANK = {"arnoldi": 0, "krylov_schur": 1, "deflate_unit": 2}
+
+
 def _options(m, rank, precision, want_transpose, v0, seed, pivot_threshold, nthreads,
-             working_vectors, autotune=False, threads=0, factor="lu", drop_tol=1e-2):
+             working_vectors, autotune=False, threads=0, factor="lu", drop_tol=1e-2,
+             lowrank="arnoldi"):
     o = pslr_default_options()
+    o.lowrank = LOWRANK[lowrank]
     o.threads = int(threads)
     o.factor = FACTORS[factor]
     o.drop_tol = float(drop_tol)
@@ -210,14 +219,14 @@ def _options(m, rank, precision, want_transpose, v0, seed, pivot_threshold, nthr
 def pslr_setup(rowptr, colind, vals, part, nparts, m=3, rank=16, precision=0,
                want_transpose=False, v0=None, seed=1, pivot_threshold=0.1, nthreads=0,
                working_vectors=0, autotune=False, threads=0, factor="lu", drop_tol=1e-2,
-               stream=None) -> Handle:
+               lowrank="arnoldi", stream=None) -> Handle:
     L = lib()
     rp, rpp = _arr(rowptr, np.int64)
     ci, cip = _arr(colind, np.int32)
     va, vap = _arr(vals, np.float64)
     pa, pap = _arr(part, np.int32)
     o, keep = _options(m, rank, precision, want_transpose, v0, seed, pivot_threshold, nthreads,
-                       working_vectors, autotune, threads, factor, drop_tol)
+                       working_vectors, autotune, threads, factor, drop_tol, lowrank)
     out = C.c_void_p()
     n = len(rp) - 1
     st = L.pslr_setup(n, rpp, cip, vap, pap, int(nparts), C.byref(o), _stream_ptr(stream),
@@ -230,7 +239,7 @@ def pslr_setup(rowptr, colind, vals, part, nparts, m=3, rank=16, precision=0,
 def pslr_setup_batched(rowptr, colind, vals, part, nparts, sys_ptr, m=3, rank=16, precision=0,
                        want_transpose=False, v0=None, seed=1, pivot_threshold=0.1, nthreads=0,
                        working_vectors=0, autotune=False, threads=0, factor="lu", drop_tol=1e-2,
-                       stream=None) -> Handle:
+                       lowrank="arnoldi", stream=None) -> Handle:
     L = lib()
     rp, rpp = _arr(rowptr, np.int64)
     ci, cip = _arr(colind, np.int32)
@@ -238,7 +247,7 @@ def pslr_setup_batched(rowptr, colind, vals, part, nparts, sys_ptr, m=3, rank=16
     pa, pap = _arr(part, np.int32)
     sp, spp = _arr(sys_ptr, np.int64)
     o, keep = _options(m, rank, precision, want_transpose, v0, seed, pivot_threshold, nthreads,
-                       working_vectors, autotune, threads, factor, drop_tol)
+                       working_vectors, autotune, threads, factor, drop_tol, lowrank)
     out = C.c_void_p()
     n = len(rp) - 1
     st = L.pslr_setup_batched(n, rpp, cip, vap, pap, int(nparts), len(sp) - 1, spp, C.byref(o),
@@ -408,3 +417,21 @@ def pslr_host_selfcheck(rowptr, colind, vals, part, nparts, want_transpose=True,
     _check(lib().pslr_host_selfcheck(len(rp) - 1, rpp, cip, vap, pap, int(nparts), C.byref(o),
                                      C.byref(fr), C.byref(sr)))
     return fr.value, sr.value
+
+
+def pslr_host_schur_select(Hm, k):
+    """(W, Hk, ritz) of the host-only Krylov-Schur truncation step (no GPU)."""
+    Hm = np.asfortranarray(Hm, dtype=np.float64)
+    n = Hm.shape[0]
+    kk = max(min(int(k), n), 1)
+    W = np.zeros((n, kk), dtype=np.float64, order="F")
+    Hk = np.zeros((kk, kk), dtype=np.float64, order="F")
+    rr = np.zeros(max(n, 1))
+    ri = np.zeros(max(n, 1))
+    kept = C.c_int32()
+    dp = lambda a: a.ctypes.data_as(_F64P)  # noqa: E731
+    _check(lib().pslr_host_schur_select(n, dp(Hm), max(n, 1), int(k), dp(W), max(n, 1), dp(Hk), kk,
+                                        dp(rr), dp(ri), C.byref(kept)))
+    kp = kept.value
+    return W[:, :kp].copy(), Hk[:kp, :kp].copy(), rr[:n] + 1j * ri[:n]
+

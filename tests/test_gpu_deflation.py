@@ -1,0 +1,166 @@
+"""Deflated low-rank setup on the GPU (lowrank = 1: Krylov-Schur keeping r_k;
+lowrank = 2: kept count grown to every eigenvalue of E_rr(m) outside the unit
+circle) against the oracle's Krylov-Schur (oracle/deflation.py), through the
+C ABI.
+
+The converged invariant subspace is unique where its Ritz values are
+separated from the rest, the basis inside it is not: the checks compare
+projectors, eigenvalues of H, the invariance residual measured with the
+oracle's operator, and applies (with the library's V, H imported into the
+oracle: 1e-12; with each side's own basis: 1e-6, the convergence tolerance
+1e-9 over the eigenvalue gap)."""
+import numpy as np
+import pytest
+
+from paper_2002_00917_amd import workloads as wl
+from paper_2002_00917_amd import pslr as P
+from oracle import partition as opart
+from oracle import pslr as opslr
+from oracle import deflation as odefl
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def cases():
+    out = []
+    A = wl.laplacian2d(12, wl.sigma_for_negatives(wl.laplacian_eigs((12, 12)), 10))
+    out.append(("lap2d_12_10neg", A, opart.geometric_labels((12, 12), (2, 2)), 2, 10))
+    A = wl.laplacian3d(8, wl.sigma_for_negatives(wl.laplacian_eigs((8, 8, 8)), 11))
+    out.append(("lap3d_8_11neg", A, opart.geometric_labels((8, 8, 8), (2, 2, 2)), 3, 12))
+    A = wl.convdiff3d(7, 10.0, 0.8)
+    out.append(("convdiff_7_rg", A, opart.region_growing_labels(A.to_scipy(), 5, 7), 2, 8))
+    return out
+
+
+CASES = cases()
+IDS = [c[0] for c in CASES]
+
+
+def _apply(h, b):
+    bt = torch.tensor(np.ascontiguousarray(b.T), dtype=torch.float64, device=_dev())
+    z = torch.zeros_like(bt)
+    P.pslr_apply(h, bt, z)
+    torch.cuda.synchronize()
+    return z.cpu().numpy().T
+
+
+def _rel(a, b):
+    return float(np.max(np.linalg.norm(a - b, axis=0) / np.linalg.norm(b, axis=0)))
+
+
+@pytest.mark.parametrize("name,A,lab,m,k", CASES, ids=IDS)
+def test_krylov_schur_matches_oracle(name, A, lab, m, k):
+    print("case", name, flush=True)
+    As = A.to_scipy()
+    nparts = int(lab.max()) + 1
+    pre = opslr.PSLR(As, lab, m, 0)
+    q = pre.blk.q
+    v0 = wl.start_vector(q, 3)
+    Vo, Ho, info_o = odefl.krylov_schur(pre.err_op, v0, k, tol=1e-11)
+    h = P.pslr_setup(A.rowptr, A.colind, A.vals, lab, nparts, m=m, rank=k, v0=v0,
+                     lowrank="krylov_schur")
+    info = P.pslr_info(h)
+    Vl, Hl = P.pslr_get_lowrank(h)
+    print(name, "kept", Vl.shape[1], Vo.shape[1], "restarts", info["ks_restarts"],
+          info_o["restarts"], "applies", info["ks_applies"], "residual %.2e" % info["ks_residual"],
+          flush=True)
+    assert Vl.shape[1] == Vo.shape[1]
+    kk = Vl.shape[1]
+    assert np.abs(Vl.T @ Vl - np.eye(kk)).max() < 1e-12
+    EV = np.column_stack([pre.err_op(Vl[:, j]) for j in range(kk)])
+    nE = max(np.linalg.norm(EV, 2), 1.0)
+    inv = np.linalg.norm(EV - Vl @ Hl, 2) / nE
+    proj = np.abs(Vl @ Vl.T - Vo @ Vo.T).max()
+    print(name, "invariance %.2e projector diff %.2e" % (inv, proj), flush=True)
+    assert np.abs(Hl - Vl.T @ EV).max() < 1e-10 * nE
+    assert inv < 1e-7
+    assert proj < 1e-6
+    np.testing.assert_allclose(np.sort(np.abs(np.linalg.eigvals(Hl))),
+                               np.sort(np.abs(np.linalg.eigvals(Ho))), rtol=1e-7)
+    # applies: the library's V, H in the oracle (same operator), then each side's own basis
+    b = wl.normal_rhs(A.n, 2, 11)
+    zl = _apply(h, b)
+    pre.set_lowrank(Vl, Hl)
+    e_same = _rel(zl, pre.apply(b))
+    pre.set_lowrank(Vo, Ho)
+    e_own = _rel(zl, pre.apply(b))
+    print(name, "apply vs oracle: same V %.2e, own V %.2e" % (e_same, e_own), flush=True)
+    assert e_same <= 1e-12
+    assert e_own <= 1e-6
+
+
+def test_growth_deflates_every_eigenvalue_outside_the_unit_circle():
+    name, A, lab, m, _ = CASES[1]
+    As = A.to_scipy()
+    pre = opslr.PSLR(As, lab, m, 0)
+    v0 = wl.start_vector(pre.blk.q, 9)
+    Vo, Ho, _ = odefl.krylov_schur(pre.err_op, v0, 4, tol=1e-11, grow=True)
+    h = P.pslr_setup(A.rowptr, A.colind, A.vals, lab, 8, m=m, rank=4, v0=v0, lowrank="deflate_unit")
+    info = P.pslr_info(h)
+    Vl, Hl = P.pslr_get_lowrank(h)
+    n_out_o = int(np.sum(np.abs(np.linalg.eigvals(Ho)) > 1.0))
+    print("grow: rank", info["rank"], Vo.shape[1], "above one", info["ritz_above_one"], n_out_o,
+          flush=True)
+    assert info["rank"] == Vl.shape[1] == Vo.shape[1]
+    assert info["ritz_above_one"] == n_out_o
+    assert int(np.sum(np.abs(np.linalg.eigvals(Hl)) > 1.0)) == n_out_o
+    assert np.abs(Vl @ Vl.T - Vo @ Vo.T).max() < 1e-6
+    # FGMRES with the deflated preconditioner
+    b = wl.normal_rhs(A.n, 1, 12)
+    bt = torch.tensor(np.ascontiguousarray(b.T), dtype=torch.float64, device=_dev())
+    x = torch.zeros_like(bt)
+    st, its, rel = P.fgmres_solve(h, bt, x, restart=20, maxit=200, tol=1e-10)
+    print("grow: fgmres its", its, "relres", rel, flush=True)
+    assert st == P.PSLR_OK and rel[0] <= 1e-10
+
+
+def test_batched_krylov_schur():
+    """Three systems in one handle: each system's apply equals the oracle apply
+    with that system's own Krylov-Schur basis (to the subspace tolerance), and
+    batched FGMRES converges for every (system, rhs) pair."""
+    dev = _dev()
+    systems = []
+    for N, nneg, parts in ((12, 6, (2, 2)), (16, 8, (2, 3)), (10, 4, (2, 2))):
+        A = wl.laplacian2d(N, wl.sigma_for_negatives(wl.laplacian_eigs((N, N)), nneg))
+        systems.append((A, opart.geometric_labels((N, N), parts)))
+    rowptr, colind, vals, labs, sys_ptr = [0], [], [], [], [0]
+    off_n, off_l = 0, 0
+    for A, lab in systems:
+        rowptr.extend((A.rowptr[1:] + rowptr[-1]).tolist())
+        colind.append(A.colind + off_n)
+        vals.append(A.vals)
+        labs.append(lab + off_l)
+        off_n += A.n
+        off_l += int(lab.max()) + 1
+        sys_ptr.append(off_n)
+    rowptr = np.array(rowptr, dtype=np.int64)
+    colind = np.concatenate(colind).astype(np.int32)
+    vals = np.concatenate(vals)
+    lab = np.concatenate(labs).astype(np.int32)
+    k, m = 8, 2
+    # per-system start vectors, concatenated in interface order
+    pres = [opslr.PSLR(A.to_scipy(), l, m, 0) for A, l in systems]
+    v0s = [wl.start_vector(p.blk.q, 20 + i) for i, p in enumerate(pres)]
+    h = P.pslr_setup_batched(rowptr, colind, vals, lab, off_l, sys_ptr, m=m, rank=k,
+                             v0=np.concatenate(v0s), lowrank="krylov_schur")
+    b = wl.normal_rhs(off_n, 2, 13)
+    z = _apply(h, b)
+    for i, (A, l) in enumerate(systems):
+        Vo, Ho, _ = odefl.krylov_schur(pres[i].err_op, v0s[i], k, tol=1e-11)
+        pres[i].set_lowrank(Vo, Ho)
+        r0, r1 = sys_ptr[i], sys_ptr[i + 1]
+        e = _rel(z[r0:r1], pres[i].apply(b[r0:r1]))
+        print("batched system", i, "kept", Vo.shape[1], "apply vs oracle %.2e" % e, flush=True)
+        assert e <= 1e-6
+    bt = torch.tensor(np.ascontiguousarray(b.T), dtype=torch.float64, device=dev)
+    x = torch.zeros_like(bt)
+    st, its, rel = P.fgmres_solve(h, bt, x, restart=20, maxit=300, tol=1e-10)
+    print("batched fgmres its", its, "relres", rel, flush=True)
+    assert st == P.PSLR_OK and np.all(rel <= 1e-10)

@@ -149,3 +149,33 @@ def test_raw_arnoldi_is_not_invariant_but_deflation_is():
     rk = np.linalg.norm(np.column_stack([pre.err_op(Vk[:, j]) for j in range(Vk.shape[1])]) - Vk @ Hk)
     np.testing.assert_allclose(ra, abs(Hbar[-1, -1]), rtol=1e-8)
     assert rk < 1e-6 * ra
+
+
+def test_growth_keeps_every_eigenvalue_outside_the_unit_circle():
+    """grow=True (Sec. 3.2.2): started with a rank below the count, the kept
+    space grows until it holds every eigenvalue of E_rr of modulus above 1; in
+    the shifted symmetric case that count is neg(A) - neg(B) (inertia), and
+    the kept space contains the dense invariant subspace of those eigenvalues
+    (E_s C0^{-1} may also have eigenvalues below -1, so the count outside the
+    unit circle is at least neg(A) - neg(B))."""
+    A = wl.laplacian3d(8, wl.sigma_for_negatives(wl.laplacian_eigs((8, 8, 8)), 11))
+    As = A.to_scipy()
+    lab = opart.geometric_labels((8, 8, 8), (2, 2, 2))
+    pre = opslr.PSLR(As, lab, 2, 0)
+    negA = int(np.sum(np.linalg.eigvalsh(As.toarray()) < 0))
+    negB = int(np.sum(np.linalg.eigvalsh(pre.blk.B.toarray()) < 0))
+    S, Pm, Err = dense_err(pre)
+    lam = np.linalg.eigvals(Err)
+    n_out = int(np.sum(np.abs(lam) > 1.0))
+    assert n_out >= negA - negB and n_out > 4
+    V, H, info = odefl.krylov_schur(pre.err_op, wl.start_vector(pre.blk.q, 9), 4, tol=1e-11,
+                                    grow=True)
+    th = np.linalg.eigvals(H)
+    assert V.shape[1] >= n_out + 1
+    assert int(np.sum(np.abs(th) > 1.0)) == n_out
+    assert np.abs(th).min() <= 1.0
+    Qd, _ = top_invariant_basis(Err, n_out)
+    assert np.linalg.norm(Qd - V @ (V.T @ Qd)) < 1e-7
+    # without growth the same start keeps only 4
+    V4, _, _ = odefl.krylov_schur(pre.err_op, wl.start_vector(pre.blk.q, 9), 4, tol=1e-11)
+    assert V4.shape[1] == 4
