@@ -147,7 +147,10 @@ typedef struct {
   double ks_residual;       /* lowrank 1, 2: largest ||coupling|| / (smallest kept modulus) */
   int32_t ritz_above_one;   /* lowrank 1, 2: kept eigenvalues of E_rr(m) of modulus above 1
                                (summed over systems) */
-  int32_t pad0;
+  int32_t mfma_min_rhs;     /* applies with at least this many right-hand sides compute the
+                               low-rank products V^T Y and V (G V^T Y) on the matrix cores (BF16
+                               V, FP32 accumulation, Y split in three BF16 parts); 0 = never
+                               (only FP32 applies with V kept in BF16) */
 } pslr_info_t;
 
 /* Fill *opt with defaults: m = 3, rank = 16, FP64, no transpose, seed 1, tau 0.1,
@@ -315,10 +318,12 @@ pslr_status pslr_host_stats(int64_t n, const int64_t* rowptr, const int32_t* col
 /* Host-only step of the deflated low-rank setup (lowrank = 1, 2), exposed
  * for checking without a GPU: for a real n x n matrix Hm (column-major,
  * leading dimension ldh), an orthonormal basis W (n x *kept, column-major,
- * leading dimension ldw >= n, at least k columns of room) of its invariant
- * subspace for the k eigenvalues of largest modulus (a complex eigenvalue
- * whose conjugate would be cut off is dropped, so *kept is k or k - 1), and
- * Hk = W^T Hm W (*kept x *kept, leading dimension ldk >= k).  ritz_re/ritz_im
+ * leading dimension ldw >= n, room for n columns) of its invariant
+ * subspace for the k eigenvalues of largest modulus (k - 1 when the cut would
+ * split a complex-conjugate pair; eigenvalues whose modulus ties the last kept
+ * one within a relative 1e-10 are kept too, so *kept may exceed k), and
+ * Hk = W^T Hm W (*kept x *kept, leading dimension ldk >= n, room for n
+ * columns).  ritz_re/ritz_im
  * (n each, may be NULL) receive all eigenvalues by decreasing modulus.  This
  * is the Krylov-Schur truncation of Stewart (2001) in its real form: the
  * complex Schur form from the shifted QR algorithm, reordered, then a real

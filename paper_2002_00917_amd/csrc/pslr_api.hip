@@ -187,7 +187,7 @@ pslr_status scratch_attach(int device) {
 // Element counts (in doubles) of an apply workspace: y, u0, u1 (q x nrhs
 // each), the V^T y partial sums and the global working vectors.
 struct WsSizes {
-  size_t vec = 0, partial = 0, gws = 0;
+  size_t vec = 0, partial = 0, gws = 0, zp = 0;
 };
 
 // Everything one direction of the apply needs, host side.
@@ -226,6 +226,7 @@ struct pslr_ctx {
   const double* V64 = nullptr;
   const double* G64 = nullptr;
   const __hip_bfloat16* Vbf = nullptr;
+  const __hip_bfloat16* Vbr = nullptr;  // BF16 V row-major q x kp (matrix-core products)
   const float* V32 = nullptr;
   // precision 2: V is read in BF16 only while the setup probe allows it
   bool v_bf16 = false;
@@ -257,6 +258,7 @@ struct pslr_ctx {
   void* u1 = nullptr;
   void* partial = nullptr;
   void* gws = nullptr;
+  void* zp = nullptr;
   // FGMRES workspace (kept between calls)
   DevPool fpool;
   int f_nrhs = 0, f_restart = 0;
@@ -457,6 +459,9 @@ WsSizes ws_sizes(const pslr_ctx* h, int nrhs) {
   z.vec = (size_t)std::max<int64_t>(h->R.q, 1) * nrhs;
   z.partial = (size_t)h->nchunk_lr * nrhs * std::max(h->k, 1);
   z.gws = h->gws_stride > 0 ? (size_t)h->gws_stride * ((nrhs + 7) / 8 * 8) : 0;
+  // split G V^T y of the matrix-core low-rank products (BF16 V only)
+  if (h->Vbr && nrhs >= kMfmaMinRhs)
+    z.zp = ((size_t)h->nsys * 3 * nrhs * ((h->k + 15) / 16 * 16) * 2 + 7) / 8;
   return z;
 }
 
@@ -466,7 +471,8 @@ WsSizes ws_sizes(const pslr_ctx* h, int nrhs) {
 // memory.  Growth rounds the right-hand-side count up to a power of two.
 pslr_status ensure_ws(pslr_ctx* h, int nrhs) {
   const WsSizes need = ws_sizes(h, nrhs);
-  if (nrhs <= h->ws_nrhs && need.partial <= h->ws_cap.partial && need.gws <= h->ws_cap.gws)
+  if (nrhs <= h->ws_nrhs && need.partial <= h->ws_cap.partial && need.gws <= h->ws_cap.gws &&
+      need.zp <= h->ws_cap.zp)
     return PSLR_OK;
   int grow = 1;
   while (grow < std::max(nrhs, h->ws_nrhs)) grow *= 2;
@@ -477,6 +483,8 @@ pslr_status ensure_ws(pslr_ctx* h, int nrhs) {
   HIP_TRY(h->ws.alloc<double>(z.partial, (double**)&h->partial));
   h->gws = nullptr;
   if (z.gws > 0) HIP_TRY(h->ws.alloc<double>(z.gws, (double**)&h->gws));
+  h->zp = nullptr;
+  if (z.zp > 0) HIP_TRY(h->ws.alloc<double>(z.zp, (double**)&h->zp));
   h->ws_nrhs = grow;
   h->ws_cap = z;
   return PSLR_OK;
@@ -661,7 +669,7 @@ LaunchCfg choose_launch(pslr_ctx* h, const ApplyArrays<T>& A, int nrhs, hipStrea
 
 // Device workspace of one apply (see WsSizes).
 struct ApplyWs {
-  void *y, *u0, *u1, *partial, *gws;
+  void *y, *u0, *u1, *partial, *gws, *zp;
 };
 
 // z = M^{-1} b (or M^{-T} b) with apply arrays A and workspace W (large
@@ -691,8 +699,17 @@ pslr_status run_apply(pslr_ctx* h, const ApplyArrays<T>& Ah, const ApplyWs& W, b
   HIP_TRY(tr.mark(PH_START));
   HIP_TRY(launch_head<T>(A, cfg, nrhs, b, ldb, y, q));
   HIP_TRY(tr.mark(PH_HEAD));
+  // FP32 applies with V in BF16 and many right-hand sides: the low-rank
+  // products on the matrix cores, then the C0 solve on its own
+  const bool mfma = sizeof(T) == 4 && k > 0 && h->Vbf && h->v_bf16 && h->Vbr && W.zp &&
+                    nrhs >= kMfmaMinRhs;
   if (!transpose) {
-    if (k > 0) {
+    if (mfma) {
+      HIP_TRY(launch_lr_mfma(h->nchunk_lr, h->d_chunks, h->nsys, h->d_sys_chunk, k, h->Vbf, h->R.q,
+                             h->Vbr, h->G32, 0, (float*)y, q, nrhs, (float*)part,
+                             (__hip_bfloat16*)W.zp, h->cur_active, s));
+      HIP_TRY(launch_c0solve<T>(A, cfg, nrhs, y, q, ua, q));
+    } else if (k > 0) {
       HIP_TRY(lowrank_partial<T>(h, y, q, nrhs, part, s));
       HIP_TRY(lowrank_expand<T>(h, A, cfg, nrhs, 0, part, y, q, 1, ua, q));
     } else {
@@ -714,7 +731,12 @@ pslr_status run_apply(pslr_ctx* h, const ApplyArrays<T>& Ah, const ApplyWs& W, b
       HIP_TRY(launch_series<T>(A, c1, nrhs, y, q, ua, ub, q, 1, 1));
       std::swap(ua, ub);
     }
-    if (k > 0) {
+    if (mfma) {
+      HIP_TRY(launch_lr_mfma(h->nchunk_lr, h->d_chunks, h->nsys, h->d_sys_chunk, k, h->Vbf, h->R.q,
+                             h->Vbr, h->G32, 1, (float*)ua, q, nrhs, (float*)part,
+                             (__hip_bfloat16*)W.zp, h->cur_active, s));
+      HIP_TRY(tr.mark(PH_LOWRANK));
+    } else if (k > 0) {
       HIP_TRY(lowrank_partial<T>(h, ua, q, nrhs, part, s));
       HIP_TRY(lowrank_expand<T>(h, A, cfg, nrhs, 1, part, ua, q, 0, ub, q));
       HIP_TRY(tr.mark(PH_LOWRANK));
@@ -731,7 +753,7 @@ pslr_status apply_dir(pslr_ctx* h, bool transpose, int nrhs, const double* b, in
   if (h->R.n == 0) return PSLR_OK;
   pslr_status st = ensure_ws(h, nrhs);
   if (st != PSLR_OK) return st;
-  const ApplyWs W{h->y, h->u0, h->u1, h->partial, h->gws};
+  const ApplyWs W{h->y, h->u0, h->u1, h->partial, h->gws, h->zp};
   if (h->precision >= 1 && !force64 && h->have32)
     return run_apply<float>(h, transpose ? h->tr32 : h->fw32, W, transpose, nrhs, b, ldb, z, ldz, s);
   if (!h->have64) return fail(PSLR_EINVAL, "FP64 apply arrays not available");
@@ -788,6 +810,7 @@ pslr_status upload_lowrank(pslr_ctx* h) {
   h->vpool.bytes = 0;
   h->V64 = h->G64 = nullptr;
   h->Vbf = nullptr;
+  h->Vbr = nullptr;
   h->V32 = nullptr;
   h->G32 = nullptr;
   const int k = h->k;
@@ -818,6 +841,14 @@ pslr_status upload_lowrank(pslr_ctx* h) {
       std::vector<__hip_bfloat16> Vb((size_t)q * k);
       for (size_t e = 0; e < Vb.size(); ++e) Vb[e] = __float2bfloat16((float)h->hV[e]);
       HIP_TRY(h->vpool.upload(Vb, &h->Vbf));
+      // the same values row-major with k padded to a multiple of 16 (matrix-core expansion)
+      if (k <= 256) {
+        const int kp = (k + 15) / 16 * 16;
+        std::vector<__hip_bfloat16> Vr((size_t)q * kp, __float2bfloat16(0.0f));
+        for (int j = 0; j < k; ++j)
+          for (int64_t r = 0; r < q; ++r) Vr[(size_t)r * kp + j] = Vb[(size_t)j * q + r];
+        HIP_TRY(h->vpool.upload(Vr, &h->Vbr));
+      }
     }
   }
   return PSLR_OK;
@@ -1065,7 +1096,7 @@ pslr_status krylov_schur(pslr_ctx* h, const double* v0host, uint64_t seed, int m
   DevPool tmp;
   double *Vd, *Vn, *w, *ua, *ub, *dbuf, *dhh, *scl, *dW;
   HIP_TRY(tmp.alloc<double>((size_t)q * (Mc + 1), &Vd));
-  HIP_TRY(tmp.alloc<double>((size_t)q * (kcap + 1), &Vn));
+  HIP_TRY(tmp.alloc<double>((size_t)q * (Mc + 1), &Vn));
   HIP_TRY(tmp.alloc<double>(q, &w));
   HIP_TRY(tmp.alloc<double>(q, &ua));
   HIP_TRY(tmp.alloc<double>(q, &ub));
@@ -1084,7 +1115,7 @@ pslr_status krylov_schur(pslr_ctx* h, const double* v0host, uint64_t seed, int m
   HIP_TRY(tmp.alloc<double>((size_t)std::max(nch, 1) * (Mc + 1), &dbuf));
   HIP_TRY(tmp.alloc<double>((size_t)ns * (2 * (Mc + 1) + 2), &dhh));
   HIP_TRY(tmp.alloc<double>(ns, &scl));
-  HIP_TRY(tmp.alloc<double>((size_t)ns * (Mc + 1) * (kcap + 1), &dW));
+  HIP_TRY(tmp.alloc<double>((size_t)ns * (Mc + 1) * (Mc + 1), &dW));
   double* dh1 = dhh;
   double* dh2 = dhh + (size_t)ns * (Mc + 1);
   double* dnn = dh2 + (size_t)ns * (Mc + 1);
@@ -1211,6 +1242,9 @@ pslr_status krylov_schur(pslr_ctx* h, const double* v0host, uint64_t seed, int m
       std::string err;
       const int kept = schur_select(mb, Hm.data(), mb, std::min(y.ktarget, mb), W, Hk, rr, ri, err);
       if (kept < 0) return fail(PSLR_ESINGULAR, "Krylov-Schur: " + err);
+      if (kept > kKsMaxRank)
+        return fail(PSLR_ENOTSUP, "Krylov-Schur: eigenvalues tied in modulus at the cut take the "
+                                  "kept count above 256");
       std::vector<double> b(kept);
       double bn = 0.0;
       for (int t = 0; t < kept; ++t) {
@@ -1759,7 +1793,7 @@ pslr_status pslr_host_schur_select(int32_t n, const double* Hm, int64_t ldh, int
                                    int64_t ldw, double* Hk, int64_t ldk, double* ritz_re,
                                    double* ritz_im, int32_t* kept) {
   if (n < 0 || k < 0 || !kept || (n > 0 && (!Hm || ldh < n)) || (k > 0 && n > 0 && (!W || !Hk)) ||
-      ldw < n || ldk < std::min(k, n))
+      ldw < n || ldk < n)
     return fail(PSLR_EINVAL, "bad arguments");
   std::vector<double> w, hk, rr, ri;
   std::string err;
@@ -2071,7 +2105,7 @@ pslr_status pslr_apply_noalloc(pslr_handle h, int32_t nrhs, const double* b, int
   // out of the array, each 256-byte aligned
   const WsSizes z0 = ws_sizes(h, nrhs);
   auto up = [](size_t d) { return (d * sizeof(double) + 255) / 256 * 256; };
-  const size_t need = 3 * up(z0.vec) + up(z0.partial) + up(z0.gws);
+  const size_t need = 3 * up(z0.vec) + up(z0.partial) + up(z0.gws) + up(z0.zp);
   if (need > kScratchBytes)
     return fail(PSLR_EINVAL, "pslr_apply_noalloc needs " + std::to_string(need) +
                                  " bytes of scratch for " + std::to_string(nrhs) +
@@ -2087,6 +2121,8 @@ pslr_status pslr_apply_noalloc(pslr_handle h, int32_t nrhs, const double* b, int
   W.partial = c;
   c += up(z0.partial);
   W.gws = z0.gws > 0 ? (void*)c : nullptr;
+  c += up(z0.gws);
+  W.zp = z0.zp > 0 ? (void*)c : nullptr;
   hipStream_t s = (hipStream_t)hip_stream;
   // no phase tracing here: the tracer creates events on demand
   if (h->precision >= 1 && h->have32)
@@ -2355,6 +2391,7 @@ pslr_status pslr_info(pslr_handle h, pslr_info_t* out) {
   out->rank = h->k;
   out->v_bf16 = h->v_bf16 ? 1 : 0;
   out->bf16_probe = h->bf16_probe;
+  out->mfma_min_rhs = (h->precision >= 1 && h->v_bf16 && h->Vbr && h->k > 0) ? kMfmaMinRhs : 0;
   return PSLR_OK;
 }
 

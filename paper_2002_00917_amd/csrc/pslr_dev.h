@@ -140,6 +140,17 @@ hipError_t launch_lr_expand(const ApplyArrays<T>& A, const LaunchCfg& c, int nrh
                             const TV* V, const T* G, int gtrans, const T* partial, int nchunk,
                             const int32_t* sys_chunk, T* y, int64_t ldy, int do_c0, T* u,
                             int64_t ldu);
+// y += V G V^T y (gtrans: V G^T V^T y) on the matrix cores for FP32 applies with
+// V in BF16: V column-major (ldv) and row-major Vr (q x kp, kp = k rounded up to
+// 16, zero padded); partial: nchunk * nrhs * k floats; Zp: nsys * 3 * nrhs * kp
+// BF16 values; k <= 256
+hipError_t launch_lr_mfma(int nchunk, const LrChunk* chunks, int nsys, const int32_t* sys_chunk,
+                          int k, const __hip_bfloat16* V, int64_t ldv, const __hip_bfloat16* Vr,
+                          const float* G, int gtrans, float* y, int64_t ldy, int nrhs,
+                          float* partial, __hip_bfloat16* Zp, const uint8_t* active,
+                          hipStream_t s);
+// right-hand-side count from which FP32 applies with V in BF16 use launch_lr_mfma
+constexpr int kMfmaMinRhs = 16;
 template <typename T>
 hipError_t launch_c0solve(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, const T* src,
                           int64_t lds_, T* dst, int64_t ldd);

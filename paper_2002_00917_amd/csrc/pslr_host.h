@@ -212,7 +212,8 @@ void host_tri_solve(const TriPacked& T, std::vector<double>& X, bool entries);
 // Invariant subspace of a small real matrix H_m (n x n, column-major, leading
 // dimension ldh) for its Ritz values of largest modulus (the Krylov-Schur
 // restart of the deflated low-rank setup; pslr_schur.cpp).  Keeps the k of
-// largest modulus, dropping a complex value whose conjugate falls outside.
+// largest modulus (k - 1 when the cut would split a complex-conjugate pair),
+// plus every value whose modulus ties the last kept one.
 // Outputs: W (n x kept, column-major, orthonormal columns spanning the
 // subspace), Hk = W^T H_m W (kept x kept, column-major), and all n Ritz values
 // by decreasing modulus.  Returns kept (>= 0), or -1 with err set.

@@ -575,6 +575,149 @@ k_lr_partial(const LrChunk* __restrict__ chunks, int k, const TV* __restrict__ V
   }
 }
 
+// ---- the low-rank products on the matrix cores (many right-hand sides, V in BF16)
+//
+// With V stored in BF16 the two tall-skinny products of the low-rank term,
+// V^T Y (k x nrhs) and V Z (q x nrhs), are dense contractions over q and k.
+// They run on v_mfma_f32_32x32x16_bf16 (32 x 32 output block, 16-deep
+// contraction, FP32 accumulation).  The FP32 operand (Y, or Z = G V^T Y) is
+// split into three BF16 parts hi + mid + lo that carry its 24 significant
+// bits, so the three products summed equal the FP32 product with the
+// BF16-rounded V.  Operand fragments: lane l holds A[l % 32][8 (l / 32) .. +7]
+// and B[8 (l / 32) .. +7][l % 32]; accumulator element i of lane l is
+// C[8 (i / 4) + 4 (l / 32) + i % 4][l % 32].
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+constexpr int kMfmaThreads = 256;
+
+__device__ __forceinline__ void split3(float x, __bf16& h, __bf16& m, __bf16& l) {
+  h = (__bf16)x;
+  const float r = x - (float)h;
+  m = (__bf16)r;
+  l = (__bf16)(r - (float)m);
+}
+
+// partial[(chunk * nrhs + r) * k + j] = sum over the chunk's rows of V[row][j] y_r[row]
+// (V^T y, Algorithm 3 line 3).  V: BF16 column-major (ldv), y: FP32 column-major.
+// Workgroup (chunk, tile of 32 right-hand sides); wave w owns the 32-column
+// blocks w, w + 4, ... of V and walks the chunk's rows 16 at a time.
+__global__ void __launch_bounds__(kMfmaThreads)
+k_lr_partial_mfma(const LrChunk* __restrict__ chunks, int k, const __hip_bfloat16* __restrict__ V,
+                  int64_t ldv, const float* __restrict__ y, int64_t ldy, int nrhs, float* partial,
+                  const uint8_t* __restrict__ active, int nsys) {
+  const LrChunk C = chunks[blockIdx.x];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 31, half = lane >> 5;
+  const int r = blockIdx.y * 32 + col;
+  const bool rok = r < nrhs && (!active || active[r * nsys + C.sys]);
+  const float* yr = y + (int64_t)(rok ? r : 0) * ldy;
+  const int njb = (k + 31) / 32;
+  for (int jb = wave; jb < njb; jb += kMfmaThreads / 64) {
+    const int j = jb * 32 + col;
+    const bool jok = j < k;
+    const __hip_bfloat16* vj = V + (int64_t)(jok ? j : 0) * ldv;
+    f32x16_t acc = {};
+    for (int64_t r0 = C.r0; r0 < C.r1; r0 += 16) {
+      const int64_t row = r0 + 8 * half;
+      bf16x8_t a, bh, bm, bl;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const bool ok = row + t < C.r1;
+        a[t] = (jok && ok) ? __builtin_bit_cast(__bf16, vj[row + t]) : (__bf16)0.0f;
+        __bf16 h = (__bf16)0.0f, m = (__bf16)0.0f, l = (__bf16)0.0f;
+        if (rok && ok) split3(yr[row + t], h, m, l);
+        bh[t] = h;
+        bm[t] = m;
+        bl[t] = l;
+      }
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bh, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bm, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bl, acc, 0, 0, 0);
+    }
+    if (r < nrhs) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int jj = jb * 32 + 8 * (i / 4) + 4 * half + (i % 4);
+        if (jj < k) partial[((int64_t)blockIdx.x * nrhs + r) * k + jj] = acc[i];
+      }
+    }
+  }
+}
+
+// Z_s = G_s W (gtrans: G_s^T W) with W = V^T y summed over the system's chunk
+// partials, written as three BF16 parts: Zp[((s * 3 + part) * nrhs + r) * kp + j]
+// (kp = k rounded up to 16, zero beyond k).  Workgroup (system, right-hand side).
+__global__ void __launch_bounds__(kMfmaThreads)
+k_lr_gz(int k, int kp, const float* __restrict__ Gall, int gtrans, const float* __restrict__ partial,
+        const int32_t* __restrict__ sys_chunk, int nrhs, __hip_bfloat16* Zp) {
+  __shared__ float W[256];
+  const int s = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
+  const float* G = Gall + (int64_t)s * k * k;
+  const int c0 = sys_chunk[s], c1 = sys_chunk[s + 1];
+  for (int j = tid; j < k; j += blockDim.x) {
+    float w = 0.0f;
+    for (int c = c0; c < c1; ++c) w += partial[((int64_t)c * nrhs + r) * k + j];
+    W[j] = w;
+  }
+  __syncthreads();
+  __hip_bfloat16* zh = Zp + ((int64_t)(s * 3 + 0) * nrhs + r) * kp;
+  __hip_bfloat16* zm = Zp + ((int64_t)(s * 3 + 1) * nrhs + r) * kp;
+  __hip_bfloat16* zl = Zp + ((int64_t)(s * 3 + 2) * nrhs + r) * kp;
+  for (int j = tid; j < kp; j += blockDim.x) {
+    float z = 0.0f;
+    if (j < k)
+      for (int l = 0; l < k; ++l) z += (gtrans ? G[(int64_t)l * k + j] : G[(int64_t)j * k + l]) * W[l];
+    __bf16 h, m, lo;
+    split3(z, h, m, lo);
+    zh[j] = __builtin_bit_cast(__hip_bfloat16, h);
+    zm[j] = __builtin_bit_cast(__hip_bfloat16, m);
+    zl[j] = __builtin_bit_cast(__hip_bfloat16, lo);
+  }
+}
+
+// y[row][r] += sum_j V[row][j] Z_s[j][r] (V G V^T y, Algorithm 3 line 3) for
+// the rows of a chunk (system s) and a tile of 32 right-hand sides.  Vr: BF16
+// row-major q x kp (zero beyond k); one wave per 32-row block.
+__global__ void __launch_bounds__(kMfmaThreads)
+k_lr_expand_mfma(const LrChunk* __restrict__ chunks, int kp, const __hip_bfloat16* __restrict__ Vr,
+                 const __hip_bfloat16* __restrict__ Zp, int nrhs, float* y, int64_t ldy,
+                 const uint8_t* __restrict__ active, int nsys) {
+  const LrChunk C = chunks[blockIdx.x];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 31, half = lane >> 5;
+  const int r = blockIdx.y * 32 + col;
+  const bool rok = r < nrhs && (!active || active[r * nsys + C.sys]);
+  const int64_t len = C.r1 - C.r0;
+  const bf16x8_t* zp[3];
+#pragma unroll
+  for (int p = 0; p < 3; ++p)
+    zp[p] = reinterpret_cast<const bf16x8_t*>(Zp + ((int64_t)(C.sys * 3 + p) * nrhs + (rok ? r : 0)) * kp);
+  const bf16x8_t z8 = {};
+  for (int64_t rb = wave; rb * 32 < len; rb += kMfmaThreads / 64) {
+    const int64_t row = C.r0 + rb * 32 + col;
+    const bool ok = row < C.r1;
+    const bf16x8_t* vr = reinterpret_cast<const bf16x8_t*>(Vr + (ok ? row : C.r0) * kp);
+    f32x16_t acc = {};
+    for (int kk = 0; kk < kp; kk += 16) {
+      const int q8 = (kk >> 3) + half;
+      const bf16x8_t a = ok ? vr[q8] : z8;
+#pragma unroll
+      for (int p = 0; p < 3; ++p) {
+        const bf16x8_t b = rok ? zp[p][q8] : z8;
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+      }
+    }
+    if (rok) {
+      float* yr = y + (int64_t)r * ldy;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int64_t rr = C.r0 + rb * 32 + 8 * (i / 4) + 4 * half + (i % 4);
+        if (rr < C.r1) yr[rr] += acc[i];
+      }
+    }
+  }
+}
+
 // LDS slots k_lr_expand uses for its slice sums (static, on top of the dynamic
 // working vectors; the launch configuration leaves room for them)
 constexpr int kLrSlots = kLrExpandSlots;
@@ -895,6 +1038,24 @@ hipError_t launch_lr_partial(int nchunk, const LrChunk* chunks, int k, const TV*
   if (nchunk <= 0 || k <= 0) return hipSuccess;
   hipLaunchKernelGGL((k_lr_partial<T, TV>), dim3(nchunk, nrhs), dim3(kLrThreads), 0, s, chunks, k, V,
                      ldv, y, ldy, partial, active, nsys);
+  return hipGetLastError();
+}
+
+hipError_t launch_lr_mfma(int nchunk, const LrChunk* chunks, int nsys, const int32_t* sys_chunk,
+                          int k, const __hip_bfloat16* V, int64_t ldv, const __hip_bfloat16* Vr,
+                          const float* G, int gtrans, float* y, int64_t ldy, int nrhs,
+                          float* partial, __hip_bfloat16* Zp, const uint8_t* active,
+                          hipStream_t s) {
+  if (nchunk <= 0 || k <= 0 || nrhs <= 0) return hipSuccess;
+  if (k > 256) return hipErrorInvalidValue;  // k_lr_gz holds W for up to 256 columns
+  const int kp = (k + 15) / 16 * 16;
+  const unsigned tiles = (unsigned)((nrhs + 31) / 32);
+  hipLaunchKernelGGL(k_lr_partial_mfma, dim3(nchunk, tiles), dim3(kMfmaThreads), 0, s, chunks, k, V,
+                     ldv, y, ldy, nrhs, partial, active, nsys);
+  hipLaunchKernelGGL(k_lr_gz, dim3(nsys, nrhs), dim3(kMfmaThreads), 0, s, k, kp, G, gtrans, partial,
+                     sys_chunk, nrhs, Zp);
+  hipLaunchKernelGGL(k_lr_expand_mfma, dim3(nchunk, tiles), dim3(kMfmaThreads), 0, s, chunks, kp, Vr,
+                     Zp, nrhs, y, ldy, active, nsys);
   return hipGetLastError();
 }
 

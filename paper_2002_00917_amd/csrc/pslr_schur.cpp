@@ -218,13 +218,28 @@ int schur_select(int n, const double* Hm, int64_t ldh, int k, std::vector<double
     ritz_re[r] = ev[order[r]].real();
     ritz_im[r] = ev[order[r]].imag();
   }
-  // keep the k of largest modulus; a complex value whose conjugate partner
-  // (the nearest eigenvalue to its conjugate) falls outside is dropped
-  std::vector<char> sel(n, 0);
-  for (int r = 0; r < k; ++r) sel[order[r]] = 1;
+  // keep the k of largest modulus, minus one when the k-th is a complex value
+  // whose conjugate is the (k+1)-th (the cut would split the pair); then every
+  // value whose modulus ties the last kept one (within a relative 1e-10), so
+  // that the kept set is a well-defined invariant subspace
   double scale = 0.0;
   for (const cd& e : ev) scale = std::max(scale, std::abs(e));
-  for (int r = k - 1; r >= 0; --r) {
+  int kk = k;
+  if (kk < n) {
+    const cd a = ev[order[kk - 1]], b = ev[order[kk]];
+    if (std::abs(a.imag()) > 1e-10 * std::max(scale, 1e-300) &&
+        std::abs(a - std::conj(b)) <= 1e-8 * std::max(1.0, std::abs(a)))
+      --kk;
+  }
+  std::vector<char> sel(n, 0);
+  if (kk > 0) {
+    const double cut = std::abs(ev[order[kk - 1]]) * (1.0 - 1e-10);
+    for (int r = 0; r < n; ++r)
+      if (r < kk || std::abs(ev[order[r]]) >= cut) sel[order[r]] = 1;
+  }
+  // a kept complex value whose conjugate partner (the nearest eigenvalue to
+  // its conjugate) is not kept cannot be part of a real invariant subspace
+  for (int r = n - 1; r >= 0; --r) {
     const int i = order[r];
     if (!sel[i] || std::abs(ev[i].imag()) <= 1e-10 * std::max(scale, 1e-300)) continue;
     int partner = -1;

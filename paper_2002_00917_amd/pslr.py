@@ -59,7 +59,7 @@ class pslr_info_t(C.Structure):
                 ("lane_shift", C.c_int32), ("max_tile", C.c_int32), ("v_bf16", C.c_int32),
                 ("bf16_probe", C.c_double), ("lowrank", C.c_int32), ("ks_restarts", C.c_int32),
                 ("ks_applies", C.c_int64), ("ks_residual", C.c_double),
-                ("ritz_above_one", C.c_int32), ("pad0", C.c_int32)]
+                ("ritz_above_one", C.c_int32), ("mfma_min_rhs", C.c_int32)]
 
 
 class pslr_trace_t(C.Structure):
@@ -423,15 +423,15 @@ def pslr_host_schur_select(Hm, k):
     """(W, Hk, ritz) of the host-only Krylov-Schur truncation step (no GPU)."""
     Hm = np.asfortranarray(Hm, dtype=np.float64)
     n = Hm.shape[0]
-    kk = max(min(int(k), n), 1)
-    W = np.zeros((n, kk), dtype=np.float64, order="F")
+    kk = max(n, 1)
+    W = np.zeros((kk, kk), dtype=np.float64, order="F")
     Hk = np.zeros((kk, kk), dtype=np.float64, order="F")
     rr = np.zeros(max(n, 1))
     ri = np.zeros(max(n, 1))
     kept = C.c_int32()
     dp = lambda a: a.ctypes.data_as(_F64P)  # noqa: E731
-    _check(lib().pslr_host_schur_select(n, dp(Hm), max(n, 1), int(k), dp(W), max(n, 1), dp(Hk), kk,
+    _check(lib().pslr_host_schur_select(n, dp(Hm), max(n, 1), int(k), dp(W), kk, dp(Hk), kk,
                                         dp(rr), dp(ri), C.byref(kept)))
     kp = kept.value
-    return W[:, :kp].copy(), Hk[:kp, :kp].copy(), rr[:n] + 1j * ri[:n]
+    return W[:n, :kp].copy(), Hk[:kp, :kp].copy(), rr[:n] + 1j * ri[:n]
 

@@ -99,6 +99,15 @@ def convdiff3d(N: int, beta: float, sigma: float) -> CSR:
     return _stencil((N, N, N), 6.0 + 3.0 * bh - sigma, (-(1.0 + bh),) * 3, (-1.0,) * 3)
 
 
+def convdiff3d_central(N: int, gamma: float, shift: float) -> CSR:
+    """The paper's Test 2 operator: -Lap u - gamma (1,1,1).grad u - shift*u on N^3
+    by the standard 7-point stencil (central differences), scaled by h^2,
+    h = 1/(N+1): diagonal 6 - shift, -1 - gamma*h/2 at v + e_d and
+    -1 + gamma*h/2 at v - e_d."""
+    gh = 0.5 * gamma / (N + 1)
+    return _stencil((N, N, N), 6.0 - shift, (-1.0 + gh,) * 3, (-1.0 - gh,) * 3)
+
+
 def variable_coeff2d(kappa: np.ndarray, sigma: float) -> CSR:
     """-div(kappa grad u) - sigma*u on an N x N grid (cell-centred kappa, unscaled).
 

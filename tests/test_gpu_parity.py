@@ -21,7 +21,8 @@ and the bound is at most three times the error measured on the MI355X:
   3D 9^3, kappa = 1.6e2: kappa * eps32 = 9.2e-6 (measured up to 4.4e-5; the
     FP32 solves also round the factors, so a few times kappa * eps32);
   the 24^3 upwind case (C4-shaped), kappa = 2.6e3: kappa * eps32 = 1.5e-4
-    (measured up to 2.6e-5).
+    (measured up to 1.6e-4 over runs: the atomic adds change the summation
+    order from run to run, and the FP32 solves also round the factors).
 """
 import numpy as np
 import pytest
@@ -39,7 +40,7 @@ torch = pytest.importorskip("torch")
 
 # per-case bounds where kappa * eps exceeds the benchmark spec's 1e-12 / 1e-5
 TOL64 = {"c1": 1.5e-10}
-TOL32 = {"c1": 3.3e-2, "lap3d_9_2x2x2": 8.4e-5, "c4_shaped": 1.5e-4}
+TOL32 = {"c1": 3.3e-2, "lap3d_9_2x2x2": 8.4e-5, "c4_shaped": 4.5e-4}
 # BF16 storage of V (8 significant bits) against the exact-V preconditioner,
 # where the library keeps it (pslr_info.v_bf16): the rounding breaks V's
 # orthonormality, and the change of the low-rank term is amplified by the
@@ -373,6 +374,21 @@ def test_c4_shaped_32rhs_parity(working_vectors):
             ["lds", "global"][working_vectors], prec, info["max_tile"], info["global_vectors"])
         check(name, "apply 32 rhs", _cols(z), pre.apply(b), tol)
         check(name, "apply_transpose 32 rhs", _cols(zt), pre.apply_transpose(b), tol)
+        if prec == 2 and info["v_bf16"]:
+            # 32 right-hand sides take the matrix-core low-rank products; tiles
+            # of 8 the vector ones: the same operator up to FP32 summation
+            # order, amplified like any FP32 difference by kappa = 2.6e3 (the
+            # case's FP32 bound)
+            z8 = torch.zeros_like(z)
+            zt8 = torch.zeros_like(z)
+            for c in range(0, 32, 8):
+                P.pslr_apply(h, _tens(b[:, c:c + 8]), z8[c:c + 8])
+                P.pslr_apply_transpose(h, _tens(b[:, c:c + 8]), zt8[c:c + 8])
+            torch.cuda.synchronize()
+            assert info["mfma_min_rhs"] == 16
+            check(name, "matrix-core vs vector low-rank products", _cols(z), _cols(z8), tol)
+            check(name, "matrix-core vs vector low-rank products (transposed)", _cols(zt),
+                  _cols(zt8), tol)
 
 
 def test_c2_full_size_apply_parity():
@@ -446,3 +462,27 @@ def test_tile_paths_agree(precision):
             err = np.linalg.norm(zc - single[:, :nr], axis=0) / np.linalg.norm(single[:, :nr], axis=0)
             print(apply.__name__, "precision", precision, "tile", nr, "max rel diff", err.max())
             assert np.all(err <= tol)
+
+
+def test_matrix_core_lowrank_well_conditioned():
+    """The matrix-core low-rank products on a well-conditioned case (2D 37 x 23,
+    15 parts, kappa(B_i, C_i) = 19), rank 40 (two 32-column blocks, the second
+    ragged) and 40 right-hand sides (two tiles of 32, the second ragged):
+    against the oracle with the same BF16-rounded V at the plain FP32 bound."""
+    A = wl.laplacian2d(37, 0.05, Ny=23)
+    lab = opart.geometric_labels((37, 23), (3, 5))
+    h, pre = _pair(A, lab, 2, 40, precision=2, want_T=True)
+    info = P.pslr_info(h)
+    print("well-conditioned: rank", info["rank"], "v_bf16", info["v_bf16"], "bf16_probe %.2e"
+          % info["bf16_probe"], "mfma_min_rhs", info["mfma_min_rhs"], flush=True)
+    assert info["rank"] == 40 and info["v_bf16"] == 1 and info["mfma_min_rhs"] == 16
+    pre.set_lowrank(bf16_round(pre.V), pre.H)
+    b = wl.normal_rhs(A.n, 40, 41)
+    z = torch.zeros((40, A.n), dtype=torch.float64, device=_dev())
+    zt = torch.zeros_like(z)
+    P.pslr_apply(h, _tens(b), z)
+    P.pslr_apply_transpose(h, _tens(b), zt)
+    torch.cuda.synchronize()
+    check("lap2d_37x23 rank 40, 40 rhs", "matrix-core low-rank apply", _cols(z), pre.apply(b), 1e-5)
+    check("lap2d_37x23 rank 40, 40 rhs", "matrix-core low-rank apply_transpose", _cols(zt),
+          pre.apply_transpose(b), 1e-5)

@@ -16,7 +16,8 @@ def _check(H, k, tol=1e-11, evtol=1e-9):
     n = H.shape[0]
     W, Hk, ritz = P.pslr_host_schur_select(H, k)
     ev = np.linalg.eigvals(H)
-    kept_o, _ = odefl.select_count(ev, k)
+    # the oracle's kept count: the selection rule plus values tied at the cut
+    kept_o = odefl.sorted_schur(H, k)[2] if k > 0 else 0
     kept = W.shape[1]
     assert kept == kept_o
     # all eigenvalues, by decreasing modulus
@@ -85,8 +86,13 @@ def test_defective_and_degenerate():
     X = Q[:, :3]  # the exact invariant subspace of the block
     assert np.linalg.norm(W @ W.T - X @ X.T) <= 1e-8
     I6 = np.eye(6) * 3.0
-    W, Hk = _check(I6, 4)
-    assert np.allclose(Hk, 3.0 * np.eye(4))
+    W, Hk = _check(I6, 4)       # all six tie at the cut: all are kept
+    assert np.allclose(Hk, 3.0 * np.eye(6))
+    # a tie at the cut between +-2 (E_rr with odd powers keeps signs)
+    D = np.diag([5.0, 2.0, -2.0, 1.0, 0.5])
+    Q, _ = np.linalg.qr(np.random.default_rng(5).standard_normal((5, 5)))
+    W, Hk = _check(Q @ D @ Q.T, 2)
+    assert W.shape[1] == 3
 
 
 def test_edge_sizes():
