@@ -259,6 +259,19 @@ pslr_status pslr_trace_read(pslr_handle h, pslr_trace_t* out, int32_t reset);
 pslr_status pslr_set_lowrank(pslr_handle h, int32_t k, const double* V, int64_t ldv,
                              const double* H, int64_t ldh);
 
+/* Delta(m, r_k) = ||X||_F ||Z^{-1}||_F with X = E_rr(m) - V H V^T and
+ * Z = I - V H V^T, the upper bound of Prop. l3 on ||S^{-1} - S_app^{-1}|| /
+ * ||S^{-1}|| (Sec. 3.2.3).  ||Z^{-1}||_F comes from G in closed form
+ * (Z^{-1} = I + V G V^T); ||X||_F from applications of E_rr(m) on the device
+ * (FP64, blocks of 32 columns) with the subtraction of V H V^T on the host:
+ * exactly over the q unit vectors when nprobe = 0 (q / 32 blocks of m + 1
+ * E_s C0^{-1} products: meant for small interfaces), else as the mean of
+ * ||X z||^2 over nprobe Rademacher vectors drawn by SplitMix64 from seed (an
+ * unbiased estimate of ||X||_F^2).  Single-system handles.  norm_x, norm_zinv
+ * may be NULL.  Synchronises the stream. */
+pslr_status pslr_delta(pslr_handle h, int32_t nprobe, uint64_t seed, double* delta,
+                       double* norm_x, double* norm_zinv, void* hip_stream);
+
 /* Copy the current V (q x k) and H (k x k) to host arrays (column-major). */
 pslr_status pslr_get_lowrank(pslr_handle h, int32_t* k, double* V, int64_t ldv, double* H,
                              int64_t ldh);

@@ -288,6 +288,17 @@ class PSLR:
         k = self.V.shape[1]
         return Pm @ (np.eye(self.blk.q) + self.V @ self.G @ self.V.T) if k else Pm
 
+    def delta(self):
+        """Delta(m, r_k) = ||X||_F ||Z^{-1}||_F with X = E_rr(m) - V H V^T and
+        Z = I - V H V^T, the bound of Prop. l3 (Sec. 3.2.3), from the dense forms
+        (small inputs).  Returns (delta, ||X||_F, ||Z^{-1}||_F)."""
+        S, Es, Pm, Err = dense_forms(self.blk, self.m)
+        VHV = self.V @ self.H @ self.V.T if self.V.shape[1] else np.zeros_like(Err)
+        X = Err - VHV
+        Zi = np.linalg.inv(np.eye(self.blk.q) - VHV)
+        nx, nz = np.linalg.norm(X), np.linalg.norm(Zi)
+        return nx * nz, nx, nz
+
     def dense_inverse(self):
         """M^{-1} in the permuted ordering from the block LDU inverse with S_app."""
         b = self.blk

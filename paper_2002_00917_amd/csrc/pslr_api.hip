@@ -2433,6 +2433,83 @@ pslr_status pslr_set_lowrank(pslr_handle h, int32_t k, const double* V, int64_t 
   return st;
 }
 
+pslr_status pslr_delta(pslr_handle h, int32_t nprobe, uint64_t seed, double* delta,
+                       double* norm_x, double* norm_zinv, void* hip_stream) {
+  if (!h || !delta || nprobe < 0) return fail(PSLR_EINVAL, "bad arguments");
+  if (h->nsys != 1) return fail(PSLR_EINVAL, "pslr_delta needs a single-system handle");
+  const int64_t q = h->R.q;
+  const int k = h->k;
+  hipStream_t s = (hipStream_t)hip_stream;
+  // ||Z^{-1}||_F^2 = ||I + V G V^T||_F^2 = q + 2 tr(G) + ||G||_F^2 (V orthonormal)
+  double nz2 = (double)q;
+  for (int i = 0; i < k; ++i) {
+    nz2 += 2.0 * h->hG[(size_t)i * k + i];
+    for (int j = 0; j < k; ++j) nz2 += h->hG[(size_t)i * k + j] * h->hG[(size_t)i * k + j];
+  }
+  // ||X||_F^2 = sum_j ||X e_j||^2 (nprobe = 0), else the mean of ||X z||^2 over
+  // nprobe Rademacher vectors z (E[z z^T] = I); X z = E_rr z - V (H (V^T z))
+  const int ncols = nprobe == 0 ? (int)q : nprobe;
+  const int nb = 32;
+  pslr_status st = ensure_ws(h, nb);
+  if (st) return st;
+  DevPool tmp;
+  double *zin, *ua, *ub;
+  HIP_TRY(tmp.alloc<double>((size_t)q * nb, &zin));
+  HIP_TRY(tmp.alloc<double>((size_t)q * nb, &ua));
+  HIP_TRY(tmp.alloc<double>((size_t)q * nb, &ub));
+  ApplyArrays<double> A = h->fw64;
+  A.gws = h->gws;
+  A.active = nullptr;
+  std::vector<double> zb((size_t)q * nb), eb((size_t)q * nb), c(k), d(k);
+  uint64_t state = seed;
+  double nx2 = 0.0;
+  for (int c0 = 0; c0 < ncols; c0 += nb) {
+    const int cb = std::min(nb, ncols - c0);
+    std::fill(zb.begin(), zb.end(), 0.0);
+    for (int t = 0; t < cb; ++t) {
+      if (nprobe == 0) {
+        zb[(size_t)t * q + c0 + t] = 1.0;
+      } else {
+        for (int64_t i = 0; i < q; ++i)
+          zb[(size_t)t * q + i] = (splitmix64_next(state) >> 63) ? 1.0 : -1.0;
+      }
+    }
+    HIP_TRY(hipMemcpyAsync(zin, zb.data(), sizeof(double) * q * cb, hipMemcpyHostToDevice, s));
+    LaunchCfg cfg = choose_launch(h, A, cb, s);
+    const double* cur = zin;
+    for (int r = 0; r <= h->m; ++r) {
+      HIP_TRY(launch_c0solve<double>(A, cfg, cb, cur, q, ua, q));
+      HIP_TRY(launch_series<double>(A, cfg, cb, ua, q, ua, ub, q, 0, 0));
+      cur = ub;
+    }
+    HIP_TRY(hipMemcpyAsync(eb.data(), ub, sizeof(double) * q * cb, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int t = 0; t < cb; ++t) {
+      const double* z = &zb[(size_t)t * q];
+      double* e = &eb[(size_t)t * q];
+      for (int j = 0; j < k; ++j) {  // c = V^T z
+        double a = 0.0;
+        for (int64_t i = 0; i < q; ++i) a += h->hV[(size_t)j * q + i] * z[i];
+        c[j] = a;
+      }
+      for (int i = 0; i < k; ++i) {  // d = H c
+        double a = 0.0;
+        for (int j = 0; j < k; ++j) a += h->hH[(size_t)j * k + i] * c[j];
+        d[i] = a;
+      }
+      for (int j = 0; j < k; ++j)
+        for (int64_t i = 0; i < q; ++i) e[i] -= h->hV[(size_t)j * q + i] * d[j];
+      for (int64_t i = 0; i < q; ++i) nx2 += e[i] * e[i];
+    }
+  }
+  if (nprobe > 0) nx2 /= nprobe;
+  const double nx = std::sqrt(nx2), nz = std::sqrt(std::max(nz2, 0.0));
+  *delta = nx * nz;
+  if (norm_x) *norm_x = nx;
+  if (norm_zinv) *norm_zinv = nz;
+  return PSLR_OK;
+}
+
 pslr_status pslr_get_lowrank(pslr_handle h, int32_t* k, double* V, int64_t ldv, double* H,
                              int64_t ldh) {
   if (!h || !k) return fail(PSLR_EINVAL, "null argument");

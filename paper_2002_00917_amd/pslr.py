@@ -89,6 +89,7 @@ _SIGS = {
     "pslr_trace_read": (C.c_int, [_P, C.POINTER(pslr_trace_t), C.c_int32]),
     "pslr_set_lowrank": (C.c_int, [_P, C.c_int32, _F64P, C.c_int64, _F64P, C.c_int64]),
     "pslr_get_lowrank": (C.c_int, [_P, _I32P, _F64P, C.c_int64, _F64P, C.c_int64]),
+    "pslr_delta": (C.c_int, [_P, C.c_int32, C.c_uint64, _F64P, _F64P, _F64P, _P]),
     "pslr_partition_geometric": (C.c_int, [C.c_int32, _I32P, _I32P, _I32P]),
     "pslr_partition_region_growing": (C.c_int, [C.c_int64, _I64P, _I32P, C.c_int32, C.c_uint64,
                                                 _I32P, _I32P]),
@@ -337,6 +338,14 @@ def pslr_set_lowrank(h: Handle, V, H):
     q = V.shape[0]
     _check(lib().pslr_set_lowrank(h.ptr, k, V.ctypes.data_as(_F64P), max(q, 1),
                                   H.ctypes.data_as(_F64P), max(k, 1)))
+
+
+def pslr_delta(h: Handle, nprobe=0, seed=1, stream=None):
+    """(Delta(m, r_k), ||X||_F, ||Z^{-1}||_F) of Prop. l3; nprobe = 0: exact."""
+    d, nx, nz = C.c_double(), C.c_double(), C.c_double()
+    _check(lib().pslr_delta(h.ptr, int(nprobe), int(seed), C.byref(d), C.byref(nx), C.byref(nz),
+                            _stream_ptr(stream)))
+    return d.value, nx.value, nz.value
 
 
 def pslr_get_lowrank(h: Handle):

@@ -164,3 +164,27 @@ def test_batched_krylov_schur():
     st, its, rel = P.fgmres_solve(h, bt, x, restart=20, maxit=300, tol=1e-10)
     print("batched fgmres its", its, "relres", rel, flush=True)
     assert st == P.PSLR_OK and np.all(rel <= 1e-10)
+
+
+@pytest.mark.parametrize("lowrank", ["arnoldi", "krylov_schur"])
+def test_delta_matches_oracle(lowrank):
+    """Delta(m, r_k) of Prop. l3 from the library (exact, q unit vectors) against
+    the oracle's dense Delta with the same V, H: 1e-6 relative.  The Rademacher
+    estimate (256 probes) lies within 25% of it, and deflation lowers Delta."""
+    name, A, lab, m, k = CASES[1]
+    As = A.to_scipy()
+    pre = opslr.PSLR(As, lab, m, 0)
+    v0 = wl.start_vector(pre.blk.q, 3)
+    h = P.pslr_setup(A.rowptr, A.colind, A.vals, lab, 8, m=m, rank=k, v0=v0, lowrank=lowrank)
+    Vl, Hl = P.pslr_get_lowrank(h)
+    pre.set_lowrank(Vl, Hl)
+    d_o, nx_o, nz_o = pre.delta()
+    d, nx, nz = P.pslr_delta(h, 0)
+    de, _, _ = P.pslr_delta(h, 256, seed=5)
+    print(lowrank, "Delta library %.6e oracle %.6e (||X|| %.4e / %.4e, ||Z^-1|| %.4e / %.4e), "
+          "estimate %.4e" % (d, d_o, nx, nx_o, nz, nz_o, de), flush=True)
+    assert abs(d - d_o) <= 1e-6 * d_o
+    assert abs(de - d) <= 0.25 * d
+    if lowrank == "krylov_schur":
+        h0 = P.pslr_setup(A.rowptr, A.colind, A.vals, lab, 8, m=m, rank=k, v0=v0)
+        assert d < P.pslr_delta(h0, 0)[0]

@@ -53,6 +53,16 @@ def test_generators_match_closed_form_spectra():
     A = wl.convdiff3d(5, 10.0, 0.0).to_scipy().toarray()
     ev = np.sort(np.linalg.eigvals(A).real)
     np.testing.assert_allclose(ev, wl.convdiff_eigs(5, 10.0), atol=1e-10)
+    # the paper's Test 2 operator (central differences, gamma = (1,1,1) * 0.1):
+    # each 1D factor is tridiagonal Toeplitz with sub/super diagonals
+    # -1 + gamma h/2 and -1 - gamma h/2, eigenvalues 2 - 2 sqrt(bc) cos(k pi h)
+    N, g = 5, 0.1
+    A = wl.convdiff3d_central(N, g, 0.16).to_scipy().toarray()
+    a = 0.5 * g / (N + 1)
+    e1 = 2.0 - 2.0 * np.sqrt((1.0 - a) * (1.0 + a)) * np.cos(np.arange(1, N + 1) * np.pi / (N + 1))
+    want = np.sort((e1[:, None, None] + e1[None, :, None] + e1[None, None, :]).ravel() - 0.16)
+    np.testing.assert_allclose(np.sort(np.linalg.eigvals(A).real), want, atol=1e-10)
+    assert abs(A[7, 8] - (-1.0 - a)) < 1e-15 and abs(A[8, 7] - (-1.0 + a)) < 1e-15
     # shift convention: A(sigma) = A(0) - sigma I
     d = wl.laplacian3d(5, 0.25).to_scipy() - wl.laplacian3d(5, 0.0).to_scipy()
     np.testing.assert_allclose(d.toarray(), -0.25 * np.eye(125))
@@ -300,6 +310,28 @@ def test_arnoldi_invariants_and_low_rank(name, A, lab):
     e1 = np.sort_complex(np.round(np.linalg.eigvals(Sai @ S), 7))
     e2 = np.sort_complex(np.round(1 - np.linalg.eigvals(np.linalg.solve(Z, X)), 7))
     assert np.allclose(np.sort(e1.real), np.sort(e2.real), atol=1e-6)
+
+
+@pytest.mark.parametrize("name,A,lab", CASES[:3], ids=IDS[:3])
+def test_delta_bound_and_limits(name, A, lab):
+    """Delta(m, r_k) of Prop. l3: it bounds the relative error of S_app^{-1}; with
+    r_k = 0 it is ||E_rr||_F sqrt(q) (X = E_rr, Z = I); with a full basis of
+    the interface space (V = I, H = E_rr) it vanishes."""
+    m = 2
+    blk = opslr.make_blocks(A, lab)
+    v0 = wl.start_vector(blk.q, 9)
+    S, _, _, Err = opslr.dense_forms(blk, m)
+    pre = opslr.PSLR(A, lab, m, 5, v0=v0)
+    d, nx, nz = pre.delta()
+    Sinv = np.linalg.inv(S)
+    rel = np.linalg.norm(Sinv - pre.dense_sapp_inv()) / np.linalg.norm(Sinv)
+    assert rel <= d * (1 + 1e-9) and d > 0
+    p0 = opslr.PSLR(A, lab, m, 0)
+    d0, nx0, nz0 = p0.delta()
+    np.testing.assert_allclose(nx0, np.linalg.norm(Err), rtol=1e-12)
+    np.testing.assert_allclose(nz0, np.sqrt(blk.q), rtol=1e-12)
+    pf = opslr.PSLR(A, lab, m, 0, V=np.eye(blk.q), H=Err)
+    assert pf.delta()[1] == 0.0
 
 
 @pytest.mark.parametrize("name,A,lab", CASES[:3], ids=IDS[:3])
