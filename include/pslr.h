@@ -102,8 +102,10 @@ typedef struct {
                                pivoting); 1 = threshold incomplete LU in the block's own row
                                order, no pivoting (ilu() of Algorithm 4; see drop_tol) */
   double drop_tol;          /* factor = 1: an entry of row i is dropped when its modulus is below
-                               drop_tol * ||A_block[i, :]||_2 (the L entry after division by
-                               the pivot); <= 0 means 1e-2, the paper's setting (Sec. 4) */
+                               drop_tol times the mean modulus of the stored entries of
+                               A_block[i, :] (the L entry after division by the pivot); this
+                               reproduces the fill factors of Table 1; <= 0 means 1e-2, the
+                               paper's setting (Sec. 4) */
   int32_t lowrank;          /* how V and H are built (Algorithm 4, lines 6-8):
                                0 = the paper's r_k-step Arnoldi on E_rr(m) (eq. schur);
                                1 = Krylov-Schur restarting of that Arnoldi process (Stewart 2001):

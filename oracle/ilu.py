@@ -5,9 +5,12 @@ of 1e-2 (Algorithm 4; Sec. 4, Tables 1-3).  This is the row-oriented
 threshold ILU of Saad (ILUT, Numer. Linear Algebra Appl. 1, 1994; Iterative
 Methods for Sparse Linear Systems, 2nd ed., Sec. 10.4) with the dropping
 threshold only (no cap on the entries kept per row), in the block's own row
-order and without pivoting:
+order and without pivoting.  The row's reference size is the mean modulus of
+its stored entries (||a_i||_1 / nnz(a_i), as in Saad's SPARSKIT ILUT): with
+it the fill factor of Table 1 (2.68 at s = 5 on the 50^3 problem) is
+reproduced, while the 2-norm gives about 1.55.
 
-  for each row i:  w = a_i;  tau_i = drop * ||a_i||_2
+  for each row i:  w = a_i;  tau_i = drop * ||a_i||_1 / nnz(a_i)
     for each k < i with w_k != 0, in increasing k:
       w_k = w_k / u_kk;  if |w_k| < tau_i: drop it (no update from row k)
       else: w = w - w_k * u_k            (u_k: row k of U right of the diagonal)
@@ -19,7 +22,6 @@ loops: meant for the small blocks of the tests.
 from __future__ import annotations
 
 import heapq
-import math
 
 import numpy as np
 import scipy.sparse as sp
@@ -38,11 +40,11 @@ def ilut(M, drop: float):
         cols = M.indices[M.indptr[i]:M.indptr[i + 1]]
         vals = M.data[M.indptr[i]:M.indptr[i + 1]]
         w = {}
-        nrm2 = 0.0
+        nrm1 = 0.0
         for j, v in zip(cols.tolist(), vals.tolist()):
             w[j] = v
-            nrm2 = nrm2 + v * v
-        tau_i = drop * math.sqrt(nrm2)
+            nrm1 = nrm1 + abs(v)
+        tau_i = drop * (nrm1 / len(cols)) if len(cols) else 0.0
         heap = [j for j in w if j < i]
         heapq.heapify(heap)
         lrow = []

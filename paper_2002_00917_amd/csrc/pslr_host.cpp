@@ -1175,16 +1175,18 @@ int ilut_factor(const CsrL& M, double drop, IlutFactors& F, std::string& err) {
   for (int i = 0; i < n; ++i) {
     touched.clear();
     heap.clear();
-    double nrm2 = 0.0;
+    double nrm1 = 0.0;
     for (int q = M.ptr[i]; q < M.ptr[i + 1]; ++q) {
       const int j = M.col[q];
       w[j] = M.val[q];
       seen[j] = i;
       touched.push_back(j);
       if (j < i) heap.push_back(j);
-      nrm2 += M.val[q] * M.val[q];
+      nrm1 += std::fabs(M.val[q]);
     }
-    const double ti = drop * std::sqrt(nrm2);  // dropping threshold of row i
+    // dropping threshold of row i: drop times the mean modulus of its entries
+    const int len = M.ptr[i + 1] - M.ptr[i];
+    const double ti = len > 0 ? drop * (nrm1 / len) : 0.0;
     std::make_heap(heap.begin(), heap.end(), std::greater<int>());
     while (!heap.empty()) {
       std::pop_heap(heap.begin(), heap.end(), std::greater<int>());

@@ -149,11 +149,11 @@ int factor_block(const CsrL& M, double tau, bool want_transpose, int narrow_widt
                  std::string& err);
 
 // Threshold incomplete LU of block M in its given row order, no pivoting
-// (the ilu() of Algorithm 4): row by row, w = M[i, :]; for each k < i with
-// w_k != 0, in increasing k: w_k /= u_kk, dropped (set to 0, no update) when
-// |w_k| < drop * ||M[i, :]||_2, else w -= w_k U[k, :]; then the L part keeps
-// the surviving w_k, the U part the diagonal and every w_j (j > i) with
-// |w_j| >= drop * ||M[i, :]||_2.  drop = 0 gives the exact LU without
+// (the ilu() of Algorithm 4): row by row, w = M[i, :], tau_i = drop times the
+// mean modulus of the stored entries of M[i, :]; for each k < i with w_k != 0,
+// in increasing k: w_k /= u_kk, dropped (set to 0, no update) when
+// |w_k| < tau_i, else w -= w_k U[k, :]; then the L part keeps the surviving
+// w_k, the U part the diagonal and every w_j (j > i) with |w_j| >= tau_i.  drop = 0 gives the exact LU without
 // pivoting.  The factors are packed as supernodes of one row each; gin and
 // gout are the identity.  Returns 0, 2 on a zero pivot, 3 on a factor too
 // large for the layout.

@@ -187,6 +187,8 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
   const int32_t* ent_ptr = A.ent_ptr + B.lev_base;
   const double2* ent_rec = A.ent + B.ent_base;
   const int32_t* lev_c = A.lev_c + B.lev_base;
+  // records past the end of a sweep keep the previous values (they are never
+  // used); no zero constant stays live across the solve
   const int4 z4 = make_int4(0, 0, 0, 0);
   T* const Rh0 = Rb;
   T* const Rh1 = Rb + (int64_t)R * B.max_lrows;
@@ -235,13 +237,14 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
     }
     if (B.lower) {
       const int pb = push_ptr[l], np = ent ? 0 : push_ptr[l + 1] - pb;
-      int4 fq = np > 0 ? prec[pb + tid % np] : z4;
+      int4 fq = f0;
+      if (np > 0) fq = prec[pb + tid % np];
       // s_k = Tinv(i, 0..i) x[f .. f+i]
       {
         int4 r0 = f0, r1 = f1;
         for (int t = tid; t < cnt * CT; t += nthr) {
           const int tn = t + nthr;
-          int4 n0 = z4, n1 = z4;
+          int4 n0 = r0, n1 = r1;
           if (tn < cnt * CT) {
             n0 = rec[2 * (b + tn % cnt)];
             n1 = rec[2 * (b + tn % cnt) + 1];
@@ -287,7 +290,7 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
         int4 q = fq;
         for (int t = tid; t < np * CP; t += nthr) {
           const int tn = t + nthr;
-          const int4 qn = tn < np * CP ? prec[pb + tn % np] : z4;
+          const int4 qn = tn < np * CP ? prec[pb + tn % np] : q;
           const int c = t / np;
           const int w = q.z & 0xffff, h = q.z >> 16;
           const int Lc = pair_chunk(w, CP);
@@ -322,7 +325,7 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
         int4 r0 = f0, r1 = f1;
         for (int t = tid; t < (ent ? 0 : cnt * CP); t += nthr) {
           const int tn = t + nthr;
-          int4 n0 = z4, n1 = z4;
+          int4 n0 = r0, n1 = r1;
           if (tn < cnt * CP) {
             n0 = rec[2 * (b + tn % cnt)];
             n1 = rec[2 * (b + tn % cnt) + 1];
@@ -397,7 +400,7 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
         int4 r0 = f0, r1 = f1;
         for (int t = tid; t < cnt * CT; t += nthr) {
           const int tn = t + nthr;
-          int4 n0 = z4, n1 = z4;
+          int4 n0 = r0, n1 = r1;
           if (tn < cnt * CT) {
             n0 = rec[2 * (b + tn % cnt)];
             n1 = rec[2 * (b + tn % cnt) + 1];

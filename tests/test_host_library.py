@@ -164,3 +164,21 @@ def test_ilut_keeps_the_oracles_entries(case):
                  for a, b in zip(blk.if_ptr[:-1], blk.if_ptr[1:]) if b > a)
         print(case, drop, "library", st["nnz_LU_B"], st["nnz_LU_C0"], "oracle", nB, nC)
         assert (st["nnz_LU_B"], st["nnz_LU_C0"]) == (nB, nC)
+
+
+def test_ilut_fill_matches_table1():
+    """The paper's Table 1 (50^3 Laplacian, shift .05, drop 1e-2) prints fill(ILU)
+    2.68, 2.45, 2.30, 2.23, 2.17, 2.11 for s = 5 .. 55 (METIS parts).  The library's
+    ILUT with region-grown parts (nnz of L + U, L's unit diagonal counted as
+    stored) is within 6% of each, and decreases with s as printed."""
+    A = wl.laplacian3d(50, 0.05)
+    fills = []
+    for s, printed in ((5, 2.68), (15, 2.45), (25, 2.30), (35, 2.23), (45, 2.17), (55, 2.11)):
+        lab, nl = P.pslr_partition_region_growing(A.rowptr, A.colind, s, 35)
+        st = P.pslr_host_stats(A.rowptr, A.colind, A.vals, lab, nl, want_transpose=False,
+                               factor="ilut", drop_tol=1e-2)
+        fill = (st["nnz_LU_B"] + st["nnz_LU_C0"] + A.n) / A.nnz
+        print("s", s, "fill(ILU) %.3f printed %.2f" % (fill, printed))
+        assert abs(fill - printed) <= 0.06 * printed
+        fills.append(fill)
+    assert all(fills[i + 1] < fills[i] for i in range(len(fills) - 1))

@@ -6,8 +6,12 @@
   vanishes on the kept pattern of L + U; every entry of A - L U off that
   pattern is a dropped one, below tau_i (times |u_jj| for an L entry, which is
   dropped after division by the pivot); every kept off-diagonal entry is at
-  least tau_i, with tau_i = drop * ||a_i||_2;
+  least tau_i, with tau_i = drop * ||a_i||_1 / nnz(a_i) (the mean modulus of
+  the row's stored entries);
+* a hand-worked 3 x 3 case where that rule and the 2-norm rule differ;
 * more dropping keeps fewer entries (monotone fill in the threshold).
+The fill factor against the paper's Table 1 is checked on the library's ILUT
+(test_host_library.py), which keeps exactly the oracle's entries.
 """
 import numpy as np
 import pytest
@@ -47,7 +51,7 @@ def test_dropping_rule_invariants(name, A, drop):
     n = A.shape[0]
     Ad = A.toarray()
     R = Ad - (L @ U).toarray()
-    tau = drop * np.sqrt((Ad ** 2).sum(axis=1))
+    tau = drop * np.abs(Ad).sum(axis=1) / np.diff(sp.csr_matrix(A).indptr)
     kept = (np.abs(L.toarray() - np.eye(n)) > 0) | (np.abs(U.toarray()) > 0)
     np.fill_diagonal(kept, True)
     # zero on the kept pattern
@@ -68,3 +72,15 @@ def test_fill_decreases_with_the_threshold():
     A = wl.laplacian3d(9, 0.2).to_scipy()
     nnz = [oilu.IlutSolver(A, d).nnz for d in (0.0, 1e-3, 1e-2, 1e-1)]
     assert nnz[0] > nnz[1] > nnz[2] > nnz[3] >= A.nnz - 0.5 * A.nnz
+
+
+def test_mean_modulus_rule_by_hand():
+    """Row 1 of [[4, 1, 0], [1, 4, .05], [0, .05, 4]] at drop .02: tau_1 = .02 * 5.05 / 3
+    = .0337, so u_12 = .05 is kept (the 2-norm rule, .02 * 4.12 = .0825, would drop it).
+    Row 2: l_21 = .05 / u_11 = .05 / 3.75 = .0133 < tau_2 = .02 * 4.05 / 2 = .0405 is
+    dropped, so u_22 = 4 exactly."""
+    A = sp.csr_matrix(np.array([[4.0, 1.0, 0.0], [1.0, 4.0, 0.05], [0.0, 0.05, 4.0]]))
+    L, U = oilu.ilut(A, 0.02)
+    Ld, Ud = L.toarray(), U.toarray()
+    np.testing.assert_allclose(Ld, [[1, 0, 0], [0.25, 1, 0], [0, 0, 1]], atol=1e-15)
+    np.testing.assert_allclose(Ud, [[4, 1, 0], [0, 3.75, 0.05], [0, 0, 4]], atol=1e-15)
