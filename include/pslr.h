@@ -188,6 +188,19 @@ pslr_status pslr_setup_batched(int64_t n, const int64_t* rowptr, const int32_t* 
                                int32_t nsys, const int64_t* sys_ptr, const pslr_options* opt,
                                void* hip_stream, pslr_handle* out);
 
+/* New values for the same sparsity pattern (vals: host, nnz entries in the
+ * original CSR order of the pslr_setup call): the local factors of every B_i
+ * and C_i are recomputed on the host with the setup's options (the orderings
+ * and supernodes depend on the pattern only), the value-dependent device
+ * arrays are replaced, and the low-rank correction is rebuilt on the device
+ * with the setup's construction (lowrank 1 and 2 start Krylov-Schur from the
+ * previous basis).  The reordering, partition and all structural tables are
+ * kept.  For repeated solves with changing values (optimisation loops).  The
+ * previous factors and workspaces are freed after the device is idle, so an
+ * apply captured in a HIP graph before this call must be captured again.
+ * Synchronises the device.  Returns PSLR_EBREAKDOWN like pslr_setup. */
+pslr_status pslr_refactor(pslr_handle h, const double* vals, void* hip_stream);
+
 /* z = M^{-1} b, the preconditioner of Algorithm 3 (eq. application):
  *   y = g - F B^{-1} f;  y <- y + V G V^T y;  y <- P_m y;  x = B^{-1}(f - E y).
  * b, z: device, n x nrhs column-major, leading dimensions ldb, ldz >= n. */

@@ -203,7 +203,14 @@ struct pslr_ctx {
   Reordering R;
   int32_t m = 3, rank = 0, precision = 0, want_T = 0;
   int64_t nnzA = 0;
-  std::vector<int64_t> hA_ptr;
+  std::vector<int64_t> hA_ptr;   // host pattern of A (original order), kept for pslr_refactor
+  std::vector<int32_t> hA_col;
+  pslr_options opt{};            // the setup's options (v0 copied to hv0)
+  std::vector<double> hv0;
+  DevPool facpool;               // data that depends on A's values: factors, couplings, A's values
+  const int64_t* d_int_ptr = nullptr;
+  const int64_t* d_if_ptr = nullptr;
+  const int32_t* d_if_orig = nullptr;
   DevPool pool;      // factor and matrix data
   DevPool ws;        // workspaces (grown on demand)
   DevPool vpool;     // low-rank data
@@ -1922,7 +1929,7 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
     std::vector<double> val(vals, vals + h->nnzA);
     HIP_TRY(h->pool.upload(ptr, &h->A_ptr));
     HIP_TRY(h->pool.upload(col, &h->A_col));
-    HIP_TRY(h->pool.upload(val, &h->A_val));
+    HIP_TRY(h->facpool.upload(val, &h->A_val));
     if (h->want_T) {
       std::vector<int64_t> tp(n + 1, 0);
       for (int32_t c : col) tp[c + 1]++;
@@ -1938,7 +1945,7 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
         }
       HIP_TRY(h->pool.upload(tp, &h->AT_ptr));
       HIP_TRY(h->pool.upload(tc, &h->AT_col));
-      HIP_TRY(h->pool.upload(tv, &h->AT_val));
+      HIP_TRY(h->facpool.upload(tv, &h->AT_val));
     }
   }
   const int64_t *d_int_ptr, *d_if_ptr;
@@ -1950,6 +1957,14 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
     HIP_TRY(h->pool.upload(h->R.if_ptr, &d_if_ptr));
     HIP_TRY(h->pool.upload(if_orig, &d_if_orig));
   }
+  h->d_int_ptr = d_int_ptr;
+  h->d_if_ptr = d_if_ptr;
+  h->d_if_orig = d_if_orig;
+  h->hA_ptr.assign(rowptr, rowptr + n + 1);
+  h->hA_col.assign(colind, colind + h->nnzA);
+  h->opt = o;
+  if (o.v0) h->hv0.assign(o.v0, o.v0 + h->R.q);
+  h->opt.v0 = nullptr;
   // per-system tables: subdomain -> system, V^T y row chunks, interface segments
   {
     std::vector<int32_t> ps(nparts);
@@ -1983,7 +1998,7 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
   h->lds_max = prop.sharedMemPerBlock > 0 ? prop.sharedMemPerBlock : 65536;
   DirHost Dfw = build_dir(h->R, Bk, fB, fC, false);
   int64_t bytes[4] = {0, 0, 0, 0};
-  HIP_TRY(upload_dir<double>(h->pool, h->R, fB, fC, Dfw, false, d_int_ptr, d_if_ptr, d_if_orig,
+  HIP_TRY(upload_dir<double>(h->facpool, h->R, fB, fC, Dfw, false, d_int_ptr, d_if_ptr, d_if_orig,
                              h->fw64, bytes));
   // global workspace layout, used by applies whose subdomains do not fit in
   // LDS or that solve wide right-hand-side tiles
@@ -1995,7 +2010,7 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
         for (const TriPacked* T : {&f->lo, &f->up, &f->loT, &f->upT}) mx = std::max(mx, T->max_lrows);
       rb[i + 1] = rb[i] + 2 * mx;  // two halves for alternate levels
     }
-    HIP_TRY(h->pool.upload(rb, &h->d_rb_off));
+    HIP_TRY(h->facpool.upload(rb, &h->d_rb_off));
     h->gws_stride = h->R.p + 2 * h->R.q + rb[nparts] + (int64_t)nparts * 2 * std::max(h->rank, 1);
   }
   h->gx = o.working_vectors == 1;
@@ -2033,7 +2048,7 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
   const double t3 = now_s();
 
   if (h->precision >= 1) {
-    HIP_TRY(upload_dir<float>(h->pool, h->R, fB, fC, Dfw, false, d_int_ptr, d_if_ptr, d_if_orig,
+    HIP_TRY(upload_dir<float>(h->facpool, h->R, fB, fC, Dfw, false, d_int_ptr, d_if_ptr, d_if_orig,
                               h->fw32, bytes));
     set_gx(h->fw32);
     h->have32 = true;
@@ -2042,11 +2057,11 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
     DirHost Dtr = build_dir(h->R, Bk, fB, fC, true);
     int64_t tb[4];
     if (h->precision >= 1) {
-      HIP_TRY(upload_dir<float>(h->pool, h->R, fB, fC, Dtr, true, d_int_ptr, d_if_ptr, d_if_orig,
+      HIP_TRY(upload_dir<float>(h->facpool, h->R, fB, fC, Dtr, true, d_int_ptr, d_if_ptr, d_if_orig,
                                 h->tr32, tb));
       set_gx(h->tr32);
     }
-    HIP_TRY(upload_dir<double>(h->pool, h->R, fB, fC, Dtr, true, d_int_ptr, d_if_ptr, d_if_orig,
+    HIP_TRY(upload_dir<double>(h->facpool, h->R, fB, fC, Dtr, true, d_int_ptr, d_if_ptr, d_if_orig,
                                h->tr64, tb));
     set_gx(h->tr64);
     h->haveT = true;
@@ -2068,6 +2083,140 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
 }  // namespace
 
 extern "C" {
+
+pslr_status pslr_refactor(pslr_handle h, const double* vals, void* hip_stream) {
+  if (!h || (h->nnzA > 0 && !vals)) return fail(PSLR_EINVAL, "bad arguments");
+  for (int64_t k = 0; k < h->nnzA; ++k)
+    if (!std::isfinite(vals[k])) return fail(PSLR_EINVAL, "non-finite value in A");
+  hipStream_t s = (hipStream_t)hip_stream;
+  const pslr_options& o = h->opt;
+  const int64_t n = h->R.n;
+  const int np = h->R.nparts;
+  const double t1 = now_s();
+  // local factors of the new values (the same orderings and supernodes: they
+  // depend on the pattern only; threshold ILU keeps what the new values keep)
+  Blocks Bk = extract_blocks(n, h->hA_ptr.data(), h->hA_col.data(), vals, h->R);
+  std::vector<BlockFactor> fB(np), fC(np);
+  std::vector<std::string> errs(2 * np);
+  std::vector<int> codes(2 * np, 0);
+  const double tau = o.pivot_threshold > 0 ? o.pivot_threshold : 0.1;
+  const double drop = o.drop_tol > 0 ? o.drop_tol : 1e-2;
+  parallel_for(2 * np, o.nthreads, [&](int t) {
+    const CsrL& M = t < np ? Bk.B[t] : Bk.C0[t - np];
+    BlockFactor& F = t < np ? fB[t] : fC[t - np];
+    const int narrow = t < np ? kNarrowWidthB : kNarrowWidthC;
+    codes[t] = o.factor == 1 ? ilut_block(M, drop, h->want_T != 0, narrow, F, errs[t])
+                             : factor_block(M, tau, h->want_T != 0, narrow, F, errs[t]);
+  });
+  for (int t = 0; t < 2 * np; ++t)
+    if (codes[t]) return fail(codes[t] == 3 ? PSLR_ENOTSUP : PSLR_ESINGULAR,
+                              std::string(t < np ? "B_" : "C_") + std::to_string(t % np) + ": " + errs[t]);
+  const double t2 = now_s();
+  // new device copies of everything that depends on the values
+  DevPool nf;
+  const double* A_val = nullptr;
+  const double* AT_val = nullptr;
+  {
+    std::vector<double> val(vals, vals + h->nnzA);
+    HIP_TRY(nf.upload(val, &A_val));
+    if (h->want_T) {
+      std::vector<int64_t> pos(n + 1, 0);
+      for (int64_t k = 0; k < h->nnzA; ++k) pos[h->hA_col[k] + 1]++;
+      for (int64_t i = 0; i < n; ++i) pos[i + 1] += pos[i];
+      std::vector<double> tv(h->nnzA);
+      for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = h->hA_ptr[i]; k < h->hA_ptr[i + 1]; ++k) tv[pos[h->hA_col[k]]++] = vals[k];
+      HIP_TRY(nf.upload(tv, &AT_val));
+    }
+  }
+  ApplyArrays<double> fw64{}, tr64{};
+  ApplyArrays<float> fw32{}, tr32{};
+  int64_t bytes[4] = {0, 0, 0, 0}, tb[4];
+  DirHost Dfw = build_dir(h->R, Bk, fB, fC, false);
+  HIP_TRY(upload_dir<double>(nf, h->R, fB, fC, Dfw, false, h->d_int_ptr, h->d_if_ptr, h->d_if_orig,
+                             fw64, bytes));
+  const int64_t* d_rb_off = nullptr;
+  int64_t gws_stride = 0;
+  {
+    std::vector<int64_t> rb(np + 1, 0);
+    for (int i = 0; i < np; ++i) {
+      int mx = 1;
+      for (const BlockFactor* f : {&fB[i], &fC[i]})
+        for (const TriPacked* T : {&f->lo, &f->up, &f->loT, &f->upT}) mx = std::max(mx, T->max_lrows);
+      rb[i + 1] = rb[i] + 2 * mx;
+    }
+    HIP_TRY(nf.upload(rb, &d_rb_off));
+    gws_stride = h->R.p + 2 * h->R.q + rb[np] + (int64_t)np * 2 * std::max(h->fw64.kmax, 1);
+  }
+  if (h->have32) HIP_TRY(upload_dir<float>(nf, h->R, fB, fC, Dfw, false, h->d_int_ptr, h->d_if_ptr,
+                                           h->d_if_orig, fw32, bytes));
+  if (h->haveT) {
+    DirHost Dtr = build_dir(h->R, Bk, fB, fC, true);
+    if (h->have32) HIP_TRY(upload_dir<float>(nf, h->R, fB, fC, Dtr, true, h->d_int_ptr, h->d_if_ptr,
+                                             h->d_if_orig, tr32, tb));
+    HIP_TRY(upload_dir<double>(nf, h->R, fB, fC, Dtr, true, h->d_int_ptr, h->d_if_ptr, h->d_if_orig,
+                               tr64, tb));
+  }
+  // the launch settings of the old arrays carry over (autotuned chunk scale)
+  auto carry = [&](auto& Anew, const auto& Aold) {
+    Anew.part_sys = h->d_part_sys;
+    Anew.gshift = Aold.gshift;
+    Anew.gws = nullptr;
+    Anew.gws_stride = gws_stride;
+    Anew.rb_off = d_rb_off;
+    Anew.kmax = Aold.kmax;
+    Anew.nsys = h->nsys;
+    Anew.active = nullptr;
+  };
+  carry(fw64, h->fw64);
+  carry(fw32, h->fw64);
+  carry(tr64, h->fw64);
+  carry(tr32, h->fw64);
+  // nothing queued may still read the old arrays: wait, then swap and free
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipDeviceSynchronize());
+  h->fw64 = fw64;
+  if (h->have32) h->fw32 = fw32;
+  if (h->haveT) {
+    h->tr64 = tr64;
+    if (h->have32) h->tr32 = tr32;
+  }
+  h->A_val = A_val;
+  if (h->want_T) h->AT_val = AT_val;
+  h->d_rb_off = d_rb_off;
+  h->gws_stride = gws_stride;
+  std::swap(h->facpool.ptrs, nf.ptrs);
+  std::swap(h->facpool.bytes, nf.bytes);
+  nf.release();
+  h->ws.release();
+  h->ws_nrhs = 0;
+  h->ws_cap = WsSizes{};
+  // the low-rank correction of the new operator, with the setup's construction;
+  // Krylov-Schur starts from the sum of the previous basis vectors (warm start)
+  std::vector<double> v0 = h->hv0;
+  if (o.lowrank != 0 && h->k > 0) {
+    v0.assign(h->R.q, 0.0);
+    for (int j = 0; j < h->k; ++j)
+      for (int64_t r = 0; r < h->R.q; ++r) v0[r] += h->hV[(size_t)j * h->R.q + r];
+  }
+  pslr_status st = ensure_ws(h, 1);
+  if (st) return st;
+  bool breakdown = false;
+  const double* v0p = v0.empty() ? nullptr : v0.data();
+  st = o.lowrank == 0 ? arnoldi(h, v0p, o.seed, s, breakdown)
+                      : krylov_schur(h, v0p, o.seed, o.lowrank, s, breakdown);
+  if (st) return st;
+  h->ws.release();
+  h->ws_nrhs = 0;
+  h->ws_cap = WsSizes{};
+  if ((st = probe_bf16(h, s))) return st;
+  const double t3 = now_s();
+  fill_info(h, fB, fC, Bk, bytes);
+  h->info.seconds_factor = t2 - t1;
+  h->info.seconds_arnoldi = t3 - t2;
+  HIP_TRY(hipStreamSynchronize(s));
+  return breakdown ? PSLR_EBREAKDOWN : PSLR_OK;
+}
 
 pslr_status pslr_setup(int64_t n, const int64_t* rowptr, const int32_t* colind, const double* vals,
                        const int32_t* part, int32_t nparts, const pslr_options* opt,

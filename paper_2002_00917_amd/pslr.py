@@ -78,6 +78,7 @@ _SIGS = {
                              C.POINTER(pslr_options), _P, C.POINTER(_P)]),
     "pslr_setup_batched": (C.c_int, [C.c_int64, _I64P, _I32P, _F64P, _I32P, C.c_int32, C.c_int32,
                                      _I64P, C.POINTER(pslr_options), _P, C.POINTER(_P)]),
+    "pslr_refactor": (C.c_int, [_P, _F64P, _P]),
     "pslr_apply": (C.c_int, [_P, C.c_int32, _P, C.c_int64, _P, C.c_int64, _P]),
     "pslr_apply_noalloc": (C.c_int, [_P, C.c_int32, _P, C.c_int64, _P, C.c_int64, _P]),
     "pslr_apply_transpose": (C.c_int, [_P, C.c_int32, _P, C.c_int64, _P, C.c_int64, _P]),
@@ -256,6 +257,17 @@ def pslr_setup_batched(rowptr, colind, vals, part, nparts, sys_ptr, m=3, rank=16
     _check(st, (PSLR_OK, PSLR_EBREAKDOWN))
     del keep
     return Handle(out, n, st, nsys=len(sp) - 1, vals=va)
+
+
+def pslr_refactor(h: Handle, vals, stream=None):
+    """New values on the handle's sparsity pattern (original CSR order)."""
+    va, vap = _arr(vals, np.float64)
+    if va.size != h.nnz:
+        raise ValueError("vals must have nnz(A) = %d entries" % h.nnz)
+    st = lib().pslr_refactor(h.ptr, vap, _stream_ptr(stream))
+    _check(st, (PSLR_OK, PSLR_EBREAKDOWN))
+    h.vals_fingerprint = (int(va.size), float(np.sum(va)), float(np.sum(va * va)))
+    return st
 
 
 def pslr_apply(h: Handle, b, z, stream=None):
