@@ -119,6 +119,11 @@ typedef struct {
                                    to 256), so that all eigenvalues of E_rr(m) outside the unit
                                    circle are deflated (Sec. 3.2.2); pslr_info.rank gives the
                                    count reached, which may exceed r_k */
+  int32_t team;             /* B_i solves of single-right-hand-side applies spread over `team`
+                               workgroups per subdomain (the supernodal tree cut into `team`
+                               groups of whole subtrees and the top group above them; exact LU
+                               only): 0 = automatic (4 when nparts <= 128, else 1), 1 = off,
+                               2..8 = that many */
 } pslr_options;
 
 typedef struct {
@@ -338,6 +343,11 @@ typedef struct {
   int32_t max_levels_B, max_levels_C0;
   int32_t levels_valid;
   double factor_residual, solve_residual;
+  int32_t team;             /* the team size of the B_i solves (0: no team split) */
+  int32_t team_valid;       /* 1 when every B_i's team split passes its structural check */
+  double team_residual;     /* largest relative difference between the team-split solve of
+                               every B_i (groups applied in turn on the host) and its plain
+                               packed solve */
 } pslr_host_stats_t;
 pslr_status pslr_host_stats(int64_t n, const int64_t* rowptr, const int32_t* colind,
                             const double* vals, const int32_t* part, int32_t nparts,

@@ -79,8 +79,8 @@ struct DevPool {
 // working vectors): each value it reads once (triangles, panels or entries),
 // the indices and records it reads once, the level tables.
 template <typename T>
-hipError_t upload_tri(DevPool& pool, const std::vector<BlockFactor>& F, TriPacked BlockFactor::*mem,
-                      TriArrays<T>& out, int& max_lrows, int64_t& bytes) {
+hipError_t upload_tri_list(DevPool& pool, const std::vector<const TriPacked*>& F, TriArrays<T>& out,
+                           int& max_lrows, int64_t& bytes) {
   std::vector<DevTriBlock> blk(F.size());
   std::vector<int32_t> lev_ptr, push_ptr, ent_ptr, lev_c, rec, prec, ridx, ent;
   std::vector<T> val, tri;
@@ -89,7 +89,7 @@ hipError_t upload_tri(DevPool& pool, const std::vector<BlockFactor>& F, TriPacke
   int64_t nent = 0;
   bytes = 0;
   for (size_t i = 0; i < F.size(); ++i) {
-    const TriPacked& H = F[i].*mem;
+    const TriPacked& H = *F[i];
     DevTriBlock& B = blk[i];
     B.n = H.n;
     B.nlev = H.nlev;
@@ -144,6 +144,14 @@ hipError_t upload_tri(DevPool& pool, const std::vector<BlockFactor>& F, TriPacke
   return hipSuccess;
 }
 
+template <typename T>
+hipError_t upload_tri(DevPool& pool, const std::vector<BlockFactor>& F, TriPacked BlockFactor::*mem,
+                      TriArrays<T>& out, int& max_lrows, int64_t& bytes) {
+  std::vector<const TriPacked*> list(F.size());
+  for (size_t i = 0; i < F.size(); ++i) list[i] = &(F[i].*mem);
+  return upload_tri_list(pool, list, out, max_lrows, bytes);
+}
+
 // Host CSR of the coupling blocks in the layouts the kernels read.
 struct CouplingHost {
   std::vector<int64_t> ptr;
@@ -187,7 +195,7 @@ pslr_status scratch_attach(int device) {
 // Element counts (in doubles) of an apply workspace: y, u0, u1 (q x nrhs
 // each), the V^T y partial sums and the global working vectors.
 struct WsSizes {
-  size_t vec = 0, partial = 0, gws = 0, zp = 0;
+  size_t vec = 0, partial = 0, gws = 0, zp = 0, team = 0;
 };
 
 // Everything one direction of the apply needs, host side.
@@ -266,6 +274,7 @@ struct pslr_ctx {
   void* partial = nullptr;
   void* gws = nullptr;
   void* zp = nullptr;
+  void* tws = nullptr;  // team solves: interior vector, then the top-row updates
   // FGMRES workspace (kept between calls)
   DevPool fpool;
   int f_nrhs = 0, f_restart = 0;
@@ -293,6 +302,14 @@ struct pslr_ctx {
 };
 
 namespace {
+
+// Team size of the B_i solves: exact LU only; automatic = 4 workgroups per
+// subdomain when the subdomains alone would leave most of the 256 CUs idle.
+int resolve_team(const pslr_options& o, int32_t nparts) {
+  if (o.factor != 0 || o.team == 1) return 0;
+  if (o.team >= 2) return std::min(o.team, 8);
+  return nparts <= 128 ? 4 : 0;
+}
 
 pslr_status validate_csr(int64_t n, const int64_t* rowptr, const int32_t* colind) {
   if (n < 0 || (n > 0 && (!rowptr || !colind))) return fail(PSLR_EINVAL, "null CSR arrays");
@@ -436,6 +453,25 @@ hipError_t upload_dir(DevPool& pool, const Reordering& R, const std::vector<Bloc
   bytes_out[1] = by;
   if ((e = upload_tri(pool, fC, up, A.UC, mlr, by))) return e;
   bytes_out[1] += by;
+  A.team = 0;
+  A.ntopmax = 0;
+  if (!transpose && !fB.empty() && fB[0].team > 1) {
+    const int team = fB[0].team;
+    std::vector<const TriPacked*> ls, us;
+    for (const BlockFactor& f : fB) {
+      if (f.team != team || (int)f.loS.size() != team + 1 || (int)f.upS.size() != team + 1)
+        return hipErrorInvalidValue;
+      for (int g = 0; g <= team; ++g) {
+        ls.push_back(&f.loS[g]);
+        us.push_back(&f.upS[g]);
+      }
+      A.ntopmax = std::max(A.ntopmax, f.loS[team].n);
+    }
+    int64_t tb;
+    if ((e = upload_tri_list(pool, ls, A.LBs, mlr, tb))) return e;
+    if ((e = upload_tri_list(pool, us, A.UBs, mlr, tb))) return e;
+    A.team = team;
+  }
   A.maxLR = std::max(mlr, 1);
   A.maxPB = A.maxQB = 1;
   for (int i = 0; i < R.nparts; ++i) {
@@ -466,6 +502,9 @@ WsSizes ws_sizes(const pslr_ctx* h, int nrhs) {
   z.vec = (size_t)std::max<int64_t>(h->R.q, 1) * nrhs;
   z.partial = (size_t)h->nchunk_lr * nrhs * std::max(h->k, 1);
   z.gws = h->gws_stride > 0 ? (size_t)h->gws_stride * ((nrhs + 7) / 8 * 8) : 0;
+  // interior vector and top-row updates of the team solves (one right-hand side)
+  if (h->fw64.team > 1)
+    z.team = (size_t)std::max<int64_t>(h->R.p, 1) + (size_t)h->R.nparts * h->fw64.team * h->fw64.ntopmax;
   // split G V^T y of the matrix-core low-rank products (BF16 V only)
   if (h->Vbr && nrhs >= kMfmaMinRhs)
     z.zp = ((size_t)h->nsys * 3 * nrhs * ((h->k + 15) / 16 * 16) * 2 + 7) / 8;
@@ -479,7 +518,7 @@ WsSizes ws_sizes(const pslr_ctx* h, int nrhs) {
 pslr_status ensure_ws(pslr_ctx* h, int nrhs) {
   const WsSizes need = ws_sizes(h, nrhs);
   if (nrhs <= h->ws_nrhs && need.partial <= h->ws_cap.partial && need.gws <= h->ws_cap.gws &&
-      need.zp <= h->ws_cap.zp)
+      need.zp <= h->ws_cap.zp && need.team <= h->ws_cap.team)
     return PSLR_OK;
   int grow = 1;
   while (grow < std::max(nrhs, h->ws_nrhs)) grow *= 2;
@@ -492,6 +531,8 @@ pslr_status ensure_ws(pslr_ctx* h, int nrhs) {
   if (z.gws > 0) HIP_TRY(h->ws.alloc<double>(z.gws, (double**)&h->gws));
   h->zp = nullptr;
   if (z.zp > 0) HIP_TRY(h->ws.alloc<double>(z.zp, (double**)&h->zp));
+  h->tws = nullptr;
+  if (z.team > 0) HIP_TRY(h->ws.alloc<double>(z.team, (double**)&h->tws));
   h->ws_nrhs = grow;
   h->ws_cap = z;
   return PSLR_OK;
@@ -676,7 +717,7 @@ LaunchCfg choose_launch(pslr_ctx* h, const ApplyArrays<T>& A, int nrhs, hipStrea
 
 // Device workspace of one apply (see WsSizes).
 struct ApplyWs {
-  void *y, *u0, *u1, *partial, *gws, *zp;
+  void *y, *u0, *u1, *partial, *gws, *zp, *team;
 };
 
 // z = M^{-1} b (or M^{-T} b) with apply arrays A and workspace W (large
@@ -703,8 +744,13 @@ pslr_status run_apply(pslr_ctx* h, const ApplyArrays<T>& Ah, const ApplyWs& W, b
     ~Restore() { h->trace = v; }
   } restore{h, tr_on};
   Tracer tr{h, s, {}};
+  // one right-hand side in LDS: every B_i solve spread over a team of workgroups
+  const bool team = A.team > 1 && W.team && nrhs == 1 && cfg.R == 1 && !cfg.gx && !transpose;
+  T* xb = (T*)W.team;
+  T* dtop = team ? xb + std::max<int64_t>(h->R.p, 1) : nullptr;
   HIP_TRY(tr.mark(PH_START));
-  HIP_TRY(launch_head<T>(A, cfg, nrhs, b, ldb, y, q));
+  if (team) HIP_TRY(launch_head_team<T>(A, cfg, b, y, xb, dtop));
+  else HIP_TRY(launch_head<T>(A, cfg, nrhs, b, ldb, y, q));
   HIP_TRY(tr.mark(PH_HEAD));
   // FP32 applies with V in BF16 and many right-hand sides: the low-rank
   // products on the matrix cores, then the C0 solve on its own
@@ -726,7 +772,8 @@ pslr_status run_apply(pslr_ctx* h, const ApplyArrays<T>& Ah, const ApplyWs& W, b
     for (int i = 0; i < h->m; ++i) {
       LaunchCfg c1 = cfg;
       HIP_TRY(tr.span(PH_SERIES, c1));
-      HIP_TRY(launch_series<T>(A, c1, nrhs, y, q, ua, ub, q, 1, 1));
+      if (team) HIP_TRY(launch_series_team<T>(A, c1, y, ua, ub, 1, xb, dtop));
+      else HIP_TRY(launch_series<T>(A, c1, nrhs, y, q, ua, ub, q, 1, 1));
       std::swap(ua, ub);
     }
   } else {
@@ -749,7 +796,8 @@ pslr_status run_apply(pslr_ctx* h, const ApplyArrays<T>& Ah, const ApplyWs& W, b
       HIP_TRY(tr.mark(PH_LOWRANK));
     }
   }
-  HIP_TRY(launch_tail<T>(A, cfg, nrhs, b, ldb, ua, q, z, ldz));
+  if (team) HIP_TRY(launch_tail_team<T>(A, cfg, b, ua, z, xb, dtop));
+  else HIP_TRY(launch_tail<T>(A, cfg, nrhs, b, ldb, ua, q, z, ldz));
   HIP_TRY(tr.mark(PH_TAIL));
   HIP_TRY(tr.finish());
   return PSLR_OK;
@@ -760,7 +808,7 @@ pslr_status apply_dir(pslr_ctx* h, bool transpose, int nrhs, const double* b, in
   if (h->R.n == 0) return PSLR_OK;
   pslr_status st = ensure_ws(h, nrhs);
   if (st != PSLR_OK) return st;
-  const ApplyWs W{h->y, h->u0, h->u1, h->partial, h->gws, h->zp};
+  const ApplyWs W{h->y, h->u0, h->u1, h->partial, h->gws, h->zp, h->tws};
   if (h->precision >= 1 && !force64 && h->have32)
     return run_apply<float>(h, transpose ? h->tr32 : h->fw32, W, transpose, nrhs, b, ldb, z, ldz, s);
   if (!h->have64) return fail(PSLR_EINVAL, "FP64 apply arrays not available");
@@ -1648,6 +1696,8 @@ pslr_status pslr_host_stats(int64_t n, const int64_t* rowptr, const int32_t* col
   if (opt) o = *opt;
   if (o.factor != 0 && o.factor != 1) return fail(PSLR_EINVAL, "factor must be 0 or 1");
   if (o.lowrank < 0 || o.lowrank > 2) return fail(PSLR_EINVAL, "lowrank must be 0, 1 or 2");
+  if (o.team < 0 || o.team > 8) return fail(PSLR_EINVAL, "team must be 0 .. 8");
+  const int team = resolve_team(o, nparts);
   const double tau = o.pivot_threshold > 0 ? o.pivot_threshold : 0.1;
   const double drop = o.drop_tol > 0 ? o.drop_tol : 1e-2;
   Reordering R = reorder(n, rowptr, colind, part, nparts);
@@ -1658,7 +1708,9 @@ pslr_status pslr_host_stats(int64_t n, const int64_t* rowptr, const int32_t* col
   const int nB = (int)Bk.B.size();
   std::vector<double> fres(mats.size(), 0.0), sres(mats.size(), 0.0);
   std::vector<std::string> errs(mats.size());
-  std::vector<int> codes(mats.size(), 0), lvl(mats.size(), 0), valid(mats.size(), 1);
+  std::vector<int> codes(mats.size(), 0), lvl(mats.size(), 0), valid(mats.size(), 1),
+      tvalid(mats.size(), 1);
+  std::vector<double> tres(mats.size(), 0.0);
   std::vector<int64_t> nnz(mats.size(), 0);
   parallel_for((int)mats.size(), o.nthreads, [&](int t) {
     const CsrL& M = *mats[t];
@@ -1669,9 +1721,30 @@ pslr_status pslr_host_stats(int64_t n, const int64_t* rowptr, const int32_t* col
       codes[t] = ilut_block(M, drop, o.want_transpose != 0, narrow, f, errs[t]);
       if (!codes[t]) codes[t] = ilut_factor(M, drop, I, errs[t]);
     } else {
-      codes[t] = factor_block(M, tau, o.want_transpose != 0, narrow, f, errs[t]);
+      codes[t] = factor_block(M, tau, o.want_transpose != 0, narrow, f, errs[t], t < nB ? team : 0);
     }
     if (codes[t] || M.nrows == 0) return;
+    if (f.team > 1) {
+      // team split: structure, and the groups applied in turn (subtrees, then
+      // the top group's lower and upper solves, then the subtrees' upper
+      // solves) against the plain packed solve
+      std::string terr;
+      if (!check_team(f, terr)) tvalid[t] = 0;
+      const int nb = M.nrows;
+      std::vector<double> X0(nb), X1(nb);
+      for (int i = 0; i < nb; ++i) X0[i] = X1[i] = std::cos(0.3 + 0.71 * i);
+      host_tri_solve(f.lo, X0, true);
+      host_tri_solve(f.up, X0, true);
+      for (int g = 0; g <= f.team; ++g) host_tri_solve(f.loS[g], X1, true);
+      host_tri_solve(f.upS[f.team], X1, true);
+      for (int g = 0; g < f.team; ++g) host_tri_solve(f.upS[g], X1, true);
+      double d2 = 0.0, n2 = 0.0;
+      for (int i = 0; i < nb; ++i) {
+        d2 += (X0[i] - X1[i]) * (X0[i] - X1[i]);
+        n2 += X0[i] * X0[i];
+      }
+      tres[t] = n2 > 0 ? std::sqrt(d2 / n2) : 0.0;
+    }
     nnz[t] = f.nnz_L + f.nnz_U;
     lvl[t] = f.lo.nlev;
     std::string lerr;
@@ -1784,6 +1857,12 @@ pslr_status pslr_host_stats(int64_t n, const int64_t* rowptr, const int32_t* col
     if (codes[t]) return fail(codes[t] == 3 ? PSLR_ENOTSUP : PSLR_ESINGULAR, errs[t]);
   *out = pslr_host_stats_t{};
   out->levels_valid = 1;
+  out->team = team;
+  out->team_valid = 1;
+  for (size_t t = 0; t < mats.size(); ++t) {
+    if (!tvalid[t]) out->team_valid = 0;
+    out->team_residual = std::max(out->team_residual, tres[t]);
+  }
   for (size_t t = 0; t < mats.size(); ++t) {
     const bool b = (int)t < nB;
     (b ? out->nnz_LU_B : out->nnz_LU_C0) += nnz[t];
@@ -1855,6 +1934,9 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
   if (o.threads != 0 && o.threads != 512 && o.threads != 1024)
     return fail(PSLR_EINVAL, "threads must be 0, 512 or 1024");
   if (o.factor != 0 && o.factor != 1) return fail(PSLR_EINVAL, "factor must be 0 or 1");
+  if (o.lowrank < 0 || o.lowrank > 2) return fail(PSLR_EINVAL, "lowrank must be 0, 1 or 2");
+  if (o.team < 0 || o.team > 8) return fail(PSLR_EINVAL, "team must be 0 .. 8");
+  o.team = resolve_team(o, nparts);
   const double tau = o.pivot_threshold > 0 ? o.pivot_threshold : 0.1;
   for (int64_t k = 0; k < (n > 0 ? rowptr[n] : 0); ++k)
     if (!std::isfinite(vals[k])) return fail(PSLR_EINVAL, "non-finite value in A");
@@ -1915,7 +1997,8 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
     BlockFactor& F = t < np ? fB[t] : fC[t - np];
     const int narrow = t < np ? kNarrowWidthB : kNarrowWidthC;
     codes[t] = o.factor == 1 ? ilut_block(M, drop, h->want_T != 0, narrow, F, errs[t])
-                             : factor_block(M, tau, h->want_T != 0, narrow, F, errs[t]);
+                             : factor_block(M, tau, h->want_T != 0, narrow, F, errs[t],
+                                            t < np ? o.team : 0);
   });
   for (int t = 0; t < 2 * np; ++t)
     if (codes[t]) return fail(codes[t] == 3 ? PSLR_ENOTSUP : PSLR_ESINGULAR,
@@ -2106,7 +2189,8 @@ pslr_status pslr_refactor(pslr_handle h, const double* vals, void* hip_stream) {
     BlockFactor& F = t < np ? fB[t] : fC[t - np];
     const int narrow = t < np ? kNarrowWidthB : kNarrowWidthC;
     codes[t] = o.factor == 1 ? ilut_block(M, drop, h->want_T != 0, narrow, F, errs[t])
-                             : factor_block(M, tau, h->want_T != 0, narrow, F, errs[t]);
+                             : factor_block(M, tau, h->want_T != 0, narrow, F, errs[t],
+                                            t < np ? o.team : 0);
   });
   for (int t = 0; t < 2 * np; ++t)
     if (codes[t]) return fail(codes[t] == 3 ? PSLR_ENOTSUP : PSLR_ESINGULAR,
@@ -2254,7 +2338,7 @@ pslr_status pslr_apply_noalloc(pslr_handle h, int32_t nrhs, const double* b, int
   // out of the array, each 256-byte aligned
   const WsSizes z0 = ws_sizes(h, nrhs);
   auto up = [](size_t d) { return (d * sizeof(double) + 255) / 256 * 256; };
-  const size_t need = 3 * up(z0.vec) + up(z0.partial) + up(z0.gws) + up(z0.zp);
+  const size_t need = 3 * up(z0.vec) + up(z0.partial) + up(z0.gws) + up(z0.zp) + up(z0.team);
   if (need > kScratchBytes)
     return fail(PSLR_EINVAL, "pslr_apply_noalloc needs " + std::to_string(need) +
                                  " bytes of scratch for " + std::to_string(nrhs) +
@@ -2272,6 +2356,8 @@ pslr_status pslr_apply_noalloc(pslr_handle h, int32_t nrhs, const double* b, int
   W.gws = z0.gws > 0 ? (void*)c : nullptr;
   c += up(z0.gws);
   W.zp = z0.zp > 0 ? (void*)c : nullptr;
+  c += up(z0.zp);
+  W.team = z0.team > 0 ? (void*)c : nullptr;
   hipStream_t s = (hipStream_t)hip_stream;
   // no phase tracing here: the tracer creates events on demand
   if (h->precision >= 1 && h->have32)

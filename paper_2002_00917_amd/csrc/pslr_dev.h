@@ -78,6 +78,12 @@ struct ApplyArrays {
   // optional (system, rhs) mask, index r * nsys + s: a block skips its work for
   // right-hand side r when its system's entry is 0 (converged FGMRES columns)
   const uint8_t* active;
+  // team split of the B_i solves (team > 1): the lower and upper factors of
+  // B_i restricted to subtree group g at block index i * (team + 1) + g, the
+  // top group at g = team (see BlockFactor::loS); ntopmax: the most top rows
+  // of any block
+  TriArrays<T> LBs, UBs;
+  int32_t team, ntopmax;
 };
 
 // A row chunk of the interface vectors for the V^T y partial sums; chunks never
@@ -162,6 +168,23 @@ hipError_t launch_tail(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, co
                        int64_t ldb, const T* u, int64_t ldu, double* z, int64_t ldz);
 template <typename T>
 hipError_t set_lds_limit(size_t bytes);
+// The B_i solves of one right-hand side spread over A.team workgroups per
+// subdomain (working vectors in LDS): three launches (subtree lower solves,
+// the top group's lower and upper solves, subtree upper solves) with the
+// interior vector xb (p values) and the top rows' pushed updates dtop
+// (nparts * team * ntopmax values) in global memory between them.
+//   series step: unext = C0^{-1}(y [add_y] - C_g u + F B^{-1} E u)  (+ a fourth launch)
+//   head:        y = g - F B^{-1} f                                (+ a fourth launch)
+//   tail:        z = P^T (B^{-1}(f - E u); u)
+template <typename T>
+hipError_t launch_series_team(const ApplyArrays<T>& A, const LaunchCfg& c, const T* y,
+                              const T* uprev, T* unext, int add_y, T* xb, T* dtop);
+template <typename T>
+hipError_t launch_head_team(const ApplyArrays<T>& A, const LaunchCfg& c, const double* b, T* y,
+                            T* xb, T* dtop);
+template <typename T>
+hipError_t launch_tail_team(const ApplyArrays<T>& A, const LaunchCfg& c, const double* b,
+                            const T* u, double* z, T* xb, T* dtop);
 
 // ---- FP64 vector kernels for Arnoldi and FGMRES
 hipError_t launch_spmv(int64_t n, const int64_t* ptr, const int32_t* col, const double* val,

@@ -446,12 +446,62 @@ void build_levels(TriHost& T, const std::vector<int>& sfirst, const std::vector<
 // Exact sparse LU of one block
 // ---------------------------------------------------------------------------
 
+std::vector<int> team_groups(const std::vector<int>& spar, const std::vector<double>& work, int team) {
+  const int ns = (int)spar.size();
+  std::vector<int> grp(ns, team);
+  if (team <= 1 || ns == 0) {
+    std::fill(grp.begin(), grp.end(), 0);
+    return grp;
+  }
+  std::vector<std::vector<int>> kids(ns);
+  std::vector<double> sub(work.begin(), work.end());
+  std::vector<int> lo(ns);
+  for (int s = 0; s < ns; ++s) lo[s] = s;
+  for (int s = 0; s < ns; ++s)
+    if (spar[s] >= 0) {
+      kids[spar[s]].push_back(s);
+      sub[spar[s]] += sub[s];
+      lo[spar[s]] = std::min(lo[spar[s]], lo[s]);
+    }
+  std::vector<int> cand;
+  double total = 0.0, top = 0.0;
+  for (int s = 0; s < ns; ++s)
+    if (spar[s] < 0) {
+      cand.push_back(s);
+      total += sub[s];
+    }
+  std::vector<char> is_top(ns, 0);
+  for (int it = 0; it < 4 * ns; ++it) {
+    std::sort(cand.begin(), cand.end(), [&](int a, int b) { return sub[a] > sub[b]; });
+    double csum = 0.0;
+    for (int c : cand) csum += sub[c];
+    const int c0 = cand[0];
+    if ((int)cand.size() >= team && sub[c0] <= 1.25 * csum / team) break;
+    if (kids[c0].empty() || top + work[c0] > 0.45 * total) break;
+    top += work[c0];
+    is_top[c0] = 1;
+    cand.erase(cand.begin());
+    cand.insert(cand.end(), kids[c0].begin(), kids[c0].end());
+    if (cand.empty()) break;
+  }
+  std::sort(cand.begin(), cand.end(), [&](int a, int b) { return sub[a] > sub[b]; });
+  std::vector<double> load(team, 0.0);
+  for (int c : cand) {
+    const int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    load[g] += sub[c];
+    for (int j = lo[c]; j <= c; ++j) grp[j] = g;
+  }
+  for (int s = 0; s < ns; ++s)
+    if (is_top[s]) grp[s] = team;
+  return grp;
+}
+
 // Bottom-up amalgamation: merged supernodes of at most kMergeWidth rows, at
 // most kMergePasses rounds (each removes one level at the bottom).
 constexpr int kMergeWidth = 16, kMergePasses = 3;
 
 int factor_block(const CsrL& M, double tau, bool want_T, int narrow_width, BlockFactor& out,
-                 std::string& err) {
+                 std::string& err, int team) {
   const int n = M.nrows;
   out = BlockFactor();
   out.n = n;
@@ -463,6 +513,11 @@ int factor_block(const CsrL& M, double tau, bool want_T, int narrow_width, Block
     }
     out.lo.lower = out.loT.lower = true;
     out.up.lower = out.upT.lower = false;
+    if (team > 1) {  // empty groups keep the team layout uniform over the blocks
+      out.team = team;
+      out.loS.assign(team + 1, out.lo);
+      out.upS.assign(team + 1, out.up);
+    }
     return 0;
   }
   double maxabs = 0.0;
@@ -840,6 +895,54 @@ int factor_block(const CsrL& M, double tau, bool want_T, int narrow_width, Block
           T.val.push_back(fromL ? Lp[s][(size_t)a * w + i] : Up[s][(size_t)i * h + a]);
     }
   };
+  // team split: the groups of the supernodes and one packed factor per group,
+  // each with its own level schedule (heights counted inside the group)
+  out.team = team > 1 ? team : 0;
+  std::vector<int> grp;
+  if (team > 1) {
+    std::vector<double> work(ns);
+    for (int s = 0; s < ns; ++s) {
+      const double w = sfirst[s + 1] - sfirst[s];
+      work[s] = w * (w + 1) + 2.0 * w * (double)R[s].size();
+    }
+    grp = team_groups(spar, work, team);
+  }
+  auto pack_groups = [&](TriHost& T, std::vector<TriPacked>& outS) -> bool {
+    outS.assign(team + 1, TriPacked());
+    for (int g = 0; g <= team; ++g) {
+      std::vector<int> hg(ns, 0);
+      int nl = 0;
+      std::vector<int> sf_g(1, 0);
+      for (int s = 0; s < ns; ++s)
+        if (grp[s] == g) {
+          nl = std::max(nl, hg[s] + 1);
+          if (spar[s] >= 0 && grp[spar[s]] == g) hg[spar[s]] = std::max(hg[spar[s]], hg[s] + 1);
+        }
+      // level schedule of the group's supernodes only
+      T.nlev = nl;
+      T.lev_ptr.assign(nl + 1, 0);
+      T.lrows.clear();
+      T.max_lrows = 0;
+      std::vector<std::vector<int>> bylev(nl);
+      for (int s = 0; s < ns; ++s)
+        if (grp[s] == g) bylev[hg[s]].push_back(s);
+      for (int l = 0; l < nl; ++l) {
+        for (int s : bylev[l])
+          for (int r = sfirst[s]; r < sfirst[s + 1]; ++r) {
+            T.lrows.push_back(r);
+            T.row_sn[r] = s;
+          }
+        T.lev_ptr[l + 1] = (int)T.lrows.size();
+        T.max_lrows = std::max(T.max_lrows, T.lev_ptr[l + 1] - T.lev_ptr[l]);
+      }
+      const int nfull = T.n;
+      T.n = (int)T.lrows.size();
+      const bool ok = pack_tri(T, outS[g], narrow_width);
+      T.n = nfull;
+      if (!ok) return false;
+    }
+    return true;
+  };
   {
     TriHost T;
     init_tri(T, true);
@@ -848,6 +951,10 @@ int factor_block(const CsrL& M, double tau, bool want_T, int narrow_width, Block
     build_levels(T, sfirst, height, nlev);
     if (!pack_tri(T, out.lo, narrow_width)) {
       err = "supernode wider than 32767 rows, panel taller than 32767 rows or block factor beyond 2^31 entries";
+      return 3;
+    }
+    if (team > 1 && !pack_groups(T, out.loS)) {
+      err = "team split: packed factor beyond 2^31 entries";
       return 3;
     }
   }
@@ -859,6 +966,10 @@ int factor_block(const CsrL& M, double tau, bool want_T, int narrow_width, Block
     build_levels(T, sfirst, height, nlev);
     if (!pack_tri(T, out.up, narrow_width)) {
       err = "supernode wider than 32767 rows, panel taller than 32767 rows or block factor beyond 2^31 entries";
+      return 3;
+    }
+    if (team > 1 && !pack_groups(T, out.upS)) {
+      err = "team split: packed factor beyond 2^31 entries";
       return 3;
     }
   }
@@ -1315,6 +1426,66 @@ bool check_levels(const TriPacked& T, std::string& err) {
         err = "an entry-form dependency is not across levels";
         return false;
       }
+  }
+  return true;
+}
+
+// Team split check: the groups cover every position once; in group g the
+// lower solve pushes only into its own later levels or the top group, the
+// upper solve reads only its own later-solved rows or the top group (g <
+// team); the top group's solves stay inside the top group.
+bool check_team(const BlockFactor& F, std::string& err) {
+  const int team = F.team;
+  if (team < 2) return true;
+  if ((int)F.loS.size() != team + 1 || (int)F.upS.size() != team + 1) {
+    err = "team packing missing";
+    return false;
+  }
+  const int n = F.n;
+  for (int pass = 0; pass < 2; ++pass) {
+    const std::vector<TriPacked>& G = pass == 0 ? F.loS : F.upS;
+    std::vector<int> grp(n, -1), lev(n, -1);
+    for (int g = 0; g <= team; ++g) {
+      const TriPacked& T = G[g];
+      for (int l = 0; l < T.nlev; ++l)
+        for (int k = T.lev_ptr[l]; k < T.lev_ptr[l + 1]; ++k) {
+          const int p = T.rec[(size_t)8 * k];
+          if (p < 0 || p >= n || grp[p] >= 0) {
+            err = "a position is scheduled twice or out of range";
+            return false;
+          }
+          grp[p] = g;
+          lev[p] = l;
+        }
+    }
+    for (int p = 0; p < n; ++p)
+      if (grp[p] < 0) {
+        err = "a position is in no group";
+        return false;
+      }
+    for (int g = 0; g <= team; ++g) {
+      const TriPacked& T = G[g];
+      auto ok_dep = [&](int q, int l) {
+        if (grp[q] == g) return lev[q] > l;   // solved later (lower) / earlier in the upper sweep
+        return g < team && grp[q] == team;    // a subtree may reach the top group
+      };
+      for (int l = 0; l < T.nlev; ++l) {
+        for (int k = T.lev_ptr[l]; k < T.lev_ptr[l + 1]; ++k) {
+          const int32_t* r = &T.rec[(size_t)8 * k];
+          const int h = r[3], roff = r[6];
+          for (int a = 0; a < h; ++a)
+            if (!ok_dep(T.ridx[roff + a], l)) {
+              err = "a team group depends on a row outside its reach";
+              return false;
+            }
+        }
+        for (int q = T.ent_ptr[l]; q < T.ent_ptr[l + 1]; ++q)
+          if (!ok_dep(T.eidx[q], l)) {
+            err = "a team group's entry form reaches outside its reach";
+            return false;
+          }
+      }
+    }
   }
   return true;
 }

@@ -137,6 +137,15 @@ struct BlockFactor {
   int32_t n = 0;
   std::vector<int32_t> gin, gout;
   TriPacked lo, up, loT, upT;
+  // Team split (team > 1): the supernodal elimination tree cut into `team`
+  // groups of whole subtrees (balanced by factor entries) and the top group
+  // of the supernodes above them.  loS[g] / upS[g] hold the same supernodes
+  // as lo / up restricted to group g (g = team: the top group), each with its
+  // own level schedule over the block's positions: a subtree's solve needs
+  // no row of another subtree, its lower solve pushes into top rows only, and
+  // the top group's upper solve reads top rows only.
+  int32_t team = 0;
+  std::vector<TriPacked> loS, upS;
   int64_t nnz_L = 0, nnz_U = 0;   // entries of L and U (diagonal blocks included)
   int32_t nsuper = 0;
 };
@@ -146,7 +155,17 @@ struct BlockFactor {
 // narrow_width: the entry-form threshold of pack_tri (kNarrowWidthB for
 // interior blocks, kNarrowWidthC for interface blocks).
 int factor_block(const CsrL& M, double tau, bool want_transpose, int narrow_width, BlockFactor& out,
-                 std::string& err);
+                 std::string& err, int team = 0);
+
+// Team groups of a supernodal elimination tree (postordered: children before
+// parents, every subtree a contiguous range): grp[s] in [0, team) for the
+// supernodes of the `team` groups of whole subtrees, team for the top group.
+// Subtrees are taken from the roots down, moving the heaviest (by `work`) into
+// the top group while the candidates are fewer than `team` or the heaviest
+// exceeds 1.25 times an even share, as long as the top group stays below 45%
+// of the work; the subtrees are then assigned largest first to the lightest
+// group.
+std::vector<int> team_groups(const std::vector<int>& spar, const std::vector<double>& work, int team);
 
 // Threshold incomplete LU of block M in its given row order, no pivoting
 // (the ilu() of Algorithm 4): row by row, w = M[i, :], tau_i = drop times the
@@ -175,6 +194,12 @@ int ilut_factor(const CsrL& M, double drop, IlutFactors& F, std::string& err);
 // off-diagonal dependency (panel rows, push targets, entry-form indices) is
 // solved strictly before the row that needs it.
 bool check_levels(const TriPacked& T, std::string& err);
+
+// Structural check of a team split (BlockFactor::loS/upS): every position in
+// one group; each subtree group's lower pushes and upper pulls reach only its
+// own rows on the right side of the schedule or the top group; the top
+// group's stay inside it.
+bool check_team(const BlockFactor& F, std::string& err);
 
 // Reordering of Sec. 2 (interface rule and interiors-first permutation).
 struct Reordering {

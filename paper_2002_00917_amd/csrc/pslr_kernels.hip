@@ -982,6 +982,187 @@ __global__ void __launch_bounds__(1024) k_tail(ApplyArrays<T> A, int nrhs, const
   }
 }
 
+// ---- B_i solves spread over a team of workgroups (one right-hand side,
+// working vectors in LDS).  The supernodal tree of every B_i is cut into
+// `team` groups of whole subtrees and a top group (BlockFactor::loS/upS).
+// Workgroup (i, g) solves group g's rows: its lower solve pushes into the
+// top rows of its own LDS copy (started at zero), which go to dtop; one
+// workgroup per subdomain then solves the top group (lower and upper) from
+// the right-hand side plus the team's pushes; the team then runs its upper
+// solves, pulling the top rows.  Between the launches the interior vector
+// lives in xb.  MODE: 0 power-series step (right-hand side E u), 1 head
+// (f gathered from b), 2 tail (f - E u; results scattered to z).
+
+template <typename T, int MODE>
+__device__ __forceinline__ T team_rhs(const ApplyArrays<T>& A, int64_t row, const T* U,
+                                      const double* __restrict__ b) {
+  T acc = MODE == 0 ? (T)0 : (T)b[A.gB_in[row]];
+  if (MODE != 1)
+    for (int64_t q = A.Ein.ptr[row]; q < A.Ein.ptr[row + 1]; ++q) {
+      const T v = A.Ein.val[q] * U[A.Ein.col[q]];
+      acc = MODE == 0 ? acc + v : acc - v;
+    }
+  return acc;
+}
+
+// rows (positions) of group g of block bi in a team family, in level order
+template <typename T>
+__device__ __forceinline__ int team_rows(const TriArrays<T>& F, int bi, const int4*& rec) {
+  const DevTriBlock B = F.blk[bi];
+  rec = F.rec + 2 * B.rec_base;
+  return B.nlev > 0 ? F.lev_ptr[B.lev_base + B.nlev] : 0;
+}
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(1024) k_team_lower(ApplyArrays<T> A, const double* __restrict__ b,
+                                                     const T* __restrict__ u, T* xb, T* dtop,
+                                                     double* z) {
+  const int team = A.team;
+  const int i = blockIdx.x / team, g = blockIdx.x - i * team, tid = threadIdx.x, nt = blockDim.x;
+  int r0, nr;
+  if (!tile_rhs<T, 1>(A, 1, i, r0, nr)) return;
+  Lds<T> L = carve<T, 1, false>(A);
+  const int64_t i0 = A.int_ptr[i];
+  const int64_t f0 = A.if_ptr[i], qi = A.if_ptr[i + 1] - f0;
+  if (MODE != 1) {
+    for (int64_t kk = tid; kk < qi; kk += nt) {
+      const T v = u[f0 + kk];
+      L.U[kk] = v;
+      if (MODE == 2 && g == 0) z[A.if_orig[f0 + kk]] = (double)v;
+    }
+    __syncthreads();
+  }
+  const int bs = i * (team + 1);
+  const int4 *ro, *rt;
+  const int nown = team_rows(A.LBs, bs + g, ro), ntop = team_rows(A.LBs, bs + team, rt);
+  for (int k = tid; k < nown; k += nt) {
+    const int p = ro[2 * k].x;
+    L.XB[p] = team_rhs<T, MODE>(A, i0 + p, L.U, b);
+  }
+  for (int k = tid; k < ntop; k += nt) L.XB[rt[2 * k].x] = (T)0;
+  __syncthreads();
+  tri_solve<T, 1, false>(A.LBs, bs + g, L.XB, L.Rb, A.gshift);
+  __syncthreads();
+  for (int k = tid; k < nown; k += nt) {
+    const int p = ro[2 * k].x;
+    xb[i0 + p] = L.XB[p];
+  }
+  T* d = dtop + ((int64_t)i * team + g) * A.ntopmax;
+  for (int k = tid; k < ntop; k += nt) d[k] = L.XB[rt[2 * k].x];
+}
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(1024) k_team_top(ApplyArrays<T> A, const double* __restrict__ b,
+                                                   const T* __restrict__ u, T* xb,
+                                                   const T* __restrict__ dtop, double* z) {
+  const int team = A.team;
+  const int i = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  int r0, nr;
+  if (!tile_rhs<T, 1>(A, 1, i, r0, nr)) return;
+  Lds<T> L = carve<T, 1, false>(A);
+  const int64_t i0 = A.int_ptr[i];
+  const int64_t f0 = A.if_ptr[i], qi = A.if_ptr[i + 1] - f0;
+  if (MODE != 1) {
+    for (int64_t kk = tid; kk < qi; kk += nt) L.U[kk] = u[f0 + kk];
+    __syncthreads();
+  }
+  const int bs = i * (team + 1);
+  const int4* rt;
+  const int ntop = team_rows(A.LBs, bs + team, rt);
+  const T* d = dtop + (int64_t)i * team * A.ntopmax;
+  for (int k = tid; k < ntop; k += nt) {
+    const int p = rt[2 * k].x;
+    T acc = team_rhs<T, MODE>(A, i0 + p, L.U, b);
+    for (int t = 0; t < team; ++t) acc += d[(int64_t)t * A.ntopmax + k];
+    L.XB[p] = acc;
+  }
+  __syncthreads();
+  tri_solve<T, 1, false>(A.LBs, bs + team, L.XB, L.Rb, A.gshift);
+  tri_solve<T, 1, false>(A.UBs, bs + team, L.XB, L.Rb, A.gshift);
+  __syncthreads();
+  for (int k = tid; k < ntop; k += nt) {
+    const int p = rt[2 * k].x;
+    if (MODE == 2) z[A.gB_out[i0 + p]] = (double)L.XB[p];
+    else xb[i0 + p] = L.XB[p];
+    if (MODE == 2) xb[i0 + p] = L.XB[p];
+  }
+}
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(1024) k_team_upper(ApplyArrays<T> A, T* xb, double* z) {
+  const int team = A.team;
+  const int i = blockIdx.x / team, g = blockIdx.x - i * team, tid = threadIdx.x, nt = blockDim.x;
+  int r0, nr;
+  if (!tile_rhs<T, 1>(A, 1, i, r0, nr)) return;
+  Lds<T> L = carve<T, 1, false>(A);
+  const int64_t i0 = A.int_ptr[i];
+  const int bs = i * (team + 1);
+  const int4 *ro, *rt;
+  const int nown = team_rows(A.UBs, bs + g, ro), ntop = team_rows(A.UBs, bs + team, rt);
+  for (int k = tid; k < nown; k += nt) {
+    const int p = ro[2 * k].x;
+    L.XB[p] = xb[i0 + p];
+  }
+  for (int k = tid; k < ntop; k += nt) {
+    const int p = rt[2 * k].x;
+    L.XB[p] = xb[i0 + p];
+  }
+  __syncthreads();
+  tri_solve<T, 1, false>(A.UBs, bs + g, L.XB, L.Rb, A.gshift);
+  __syncthreads();
+  for (int k = tid; k < nown; k += nt) {
+    const int p = ro[2 * k].x;
+    if (MODE == 2) z[A.gB_out[i0 + p]] = (double)L.XB[p];
+    else xb[i0 + p] = L.XB[p];
+  }
+}
+
+// the C0 part of a power-series step with t = B^{-1} E u read from xb
+template <typename T>
+__global__ void __launch_bounds__(1024) k_team_c0(ApplyArrays<T> A, const T* __restrict__ y,
+                                                  const T* __restrict__ uprev, T* unext,
+                                                  const T* __restrict__ xb, int add_y) {
+  const int i = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  int r0, nr;
+  if (!tile_rhs<T, 1>(A, 1, i, r0, nr)) return;
+  Lds<T> L = carve<T, 1, false>(A);
+  const int64_t f0 = A.if_ptr[i], qi = A.if_ptr[i + 1] - f0;
+  const int64_t i0 = A.int_ptr[i];
+  for (int64_t kk = tid; kk < qi; kk += nt) {
+    const int64_t row = f0 + kk;
+    T acc = add_y ? y[row] : (T)0;
+    for (int64_t q = A.Cg.ptr[row]; q < A.Cg.ptr[row + 1]; ++q) acc -= A.Cg.val[q] * uprev[A.Cg.col[q]];
+    for (int64_t q = A.Fout.ptr[row]; q < A.Fout.ptr[row + 1]; ++q)
+      acc += A.Fout.val[q] * xb[i0 + A.Fout.col[q]];
+    L.XC[A.gC_inv[row]] = acc;
+  }
+  __syncthreads();
+  tri_solve<T, 1, false>(A.LC, i, L.XC, L.Rb, A.gshift);
+  tri_solve<T, 1, false>(A.UC, i, L.XC, L.Rb, A.gshift);
+  for (int64_t c = tid; c < qi; c += nt) unext[f0 + A.gC_out[f0 + c]] = L.XC[c];
+}
+
+// y = g - F t of the head with t = B^{-1} f read from xb (one thread per interface row)
+template <typename T>
+__global__ void __launch_bounds__(256) k_team_headF(ApplyArrays<T> A, const double* __restrict__ b,
+                                                    const T* __restrict__ xb, T* y) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= A.q) return;
+  // subdomain of the row: the last i with if_ptr[i] <= row (binary search)
+  int lo = 0, hi = A.nparts - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (A.if_ptr[mid] <= row) lo = mid;
+    else hi = mid - 1;
+  }
+  if (A.active && !A.active[A.part_sys[lo]]) return;
+  const int64_t i0 = A.int_ptr[lo];
+  T acc = (T)b[A.if_orig[row]];
+  for (int64_t q = A.Fout.ptr[row]; q < A.Fout.ptr[row + 1]; ++q)
+    acc -= A.Fout.val[q] * xb[i0 + A.Fout.col[q]];
+  y[row] = acc;
+}
+
 inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
@@ -1020,6 +1201,19 @@ hipError_t set_lds_limit(size_t bytes) {
   PSLR_SETATTR(4)
   PSLR_SETATTR(8)
 #undef PSLR_SETATTR
+#define PSLR_SETATTR_TEAM(K)                                                                         \
+  if ((e = hipFuncSetAttribute((const void*)K, hipFuncAttributeMaxDynamicSharedMemorySize, b))) return e;
+  PSLR_SETATTR_TEAM((k_team_lower<T, 0>))
+  PSLR_SETATTR_TEAM((k_team_lower<T, 1>))
+  PSLR_SETATTR_TEAM((k_team_lower<T, 2>))
+  PSLR_SETATTR_TEAM((k_team_top<T, 0>))
+  PSLR_SETATTR_TEAM((k_team_top<T, 1>))
+  PSLR_SETATTR_TEAM((k_team_top<T, 2>))
+  PSLR_SETATTR_TEAM((k_team_upper<T, 0>))
+  PSLR_SETATTR_TEAM((k_team_upper<T, 1>))
+  PSLR_SETATTR_TEAM((k_team_upper<T, 2>))
+  PSLR_SETATTR_TEAM((k_team_c0<T>))
+#undef PSLR_SETATTR_TEAM
   return hipSuccess;
 }
 
@@ -1137,6 +1331,50 @@ hipError_t launch_tail(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, co
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_series_team(const ApplyArrays<T>& A, const LaunchCfg& c, const T* y,
+                              const T* uprev, T* unext, int add_y, T* xb, T* dtop) {
+  if (A.team < 2 || c.R != 1 || c.gx) return hipErrorInvalidValue;
+  const dim3 gt((unsigned)(A.nparts * A.team)), g1((unsigned)A.nparts), bt(c.threads);
+  if (c.ev_start)
+    hipExtLaunchKernelGGL((k_team_lower<T, 0>), gt, bt, (uint32_t)c.lds, c.stream, c.ev_start, nullptr, 0,
+                          A, nullptr, uprev, xb, dtop, nullptr);
+  else
+    hipLaunchKernelGGL((k_team_lower<T, 0>), gt, bt, c.lds, c.stream, A, nullptr, uprev, xb, dtop, nullptr);
+  hipLaunchKernelGGL((k_team_top<T, 0>), g1, bt, c.lds, c.stream, A, nullptr, uprev, xb, dtop, nullptr);
+  hipLaunchKernelGGL((k_team_upper<T, 0>), gt, bt, c.lds, c.stream, A, xb, nullptr);
+  if (c.ev_stop)
+    hipExtLaunchKernelGGL((k_team_c0<T>), g1, bt, (uint32_t)c.lds, c.stream, nullptr, c.ev_stop, 0, A, y,
+                          uprev, unext, xb, add_y);
+  else
+    hipLaunchKernelGGL((k_team_c0<T>), g1, bt, c.lds, c.stream, A, y, uprev, unext, xb, add_y);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_head_team(const ApplyArrays<T>& A, const LaunchCfg& c, const double* b, T* y,
+                            T* xb, T* dtop) {
+  if (A.team < 2 || c.R != 1 || c.gx) return hipErrorInvalidValue;
+  const dim3 gt((unsigned)(A.nparts * A.team)), g1((unsigned)A.nparts), bt(c.threads);
+  hipLaunchKernelGGL((k_team_lower<T, 1>), gt, bt, c.lds, c.stream, A, b, nullptr, xb, dtop, nullptr);
+  hipLaunchKernelGGL((k_team_top<T, 1>), g1, bt, c.lds, c.stream, A, b, nullptr, xb, dtop, nullptr);
+  hipLaunchKernelGGL((k_team_upper<T, 1>), gt, bt, c.lds, c.stream, A, xb, nullptr);
+  if (A.q > 0)
+    hipLaunchKernelGGL((k_team_headF<T>), dim3(nblk(A.q, 256)), dim3(256), 0, c.stream, A, b, xb, y);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_tail_team(const ApplyArrays<T>& A, const LaunchCfg& c, const double* b,
+                            const T* u, double* z, T* xb, T* dtop) {
+  if (A.team < 2 || c.R != 1 || c.gx) return hipErrorInvalidValue;
+  const dim3 gt((unsigned)(A.nparts * A.team)), g1((unsigned)A.nparts), bt(c.threads);
+  hipLaunchKernelGGL((k_team_lower<T, 2>), gt, bt, c.lds, c.stream, A, b, u, xb, dtop, z);
+  hipLaunchKernelGGL((k_team_top<T, 2>), g1, bt, c.lds, c.stream, A, b, u, xb, dtop, z);
+  hipLaunchKernelGGL((k_team_upper<T, 2>), gt, bt, c.lds, c.stream, A, xb, z);
+  return hipGetLastError();
+}
+
 #define PSLR_INST(T)                                                                             \
   template hipError_t set_lds_limit<T>(size_t);                                                  \
   template hipError_t launch_head<T>(const ApplyArrays<T>&, const LaunchCfg&, int, const double*, \
@@ -1146,7 +1384,13 @@ hipError_t launch_tail(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, co
   template hipError_t launch_series<T>(const ApplyArrays<T>&, const LaunchCfg&, int, const T*,    \
                                        int64_t, const T*, T*, int64_t, int, int);                \
   template hipError_t launch_tail<T>(const ApplyArrays<T>&, const LaunchCfg&, int, const double*, \
-                                     int64_t, const T*, int64_t, double*, int64_t);
+                                     int64_t, const T*, int64_t, double*, int64_t);              \
+  template hipError_t launch_series_team<T>(const ApplyArrays<T>&, const LaunchCfg&, const T*,    \
+                                            const T*, T*, int, T*, T*);                          \
+  template hipError_t launch_head_team<T>(const ApplyArrays<T>&, const LaunchCfg&, const double*, \
+                                          T*, T*, T*);                                           \
+  template hipError_t launch_tail_team<T>(const ApplyArrays<T>&, const LaunchCfg&, const double*, \
+                                          const T*, double*, T*, T*);
 
 PSLR_INST(double)
 PSLR_INST(float)

@@ -35,13 +35,15 @@ class pslr_options(C.Structure):
                 ("want_transpose", C.c_int32), ("v0", C.POINTER(C.c_double)),
                 ("seed", C.c_uint64), ("pivot_threshold", C.c_double), ("nthreads", C.c_int32),
                 ("working_vectors", C.c_int32), ("autotune", C.c_int32), ("threads", C.c_int32),
-                ("factor", C.c_int32), ("drop_tol", C.c_double), ("lowrank", C.c_int32)]
+                ("factor", C.c_int32), ("drop_tol", C.c_double), ("lowrank", C.c_int32),
+                ("team", C.c_int32)]
 
 
 class pslr_host_stats_t(C.Structure):
     _fields_ = [("nnz_LU_B", C.c_int64), ("nnz_LU_C0", C.c_int64), ("max_levels_B", C.c_int32),
                 ("max_levels_C0", C.c_int32), ("levels_valid", C.c_int32),
-                ("factor_residual", C.c_double), ("solve_residual", C.c_double)]
+                ("factor_residual", C.c_double), ("solve_residual", C.c_double),
+                ("team", C.c_int32), ("team_valid", C.c_int32), ("team_residual", C.c_double)]
 
 
 class pslr_info_t(C.Structure):
@@ -201,9 +203,10 @@ LOWRANK = {"arnoldi": 0, "krylov_schur": 1, "deflate_unit": 2}
 
 def _options(m, rank, precision, want_transpose, v0, seed, pivot_threshold, nthreads,
              working_vectors, autotune=False, threads=0, factor="lu", drop_tol=1e-2,
-             lowrank="arnoldi"):
+             lowrank="arnoldi", team=0):
     o = pslr_default_options()
     o.lowrank = LOWRANK[lowrank]
+    o.team = int(team)
     o.threads = int(threads)
     o.factor = FACTORS[factor]
     o.drop_tol = float(drop_tol)
@@ -221,14 +224,14 @@ def _options(m, rank, precision, want_transpose, v0, seed, pivot_threshold, nthr
 def pslr_setup(rowptr, colind, vals, part, nparts, m=3, rank=16, precision=0,
                want_transpose=False, v0=None, seed=1, pivot_threshold=0.1, nthreads=0,
                working_vectors=0, autotune=False, threads=0, factor="lu", drop_tol=1e-2,
-               lowrank="arnoldi", stream=None) -> Handle:
+               lowrank="arnoldi", team=0, stream=None) -> Handle:
     L = lib()
     rp, rpp = _arr(rowptr, np.int64)
     ci, cip = _arr(colind, np.int32)
     va, vap = _arr(vals, np.float64)
     pa, pap = _arr(part, np.int32)
     o, keep = _options(m, rank, precision, want_transpose, v0, seed, pivot_threshold, nthreads,
-                       working_vectors, autotune, threads, factor, drop_tol, lowrank)
+                       working_vectors, autotune, threads, factor, drop_tol, lowrank, team)
     out = C.c_void_p()
     n = len(rp) - 1
     st = L.pslr_setup(n, rpp, cip, vap, pap, int(nparts), C.byref(o), _stream_ptr(stream),
@@ -241,7 +244,7 @@ def pslr_setup(rowptr, colind, vals, part, nparts, m=3, rank=16, precision=0,
 def pslr_setup_batched(rowptr, colind, vals, part, nparts, sys_ptr, m=3, rank=16, precision=0,
                        want_transpose=False, v0=None, seed=1, pivot_threshold=0.1, nthreads=0,
                        working_vectors=0, autotune=False, threads=0, factor="lu", drop_tol=1e-2,
-                       lowrank="arnoldi", stream=None) -> Handle:
+                       lowrank="arnoldi", team=0, stream=None) -> Handle:
     L = lib()
     rp, rpp = _arr(rowptr, np.int64)
     ci, cip = _arr(colind, np.int32)
@@ -249,7 +252,7 @@ def pslr_setup_batched(rowptr, colind, vals, part, nparts, sys_ptr, m=3, rank=16
     pa, pap = _arr(part, np.int32)
     sp, spp = _arr(sys_ptr, np.int64)
     o, keep = _options(m, rank, precision, want_transpose, v0, seed, pivot_threshold, nthreads,
-                       working_vectors, autotune, threads, factor, drop_tol, lowrank)
+                       working_vectors, autotune, threads, factor, drop_tol, lowrank, team)
     out = C.c_void_p()
     n = len(rp) - 1
     st = L.pslr_setup_batched(n, rpp, cip, vap, pap, int(nparts), len(sp) - 1, spp, C.byref(o),
@@ -404,7 +407,7 @@ def pslr_reorder(rowptr, colind, part, nparts):
 
 
 def pslr_host_stats(rowptr, colind, vals, part, nparts, want_transpose=True, pivot_threshold=0.1,
-                    nthreads=0, factor="lu", drop_tol=1e-2) -> dict:
+                    nthreads=0, factor="lu", drop_tol=1e-2, team=0) -> dict:
     rp, rpp = _arr(rowptr, np.int64)
     ci, cip = _arr(colind, np.int32)
     va, vap = _arr(vals, np.float64)
@@ -415,6 +418,7 @@ def pslr_host_stats(rowptr, colind, vals, part, nparts, want_transpose=True, piv
     o.nthreads = int(nthreads)
     o.factor = FACTORS[factor]
     o.drop_tol = float(drop_tol)
+    o.team = int(team)
     out = pslr_host_stats_t()
     _check(lib().pslr_host_stats(len(rp) - 1, rpp, cip, vap, pap, int(nparts), C.byref(o),
                                  C.byref(out)))

@@ -182,3 +182,28 @@ def test_ilut_fill_matches_table1():
         assert abs(fill - printed) <= 0.06 * printed
         fills.append(fill)
     assert all(fills[i + 1] < fills[i] for i in range(len(fills) - 1))
+
+
+@pytest.mark.parametrize("team", [2, 3, 4, 8])
+def test_team_split_structure_and_host_solve(team):
+    """The team split of every B_i: each position in one group, subtree groups
+    reach only their own rows or the top group, and the groups applied in turn
+    on the host equal the plain packed solve."""
+    A = wl.laplacian3d(16, 0.1)
+    lab = opart.geometric_labels((16,) * 3, (2, 2, 2))
+    st = P.pslr_host_stats(A.rowptr, A.colind, A.vals, lab, 8, want_transpose=False, team=team)
+    assert st["team"] == team and st["team_valid"] == 1 and st["levels_valid"] == 1
+    assert st["team_residual"] < 1e-14
+    A = wl.convdiff3d(12, 10.0, 0.2)
+    lab, nl = P.pslr_partition_region_growing(A.rowptr, A.colind, 6, 4)
+    st = P.pslr_host_stats(A.rowptr, A.colind, A.vals, lab, nl, want_transpose=False, team=team)
+    assert st["team_valid"] == 1 and st["team_residual"] < 1e-14
+    # parts without interior unknowns keep the team layout (empty groups)
+    A2 = wl.laplacian2d(9, 0.1)
+    lab2 = opart.geometric_labels((9, 9), (4, 4))
+    st = P.pslr_host_stats(A2.rowptr, A2.colind, A2.vals, lab2, 16, want_transpose=False, team=team)
+    assert st["team"] == team and st["team_valid"] == 1
+    # threshold ILU has no team split
+    st = P.pslr_host_stats(A.rowptr, A.colind, A.vals, lab, nl, want_transpose=False, team=team,
+                           factor="ilut")
+    assert st["team"] == 0
