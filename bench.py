@@ -159,6 +159,7 @@ def form_record(r):
         "nnz_LU_B": inf["nnz_LU_B"], "nnz_LU_C0": inf["nnz_LU_C0"],
         "levels_B": inf["max_levels_B"], "levels_C0": inf["max_levels_C0"],
         "fill_lu": inf["fill_lu"], "fill_total": inf["fill_total"],
+        "team": inf["team"], "team_top": inf["team_top"],
     }
 
 

@@ -119,11 +119,19 @@ typedef struct {
                                    to 256), so that all eigenvalues of E_rr(m) outside the unit
                                    circle are deflated (Sec. 3.2.2); pslr_info.rank gives the
                                    count reached, which may exceed r_k */
-  int32_t team;             /* B_i solves of single-right-hand-side applies spread over `team`
-                               workgroups per subdomain (the supernodal tree cut into `team`
-                               groups of whole subtrees and the top group above them; exact LU
-                               only): 0 = automatic (4 when nparts <= 128, else 1), 1 = off,
-                               2..8 = that many */
+  int32_t team;             /* B_i and C_i solves of single-right-hand-side applies spread over
+                               `team` workgroups per subdomain (the supernodal tree of each
+                               block cut into `team` groups of whole subtrees and the top group
+                               above them; exact LU only): 0 = automatic (4 when nparts <= 128,
+                               else 1), 1 = off, 2..8 = that many */
+  int32_t team_top;         /* how the team split solves its top group: 0 = automatic (2 when
+                               every block's top group has at most 1024 rows and the dense
+                               inverses hold at most twice the values the top groups' packed
+                               factors hold, else 1); 1 = lower and upper solve of the packed
+                               top-group factors, one workgroup per subdomain; 2 = one product
+                               with the dense inverse of the top group's block of L U, spread
+                               over one workgroup per 64 top rows (PSLR_EINVAL when a top
+                               group has more than 1024 rows) */
 } pslr_options;
 
 typedef struct {
@@ -158,6 +166,11 @@ typedef struct {
                                low-rank products V^T Y and V (G V^T Y) on the matrix cores (BF16
                                V, FP32 accumulation, Y split in three BF16 parts); 0 = never
                                (only FP32 applies with V kept in BF16) */
+  int32_t team;             /* team size of the single-right-hand-side B_i solves (0: no split) */
+  int32_t team_top;         /* the B_i top groups' solve: 1 packed factors, 2 dense inverse (0: no
+                               split) */
+  int32_t team_c;           /* team size of the single-right-hand-side C_i solves (0: no split) */
+  int32_t team_top_c;       /* the C_i top groups' solve, as team_top */
 } pslr_info_t;
 
 /* Fill *opt with defaults: m = 3, rank = 16, FP64, no transpose, seed 1, tau 0.1,
@@ -343,11 +356,12 @@ typedef struct {
   int32_t max_levels_B, max_levels_C0;
   int32_t levels_valid;
   double factor_residual, solve_residual;
-  int32_t team;             /* the team size of the B_i solves (0: no team split) */
-  int32_t team_valid;       /* 1 when every B_i's team split passes its structural check */
+  int32_t team;             /* the team size of the B_i and C_i solves (0: no team split) */
+  int32_t team_valid;       /* 1 when every block's team split passes its structural check */
   double team_residual;     /* largest relative difference between the team-split solve of
-                               every B_i (groups applied in turn on the host) and its plain
-                               packed solve */
+                               every B_i and C_i (groups applied in turn on the host, the top group
+                               once by its packed factors and once by its dense inverse
+                               where it has one) and its plain packed solve */
 } pslr_host_stats_t;
 pslr_status pslr_host_stats(int64_t n, const int64_t* rowptr, const int32_t* colind,
                             const double* vals, const int32_t* part, int32_t nparts,

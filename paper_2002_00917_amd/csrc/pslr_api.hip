@@ -427,10 +427,64 @@ DirHost build_dir(const Reordering& R, const Blocks& Bk, const std::vector<Block
   return D;
 }
 
+// Team split of one family of blocks (every block split into the same
+// number of groups; F[0].team <= 1: none).  team_top as pslr_options.team_top.
+// bytes: set to what the team solves read (the groups' packed factors, the
+// top groups' packed factors or dense inverses and their row records).
+template <typename T>
+hipError_t upload_team(DevPool& pool, const std::vector<BlockFactor>& F, int team_top, TeamArrays<T>& out,
+                       int& mlr, int64_t& bytes) {
+  out = TeamArrays<T>{};
+  if (F.empty() || F[0].team <= 1) return hipSuccess;
+  const int team = F[0].team;
+  const int w = (int)sizeof(T);
+  const int path = w == 8 ? 0 : 1;
+  auto rd = [&](const TriPacked& P) { return P.read_vals[path] * (int64_t)w + 4 * P.read_ints[path]; };
+  std::vector<const TriPacked*> ls, us;
+  int64_t groups = 0, top_packed = 0, top_vals = 0, dense_vals = 0;
+  bool dense_ok = true;
+  for (const BlockFactor& f : F) {
+    if (f.team != team || (int)f.loS.size() != team + 1 || (int)f.upS.size() != team + 1)
+      return hipErrorInvalidValue;
+    for (int g = 0; g <= team; ++g) {
+      ls.push_back(&f.loS[g]);
+      us.push_back(&f.upS[g]);
+      (g < team ? groups : top_packed) += rd(f.loS[g]) + rd(f.upS[g]);
+    }
+    top_vals += f.loS[team].read_vals[path] + f.upS[team].read_vals[path];
+    dense_vals += (int64_t)f.ntop * f.ntop;
+    if (f.ntop > 0 && f.topinv.empty()) dense_ok = false;
+    out.ntopmax = std::max(out.ntopmax, f.loS[team].n);
+  }
+  hipError_t e;
+  int64_t tb;
+  if ((e = upload_tri_list(pool, ls, out.L, mlr, tb))) return e;
+  if ((e = upload_tri_list(pool, us, out.U, mlr, tb))) return e;
+  out.team = team;
+  if (team_top == 2 && !dense_ok) return hipErrorInvalidValue;
+  const bool dense = dense_ok && (team_top == 2 || (team_top == 0 && dense_vals <= 2 * top_vals));
+  bytes = groups + top_packed;
+  if (dense) {
+    std::vector<T> ti;
+    std::vector<int64_t> off(1, 0);
+    int64_t rec_bytes = 0;
+    for (const BlockFactor& f : F) {
+      for (double v : f.topinv) ti.push_back((T)v);
+      off.push_back((int64_t)ti.size());
+      rec_bytes += 16 * (int64_t)f.ntop;
+    }
+    if ((e = pool.upload(ti, &out.TI))) return e;
+    if ((e = pool.upload(off, &out.ti_off))) return e;
+    out.nrb = (out.ntopmax + 63) / 64;
+    bytes = groups + dense_vals * w + rec_bytes;
+  }
+  return hipSuccess;
+}
+
 template <typename T>
 hipError_t upload_dir(DevPool& pool, const Reordering& R, const std::vector<BlockFactor>& fB,
                       const std::vector<BlockFactor>& fC, const DirHost& D, bool transpose,
-                      const int64_t* d_int_ptr, const int64_t* d_if_ptr, const int32_t* d_if_orig,
+                      int team_top, const int64_t* d_int_ptr, const int64_t* d_if_ptr, const int32_t* d_if_orig,
                       ApplyArrays<T>& A, int64_t bytes_out[4]) {
   hipError_t e;
   A.nparts = R.nparts;
@@ -453,24 +507,11 @@ hipError_t upload_dir(DevPool& pool, const Reordering& R, const std::vector<Bloc
   bytes_out[1] = by;
   if ((e = upload_tri(pool, fC, up, A.UC, mlr, by))) return e;
   bytes_out[1] += by;
-  A.team = 0;
-  A.ntopmax = 0;
-  if (!transpose && !fB.empty() && fB[0].team > 1) {
-    const int team = fB[0].team;
-    std::vector<const TriPacked*> ls, us;
-    for (const BlockFactor& f : fB) {
-      if (f.team != team || (int)f.loS.size() != team + 1 || (int)f.upS.size() != team + 1)
-        return hipErrorInvalidValue;
-      for (int g = 0; g <= team; ++g) {
-        ls.push_back(&f.loS[g]);
-        us.push_back(&f.upS[g]);
-      }
-      A.ntopmax = std::max(A.ntopmax, f.loS[team].n);
-    }
-    int64_t tb;
-    if ((e = upload_tri_list(pool, ls, A.LBs, mlr, tb))) return e;
-    if ((e = upload_tri_list(pool, us, A.UBs, mlr, tb))) return e;
-    A.team = team;
+  A.TB = TeamArrays<T>{};
+  A.TC = TeamArrays<T>{};
+  if (!transpose) {
+    if ((e = upload_team(pool, fB, team_top, A.TB, mlr, bytes_out[0]))) return e;
+    if ((e = upload_team(pool, fC, team_top, A.TC, mlr, bytes_out[1]))) return e;
   }
   A.maxLR = std::max(mlr, 1);
   A.maxPB = A.maxQB = 1;
@@ -502,9 +543,14 @@ WsSizes ws_sizes(const pslr_ctx* h, int nrhs) {
   z.vec = (size_t)std::max<int64_t>(h->R.q, 1) * nrhs;
   z.partial = (size_t)h->nchunk_lr * nrhs * std::max(h->k, 1);
   z.gws = h->gws_stride > 0 ? (size_t)h->gws_stride * ((nrhs + 7) / 8 * 8) : 0;
-  // interior vector and top-row updates of the team solves (one right-hand side)
-  if (h->fw64.team > 1)
-    z.team = (size_t)std::max<int64_t>(h->R.p, 1) + (size_t)h->R.nparts * h->fw64.team * h->fw64.ntopmax;
+  // the family vectors and top-row updates of the team solves (one right-hand
+  // side): [xb: p][dtopb: nparts x team x ntopmax of B][xc: q][dtopc: the same of C]
+  if (h->fw64.TB.team > 1) {
+    const TeamArrays<double>&TB = h->fw64.TB, &TC = h->fw64.TC;
+    z.team = (size_t)std::max<int64_t>(h->R.p, 1) + (size_t)h->R.nparts * TB.team * TB.ntopmax;
+    if (TC.team > 1)
+      z.team += (size_t)std::max<int64_t>(h->R.q, 1) + (size_t)h->R.nparts * TC.team * TC.ntopmax;
+  }
   // split G V^T y of the matrix-core low-rank products (BF16 V only)
   if (h->Vbr && nrhs >= kMfmaMinRhs)
     z.zp = ((size_t)h->nsys * 3 * nrhs * ((h->k + 15) / 16 * 16) * 2 + 7) / 8;
@@ -744,12 +790,25 @@ pslr_status run_apply(pslr_ctx* h, const ApplyArrays<T>& Ah, const ApplyWs& W, b
     ~Restore() { h->trace = v; }
   } restore{h, tr_on};
   Tracer tr{h, s, {}};
-  // one right-hand side in LDS: every B_i solve spread over a team of workgroups
-  const bool team = A.team > 1 && W.team && nrhs == 1 && cfg.R == 1 && !cfg.gx && !transpose;
-  T* xb = (T*)W.team;
-  T* dtop = team ? xb + std::max<int64_t>(h->R.p, 1) : nullptr;
+  // one right-hand side in LDS: every B_i (and C_i) solve spread over a team
+  // of workgroups (workspace layout as in ws_sizes)
+  const bool team = A.TB.team > 1 && W.team && nrhs == 1 && cfg.R == 1 && !cfg.gx && !transpose;
+  const bool cteam = team && A.TC.team > 1;
+  TeamWs tw{nullptr, nullptr, nullptr, nullptr};
+  if (team) {
+    T* t = (T*)W.team;
+    tw.xb = t;
+    t += std::max<int64_t>(h->R.p, 1);
+    tw.dtopb = t;
+    t += (int64_t)A.nparts * A.TB.team * A.TB.ntopmax;
+    if (cteam) {
+      tw.xc = t;
+      t += std::max<int64_t>(h->R.q, 1);
+      tw.dtopc = t;
+    }
+  }
   HIP_TRY(tr.mark(PH_START));
-  if (team) HIP_TRY(launch_head_team<T>(A, cfg, b, y, xb, dtop));
+  if (team) HIP_TRY(launch_head_team<T>(A, cfg, b, y, tw));
   else HIP_TRY(launch_head<T>(A, cfg, nrhs, b, ldb, y, q));
   HIP_TRY(tr.mark(PH_HEAD));
   // FP32 applies with V in BF16 and many right-hand sides: the low-rank
@@ -764,7 +823,10 @@ pslr_status run_apply(pslr_ctx* h, const ApplyArrays<T>& Ah, const ApplyWs& W, b
       HIP_TRY(launch_c0solve<T>(A, cfg, nrhs, y, q, ua, q));
     } else if (k > 0) {
       HIP_TRY(lowrank_partial<T>(h, y, q, nrhs, part, s));
-      HIP_TRY(lowrank_expand<T>(h, A, cfg, nrhs, 0, part, y, q, 1, ua, q));
+      HIP_TRY(lowrank_expand<T>(h, A, cfg, nrhs, 0, part, y, q, cteam ? 0 : 1, ua, q));
+      if (cteam) HIP_TRY(launch_c0_team<T>(A, cfg, y, ua, tw));
+    } else if (cteam) {
+      HIP_TRY(launch_c0_team<T>(A, cfg, y, ua, tw));
     } else {
       HIP_TRY(launch_c0solve<T>(A, cfg, nrhs, y, q, ua, q));
     }
@@ -772,7 +834,7 @@ pslr_status run_apply(pslr_ctx* h, const ApplyArrays<T>& Ah, const ApplyWs& W, b
     for (int i = 0; i < h->m; ++i) {
       LaunchCfg c1 = cfg;
       HIP_TRY(tr.span(PH_SERIES, c1));
-      if (team) HIP_TRY(launch_series_team<T>(A, c1, y, ua, ub, 1, xb, dtop));
+      if (team) HIP_TRY(launch_series_team<T>(A, c1, y, ua, ub, 1, tw));
       else HIP_TRY(launch_series<T>(A, c1, nrhs, y, q, ua, ub, q, 1, 1));
       std::swap(ua, ub);
     }
@@ -796,7 +858,7 @@ pslr_status run_apply(pslr_ctx* h, const ApplyArrays<T>& Ah, const ApplyWs& W, b
       HIP_TRY(tr.mark(PH_LOWRANK));
     }
   }
-  if (team) HIP_TRY(launch_tail_team<T>(A, cfg, b, ua, z, xb, dtop));
+  if (team) HIP_TRY(launch_tail_team<T>(A, cfg, b, ua, z, tw));
   else HIP_TRY(launch_tail<T>(A, cfg, nrhs, b, ldb, ua, q, z, ldz));
   HIP_TRY(tr.mark(PH_TAIL));
   HIP_TRY(tr.finish());
@@ -1550,6 +1612,10 @@ void fill_info(pslr_ctx* h, const std::vector<BlockFactor>& fB, const std::vecto
   const int64_t vecB = (int64_t)w * 2 * p, vecC = (int64_t)w * 2 * q;  // one gather in, one scatter out
   const int64_t series = bB + bC + bEF + bCg + vecB + vecC + (int64_t)w * 3 * q + 8 * 2 * q;
   I.series_bytes = series;
+  I.team = h->fw64.TB.team > 1 ? h->fw64.TB.team : 0;
+  I.team_top = I.team ? (h->fw64.TB.TI ? 2 : 1) : 0;
+  I.team_c = h->fw64.TC.team > 1 ? h->fw64.TC.team : 0;
+  I.team_top_c = I.team_c ? (h->fw64.TC.TI ? 2 : 1) : 0;
   const int64_t matrix = (m + 2) * bB + (m + 1) * bC + (m + 1) * bEF + m * bCg + 2 * q * k * wv +
                          k * k * w;
   const int64_t vectors = (int64_t)(m + 2) * vecB + (m + 1) * vecC + (int64_t)w * (2 * m + 3) * q +
@@ -1588,6 +1654,8 @@ void pslr_default_options(pslr_options* o) {
   o->factor = 0;
   o->drop_tol = 1e-2;
   o->lowrank = 0;
+  o->team = 0;
+  o->team_top = 0;
 }
 
 const char* pslr_status_string(pslr_status s) {
@@ -1721,7 +1789,7 @@ pslr_status pslr_host_stats(int64_t n, const int64_t* rowptr, const int32_t* col
       codes[t] = ilut_block(M, drop, o.want_transpose != 0, narrow, f, errs[t]);
       if (!codes[t]) codes[t] = ilut_factor(M, drop, I, errs[t]);
     } else {
-      codes[t] = factor_block(M, tau, o.want_transpose != 0, narrow, f, errs[t], t < nB ? team : 0);
+      codes[t] = factor_block(M, tau, o.want_transpose != 0, narrow, f, errs[t], team);
     }
     if (codes[t] || M.nrows == 0) return;
     if (f.team > 1) {
@@ -1735,15 +1803,32 @@ pslr_status pslr_host_stats(int64_t n, const int64_t* rowptr, const int32_t* col
       for (int i = 0; i < nb; ++i) X0[i] = X1[i] = std::cos(0.3 + 0.71 * i);
       host_tri_solve(f.lo, X0, true);
       host_tri_solve(f.up, X0, true);
+      std::vector<double> X2(X1);
       for (int g = 0; g <= f.team; ++g) host_tri_solve(f.loS[g], X1, true);
       host_tri_solve(f.upS[f.team], X1, true);
       for (int g = 0; g < f.team; ++g) host_tri_solve(f.upS[g], X1, true);
-      double d2 = 0.0, n2 = 0.0;
+      // the top group through its dense inverse
+      if (!f.topinv.empty()) {
+        for (int g = 0; g < f.team; ++g) host_tri_solve(f.loS[g], X2, true);
+        const int nt = f.ntop;
+        std::vector<double> d(nt + 1, 0.0);
+        for (int k = 0; k < nt; ++k) d[k] = X2[f.loS[f.team].rec[(size_t)8 * k]];
+        for (int r = 0; r < nt; ++r) {
+          double acc = 0.0;
+          for (int c = 0; c < (nt + 1) / 2; ++c)
+            acc += f.topinv[2 * ((size_t)c * nt + r)] * d[2 * c] +
+                   f.topinv[2 * ((size_t)c * nt + r) + 1] * d[2 * c + 1];
+          X2[f.loS[f.team].rec[(size_t)8 * r]] = acc;
+        }
+        for (int g = 0; g < f.team; ++g) host_tri_solve(f.upS[g], X2, true);
+      }
+      double d2 = 0.0, e2 = 0.0, n2 = 0.0;
       for (int i = 0; i < nb; ++i) {
         d2 += (X0[i] - X1[i]) * (X0[i] - X1[i]);
+        if (!f.topinv.empty()) e2 += (X0[i] - X2[i]) * (X0[i] - X2[i]);
         n2 += X0[i] * X0[i];
       }
-      tres[t] = n2 > 0 ? std::sqrt(d2 / n2) : 0.0;
+      tres[t] = n2 > 0 ? std::sqrt(std::max(d2, e2) / n2) : 0.0;
     }
     nnz[t] = f.nnz_L + f.nnz_U;
     lvl[t] = f.lo.nlev;
@@ -1936,6 +2021,7 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
   if (o.factor != 0 && o.factor != 1) return fail(PSLR_EINVAL, "factor must be 0 or 1");
   if (o.lowrank < 0 || o.lowrank > 2) return fail(PSLR_EINVAL, "lowrank must be 0, 1 or 2");
   if (o.team < 0 || o.team > 8) return fail(PSLR_EINVAL, "team must be 0 .. 8");
+  if (o.team_top < 0 || o.team_top > 2) return fail(PSLR_EINVAL, "team_top must be 0, 1 or 2");
   o.team = resolve_team(o, nparts);
   const double tau = o.pivot_threshold > 0 ? o.pivot_threshold : 0.1;
   for (int64_t k = 0; k < (n > 0 ? rowptr[n] : 0); ++k)
@@ -1998,7 +2084,7 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
     const int narrow = t < np ? kNarrowWidthB : kNarrowWidthC;
     codes[t] = o.factor == 1 ? ilut_block(M, drop, h->want_T != 0, narrow, F, errs[t])
                              : factor_block(M, tau, h->want_T != 0, narrow, F, errs[t],
-                                            t < np ? o.team : 0);
+                                            o.team);
   });
   for (int t = 0; t < 2 * np; ++t)
     if (codes[t]) return fail(codes[t] == 3 ? PSLR_ENOTSUP : PSLR_ESINGULAR,
@@ -2081,7 +2167,7 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
   h->lds_max = prop.sharedMemPerBlock > 0 ? prop.sharedMemPerBlock : 65536;
   DirHost Dfw = build_dir(h->R, Bk, fB, fC, false);
   int64_t bytes[4] = {0, 0, 0, 0};
-  HIP_TRY(upload_dir<double>(h->facpool, h->R, fB, fC, Dfw, false, d_int_ptr, d_if_ptr, d_if_orig,
+  HIP_TRY(upload_dir<double>(h->facpool, h->R, fB, fC, Dfw, false, o.team_top, d_int_ptr, d_if_ptr, d_if_orig,
                              h->fw64, bytes));
   // global workspace layout, used by applies whose subdomains do not fit in
   // LDS or that solve wide right-hand-side tiles
@@ -2131,7 +2217,7 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
   const double t3 = now_s();
 
   if (h->precision >= 1) {
-    HIP_TRY(upload_dir<float>(h->facpool, h->R, fB, fC, Dfw, false, d_int_ptr, d_if_ptr, d_if_orig,
+    HIP_TRY(upload_dir<float>(h->facpool, h->R, fB, fC, Dfw, false, o.team_top, d_int_ptr, d_if_ptr, d_if_orig,
                               h->fw32, bytes));
     set_gx(h->fw32);
     h->have32 = true;
@@ -2140,11 +2226,11 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
     DirHost Dtr = build_dir(h->R, Bk, fB, fC, true);
     int64_t tb[4];
     if (h->precision >= 1) {
-      HIP_TRY(upload_dir<float>(h->facpool, h->R, fB, fC, Dtr, true, d_int_ptr, d_if_ptr, d_if_orig,
+      HIP_TRY(upload_dir<float>(h->facpool, h->R, fB, fC, Dtr, true, 0, d_int_ptr, d_if_ptr, d_if_orig,
                                 h->tr32, tb));
       set_gx(h->tr32);
     }
-    HIP_TRY(upload_dir<double>(h->facpool, h->R, fB, fC, Dtr, true, d_int_ptr, d_if_ptr, d_if_orig,
+    HIP_TRY(upload_dir<double>(h->facpool, h->R, fB, fC, Dtr, true, 0, d_int_ptr, d_if_ptr, d_if_orig,
                                h->tr64, tb));
     set_gx(h->tr64);
     h->haveT = true;
@@ -2190,7 +2276,7 @@ pslr_status pslr_refactor(pslr_handle h, const double* vals, void* hip_stream) {
     const int narrow = t < np ? kNarrowWidthB : kNarrowWidthC;
     codes[t] = o.factor == 1 ? ilut_block(M, drop, h->want_T != 0, narrow, F, errs[t])
                              : factor_block(M, tau, h->want_T != 0, narrow, F, errs[t],
-                                            t < np ? o.team : 0);
+                                            o.team);
   });
   for (int t = 0; t < 2 * np; ++t)
     if (codes[t]) return fail(codes[t] == 3 ? PSLR_ENOTSUP : PSLR_ESINGULAR,
@@ -2217,7 +2303,7 @@ pslr_status pslr_refactor(pslr_handle h, const double* vals, void* hip_stream) {
   ApplyArrays<float> fw32{}, tr32{};
   int64_t bytes[4] = {0, 0, 0, 0}, tb[4];
   DirHost Dfw = build_dir(h->R, Bk, fB, fC, false);
-  HIP_TRY(upload_dir<double>(nf, h->R, fB, fC, Dfw, false, h->d_int_ptr, h->d_if_ptr, h->d_if_orig,
+  HIP_TRY(upload_dir<double>(nf, h->R, fB, fC, Dfw, false, o.team_top, h->d_int_ptr, h->d_if_ptr, h->d_if_orig,
                              fw64, bytes));
   const int64_t* d_rb_off = nullptr;
   int64_t gws_stride = 0;
@@ -2232,13 +2318,13 @@ pslr_status pslr_refactor(pslr_handle h, const double* vals, void* hip_stream) {
     HIP_TRY(nf.upload(rb, &d_rb_off));
     gws_stride = h->R.p + 2 * h->R.q + rb[np] + (int64_t)np * 2 * std::max(h->fw64.kmax, 1);
   }
-  if (h->have32) HIP_TRY(upload_dir<float>(nf, h->R, fB, fC, Dfw, false, h->d_int_ptr, h->d_if_ptr,
+  if (h->have32) HIP_TRY(upload_dir<float>(nf, h->R, fB, fC, Dfw, false, o.team_top, h->d_int_ptr, h->d_if_ptr,
                                            h->d_if_orig, fw32, bytes));
   if (h->haveT) {
     DirHost Dtr = build_dir(h->R, Bk, fB, fC, true);
-    if (h->have32) HIP_TRY(upload_dir<float>(nf, h->R, fB, fC, Dtr, true, h->d_int_ptr, h->d_if_ptr,
+    if (h->have32) HIP_TRY(upload_dir<float>(nf, h->R, fB, fC, Dtr, true, 0, h->d_int_ptr, h->d_if_ptr,
                                              h->d_if_orig, tr32, tb));
-    HIP_TRY(upload_dir<double>(nf, h->R, fB, fC, Dtr, true, h->d_int_ptr, h->d_if_ptr, h->d_if_orig,
+    HIP_TRY(upload_dir<double>(nf, h->R, fB, fC, Dtr, true, 0, h->d_int_ptr, h->d_if_ptr, h->d_if_orig,
                                tr64, tb));
   }
   // the launch settings of the old arrays carry over (autotuned chunk scale)

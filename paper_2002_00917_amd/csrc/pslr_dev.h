@@ -49,6 +49,22 @@ struct DevCsr {
   const T* val;
 };
 
+// Team split of one family of diagonal blocks (B_i or C_i): the supernodal
+// tree of every block cut into `team` groups of whole subtrees and a top
+// group (see BlockFactor::loS/upS).  L / U hold group g of block i at index
+// i * (team + 1) + g, the top group at g = team; ntopmax: the most top rows
+// of any block.  TI: the dense inverses of the top groups (null: the top
+// group runs its packed factors), block i's at TI + ti_off[i] in the
+// column-pair layout of BlockFactor::topinv, nrb workgroups of 64 top rows
+// per block.  team = 0: no split.
+template <typename T>
+struct TeamArrays {
+  TriArrays<T> L, U;
+  int32_t team, ntopmax, nrb;
+  const T* TI;
+  const int64_t* ti_off;
+};
+
 // Everything one direction (forward or transposed) of the apply needs.
 template <typename T>
 struct ApplyArrays {
@@ -78,12 +94,8 @@ struct ApplyArrays {
   // optional (system, rhs) mask, index r * nsys + s: a block skips its work for
   // right-hand side r when its system's entry is 0 (converged FGMRES columns)
   const uint8_t* active;
-  // team split of the B_i solves (team > 1): the lower and upper factors of
-  // B_i restricted to subtree group g at block index i * (team + 1) + g, the
-  // top group at g = team (see BlockFactor::loS); ntopmax: the most top rows
-  // of any block
-  TriArrays<T> LBs, UBs;
-  int32_t team, ntopmax;
+  // team splits of the single-right-hand-side B_i and C_i solves
+  TeamArrays<T> TB, TC;
 };
 
 // A row chunk of the interface vectors for the V^T y partial sums; chunks never
@@ -168,23 +180,34 @@ hipError_t launch_tail(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, co
                        int64_t ldb, const T* u, int64_t ldu, double* z, int64_t ldz);
 template <typename T>
 hipError_t set_lds_limit(size_t bytes);
-// The B_i solves of one right-hand side spread over A.team workgroups per
-// subdomain (working vectors in LDS): three launches (subtree lower solves,
-// the top group's lower and upper solves, subtree upper solves) with the
-// interior vector xb (p values) and the top rows' pushed updates dtop
-// (nparts * team * ntopmax values) in global memory between them.
-//   series step: unext = C0^{-1}(y [add_y] - C_g u + F B^{-1} E u)  (+ a fourth launch)
-//   head:        y = g - F B^{-1} f                                (+ a fourth launch)
+// Solves of one right-hand side spread over the team of workgroups of each
+// block (working vectors in LDS), three launches per family: the subtree
+// groups' lower solves, the top group, the groups' upper solves.  Between the
+// launches the family's vector and the top rows' pushed updates live in the
+// workspace TeamWs.
+struct TeamWs {
+  void* xb;     // p values: the B-solve vector
+  void* dtopb;  // nparts * TB.team * TB.ntopmax values
+  void* xc;     // q values: the C0-solve vector
+  void* dtopc;  // nparts * TC.team * TC.ntopmax values
+};
+//   series step: unext = C0^{-1}(y [add_y] - C_g u + F B^{-1} E u)  (C0 solve split when
+//                A.TC.team > 1, else one workgroup per subdomain)
+//   head:        y = g - F B^{-1} f                                (+ a launch for F)
 //   tail:        z = P^T (B^{-1}(f - E u); u)
+//   c0:          dst = C0^{-1} src                                 (A.TC.team > 1 only)
 template <typename T>
 hipError_t launch_series_team(const ApplyArrays<T>& A, const LaunchCfg& c, const T* y,
-                              const T* uprev, T* unext, int add_y, T* xb, T* dtop);
+                              const T* uprev, T* unext, int add_y, const TeamWs& W);
 template <typename T>
 hipError_t launch_head_team(const ApplyArrays<T>& A, const LaunchCfg& c, const double* b, T* y,
-                            T* xb, T* dtop);
+                            const TeamWs& W);
 template <typename T>
 hipError_t launch_tail_team(const ApplyArrays<T>& A, const LaunchCfg& c, const double* b,
-                            const T* u, double* z, T* xb, T* dtop);
+                            const T* u, double* z, const TeamWs& W);
+template <typename T>
+hipError_t launch_c0_team(const ApplyArrays<T>& A, const LaunchCfg& c, const T* src, T* dst,
+                          const TeamWs& W);
 
 // ---- FP64 vector kernels for Arnoldi and FGMRES
 hipError_t launch_spmv(int64_t n, const int64_t* ptr, const int32_t* col, const double* val,

@@ -973,6 +973,13 @@ int factor_block(const CsrL& M, double tau, bool want_T, int narrow_width, Block
       return 3;
     }
   }
+  if (team > 1) {
+    out.ntop = out.loS[team].nlev > 0 ? out.loS[team].lev_ptr[out.loS[team].nlev] : 0;
+    if (out.ntop <= kTopInvMaxRows && !top_inverse(out.loS[team], out.upS[team], n, out.topinv)) {
+      err = "team split: the top group reaches outside itself";
+      return 3;
+    }
+  }
   if (want_T) {
     {
       TriHost T;
@@ -1141,8 +1148,15 @@ bool pack_tri(const TriHost& T, TriPacked& P, int narrow_width) {
                            : chunks_for(cnt, cnt ? panel_len / cnt : 0.0);
     P.lev_c[l] = ct | (cp << 8) | ((ent ? 1 : 0) << 16);
   }
-  int64_t tri_vals = 0;  // triangle entries without the pair padding
-  for (const SnHost& S : T.sn) tri_vals += (int64_t)S.w * (S.w + 1) / 2;
+  // triangle entries without the pair padding, of the supernodes scheduled
+  // here (a team group packs a subset of the block's supernodes)
+  int64_t tri_vals = 0;
+  for (int l = 0; l < T.nlev; ++l)
+    for (int k = T.lev_ptr[l]; k < T.lev_ptr[l + 1];) {
+      const SnHost& S = T.sn[T.row_sn[T.lrows[k]]];
+      tri_vals += (int64_t)S.w * (S.w + 1) / 2;
+      k += S.w;
+    }
   for (int q = 0; q < 2; ++q) {
     P.read_vals[q] += tri_vals;
     P.read_ints[q] += (int64_t)P.rec.size() + 4 * (int64_t)(T.nlev + 1);
@@ -1216,6 +1230,90 @@ void host_tri_solve(const TriPacked& T, std::vector<double>& X, bool entries) {
       }
     }
   }
+}
+
+// Dense inverse of the top group's diagonal block of L U (see BlockFactor::
+// topinv): the packed top-group solves of host_tri_solve applied to all ntop
+// unit vectors at once, every scalar operation of the sequential algorithm
+// becoming an operation on a row of ntop right-hand sides.
+bool top_inverse(const TriPacked& lo, const TriPacked& up, int n, std::vector<double>& M) {
+  const int nt = lo.nlev > 0 ? lo.lev_ptr[lo.nlev] : 0;
+  M.clear();
+  if (nt == 0) return true;
+  std::vector<int> loc(n, -1);
+  for (int k = 0; k < nt; ++k) loc[lo.rec[(size_t)8 * k]] = k;
+  auto L = [&](int p) {
+    const int k = p >= 0 && p < n ? loc[p] : -1;
+    return k;
+  };
+  std::vector<double> X((size_t)nt * nt, 0.0);
+  for (int k = 0; k < nt; ++k) X[(size_t)k * nt + k] = 1.0;
+  const int mr = std::max(std::max(lo.max_lrows, up.max_lrows), 1);
+  std::vector<double> Rb((size_t)mr * nt);
+  std::vector<double> acc(nt);
+  auto row = [&](int p) -> double* {
+    const int k = L(p);
+    return k < 0 ? nullptr : &X[(size_t)k * nt];
+  };
+  auto axpy = [&](double* y, double a, const double* x) {
+    if (a != 0.0)
+      for (int c = 0; c < nt; ++c) y[c] += a * x[c];
+  };
+  for (int li = 0; li < lo.nlev; ++li) {
+    const int b = lo.lev_ptr[li], e = lo.lev_ptr[li + 1];
+    for (int k = b; k < e; ++k) {
+      const int32_t* r = &lo.rec[(size_t)8 * k];
+      const int p = r[0], i = r[1], w = r[2];
+      std::fill(acc.begin(), acc.end(), 0.0);
+      for (int j = 0; j <= i; ++j) {
+        const double* xj = row(p - i + j);
+        if (!xj) return false;
+        axpy(acc.data(), lo.tri[r[4] + 2 * tri_pair_lower(i, j, w) + (j & 1)], xj);
+      }
+      std::copy(acc.begin(), acc.end(), &Rb[(size_t)(k - b) * nt]);
+    }
+    for (int k = b; k < e; ++k) std::copy(&Rb[(size_t)(k - b) * nt], &Rb[(size_t)(k - b + 1) * nt],
+                                          row(lo.rec[(size_t)8 * k]));
+    for (int m = lo.push_ptr[li]; m < lo.push_ptr[li + 1]; ++m) {
+      const int32_t* q = &lo.prec[(size_t)4 * m];
+      const int w = q[2] & 0xffff, h = q[2] >> 16;
+      double* xd = row(q[0]);
+      if (!xd) return false;
+      for (int j = 0; j < w; ++j)
+        axpy(xd, -lo.val[2 * (q[1] + (int64_t)(j >> 1) * h) + (j & 1)], &Rb[(size_t)(q[3] + j) * nt]);
+    }
+  }
+  for (int li = 0; li < up.nlev; ++li) {
+    const int l = up.nlev - 1 - li;
+    const int b = up.lev_ptr[l], e = up.lev_ptr[l + 1];
+    for (int k = b; k < e; ++k) {
+      const int32_t* r = &up.rec[(size_t)8 * k];
+      const int i = r[1], w = r[2], h = r[3];
+      const double* xp = row(r[0]);
+      if (!xp) return false;
+      double* rk = &Rb[(size_t)(k - b) * nt];
+      std::copy(xp, xp + nt, rk);
+      for (int a = 0; a < h; ++a) {
+        const double* xa = row(up.ridx[r[6] + a]);
+        if (!xa) return false;
+        axpy(rk, -up.val[r[5] + 2 * ((int64_t)(a >> 1) * w + i) + (a & 1)], xa);
+      }
+    }
+    for (int k = b; k < e; ++k) {
+      const int32_t* r = &up.rec[(size_t)8 * k];
+      const int i = r[1], w = r[2];
+      std::fill(acc.begin(), acc.end(), 0.0);
+      for (int j = i; j < w; ++j)
+        axpy(acc.data(), up.tri[r[4] + 2 * tri_pair_upper(i, j) + (j & 1)], &Rb[(size_t)(r[7] + j) * nt]);
+      std::copy(acc.begin(), acc.end(), row(r[0]));
+    }
+  }
+  // column pairs: (r, j) at 2 ((j / 2) nt + r) + (j % 2); an odd last column pairs with zeros
+  const int np = (nt + 1) / 2;
+  M.assign((size_t)2 * np * nt, 0.0);
+  for (int r = 0; r < nt; ++r)
+    for (int j = 0; j < nt; ++j) M[2 * ((size_t)(j >> 1) * nt + r) + (j & 1)] = X[(size_t)r * nt + j];
+  return true;
 }
 
 // ---------------------------------------------------------------------------

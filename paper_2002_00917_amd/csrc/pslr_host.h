@@ -146,6 +146,15 @@ struct BlockFactor {
   // the top group's upper solve reads top rows only.
   int32_t team = 0;
   std::vector<TriPacked> loS, upS;
+  // Dense inverse of the top group's block of L U (team > 1, top group of at
+  // most kTopInvMaxRows rows; empty otherwise).  Positions of the top group in
+  // the order of loS[team]'s row records, T; the top group holds every
+  // ancestor of its supernodes, so L[G, T] = 0 and U[T, G] = 0 for the other
+  // positions G, and the solve gives x_T = (L_TT U_TT)^{-1} (b_T - L_TG y_G)
+  // with y_G the subtrees' lower solves.  Column pairs: entry (r, j) at
+  // 2 ((j / 2) ntop + r) + (j % 2), an odd last column paired with zeros.
+  std::vector<double> topinv;
+  int32_t ntop = 0;
   int64_t nnz_L = 0, nnz_U = 0;   // entries of L and U (diagonal blocks included)
   int32_t nsuper = 0;
 };
@@ -229,6 +238,14 @@ void parallel_for(int count, int nthreads, const std::function<void(int)>& fn);
 // fewer than narrow_width rows also get the entry form); false if a supernode exceeds the
 // record field widths (w or h above 32767) or a block's arrays exceed 2^31.
 bool pack_tri(const TriHost& T, TriPacked& P, int narrow_width);
+
+// Largest top group stored as a dense inverse (8 MiB of FP64 per block).
+constexpr int kTopInvMaxRows = 1024;
+
+// The dense inverse of BlockFactor::topinv from the top group's packed lower
+// and upper factors of a block of n positions; false when a record reaches a
+// position outside the top group.
+bool top_inverse(const TriPacked& lo, const TriPacked& up, int n, std::vector<double>& M);
 
 // Host execution of a packed factor on one vector (diagnostics only).
 // entries: use the entry form where a level has one (else the panels).

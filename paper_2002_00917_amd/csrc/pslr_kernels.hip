@@ -982,27 +982,85 @@ __global__ void __launch_bounds__(1024) k_tail(ApplyArrays<T> A, int nrhs, const
   }
 }
 
-// ---- B_i solves spread over a team of workgroups (one right-hand side,
-// working vectors in LDS).  The supernodal tree of every B_i is cut into
+// ---- Team solves (one right-hand side, working vectors in LDS).  The
+// supernodal tree of every B_i (family 0) and C_i (family 1) is cut into
 // `team` groups of whole subtrees and a top group (BlockFactor::loS/upS).
-// Workgroup (i, g) solves group g's rows: its lower solve pushes into the
-// top rows of its own LDS copy (started at zero), which go to dtop; one
-// workgroup per subdomain then solves the top group (lower and upper) from
-// the right-hand side plus the team's pushes; the team then runs its upper
-// solves, pulling the top rows.  Between the launches the interior vector
-// lives in xb.  MODE: 0 power-series step (right-hand side E u), 1 head
-// (f gathered from b), 2 tail (f - E u; results scattered to z).
+// Launch 1, workgroup (i, g): group g's rows from the right-hand side and its
+// lower solve on an LDS copy whose top rows start at zero; the group's rows
+// go to the family vector xw, its pushes into the top rows to dtop.  Launch
+// 2: the top group from its right-hand side plus the pushes, by its packed
+// lower and upper solves (one workgroup per block) or by its dense inverse
+// (one workgroup per 64 top rows).  Launch 3, workgroup (i, g): group g's
+// upper solve, pulling the top rows.
+//
+// Right-hand sides and results by family and MODE:
+//   B, 0 (power-series step): E u                  x to xb
+//   B, 1 (head):              f gathered from b    x to xb
+//   B, 2 (tail):              f - E u              x to z (top rows also to xb)
+//   C, 0 (power-series step): [y] - C_g u + F xb   x to out (top rows also to xc)
+//   C, 1 (C0 solve):          y                    x to out (top rows also to xc)
+template <typename T>
+struct TeamIO {
+  const double* b;  // B modes 1, 2
+  const T* u;       // B modes 0, 2: interface vector; C mode 0: u of the previous step
+  const T* y;       // C: [y] of mode 0, the vector solved in mode 1
+  const T* xb;      // C mode 0: B^{-1} E u
+  T* xw;            // the family's vector between the launches
+  T* dtop;          // nparts x team x ntopmax pushes into the top rows
+  double* z;        // B mode 2
+  T* out;           // C: the result
+  int add_y;
+};
 
-template <typename T, int MODE>
-__device__ __forceinline__ T team_rhs(const ApplyArrays<T>& A, int64_t row, const T* U,
-                                      const double* __restrict__ b) {
-  T acc = MODE == 0 ? (T)0 : (T)b[A.gB_in[row]];
-  if (MODE != 1)
-    for (int64_t q = A.Ein.ptr[row]; q < A.Ein.ptr[row + 1]; ++q) {
-      const T v = A.Ein.val[q] * U[A.Ein.col[q]];
-      acc = MODE == 0 ? acc + v : acc - v;
-    }
-  return acc;
+template <typename T, int FAM>
+__device__ __forceinline__ const TeamArrays<T>& team_fam(const ApplyArrays<T>& A) {
+  return FAM == 0 ? A.TB : A.TC;
+}
+
+// first position of block i in the family's vectors
+template <typename T, int FAM>
+__device__ __forceinline__ int64_t team_base(const ApplyArrays<T>& A, int i) {
+  return FAM == 0 ? A.int_ptr[i] : A.if_ptr[i];
+}
+
+// right-hand side of position p of block i (base: team_base); U: block i's
+// interface values (B modes 0 and 2)
+template <typename T, int FAM, int MODE>
+__device__ __forceinline__ T team_rhs(const ApplyArrays<T>& A, const TeamIO<T>& io, int i, int64_t base,
+                                      int p, const T* U) {
+  if (FAM == 0) {
+    const int64_t row = base + p;
+    T acc = MODE == 0 ? (T)0 : (T)io.b[A.gB_in[row]];
+    if (MODE != 1)
+      for (int64_t q = A.Ein.ptr[row]; q < A.Ein.ptr[row + 1]; ++q) {
+        const T v = A.Ein.val[q] * U[A.Ein.col[q]];
+        acc = MODE == 0 ? acc + v : acc - v;
+      }
+    return acc;
+  } else {
+    const int64_t row = base + A.gC_in[base + p];
+    if (MODE == 1) return io.y[row];
+    T acc = io.add_y ? io.y[row] : (T)0;
+    for (int64_t q = A.Cg.ptr[row]; q < A.Cg.ptr[row + 1]; ++q) acc -= A.Cg.val[q] * io.u[A.Cg.col[q]];
+    const int64_t i0 = A.int_ptr[i];
+    for (int64_t q = A.Fout.ptr[row]; q < A.Fout.ptr[row + 1]; ++q)
+      acc += A.Fout.val[q] * io.xb[i0 + A.Fout.col[q]];
+    return acc;
+  }
+}
+
+// the solved value x of position p (top: a top-group row, which the upper
+// solves read back from xw)
+template <typename T, int FAM, int MODE>
+__device__ __forceinline__ void team_out(const ApplyArrays<T>& A, const TeamIO<T>& io, int64_t base, int p,
+                                         T x, bool top) {
+  if (FAM == 0) {
+    if (MODE == 2) io.z[A.gB_out[base + p]] = (double)x;
+    if (MODE != 2 || top) io.xw[base + p] = x;
+  } else {
+    io.out[base + A.gC_out[base + p]] = x;
+    if (top) io.xw[base + p] = x;
+  }
 }
 
 // rows (positions) of group g of block bi in a team family, in level order
@@ -1013,111 +1071,179 @@ __device__ __forceinline__ int team_rows(const TriArrays<T>& F, int bi, const in
   return B.nlev > 0 ? F.lev_ptr[B.lev_base + B.nlev] : 0;
 }
 
-template <typename T, int MODE>
-__global__ void __launch_bounds__(1024) k_team_lower(ApplyArrays<T> A, const double* __restrict__ b,
-                                                     const T* __restrict__ u, T* xb, T* dtop,
-                                                     double* z) {
-  const int team = A.team;
+// block i's interface values into LDS (B modes 0, 2); the tail's group 0 also
+// writes them to z
+template <typename T, int FAM, int MODE>
+__device__ __forceinline__ void team_load_u(const ApplyArrays<T>& A, const TeamIO<T>& io, int i, T* U,
+                                            bool write_z) {
+  if (FAM != 0 || MODE == 1) return;
+  const int64_t f0 = A.if_ptr[i], qi = A.if_ptr[i + 1] - f0;
+  for (int64_t kk = threadIdx.x; kk < qi; kk += blockDim.x) {
+    const T v = io.u[f0 + kk];
+    U[kk] = v;
+    if (MODE == 2 && write_z) io.z[A.if_orig[f0 + kk]] = (double)v;
+  }
+  __syncthreads();
+}
+
+template <typename T, int FAM, int MODE>
+__global__ void __launch_bounds__(1024) k_team_lower(ApplyArrays<T> A, TeamIO<T> io) {
+  const TeamArrays<T>& TA = team_fam<T, FAM>(A);
+  const int team = TA.team;
   const int i = blockIdx.x / team, g = blockIdx.x - i * team, tid = threadIdx.x, nt = blockDim.x;
   int r0, nr;
   if (!tile_rhs<T, 1>(A, 1, i, r0, nr)) return;
   Lds<T> L = carve<T, 1, false>(A);
-  const int64_t i0 = A.int_ptr[i];
-  const int64_t f0 = A.if_ptr[i], qi = A.if_ptr[i + 1] - f0;
-  if (MODE != 1) {
-    for (int64_t kk = tid; kk < qi; kk += nt) {
-      const T v = u[f0 + kk];
-      L.U[kk] = v;
-      if (MODE == 2 && g == 0) z[A.if_orig[f0 + kk]] = (double)v;
-    }
-    __syncthreads();
-  }
+  T* X = FAM == 0 ? L.XB : L.XC;
+  const int64_t base = team_base<T, FAM>(A, i);
+  team_load_u<T, FAM, MODE>(A, io, i, L.U, g == 0);
   const int bs = i * (team + 1);
   const int4 *ro, *rt;
-  const int nown = team_rows(A.LBs, bs + g, ro), ntop = team_rows(A.LBs, bs + team, rt);
+  const int nown = team_rows(TA.L, bs + g, ro), ntop = team_rows(TA.L, bs + team, rt);
   for (int k = tid; k < nown; k += nt) {
     const int p = ro[2 * k].x;
-    L.XB[p] = team_rhs<T, MODE>(A, i0 + p, L.U, b);
+    X[p] = team_rhs<T, FAM, MODE>(A, io, i, base, p, L.U);
   }
-  for (int k = tid; k < ntop; k += nt) L.XB[rt[2 * k].x] = (T)0;
+  for (int k = tid; k < ntop; k += nt) X[rt[2 * k].x] = (T)0;
   __syncthreads();
-  tri_solve<T, 1, false>(A.LBs, bs + g, L.XB, L.Rb, A.gshift);
+  tri_solve<T, 1, false>(TA.L, bs + g, X, L.Rb, A.gshift);
   __syncthreads();
   for (int k = tid; k < nown; k += nt) {
     const int p = ro[2 * k].x;
-    xb[i0 + p] = L.XB[p];
+    io.xw[base + p] = X[p];
   }
-  T* d = dtop + ((int64_t)i * team + g) * A.ntopmax;
-  for (int k = tid; k < ntop; k += nt) d[k] = L.XB[rt[2 * k].x];
+  T* d = io.dtop + ((int64_t)i * team + g) * TA.ntopmax;
+  for (int k = tid; k < ntop; k += nt) d[k] = X[rt[2 * k].x];
 }
 
-template <typename T, int MODE>
-__global__ void __launch_bounds__(1024) k_team_top(ApplyArrays<T> A, const double* __restrict__ b,
-                                                   const T* __restrict__ u, T* xb,
-                                                   const T* __restrict__ dtop, double* z) {
-  const int team = A.team;
+// the top group by its packed factors, one workgroup per block
+template <typename T, int FAM, int MODE>
+__global__ void __launch_bounds__(1024) k_team_top(ApplyArrays<T> A, TeamIO<T> io) {
+  const TeamArrays<T>& TA = team_fam<T, FAM>(A);
+  const int team = TA.team;
   const int i = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
   int r0, nr;
   if (!tile_rhs<T, 1>(A, 1, i, r0, nr)) return;
   Lds<T> L = carve<T, 1, false>(A);
-  const int64_t i0 = A.int_ptr[i];
-  const int64_t f0 = A.if_ptr[i], qi = A.if_ptr[i + 1] - f0;
-  if (MODE != 1) {
-    for (int64_t kk = tid; kk < qi; kk += nt) L.U[kk] = u[f0 + kk];
-    __syncthreads();
-  }
+  T* X = FAM == 0 ? L.XB : L.XC;
+  const int64_t base = team_base<T, FAM>(A, i);
+  team_load_u<T, FAM, MODE>(A, io, i, L.U, false);
   const int bs = i * (team + 1);
   const int4* rt;
-  const int ntop = team_rows(A.LBs, bs + team, rt);
-  const T* d = dtop + (int64_t)i * team * A.ntopmax;
+  const int ntop = team_rows(TA.L, bs + team, rt);
+  const T* d = io.dtop + (int64_t)i * team * TA.ntopmax;
   for (int k = tid; k < ntop; k += nt) {
     const int p = rt[2 * k].x;
-    T acc = team_rhs<T, MODE>(A, i0 + p, L.U, b);
-    for (int t = 0; t < team; ++t) acc += d[(int64_t)t * A.ntopmax + k];
-    L.XB[p] = acc;
+    T acc = team_rhs<T, FAM, MODE>(A, io, i, base, p, L.U);
+    for (int t = 0; t < team; ++t) acc += d[(int64_t)t * TA.ntopmax + k];
+    X[p] = acc;
   }
   __syncthreads();
-  tri_solve<T, 1, false>(A.LBs, bs + team, L.XB, L.Rb, A.gshift);
-  tri_solve<T, 1, false>(A.UBs, bs + team, L.XB, L.Rb, A.gshift);
+  tri_solve<T, 1, false>(TA.L, bs + team, X, L.Rb, A.gshift);
+  tri_solve<T, 1, false>(TA.U, bs + team, X, L.Rb, A.gshift);
   __syncthreads();
   for (int k = tid; k < ntop; k += nt) {
     const int p = rt[2 * k].x;
-    if (MODE == 2) z[A.gB_out[i0 + p]] = (double)L.XB[p];
-    else xb[i0 + p] = L.XB[p];
-    if (MODE == 2) xb[i0 + p] = L.XB[p];
+    team_out<T, FAM, MODE>(A, io, base, p, X[p], true);
   }
 }
 
-template <typename T, int MODE>
-__global__ void __launch_bounds__(1024) k_team_upper(ApplyArrays<T> A, T* xb, double* z) {
-  const int team = A.team;
+// The top group through its dense inverse: workgroup (i, rb) forms the
+// top-group right-hand side d (the rows' own terms plus the subtrees'
+// pushes) and the 64 rows rb * 64 .. of x_T = M_i d, the waves splitting the
+// column pairs and meeting in LDS.  Lane l of a wave reads row rb * 64 + l of
+// a column pair: 64 consecutive pairs, one coalesced load per pair.
+constexpr int kTopRows = 64;
+
+template <typename T, int FAM, int MODE>
+__global__ void __launch_bounds__(1024) k_team_topinv(ApplyArrays<T> A, TeamIO<T> io) {
+  using P2 = typename Pair<T>::type;
+  const TeamArrays<T>& TA = team_fam<T, FAM>(A);
+  const int team = TA.team, nrb = TA.nrb;
+  const int i = blockIdx.x / nrb, rb = blockIdx.x - i * nrb, tid = threadIdx.x, nt = blockDim.x;
+  int r0, nr;
+  if (!tile_rhs<T, 1>(A, 1, i, r0, nr)) return;
+  const int4* rt;
+  const int ntop = team_rows(TA.L, i * (team + 1) + team, rt);
+  if (rb * kTopRows >= ntop) return;  // uniform over the workgroup
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* D = reinterpret_cast<T*>(smem);          // ntopmax + 2
+  T* Ps = D + ((TA.ntopmax + 2 + 1) & ~1);    // (nt / 64) x 64 partial sums
+  const int64_t base = team_base<T, FAM>(A, i);
+  const T* U = FAM == 0 && MODE != 1 ? io.u + A.if_ptr[i] : nullptr;
+  const T* d = io.dtop + (int64_t)i * team * TA.ntopmax;
+  for (int k = tid; k < ntop; k += nt) {
+    T acc = team_rhs<T, FAM, MODE>(A, io, i, base, rt[2 * k].x, U);
+    for (int t = 0; t < team; ++t) acc += d[(int64_t)t * TA.ntopmax + k];
+    D[k] = acc;
+  }
+  if (tid == 0) D[ntop] = (T)0;  // partner of an odd last column
+  __syncthreads();
+  const int wv = tid >> 6, lane = tid & 63, nw = nt >> 6;
+  const int row = rb * kTopRows + lane;
+  const int npair = (ntop + 1) >> 1;
+  const P2* M = reinterpret_cast<const P2*>(TA.TI + TA.ti_off[i]);
+  T acc = (T)0;
+  if (row < ntop) {
+    constexpr int UN = 4;
+    for (int c = wv; c < npair; c += UN * nw) {
+      // every slot loads (a slot past the end re-reads pair c); the extra
+      // products are dropped
+      P2 v[UN];
+#pragma unroll
+      for (int s = 0; s < UN; ++s) {
+        const int cs = c + s * nw < npair ? c + s * nw : c;
+        v[s] = M[(int64_t)cs * ntop + row];
+      }
+#pragma unroll
+      for (int s = 0; s < UN; ++s) {
+        const int cs = c + s * nw < npair ? c + s * nw : c;
+        const T a = v[s].x * D[2 * cs] + v[s].y * D[2 * cs + 1];
+        acc += c + s * nw < npair ? a : (T)0;
+      }
+    }
+  }
+  Ps[wv * kTopRows + lane] = acc;
+  __syncthreads();
+  if (wv == 0 && row < ntop) {
+    T x = (T)0;
+    for (int w = 0; w < nw; ++w) x += Ps[w * kTopRows + lane];
+    team_out<T, FAM, MODE>(A, io, base, rt[2 * row].x, x, true);
+  }
+}
+
+template <typename T, int FAM, int MODE>
+__global__ void __launch_bounds__(1024) k_team_upper(ApplyArrays<T> A, TeamIO<T> io) {
+  const TeamArrays<T>& TA = team_fam<T, FAM>(A);
+  const int team = TA.team;
   const int i = blockIdx.x / team, g = blockIdx.x - i * team, tid = threadIdx.x, nt = blockDim.x;
   int r0, nr;
   if (!tile_rhs<T, 1>(A, 1, i, r0, nr)) return;
   Lds<T> L = carve<T, 1, false>(A);
-  const int64_t i0 = A.int_ptr[i];
+  T* X = FAM == 0 ? L.XB : L.XC;
+  const int64_t base = team_base<T, FAM>(A, i);
   const int bs = i * (team + 1);
   const int4 *ro, *rt;
-  const int nown = team_rows(A.UBs, bs + g, ro), ntop = team_rows(A.UBs, bs + team, rt);
+  const int nown = team_rows(TA.U, bs + g, ro), ntop = team_rows(TA.U, bs + team, rt);
   for (int k = tid; k < nown; k += nt) {
     const int p = ro[2 * k].x;
-    L.XB[p] = xb[i0 + p];
+    X[p] = io.xw[base + p];
   }
   for (int k = tid; k < ntop; k += nt) {
     const int p = rt[2 * k].x;
-    L.XB[p] = xb[i0 + p];
+    X[p] = io.xw[base + p];
   }
   __syncthreads();
-  tri_solve<T, 1, false>(A.UBs, bs + g, L.XB, L.Rb, A.gshift);
+  tri_solve<T, 1, false>(TA.U, bs + g, X, L.Rb, A.gshift);
   __syncthreads();
   for (int k = tid; k < nown; k += nt) {
     const int p = ro[2 * k].x;
-    if (MODE == 2) z[A.gB_out[i0 + p]] = (double)L.XB[p];
-    else xb[i0 + p] = L.XB[p];
+    team_out<T, FAM, MODE>(A, io, base, p, X[p], false);
   }
 }
 
-// the C0 part of a power-series step with t = B^{-1} E u read from xb
+// the C0 part of a power-series step with t = B^{-1} E u read from xb, one
+// workgroup per subdomain (C_i without a team split)
 template <typename T>
 __global__ void __launch_bounds__(1024) k_team_c0(ApplyArrays<T> A, const T* __restrict__ y,
                                                   const T* __restrict__ uprev, T* unext,
@@ -1203,15 +1329,21 @@ hipError_t set_lds_limit(size_t bytes) {
 #undef PSLR_SETATTR
 #define PSLR_SETATTR_TEAM(K)                                                                         \
   if ((e = hipFuncSetAttribute((const void*)K, hipFuncAttributeMaxDynamicSharedMemorySize, b))) return e;
-  PSLR_SETATTR_TEAM((k_team_lower<T, 0>))
-  PSLR_SETATTR_TEAM((k_team_lower<T, 1>))
-  PSLR_SETATTR_TEAM((k_team_lower<T, 2>))
-  PSLR_SETATTR_TEAM((k_team_top<T, 0>))
-  PSLR_SETATTR_TEAM((k_team_top<T, 1>))
-  PSLR_SETATTR_TEAM((k_team_top<T, 2>))
-  PSLR_SETATTR_TEAM((k_team_upper<T, 0>))
-  PSLR_SETATTR_TEAM((k_team_upper<T, 1>))
-  PSLR_SETATTR_TEAM((k_team_upper<T, 2>))
+  PSLR_SETATTR_TEAM((k_team_lower<T, 0, 0>))
+  PSLR_SETATTR_TEAM((k_team_lower<T, 0, 1>))
+  PSLR_SETATTR_TEAM((k_team_lower<T, 0, 2>))
+  PSLR_SETATTR_TEAM((k_team_lower<T, 1, 0>))
+  PSLR_SETATTR_TEAM((k_team_lower<T, 1, 1>))
+  PSLR_SETATTR_TEAM((k_team_top<T, 0, 0>))
+  PSLR_SETATTR_TEAM((k_team_top<T, 0, 1>))
+  PSLR_SETATTR_TEAM((k_team_top<T, 0, 2>))
+  PSLR_SETATTR_TEAM((k_team_top<T, 1, 0>))
+  PSLR_SETATTR_TEAM((k_team_top<T, 1, 1>))
+  PSLR_SETATTR_TEAM((k_team_upper<T, 0, 0>))
+  PSLR_SETATTR_TEAM((k_team_upper<T, 0, 1>))
+  PSLR_SETATTR_TEAM((k_team_upper<T, 0, 2>))
+  PSLR_SETATTR_TEAM((k_team_upper<T, 1, 0>))
+  PSLR_SETATTR_TEAM((k_team_upper<T, 1, 1>))
   PSLR_SETATTR_TEAM((k_team_c0<T>))
 #undef PSLR_SETATTR_TEAM
   return hipSuccess;
@@ -1331,47 +1463,112 @@ hipError_t launch_tail(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, co
   return hipGetLastError();
 }
 
+// the three launches of a team solve of family FAM; ev0 / ev1 (may be null)
+// are recorded at the start of the first and the end of the last launch
+template <typename T, int FAM, int MODE>
+void launch_team(const ApplyArrays<T>& A, const LaunchCfg& c, const TeamIO<T>& io, hipEvent_t ev0,
+                 hipEvent_t ev1) {
+  const TeamArrays<T>& TA = FAM == 0 ? A.TB : A.TC;
+  const dim3 gt((unsigned)(A.nparts * TA.team)), bt(c.threads);
+  if (ev0)
+    hipExtLaunchKernelGGL((k_team_lower<T, FAM, MODE>), gt, bt, (uint32_t)c.lds, c.stream, ev0, nullptr, 0,
+                          A, io);
+  else
+    hipLaunchKernelGGL((k_team_lower<T, FAM, MODE>), gt, bt, c.lds, c.stream, A, io);
+  if (TA.TI) {
+    const size_t lds = sizeof(T) * ((size_t)((TA.ntopmax + 3) & ~1) + (size_t)(c.threads / 64) * kTopRows);
+    hipLaunchKernelGGL((k_team_topinv<T, FAM, MODE>), dim3((unsigned)(A.nparts * TA.nrb)), bt, lds, c.stream,
+                       A, io);
+  } else {
+    hipLaunchKernelGGL((k_team_top<T, FAM, MODE>), dim3((unsigned)A.nparts), bt, c.lds, c.stream, A, io);
+  }
+  if (ev1)
+    hipExtLaunchKernelGGL((k_team_upper<T, FAM, MODE>), gt, bt, (uint32_t)c.lds, c.stream, nullptr, ev1, 0,
+                          A, io);
+  else
+    hipLaunchKernelGGL((k_team_upper<T, FAM, MODE>), gt, bt, c.lds, c.stream, A, io);
+}
+
+template <typename T>
+TeamIO<T> team_io() {
+  TeamIO<T> io;
+  io.b = nullptr;
+  io.u = io.y = io.xb = nullptr;
+  io.xw = io.dtop = io.out = nullptr;
+  io.z = nullptr;
+  io.add_y = 0;
+  return io;
+}
+
 template <typename T>
 hipError_t launch_series_team(const ApplyArrays<T>& A, const LaunchCfg& c, const T* y,
-                              const T* uprev, T* unext, int add_y, T* xb, T* dtop) {
-  if (A.team < 2 || c.R != 1 || c.gx) return hipErrorInvalidValue;
-  const dim3 gt((unsigned)(A.nparts * A.team)), g1((unsigned)A.nparts), bt(c.threads);
-  if (c.ev_start)
-    hipExtLaunchKernelGGL((k_team_lower<T, 0>), gt, bt, (uint32_t)c.lds, c.stream, c.ev_start, nullptr, 0,
-                          A, nullptr, uprev, xb, dtop, nullptr);
-  else
-    hipLaunchKernelGGL((k_team_lower<T, 0>), gt, bt, c.lds, c.stream, A, nullptr, uprev, xb, dtop, nullptr);
-  hipLaunchKernelGGL((k_team_top<T, 0>), g1, bt, c.lds, c.stream, A, nullptr, uprev, xb, dtop, nullptr);
-  hipLaunchKernelGGL((k_team_upper<T, 0>), gt, bt, c.lds, c.stream, A, xb, nullptr);
-  if (c.ev_stop)
-    hipExtLaunchKernelGGL((k_team_c0<T>), g1, bt, (uint32_t)c.lds, c.stream, nullptr, c.ev_stop, 0, A, y,
-                          uprev, unext, xb, add_y);
-  else
-    hipLaunchKernelGGL((k_team_c0<T>), g1, bt, c.lds, c.stream, A, y, uprev, unext, xb, add_y);
+                              const T* uprev, T* unext, int add_y, const TeamWs& W) {
+  if (A.TB.team < 2 || c.R != 1 || c.gx) return hipErrorInvalidValue;
+  TeamIO<T> io = team_io<T>();
+  io.u = uprev;
+  io.xw = (T*)W.xb;
+  io.dtop = (T*)W.dtopb;
+  launch_team<T, 0, 0>(A, c, io, c.ev_start, nullptr);
+  if (A.TC.team > 1) {
+    TeamIO<T> ic = team_io<T>();
+    ic.u = uprev;
+    ic.y = y;
+    ic.xb = (const T*)W.xb;
+    ic.xw = (T*)W.xc;
+    ic.dtop = (T*)W.dtopc;
+    ic.out = unext;
+    ic.add_y = add_y;
+    launch_team<T, 1, 0>(A, c, ic, nullptr, c.ev_stop);
+  } else {
+    const dim3 g1((unsigned)A.nparts), bt(c.threads);
+    if (c.ev_stop)
+      hipExtLaunchKernelGGL((k_team_c0<T>), g1, bt, (uint32_t)c.lds, c.stream, nullptr, c.ev_stop, 0, A, y,
+                            uprev, unext, (const T*)W.xb, add_y);
+    else
+      hipLaunchKernelGGL((k_team_c0<T>), g1, bt, c.lds, c.stream, A, y, uprev, unext, (const T*)W.xb, add_y);
+  }
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_head_team(const ApplyArrays<T>& A, const LaunchCfg& c, const double* b, T* y,
-                            T* xb, T* dtop) {
-  if (A.team < 2 || c.R != 1 || c.gx) return hipErrorInvalidValue;
-  const dim3 gt((unsigned)(A.nparts * A.team)), g1((unsigned)A.nparts), bt(c.threads);
-  hipLaunchKernelGGL((k_team_lower<T, 1>), gt, bt, c.lds, c.stream, A, b, nullptr, xb, dtop, nullptr);
-  hipLaunchKernelGGL((k_team_top<T, 1>), g1, bt, c.lds, c.stream, A, b, nullptr, xb, dtop, nullptr);
-  hipLaunchKernelGGL((k_team_upper<T, 1>), gt, bt, c.lds, c.stream, A, xb, nullptr);
+                            const TeamWs& W) {
+  if (A.TB.team < 2 || c.R != 1 || c.gx) return hipErrorInvalidValue;
+  TeamIO<T> io = team_io<T>();
+  io.b = b;
+  io.xw = (T*)W.xb;
+  io.dtop = (T*)W.dtopb;
+  launch_team<T, 0, 1>(A, c, io, nullptr, nullptr);
   if (A.q > 0)
-    hipLaunchKernelGGL((k_team_headF<T>), dim3(nblk(A.q, 256)), dim3(256), 0, c.stream, A, b, xb, y);
+    hipLaunchKernelGGL((k_team_headF<T>), dim3(nblk(A.q, 256)), dim3(256), 0, c.stream, A, b,
+                       (const T*)W.xb, y);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_tail_team(const ApplyArrays<T>& A, const LaunchCfg& c, const double* b,
-                            const T* u, double* z, T* xb, T* dtop) {
-  if (A.team < 2 || c.R != 1 || c.gx) return hipErrorInvalidValue;
-  const dim3 gt((unsigned)(A.nparts * A.team)), g1((unsigned)A.nparts), bt(c.threads);
-  hipLaunchKernelGGL((k_team_lower<T, 2>), gt, bt, c.lds, c.stream, A, b, u, xb, dtop, z);
-  hipLaunchKernelGGL((k_team_top<T, 2>), g1, bt, c.lds, c.stream, A, b, u, xb, dtop, z);
-  hipLaunchKernelGGL((k_team_upper<T, 2>), gt, bt, c.lds, c.stream, A, xb, z);
+                            const T* u, double* z, const TeamWs& W) {
+  if (A.TB.team < 2 || c.R != 1 || c.gx) return hipErrorInvalidValue;
+  TeamIO<T> io = team_io<T>();
+  io.b = b;
+  io.u = u;
+  io.z = z;
+  io.xw = (T*)W.xb;
+  io.dtop = (T*)W.dtopb;
+  launch_team<T, 0, 2>(A, c, io, nullptr, nullptr);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_c0_team(const ApplyArrays<T>& A, const LaunchCfg& c, const T* src, T* dst,
+                          const TeamWs& W) {
+  if (A.TC.team < 2 || c.R != 1 || c.gx) return hipErrorInvalidValue;
+  TeamIO<T> io = team_io<T>();
+  io.y = src;
+  io.xw = (T*)W.xc;
+  io.dtop = (T*)W.dtopc;
+  io.out = dst;
+  launch_team<T, 1, 1>(A, c, io, nullptr, nullptr);
   return hipGetLastError();
 }
 
@@ -1386,11 +1583,13 @@ hipError_t launch_tail_team(const ApplyArrays<T>& A, const LaunchCfg& c, const d
   template hipError_t launch_tail<T>(const ApplyArrays<T>&, const LaunchCfg&, int, const double*, \
                                      int64_t, const T*, int64_t, double*, int64_t);              \
   template hipError_t launch_series_team<T>(const ApplyArrays<T>&, const LaunchCfg&, const T*,    \
-                                            const T*, T*, int, T*, T*);                          \
+                                            const T*, T*, int, const TeamWs&);                   \
   template hipError_t launch_head_team<T>(const ApplyArrays<T>&, const LaunchCfg&, const double*, \
-                                          T*, T*, T*);                                           \
+                                          T*, const TeamWs&);                                    \
   template hipError_t launch_tail_team<T>(const ApplyArrays<T>&, const LaunchCfg&, const double*, \
-                                          const T*, double*, T*, T*);
+                                          const T*, double*, const TeamWs&);                     \
+  template hipError_t launch_c0_team<T>(const ApplyArrays<T>&, const LaunchCfg&, const T*, T*,    \
+                                        const TeamWs&);
 
 PSLR_INST(double)
 PSLR_INST(float)

@@ -2,7 +2,8 @@
 tree cut into subtree groups and a top group; option `team`), through the C
 ABI: single-right-hand-side applies with and without the team split agree
 (same operator, different summation order), and both match the oracle; the
-FGMRES iteration counts agree."""
+FGMRES iteration counts agree.  The top group runs either its packed factors
+or the dense inverse of its block of L U (option `team_top`)."""
 import numpy as np
 import pytest
 
@@ -42,9 +43,10 @@ CASES = cases()
 IDS = [c[0] for c in CASES]
 
 
+@pytest.mark.parametrize("team_top", [1, 2])
 @pytest.mark.parametrize("team", [2, 4])
 @pytest.mark.parametrize("name,A,lab,m,rank", CASES, ids=IDS)
-def test_team_apply_matches_plain_and_oracle(name, A, lab, m, rank, team):
+def test_team_apply_matches_plain_and_oracle(name, A, lab, m, rank, team, team_top):
     dev = _dev()
     nparts = int(lab.max()) + 1
     As = A.to_scipy()
@@ -57,7 +59,10 @@ def test_team_apply_matches_plain_and_oracle(name, A, lab, m, rank, team):
         hs = {}
         for t in (1, team):
             h = P.pslr_setup(A.rowptr, A.colind, A.vals, lab, nparts, m=m, rank=0, precision=prec,
-                             team=t)
+                             team=t, team_top=team_top)
+            inf = P.pslr_info(h)
+            assert inf["team"] == (t if t > 1 else 0)
+            assert inf["team_top"] == (team_top if t > 1 else 0)
             P.pslr_set_lowrank(h, pre.V, pre.H)
             z = torch.zeros_like(bt)
             P.pslr_apply(h, bt, z)
@@ -67,7 +72,7 @@ def test_team_apply_matches_plain_and_oracle(name, A, lab, m, rank, team):
                                team=team)
         e_pl = _rel(hs[team][1], hs[1][1])
         e_or = _rel(hs[team][1], ref)
-        print(name, "team", team, "precision", prec, "team vs plain %.2e, vs oracle %.2e (plain %.2e); "
+        print(name, "team", team, "top", team_top, "precision", prec, "team vs plain %.2e, vs oracle %.2e (plain %.2e); "
               "host team residual %.1e" % (e_pl, e_or, _rel(hs[1][1], ref), st["team_residual"]),
               flush=True)
         assert st["team"] == team and st["team_valid"] == 1
@@ -102,3 +107,14 @@ def test_team_fgmres_and_batched_fallback():
           % (out[1][0], out[4][0], _rel(out[4][2], out[1][2])), flush=True)
     assert out[4][1] <= 1e-10 and abs(out[4][0] - out[1][0]) <= 1
     assert _rel(out[4][2], out[1][2]) <= 1e-12
+
+
+def test_team_top_auto_and_limits():
+    """team_top = 0 picks the dense inverse when it holds at most twice the
+    packed top factors' values; bad values are rejected."""
+    _dev()
+    name, A, lab, m, rank = CASES[0]
+    h = P.pslr_setup(A.rowptr, A.colind, A.vals, lab, 8, m=m, rank=0, team=4)
+    assert P.pslr_info(h)["team_top"] in (1, 2)
+    with pytest.raises(P.PslrError):
+        P.pslr_setup(A.rowptr, A.colind, A.vals, lab, 8, m=m, rank=0, team=4, team_top=3)
