@@ -257,6 +257,7 @@ struct pslr_ctx {
   const LrChunk* d_chunks = nullptr;
   const int32_t* d_sys_chunk = nullptr;
   int nchunk_lr = 1;
+  int lr_maxrows = 0;           // the most rows of a V^T y chunk
   const Seg* d_qcols = nullptr;
   // global working vectors when a subdomain does not fit in LDS
   bool gx = false;          // working vectors forced to global memory
@@ -462,7 +463,9 @@ hipError_t upload_team(DevPool& pool, const std::vector<BlockFactor>& F, int tea
   if ((e = upload_tri_list(pool, us, out.U, mlr, tb))) return e;
   out.team = team;
   if (team_top == 2 && !dense_ok) return hipErrorInvalidValue;
-  const bool dense = dense_ok && (team_top == 2 || (team_top == 0 && dense_vals <= 2 * top_vals));
+  // (blocks without top rows keep the packed path: nothing to multiply)
+  const bool dense =
+      dense_ok && dense_vals > 0 && (team_top == 2 || (team_top == 0 && dense_vals <= 2 * top_vals));
   bytes = groups + top_packed;
   if (dense) {
     std::vector<T> ti;
@@ -541,7 +544,8 @@ size_t lds_bytes(const ApplyArrays<T>& A, int kmax, int R = 1) {
 WsSizes ws_sizes(const pslr_ctx* h, int nrhs) {
   WsSizes z;
   z.vec = (size_t)std::max<int64_t>(h->R.q, 1) * nrhs;
-  z.partial = (size_t)h->nchunk_lr * nrhs * std::max(h->k, 1);
+  // V^T y chunk partials, then G W per system (one right-hand side)
+  z.partial = (size_t)h->nchunk_lr * nrhs * std::max(h->k, 1) + (size_t)h->nsys * std::max(h->k, 1);
   z.gws = h->gws_stride > 0 ? (size_t)h->gws_stride * ((nrhs + 7) / 8 * 8) : 0;
   // the family vectors and top-row updates of the team solves (one right-hand
   // side): [xb: p][dtopb: nparts x team x ntopmax of B][xc: q][dtopc: the same of C]
@@ -601,6 +605,26 @@ hipError_t lowrank_partial<float>(pslr_ctx* h, const float* y, int64_t ldy, int 
                                                     nrhs, part, h->cur_active, h->nsys, s);
   return launch_lr_partial<float, float>(h->nchunk_lr, h->d_chunks, h->k, h->V32, h->R.q, y, ldy, nrhs, part,
                                          h->cur_active, h->nsys, s);
+}
+// y += V G V^T y (gtrans: G^T) for one right-hand side over the whole chip;
+// part: nchunk_lr * k values, then nsys * k for G W
+template <typename T>
+hipError_t lowrank1(pslr_ctx* h, T* y, T* part, int gtrans, hipStream_t s);
+template <>
+hipError_t lowrank1<double>(pslr_ctx* h, double* y, double* part, int gtrans, hipStream_t s) {
+  return launch_lr1<double, double>(h->nchunk_lr, h->d_chunks, h->lr_maxrows, h->nsys, h->d_sys_chunk, h->k,
+                                    h->V64, h->R.q, h->G64, gtrans, y, part,
+                                    part + (int64_t)h->nchunk_lr * h->k, h->cur_active, s);
+}
+template <>
+hipError_t lowrank1<float>(pslr_ctx* h, float* y, float* part, int gtrans, hipStream_t s) {
+  float* z = part + (int64_t)h->nchunk_lr * h->k;
+  if (h->Vbf && h->v_bf16)
+    return launch_lr1<float, __hip_bfloat16>(h->nchunk_lr, h->d_chunks, h->lr_maxrows, h->nsys, h->d_sys_chunk,
+                                             h->k, h->Vbf, h->R.q, h->G32, gtrans, y, part, z, h->cur_active,
+                                             s);
+  return launch_lr1<float, float>(h->nchunk_lr, h->d_chunks, h->lr_maxrows, h->nsys, h->d_sys_chunk, h->k,
+                                  h->V32, h->R.q, h->G32, gtrans, y, part, z, h->cur_active, s);
 }
 template <typename T>
 hipError_t lowrank_expand(pslr_ctx* h, const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs,
@@ -821,10 +845,13 @@ pslr_status run_apply(pslr_ctx* h, const ApplyArrays<T>& Ah, const ApplyWs& W, b
                              h->Vbr, h->G32, 0, (float*)y, q, nrhs, (float*)part,
                              (__hip_bfloat16*)W.zp, h->cur_active, s));
       HIP_TRY(launch_c0solve<T>(A, cfg, nrhs, y, q, ua, q));
+    } else if (k > 0 && nrhs == 1) {
+      HIP_TRY(lowrank1<T>(h, y, part, 0, s));
+      if (cteam) HIP_TRY(launch_c0_team<T>(A, cfg, y, ua, tw));
+      else HIP_TRY(launch_c0solve<T>(A, cfg, nrhs, y, q, ua, q));
     } else if (k > 0) {
       HIP_TRY(lowrank_partial<T>(h, y, q, nrhs, part, s));
-      HIP_TRY(lowrank_expand<T>(h, A, cfg, nrhs, 0, part, y, q, cteam ? 0 : 1, ua, q));
-      if (cteam) HIP_TRY(launch_c0_team<T>(A, cfg, y, ua, tw));
+      HIP_TRY(lowrank_expand<T>(h, A, cfg, nrhs, 0, part, y, q, 1, ua, q));
     } else if (cteam) {
       HIP_TRY(launch_c0_team<T>(A, cfg, y, ua, tw));
     } else {
@@ -851,6 +878,9 @@ pslr_status run_apply(pslr_ctx* h, const ApplyArrays<T>& Ah, const ApplyWs& W, b
       HIP_TRY(launch_lr_mfma(h->nchunk_lr, h->d_chunks, h->nsys, h->d_sys_chunk, k, h->Vbf, h->R.q,
                              h->Vbr, h->G32, 1, (float*)ua, q, nrhs, (float*)part,
                              (__hip_bfloat16*)W.zp, h->cur_active, s));
+      HIP_TRY(tr.mark(PH_LOWRANK));
+    } else if (k > 0 && nrhs == 1) {
+      HIP_TRY(lowrank1<T>(h, ua, part, 1, s));
       HIP_TRY(tr.mark(PH_LOWRANK));
     } else if (k > 0) {
       HIP_TRY(lowrank_partial<T>(h, ua, q, nrhs, part, s));
@@ -2154,6 +2184,8 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
     }
     if (ch.empty()) ch.push_back(LrChunk{0, 0, 0, 0});
     h->nchunk_lr = (int)ch.size();
+    h->lr_maxrows = 0;
+    for (const LrChunk& c : ch) h->lr_maxrows = std::max<int>(h->lr_maxrows, (int)(c.r1 - c.r0));
     HIP_TRY(h->pool.upload(ch, &h->d_chunks));
     HIP_TRY(h->pool.upload(sc, &h->d_sys_chunk));
     std::vector<Seg> qc(nsys);

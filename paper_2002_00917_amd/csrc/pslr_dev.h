@@ -158,6 +158,13 @@ hipError_t launch_lr_expand(const ApplyArrays<T>& A, const LaunchCfg& c, int nrh
                             const TV* V, const T* G, int gtrans, const T* partial, int nchunk,
                             const int32_t* sys_chunk, T* y, int64_t ldy, int do_c0, T* u,
                             int64_t ldu);
+// y += V G V^T y (gtrans: V G^T V^T y) for one right-hand side: V^T y per row
+// chunk into partial (nchunk * k), z_s = G_s W_s into z (nsys * k), then the
+// expansion; maxrows: the most rows of any chunk; k <= 256
+template <typename T, typename TV>
+hipError_t launch_lr1(int nchunk, const LrChunk* chunks, int maxrows, int nsys, const int32_t* sys_chunk,
+                      int k, const TV* V, int64_t ldv, const T* G, int gtrans, T* y, T* partial, T* z,
+                      const uint8_t* active, hipStream_t s);
 // y += V G V^T y (gtrans: V G^T V^T y) on the matrix cores for FP32 applies with
 // V in BF16: V column-major (ldv) and row-major Vr (q x kp, kp = k rounded up to
 // 16, zero padded); partial: nchunk * nrhs * k floats; Zp: nsys * 3 * nrhs * kp

@@ -578,6 +578,133 @@ k_lr_partial(const LrChunk* __restrict__ chunks, int k, const TV* __restrict__ V
   }
 }
 
+// ---- the low-rank term for one right-hand side (Algorithm 3, line 3):
+// y += V (G (V^T y)) in three launches that spread V over the whole chip.
+// V column-major (ldv); a column's rows are contiguous, so lanes run along
+// the rows in both products.
+//  1. partial[c * k + j] = sum over chunk c's rows of V[row][j] y[row]:
+//     workgroup (c, block of 16 columns), wave w the columns 4w .. 4w + 3 of
+//     the block; every lane keeps all its loads of the chunk in flight.
+//  2. z_s = G_s W_s (or G_s^T W_s), W_s the sum of system s's chunk
+//     partials, in column slices that meet in LDS.
+//  3. y[row] += V[row, :] z_s: workgroup (c, block of 64 rows), wave w the
+//     w-th quarter of the columns, lanes along the rows; the waves meet in LDS.
+constexpr int kLr1Cols = 16;
+constexpr int kLr1Rows = 64;
+
+template <typename T, typename TV>
+__global__ void __launch_bounds__(256) k_lr1_partial(const LrChunk* __restrict__ chunks, int k,
+                                                     const TV* __restrict__ V, int64_t ldv,
+                                                     const T* __restrict__ y, T* partial,
+                                                     const uint8_t* __restrict__ active) {
+  __shared__ T ys[kLrChunkRows];
+  const LrChunk C = chunks[blockIdx.x];
+  if (active && !active[C.sys]) return;
+  const int nr = (int)(C.r1 - C.r0);
+  for (int t = threadIdx.x; t < nr; t += blockDim.x) ys[t] = y[C.r0 + t];
+  __syncthreads();
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int jb = blockIdx.y * kLr1Cols + 4 * w;
+  if (jb >= k) return;
+  const TV* Vc[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) Vc[u] = V + (int64_t)min(jb + u, k - 1) * ldv + C.r0;
+  T acc[4] = {(T)0, (T)0, (T)0, (T)0};
+  constexpr int S = 4;  // rows per lane per round: 16 loads in flight
+  for (int t = lane; t < nr; t += 64 * S) {
+    TV v[S][4];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int ts = min(t + 64 * s, nr - 1);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[s][u] = Vc[u][ts];
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const T yv = t + 64 * s < nr ? ys[t + 64 * s] : (T)0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += (T)tv_to_float(v[s][u]) * yv;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) acc[u] = group_sum(acc[u], 64);
+  if (lane == 0)
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (jb + u < k) partial[(int64_t)blockIdx.x * k + jb + u] = acc[u];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024) k_lr1_gz(int k, const T* __restrict__ Gall, int gtrans,
+                                                 const T* __restrict__ partial,
+                                                 const int32_t* __restrict__ sys_chunk, T* zout,
+                                                 const uint8_t* __restrict__ active) {
+  __shared__ T W[256];
+  __shared__ T red[1024];
+  const int s = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  if (active && !active[s]) return;
+  const int c0 = sys_chunk[s], c1 = sys_chunk[s + 1];
+  const int S = max(1, min(nt / max(k, 1), 32));  // slices of the summation range
+  const int j = tid % k, sl = tid / k;
+  {
+    T a = (T)0;
+    if (sl < S)
+      for (int c = c0 + sl; c < c1; c += S) a += partial[(int64_t)c * k + j];
+    red[tid] = a;
+  }
+  __syncthreads();
+  if (tid < k) {
+    T a = (T)0;
+    for (int t = 0; t < S; ++t) a += red[t * k + tid];
+    W[tid] = a;
+  }
+  __syncthreads();
+  const T* G = Gall + (int64_t)s * k * k;
+  {
+    T a = (T)0;
+    if (sl < S)
+      for (int l = sl; l < k; l += S) a += (gtrans ? G[(int64_t)l * k + j] : G[(int64_t)j * k + l]) * W[l];
+    red[tid] = a;
+  }
+  __syncthreads();
+  if (tid < k) {
+    T a = (T)0;
+    for (int t = 0; t < S; ++t) a += red[t * k + tid];
+    zout[(int64_t)s * k + tid] = a;
+  }
+}
+
+template <typename T, typename TV>
+__global__ void __launch_bounds__(256) k_lr1_expand(const LrChunk* __restrict__ chunks, int k,
+                                                    const TV* __restrict__ V, int64_t ldv,
+                                                    const T* __restrict__ zall, T* y,
+                                                    const uint8_t* __restrict__ active) {
+  __shared__ T zs[256];
+  __shared__ T red[3 * kLr1Rows];
+  const LrChunk C = chunks[blockIdx.x];
+  if (active && !active[C.sys]) return;
+  const int64_t r0 = C.r0 + (int64_t)blockIdx.y * kLr1Rows;
+  if (r0 >= C.r1) return;  // uniform over the workgroup
+  for (int j = threadIdx.x; j < k; j += blockDim.x) zs[j] = zall[(int64_t)C.sys * k + j];
+  __syncthreads();
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t row = min(r0 + lane, C.r1 - 1);
+  const int kq = (k + 3) / 4, ja = w * kq, je = min(k, ja + kq);
+  T acc = (T)0;
+  constexpr int U = 8;
+  for (int j = ja; j < je; j += U) {
+    TV v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = V[(int64_t)min(j + u, je - 1) * ldv + row];
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc += j + u < je ? (T)tv_to_float(v[u]) * zs[j + u] : (T)0;
+  }
+  if (w > 0) red[(w - 1) * kLr1Rows + lane] = acc;
+  __syncthreads();
+  if (w == 0 && r0 + lane < C.r1)
+    y[row] += acc + red[lane] + red[kLr1Rows + lane] + red[2 * kLr1Rows + lane];
+}
+
 // ---- the low-rank products on the matrix cores (many right-hand sides, V in BF16)
 //
 // With V stored in BF16 the two tall-skinny products of the low-rank term,
@@ -1370,6 +1497,21 @@ hipError_t launch_lr_partial(int nchunk, const LrChunk* chunks, int k, const TV*
   return hipGetLastError();
 }
 
+template <typename T, typename TV>
+hipError_t launch_lr1(int nchunk, const LrChunk* chunks, int maxrows, int nsys, const int32_t* sys_chunk,
+                      int k, const TV* V, int64_t ldv, const T* G, int gtrans, T* y, T* partial, T* z,
+                      const uint8_t* active, hipStream_t s) {
+  if (nchunk <= 0 || k <= 0) return hipSuccess;
+  if (k > 256 || maxrows > kLrChunkRows) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_lr1_partial<T, TV>), dim3(nchunk, (k + kLr1Cols - 1) / kLr1Cols), dim3(256), 0, s,
+                     chunks, k, V, ldv, y, partial, active);
+  hipLaunchKernelGGL((k_lr1_gz<T>), dim3(nsys), dim3(1024), 0, s, k, G, gtrans, partial, sys_chunk, z,
+                     active);
+  hipLaunchKernelGGL((k_lr1_expand<T, TV>), dim3(nchunk, (maxrows + kLr1Rows - 1) / kLr1Rows), dim3(256), 0,
+                     s, chunks, k, V, ldv, z, y, active);
+  return hipGetLastError();
+}
+
 hipError_t launch_lr_mfma(int nchunk, const LrChunk* chunks, int nsys, const int32_t* sys_chunk,
                           int k, const __hip_bfloat16* V, int64_t ldv, const __hip_bfloat16* Vr,
                           const float* G, int gtrans, float* y, int64_t ldy, int nrhs,
@@ -1475,7 +1617,7 @@ void launch_team(const ApplyArrays<T>& A, const LaunchCfg& c, const TeamIO<T>& i
                           A, io);
   else
     hipLaunchKernelGGL((k_team_lower<T, FAM, MODE>), gt, bt, c.lds, c.stream, A, io);
-  if (TA.TI) {
+  if (TA.TI && TA.nrb > 0) {
     const size_t lds = sizeof(T) * ((size_t)((TA.ntopmax + 3) & ~1) + (size_t)(c.threads / 64) * kTopRows);
     hipLaunchKernelGGL((k_team_topinv<T, FAM, MODE>), dim3((unsigned)(A.nparts * TA.nrb)), bt, lds, c.stream,
                        A, io);
@@ -1594,6 +1736,16 @@ hipError_t launch_c0_team(const ApplyArrays<T>& A, const LaunchCfg& c, const T* 
 PSLR_INST(double)
 PSLR_INST(float)
 
+template hipError_t launch_lr1<double, double>(int, const LrChunk*, int, int, const int32_t*, int,
+                                               const double*, int64_t, const double*, int, double*,
+                                               double*, double*, const uint8_t*, hipStream_t);
+template hipError_t launch_lr1<float, float>(int, const LrChunk*, int, int, const int32_t*, int,
+                                             const float*, int64_t, const float*, int, float*, float*,
+                                             float*, const uint8_t*, hipStream_t);
+template hipError_t launch_lr1<float, __hip_bfloat16>(int, const LrChunk*, int, int, const int32_t*, int,
+                                                      const __hip_bfloat16*, int64_t, const float*, int,
+                                                      float*, float*, float*, const uint8_t*,
+                                                      hipStream_t);
 template hipError_t launch_lr_partial<double, double>(int, const LrChunk*, int, const double*,
                                                       int64_t, const double*, int64_t, int, double*,
                                                       const uint8_t*, int, hipStream_t);
