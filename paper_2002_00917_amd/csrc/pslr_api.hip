@@ -538,7 +538,7 @@ hipError_t upload_dir(DevPool& pool, const Reordering& R, const std::vector<Bloc
 template <typename T>
 size_t lds_bytes(const ApplyArrays<T>& A, int kmax, int R = 1) {
   return sizeof(T) * (size_t)R *
-         ((size_t)A.maxPB + 2 * (size_t)A.maxLR + 2 * (size_t)A.maxQB + 2 * (size_t)std::max(kmax, 1));
+         ((size_t)A.maxPB + 3 * (size_t)A.maxLR + 2 * (size_t)A.maxQB + 2 * (size_t)std::max(kmax, 1));
 }
 
 WsSizes ws_sizes(const pslr_ctx* h, int nrhs) {
@@ -2209,7 +2209,7 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
       int mx = 1;
       for (const BlockFactor* f : {&fB[i], &fC[i]})
         for (const TriPacked* T : {&f->lo, &f->up, &f->loT, &f->upT}) mx = std::max(mx, T->max_lrows);
-      rb[i + 1] = rb[i] + 2 * mx;  // two halves for alternate levels
+      rb[i + 1] = rb[i] + 3 * mx;  // thirds rotated over the levels
     }
     HIP_TRY(h->facpool.upload(rb, &h->d_rb_off));
     h->gws_stride = h->R.p + 2 * h->R.q + rb[nparts] + (int64_t)nparts * 2 * std::max(h->rank, 1);
@@ -2345,7 +2345,7 @@ pslr_status pslr_refactor(pslr_handle h, const double* vals, void* hip_stream) {
       int mx = 1;
       for (const BlockFactor* f : {&fB[i], &fC[i]})
         for (const TriPacked* T : {&f->lo, &f->up, &f->loT, &f->upT}) mx = std::max(mx, T->max_lrows);
-      rb[i + 1] = rb[i] + 2 * mx;
+      rb[i + 1] = rb[i] + 3 * mx;
     }
     HIP_TRY(nf.upload(rb, &d_rb_off));
     gws_stride = h->R.p + 2 * h->R.q + rb[np] + (int64_t)np * 2 * std::max(h->fw64.kmax, 1);

@@ -1033,6 +1033,7 @@ bool pack_tri(const TriHost& T, TriPacked& P, int narrow_width) {
   P.ent_ptr.assign(T.nlev + 1, 0);
   P.lev_c.assign(T.nlev, 0);
   P.rec.assign((size_t)8 * T.n, 0);
+  std::vector<double> pf;
   for (int l = 0; l < T.nlev; ++l) {
     const int b = T.lev_ptr[l], e = T.lev_ptr[l + 1];
     const int cnt = e - b;
@@ -1064,22 +1065,45 @@ bool pack_tri(const TriHost& T, TriPacked& P, int narrow_width) {
           P.tri.push_back(tinv(i, 2 * c + 1));
         }
       }
+      // folded panels: the panel times the inverted triangle, so that a level's
+      // off-diagonal products read the rows' values from before the level's
+      // solve.  Lower: Pf(a, j) = sum_l Lp(a, l) Tinv(l, j) (h x w, the pushes
+      // x[ridx[a]] -= Pf(a, :) x[f .. f+w-1]); upper: Pf(i, a) = sum_l
+      // Tinv(i, l) Up(l, a) (w x h, x[f + i] = Tinv(i, :) x[f ..] - Pf(i, :) x[ridx]).
+      pf.assign((size_t)w * h, 0.0);
+      if (T.lower) {
+        for (int q = 0; q < h; ++q) {
+          const double* lp = &T.val[S.panel_off + (int64_t)q * w];
+          for (int l = 0; l < w; ++l)
+            if (lp[l] != 0.0)
+              for (int j = 0; j <= l; ++j) pf[(size_t)q * w + j] += lp[l] * tinv(l, j);
+        }
+      } else {
+        for (int i = 0; i < w; ++i)
+          for (int l = i; l < w; ++l) {
+            const double t = tinv(i, l);
+            if (t == 0.0) continue;
+            const double* up = &T.val[S.panel_off + (int64_t)l * h];
+            for (int q = 0; q < h; ++q) pf[(size_t)i * h + q] += t * up[q];
+          }
+      }
       if (ent) {
-        // entry form (kept besides the panels; the solve picks one):
-        // lower: (a, j) -> x[ridx[a]] -= v * s_{k0 + j};  upper: (i, a) -> r_{k0 + i} -= v * x[ridx[a]]
+        // entry form (kept besides the panels; the solve picks one), targets
+        // and sources as positions: lower (a, j) -> x[ridx[a]] -= v x[f + j];
+        // upper (i, a) -> x[f + i] -= v x[ridx[a]]
         if (T.lower) {
           for (int j = 0; j < w; ++j)
             for (int q = 0; q < h; ++q) {
-              P.eval.push_back(T.val[S.panel_off + (int64_t)q * w + j]);
+              P.eval.push_back(pf[(size_t)q * w + j]);
               P.eidx.push_back(T.ridx[S.ridx_off + q]);
-              P.eloc.push_back(k - b + j);
+              P.eloc.push_back(S.f + j);
             }
         } else {
           for (int q = 0; q < h; ++q)
             for (int i = 0; i < w; ++i) {
-              P.eval.push_back(T.val[S.panel_off + (int64_t)i * h + q]);
+              P.eval.push_back(pf[(size_t)i * h + q]);
               P.eidx.push_back(T.ridx[S.ridx_off + q]);
-              P.eloc.push_back(k - b + i);
+              P.eloc.push_back(S.f + i);
             }
         }
       }
@@ -1090,12 +1114,12 @@ bool pack_tri(const TriHost& T, TriPacked& P, int narrow_width) {
           for (int c = 0; c < (w + 1) / 2; ++c)
             for (int q = 0; q < h; ++q)
               for (int t = 0; t < 2; ++t)
-                P.val.push_back(2 * c + t < w ? T.val[S.panel_off + (int64_t)q * w + 2 * c + t] : 0.0);
+                P.val.push_back(2 * c + t < w ? pf[(size_t)q * w + 2 * c + t] : 0.0);
         } else {
           for (int c = 0; c < (h + 1) / 2; ++c)
             for (int i = 0; i < w; ++i)
               for (int t = 0; t < 2; ++t)
-                P.val.push_back(2 * c + t < h ? T.val[S.panel_off + (int64_t)i * h + 2 * c + t] : 0.0);
+                P.val.push_back(2 * c + t < h ? pf[(size_t)i * h + 2 * c + t] : 0.0);
         }
         // position list padded to even length with its last position (paired with zeros)
         P.ridx.insert(P.ridx.end(), T.ridx.begin() + S.ridx_off, T.ridx.begin() + S.ridx_off + h);
@@ -1105,7 +1129,7 @@ bool pack_tri(const TriHost& T, TriPacked& P, int narrow_width) {
             P.prec.push_back(T.ridx[S.ridx_off + q]);
             P.prec.push_back(poff / 2 + q);
             P.prec.push_back(w | (h << 16));
-            P.prec.push_back(k - b);
+            P.prec.push_back(S.f);
           }
           npush += h;
           push_len += (double)h * w;
@@ -1190,6 +1214,8 @@ void host_tri_solve(const TriPacked& T, std::vector<double>& X, bool entries) {
     const int b = T.lev_ptr[l], e = T.lev_ptr[l + 1];
     const bool ent = entries && ((T.lev_c[l] >> 16) & 1);
     if (T.lower) {
+      // the level's new values from its rows' old ones, then the pushes (also
+      // from the old ones), then the new values
       for (int k = b; k < e; ++k) {
         const int32_t* r = &T.rec[(size_t)8 * k];
         const int p = r[0], i = r[1], w = r[2];
@@ -1198,36 +1224,31 @@ void host_tri_solve(const TriPacked& T, std::vector<double>& X, bool entries) {
           acc += T.tri[r[4] + 2 * tri_pair_lower(i, j, w) + (j & 1)] * X[p - i + j];
         Rb[k - b] = acc;
       }
-      for (int k = b; k < e; ++k) X[T.rec[(size_t)8 * k]] = Rb[k - b];
       if (ent) {
-        for (int q = T.ent_ptr[l]; q < T.ent_ptr[l + 1]; ++q) X[T.eidx[q]] -= T.eval[q] * Rb[T.eloc[q]];
+        for (int q = T.ent_ptr[l]; q < T.ent_ptr[l + 1]; ++q) X[T.eidx[q]] -= T.eval[q] * X[T.eloc[q]];
       } else {
         for (int m = T.push_ptr[l]; m < T.push_ptr[l + 1]; ++m) {
           const int32_t* q = &T.prec[(size_t)4 * m];
           const int w = q[2] & 0xffff, h = q[2] >> 16;
           double acc = 0.0;
-          for (int j = 0; j < w; ++j) acc += T.val[2 * (q[1] + (int64_t)(j >> 1) * h) + (j & 1)] * Rb[q[3] + j];
+          for (int j = 0; j < w; ++j) acc += T.val[2 * (q[1] + (int64_t)(j >> 1) * h) + (j & 1)] * X[q[3] + j];
           X[q[0]] -= acc;
         }
       }
+      for (int k = b; k < e; ++k) X[T.rec[(size_t)8 * k]] = Rb[k - b];
     } else {
+      for (int k = b; k < e; ++k) Rb[k - b] = X[T.rec[(size_t)8 * k]];
       for (int k = b; k < e; ++k) {
         const int32_t* r = &T.rec[(size_t)8 * k];
-        const int i = r[1], w = r[2], h = ent ? 0 : r[3];
-        double acc = 0.0;
-        for (int a = 0; a < h; ++a)
-          acc += T.val[r[5] + 2 * ((int64_t)(a >> 1) * w + i) + (a & 1)] * X[T.ridx[r[6] + a]];
-        Rb[k - b] = X[r[0]] - acc;
-      }
-      if (ent)
-        for (int q = T.ent_ptr[l]; q < T.ent_ptr[l + 1]; ++q) Rb[T.eloc[q]] -= T.eval[q] * X[T.eidx[q]];
-      for (int k = b; k < e; ++k) {
-        const int32_t* r = &T.rec[(size_t)8 * k];
-        const int p = r[0], i = r[1], w = r[2];
+        const int p = r[0], i = r[1], w = r[2], h = ent ? 0 : r[3];
         double acc = 0.0;
         for (int j = i; j < w; ++j) acc += T.tri[r[4] + 2 * tri_pair_upper(i, j) + (j & 1)] * Rb[r[7] + j];
+        for (int a = 0; a < h; ++a)
+          acc -= T.val[r[5] + 2 * ((int64_t)(a >> 1) * w + i) + (a & 1)] * X[T.ridx[r[6] + a]];
         X[p] = acc;
       }
+      if (ent)
+        for (int q = T.ent_ptr[l]; q < T.ent_ptr[l + 1]; ++q) X[T.eloc[q]] -= T.eval[q] * X[T.eidx[q]];
     }
   }
 }
@@ -1242,17 +1263,13 @@ bool top_inverse(const TriPacked& lo, const TriPacked& up, int n, std::vector<do
   if (nt == 0) return true;
   std::vector<int> loc(n, -1);
   for (int k = 0; k < nt; ++k) loc[lo.rec[(size_t)8 * k]] = k;
-  auto L = [&](int p) {
-    const int k = p >= 0 && p < n ? loc[p] : -1;
-    return k;
-  };
   std::vector<double> X((size_t)nt * nt, 0.0);
   for (int k = 0; k < nt; ++k) X[(size_t)k * nt + k] = 1.0;
   const int mr = std::max(std::max(lo.max_lrows, up.max_lrows), 1);
   std::vector<double> Rb((size_t)mr * nt);
   std::vector<double> acc(nt);
   auto row = [&](int p) -> double* {
-    const int k = L(p);
+    const int k = p >= 0 && p < n ? loc[p] : -1;
     return k < 0 ? nullptr : &X[(size_t)k * nt];
   };
   auto axpy = [&](double* y, double a, const double* x) {
@@ -1272,39 +1289,39 @@ bool top_inverse(const TriPacked& lo, const TriPacked& up, int n, std::vector<do
       }
       std::copy(acc.begin(), acc.end(), &Rb[(size_t)(k - b) * nt]);
     }
-    for (int k = b; k < e; ++k) std::copy(&Rb[(size_t)(k - b) * nt], &Rb[(size_t)(k - b + 1) * nt],
-                                          row(lo.rec[(size_t)8 * k]));
     for (int m = lo.push_ptr[li]; m < lo.push_ptr[li + 1]; ++m) {
       const int32_t* q = &lo.prec[(size_t)4 * m];
       const int w = q[2] & 0xffff, h = q[2] >> 16;
       double* xd = row(q[0]);
       if (!xd) return false;
-      for (int j = 0; j < w; ++j)
-        axpy(xd, -lo.val[2 * (q[1] + (int64_t)(j >> 1) * h) + (j & 1)], &Rb[(size_t)(q[3] + j) * nt]);
+      for (int j = 0; j < w; ++j) {
+        const double* xs = row(q[3] + j);
+        if (!xs) return false;
+        axpy(xd, -lo.val[2 * (q[1] + (int64_t)(j >> 1) * h) + (j & 1)], xs);
+      }
     }
+    for (int k = b; k < e; ++k) std::copy(&Rb[(size_t)(k - b) * nt], &Rb[(size_t)(k - b + 1) * nt],
+                                          row(lo.rec[(size_t)8 * k]));
   }
   for (int li = 0; li < up.nlev; ++li) {
     const int l = up.nlev - 1 - li;
     const int b = up.lev_ptr[l], e = up.lev_ptr[l + 1];
     for (int k = b; k < e; ++k) {
-      const int32_t* r = &up.rec[(size_t)8 * k];
-      const int i = r[1], w = r[2], h = r[3];
-      const double* xp = row(r[0]);
+      const double* xp = row(up.rec[(size_t)8 * k]);
       if (!xp) return false;
-      double* rk = &Rb[(size_t)(k - b) * nt];
-      std::copy(xp, xp + nt, rk);
-      for (int a = 0; a < h; ++a) {
-        const double* xa = row(up.ridx[r[6] + a]);
-        if (!xa) return false;
-        axpy(rk, -up.val[r[5] + 2 * ((int64_t)(a >> 1) * w + i) + (a & 1)], xa);
-      }
+      std::copy(xp, xp + nt, &Rb[(size_t)(k - b) * nt]);
     }
     for (int k = b; k < e; ++k) {
       const int32_t* r = &up.rec[(size_t)8 * k];
-      const int i = r[1], w = r[2];
+      const int i = r[1], w = r[2], h = r[3];
       std::fill(acc.begin(), acc.end(), 0.0);
       for (int j = i; j < w; ++j)
         axpy(acc.data(), up.tri[r[4] + 2 * tri_pair_upper(i, j) + (j & 1)], &Rb[(size_t)(r[7] + j) * nt]);
+      for (int a = 0; a < h; ++a) {
+        const double* xa = row(up.ridx[r[6] + a]);
+        if (!xa) return false;
+        axpy(acc.data(), -up.val[r[5] + 2 * ((int64_t)(a >> 1) * w + i) + (a & 1)], xa);
+      }
       std::copy(acc.begin(), acc.end(), row(r[0]));
     }
   }
@@ -1514,16 +1531,28 @@ bool check_levels(const TriPacked& T, std::string& err) {
           }
     }
     if (T.lower)
-      for (int m = T.push_ptr[l]; m < T.push_ptr[l + 1]; ++m)
-        if (lev[T.prec[(size_t)4 * m]] <= l) {
+      for (int m = T.push_ptr[l]; m < T.push_ptr[l + 1]; ++m) {
+        const int32_t* q = &T.prec[(size_t)4 * m];
+        if (lev[q[0]] <= l) {
           err = "a lower update targets a row that is not solved after it";
           return false;
         }
-    for (int q = T.ent_ptr[l]; q < T.ent_ptr[l + 1]; ++q)
+        const int f = q[3], w = q[2] & 0xffff;
+        if (f < 0 || f + w > T.n || lev[f] != l || lev[f + w - 1] != l) {
+          err = "a lower update reads rows outside its level";
+          return false;
+        }
+      }
+    for (int q = T.ent_ptr[l]; q < T.ent_ptr[l + 1]; ++q) {
       if (lev[T.eidx[q]] <= l) {
         err = "an entry-form dependency is not across levels";
         return false;
       }
+      if (T.eloc[q] < 0 || T.eloc[q] >= T.n || lev[T.eloc[q]] != l) {
+        err = "an entry-form row is outside its level";
+        return false;
+      }
+    }
   }
   return true;
 }

@@ -77,9 +77,10 @@ constexpr int kNarrowWidthC = PSLR_NARROW_C;
 // triangle item into C_T chunks and of every panel item into C_P chunks
 // (chunks meet through atomic adds).  The off-diagonal part of a level is
 // stored as panels and, for levels of narrow supernodes (E = 1), also as
-// entries ent_ptr[l] .. ent_ptr[l+1] with one value and two indices each, so
+// entries ent_ptr[l] .. ent_ptr[l+1] with one value and two positions each, so
 // that every thread streams independent loads:
-//   lower: x[eidx] -= eval * s_{eloc}        upper: r_{eloc} -= eval * x[eidx]
+//   lower: x[eidx] -= eval * x0[eloc]        upper: x[eloc] -= eval * x[eidx]
+// (x0: the level's rows before its solve)
 // FP64 single-right-hand-side solves with working vectors in LDS use the
 // entries (one atomic add per entry is cheap there); other solves use the panels.  A
 // lower factor has push items push_ptr[l] .. push_ptr[l+1], one per panel row
@@ -91,7 +92,7 @@ constexpr int kNarrowWidthC = PSLR_NARROW_C;
 //   [6] ridx start   [7] level-local index of the supernode's first row
 // Push record (lower panel levels), 4 int32:
 //   [0] target position ridx[a]   [1] panel start + a   [2] w | (h << 16)
-//   [3] level-local index of the supernode's first row
+//   [3] position of the supernode's first row
 //
 // Triangles and panels store their columns in interleaved pairs (2c, 2c+1),
 // so that one load brings a lane two columns, and consecutive lanes
@@ -107,11 +108,14 @@ constexpr int kNarrowWidthC = PSLR_NARROW_C;
 // offset.  Entries follow the panel order within each supernode.
 // The push record's panel start [1] is a pair index (panel start / 2 + a).
 //
-// Lower solve (right-looking), per level: s_k = sum_j Tinv(i, j) x[f + j]
-// for every row item (x holds b minus the pushed updates), then x[p] = s_k and
-// x[ridx[a]] -= sum_j Lpanel(a, j) s_{first + j}.
-// Upper solve (left-looking), per level: r_k = x[p] - sum_a Upanel(i, a)
-// x[ridx[a]], then x[p] = sum_j Tinv(i, j) r_{first + j}.
+// Panels are stored folded with the inverted triangle (Pf = Lpanel Tinv for
+// lower factors, Tinv Upanel for upper ones), so that each level is one step
+// over values from before the level:
+// Lower solve (right-looking), per level, with x0 = x[f .. f+w-1] (b minus the
+// pushed updates): x[p] = sum_j Tinv(i, j) x0_j for every row item and
+// x[ridx[a]] -= sum_j Pf(a, j) x0_j for every push item.
+// Upper solve (left-looking), per level, with x0 the level's rows from the
+// lower solve: x[p] = sum_j Tinv(i, j) x0_{first + j} - sum_a Pf(i, a) x[ridx[a]].
 struct TriPacked {
   bool lower = true;
   int32_t n = 0, nlev = 0, max_lrows = 0;

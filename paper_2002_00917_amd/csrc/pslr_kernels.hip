@@ -153,24 +153,26 @@ __device__ __forceinline__ void entry_sweep(const double2* __restrict__ er, int 
 }
 
 // Solve one packed triangular factor of block `bi` in place on the vector tile
-// X (positions 0..n-1, R right-hand sides).  Rb is scratch of 2 * max_lrows * R
-// entries (two halves used by alternate levels, so that one level's chunk sums
-// can be cleared while the other's are read).  All threads of the workgroup
+// X (positions 0..n-1, R right-hand sides).  Rb is scratch of 3 * max_lrows * R
+// entries (thirds rotated over the levels).  All threads of the workgroup
 // must call it; it ends with a barrier.
 //
-// Lower factors run right-looking: per level, every row item forms
-// s_k = sum_j Tinv(i, j) x[f + j] (x already holds b minus all pushed updates),
-// then x[p] = s_k and every push item subtracts its panel row times s from
-// x[ridx[a]] (atomic adds: supernodes of a level may update the same rows).
-// Upper factors run left-looking: r_k = x[p] - sum_a Upanel(i, a) x[ridx[a]],
-// then x[p] = sum_j Tinv(i, j) r_j; r_k starts as x[p], copied one level ahead
-// (rows of later levels keep their input values until their own level).
-// Inner loops are split into CT / CP chunks whose partial sums meet through
-// atomic adds; levels of narrow supernodes use the entry form instead of
-// panels.
+// The panels are folded with the inverted triangles (see TriPacked), so each
+// level is one step between two barriers over values from before the level.
+// Lower factors run right-looking: every row item forms s_k = sum_j Tinv(i, j)
+// x[f + j] into the level's third of Rb while every push item subtracts
+// Pf(a, :) x[f ..] from x[ridx[a]] (atomic adds: supernodes of a level may
+// update the same rows); the level's s goes into x during the next level,
+// which reads none of its rows.  Upper factors run left-looking: x[p] =
+// sum_j Tinv(i, j) r_j - sum_a Pf(i, a) x[ridx[a]] with r the level's rows
+// before the level, copied into Rb one level ahead; where a level's products
+// are chunked or in entry form, x[p] starts at zero and every part adds
+// atomically.  Inner loops are split into CT / CP chunks whose partial sums
+// meet through atomic adds; levels of narrow supernodes use the entry form
+// instead of panels.
 //
-// Records do not depend on x, so each thread's first record of a sweep is
-// loaded before the barrier that precedes the sweep, and the record of its
+// Records do not depend on x, so each thread's first record of a level is
+// loaded before the barrier that precedes the level, and the record of its
 // next task while it works on the current one.
 template <typename T, int R, bool GX>
 __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift) {
@@ -187,13 +189,13 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
   const int32_t* ent_ptr = A.ent_ptr + B.lev_base;
   const double2* ent_rec = A.ent + B.ent_base;
   const int32_t* lev_c = A.lev_c + B.lev_base;
-  // records past the end of a sweep keep the previous values (they are never
-  // used); no zero constant stays live across the solve
-  const int4 z4 = make_int4(0, 0, 0, 0);
-  T* const Rh0 = Rb;
-  T* const Rh1 = Rb + (int64_t)R * B.max_lrows;
-  // first row record of this thread in the coming sweep: row tid % cnt
-  int4 f0 = z4, f1 = z4;
+  const int64_t RS = (int64_t)R * B.max_lrows;
+  // entry form for FP64 single right-hand sides in LDS (one atomic add per
+  // entry; in FP32 the two indices per value cost more than they save)
+  auto use_ent = [&](int l) { return sizeof(T) == 8 && R == 1 && !GX && ((lev_c[l] >> 16) & 1); };
+  // first row record of this thread in the coming level: row tid % cnt
+  // (records past the end of a level keep the previous values, never used)
+  int4 f0 = make_int4(0, 0, 0, 0), f1 = f0;
   {
     const int l0 = B.lower ? 0 : B.nlev - 1;
     const int b0 = lev_ptr[l0], c0 = lev_ptr[l0 + 1] - b0;
@@ -202,43 +204,39 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
       f1 = rec[2 * (b0 + tid % c0) + 1];
     }
   }
-  for (int li = 0; li < B.nlev; ++li) {
-    const int l = B.lower ? li : B.nlev - 1 - li;
-    const int b = lev_ptr[l];
-    const int cnt = lev_ptr[l + 1] - b;
-    int CT, CP;
-    level_chunks(lev_c[l], gshift, CT, CP);
-    // entry form for FP64 single right-hand sides in LDS (one atomic add per
-    // entry; in FP32 the two indices per value cost more than they save)
-    const bool ent = sizeof(T) == 8 && R == 1 && !GX && ((lev_c[l] >> 16) & 1);
-    T* Rc = (li & 1) ? Rh1 : Rh0;
-    T* Rn = (li & 1) ? Rh0 : Rh1;
-    int bn = 0, cntn = 0, CTn = 1, CPn = 1;
-    if (li + 1 < B.nlev) {
-      const int ln = B.lower ? l + 1 : l - 1;
-      bn = lev_ptr[ln];
-      cntn = lev_ptr[ln + 1] - bn;
-      level_chunks(lev_c[ln], gshift, CTn, CPn);
-    }
-    if (li == 0) {
-      if (B.lower) {
-        if (CT > 1) {
-          for (int e = tid; e < cnt * R; e += nthr) Rc[e] = (T)0;
-          __syncthreads();
-        }
-      } else {
-        for (int k = tid; k < cnt; k += nthr) {
-          const int p = k == tid ? f0.x : rec[2 * (b + k)].x;
-#pragma unroll
-          for (int r = 0; r < R; ++r) Rc[k * R + r] = X[p * R + r];
-        }
+  if (B.lower) {
+    int bp = 0, cntp = 0, pfx = 0;  // the previous level's rows and this thread's first position
+    T* Rp = Rb;
+    for (int l = 0; l < B.nlev; ++l) {
+      const int b = lev_ptr[l];
+      const int cnt = lev_ptr[l + 1] - b;
+      int CT, CP;
+      level_chunks(lev_c[l], gshift, CT, CP);
+      const bool ent = use_ent(l);
+      T* Rc = Rb + (l % 3) * RS;
+      T* Rn = Rb + ((l + 1) % 3) * RS;
+      int bn = 0, cntn = 0, CTn = 1, CPn = 1;
+      if (l + 1 < B.nlev) {
+        bn = lev_ptr[l + 1];
+        cntn = lev_ptr[l + 2] - bn;
+        level_chunks(lev_c[l + 1], gshift, CTn, CPn);
+      }
+      if (l == 0 && CT > 1) {
+        for (int e = tid; e < cnt * R; e += nthr) Rc[e] = (T)0;
         __syncthreads();
       }
-    }
-    if (B.lower) {
       const int pb = push_ptr[l], np = ent ? 0 : push_ptr[l + 1] - pb;
       int4 fq = f0;
       if (np > 0) fq = prec[pb + tid % np];
+      // the previous level's results into x; the next level's third cleared
+      // when its triangle items are chunked
+      for (int k = tid; k < cntp; k += nthr) {
+        const int p = k == tid ? pfx : rec[2 * (bp + k)].x;
+#pragma unroll
+        for (int r = 0; r < R; ++r) X[p * R + r] = Rp[k * R + r];
+      }
+      if (CTn > 1)
+        for (int e = tid; e < cntn * R; e += nthr) Rn[e] = (T)0;
       // s_k = Tinv(i, 0..i) x[f .. f+i]
       {
         int4 r0 = f0, r1 = f1;
@@ -263,8 +261,8 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
             const auto* M = reinterpret_cast<const typename Pair<T>::type*>(tri + r1.x);
             auto off = [=](int cc) { return cc * (w - cc + 1) + (i - 2 * cc); };
             const T* S = X + (int64_t)(r0.x - i) * R;
-            const int np = (ncol + 1) >> 1;
-            pair_dot<T, R>(M, off, j0 >> 1, 1, np, (ncol & 1) ? np - 1 : -1, S, acc);
+            const int npr = (ncol + 1) >> 1;
+            pair_dot<T, R>(M, off, j0 >> 1, 1, npr, (ncol & 1) ? npr - 1 : -1, S, acc);
           }
           if (CT == 1) {
 #pragma unroll
@@ -277,15 +275,8 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
           r1 = n1;
         }
       }
-      __syncthreads();
-      // x[p] = s_k
-      for (int k = tid; k < cnt; k += nthr) {
-        const int p = k == tid ? f0.x : rec[2 * (b + k)].x;
-#pragma unroll
-        for (int r = 0; r < R; ++r) X[p * R + r] = Rc[k * R + r];
-      }
-      // x[ridx[a]] -= Lpanel(a, :) s
-      if (ent) entry_sweep<T, R>(ent_rec, ent_ptr[l], ent_ptr[l + 1], X, Rc, true);
+      // x[ridx[a]] -= Pf(a, :) x[f ..]
+      if (ent) entry_sweep<T, R>(ent_rec, ent_ptr[l], ent_ptr[l + 1], X, X, true);
       {
         int4 q = fq;
         for (int t = tid; t < np * CP; t += nthr) {
@@ -302,100 +293,153 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
             // panel row a: pair c at pair index q.y + c h
             const auto* M = reinterpret_cast<const typename Pair<T>::type*>(pan) + q.y;
             auto off = [=](int cc) { return cc * h; };
-            const T* S = Rc + (int64_t)q.w * R;
+            const T* S = X + (int64_t)q.w * R;
             const int ncol = j1 - j0;
-            const int np = (ncol + 1) >> 1;
-            pair_dot<T, R>(M, off, j0 >> 1, 1, np, (ncol & 1) ? np - 1 : -1, S, acc);
+            const int npr = (ncol + 1) >> 1;
+            pair_dot<T, R>(M, off, j0 >> 1, 1, npr, (ncol & 1) ? npr - 1 : -1, S, acc);
 #pragma unroll
             for (int r = 0; r < R; ++r) atomic_add(&X[q.x * R + r], -acc[r]);
           }
           q = qn;
         }
       }
-      if (CTn > 1)
-        for (int e = tid; e < cntn * R; e += nthr) Rn[e] = (T)0;
+      bp = b;
+      cntp = cnt;
+      pfx = f0.x;
+      Rp = Rc;
       if (cntn > 0) {
         f0 = rec[2 * (bn + tid % cntn)];
         f1 = rec[2 * (bn + tid % cntn) + 1];
       }
       __syncthreads();
-    } else {
-      // r_k = x[p] - Upanel(i, :) x[ridx]
-      {
-        int4 r0 = f0, r1 = f1;
-        for (int t = tid; t < (ent ? 0 : cnt * CP); t += nthr) {
-          const int tn = t + nthr;
-          int4 n0 = r0, n1 = r1;
-          if (tn < cnt * CP) {
-            n0 = rec[2 * (b + tn % cnt)];
-            n1 = rec[2 * (b + tn % cnt) + 1];
-          }
-          const int c = t / cnt, k = t - c * cnt;
-          const int i = r0.y, w = r0.z, h = r0.w;
-          const int Lc = pair_chunk(h, CP);
-          const int a0 = c * Lc, a1 = min(h, a0 + Lc);
-          // row i: pair g (columns 2g, 2g + 1) at pair index g w + i, positions
-          // ridx[2g], ridx[2g + 1] (an odd last column pairs with a zero value
-          // and a repeated position)
-          const auto* pc = reinterpret_cast<const typename Pair<T>::type*>(pan + r1.y) + i;
-          const int2* rc = reinterpret_cast<const int2*>(ridx + r1.z);
-          T acc[R];
+    }
+    for (int k = tid; k < cntp; k += nthr) {
+      const int p = k == tid ? pfx : rec[2 * (bp + k)].x;
 #pragma unroll
-          for (int r = 0; r < R; ++r) acc[r] = 0;
-          constexpr int U = R == 1 ? PSLR_PAIR_U : 2;
-          int g = a0 >> 1;
-          const int g1 = (a1 + 1) >> 1;
-          for (; g + U <= g1; g += U) {
-            typename Pair<T>::type v[U];
-            int2 cc[U];
+      for (int r = 0; r < R; ++r) X[p * R + r] = Rp[k * R + r];
+    }
+    __syncthreads();
+    return;
+  }
+  // upper: levels from the top; Rc holds the level's rows before the level
+  auto joint = [&](int l) {
+    int ct, cp;
+    level_chunks(lev_c[l], gshift, ct, cp);
+    return ct == 1 && cp == 1 && !use_ent(l);
+  };
+  {
+    const int l = B.nlev - 1;
+    const int b = lev_ptr[l], cnt = lev_ptr[l + 1] - b;
+    const bool jn = joint(l);
+    for (int k = tid; k < cnt; k += nthr) {
+      const int p = k == tid ? f0.x : rec[2 * (b + k)].x;
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-              v[u] = pc[(g + u) * w];
-              cc[u] = rc[g + u];
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-#pragma unroll
-              for (int r = 0; r < R; ++r) acc[r] += v[u].x * X[cc[u].x * R + r] + v[u].y * X[cc[u].y * R + r];
-          }
-          if (g < g1) {
-            // last round masked (slots past g1 re-read pair g1 - 1, products dropped)
-            typename Pair<T>::type v[U];
-            int2 cc[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-              v[u] = pc[min(g + u, g1 - 1) * w];
-              cc[u] = rc[min(g + u, g1 - 1)];
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-#pragma unroll
-              for (int r = 0; r < R; ++r) {
-                const T a = v[u].x * X[cc[u].x * R + r] + v[u].y * X[cc[u].y * R + r];
-                acc[r] += g + u < g1 ? a : (T)0;
-              }
-          }
-          if (CP == 1) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) Rc[k * R + r] -= acc[r];
-          } else if (a0 < a1) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) atomic_add(&Rc[k * R + r], -acc[r]);
-          }
-          r0 = n0;
-          r1 = n1;
-        }
+      for (int r = 0; r < R; ++r) {
+        Rb[k * R + r] = X[p * R + r];
+        if (!jn) X[p * R + r] = (T)0;
       }
-      if (ent) entry_sweep<T, R>(ent_rec, ent_ptr[l], ent_ptr[l + 1], Rc, X, false);
-      // rows whose triangle products are chunked accumulate into x[p]
-      if (CT > 1)
-        for (int k = tid; k < cnt; k += nthr) {
-          const int p = k == tid ? f0.x : rec[2 * (b + k)].x;
+    }
+    __syncthreads();
+  }
+  for (int li = 0; li < B.nlev; ++li) {
+    const int l = B.nlev - 1 - li;
+    const int b = lev_ptr[l];
+    const int cnt = lev_ptr[l + 1] - b;
+    int CT, CP;
+    level_chunks(lev_c[l], gshift, CT, CP);
+    const bool ent = use_ent(l);
+    const bool jn = CT == 1 && CP == 1 && !ent;
+    T* Rc = Rb + (li & 1) * RS;
+    T* Rn = Rb + ((li + 1) & 1) * RS;
+    int bn = 0, cntn = 0;
+    if (l > 0) {
+      bn = lev_ptr[l - 1];
+      cntn = lev_ptr[l] - bn;
+    }
+    // the triangle part of row item t of chunk c over columns [j0, j1)
+    auto tri_part = [&](const int4& r0, const int4& r1, int c, int CTc, T (&acc)[R]) {
+      const int i = r0.y, w = r0.z;
+      const int Lc = pair_chunk(w, CTc);
+      const int j0 = c * Lc, j1 = min(w, j0 + Lc);
+      // columns j1-1 down to jlo = max(j0, i), a common start for the lanes;
+      // pair c of an upper triangle holds rows 0 .. 2c+1 at pair index
+      // c (c + 1) + i (entries left of the diagonal are zeros).  An odd j1
+      // (= w) leaves the top pair with one column.
+      const int jlo = max(j0, i);
+      const auto* M = reinterpret_cast<const typename Pair<T>::type*>(tri + r1.x);
+      auto off = [=](int cc) { return cc * (cc + 1) + i; };
+      const T* S = Rc + (int64_t)r1.w * R;
+      const int top = (j1 & 1) ? (j1 >> 1) : (j1 >> 1) - 1;
+      const int npr = jlo < j1 ? top - (jlo >> 1) + 1 : 0;
+      if (npr > 0) pair_dot<T, R>(M, off, top, -1, npr, (j1 & 1) ? 0 : -1, S, acc);
+      return j1 > i;
+    };
+    // the panel part: acc += Pf(i, a0 .. a1-1) x[ridx[a0 .. a1-1]]
+    auto pan_part = [&](const int4& r0, const int4& r1, int c, int CPc, T (&acc)[R]) {
+      const int i = r0.y, w = r0.z, h = r0.w;
+      const int Lc = pair_chunk(h, CPc);
+      const int a0 = c * Lc, a1 = min(h, a0 + Lc);
+      // row i: pair g (columns 2g, 2g + 1) at pair index g w + i, positions
+      // ridx[2g], ridx[2g + 1] (an odd last column pairs with a zero value
+      // and a repeated position)
+      const auto* pc = reinterpret_cast<const typename Pair<T>::type*>(pan + r1.y) + i;
+      const int2* rc = reinterpret_cast<const int2*>(ridx + r1.z);
+      constexpr int U = R == 1 ? PSLR_PAIR_U : 2;
+      int g = a0 >> 1;
+      const int g1 = (a1 + 1) >> 1;
+      for (; g + U <= g1; g += U) {
+        typename Pair<T>::type v[U];
+        int2 cc[U];
 #pragma unroll
-          for (int r = 0; r < R; ++r) X[p * R + r] = (T)0;
+        for (int u = 0; u < U; ++u) {
+          v[u] = pc[(g + u) * w];
+          cc[u] = rc[g + u];
         }
-      __syncthreads();
-      // x[p] = Tinv(i, i..w-1) r
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int r = 0; r < R; ++r) acc[r] += v[u].x * X[cc[u].x * R + r] + v[u].y * X[cc[u].y * R + r];
+      }
+      if (g < g1) {
+        // last round masked (slots past g1 re-read pair g1 - 1, products dropped)
+        typename Pair<T>::type v[U];
+        int2 cc[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          v[u] = pc[min(g + u, g1 - 1) * w];
+          cc[u] = rc[min(g + u, g1 - 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const T a = v[u].x * X[cc[u].x * R + r] + v[u].y * X[cc[u].y * R + r];
+            acc[r] += g + u < g1 ? a : (T)0;
+          }
+      }
+      return a0 < a1;
+    };
+    if (jn) {
+      // one item per row: x[p] = Tinv(i, :) r - Pf(i, :) x[ridx]
+      int4 r0 = f0, r1 = f1;
+      for (int t = tid; t < cnt; t += nthr) {
+        const int tn = t + nthr;
+        int4 n0 = r0, n1 = r1;
+        if (tn < cnt) {
+          n0 = rec[2 * (b + tn)];
+          n1 = rec[2 * (b + tn) + 1];
+        }
+        T at[R], ap[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) at[r] = ap[r] = 0;
+        tri_part(r0, r1, 0, 1, at);
+        pan_part(r0, r1, 0, 1, ap);
+#pragma unroll
+        for (int r = 0; r < R; ++r) X[r0.x * R + r] = at[r] - ap[r];
+        r0 = n0;
+        r1 = n1;
+      }
+    } else {
       {
         int4 r0 = f0, r1 = f1;
         for (int t = tid; t < cnt * CT; t += nthr) {
@@ -405,50 +449,54 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
             n0 = rec[2 * (b + tn % cnt)];
             n1 = rec[2 * (b + tn % cnt) + 1];
           }
-          const int c = t / cnt;
-          const int p = r0.x, i = r0.y, w = r0.z;
-          const int Lc = pair_chunk(w, CT);
-          const int j0 = c * Lc, j1 = min(w, j0 + Lc);
           T acc[R];
 #pragma unroll
           for (int r = 0; r < R; ++r) acc[r] = 0;
-          // columns j1-1 down to jlo = max(j0, i), a common start for the
-          // lanes; pair c of an upper triangle holds rows 0 .. 2c+1 at pair
-          // index c (c + 1) + i (entries left of the diagonal are zeros).  An
-          // odd j1 (= w) leaves the top pair with one column.
-          {
-            const int jlo = max(j0, i);
-            const auto* M = reinterpret_cast<const typename Pair<T>::type*>(tri + r1.x);
-            auto off = [=](int cc) { return cc * (cc + 1) + i; };
-            const T* S = Rc + (int64_t)r1.w * R;
-            // from the top pair (one column when j1 is odd) down to pair jlo / 2
-            const int top = (j1 & 1) ? (j1 >> 1) : (j1 >> 1) - 1;
-            const int np = jlo < j1 ? top - (jlo >> 1) + 1 : 0;
-            if (np > 0) pair_dot<T, R>(M, off, top, -1, np, (j1 & 1) ? 0 : -1, S, acc);
-          }
-          if (CT == 1) {
+          if (tri_part(r0, r1, t / cnt, CT, acc))
 #pragma unroll
-            for (int r = 0; r < R; ++r) X[p * R + r] = acc[r];
-          } else if (j1 > i) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) atomic_add(&X[p * R + r], acc[r]);
-          }
+            for (int r = 0; r < R; ++r) atomic_add(&X[r0.x * R + r], acc[r]);
           r0 = n0;
           r1 = n1;
         }
       }
-      if (cntn > 0) {
-        f0 = rec[2 * (bn + tid % cntn)];
-        f1 = rec[2 * (bn + tid % cntn) + 1];
+      if (ent) {
+        entry_sweep<T, R>(ent_rec, ent_ptr[l], ent_ptr[l + 1], X, X, false);
+      } else {
+        int4 r0 = f0, r1 = f1;
+        for (int t = tid; t < cnt * CP; t += nthr) {
+          const int tn = t + nthr;
+          int4 n0 = r0, n1 = r1;
+          if (tn < cnt * CP) {
+            n0 = rec[2 * (b + tn % cnt)];
+            n1 = rec[2 * (b + tn % cnt) + 1];
+          }
+          T acc[R];
+#pragma unroll
+          for (int r = 0; r < R; ++r) acc[r] = 0;
+          if (pan_part(r0, r1, t / cnt, CP, acc))
+#pragma unroll
+            for (int r = 0; r < R; ++r) atomic_add(&X[r0.x * R + r], -acc[r]);
+          r0 = n0;
+          r1 = n1;
+        }
       }
-      // r of the next level starts as its rows' (untouched) x values
+    }
+    // the next level's rows before it into Rn (cleared in x where its parts
+    // add atomically); its first records
+    if (cntn > 0) {
+      f0 = rec[2 * (bn + tid % cntn)];
+      f1 = rec[2 * (bn + tid % cntn) + 1];
+      const bool jnn = joint(l - 1);
       for (int k = tid; k < cntn; k += nthr) {
         const int p = k == tid ? f0.x : rec[2 * (bn + k)].x;
 #pragma unroll
-        for (int r = 0; r < R; ++r) Rn[k * R + r] = X[p * R + r];
+        for (int r = 0; r < R; ++r) {
+          Rn[k * R + r] = X[p * R + r];
+          if (!jnn) X[p * R + r] = (T)0;
+        }
       }
-      __syncthreads();
     }
+    __syncthreads();
   }
 }
 
@@ -476,7 +524,7 @@ __device__ Lds<T> carve(const ApplyArrays<T>& A) {
     extern __shared__ __align__(16) unsigned char smem[];
     L.XB = reinterpret_cast<T*>(smem);
     L.Rb = L.XB + R * A.maxPB;
-    L.XC = L.Rb + 2 * R * A.maxLR;
+    L.XC = L.Rb + 3 * R * A.maxLR;
     L.U = L.XC + R * A.maxQB;
     L.W = L.U + R * A.maxQB;
   }
