@@ -192,7 +192,7 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
   const int64_t RS = (int64_t)R * B.max_lrows;
   // entry form for FP64 single right-hand sides in LDS (one atomic add per
   // entry; in FP32 the two indices per value cost more than they save)
-  auto use_ent = [&](int l) { return sizeof(T) == 8 && R == 1 && !GX && ((lev_c[l] >> 16) & 1); };
+  auto use_ent = [&](int l) __attribute__((always_inline)) { return sizeof(T) == 8 && R == 1 && !GX && ((lev_c[l] >> 16) & 1); };
   // first row record of this thread in the coming level: row tid % cnt
   // (records past the end of a level keep the previous values, never used)
   int4 f0 = make_int4(0, 0, 0, 0), f1 = f0;
@@ -322,7 +322,7 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
     return;
   }
   // upper: levels from the top; Rc holds the level's rows before the level
-  auto joint = [&](int l) {
+  auto joint = [&](int l) __attribute__((always_inline)) {
     int ct, cp;
     level_chunks(lev_c[l], gshift, ct, cp);
     return ct == 1 && cp == 1 && !use_ent(l);
@@ -357,7 +357,7 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
       cntn = lev_ptr[l] - bn;
     }
     // the triangle part of row item t of chunk c over columns [j0, j1)
-    auto tri_part = [&](const int4& r0, const int4& r1, int c, int CTc, T (&acc)[R]) {
+    auto tri_part = [&](int4 r0, int4 r1, int c, int CTc, T (&acc)[R]) __attribute__((always_inline)) {
       const int i = r0.y, w = r0.z;
       const int Lc = pair_chunk(w, CTc);
       const int j0 = c * Lc, j1 = min(w, j0 + Lc);
@@ -375,7 +375,7 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
       return j1 > i;
     };
     // the panel part: acc += Pf(i, a0 .. a1-1) x[ridx[a0 .. a1-1]]
-    auto pan_part = [&](const int4& r0, const int4& r1, int c, int CPc, T (&acc)[R]) {
+    auto pan_part = [&](int4 r0, int4 r1, int c, int CPc, T (&acc)[R]) __attribute__((always_inline)) {
       const int i = r0.y, w = r0.z, h = r0.w;
       const int Lc = pair_chunk(h, CPc);
       const int a0 = c * Lc, a1 = min(h, a0 + Lc);
