@@ -1185,8 +1185,9 @@ bool pack_tri(const TriHost& T, TriPacked& P, int narrow_width) {
     P.read_vals[q] += tri_vals;
     P.read_ints[q] += (int64_t)P.rec.size() + 4 * (int64_t)(T.nlev + 1);
   }
-  // record fields are int32 offsets into the block's arrays
-  return P.val.size() < (size_t)INT32_MAX && P.tri.size() < (size_t)INT32_MAX &&
+  // record fields are int32 offsets into the block's arrays, and the device
+  // addresses a block's values with 32-bit byte offsets (FP64: below 2^29 values)
+  return P.val.size() < ((size_t)1 << 29) && P.tri.size() < ((size_t)1 << 29) &&
          P.ridx.size() < (size_t)INT32_MAX && P.eval.size() < (size_t)INT32_MAX;
 }
 

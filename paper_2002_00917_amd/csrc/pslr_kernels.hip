@@ -82,37 +82,59 @@ struct Pair<float> {
 // column only: its second stored value is a zero (across the diagonal, or
 // padding), and S is read at its first column instead of the second, which
 // the lane does not own.
-template <typename T, int R, typename Off>
-__device__ __forceinline__ void pair_dot(const typename Pair<T>::type* __restrict__ M, Off off, int c0,
-                                         int d, int np, int half_t, const T* S, T (&acc)[R]) {
+// The walk uses 32-bit pair indices from a block-uniform base (so that every
+// load is a uniform base plus a 32-bit lane offset): pair t of
+// the walk is Mb[o_t] with o_{t+1} = o_t + delta_t and delta_{t+1} = delta_t +
+// dd (a triangle's column pairs are a quadratic sequence, a panel's an
+// arithmetic one); its columns are S[t * ds] and S[t * ds + R] (S[t * ds]
+// twice at t = half_t).
+// base[idx] with a 32-bit byte offset, so that the load can take the form
+// "uniform base + 32-bit lane offset" (a block's packed arrays stay below 4 GiB)
+template <typename V>
+__device__ __forceinline__ V ld32(const V* __restrict__ base, uint32_t idx) {
+  return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + (uint32_t)(idx * (uint32_t)sizeof(V)));
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void pair_walk(const typename Pair<T>::type* __restrict__ Mb, uint32_t o,
+                                          int delta, int dd, int np, int half_t, const T* S, int ds,
+                                          T (&acc)[R]) {
   constexpr int U = R == 1 ? PSLR_PAIR_U : 2;
   int t = 0;
   for (; t + U <= np; t += U) {
     typename Pair<T>::type v[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) v[u] = M[off(c0 + d * (t + u))];
+    for (int u = 0; u < U; ++u) {
+      v[u] = ld32(Mb, o);
+      o += (uint32_t)delta;
+      delta += dd;
+    }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int j = 2 * (c0 + d * (t + u));
-      const int j2 = t + u == half_t ? j : j + 1;
+      const T* s = S + (t + u) * ds;
+      const int k2 = t + u == half_t ? 0 : R;
 #pragma unroll
-      for (int r = 0; r < R; ++r) acc[r] += v[u].x * S[j * R + r] + v[u].y * S[j2 * R + r];
+      for (int r = 0; r < R; ++r) acc[r] += v[u].x * s[r] + v[u].y * s[k2 + r];
     }
   }
   if (t < np) {
-    // last round masked rather than one pair at a time: every slot loads
-    // (slots past np re-read pair np - 1) and the extra products are dropped
+    // last round masked: slots past np re-read pair np - 1, products dropped
     typename Pair<T>::type v[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) v[u] = M[off(c0 + d * min(t + u, np - 1))];
+    for (int u = 0; u < U; ++u) {
+      v[u] = ld32(Mb, o);
+      const bool adv = t + u + 1 < np;
+      o += adv ? (uint32_t)delta : 0u;
+      delta += adv ? dd : 0;
+    }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int tu = min(t + u, np - 1);
-      const int j = 2 * (c0 + d * tu);
-      const int j2 = tu == half_t ? j : j + 1;
+      const T* s = S + tu * ds;
+      const int k2 = tu == half_t ? 0 : R;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const T a = v[u].x * S[j * R + r] + v[u].y * S[j2 * R + r];
+        const T a = v[u].x * s[r] + v[u].y * s[k2 + r];
         acc[r] += t + u < np ? a : (T)0;
       }
     }
@@ -126,10 +148,14 @@ __device__ __forceinline__ int pair_chunk(int len, int C) { return (((len + C - 
 // D[dst(e)] -= v[e] * S[src(e)] with atomic adds.  Every entry is one 16-byte
 // record (value, target/source position, level-local row), loaded with one
 // instruction; each thread keeps U of them in flight.
+#ifndef PSLR_ENT_U
+#define PSLR_ENT_U 4
+#endif
+
 template <typename T, int R>
 __device__ __forceinline__ void entry_sweep(const double2* __restrict__ er, int e0, int e1, T* D,
                                             const T* S, bool lower) {
-  constexpr int U = 4;
+  constexpr int U = PSLR_ENT_U;
   const int tid = threadIdx.x, nthr = blockDim.x;
   for (int e = e0 + tid; e < e1; e += U * nthr) {
     // unconditional loads and adds, so that the compiler keeps all U loads in
@@ -258,11 +284,12 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
           // rows 2c .. w-1 at pair index c (w - c + 1) + (i - 2c)
           const int ncol = min(j1, i + 1) - j0;
           if (ncol > 0) {
-            const auto* M = reinterpret_cast<const typename Pair<T>::type*>(tri + r1.x);
-            auto off = [=](int cc) { return cc * (w - cc + 1) + (i - 2 * cc); };
-            const T* S = X + (int64_t)(r0.x - i) * R;
+            const int c0 = j0 >> 1;
+            const uint32_t o = (uint32_t)(r1.x >> 1) + (uint32_t)(c0 * (w - c0 + 1) + (i - 2 * c0));
+            const T* S = X + (int64_t)(r0.x - i + 2 * c0) * R;
             const int npr = (ncol + 1) >> 1;
-            pair_dot<T, R>(M, off, j0 >> 1, 1, npr, (ncol & 1) ? npr - 1 : -1, S, acc);
+            pair_walk<T, R>(reinterpret_cast<const typename Pair<T>::type*>(tri), o, w - 2 * c0 - 2, -2, npr,
+                            (ncol & 1) ? npr - 1 : -1, S, 2 * R, acc);
           }
           if (CT == 1) {
 #pragma unroll
@@ -291,12 +318,12 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
 #pragma unroll
             for (int r = 0; r < R; ++r) acc[r] = 0;
             // panel row a: pair c at pair index q.y + c h
-            const auto* M = reinterpret_cast<const typename Pair<T>::type*>(pan) + q.y;
-            auto off = [=](int cc) { return cc * h; };
-            const T* S = X + (int64_t)q.w * R;
+            const int c0 = j0 >> 1;
+            const T* S = X + (int64_t)(q.w + 2 * c0) * R;
             const int ncol = j1 - j0;
             const int npr = (ncol + 1) >> 1;
-            pair_dot<T, R>(M, off, j0 >> 1, 1, npr, (ncol & 1) ? npr - 1 : -1, S, acc);
+            pair_walk<T, R>(reinterpret_cast<const typename Pair<T>::type*>(pan), (uint32_t)(q.y + c0 * h), h, 0,
+                            npr, (ncol & 1) ? npr - 1 : -1, S, 2 * R, acc);
 #pragma unroll
             for (int r = 0; r < R; ++r) atomic_add(&X[q.x * R + r], -acc[r]);
           }
@@ -366,12 +393,13 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
       // c (c + 1) + i (entries left of the diagonal are zeros).  An odd j1
       // (= w) leaves the top pair with one column.
       const int jlo = max(j0, i);
-      const auto* M = reinterpret_cast<const typename Pair<T>::type*>(tri + r1.x);
-      auto off = [=](int cc) { return cc * (cc + 1) + i; };
-      const T* S = Rc + (int64_t)r1.w * R;
       const int top = (j1 & 1) ? (j1 >> 1) : (j1 >> 1) - 1;
       const int npr = jlo < j1 ? top - (jlo >> 1) + 1 : 0;
-      if (npr > 0) pair_dot<T, R>(M, off, top, -1, npr, (j1 & 1) ? 0 : -1, S, acc);
+      const T* S = Rc + (int64_t)(r1.w + 2 * top) * R;
+      const uint32_t o = (uint32_t)(r1.x >> 1) + (uint32_t)(top * (top + 1) + i);
+      if (npr > 0)
+        pair_walk<T, R>(reinterpret_cast<const typename Pair<T>::type*>(tri), o, -2 * top, 2, npr,
+                        (j1 & 1) ? 0 : -1, S, -2 * R, acc);
       return j1 > i;
     };
     // the panel part: acc += Pf(i, a0 .. a1-1) x[ridx[a0 .. a1-1]]
@@ -382,8 +410,10 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
       // row i: pair g (columns 2g, 2g + 1) at pair index g w + i, positions
       // ridx[2g], ridx[2g + 1] (an odd last column pairs with a zero value
       // and a repeated position)
-      const auto* pc = reinterpret_cast<const typename Pair<T>::type*>(pan + r1.y) + i;
-      const int2* rc = reinterpret_cast<const int2*>(ridx + r1.z);
+      // (32-bit pair indices from the block-uniform bases pan and ridx)
+      const auto* pc = reinterpret_cast<const typename Pair<T>::type*>(pan);
+      const int2* rc = reinterpret_cast<const int2*>(ridx);
+      const uint32_t pbase = (uint32_t)((r1.y >> 1) + i), rbase = (uint32_t)(r1.z >> 1);
       constexpr int U = R == 1 ? PSLR_PAIR_U : 2;
       int g = a0 >> 1;
       const int g1 = (a1 + 1) >> 1;
@@ -392,8 +422,8 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
         int2 cc[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          v[u] = pc[(g + u) * w];
-          cc[u] = rc[g + u];
+          v[u] = ld32(pc, pbase + (uint32_t)((g + u) * w));
+          cc[u] = ld32(rc, rbase + (uint32_t)(g + u));
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
@@ -406,8 +436,8 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
         int2 cc[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          v[u] = pc[min(g + u, g1 - 1) * w];
-          cc[u] = rc[min(g + u, g1 - 1)];
+          v[u] = ld32(pc, pbase + (uint32_t)(min(g + u, g1 - 1) * w));
+          cc[u] = ld32(rc, rbase + (uint32_t)min(g + u, g1 - 1));
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
