@@ -497,8 +497,20 @@ std::vector<int> team_groups(const std::vector<int>& spar, const std::vector<dou
 }
 
 // Bottom-up amalgamation: merged supernodes of at most kMergeWidth rows, at
-// most kMergePasses rounds (each removes one level at the bottom).
-constexpr int kMergeWidth = 16, kMergePasses = 3;
+// most kMergePasses rounds (each removes one level at the bottom).  Width 32
+// was the fastest of 16, 32, 64 and 128 on the 64^3 workload with team solves
+// (fewer levels against more stored zeros); the build-time overrides serve
+// such sweeps.
+#ifndef PSLR_MERGE_W
+#define PSLR_MERGE_W 32
+#endif
+#ifndef PSLR_MERGE_P
+#define PSLR_MERGE_P 3
+#endif
+#ifndef PSLR_CHAIN_FILL
+#define PSLR_CHAIN_FILL 0.15
+#endif
+constexpr int kMergeWidth = PSLR_MERGE_W, kMergePasses = PSLR_MERGE_P;
 
 int factor_block(const CsrL& M, double tau, bool want_T, int narrow_width, BlockFactor& out,
                  std::string& err, int team) {
@@ -610,7 +622,7 @@ int factor_block(const CsrL& M, double tau, bool want_T, int narrow_width, Block
       const double hp = (double)st[sfirst[s + 1] - 1].size();
       const double dense = mw * (mw - 1) / 2 + mw * hp;
       const double tnz = truenz[c] + truenz[s];
-      if (mw <= 512 && (mw <= 16 || dense - tnz <= 0.15 * dense)) {
+      if (mw <= 512 && (mw <= 16 || dense - tnz <= PSLR_CHAIN_FILL * dense)) {
         gfirst[s] = gfirst[c];
         truenz[s] = tnz;
         absorbed[c] = 1;
