@@ -20,9 +20,12 @@ the paper's own local factors (threshold ILU, drop 1e-2), the batched
 workload (48 uneven systems, 8 right-hand sides each), the 128^3 upwind
 convection-diffusion workload at 32 right-hand sides and the forward+adjoint
 time of the differentiable solve are reported beside it.  The roofline entry
-is for the dominant kernel, the fused power-series step (one B_i solve, one
-C_i solve and the E, F, C_g products per subdomain): algorithmic bytes per
-launch over its mean HIP-event duration measured during the timed solves.
+is for the dominant kernel sequence, the power-series step: with one
+right-hand side it is six back-to-back launches (the team-split B_i solve as
+subtree lower solves, the top groups' dense-inverse product and subtree
+upper solves, then the same three for C_i with the E, F, C_g products fused
+into them); algorithmic bytes per step over its mean HIP-event span (first
+launch start to last launch end) measured during the timed solves.
 The CPU baseline times the FP64 oracle on the host cores.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--forms a,b] [--no-cpu]
@@ -43,11 +46,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "PSLR-FGMRES solves/s to rel-res 1e-8 (FP64 vs mixed/batched); apply HBM GB/s"
 HBM_PEAK_GBS = 8000.0
-# what decides the data a k_series launch reads: the kernels and the host
-# packing of the factors (layouts, entry-form thresholds)
+# what decides the data a power-series step reads: the kernels, the host
+# packing of the factors (layouts, entry-form thresholds, team groups, top
+# inverses) and the upload choosing the top groups' form
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2002_00917_amd", "csrc", f)
-               for f in ("pslr_kernels.hip", "pslr_host.cpp", "pslr_host.h")]
-PMC_FILE = os.path.join(ROOT, "profiles", "k_series_lap3d64_pmc.txt")
+               for f in ("pslr_kernels.hip", "pslr_host.cpp", "pslr_host.h", "pslr_api.hip")]
+PMC_FILE = os.path.join(ROOT, "profiles", "series_step_lap3d64_pmc.txt")
 
 # C2 forms: (precision, low-rank construction, restart, local factor, default timed solves)
 FORMS = {
@@ -76,7 +80,7 @@ def kernel_hash():
 
 
 def measured_traffic():
-    """HBM bytes per k_series launch from the committed rocprofv3 counter summary, if current."""
+    """HBM bytes per power-series step from the committed rocprofv3 counter summary, if current."""
     try:
         with open(PMC_FILE) as fh:
             kv = dict(line.split(" = ", 1) for line in fh.read().splitlines() if " = " in line)
@@ -489,7 +493,8 @@ def main():
                    "n": A.n, "nnz": A.nnz, "nparts": 64, "m": m, "rank_requested": rank,
                    "rank": info["rank"], "lowrank": head["lowrank"], "restart": head["restart"],
                    "nrhs": 1},
-        "roofline": {"bound": "hbm", "kernel": "k_series (one power-series step)",
+        "roofline": {"bound": "hbm",
+                     "kernel": "power-series step (k_team_lower/topinv/upper for B_i, then C_i)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "algorithmic_bytes_per_launch": series_bytes,

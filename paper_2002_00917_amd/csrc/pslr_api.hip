@@ -1845,9 +1845,9 @@ pslr_status pslr_host_stats(int64_t n, const int64_t* rowptr, const int32_t* col
         for (int k = 0; k < nt; ++k) d[k] = X2[f.loS[f.team].rec[(size_t)8 * k]];
         for (int r = 0; r < nt; ++r) {
           double acc = 0.0;
+          const size_t ld = (size_t)top_ld(nt);
           for (int c = 0; c < (nt + 1) / 2; ++c)
-            acc += f.topinv[2 * ((size_t)c * nt + r)] * d[2 * c] +
-                   f.topinv[2 * ((size_t)c * nt + r) + 1] * d[2 * c + 1];
+            acc += f.topinv[2 * (c * ld + r)] * d[2 * c] + f.topinv[2 * (c * ld + r) + 1] * d[2 * c + 1];
           X2[f.loS[f.team].rec[(size_t)8 * r]] = acc;
         }
         for (int g = 0; g < f.team; ++g) host_tri_solve(f.upS[g], X2, true);

@@ -1338,11 +1338,12 @@ bool top_inverse(const TriPacked& lo, const TriPacked& up, int n, std::vector<do
       std::copy(acc.begin(), acc.end(), row(r[0]));
     }
   }
-  // column pairs: (r, j) at 2 ((j / 2) nt + r) + (j % 2); an odd last column pairs with zeros
-  const int np = (nt + 1) / 2;
-  M.assign((size_t)2 * np * nt, 0.0);
+  // column pairs: (r, j) at 2 ((j / 2) ld + r) + (j % 2) with ld = top_ld(nt);
+  // an odd last column and the rows past nt are zeros
+  const int np = (nt + 1) / 2, ld = top_ld(nt);
+  M.assign((size_t)2 * np * ld, 0.0);
   for (int r = 0; r < nt; ++r)
-    for (int j = 0; j < nt; ++j) M[2 * ((size_t)(j >> 1) * nt + r) + (j & 1)] = X[(size_t)r * nt + j];
+    for (int j = 0; j < nt; ++j) M[2 * ((size_t)(j >> 1) * ld + r) + (j & 1)] = X[(size_t)r * nt + j];
   return true;
 }
 

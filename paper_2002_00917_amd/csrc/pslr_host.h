@@ -156,7 +156,8 @@ struct BlockFactor {
   // ancestor of its supernodes, so L[G, T] = 0 and U[T, G] = 0 for the other
   // positions G, and the solve gives x_T = (L_TT U_TT)^{-1} (b_T - L_TG y_G)
   // with y_G the subtrees' lower solves.  Column pairs: entry (r, j) at
-  // 2 ((j / 2) ntop + r) + (j % 2), an odd last column paired with zeros.
+  // 2 ((j / 2) ld + r) + (j % 2) with ld = top_ld(ntop) (whole 256-byte FP64
+  // lines per column pair), an odd last column and rows past ntop zeros.
   std::vector<double> topinv;
   int32_t ntop = 0;
   int64_t nnz_L = 0, nnz_U = 0;   // entries of L and U (diagonal blocks included)
@@ -245,6 +246,8 @@ bool pack_tri(const TriHost& T, TriPacked& P, int narrow_width);
 
 // Largest top group stored as a dense inverse (8 MiB of FP64 per block).
 constexpr int kTopInvMaxRows = 1024;
+// leading dimension (in pairs) of a dense top inverse: ntop rounded up to 16
+inline int top_ld(int ntop) { return (ntop + 15) & ~15; }
 
 // The dense inverse of BlockFactor::topinv from the top group's packed lower
 // and upper factors of a block of n positions; false when a record reaches a

@@ -724,11 +724,23 @@ __global__ void __launch_bounds__(1024) k_lr1_gz(int k, const T* __restrict__ Ga
   const int c0 = sys_chunk[s], c1 = sys_chunk[s + 1];
   const int S = max(1, min(nt / max(k, 1), 32));  // slices of the summation range
   const int j = tid % k, sl = tid / k;
+  // eight independent partial sums per thread keep eight loads in flight
+  constexpr int UG = 8;
   {
-    T a = (T)0;
-    if (sl < S)
-      for (int c = c0 + sl; c < c1; c += S) a += partial[(int64_t)c * k + j];
-    red[tid] = a;
+    T a[UG];
+#pragma unroll
+    for (int u = 0; u < UG; ++u) a[u] = (T)0;
+    if (sl < S) {
+      int c = c0 + sl;
+      for (; c + (UG - 1) * S < c1; c += UG * S)
+#pragma unroll
+        for (int u = 0; u < UG; ++u) a[u] += partial[(int64_t)(c + u * S) * k + j];
+      for (; c < c1; c += S) a[0] += partial[(int64_t)c * k + j];
+    }
+    T t = (T)0;
+#pragma unroll
+    for (int u = 0; u < UG; ++u) t += a[u];
+    red[tid] = t;
   }
   __syncthreads();
   if (tid < k) {
@@ -739,10 +751,23 @@ __global__ void __launch_bounds__(1024) k_lr1_gz(int k, const T* __restrict__ Ga
   __syncthreads();
   const T* G = Gall + (int64_t)s * k * k;
   {
-    T a = (T)0;
-    if (sl < S)
-      for (int l = sl; l < k; l += S) a += (gtrans ? G[(int64_t)l * k + j] : G[(int64_t)j * k + l]) * W[l];
-    red[tid] = a;
+    T a[UG];
+#pragma unroll
+    for (int u = 0; u < UG; ++u) a[u] = (T)0;
+    if (sl < S) {
+      int l = sl;
+      for (; l + (UG - 1) * S < k; l += UG * S)
+#pragma unroll
+        for (int u = 0; u < UG; ++u) {
+          const int lu = l + u * S;
+          a[u] += (gtrans ? G[(int64_t)lu * k + j] : G[(int64_t)j * k + lu]) * W[lu];
+        }
+      for (; l < k; l += S) a[0] += (gtrans ? G[(int64_t)l * k + j] : G[(int64_t)j * k + l]) * W[l];
+    }
+    T t = (T)0;
+#pragma unroll
+    for (int u = 0; u < UG; ++u) t += a[u];
+    red[tid] = t;
   }
   __syncthreads();
   if (tid < k) {
@@ -1386,7 +1411,7 @@ __global__ void __launch_bounds__(1024) k_team_topinv(ApplyArrays<T> A, TeamIO<T
   __syncthreads();
   const int wv = tid >> 6, lane = tid & 63, nw = nt >> 6;
   const int row = rb * kTopRows + lane;
-  const int npair = (ntop + 1) >> 1;
+  const int npair = (ntop + 1) >> 1, ld = (ntop + 15) & ~15;  // the host's top_ld
   const P2* M = reinterpret_cast<const P2*>(TA.TI + TA.ti_off[i]);
   T acc = (T)0;
   if (row < ntop) {
@@ -1398,7 +1423,7 @@ __global__ void __launch_bounds__(1024) k_team_topinv(ApplyArrays<T> A, TeamIO<T
 #pragma unroll
       for (int s = 0; s < UN; ++s) {
         const int cs = c + s * nw < npair ? c + s * nw : c;
-        v[s] = M[(int64_t)cs * ntop + row];
+        v[s] = M[(int64_t)cs * ld + row];
       }
 #pragma unroll
       for (int s = 0; s < UN; ++s) {
