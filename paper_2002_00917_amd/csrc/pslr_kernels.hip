@@ -1400,6 +1400,20 @@ __global__ void __launch_bounds__(1024) k_team_topinv(ApplyArrays<T> A, TeamIO<T
   T* D = reinterpret_cast<T*>(smem);          // ntopmax + 2
   T* Ps = D + ((TA.ntopmax + 2 + 1) & ~1);    // (nt / 64) x 64 partial sums
   const int64_t base = team_base<T, FAM>(A, i);
+  const int wv = tid >> 6, lane = tid & 63, nw = nt >> 6;
+  const int row = rb * kTopRows + lane;
+  const int npair = (ntop + 1) >> 1, ld = (ntop + 15) & ~15;  // the host's top_ld
+  const P2* M = reinterpret_cast<const P2*>(TA.TI + TA.ti_off[i]);
+  // the first round of this lane's pairs does not depend on d: loaded before
+  // d is formed (slots past the end re-read pair wv, products dropped)
+  constexpr int UN = 4;
+  P2 v0[UN];
+  if (row < ntop)
+#pragma unroll
+    for (int s = 0; s < UN; ++s) {
+      const int cs = wv + s * nw < npair ? wv + s * nw : wv;
+      v0[s] = M[(int64_t)cs * ld + row];
+    }
   const T* U = FAM == 0 && MODE != 1 ? io.u + A.if_ptr[i] : nullptr;
   const T* d = io.dtop + (int64_t)i * team * TA.ntopmax;
   for (int k = tid; k < ntop; k += nt) {
@@ -1409,14 +1423,15 @@ __global__ void __launch_bounds__(1024) k_team_topinv(ApplyArrays<T> A, TeamIO<T
   }
   if (tid == 0) D[ntop] = (T)0;  // partner of an odd last column
   __syncthreads();
-  const int wv = tid >> 6, lane = tid & 63, nw = nt >> 6;
-  const int row = rb * kTopRows + lane;
-  const int npair = (ntop + 1) >> 1, ld = (ntop + 15) & ~15;  // the host's top_ld
-  const P2* M = reinterpret_cast<const P2*>(TA.TI + TA.ti_off[i]);
   T acc = (T)0;
   if (row < ntop) {
-    constexpr int UN = 4;
-    for (int c = wv; c < npair; c += UN * nw) {
+#pragma unroll
+    for (int s = 0; s < UN; ++s) {
+      const int cs = wv + s * nw < npair ? wv + s * nw : wv;
+      const T a = v0[s].x * D[2 * cs] + v0[s].y * D[2 * cs + 1];
+      acc += wv + s * nw < npair ? a : (T)0;
+    }
+    for (int c = wv + UN * nw; c < npair; c += UN * nw) {
       // every slot loads (a slot past the end re-reads pair c); the extra
       // products are dropped
       P2 v[UN];
