@@ -727,7 +727,9 @@ struct Tracer {
 };
 
 // Rows per chunk for columns cols: at least ~1024 chunks over all columns so
-// that every CU holds several, between 256 and kChunkRows rows each.
+// that every CU holds several, between 256 and kChunkRows rows each (1024:
+// per FGMRES iteration on the 64^3 workload the vector work took 154.5 us
+// against 163.3 us with chunks of up to 4096 rows).
 int64_t chunk_rows(const std::vector<Seg>& cols) {
   int64_t tot = 0;
   for (const Seg& s : cols) tot += s.len;
@@ -2654,12 +2656,9 @@ pslr_status fgmres_solve(pslr_handle h, int32_t nrhs, const double* b, int64_t l
       HIP_TRY(launch_reduce_chunk(ncol, h->fcpM, 1, nchM, h->fdbuf, dnn, s));
       HIP_TRY(launch_inv_sqrt(ncol, dnn, h->factive, h->fscl, s));
       HIP_TRY(launch_scale_chunk(nchF, h->fchF, cV, cV, W, h->fscl, Vb + (size_t)(j + 1) * blk, s));
+      // dh1, dh2 and dnn are one contiguous block (same offsets in the slot): one copy
       double* slot = h->fpin + (size_t)(j & 1) * hsz;
-      HIP_TRY(hipMemcpyAsync(slot, dh1, sizeof(double) * ncol * nv, hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipMemcpyAsync(slot + (size_t)ncol * R1, dh2, sizeof(double) * ncol * nv,
-                             hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipMemcpyAsync(slot + (size_t)2 * ncol * R1, dnn, sizeof(double) * ncol,
-                             hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipMemcpyAsync(slot, dh1, sizeof(double) * hsz, hipMemcpyDeviceToHost, s));
       HIP_TRY(hipEventRecord(hev.e[j & 1], s));
       return PSLR_OK;
     };

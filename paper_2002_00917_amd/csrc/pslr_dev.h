@@ -118,7 +118,10 @@ struct Chunk {
   int64_t r0, r1;
 };
 // longest row chunk of the chunked vector kernels (16 rows per thread at 256 threads)
-constexpr int64_t kChunkRows = 4096;
+#ifndef PSLR_CHUNK_ROWS
+#define PSLR_CHUNK_ROWS 1024
+#endif
+constexpr int64_t kChunkRows = PSLR_CHUNK_ROWS;
 
 // LDS slots of k_lr_expand's slice sums, and its slice count: the k x R
 // sums of V^T y and G W are each split into S slices of the summation range

@@ -40,7 +40,11 @@ __global__ void k_sddmm(int64_t n, const int64_t* __restrict__ ptr, const int32_
 // Chunked vector kernels: 256 threads per chunk, each thread owns rows
 // r0 + tid + t*256 (t < kRows) of its chunk; vectors go in groups of kUnroll so
 // that kUnroll * kRows independent loads are in flight per thread.
-constexpr int kChunkThreads = 256, kRows = 16, kUnroll = 4, kDotGroup = 64;
+#ifndef PSLR_VEC_UNROLL
+#define PSLR_VEC_UNROLL 4
+#endif
+constexpr int kChunkThreads = 256, kRows = (int)((kChunkRows + 255) / 256), kUnroll = PSLR_VEC_UNROLL,
+              kDotGroup = 64;
 static_assert(kRows * kChunkThreads >= kChunkRows, "chunk longer than one workgroup covers");
 
 // partial[i * nchunk + c] = sum over chunk c's rows of V_i[vbase + row] * W[wbase + row]
