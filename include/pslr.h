@@ -126,8 +126,8 @@ typedef struct {
                                else 1), 1 = off, 2..8 = that many */
   int32_t team_top;         /* how the team split solves its top group: 0 = automatic (2 when
                                every block's top group has at most 1024 rows and the dense
-                               inverses hold at most twice the values the top groups' packed
-                               factors hold, else 1); 1 = lower and upper solve of the packed
+                               inverses hold at most twice the values of the family's packed
+                               factors, else 1); 1 = lower and upper solve of the packed
                                top-group factors, one workgroup per subdomain; 2 = one product
                                with the dense inverse of the top group's block of L U, spread
                                over one workgroup per 64 top rows (PSLR_EINVAL when a top

@@ -442,7 +442,7 @@ hipError_t upload_team(DevPool& pool, const std::vector<BlockFactor>& F, int tea
   const int path = w == 8 ? 0 : 1;
   auto rd = [&](const TriPacked& P) { return P.read_vals[path] * (int64_t)w + 4 * P.read_ints[path]; };
   std::vector<const TriPacked*> ls, us;
-  int64_t groups = 0, top_packed = 0, top_vals = 0, dense_vals = 0;
+  int64_t groups = 0, top_packed = 0, all_vals = 0, dense_vals = 0;
   bool dense_ok = true;
   for (const BlockFactor& f : F) {
     if (f.team != team || (int)f.loS.size() != team + 1 || (int)f.upS.size() != team + 1)
@@ -452,7 +452,7 @@ hipError_t upload_team(DevPool& pool, const std::vector<BlockFactor>& F, int tea
       us.push_back(&f.upS[g]);
       (g < team ? groups : top_packed) += rd(f.loS[g]) + rd(f.upS[g]);
     }
-    top_vals += f.loS[team].read_vals[path] + f.upS[team].read_vals[path];
+    for (int g = 0; g <= team; ++g) all_vals += f.loS[g].read_vals[path] + f.upS[g].read_vals[path];
     dense_vals += (int64_t)f.ntop * f.ntop;
     if (f.ntop > 0 && f.topinv.empty()) dense_ok = false;
     out.ntopmax = std::max(out.ntopmax, f.loS[team].n);
@@ -465,7 +465,7 @@ hipError_t upload_team(DevPool& pool, const std::vector<BlockFactor>& F, int tea
   if (team_top == 2 && !dense_ok) return hipErrorInvalidValue;
   // (blocks without top rows keep the packed path: nothing to multiply)
   const bool dense =
-      dense_ok && dense_vals > 0 && (team_top == 2 || (team_top == 0 && dense_vals <= 2 * top_vals));
+      dense_ok && dense_vals > 0 && (team_top == 2 || (team_top == 0 && dense_vals <= 2 * all_vals));
   bytes = groups + top_packed;
   if (dense) {
     std::vector<T> ti;
@@ -1821,7 +1821,8 @@ pslr_status pslr_host_stats(int64_t n, const int64_t* rowptr, const int32_t* col
       codes[t] = ilut_block(M, drop, o.want_transpose != 0, narrow, f, errs[t]);
       if (!codes[t]) codes[t] = ilut_factor(M, drop, I, errs[t]);
     } else {
-      codes[t] = factor_block(M, tau, o.want_transpose != 0, narrow, f, errs[t], team);
+      codes[t] = factor_block(M, tau, o.want_transpose != 0, narrow, f, errs[t], team,
+                              t < nB ? kTopRowsB : kTopRowsC);
     }
     if (codes[t] || M.nrows == 0) return;
     if (f.team > 1) {
@@ -2116,7 +2117,7 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
     const int narrow = t < np ? kNarrowWidthB : kNarrowWidthC;
     codes[t] = o.factor == 1 ? ilut_block(M, drop, h->want_T != 0, narrow, F, errs[t])
                              : factor_block(M, tau, h->want_T != 0, narrow, F, errs[t],
-                                            o.team);
+                                            o.team, t < np ? kTopRowsB : kTopRowsC);
   });
   for (int t = 0; t < 2 * np; ++t)
     if (codes[t]) return fail(codes[t] == 3 ? PSLR_ENOTSUP : PSLR_ESINGULAR,
@@ -2310,7 +2311,7 @@ pslr_status pslr_refactor(pslr_handle h, const double* vals, void* hip_stream) {
     const int narrow = t < np ? kNarrowWidthB : kNarrowWidthC;
     codes[t] = o.factor == 1 ? ilut_block(M, drop, h->want_T != 0, narrow, F, errs[t])
                              : factor_block(M, tau, h->want_T != 0, narrow, F, errs[t],
-                                            o.team);
+                                            o.team, t < np ? kTopRowsB : kTopRowsC);
   });
   for (int t = 0; t < 2 * np; ++t)
     if (codes[t]) return fail(codes[t] == 3 ? PSLR_ENOTSUP : PSLR_ESINGULAR,

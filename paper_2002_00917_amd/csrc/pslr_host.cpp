@@ -446,7 +446,8 @@ void build_levels(TriHost& T, const std::vector<int>& sfirst, const std::vector<
 // Exact sparse LU of one block
 // ---------------------------------------------------------------------------
 
-std::vector<int> team_groups(const std::vector<int>& spar, const std::vector<double>& work, int team) {
+std::vector<int> team_groups(const std::vector<int>& spar, const std::vector<double>& work, int team,
+                             const std::vector<int>* rows, int min_top_rows) {
   const int ns = (int)spar.size();
   std::vector<int> grp(ns, team);
   if (team <= 1 || ns == 0) {
@@ -471,14 +472,17 @@ std::vector<int> team_groups(const std::vector<int>& spar, const std::vector<dou
       total += sub[s];
     }
   std::vector<char> is_top(ns, 0);
+  int top_rows = 0;
   for (int it = 0; it < 4 * ns; ++it) {
     std::sort(cand.begin(), cand.end(), [&](int a, int b) { return sub[a] > sub[b]; });
     double csum = 0.0;
     for (int c : cand) csum += sub[c];
     const int c0 = cand[0];
-    if ((int)cand.size() >= team && sub[c0] <= 1.25 * csum / team) break;
-    if (kids[c0].empty() || top + work[c0] > 0.45 * total) break;
+    const bool deepen = rows && top_rows < min_top_rows && top_rows + (*rows)[c0] <= kTopInvMaxRows;
+    if (!deepen && (int)cand.size() >= team && sub[c0] <= 1.25 * csum / team) break;
+    if (kids[c0].empty() || (!deepen && top + work[c0] > 0.45 * total)) break;
     top += work[c0];
+    if (rows) top_rows += (*rows)[c0];
     is_top[c0] = 1;
     cand.erase(cand.begin());
     cand.insert(cand.end(), kids[c0].begin(), kids[c0].end());
@@ -513,7 +517,7 @@ std::vector<int> team_groups(const std::vector<int>& spar, const std::vector<dou
 constexpr int kMergeWidth = PSLR_MERGE_W, kMergePasses = PSLR_MERGE_P;
 
 int factor_block(const CsrL& M, double tau, bool want_T, int narrow_width, BlockFactor& out,
-                 std::string& err, int team) {
+                 std::string& err, int team, int min_top_rows) {
   const int n = M.nrows;
   out = BlockFactor();
   out.n = n;
@@ -917,7 +921,9 @@ int factor_block(const CsrL& M, double tau, bool want_T, int narrow_width, Block
       const double w = sfirst[s + 1] - sfirst[s];
       work[s] = w * (w + 1) + 2.0 * w * (double)R[s].size();
     }
-    grp = team_groups(spar, work, team);
+    std::vector<int> srows(ns);
+    for (int s = 0; s < ns; ++s) srows[s] = sfirst[s + 1] - sfirst[s];
+    grp = team_groups(spar, work, team, &srows, min_top_rows);
   }
   auto pack_groups = [&](TriHost& T, std::vector<TriPacked>& outS) -> bool {
     outS.assign(team + 1, TriPacked());

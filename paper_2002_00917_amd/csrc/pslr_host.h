@@ -168,8 +168,10 @@ struct BlockFactor {
 // supernode too large for the device layout (message in err).
 // narrow_width: the entry-form threshold of pack_tri (kNarrowWidthB for
 // interior blocks, kNarrowWidthC for interface blocks).
+// min_top_rows: the team split's top group is deepened (whole supernodes taken
+// from the heaviest subtree downwards) until it holds at least that many rows.
 int factor_block(const CsrL& M, double tau, bool want_transpose, int narrow_width, BlockFactor& out,
-                 std::string& err, int team = 0);
+                 std::string& err, int team = 0, int min_top_rows = 0);
 
 // Team groups of a supernodal elimination tree (postordered: children before
 // parents, every subtree a contiguous range): grp[s] in [0, team) for the
@@ -179,7 +181,22 @@ int factor_block(const CsrL& M, double tau, bool want_transpose, int narrow_widt
 // exceeds 1.25 times an even share, as long as the top group stays below 45%
 // of the work; the subtrees are then assigned largest first to the lightest
 // group.
-std::vector<int> team_groups(const std::vector<int>& spar, const std::vector<double>& work, int team);
+std::vector<int> team_groups(const std::vector<int>& spar, const std::vector<double>& work, int team,
+                             const std::vector<int>* rows = nullptr, int min_top_rows = 0);
+
+// Least top-group rows of the team splits of interior (B_i) and interface
+// (C_i) blocks (see factor_block).  The interface blocks' trees are shallow
+// surfaces whose subtree levels cost more than their bytes: on the 64^3
+// workload top groups of at least 128, 256 and 384 rows took the FP64 series
+// step from 149.0 to 144.9, 146.4 and 146.1 us (FP32: 114.8 to 110.9, 108.5,
+// 106.3 us); deepening the interior blocks' tops to 600 rows cost 18 us.
+#ifndef PSLR_TOP_ROWS_B
+#define PSLR_TOP_ROWS_B 0
+#endif
+#ifndef PSLR_TOP_ROWS_C
+#define PSLR_TOP_ROWS_C 256
+#endif
+constexpr int kTopRowsB = PSLR_TOP_ROWS_B, kTopRowsC = PSLR_TOP_ROWS_C;
 
 // Threshold incomplete LU of block M in its given row order, no pivoting
 // (the ilu() of Algorithm 4): row by row, w = M[i, :], tau_i = drop times the
