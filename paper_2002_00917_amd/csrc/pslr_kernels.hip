@@ -1216,11 +1216,11 @@ __global__ void __launch_bounds__(1024) k_tail(ApplyArrays<T> A, int nrhs, const
 // supernodal tree of every B_i (family 0) and C_i (family 1) is cut into
 // `team` groups of whole subtrees and a top group (BlockFactor::loS/upS).
 // Launch 1, workgroup (i, g): group g's rows from the right-hand side and its
-// lower solve on an LDS copy whose top rows start at zero; the group's rows
-// go to the family vector xw, its pushes into the top rows to dtop.  Launch
-// 2: the top group from its right-hand side plus the pushes, by its packed
-// lower and upper solves (one workgroup per block) or by its dense inverse
-// (one workgroup per 64 top rows).  Launch 3, workgroup (i, g): group g's
+// lower solve on an LDS copy whose top rows start at their right-hand side
+// (g = 0) or zero; the group's rows go to the family vector xw, its top rows
+// (right-hand side minus its pushes) to dtop.  Launch 2: the top group from
+// the sum of the groups' top rows, by its packed lower and upper solves (one
+// workgroup per block) or by its dense inverse (one workgroup per 64 top rows).  Launch 3, workgroup (i, g): group g's
 // upper solve, pulling the top rows.
 //
 // Right-hand sides and results by family and MODE:
@@ -1334,7 +1334,13 @@ __global__ void __launch_bounds__(1024) k_team_lower(ApplyArrays<T> A, TeamIO<T>
     const int p = ro[2 * k].x;
     X[p] = team_rhs<T, FAM, MODE>(A, io, i, base, p, L.U);
   }
-  for (int k = tid; k < ntop; k += nt) X[rt[2 * k].x] = (T)0;
+  // the top rows start from their right-hand side in group 0 and from zero in
+  // the others, so that the sum of the groups' top rows is the right-hand side
+  // minus every push, each term formed once
+  for (int k = tid; k < ntop; k += nt) {
+    const int p = rt[2 * k].x;
+    X[p] = g == 0 ? team_rhs<T, FAM, MODE>(A, io, i, base, p, L.U) : (T)0;
+  }
   __syncthreads();
   tri_solve<T, 1, false>(TA.L, bs + g, X, L.Rb, A.gshift);
   __syncthreads();
@@ -1357,16 +1363,14 @@ __global__ void __launch_bounds__(1024) k_team_top(ApplyArrays<T> A, TeamIO<T> i
   Lds<T> L = carve<T, 1, false>(A);
   T* X = FAM == 0 ? L.XB : L.XC;
   const int64_t base = team_base<T, FAM>(A, i);
-  team_load_u<T, FAM, MODE>(A, io, i, L.U, false);
   const int bs = i * (team + 1);
   const int4* rt;
   const int ntop = team_rows(TA.L, bs + team, rt);
   const T* d = io.dtop + (int64_t)i * team * TA.ntopmax;
   for (int k = tid; k < ntop; k += nt) {
-    const int p = rt[2 * k].x;
-    T acc = team_rhs<T, FAM, MODE>(A, io, i, base, p, L.U);
+    T acc = (T)0;  // the right-hand side came with group 0's top rows
     for (int t = 0; t < team; ++t) acc += d[(int64_t)t * TA.ntopmax + k];
-    X[p] = acc;
+    X[rt[2 * k].x] = acc;
   }
   __syncthreads();
   tri_solve<T, 1, false>(TA.L, bs + team, X, L.Rb, A.gshift);
@@ -1378,9 +1382,9 @@ __global__ void __launch_bounds__(1024) k_team_top(ApplyArrays<T> A, TeamIO<T> i
   }
 }
 
-// The top group through its dense inverse: workgroup (i, rb) forms the
-// top-group right-hand side d (the rows' own terms plus the subtrees'
-// pushes) and the 64 rows rb * 64 .. of x_T = M_i d, the waves splitting the
+// The top group through its dense inverse: workgroup (i, rb) sums the
+// groups' top rows into d (the right-hand side minus every push) and forms
+// the 64 rows rb * 64 .. of x_T = M_i d, the waves splitting the
 // column pairs and meeting in LDS.  Lane l of a wave reads row rb * 64 + l of
 // a column pair: 64 consecutive pairs, one coalesced load per pair.
 constexpr int kTopRows = 64;
@@ -1414,10 +1418,9 @@ __global__ void __launch_bounds__(1024) k_team_topinv(ApplyArrays<T> A, TeamIO<T
       const int cs = wv + s * nw < npair ? wv + s * nw : wv;
       v0[s] = M[(int64_t)cs * ld + row];
     }
-  const T* U = FAM == 0 && MODE != 1 ? io.u + A.if_ptr[i] : nullptr;
   const T* d = io.dtop + (int64_t)i * team * TA.ntopmax;
   for (int k = tid; k < ntop; k += nt) {
-    T acc = team_rhs<T, FAM, MODE>(A, io, i, base, rt[2 * k].x, U);
+    T acc = (T)0;  // the right-hand side came with group 0's top rows
     for (int t = 0; t < team; ++t) acc += d[(int64_t)t * TA.ntopmax + k];
     D[k] = acc;
   }
