@@ -171,6 +171,11 @@ typedef struct {
                                split) */
   int32_t team_c;           /* team size of the single-right-hand-side C_i solves (0: no split) */
   int32_t team_top_c;       /* the C_i top groups' solve, as team_top */
+  int32_t team_apply;       /* solves of single-right-hand-side forward applies: 0 one workgroup
+                               per block, 1 team split of the B_i, 2 of the B_i and the C_i.  A
+                               split runs when each of its groups (rows, level scratch, the
+                               block's interface values) fits one workgroup's LDS, so it also
+                               serves blocks too large for the LDS of one workgroup */
 } pslr_info_t;
 
 /* Fill *opt with defaults: m = 3, rank = 16, FP64, no transpose, seed 1, tau 0.1,
@@ -362,6 +367,13 @@ typedef struct {
                                every B_i and C_i (groups applied in turn on the host, the top group
                                once by its packed factors and once by its dense inverse
                                where it has one) and its plain packed solve */
+  int64_t team_lds_slots_B; /* largest LDS footprint of one team workgroup over the B_i, in
+                               values of the working precision: the group's own and top rows
+                               (rounded up to even) plus three times its widest level.  The
+                               B_i team solves also hold the block's interface values, so a
+                               split runs when (slots_B + max q_i) * value size and
+                               slots_C * value size fit one workgroup's LDS */
+  int64_t team_lds_slots_C; /* the same over the C_i */
 } pslr_host_stats_t;
 pslr_status pslr_host_stats(int64_t n, const int64_t* rowptr, const int32_t* colind,
                             const double* vals, const int32_t* part, int32_t nparts,

@@ -459,9 +459,26 @@ hipError_t upload_team(DevPool& pool, const std::vector<BlockFactor>& F, int tea
   }
   hipError_t e;
   int64_t tb;
-  if ((e = upload_tri_list(pool, ls, out.L, mlr, tb))) return e;
-  if ((e = upload_tri_list(pool, us, out.U, mlr, tb))) return e;
+  int tmlr = 0;
+  if ((e = upload_tri_list(pool, ls, out.L, tmlr, tb))) return e;
+  if ((e = upload_tri_list(pool, us, out.U, tmlr, tb))) return e;
   out.team = team;
+  out.maxlr = std::max(tmlr, 1);
+  {
+    std::vector<int32_t> pos;
+    std::vector<int64_t> off(1, 0);
+    int maxloc = 1;
+    for (const TriPacked* P : ls) {
+      if (P->pos.empty() && P->n > 0) return hipErrorInvalidValue;  // groups are packed locally
+      pos.insert(pos.end(), P->pos.begin(), P->pos.end());
+      off.push_back((int64_t)pos.size());
+      maxloc = std::max<int>(maxloc, (int)P->pos.size());
+    }
+    if (pos.empty()) pos.push_back(0);
+    if ((e = pool.upload(pos, &out.pos))) return e;
+    if ((e = pool.upload(off, &out.pos_off))) return e;
+    out.maxloc = maxloc;
+  }
   if (team_top == 2 && !dense_ok) return hipErrorInvalidValue;
   // (blocks without top rows keep the packed path: nothing to multiply)
   const bool dense =
@@ -787,6 +804,20 @@ LaunchCfg choose_launch(pslr_ctx* h, const ApplyArrays<T>& A, int nrhs, hipStrea
   return c;
 }
 
+// Team path of a single-right-hand-side forward apply with arrays A and
+// launch configuration c: team (every B_i solve split over a team of
+// workgroups, each holding its group's rows in LDS) and cteam (the C_i solves
+// too).  The split also serves subdomains too large for one workgroup's LDS,
+// as long as each group fits; a C_i without a team split is then solved in
+// LDS by one workgroup, which needs the plain path's fit.
+template <typename T>
+void team_path(const pslr_ctx* h, const ApplyArrays<T>& A, const LaunchCfg& c, bool& team, bool& cteam) {
+  const bool tb_fit = A.TB.team > 1 && team_lds_bytes(A.TB, A.maxQB) <= h->lds_max;
+  const bool tc_fit = A.TC.team > 1 && team_lds_bytes(A.TC, A.maxQB) <= h->lds_max;
+  team = tb_fit && (tc_fit || !c.gx) && c.R == 1;
+  cteam = team && tc_fit;
+}
+
 // Device workspace of one apply (see WsSizes).
 struct ApplyWs {
   void *y, *u0, *u1, *partial, *gws, *zp, *team;
@@ -816,10 +847,10 @@ pslr_status run_apply(pslr_ctx* h, const ApplyArrays<T>& Ah, const ApplyWs& W, b
     ~Restore() { h->trace = v; }
   } restore{h, tr_on};
   Tracer tr{h, s, {}};
-  // one right-hand side in LDS: every B_i (and C_i) solve spread over a team
-  // of workgroups (workspace layout as in ws_sizes)
-  const bool team = A.TB.team > 1 && W.team && nrhs == 1 && cfg.R == 1 && !cfg.gx && !transpose;
-  const bool cteam = team && A.TC.team > 1;
+  // one right-hand side: the team solves (workspace layout as in ws_sizes)
+  bool team = false, cteam = false;
+  if (W.team && nrhs == 1 && !transpose) team_path<T>(h, A, cfg, team, cteam);
+  if (team && !cteam) A.TC.team = 0;
   TeamWs tw{nullptr, nullptr, nullptr, nullptr};
   if (team) {
     T* t = (T*)W.team;
@@ -1648,6 +1679,10 @@ void fill_info(pslr_ctx* h, const std::vector<BlockFactor>& fB, const std::vecto
   I.team_top = I.team ? (h->fw64.TB.TI ? 2 : 1) : 0;
   I.team_c = h->fw64.TC.team > 1 ? h->fw64.TC.team : 0;
   I.team_top_c = I.team_c ? (h->fw64.TC.TI ? 2 : 1) : 0;
+  bool tb = false, tc = false;
+  if (h->precision >= 1) team_path<float>(h, h->fw32, choose_launch(h, h->fw32, 1, nullptr), tb, tc);
+  else team_path<double>(h, h->fw64, choose_launch(h, h->fw64, 1, nullptr), tb, tc);
+  I.team_apply = tb ? (tc ? 2 : 1) : 0;
   const int64_t matrix = (m + 2) * bB + (m + 1) * bC + (m + 1) * bEF + m * bCg + 2 * q * k * wv +
                          k * k * w;
   const int64_t vectors = (int64_t)(m + 2) * vecB + (m + 1) * vecC + (int64_t)w * (2 * m + 3) * q +
@@ -1811,6 +1846,7 @@ pslr_status pslr_host_stats(int64_t n, const int64_t* rowptr, const int32_t* col
   std::vector<int> codes(mats.size(), 0), lvl(mats.size(), 0), valid(mats.size(), 1),
       tvalid(mats.size(), 1);
   std::vector<double> tres(mats.size(), 0.0);
+  std::vector<int64_t> tslots(mats.size(), 0);
   std::vector<int64_t> nnz(mats.size(), 0);
   parallel_for((int)mats.size(), o.nthreads, [&](int t) {
     const CsrL& M = *mats[t];
@@ -1831,29 +1867,38 @@ pslr_status pslr_host_stats(int64_t n, const int64_t* rowptr, const int32_t* col
       // solves) against the plain packed solve
       std::string terr;
       if (!check_team(f, terr)) tvalid[t] = 0;
+      // LDS slots of one team workgroup: the group's local vector and three
+      // thirds of level scratch (as the device layout)
+      int maxloc = 1, maxlr = 1;
+      for (int g = 0; g <= f.team; ++g) {
+        maxloc = std::max<int>(maxloc, (int)f.loS[g].pos.size());
+        maxlr = std::max({maxlr, f.loS[g].max_lrows, f.upS[g].max_lrows});
+      }
+      tslots[t] = ((maxloc + 1) & ~1) + 3 * (int64_t)maxlr;
       const int nb = M.nrows;
       std::vector<double> X0(nb), X1(nb);
       for (int i = 0; i < nb; ++i) X0[i] = X1[i] = std::cos(0.3 + 0.71 * i);
       host_tri_solve(f.lo, X0, true);
       host_tri_solve(f.up, X0, true);
       std::vector<double> X2(X1);
-      for (int g = 0; g <= f.team; ++g) host_tri_solve(f.loS[g], X1, true);
-      host_tri_solve(f.upS[f.team], X1, true);
-      for (int g = 0; g < f.team; ++g) host_tri_solve(f.upS[g], X1, true);
+      for (int g = 0; g <= f.team; ++g) host_tri_solve_pos(f.loS[g], X1, true);
+      host_tri_solve_pos(f.upS[f.team], X1, true);
+      for (int g = 0; g < f.team; ++g) host_tri_solve_pos(f.upS[g], X1, true);
       // the top group through its dense inverse
       if (!f.topinv.empty()) {
-        for (int g = 0; g < f.team; ++g) host_tri_solve(f.loS[g], X2, true);
+        for (int g = 0; g < f.team; ++g) host_tri_solve_pos(f.loS[g], X2, true);
         const int nt = f.ntop;
+        const std::vector<int32_t>& tp = f.loS[f.team].pos;
         std::vector<double> d(nt + 1, 0.0);
-        for (int k = 0; k < nt; ++k) d[k] = X2[f.loS[f.team].rec[(size_t)8 * k]];
+        for (int k = 0; k < nt; ++k) d[k] = X2[tp[k]];
         for (int r = 0; r < nt; ++r) {
           double acc = 0.0;
           const size_t ld = (size_t)top_ld(nt);
           for (int c = 0; c < (nt + 1) / 2; ++c)
             acc += f.topinv[2 * (c * ld + r)] * d[2 * c] + f.topinv[2 * (c * ld + r) + 1] * d[2 * c + 1];
-          X2[f.loS[f.team].rec[(size_t)8 * r]] = acc;
+          X2[tp[r]] = acc;
         }
-        for (int g = 0; g < f.team; ++g) host_tri_solve(f.upS[g], X2, true);
+        for (int g = 0; g < f.team; ++g) host_tri_solve_pos(f.upS[g], X2, true);
       }
       double d2 = 0.0, e2 = 0.0, n2 = 0.0;
       for (int i = 0; i < nb; ++i) {
@@ -1980,6 +2025,8 @@ pslr_status pslr_host_stats(int64_t n, const int64_t* rowptr, const int32_t* col
   for (size_t t = 0; t < mats.size(); ++t) {
     if (!tvalid[t]) out->team_valid = 0;
     out->team_residual = std::max(out->team_residual, tres[t]);
+    int64_t& sl = (int)t < nB ? out->team_lds_slots_B : out->team_lds_slots_C;
+    sl = std::max(sl, tslots[t]);
   }
   for (size_t t = 0; t < mats.size(); ++t) {
     const bool b = (int)t < nB;

@@ -63,7 +63,21 @@ struct TeamArrays {
   int32_t team, ntopmax, nrb;
   const T* TI;
   const int64_t* ti_off;
+  // the groups' local positions (TriPacked::pos): group g of block i at
+  // pos[pos_off[i * (team + 1) + g] ..), its own rows first, then (subtree
+  // groups) the top group's rows; maxloc, maxlr: the most local positions and
+  // level rows of any group (the team kernels' LDS)
+  const int32_t* pos;
+  const int64_t* pos_off;
+  int32_t maxloc, maxlr;
 };
+
+// LDS of a team launch: the group's local vector, three thirds of level
+// scratch, and the block's interface values (interior family)
+template <typename T>
+inline size_t team_lds_bytes(const TeamArrays<T>& TA, int32_t maxQB) {
+  return sizeof(T) * ((size_t)((TA.maxloc + 1) & ~1) + 3 * (size_t)TA.maxlr + (size_t)maxQB);
+}
 
 // Everything one direction (forward or transposed) of the apply needs.
 template <typename T>

@@ -925,9 +925,14 @@ int factor_block(const CsrL& M, double tau, bool want_T, int narrow_width, Block
     for (int s = 0; s < ns; ++s) srows[s] = sfirst[s + 1] - sfirst[s];
     grp = team_groups(spar, work, team, &srows, min_top_rows);
   }
+  // Every group is packed over local positions: its own rows in level order,
+  // then (subtree groups) the top group's rows in the top group's level order;
+  // TriPacked::pos maps them back to block positions.
   auto pack_groups = [&](TriHost& T, std::vector<TriPacked>& outS) -> bool {
     outS.assign(team + 1, TriPacked());
-    for (int g = 0; g <= team; ++g) {
+    std::vector<int> top_rows;
+    std::vector<int> loc(n, -1);
+    for (int g = team; g >= 0; --g) {
       std::vector<int> hg(ns, 0);
       int nl = 0;
       std::vector<int> sf_g(1, 0);
@@ -953,11 +958,17 @@ int factor_block(const CsrL& M, double tau, bool want_T, int narrow_width, Block
         T.lev_ptr[l + 1] = (int)T.lrows.size();
         T.max_lrows = std::max(T.max_lrows, T.lev_ptr[l + 1] - T.lev_ptr[l]);
       }
+      std::vector<int> pos(T.lrows);
+      if (g == team) top_rows = pos;
+      else pos.insert(pos.end(), top_rows.begin(), top_rows.end());
+      for (int k = 0; k < (int)pos.size(); ++k) loc[pos[k]] = k;
       const int nfull = T.n;
       T.n = (int)T.lrows.size();
-      const bool ok = pack_tri(T, outS[g], narrow_width);
+      const bool ok = pack_tri(T, outS[g], narrow_width, &loc);
       T.n = nfull;
+      for (int p : pos) loc[p] = -1;
       if (!ok) return false;
+      outS[g].pos = std::move(pos);
     }
     return true;
   };
@@ -1040,7 +1051,8 @@ int chunks_for(int64_t items, double avg_len) {
 }
 }  // namespace
 
-bool pack_tri(const TriHost& T, TriPacked& P, int narrow_width) {
+bool pack_tri(const TriHost& T, TriPacked& P, int narrow_width, const std::vector<int>* map) {
+  auto M = [&](int v) { return map ? (*map)[v] : v; };
   P = TriPacked();
   P.lower = T.lower;
   P.n = T.n;
@@ -1113,15 +1125,15 @@ bool pack_tri(const TriHost& T, TriPacked& P, int narrow_width) {
           for (int j = 0; j < w; ++j)
             for (int q = 0; q < h; ++q) {
               P.eval.push_back(pf[(size_t)q * w + j]);
-              P.eidx.push_back(T.ridx[S.ridx_off + q]);
-              P.eloc.push_back(S.f + j);
+              P.eidx.push_back(M(T.ridx[S.ridx_off + q]));
+              P.eloc.push_back(M(S.f + j));
             }
         } else {
           for (int q = 0; q < h; ++q)
             for (int i = 0; i < w; ++i) {
               P.eval.push_back(pf[(size_t)i * h + q]);
-              P.eidx.push_back(T.ridx[S.ridx_off + q]);
-              P.eloc.push_back(S.f + i);
+              P.eidx.push_back(M(T.ridx[S.ridx_off + q]));
+              P.eloc.push_back(M(S.f + i));
             }
         }
       }
@@ -1140,14 +1152,14 @@ bool pack_tri(const TriHost& T, TriPacked& P, int narrow_width) {
                 P.val.push_back(2 * c + t < h ? pf[(size_t)i * h + 2 * c + t] : 0.0);
         }
         // position list padded to even length with its last position (paired with zeros)
-        P.ridx.insert(P.ridx.end(), T.ridx.begin() + S.ridx_off, T.ridx.begin() + S.ridx_off + h);
-        if (h & 1) P.ridx.push_back(T.ridx[S.ridx_off + h - 1]);
+        for (int q = 0; q < h; ++q) P.ridx.push_back(M(T.ridx[S.ridx_off + q]));
+        if (h & 1) P.ridx.push_back(M(T.ridx[S.ridx_off + h - 1]));
         if (T.lower) {
           for (int q = 0; q < h; ++q) {
-            P.prec.push_back(T.ridx[S.ridx_off + q]);
+            P.prec.push_back(M(T.ridx[S.ridx_off + q]));
             P.prec.push_back(poff / 2 + q);
             P.prec.push_back(w | (h << 16));
-            P.prec.push_back(S.f);
+            P.prec.push_back(M(S.f));
           }
           npush += h;
           push_len += (double)h * w;
@@ -1155,7 +1167,7 @@ bool pack_tri(const TriHost& T, TriPacked& P, int narrow_width) {
       }
       for (int i = 0; i < w; ++i) {
         int32_t* r = &P.rec[(size_t)8 * (k + i)];
-        r[0] = S.f + i;
+        r[0] = M(S.f + i);
         r[1] = i;
         r[2] = w;
         r[3] = h;
@@ -1270,6 +1282,17 @@ void host_tri_solve(const TriPacked& T, std::vector<double>& X, bool entries) {
         for (int q = T.ent_ptr[l]; q < T.ent_ptr[l + 1]; ++q) X[T.eloc[q]] -= T.eval[q] * X[T.eidx[q]];
     }
   }
+}
+
+void host_tri_solve_pos(const TriPacked& T, std::vector<double>& X, bool entries) {
+  if (T.pos.empty()) {
+    host_tri_solve(T, X, entries);
+    return;
+  }
+  std::vector<double> Y(T.pos.size());
+  for (size_t k = 0; k < T.pos.size(); ++k) Y[k] = X[T.pos[k]];
+  host_tri_solve(T, Y, entries);
+  for (size_t k = 0; k < T.pos.size(); ++k) X[T.pos[k]] = Y[k];
 }
 
 // Dense inverse of the top group's diagonal block of L U (see BlockFactor::
@@ -1589,14 +1612,25 @@ bool check_team(const BlockFactor& F, std::string& err) {
     return false;
   }
   const int n = F.n;
+  for (int g = 0; g <= team; ++g)
+    if (F.loS[g].pos != F.upS[g].pos) {
+      err = "a team group's lower and upper packings number its rows differently";
+      return false;
+    }
   for (int pass = 0; pass < 2; ++pass) {
     const std::vector<TriPacked>& G = pass == 0 ? F.loS : F.upS;
     std::vector<int> grp(n, -1), lev(n, -1);
+    // block position of local position p of group g (-1: out of range)
+    auto bp = [&](int g, int p) {
+      const TriPacked& T = G[g];
+      if (T.pos.empty()) return p >= 0 && p < n ? p : -1;
+      return p >= 0 && p < (int)T.pos.size() ? (int)T.pos[p] : -1;
+    };
     for (int g = 0; g <= team; ++g) {
       const TriPacked& T = G[g];
       for (int l = 0; l < T.nlev; ++l)
         for (int k = T.lev_ptr[l]; k < T.lev_ptr[l + 1]; ++k) {
-          const int p = T.rec[(size_t)8 * k];
+          const int p = bp(g, T.rec[(size_t)8 * k]);
           if (p < 0 || p >= n || grp[p] >= 0) {
             err = "a position is scheduled twice or out of range";
             return false;
@@ -1612,7 +1646,9 @@ bool check_team(const BlockFactor& F, std::string& err) {
       }
     for (int g = 0; g <= team; ++g) {
       const TriPacked& T = G[g];
-      auto ok_dep = [&](int q, int l) {
+      auto ok_dep = [&](int ql, int l) {
+        const int q = bp(g, ql);
+        if (q < 0) return false;
         if (grp[q] == g) return lev[q] > l;   // solved later (lower) / earlier in the upper sweep
         return g < team && grp[q] == team;    // a subtree may reach the top group
       };

@@ -130,6 +130,9 @@ struct TriPacked {
   // entries a solve reads: values and int32 indices/record words, [0] on the
   // single-right-hand-side path (entry form where present), [1] on the panel path
   int64_t read_vals[2] = {0, 0}, read_ints[2] = {0, 0};
+  // team groups (BlockFactor::loS/upS) store local positions: pos[k] is the
+  // block position of local position k (empty: positions are block positions)
+  std::vector<int32_t> pos;
 };
 
 // Factorisation of one block M: P (Q M Q^T) = L U with Q a nested-dissection
@@ -259,7 +262,8 @@ void parallel_for(int count, int nthreads, const std::function<void(int)>& fn);
 // Pack a TriHost into the device layout (levels whose supernodes average
 // fewer than narrow_width rows also get the entry form); false if a supernode exceeds the
 // record field widths (w or h above 32767) or a block's arrays exceed 2^31.
-bool pack_tri(const TriHost& T, TriPacked& P, int narrow_width);
+// map (optional): block position -> the position the packed layout stores
+bool pack_tri(const TriHost& T, TriPacked& P, int narrow_width, const std::vector<int>* map = nullptr);
 
 // Largest top group stored as a dense inverse (8 MiB of FP64 per block).
 constexpr int kTopInvMaxRows = 1024;
@@ -274,6 +278,8 @@ bool top_inverse(const TriPacked& lo, const TriPacked& up, int n, std::vector<do
 // Host execution of a packed factor on one vector (diagnostics only).
 // entries: use the entry form where a level has one (else the panels).
 void host_tri_solve(const TriPacked& T, std::vector<double>& X, bool entries);
+// the same for a layout over local positions (TriPacked::pos): X by block position
+void host_tri_solve_pos(const TriPacked& T, std::vector<double>& X, bool entries);
 
 // Invariant subspace of a small real matrix H_m (n x n, column-major, leading
 // dimension ldh) for its Ritz values of largest modulus (the Krylov-Schur

@@ -1293,12 +1293,38 @@ __device__ __forceinline__ void team_out(const ApplyArrays<T>& A, const TeamIO<T
   }
 }
 
-// rows (positions) of group g of block bi in a team family, in level order
+// group g of block i of a team family: its local positions (own rows first,
+// then for a subtree group the top rows) and its own-row count
 template <typename T>
-__device__ __forceinline__ int team_rows(const TriArrays<T>& F, int bi, const int4*& rec) {
-  const DevTriBlock B = F.blk[bi];
-  rec = F.rec + 2 * B.rec_base;
-  return B.nlev > 0 ? F.lev_ptr[B.lev_base + B.nlev] : 0;
+struct TeamGroup {
+  const int32_t* P;  // local position -> block position
+  int nloc, nown;
+};
+template <typename T>
+__device__ __forceinline__ TeamGroup<T> team_group(const TeamArrays<T>& TA, int bi) {
+  TeamGroup<T> G;
+  const int64_t o = TA.pos_off[bi];
+  G.P = TA.pos + o;
+  G.nloc = (int)(TA.pos_off[bi + 1] - o);
+  const DevTriBlock B = TA.L.blk[bi];
+  G.nown = B.nlev > 0 ? TA.L.lev_ptr[B.lev_base + B.nlev] : 0;
+  return G;
+}
+
+// LDS of a team launch (team_lds_bytes): the local vector, level scratch and
+// the block's interface values
+template <typename T>
+struct TeamLds {
+  T *X, *Rb, *U;
+};
+template <typename T>
+__device__ __forceinline__ TeamLds<T> team_lds(const TeamArrays<T>& TA) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  TeamLds<T> L;
+  L.X = reinterpret_cast<T*>(smem);
+  L.Rb = L.X + ((TA.maxloc + 1) & ~1);
+  L.U = L.Rb + 3 * TA.maxlr;
+  return L;
 }
 
 // block i's interface values into LDS (B modes 0, 2); the tail's group 0 also
@@ -1323,33 +1349,24 @@ __global__ void __launch_bounds__(1024) k_team_lower(ApplyArrays<T> A, TeamIO<T>
   const int i = blockIdx.x / team, g = blockIdx.x - i * team, tid = threadIdx.x, nt = blockDim.x;
   int r0, nr;
   if (!tile_rhs<T, 1>(A, 1, i, r0, nr)) return;
-  Lds<T> L = carve<T, 1, false>(A);
-  T* X = FAM == 0 ? L.XB : L.XC;
+  TeamLds<T> L = team_lds<T>(TA);
+  T* X = L.X;
   const int64_t base = team_base<T, FAM>(A, i);
   team_load_u<T, FAM, MODE>(A, io, i, L.U, g == 0);
   const int bs = i * (team + 1);
-  const int4 *ro, *rt;
-  const int nown = team_rows(TA.L, bs + g, ro), ntop = team_rows(TA.L, bs + team, rt);
-  for (int k = tid; k < nown; k += nt) {
-    const int p = ro[2 * k].x;
-    X[p] = team_rhs<T, FAM, MODE>(A, io, i, base, p, L.U);
-  }
+  const TeamGroup<T> G = team_group<T>(TA, bs + g);
+  for (int k = tid; k < G.nown; k += nt) X[k] = team_rhs<T, FAM, MODE>(A, io, i, base, G.P[k], L.U);
   // the top rows start from their right-hand side in group 0 and from zero in
   // the others, so that the sum of the groups' top rows is the right-hand side
   // minus every push, each term formed once
-  for (int k = tid; k < ntop; k += nt) {
-    const int p = rt[2 * k].x;
-    X[p] = g == 0 ? team_rhs<T, FAM, MODE>(A, io, i, base, p, L.U) : (T)0;
-  }
+  for (int k = G.nown + tid; k < G.nloc; k += nt)
+    X[k] = g == 0 ? team_rhs<T, FAM, MODE>(A, io, i, base, G.P[k], L.U) : (T)0;
   __syncthreads();
   tri_solve<T, 1, false>(TA.L, bs + g, X, L.Rb, A.gshift);
   __syncthreads();
-  for (int k = tid; k < nown; k += nt) {
-    const int p = ro[2 * k].x;
-    io.xw[base + p] = X[p];
-  }
+  for (int k = tid; k < G.nown; k += nt) io.xw[base + G.P[k]] = X[k];
   T* d = io.dtop + ((int64_t)i * team + g) * TA.ntopmax;
-  for (int k = tid; k < ntop; k += nt) d[k] = X[rt[2 * k].x];
+  for (int k = G.nown + tid; k < G.nloc; k += nt) d[k - G.nown] = X[k];
 }
 
 // the top group by its packed factors, one workgroup per block
@@ -1360,26 +1377,22 @@ __global__ void __launch_bounds__(1024) k_team_top(ApplyArrays<T> A, TeamIO<T> i
   const int i = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
   int r0, nr;
   if (!tile_rhs<T, 1>(A, 1, i, r0, nr)) return;
-  Lds<T> L = carve<T, 1, false>(A);
-  T* X = FAM == 0 ? L.XB : L.XC;
+  TeamLds<T> L = team_lds<T>(TA);
+  T* X = L.X;
   const int64_t base = team_base<T, FAM>(A, i);
   const int bs = i * (team + 1);
-  const int4* rt;
-  const int ntop = team_rows(TA.L, bs + team, rt);
+  const TeamGroup<T> G = team_group<T>(TA, bs + team);
   const T* d = io.dtop + (int64_t)i * team * TA.ntopmax;
-  for (int k = tid; k < ntop; k += nt) {
+  for (int k = tid; k < G.nloc; k += nt) {
     T acc = (T)0;  // the right-hand side came with group 0's top rows
     for (int t = 0; t < team; ++t) acc += d[(int64_t)t * TA.ntopmax + k];
-    X[rt[2 * k].x] = acc;
+    X[k] = acc;
   }
   __syncthreads();
   tri_solve<T, 1, false>(TA.L, bs + team, X, L.Rb, A.gshift);
   tri_solve<T, 1, false>(TA.U, bs + team, X, L.Rb, A.gshift);
   __syncthreads();
-  for (int k = tid; k < ntop; k += nt) {
-    const int p = rt[2 * k].x;
-    team_out<T, FAM, MODE>(A, io, base, p, X[p], true);
-  }
+  for (int k = tid; k < G.nloc; k += nt) team_out<T, FAM, MODE>(A, io, base, G.P[k], X[k], true);
 }
 
 // The top group through its dense inverse: workgroup (i, rb) sums the
@@ -1397,8 +1410,8 @@ __global__ void __launch_bounds__(1024) k_team_topinv(ApplyArrays<T> A, TeamIO<T
   const int i = blockIdx.x / nrb, rb = blockIdx.x - i * nrb, tid = threadIdx.x, nt = blockDim.x;
   int r0, nr;
   if (!tile_rhs<T, 1>(A, 1, i, r0, nr)) return;
-  const int4* rt;
-  const int ntop = team_rows(TA.L, i * (team + 1) + team, rt);
+  const TeamGroup<T> G = team_group<T>(TA, i * (team + 1) + team);
+  const int ntop = G.nloc;
   if (rb * kTopRows >= ntop) return;  // uniform over the workgroup
   extern __shared__ __align__(16) unsigned char smem[];
   T* D = reinterpret_cast<T*>(smem);          // ntopmax + 2
@@ -1456,7 +1469,7 @@ __global__ void __launch_bounds__(1024) k_team_topinv(ApplyArrays<T> A, TeamIO<T
   if (wv == 0 && row < ntop) {
     T x = (T)0;
     for (int w = 0; w < nw; ++w) x += Ps[w * kTopRows + lane];
-    team_out<T, FAM, MODE>(A, io, base, rt[2 * row].x, x, true);
+    team_out<T, FAM, MODE>(A, io, base, G.P[row], x, true);
   }
 }
 
@@ -1467,27 +1480,17 @@ __global__ void __launch_bounds__(1024) k_team_upper(ApplyArrays<T> A, TeamIO<T>
   const int i = blockIdx.x / team, g = blockIdx.x - i * team, tid = threadIdx.x, nt = blockDim.x;
   int r0, nr;
   if (!tile_rhs<T, 1>(A, 1, i, r0, nr)) return;
-  Lds<T> L = carve<T, 1, false>(A);
-  T* X = FAM == 0 ? L.XB : L.XC;
+  TeamLds<T> L = team_lds<T>(TA);
+  T* X = L.X;
   const int64_t base = team_base<T, FAM>(A, i);
   const int bs = i * (team + 1);
-  const int4 *ro, *rt;
-  const int nown = team_rows(TA.U, bs + g, ro), ntop = team_rows(TA.U, bs + team, rt);
-  for (int k = tid; k < nown; k += nt) {
-    const int p = ro[2 * k].x;
-    X[p] = io.xw[base + p];
-  }
-  for (int k = tid; k < ntop; k += nt) {
-    const int p = rt[2 * k].x;
-    X[p] = io.xw[base + p];
-  }
+  const TeamGroup<T> G = team_group<T>(TA, bs + g);
+  // own rows (the lower solve's results) and the top rows
+  for (int k = tid; k < G.nloc; k += nt) X[k] = io.xw[base + G.P[k]];
   __syncthreads();
   tri_solve<T, 1, false>(TA.U, bs + g, X, L.Rb, A.gshift);
   __syncthreads();
-  for (int k = tid; k < nown; k += nt) {
-    const int p = ro[2 * k].x;
-    team_out<T, FAM, MODE>(A, io, base, p, X[p], false);
-  }
+  for (int k = tid; k < G.nown; k += nt) team_out<T, FAM, MODE>(A, io, base, G.P[k], X[k], false);
 }
 
 // the C0 part of a power-series step with t = B^{-1} E u read from xb, one
@@ -1733,23 +1736,24 @@ void launch_team(const ApplyArrays<T>& A, const LaunchCfg& c, const TeamIO<T>& i
                  hipEvent_t ev1) {
   const TeamArrays<T>& TA = FAM == 0 ? A.TB : A.TC;
   const dim3 gt((unsigned)(A.nparts * TA.team)), bt(c.threads);
+  const size_t lds = team_lds_bytes(TA, A.maxQB);
   if (ev0)
-    hipExtLaunchKernelGGL((k_team_lower<T, FAM, MODE>), gt, bt, (uint32_t)c.lds, c.stream, ev0, nullptr, 0,
-                          A, io);
+    hipExtLaunchKernelGGL((k_team_lower<T, FAM, MODE>), gt, bt, (uint32_t)lds, c.stream, ev0, nullptr, 0, A,
+                          io);
   else
-    hipLaunchKernelGGL((k_team_lower<T, FAM, MODE>), gt, bt, c.lds, c.stream, A, io);
+    hipLaunchKernelGGL((k_team_lower<T, FAM, MODE>), gt, bt, lds, c.stream, A, io);
   if (TA.TI && TA.nrb > 0) {
     const size_t lds = sizeof(T) * ((size_t)((TA.ntopmax + 3) & ~1) + (size_t)(c.threads / 64) * kTopRows);
     hipLaunchKernelGGL((k_team_topinv<T, FAM, MODE>), dim3((unsigned)(A.nparts * TA.nrb)), bt, lds, c.stream,
                        A, io);
   } else {
-    hipLaunchKernelGGL((k_team_top<T, FAM, MODE>), dim3((unsigned)A.nparts), bt, c.lds, c.stream, A, io);
+    hipLaunchKernelGGL((k_team_top<T, FAM, MODE>), dim3((unsigned)A.nparts), bt, lds, c.stream, A, io);
   }
   if (ev1)
-    hipExtLaunchKernelGGL((k_team_upper<T, FAM, MODE>), gt, bt, (uint32_t)c.lds, c.stream, nullptr, ev1, 0,
-                          A, io);
+    hipExtLaunchKernelGGL((k_team_upper<T, FAM, MODE>), gt, bt, (uint32_t)lds, c.stream, nullptr, ev1, 0, A,
+                          io);
   else
-    hipLaunchKernelGGL((k_team_upper<T, FAM, MODE>), gt, bt, c.lds, c.stream, A, io);
+    hipLaunchKernelGGL((k_team_upper<T, FAM, MODE>), gt, bt, lds, c.stream, A, io);
 }
 
 template <typename T>
@@ -1766,7 +1770,7 @@ TeamIO<T> team_io() {
 template <typename T>
 hipError_t launch_series_team(const ApplyArrays<T>& A, const LaunchCfg& c, const T* y,
                               const T* uprev, T* unext, int add_y, const TeamWs& W) {
-  if (A.TB.team < 2 || c.R != 1 || c.gx) return hipErrorInvalidValue;
+  if (A.TB.team < 2 || c.R != 1 || (A.TC.team < 2 && c.gx)) return hipErrorInvalidValue;
   TeamIO<T> io = team_io<T>();
   io.u = uprev;
   io.xw = (T*)W.xb;
@@ -1796,7 +1800,7 @@ hipError_t launch_series_team(const ApplyArrays<T>& A, const LaunchCfg& c, const
 template <typename T>
 hipError_t launch_head_team(const ApplyArrays<T>& A, const LaunchCfg& c, const double* b, T* y,
                             const TeamWs& W) {
-  if (A.TB.team < 2 || c.R != 1 || c.gx) return hipErrorInvalidValue;
+  if (A.TB.team < 2 || c.R != 1) return hipErrorInvalidValue;
   TeamIO<T> io = team_io<T>();
   io.b = b;
   io.xw = (T*)W.xb;
@@ -1811,7 +1815,7 @@ hipError_t launch_head_team(const ApplyArrays<T>& A, const LaunchCfg& c, const d
 template <typename T>
 hipError_t launch_tail_team(const ApplyArrays<T>& A, const LaunchCfg& c, const double* b,
                             const T* u, double* z, const TeamWs& W) {
-  if (A.TB.team < 2 || c.R != 1 || c.gx) return hipErrorInvalidValue;
+  if (A.TB.team < 2 || c.R != 1) return hipErrorInvalidValue;
   TeamIO<T> io = team_io<T>();
   io.b = b;
   io.u = u;
@@ -1825,7 +1829,7 @@ hipError_t launch_tail_team(const ApplyArrays<T>& A, const LaunchCfg& c, const d
 template <typename T>
 hipError_t launch_c0_team(const ApplyArrays<T>& A, const LaunchCfg& c, const T* src, T* dst,
                           const TeamWs& W) {
-  if (A.TC.team < 2 || c.R != 1 || c.gx) return hipErrorInvalidValue;
+  if (A.TC.team < 2 || c.R != 1) return hipErrorInvalidValue;
   TeamIO<T> io = team_io<T>();
   io.y = src;
   io.xw = (T*)W.xc;

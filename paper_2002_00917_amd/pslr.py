@@ -43,7 +43,8 @@ class pslr_host_stats_t(C.Structure):
     _fields_ = [("nnz_LU_B", C.c_int64), ("nnz_LU_C0", C.c_int64), ("max_levels_B", C.c_int32),
                 ("max_levels_C0", C.c_int32), ("levels_valid", C.c_int32),
                 ("factor_residual", C.c_double), ("solve_residual", C.c_double),
-                ("team", C.c_int32), ("team_valid", C.c_int32), ("team_residual", C.c_double)]
+                ("team", C.c_int32), ("team_valid", C.c_int32), ("team_residual", C.c_double),
+                ("team_lds_slots_B", C.c_int64), ("team_lds_slots_C", C.c_int64)]
 
 
 class pslr_info_t(C.Structure):
@@ -62,7 +63,8 @@ class pslr_info_t(C.Structure):
                 ("bf16_probe", C.c_double), ("lowrank", C.c_int32), ("ks_restarts", C.c_int32),
                 ("ks_applies", C.c_int64), ("ks_residual", C.c_double),
                 ("ritz_above_one", C.c_int32), ("mfma_min_rhs", C.c_int32), ("team", C.c_int32),
-                ("team_top", C.c_int32), ("team_c", C.c_int32), ("team_top_c", C.c_int32)]
+                ("team_top", C.c_int32), ("team_c", C.c_int32), ("team_top_c", C.c_int32),
+                ("team_apply", C.c_int32)]
 
 
 class pslr_trace_t(C.Structure):

@@ -118,3 +118,50 @@ def test_team_top_auto_and_limits():
     assert P.pslr_info(h)["team_top"] in (1, 2)
     with pytest.raises(P.PslrError):
         P.pslr_setup(A.rowptr, A.colind, A.vals, lab, 8, m=m, rank=0, team=4, team_top=3)
+
+
+@pytest.mark.parametrize("team", [4, 8])
+def test_team_blocks_larger_than_lds(team):
+    """Subdomains of 45000 rows (too large for one workgroup's LDS in FP64 and
+    in FP32, so the unsplit path keeps their working vectors in global memory)
+    take the team split when each group (its own rows and top rows, level
+    scratch, the interface values) fits one workgroup's LDS, by the host's
+    count of those slots: the single-right-hand-side applies match the
+    unsplit path and the oracle either way."""
+    dev = _dev()
+    N = 300
+    A = wl.laplacian2d(N, 0.05, Ny=N)
+    lab = opart.geometric_labels((N, N), (2, 1))
+    As = A.to_scipy()
+    blk = opslr.make_blocks(As, lab)
+    pre = opslr.PSLR(As, lab, 2, 4, v0=wl.start_vector(blk.q, 5))
+    b = wl.normal_rhs(A.n, 1, 23)
+    bt = torch.tensor(b[:, 0], dtype=torch.float64, device=dev)
+    ref = pre.apply(b)[:, 0]
+    st = P.pslr_host_stats(A.rowptr, A.colind, A.vals, lab, 2, want_transpose=False, team=team)
+    lds = 160 * 1024  # LDS of one workgroup on gfx950
+    # kappa(B_i) = 5.2e4 (extreme eigenvalues 7.95 and 1.53e-4 in modulus):
+    # kappa * eps is 1.15e-11 in FP64 and 3.1e-3 in FP32, above the 1e-12 and
+    # 1e-5 that better-conditioned blocks meet
+    for prec, tol in ((0, 1.2e-11), (1, 3.1e-3)):
+        w = 8 if prec == 0 else 4
+        assert w * blk.p // 2 > lds  # each block alone overflows the LDS
+        fits = w * (st["team_lds_slots_B"] + blk.q) <= lds
+        zs = {}
+        for t in (1, team):
+            h = P.pslr_setup(A.rowptr, A.colind, A.vals, lab, 2, m=2, rank=0, precision=prec, team=t)
+            inf = P.pslr_info(h)
+            if t > 1:
+                assert inf["team"] == team and (inf["team_apply"] >= 1) == fits, (st, inf["team_apply"])
+            else:
+                assert inf["team_apply"] == 0
+            P.pslr_set_lowrank(h, pre.V, pre.H)
+            z = torch.zeros_like(bt)
+            P.pslr_apply(h, bt, z)
+            torch.cuda.synchronize()
+            zs[t] = z.cpu().numpy()
+        e_pl, e_or = _rel(zs[team], zs[1]), _rel(zs[team], ref)
+        print("45000-row blocks team", team, "precision", prec, "team path", fits,
+              "team vs plain %.2e, vs oracle %.2e" % (e_pl, e_or), flush=True)
+        assert e_pl <= tol
+        assert e_or <= tol
