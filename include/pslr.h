@@ -119,7 +119,7 @@ typedef struct {
                                    to 256), so that all eigenvalues of E_rr(m) outside the unit
                                    circle are deflated (Sec. 3.2.2); pslr_info.rank gives the
                                    count reached, which may exceed r_k */
-  int32_t team;             /* B_i and C_i solves of single-right-hand-side applies spread over
+  int32_t team;             /* B_i and C_i solves of forward applies spread over
                                `team` workgroups per subdomain (the supernodal tree of each
                                block cut into `team` groups of whole subtrees and the top group
                                above them; exact LU only): 0 = automatic (4 when nparts <= 128,
@@ -132,6 +132,10 @@ typedef struct {
                                with the dense inverse of the top group's block of L U, spread
                                over one workgroup per 64 top rows (PSLR_EINVAL when a top
                                group has more than 1024 rows) */
+  int32_t team_rhs;         /* forward applies of up to team_rhs right-hand sides take the team
+                               split, one right-hand side per workgroup (wider applies keep one
+                               workgroup per block and tile of right-hand sides, which reads
+                               the factors once per tile): 0 = automatic (1), 1 .. 64 */
 } pslr_options;
 
 typedef struct {
@@ -369,7 +373,7 @@ typedef struct {
                                where it has one) and its plain packed solve */
   int64_t team_lds_slots_B; /* largest LDS footprint of one team workgroup over the B_i, in
                                values of the working precision: the group's own and top rows
-                               (rounded up to even) plus three times its widest level.  The
+                               (rounded up to even) plus twice its widest level.  The
                                B_i team solves also hold the block's interface values, so a
                                split runs when (slots_B + max q_i) * value size and
                                slots_C * value size fit one workgroup's LDS */

@@ -265,6 +265,7 @@ struct pslr_ctx {
   int64_t gws_stride = 0;
   int tuned_threads = 0, tuned_gshift = 0;
   int rmax = 8;      // widest right-hand-side tile of a launch (autotuned)
+  int team_rhs = 1;  // applies of up to this many right-hand sides take the team solves
   const int64_t* d_rb_off = nullptr;
   // apply workspaces (grow-only, see ensure_ws)
   int ws_nrhs = 0;
@@ -555,7 +556,7 @@ hipError_t upload_dir(DevPool& pool, const Reordering& R, const std::vector<Bloc
 template <typename T>
 size_t lds_bytes(const ApplyArrays<T>& A, int kmax, int R = 1) {
   return sizeof(T) * (size_t)R *
-         ((size_t)A.maxPB + 3 * (size_t)A.maxLR + 2 * (size_t)A.maxQB + 2 * (size_t)std::max(kmax, 1));
+         ((size_t)A.maxPB + 2 * (size_t)A.maxLR + 2 * (size_t)A.maxQB + 2 * (size_t)std::max(kmax, 1));
 }
 
 WsSizes ws_sizes(const pslr_ctx* h, int nrhs) {
@@ -564,13 +565,15 @@ WsSizes ws_sizes(const pslr_ctx* h, int nrhs) {
   // V^T y chunk partials, then G W per system (one right-hand side)
   z.partial = (size_t)h->nchunk_lr * nrhs * std::max(h->k, 1) + (size_t)h->nsys * std::max(h->k, 1);
   z.gws = h->gws_stride > 0 ? (size_t)h->gws_stride * ((nrhs + 7) / 8 * 8) : 0;
-  // the family vectors and top-row updates of the team solves (one right-hand
-  // side): [xb: p][dtopb: nparts x team x ntopmax of B][xc: q][dtopc: the same of C]
+  // the family vectors and top-row updates of the team solves, each with one
+  // slice per right-hand side: [xb: p][dtopb: nparts x team x ntopmax of B]
+  // [xc: q][dtopc: the same of C]
   if (h->fw64.TB.team > 1) {
     const TeamArrays<double>&TB = h->fw64.TB, &TC = h->fw64.TC;
     z.team = (size_t)std::max<int64_t>(h->R.p, 1) + (size_t)h->R.nparts * TB.team * TB.ntopmax;
     if (TC.team > 1)
       z.team += (size_t)std::max<int64_t>(h->R.q, 1) + (size_t)h->R.nparts * TC.team * TC.ntopmax;
+    z.team *= (size_t)std::min(nrhs, h->team_rhs);
   }
   // split G V^T y of the matrix-core low-rank products (BF16 V only)
   if (h->Vbr && nrhs >= kMfmaMinRhs)
@@ -804,8 +807,8 @@ LaunchCfg choose_launch(pslr_ctx* h, const ApplyArrays<T>& A, int nrhs, hipStrea
   return c;
 }
 
-// Team path of a single-right-hand-side forward apply with arrays A and
-// launch configuration c: team (every B_i solve split over a team of
+// Team path of a forward apply with arrays A and launch configuration c (of
+// at most team_rhs right-hand sides): team (every B_i solve split over a team of
 // workgroups, each holding its group's rows in LDS) and cteam (the C_i solves
 // too).  The split also serves subdomains too large for one workgroup's LDS,
 // as long as each group fits; a C_i without a team split is then solved in
@@ -814,7 +817,7 @@ template <typename T>
 void team_path(const pslr_ctx* h, const ApplyArrays<T>& A, const LaunchCfg& c, bool& team, bool& cteam) {
   const bool tb_fit = A.TB.team > 1 && team_lds_bytes(A.TB, A.maxQB) <= h->lds_max;
   const bool tc_fit = A.TC.team > 1 && team_lds_bytes(A.TC, A.maxQB) <= h->lds_max;
-  team = tb_fit && (tc_fit || !c.gx) && c.R == 1;
+  team = tb_fit && (tc_fit || !c.gx);
   cteam = team && tc_fit;
 }
 
@@ -847,25 +850,30 @@ pslr_status run_apply(pslr_ctx* h, const ApplyArrays<T>& Ah, const ApplyWs& W, b
     ~Restore() { h->trace = v; }
   } restore{h, tr_on};
   Tracer tr{h, s, {}};
-  // one right-hand side: the team solves (workspace layout as in ws_sizes)
+  // the team solves (workspace layout as in ws_sizes), for up to
+  // team_rhs right-hand sides
   bool team = false, cteam = false;
-  if (W.team && nrhs == 1 && !transpose) team_path<T>(h, A, cfg, team, cteam);
+  if (W.team && nrhs <= h->team_rhs && !transpose) team_path<T>(h, A, cfg, team, cteam);
   if (team && !cteam) A.TC.team = 0;
-  TeamWs tw{nullptr, nullptr, nullptr, nullptr};
+  TeamWs tw{};
   if (team) {
     T* t = (T*)W.team;
+    tw.ldxb = std::max<int64_t>(h->R.p, 1);
+    tw.lddb = (int64_t)A.nparts * A.TB.team * A.TB.ntopmax;
     tw.xb = t;
-    t += std::max<int64_t>(h->R.p, 1);
+    t += tw.ldxb * nrhs;
     tw.dtopb = t;
-    t += (int64_t)A.nparts * A.TB.team * A.TB.ntopmax;
+    t += tw.lddb * nrhs;
     if (cteam) {
+      tw.ldxc = std::max<int64_t>(h->R.q, 1);
+      tw.lddc = (int64_t)A.nparts * A.TC.team * A.TC.ntopmax;
       tw.xc = t;
-      t += std::max<int64_t>(h->R.q, 1);
+      t += tw.ldxc * nrhs;
       tw.dtopc = t;
     }
   }
   HIP_TRY(tr.mark(PH_START));
-  if (team) HIP_TRY(launch_head_team<T>(A, cfg, b, y, tw));
+  if (team) HIP_TRY(launch_head_team<T>(A, cfg, nrhs, b, ldb, y, q, tw));
   else HIP_TRY(launch_head<T>(A, cfg, nrhs, b, ldb, y, q));
   HIP_TRY(tr.mark(PH_HEAD));
   // FP32 applies with V in BF16 and many right-hand sides: the low-rank
@@ -877,16 +885,19 @@ pslr_status run_apply(pslr_ctx* h, const ApplyArrays<T>& Ah, const ApplyWs& W, b
       HIP_TRY(launch_lr_mfma(h->nchunk_lr, h->d_chunks, h->nsys, h->d_sys_chunk, k, h->Vbf, h->R.q,
                              h->Vbr, h->G32, 0, (float*)y, q, nrhs, (float*)part,
                              (__hip_bfloat16*)W.zp, h->cur_active, s));
-      HIP_TRY(launch_c0solve<T>(A, cfg, nrhs, y, q, ua, q));
+      if (cteam) HIP_TRY(launch_c0_team<T>(A, cfg, nrhs, y, ua, q, tw));
+      else HIP_TRY(launch_c0solve<T>(A, cfg, nrhs, y, q, ua, q));
     } else if (k > 0 && nrhs == 1) {
       HIP_TRY(lowrank1<T>(h, y, part, 0, s));
-      if (cteam) HIP_TRY(launch_c0_team<T>(A, cfg, y, ua, tw));
+      if (cteam) HIP_TRY(launch_c0_team<T>(A, cfg, nrhs, y, ua, q, tw));
       else HIP_TRY(launch_c0solve<T>(A, cfg, nrhs, y, q, ua, q));
     } else if (k > 0) {
       HIP_TRY(lowrank_partial<T>(h, y, q, nrhs, part, s));
-      HIP_TRY(lowrank_expand<T>(h, A, cfg, nrhs, 0, part, y, q, 1, ua, q));
+      // the expansion fused with the C0 solve, or the C_i team solves after it
+      HIP_TRY(lowrank_expand<T>(h, A, cfg, nrhs, 0, part, y, q, cteam ? 0 : 1, ua, q));
+      if (cteam) HIP_TRY(launch_c0_team<T>(A, cfg, nrhs, y, ua, q, tw));
     } else if (cteam) {
-      HIP_TRY(launch_c0_team<T>(A, cfg, y, ua, tw));
+      HIP_TRY(launch_c0_team<T>(A, cfg, nrhs, y, ua, q, tw));
     } else {
       HIP_TRY(launch_c0solve<T>(A, cfg, nrhs, y, q, ua, q));
     }
@@ -894,7 +905,7 @@ pslr_status run_apply(pslr_ctx* h, const ApplyArrays<T>& Ah, const ApplyWs& W, b
     for (int i = 0; i < h->m; ++i) {
       LaunchCfg c1 = cfg;
       HIP_TRY(tr.span(PH_SERIES, c1));
-      if (team) HIP_TRY(launch_series_team<T>(A, c1, y, ua, ub, 1, tw));
+      if (team) HIP_TRY(launch_series_team<T>(A, c1, nrhs, y, ua, ub, q, 1, tw));
       else HIP_TRY(launch_series<T>(A, c1, nrhs, y, q, ua, ub, q, 1, 1));
       std::swap(ua, ub);
     }
@@ -921,7 +932,7 @@ pslr_status run_apply(pslr_ctx* h, const ApplyArrays<T>& Ah, const ApplyWs& W, b
       HIP_TRY(tr.mark(PH_LOWRANK));
     }
   }
-  if (team) HIP_TRY(launch_tail_team<T>(A, cfg, b, ua, z, tw));
+  if (team) HIP_TRY(launch_tail_team<T>(A, cfg, nrhs, b, ldb, ua, q, z, ldz, tw));
   else HIP_TRY(launch_tail<T>(A, cfg, nrhs, b, ldb, ua, q, z, ldz));
   HIP_TRY(tr.mark(PH_TAIL));
   HIP_TRY(tr.finish());
@@ -1723,6 +1734,7 @@ void pslr_default_options(pslr_options* o) {
   o->lowrank = 0;
   o->team = 0;
   o->team_top = 0;
+  o->team_rhs = 0;
 }
 
 const char* pslr_status_string(pslr_status s) {
@@ -1867,14 +1879,14 @@ pslr_status pslr_host_stats(int64_t n, const int64_t* rowptr, const int32_t* col
       // solves) against the plain packed solve
       std::string terr;
       if (!check_team(f, terr)) tvalid[t] = 0;
-      // LDS slots of one team workgroup: the group's local vector and three
-      // thirds of level scratch (as the device layout)
+      // LDS slots of one team workgroup: the group's local vector and two
+      // halves of level scratch (as the device layout)
       int maxloc = 1, maxlr = 1;
       for (int g = 0; g <= f.team; ++g) {
         maxloc = std::max<int>(maxloc, (int)f.loS[g].pos.size());
         maxlr = std::max({maxlr, f.loS[g].max_lrows, f.upS[g].max_lrows});
       }
-      tslots[t] = ((maxloc + 1) & ~1) + 3 * (int64_t)maxlr;
+      tslots[t] = ((maxloc + 1) & ~1) + 2 * (int64_t)maxlr;
       const int nb = M.nrows;
       std::vector<double> X0(nb), X1(nb);
       for (int i = 0; i < nb; ++i) X0[i] = X1[i] = std::cos(0.3 + 0.71 * i);
@@ -2102,6 +2114,7 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
   if (o.lowrank < 0 || o.lowrank > 2) return fail(PSLR_EINVAL, "lowrank must be 0, 1 or 2");
   if (o.team < 0 || o.team > 8) return fail(PSLR_EINVAL, "team must be 0 .. 8");
   if (o.team_top < 0 || o.team_top > 2) return fail(PSLR_EINVAL, "team_top must be 0, 1 or 2");
+  if (o.team_rhs < 0 || o.team_rhs > 64) return fail(PSLR_EINVAL, "team_rhs must be 0 .. 64");
   o.team = resolve_team(o, nparts);
   const double tau = o.pivot_threshold > 0 ? o.pivot_threshold : 0.1;
   for (int64_t k = 0; k < (n > 0 ? rowptr[n] : 0); ++k)
@@ -2212,6 +2225,7 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
   h->hA_ptr.assign(rowptr, rowptr + n + 1);
   h->hA_col.assign(colind, colind + h->nnzA);
   h->opt = o;
+  h->team_rhs = o.team_rhs > 0 ? o.team_rhs : 1;
   if (o.v0) h->hv0.assign(o.v0, o.v0 + h->R.q);
   h->opt.v0 = nullptr;
   // per-system tables: subdomain -> system, V^T y row chunks, interface segments
@@ -2259,7 +2273,7 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
       int mx = 1;
       for (const BlockFactor* f : {&fB[i], &fC[i]})
         for (const TriPacked* T : {&f->lo, &f->up, &f->loT, &f->upT}) mx = std::max(mx, T->max_lrows);
-      rb[i + 1] = rb[i] + 3 * mx;  // thirds rotated over the levels
+      rb[i + 1] = rb[i] + 2 * mx;  // halves alternating over the levels
     }
     HIP_TRY(h->facpool.upload(rb, &h->d_rb_off));
     h->gws_stride = h->R.p + 2 * h->R.q + rb[nparts] + (int64_t)nparts * 2 * std::max(h->rank, 1);
@@ -2395,7 +2409,7 @@ pslr_status pslr_refactor(pslr_handle h, const double* vals, void* hip_stream) {
       int mx = 1;
       for (const BlockFactor* f : {&fB[i], &fC[i]})
         for (const TriPacked* T : {&f->lo, &f->up, &f->loT, &f->upT}) mx = std::max(mx, T->max_lrows);
-      rb[i + 1] = rb[i] + 3 * mx;
+      rb[i + 1] = rb[i] + 2 * mx;  // halves alternating over the levels
     }
     HIP_TRY(nf.upload(rb, &d_rb_off));
     gws_stride = h->R.p + 2 * h->R.q + rb[np] + (int64_t)np * 2 * std::max(h->fw64.kmax, 1);

@@ -72,11 +72,11 @@ struct TeamArrays {
   int32_t maxloc, maxlr;
 };
 
-// LDS of a team launch: the group's local vector, three thirds of level
+// LDS of a team launch: the group's local vector, two halves of level
 // scratch, and the block's interface values (interior family)
 template <typename T>
 inline size_t team_lds_bytes(const TeamArrays<T>& TA, int32_t maxQB) {
-  return sizeof(T) * ((size_t)((TA.maxloc + 1) & ~1) + 3 * (size_t)TA.maxlr + (size_t)maxQB);
+  return sizeof(T) * ((size_t)((TA.maxloc + 1) & ~1) + 2 * (size_t)TA.maxlr + (size_t)maxQB);
 }
 
 // Everything one direction (forward or transposed) of the apply needs.
@@ -204,34 +204,37 @@ hipError_t launch_tail(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, co
                        int64_t ldb, const T* u, int64_t ldu, double* z, int64_t ldz);
 template <typename T>
 hipError_t set_lds_limit(size_t bytes);
-// Solves of one right-hand side spread over the team of workgroups of each
-// block (working vectors in LDS), three launches per family: the subtree
-// groups' lower solves, the top group, the groups' upper solves.  Between the
-// launches the family's vector and the top rows' pushed updates live in the
-// workspace TeamWs.
+// Solves spread over the team of workgroups of each block, one right-hand
+// side per workgroup (column blockIdx.y, working vectors in LDS), three
+// launches per family: the subtree groups' lower solves, the top group, the
+// groups' upper solves.  Between the launches the family's vector and the top
+// rows' pushed updates live in the workspace TeamWs, one slice per column.
 struct TeamWs {
-  void* xb;     // p values: the B-solve vector
-  void* dtopb;  // nparts * TB.team * TB.ntopmax values
-  void* xc;     // q values: the C0-solve vector
-  void* dtopc;  // nparts * TC.team * TC.ntopmax values
+  void* xb;     // per column p values: the B-solve vector
+  void* dtopb;  // per column nparts * TB.team * TB.ntopmax values
+  void* xc;     // per column q values: the C0-solve vector
+  void* dtopc;  // per column nparts * TC.team * TC.ntopmax values
+  int64_t ldxb, lddb, ldxc, lddc;  // the slices' lengths (column strides)
 };
+// Vectors of nrhs columns with the given leading dimensions (y, u, src, dst:
+// ldv; b: ldb; z: ldz):
 //   series step: unext = C0^{-1}(y [add_y] - C_g u + F B^{-1} E u)  (C0 solve split when
-//                A.TC.team > 1, else one workgroup per subdomain)
+//                A.TC.team > 1, else one workgroup per subdomain and column)
 //   head:        y = g - F B^{-1} f                                (+ a launch for F)
 //   tail:        z = P^T (B^{-1}(f - E u); u)
 //   c0:          dst = C0^{-1} src                                 (A.TC.team > 1 only)
 template <typename T>
-hipError_t launch_series_team(const ApplyArrays<T>& A, const LaunchCfg& c, const T* y,
-                              const T* uprev, T* unext, int add_y, const TeamWs& W);
+hipError_t launch_series_team(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, const T* y,
+                              const T* uprev, T* unext, int64_t ldv, int add_y, const TeamWs& W);
 template <typename T>
-hipError_t launch_head_team(const ApplyArrays<T>& A, const LaunchCfg& c, const double* b, T* y,
-                            const TeamWs& W);
+hipError_t launch_head_team(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, const double* b,
+                            int64_t ldb, T* y, int64_t ldy, const TeamWs& W);
 template <typename T>
-hipError_t launch_tail_team(const ApplyArrays<T>& A, const LaunchCfg& c, const double* b,
-                            const T* u, double* z, const TeamWs& W);
+hipError_t launch_tail_team(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, const double* b,
+                            int64_t ldb, const T* u, int64_t ldu, double* z, int64_t ldz, const TeamWs& W);
 template <typename T>
-hipError_t launch_c0_team(const ApplyArrays<T>& A, const LaunchCfg& c, const T* src, T* dst,
-                          const TeamWs& W);
+hipError_t launch_c0_team(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, const T* src, T* dst,
+                          int64_t ldv, const TeamWs& W);
 
 // ---- FP64 vector kernels for Arnoldi and FGMRES
 hipError_t launch_spmv(int64_t n, const int64_t* ptr, const int32_t* col, const double* val,

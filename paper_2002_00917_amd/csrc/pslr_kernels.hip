@@ -179,14 +179,14 @@ __device__ __forceinline__ void entry_sweep(const double2* __restrict__ er, int 
 }
 
 // Solve one packed triangular factor of block `bi` in place on the vector tile
-// X (positions 0..n-1, R right-hand sides).  Rb is scratch of 3 * max_lrows * R
-// entries (thirds rotated over the levels).  All threads of the workgroup
+// X (positions 0..n-1, R right-hand sides).  Rb is scratch of 2 * max_lrows * R
+// entries (halves alternating over the levels).  All threads of the workgroup
 // must call it; it ends with a barrier.
 //
 // The panels are folded with the inverted triangles (see TriPacked), so each
 // level is one step between two barriers over values from before the level.
 // Lower factors run right-looking: every row item forms s_k = sum_j Tinv(i, j)
-// x[f + j] into the level's third of Rb while every push item subtracts
+// x[f + j] into the level's half of Rb while every push item subtracts
 // Pf(a, :) x[f ..] from x[ridx[a]] (atomic adds: supernodes of a level may
 // update the same rows); the level's s goes into x during the next level,
 // which reads none of its rows.  Upper factors run left-looking: x[p] =
@@ -231,16 +231,18 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
     }
   }
   if (B.lower) {
+    // two halves of the scratch alternate over the levels: level l's results
+    // go to half l & 1 while the other half (level l - 1's results) is copied
+    // into x and, when level l + 1 accumulates chunks, cleared for it
     int bp = 0, cntp = 0, pfx = 0;  // the previous level's rows and this thread's first position
-    T* Rp = Rb;
+    T* Rp = Rb + RS;
     for (int l = 0; l < B.nlev; ++l) {
       const int b = lev_ptr[l];
       const int cnt = lev_ptr[l + 1] - b;
       int CT, CP;
       level_chunks(lev_c[l], gshift, CT, CP);
       const bool ent = use_ent(l);
-      T* Rc = Rb + (l % 3) * RS;
-      T* Rn = Rb + ((l + 1) % 3) * RS;
+      T* Rc = Rb + (l & 1) * RS;
       int bn = 0, cntn = 0, CTn = 1, CPn = 1;
       if (l + 1 < B.nlev) {
         bn = lev_ptr[l + 1];
@@ -254,15 +256,22 @@ __device__ void tri_solve(const TriArrays<T>& A, int bi, T* X, T* Rb, int gshift
       const int pb = push_ptr[l], np = ent ? 0 : push_ptr[l + 1] - pb;
       int4 fq = f0;
       if (np > 0) fq = prec[pb + tid % np];
-      // the previous level's results into x; the next level's third cleared
-      // when its triangle items are chunked
-      for (int k = tid; k < cntp; k += nthr) {
-        const int p = k == tid ? pfx : rec[2 * (bp + k)].x;
+      // the previous level's results into x, then (by the same thread, after
+      // its read) that half cleared for the next level when its triangle items
+      // are chunked
+      {
+        const int kz = CTn > 1 ? cntn : 0;
+        for (int k = tid; k < max(cntp, kz); k += nthr) {
+          if (k < cntp) {
+            const int p = k == tid ? pfx : rec[2 * (bp + k)].x;
 #pragma unroll
-        for (int r = 0; r < R; ++r) X[p * R + r] = Rp[k * R + r];
+            for (int r = 0; r < R; ++r) X[p * R + r] = Rp[k * R + r];
+          }
+          if (k < kz)
+#pragma unroll
+            for (int r = 0; r < R; ++r) Rp[k * R + r] = (T)0;
+        }
       }
-      if (CTn > 1)
-        for (int e = tid; e < cntn * R; e += nthr) Rn[e] = (T)0;
       // s_k = Tinv(i, 0..i) x[f .. f+i]
       {
         int4 r0 = f0, r1 = f1;
@@ -554,7 +563,7 @@ __device__ Lds<T> carve(const ApplyArrays<T>& A) {
     extern __shared__ __align__(16) unsigned char smem[];
     L.XB = reinterpret_cast<T*>(smem);
     L.Rb = L.XB + R * A.maxPB;
-    L.XC = L.Rb + 3 * R * A.maxLR;
+    L.XC = L.Rb + 2 * R * A.maxLR;
     L.U = L.XC + R * A.maxQB;
     L.W = L.U + R * A.maxQB;
   }
@@ -1240,7 +1249,25 @@ struct TeamIO {
   double* z;        // B mode 2
   T* out;           // C: the result
   int add_y;
+  // distances between the columns of a multi-right-hand-side launch (column
+  // blockIdx.y), in elements of each array
+  int64_t ldb, ldu, ldy, ldxb, ldxw, lddt, ldz, ldo;
 };
+
+// io moved to column blockIdx.y of a multi-right-hand-side team launch
+template <typename T>
+__device__ __forceinline__ void team_col(TeamIO<T>& io) {
+  const int64_t r = blockIdx.y;
+  if (r == 0) return;
+  if (io.b) io.b += r * io.ldb;
+  if (io.u) io.u += r * io.ldu;
+  if (io.y) io.y += r * io.ldy;
+  if (io.xb) io.xb += r * io.ldxb;
+  if (io.xw) io.xw += r * io.ldxw;
+  if (io.dtop) io.dtop += r * io.lddt;
+  if (io.z) io.z += r * io.ldz;
+  if (io.out) io.out += r * io.ldo;
+}
 
 template <typename T, int FAM>
 __device__ __forceinline__ const TeamArrays<T>& team_fam(const ApplyArrays<T>& A) {
@@ -1323,7 +1350,7 @@ __device__ __forceinline__ TeamLds<T> team_lds(const TeamArrays<T>& TA) {
   TeamLds<T> L;
   L.X = reinterpret_cast<T*>(smem);
   L.Rb = L.X + ((TA.maxloc + 1) & ~1);
-  L.U = L.Rb + 3 * TA.maxlr;
+  L.U = L.Rb + 2 * TA.maxlr;
   return L;
 }
 
@@ -1348,7 +1375,8 @@ __global__ void __launch_bounds__(1024) k_team_lower(ApplyArrays<T> A, TeamIO<T>
   const int team = TA.team;
   const int i = blockIdx.x / team, g = blockIdx.x - i * team, tid = threadIdx.x, nt = blockDim.x;
   int r0, nr;
-  if (!tile_rhs<T, 1>(A, 1, i, r0, nr)) return;
+  if (!tile_rhs<T, 1>(A, gridDim.y, i, r0, nr)) return;
+  team_col(io);
   TeamLds<T> L = team_lds<T>(TA);
   T* X = L.X;
   const int64_t base = team_base<T, FAM>(A, i);
@@ -1376,7 +1404,8 @@ __global__ void __launch_bounds__(1024) k_team_top(ApplyArrays<T> A, TeamIO<T> i
   const int team = TA.team;
   const int i = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
   int r0, nr;
-  if (!tile_rhs<T, 1>(A, 1, i, r0, nr)) return;
+  if (!tile_rhs<T, 1>(A, gridDim.y, i, r0, nr)) return;
+  team_col(io);
   TeamLds<T> L = team_lds<T>(TA);
   T* X = L.X;
   const int64_t base = team_base<T, FAM>(A, i);
@@ -1409,7 +1438,8 @@ __global__ void __launch_bounds__(1024) k_team_topinv(ApplyArrays<T> A, TeamIO<T
   const int team = TA.team, nrb = TA.nrb;
   const int i = blockIdx.x / nrb, rb = blockIdx.x - i * nrb, tid = threadIdx.x, nt = blockDim.x;
   int r0, nr;
-  if (!tile_rhs<T, 1>(A, 1, i, r0, nr)) return;
+  if (!tile_rhs<T, 1>(A, gridDim.y, i, r0, nr)) return;
+  team_col(io);
   const TeamGroup<T> G = team_group<T>(TA, i * (team + 1) + team);
   const int ntop = G.nloc;
   if (rb * kTopRows >= ntop) return;  // uniform over the workgroup
@@ -1479,7 +1509,8 @@ __global__ void __launch_bounds__(1024) k_team_upper(ApplyArrays<T> A, TeamIO<T>
   const int team = TA.team;
   const int i = blockIdx.x / team, g = blockIdx.x - i * team, tid = threadIdx.x, nt = blockDim.x;
   int r0, nr;
-  if (!tile_rhs<T, 1>(A, 1, i, r0, nr)) return;
+  if (!tile_rhs<T, 1>(A, gridDim.y, i, r0, nr)) return;
+  team_col(io);
   TeamLds<T> L = team_lds<T>(TA);
   T* X = L.X;
   const int64_t base = team_base<T, FAM>(A, i);
@@ -1498,10 +1529,16 @@ __global__ void __launch_bounds__(1024) k_team_upper(ApplyArrays<T> A, TeamIO<T>
 template <typename T>
 __global__ void __launch_bounds__(1024) k_team_c0(ApplyArrays<T> A, const T* __restrict__ y,
                                                   const T* __restrict__ uprev, T* unext,
-                                                  const T* __restrict__ xb, int add_y) {
+                                                  const T* __restrict__ xb, int add_y, int64_t ldv,
+                                                  int64_t ldxb) {
   const int i = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
   int r0, nr;
-  if (!tile_rhs<T, 1>(A, 1, i, r0, nr)) return;
+  if (!tile_rhs<T, 1>(A, gridDim.y, i, r0, nr)) return;
+  // column blockIdx.y: y, uprev and unext with leading dimension ldv, xb with ldxb
+  y += (int64_t)r0 * ldv;
+  uprev += (int64_t)r0 * ldv;
+  unext += (int64_t)r0 * ldv;
+  xb += (int64_t)r0 * ldxb;
   Lds<T> L = carve<T, 1, false>(A);
   const int64_t f0 = A.if_ptr[i], qi = A.if_ptr[i + 1] - f0;
   const int64_t i0 = A.int_ptr[i];
@@ -1522,9 +1559,15 @@ __global__ void __launch_bounds__(1024) k_team_c0(ApplyArrays<T> A, const T* __r
 // y = g - F t of the head with t = B^{-1} f read from xb (one thread per interface row)
 template <typename T>
 __global__ void __launch_bounds__(256) k_team_headF(ApplyArrays<T> A, const double* __restrict__ b,
-                                                    const T* __restrict__ xb, T* y) {
+                                                    const T* __restrict__ xb, T* y, int64_t ldb,
+                                                    int64_t ldxb, int64_t ldy) {
   const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (row >= A.q) return;
+  // column blockIdx.y
+  const int64_t r = blockIdx.y;
+  b += r * ldb;
+  xb += r * ldxb;
+  y += r * ldy;
   // subdomain of the row: the last i with if_ptr[i] <= row (binary search)
   int lo = 0, hi = A.nparts - 1;
   while (lo < hi) {
@@ -1532,7 +1575,7 @@ __global__ void __launch_bounds__(256) k_team_headF(ApplyArrays<T> A, const doub
     if (A.if_ptr[mid] <= row) lo = mid;
     else hi = mid - 1;
   }
-  if (A.active && !A.active[A.part_sys[lo]]) return;
+  if (A.active && !A.active[r * A.nsys + A.part_sys[lo]]) return;
   const int64_t i0 = A.int_ptr[lo];
   T acc = (T)b[A.if_orig[row]];
   for (int64_t q = A.Fout.ptr[row]; q < A.Fout.ptr[row + 1]; ++q)
@@ -1732,10 +1775,11 @@ hipError_t launch_tail(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, co
 // the three launches of a team solve of family FAM; ev0 / ev1 (may be null)
 // are recorded at the start of the first and the end of the last launch
 template <typename T, int FAM, int MODE>
-void launch_team(const ApplyArrays<T>& A, const LaunchCfg& c, const TeamIO<T>& io, hipEvent_t ev0,
+void launch_team(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, const TeamIO<T>& io, hipEvent_t ev0,
                  hipEvent_t ev1) {
   const TeamArrays<T>& TA = FAM == 0 ? A.TB : A.TC;
-  const dim3 gt((unsigned)(A.nparts * TA.team)), bt(c.threads);
+  const unsigned ny = (unsigned)nrhs;
+  const dim3 gt((unsigned)(A.nparts * TA.team), ny), bt(c.threads);
   const size_t lds = team_lds_bytes(TA, A.maxQB);
   if (ev0)
     hipExtLaunchKernelGGL((k_team_lower<T, FAM, MODE>), gt, bt, (uint32_t)lds, c.stream, ev0, nullptr, 0, A,
@@ -1744,10 +1788,10 @@ void launch_team(const ApplyArrays<T>& A, const LaunchCfg& c, const TeamIO<T>& i
     hipLaunchKernelGGL((k_team_lower<T, FAM, MODE>), gt, bt, lds, c.stream, A, io);
   if (TA.TI && TA.nrb > 0) {
     const size_t lds = sizeof(T) * ((size_t)((TA.ntopmax + 3) & ~1) + (size_t)(c.threads / 64) * kTopRows);
-    hipLaunchKernelGGL((k_team_topinv<T, FAM, MODE>), dim3((unsigned)(A.nparts * TA.nrb)), bt, lds, c.stream,
-                       A, io);
+    hipLaunchKernelGGL((k_team_topinv<T, FAM, MODE>), dim3((unsigned)(A.nparts * TA.nrb), ny), bt, lds,
+                       c.stream, A, io);
   } else {
-    hipLaunchKernelGGL((k_team_top<T, FAM, MODE>), dim3((unsigned)A.nparts), bt, lds, c.stream, A, io);
+    hipLaunchKernelGGL((k_team_top<T, FAM, MODE>), dim3((unsigned)A.nparts, ny), bt, lds, c.stream, A, io);
   }
   if (ev1)
     hipExtLaunchKernelGGL((k_team_upper<T, FAM, MODE>), gt, bt, (uint32_t)lds, c.stream, nullptr, ev1, 0, A,
@@ -1757,85 +1801,101 @@ void launch_team(const ApplyArrays<T>& A, const LaunchCfg& c, const TeamIO<T>& i
 }
 
 template <typename T>
-TeamIO<T> team_io() {
+TeamIO<T> team_io(const TeamWs& W) {
   TeamIO<T> io;
   io.b = nullptr;
   io.u = io.y = io.xb = nullptr;
   io.xw = io.dtop = io.out = nullptr;
   io.z = nullptr;
   io.add_y = 0;
+  io.ldb = io.ldu = io.ldy = io.ldz = io.ldo = 0;
+  io.ldxb = W.ldxb;
+  io.ldxw = W.ldxb;
+  io.lddt = W.lddb;
   return io;
 }
 
 template <typename T>
-hipError_t launch_series_team(const ApplyArrays<T>& A, const LaunchCfg& c, const T* y,
-                              const T* uprev, T* unext, int add_y, const TeamWs& W) {
-  if (A.TB.team < 2 || c.R != 1 || (A.TC.team < 2 && c.gx)) return hipErrorInvalidValue;
-  TeamIO<T> io = team_io<T>();
+hipError_t launch_series_team(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, const T* y,
+                              const T* uprev, T* unext, int64_t ldv, int add_y, const TeamWs& W) {
+  if (A.TB.team < 2 || nrhs < 1 || (A.TC.team < 2 && c.gx)) return hipErrorInvalidValue;
+  TeamIO<T> io = team_io<T>(W);
   io.u = uprev;
+  io.ldu = ldv;
   io.xw = (T*)W.xb;
   io.dtop = (T*)W.dtopb;
-  launch_team<T, 0, 0>(A, c, io, c.ev_start, nullptr);
+  launch_team<T, 0, 0>(A, c, nrhs, io, c.ev_start, nullptr);
   if (A.TC.team > 1) {
-    TeamIO<T> ic = team_io<T>();
+    TeamIO<T> ic = team_io<T>(W);
     ic.u = uprev;
     ic.y = y;
+    ic.ldu = ic.ldy = ic.ldo = ldv;
     ic.xb = (const T*)W.xb;
     ic.xw = (T*)W.xc;
+    ic.ldxw = W.ldxc;
     ic.dtop = (T*)W.dtopc;
+    ic.lddt = W.lddc;
     ic.out = unext;
     ic.add_y = add_y;
-    launch_team<T, 1, 0>(A, c, ic, nullptr, c.ev_stop);
+    launch_team<T, 1, 0>(A, c, nrhs, ic, nullptr, c.ev_stop);
   } else {
-    const dim3 g1((unsigned)A.nparts), bt(c.threads);
+    const dim3 g1((unsigned)A.nparts, (unsigned)nrhs), bt(c.threads);
     if (c.ev_stop)
       hipExtLaunchKernelGGL((k_team_c0<T>), g1, bt, (uint32_t)c.lds, c.stream, nullptr, c.ev_stop, 0, A, y,
-                            uprev, unext, (const T*)W.xb, add_y);
+                            uprev, unext, (const T*)W.xb, add_y, ldv, W.ldxb);
     else
-      hipLaunchKernelGGL((k_team_c0<T>), g1, bt, c.lds, c.stream, A, y, uprev, unext, (const T*)W.xb, add_y);
+      hipLaunchKernelGGL((k_team_c0<T>), g1, bt, c.lds, c.stream, A, y, uprev, unext, (const T*)W.xb, add_y,
+                         ldv, W.ldxb);
   }
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_head_team(const ApplyArrays<T>& A, const LaunchCfg& c, const double* b, T* y,
-                            const TeamWs& W) {
-  if (A.TB.team < 2 || c.R != 1) return hipErrorInvalidValue;
-  TeamIO<T> io = team_io<T>();
+hipError_t launch_head_team(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, const double* b,
+                            int64_t ldb, T* y, int64_t ldy, const TeamWs& W) {
+  if (A.TB.team < 2 || nrhs < 1) return hipErrorInvalidValue;
+  TeamIO<T> io = team_io<T>(W);
   io.b = b;
+  io.ldb = ldb;
   io.xw = (T*)W.xb;
   io.dtop = (T*)W.dtopb;
-  launch_team<T, 0, 1>(A, c, io, nullptr, nullptr);
+  launch_team<T, 0, 1>(A, c, nrhs, io, nullptr, nullptr);
   if (A.q > 0)
-    hipLaunchKernelGGL((k_team_headF<T>), dim3(nblk(A.q, 256)), dim3(256), 0, c.stream, A, b,
-                       (const T*)W.xb, y);
+    hipLaunchKernelGGL((k_team_headF<T>), dim3(nblk(A.q, 256), (unsigned)nrhs), dim3(256), 0, c.stream, A, b,
+                       (const T*)W.xb, y, ldb, W.ldxb, ldy);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_tail_team(const ApplyArrays<T>& A, const LaunchCfg& c, const double* b,
-                            const T* u, double* z, const TeamWs& W) {
-  if (A.TB.team < 2 || c.R != 1) return hipErrorInvalidValue;
-  TeamIO<T> io = team_io<T>();
+hipError_t launch_tail_team(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, const double* b,
+                            int64_t ldb, const T* u, int64_t ldu, double* z, int64_t ldz, const TeamWs& W) {
+  if (A.TB.team < 2 || nrhs < 1) return hipErrorInvalidValue;
+  TeamIO<T> io = team_io<T>(W);
   io.b = b;
+  io.ldb = ldb;
   io.u = u;
+  io.ldu = ldu;
   io.z = z;
+  io.ldz = ldz;
   io.xw = (T*)W.xb;
   io.dtop = (T*)W.dtopb;
-  launch_team<T, 0, 2>(A, c, io, nullptr, nullptr);
+  launch_team<T, 0, 2>(A, c, nrhs, io, nullptr, nullptr);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_c0_team(const ApplyArrays<T>& A, const LaunchCfg& c, const T* src, T* dst,
-                          const TeamWs& W) {
-  if (A.TC.team < 2 || c.R != 1) return hipErrorInvalidValue;
-  TeamIO<T> io = team_io<T>();
+hipError_t launch_c0_team(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, const T* src, T* dst,
+                          int64_t ldv, const TeamWs& W) {
+  if (A.TC.team < 2 || nrhs < 1) return hipErrorInvalidValue;
+  TeamIO<T> io = team_io<T>(W);
   io.y = src;
+  io.ldy = io.ldo = ldv;
   io.xw = (T*)W.xc;
+  io.ldxw = W.ldxc;
   io.dtop = (T*)W.dtopc;
+  io.lddt = W.lddc;
   io.out = dst;
-  launch_team<T, 1, 1>(A, c, io, nullptr, nullptr);
+  launch_team<T, 1, 1>(A, c, nrhs, io, nullptr, nullptr);
   return hipGetLastError();
 }
 
@@ -1849,14 +1909,15 @@ hipError_t launch_c0_team(const ApplyArrays<T>& A, const LaunchCfg& c, const T* 
                                        int64_t, const T*, T*, int64_t, int, int);                \
   template hipError_t launch_tail<T>(const ApplyArrays<T>&, const LaunchCfg&, int, const double*, \
                                      int64_t, const T*, int64_t, double*, int64_t);              \
-  template hipError_t launch_series_team<T>(const ApplyArrays<T>&, const LaunchCfg&, const T*,    \
-                                            const T*, T*, int, const TeamWs&);                   \
-  template hipError_t launch_head_team<T>(const ApplyArrays<T>&, const LaunchCfg&, const double*, \
-                                          T*, const TeamWs&);                                    \
-  template hipError_t launch_tail_team<T>(const ApplyArrays<T>&, const LaunchCfg&, const double*, \
-                                          const T*, double*, const TeamWs&);                     \
-  template hipError_t launch_c0_team<T>(const ApplyArrays<T>&, const LaunchCfg&, const T*, T*,    \
-                                        const TeamWs&);
+  template hipError_t launch_series_team<T>(const ApplyArrays<T>&, const LaunchCfg&, int, const T*, \
+                                            const T*, T*, int64_t, int, const TeamWs&);           \
+  template hipError_t launch_head_team<T>(const ApplyArrays<T>&, const LaunchCfg&, int,            \
+                                          const double*, int64_t, T*, int64_t, const TeamWs&);     \
+  template hipError_t launch_tail_team<T>(const ApplyArrays<T>&, const LaunchCfg&, int,            \
+                                          const double*, int64_t, const T*, int64_t, double*,      \
+                                          int64_t, const TeamWs&);                                 \
+  template hipError_t launch_c0_team<T>(const ApplyArrays<T>&, const LaunchCfg&, int, const T*, T*, \
+                                        int64_t, const TeamWs&);
 
 PSLR_INST(double)
 PSLR_INST(float)

@@ -36,7 +36,7 @@ class pslr_options(C.Structure):
                 ("seed", C.c_uint64), ("pivot_threshold", C.c_double), ("nthreads", C.c_int32),
                 ("working_vectors", C.c_int32), ("autotune", C.c_int32), ("threads", C.c_int32),
                 ("factor", C.c_int32), ("drop_tol", C.c_double), ("lowrank", C.c_int32),
-                ("team", C.c_int32), ("team_top", C.c_int32)]
+                ("team", C.c_int32), ("team_top", C.c_int32), ("team_rhs", C.c_int32)]
 
 
 class pslr_host_stats_t(C.Structure):
@@ -206,11 +206,12 @@ LOWRANK = {"arnoldi": 0, "krylov_schur": 1, "deflate_unit": 2}
 
 def _options(m, rank, precision, want_transpose, v0, seed, pivot_threshold, nthreads,
              working_vectors, autotune=False, threads=0, factor="lu", drop_tol=1e-2,
-             lowrank="arnoldi", team=0, team_top=0):
+             lowrank="arnoldi", team=0, team_top=0, team_rhs=0):
     o = pslr_default_options()
     o.lowrank = LOWRANK[lowrank]
     o.team = int(team)
     o.team_top = int(team_top)
+    o.team_rhs = int(team_rhs)
     o.threads = int(threads)
     o.factor = FACTORS[factor]
     o.drop_tol = float(drop_tol)
@@ -228,7 +229,7 @@ def _options(m, rank, precision, want_transpose, v0, seed, pivot_threshold, nthr
 def pslr_setup(rowptr, colind, vals, part, nparts, m=3, rank=16, precision=0,
                want_transpose=False, v0=None, seed=1, pivot_threshold=0.1, nthreads=0,
                working_vectors=0, autotune=False, threads=0, factor="lu", drop_tol=1e-2,
-               lowrank="arnoldi", team=0, team_top=0, stream=None) -> Handle:
+               lowrank="arnoldi", team=0, team_top=0, team_rhs=0, stream=None) -> Handle:
     L = lib()
     rp, rpp = _arr(rowptr, np.int64)
     ci, cip = _arr(colind, np.int32)
@@ -236,7 +237,7 @@ def pslr_setup(rowptr, colind, vals, part, nparts, m=3, rank=16, precision=0,
     pa, pap = _arr(part, np.int32)
     o, keep = _options(m, rank, precision, want_transpose, v0, seed, pivot_threshold, nthreads,
                        working_vectors, autotune, threads, factor, drop_tol, lowrank, team,
-                       team_top)
+                       team_top, team_rhs)
     out = C.c_void_p()
     n = len(rp) - 1
     st = L.pslr_setup(n, rpp, cip, vap, pap, int(nparts), C.byref(o), _stream_ptr(stream),
@@ -249,7 +250,7 @@ def pslr_setup(rowptr, colind, vals, part, nparts, m=3, rank=16, precision=0,
 def pslr_setup_batched(rowptr, colind, vals, part, nparts, sys_ptr, m=3, rank=16, precision=0,
                        want_transpose=False, v0=None, seed=1, pivot_threshold=0.1, nthreads=0,
                        working_vectors=0, autotune=False, threads=0, factor="lu", drop_tol=1e-2,
-                       lowrank="arnoldi", team=0, team_top=0, stream=None) -> Handle:
+                       lowrank="arnoldi", team=0, team_top=0, team_rhs=0, stream=None) -> Handle:
     L = lib()
     rp, rpp = _arr(rowptr, np.int64)
     ci, cip = _arr(colind, np.int32)
@@ -258,7 +259,7 @@ def pslr_setup_batched(rowptr, colind, vals, part, nparts, sys_ptr, m=3, rank=16
     sp, spp = _arr(sys_ptr, np.int64)
     o, keep = _options(m, rank, precision, want_transpose, v0, seed, pivot_threshold, nthreads,
                        working_vectors, autotune, threads, factor, drop_tol, lowrank, team,
-                       team_top)
+                       team_top, team_rhs)
     out = C.c_void_p()
     n = len(rp) - 1
     st = L.pslr_setup_batched(n, rpp, cip, vap, pap, int(nparts), len(sp) - 1, spp, C.byref(o),

@@ -165,3 +165,85 @@ def test_team_blocks_larger_than_lds(team):
               "team vs plain %.2e, vs oracle %.2e" % (e_pl, e_or), flush=True)
         assert e_pl <= tol
         assert e_or <= tol
+
+
+@pytest.mark.parametrize("name,A,lab,m,rank", CASES[:2], ids=IDS[:2])
+def test_team_multi_rhs(name, A, lab, m, rank):
+    """Applies of several right-hand sides take the team split when
+    team_rhs allows (one right-hand side per workgroup, columns on the
+    second grid axis): they match the unsplit tiles and the oracle, column by
+    column, in FP64 and FP32."""
+    dev = _dev()
+    nparts = int(lab.max()) + 1
+    As = A.to_scipy()
+    blk = opslr.make_blocks(As, lab)
+    pre = opslr.PSLR(As, lab, m, rank, v0=wl.start_vector(blk.q, 5))
+    nr = 3
+    b = wl.normal_rhs(A.n, nr, 24)
+    bt = torch.tensor(np.ascontiguousarray(b.T), dtype=torch.float64, device=dev)
+    ref = pre.apply(b)
+    for prec, tol in ((0, 1e-12), (1, 1e-5)):
+        zs = {}
+        for t, trhs in ((1, 0), (4, 4)):
+            h = P.pslr_setup(A.rowptr, A.colind, A.vals, lab, nparts, m=m, rank=0, precision=prec,
+                             team=t, team_rhs=trhs)
+            P.pslr_set_lowrank(h, pre.V, pre.H)
+            z = torch.zeros_like(bt)
+            P.pslr_apply(h, bt, z)
+            torch.cuda.synchronize()
+            zs[t] = z.cpu().numpy().T
+        for r in range(nr):
+            e_pl, e_or = _rel(zs[4][:, r], zs[1][:, r]), _rel(zs[4][:, r], ref[:, r])
+            print(name, "precision", prec, "column", r, "team vs tiles %.2e, vs oracle %.2e"
+                  % (e_pl, e_or), flush=True)
+            assert e_pl <= (1e-13 if prec == 0 else 1e-5)
+            assert e_or <= tol
+
+
+def test_team_batched_fgmres_masks():
+    """A batched handle (uneven systems, one Krylov space per system and
+    right-hand side) with the team split on its multi-right-hand-side
+    applies: the apply equals the unsplit handle's, and masked FGMRES (the
+    converged (system, column) pairs skip their workgroups) reaches the
+    tolerance with the same iteration counts."""
+    dev = _dev()
+    systems = []
+    A = wl.laplacian2d(40, wl.sigma20_2d(40))
+    systems.append((A, opart.region_growing_labels(A.to_scipy(), 6, 32)))
+    A = wl.laplacian3d(10, 0.3)
+    systems.append((A, opart.geometric_labels((10, 10, 10), (2, 2, 1))))
+    A = wl.laplacian2d(23, 0.2, Ny=17)
+    systems.append((A, opart.region_growing_labels(A.to_scipy(), 3, 31)))
+    mats, labels, sys_ptr, off = [], [], [0], 0
+    for A, lab in systems:
+        mats.append(A.to_scipy())
+        labels.append(lab + off)
+        off += int(lab.max()) + 1
+        sys_ptr.append(sys_ptr[-1] + A.n)
+    import scipy.sparse as sp
+    U = sp.block_diag(mats, format="csr")
+    U.sort_indices()
+    rp, ci, va = U.indptr.astype(np.int64), U.indices.astype(np.int32), U.data.astype(np.float64)
+    lab = np.concatenate(labels).astype(np.int32)
+    sys_ptr = np.array(sys_ptr, dtype=np.int64)
+    nr = 2
+    b = wl.normal_rhs(U.shape[0], nr, 25)
+    bt = torch.tensor(np.ascontiguousarray(b.T), dtype=torch.float64, device=dev)
+    out = {}
+    for t, trhs in ((1, 0), (4, 2)):
+        # no low-rank term: the two handles' Arnoldi bases would differ by rounding
+        h = P.pslr_setup_batched(rp, ci, va, lab, off, sys_ptr, m=3, rank=0, team=t, team_rhs=trhs)
+        assert P.pslr_info(h)["team"] == (4 if t > 1 else 0)
+        z = torch.zeros_like(bt)
+        P.pslr_apply(h, bt, z)
+        x = torch.zeros_like(bt)
+        st, its, rel = P.fgmres_solve(h, bt, x, restart=30, maxit=300, tol=1e-10)
+        torch.cuda.synchronize()
+        out[t] = (z.cpu().numpy().T, np.array(its), np.array(rel), x.cpu().numpy().T)
+    e = max(_rel(out[4][0][:, r], out[1][0][:, r]) for r in range(nr))
+    print("batched team apply vs unsplit %.2e; its" % e, list(out[1][1]), list(out[4][1]), flush=True)
+    assert e <= 1e-12
+    assert np.all(out[4][2] <= 1e-10)
+    assert np.all(np.abs(out[4][1] - out[1][1]) <= 1)
+    res = b - U @ out[4][3]
+    assert np.linalg.norm(res) <= 1.01e-10 * np.linalg.norm(b)
