@@ -119,11 +119,15 @@ typedef struct {
                                    to 256), so that all eigenvalues of E_rr(m) outside the unit
                                    circle are deflated (Sec. 3.2.2); pslr_info.rank gives the
                                    count reached, which may exceed r_k */
-  int32_t team;             /* B_i and C_i solves of forward applies spread over
-                               `team` workgroups per subdomain (the supernodal tree of each
-                               block cut into `team` groups of whole subtrees and the top group
-                               above them; exact LU only): 0 = automatic (4 when nparts <= 128,
-                               else 1), 1 = off, 2..8 = that many */
+  int32_t team;             /* B_i and C_i solves of forward applies spread over a team of
+                               workgroups per subdomain (the supernodal tree of each block cut
+                               into groups of whole subtrees and the top group above them;
+                               exact LU only).  Block i of a family gets t_i groups: `team`
+                               times its share of the family's largest block, at least one group
+                               per 2048 rows (so that each group fits one workgroup's LDS), at
+                               least 1 and at most 32; all groups of all blocks form one work
+                               list per launch.  0 = automatic (4 when nparts <= 128, else 2 when
+                               a part has more than 2048 rows, else 1), 1 = off, 2..8 */
   int32_t team_top;         /* how the team split solves its top group: 0 = automatic (2 when
                                every block's top group has at most 1024 rows and the dense
                                inverses hold at most twice the values of the family's packed
@@ -135,7 +139,9 @@ typedef struct {
   int32_t team_rhs;         /* forward applies of up to team_rhs right-hand sides take the team
                                split, one right-hand side per workgroup (wider applies keep one
                                workgroup per block and tile of right-hand sides, which reads
-                               the factors once per tile): 0 = automatic (1), 1 .. 64 */
+                               the factors once per tile): 0 = automatic (1; up to 8 when the
+                               tiled path would keep its working vectors in global memory, i.e.
+                               blocks too large for one workgroup's LDS), 1 .. 64 */
 } pslr_options;
 
 typedef struct {
@@ -170,10 +176,10 @@ typedef struct {
                                low-rank products V^T Y and V (G V^T Y) on the matrix cores (BF16
                                V, FP32 accumulation, Y split in three BF16 parts); 0 = never
                                (only FP32 applies with V kept in BF16) */
-  int32_t team;             /* team size of the single-right-hand-side B_i solves (0: no split) */
+  int32_t team;             /* most groups of one B_i in the team split (0: no split) */
   int32_t team_top;         /* the B_i top groups' solve: 1 packed factors, 2 dense inverse (0: no
                                split) */
-  int32_t team_c;           /* team size of the single-right-hand-side C_i solves (0: no split) */
+  int32_t team_c;           /* most groups of one C_i in the team split (0: no split) */
   int32_t team_top_c;       /* the C_i top groups' solve, as team_top */
   int32_t team_apply;       /* solves of single-right-hand-side forward applies: 0 one workgroup
                                per block, 1 team split of the B_i, 2 of the B_i and the C_i.  A

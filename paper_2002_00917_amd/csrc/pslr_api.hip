@@ -265,7 +265,7 @@ struct pslr_ctx {
   int64_t gws_stride = 0;
   int tuned_threads = 0, tuned_gshift = 0;
   int rmax = 8;      // widest right-hand-side tile of a launch (autotuned)
-  int team_rhs = 1;  // applies of up to this many right-hand sides take the team solves
+  int team_rhs = 0;  // pslr_options.team_rhs (0: automatic, see run_apply)
   const int64_t* d_rb_off = nullptr;
   // apply workspaces (grow-only, see ensure_ws)
   int ws_nrhs = 0;
@@ -305,12 +305,50 @@ struct pslr_ctx {
 
 namespace {
 
+#ifndef PSLR_TEAM_ROWS
+#define PSLR_TEAM_ROWS 2048
+#endif
+constexpr int64_t kTeamRows = PSLR_TEAM_ROWS;
+constexpr int kTeamRhsAuto = 8;
+
 // Team size of the B_i solves: exact LU only; automatic = 4 workgroups per
-// subdomain when the subdomains alone would leave most of the 256 CUs idle.
-int resolve_team(const pslr_options& o, int32_t nparts) {
+// subdomain when the subdomains alone would leave most of the 256 CUs idle,
+// else 2 when a subdomain has more than kTeamRows rows (the split then
+// mainly cuts large blocks to what one workgroup's LDS holds).
+int resolve_team(const pslr_options& o, int64_t n, const int32_t* part, int32_t nparts) {
   if (o.factor != 0 || o.team == 1) return 0;
   if (o.team >= 2) return std::min(o.team, 8);
-  return nparts <= 128 ? 4 : 0;
+  if (nparts <= 128) return 4;
+  std::vector<int64_t> cnt(nparts, 0);
+  for (int64_t i = 0; i < n; ++i) cnt[part[i]]++;
+  return *std::max_element(cnt.begin(), cnt.end()) > kTeamRows ? 2 : 0;
+}
+
+// Groups of every block of a split family (B_i then C_i, 2 * nparts entries;
+// all 0 when team < 2): the team size scaled by the block's share of its
+// family's largest block, so that the groups of one launch hold about the
+// same number of rows whatever the spread of block sizes, and at least one
+// group per kTeamRows rows, so that a group's rows and level scratch fit one
+// workgroup's LDS; between 1 and kTeamMax.  2048 rows was the fastest of
+// 1024, 2048 and 4096 on 48 uneven 2D systems (blocks of up to 53k rows):
+// smaller groups need less LDS, so more workgroups share a CU, until the
+// top groups' extra work outweighs that.
+constexpr int kTeamMax = 32;
+std::vector<int> block_teams(const Blocks& Bk, int team) {
+  const int np = (int)Bk.B.size();
+  std::vector<int> t(2 * (size_t)np, 0);
+  if (team < 2) return t;
+  for (int fam = 0; fam < 2; ++fam) {
+    const std::vector<CsrL>& M = fam == 0 ? Bk.B : Bk.C0;
+    int64_t nmax = 1;
+    for (int i = 0; i < np; ++i) nmax = std::max<int64_t>(nmax, M[i].nrows);
+    for (int i = 0; i < np; ++i) {
+      const int64_t n = M[i].nrows;
+      const int64_t share = std::lround(team * (double)n / nmax), fit = (n + kTeamRows - 1) / kTeamRows;
+      t[(size_t)fam * np + i] = (int)std::clamp<int64_t>(std::max(share, fit), 1, kTeamMax);
+    }
+  }
+  return t;
 }
 
 pslr_status validate_csr(int64_t n, const int64_t* rowptr, const int32_t* colind) {
@@ -429,41 +467,51 @@ DirHost build_dir(const Reordering& R, const Blocks& Bk, const std::vector<Block
   return D;
 }
 
-// Team split of one family of blocks (every block split into the same
-// number of groups; F[0].team <= 1: none).  team_top as pslr_options.team_top.
+// Team split of one family of blocks (block i in F[i].team subtree groups and
+// a top group; no split when no block is divided).  team_top as
+// pslr_options.team_top.
 // bytes: set to what the team solves read (the groups' packed factors, the
 // top groups' packed factors or dense inverses and their row records).
 template <typename T>
 hipError_t upload_team(DevPool& pool, const std::vector<BlockFactor>& F, int team_top, TeamArrays<T>& out,
                        int& mlr, int64_t& bytes) {
   out = TeamArrays<T>{};
-  if (F.empty() || F[0].team <= 1) return hipSuccess;
-  const int team = F[0].team;
+  int team = 0;
+  for (const BlockFactor& f : F) team = std::max<int>(team, f.team);
+  if (team <= 1) return hipSuccess;  // no block divided: no split
   const int w = (int)sizeof(T);
   const int path = w == 8 ? 0 : 1;
   auto rd = [&](const TriPacked& P) { return P.read_vals[path] * (int64_t)w + 4 * P.read_ints[path]; };
   std::vector<const TriPacked*> ls, us;
+  std::vector<int32_t> gptr(1, 0);
+  std::vector<int4> item;
   int64_t groups = 0, top_packed = 0, all_vals = 0, dense_vals = 0;
   bool dense_ok = true;
-  for (const BlockFactor& f : F) {
-    if (f.team != team || (int)f.loS.size() != team + 1 || (int)f.upS.size() != team + 1)
-      return hipErrorInvalidValue;
-    for (int g = 0; g <= team; ++g) {
+  for (size_t i = 0; i < F.size(); ++i) {
+    const BlockFactor& f = F[i];
+    const int t = f.team;
+    if (t < 1 || (int)f.loS.size() != t + 1 || (int)f.upS.size() != t + 1) return hipErrorInvalidValue;
+    for (int g = 0; g <= t; ++g) {
       ls.push_back(&f.loS[g]);
       us.push_back(&f.upS[g]);
-      (g < team ? groups : top_packed) += rd(f.loS[g]) + rd(f.upS[g]);
+      (g < t ? groups : top_packed) += rd(f.loS[g]) + rd(f.upS[g]);
+      all_vals += f.loS[g].read_vals[path] + f.upS[g].read_vals[path];
     }
-    for (int g = 0; g <= team; ++g) all_vals += f.loS[g].read_vals[path] + f.upS[g].read_vals[path];
+    for (int g = 0; g < t; ++g) item.push_back(make_int4((int)i, gptr.back() + g, g, 0));
+    gptr.push_back(gptr.back() + t + 1);
     dense_vals += (int64_t)f.ntop * f.ntop;
     if (f.ntop > 0 && f.topinv.empty()) dense_ok = false;
-    out.ntopmax = std::max(out.ntopmax, f.loS[team].n);
+    out.ntopmax = std::max(out.ntopmax, f.loS[t].n);
   }
   hipError_t e;
   int64_t tb;
   int tmlr = 0;
   if ((e = upload_tri_list(pool, ls, out.L, tmlr, tb))) return e;
   if ((e = upload_tri_list(pool, us, out.U, tmlr, tb))) return e;
+  if ((e = pool.upload(gptr, &out.gptr))) return e;
+  if ((e = pool.upload(item, &out.item))) return e;
   out.team = team;
+  out.nitems = (int32_t)item.size();
   out.maxlr = std::max(tmlr, 1);
   {
     std::vector<int32_t> pos;
@@ -566,14 +614,13 @@ WsSizes ws_sizes(const pslr_ctx* h, int nrhs) {
   z.partial = (size_t)h->nchunk_lr * nrhs * std::max(h->k, 1) + (size_t)h->nsys * std::max(h->k, 1);
   z.gws = h->gws_stride > 0 ? (size_t)h->gws_stride * ((nrhs + 7) / 8 * 8) : 0;
   // the family vectors and top-row updates of the team solves, each with one
-  // slice per right-hand side: [xb: p][dtopb: nparts x team x ntopmax of B]
+  // slice per right-hand side: [xb: p][dtopb: nitems x ntopmax of B]
   // [xc: q][dtopc: the same of C]
   if (h->fw64.TB.team > 1) {
     const TeamArrays<double>&TB = h->fw64.TB, &TC = h->fw64.TC;
-    z.team = (size_t)std::max<int64_t>(h->R.p, 1) + (size_t)h->R.nparts * TB.team * TB.ntopmax;
-    if (TC.team > 1)
-      z.team += (size_t)std::max<int64_t>(h->R.q, 1) + (size_t)h->R.nparts * TC.team * TC.ntopmax;
-    z.team *= (size_t)std::min(nrhs, h->team_rhs);
+    z.team = (size_t)std::max<int64_t>(h->R.p, 1) + (size_t)TB.nitems * TB.ntopmax;
+    if (TC.team > 1) z.team += (size_t)std::max<int64_t>(h->R.q, 1) + (size_t)TC.nitems * TC.ntopmax;
+    z.team *= (size_t)std::min(nrhs, h->team_rhs > 0 ? h->team_rhs : kTeamRhsAuto);
   }
   // split G V^T y of the matrix-core low-rank products (BF16 V only)
   if (h->Vbr && nrhs >= kMfmaMinRhs)
@@ -850,23 +897,26 @@ pslr_status run_apply(pslr_ctx* h, const ApplyArrays<T>& Ah, const ApplyWs& W, b
     ~Restore() { h->trace = v; }
   } restore{h, tr_on};
   Tracer tr{h, s, {}};
-  // the team solves (workspace layout as in ws_sizes), for up to
-  // team_rhs right-hand sides
+  // the team solves (workspace layout as in ws_sizes) for up to team_rhs
+  // right-hand sides; automatic: one, or up to kTeamRhsAuto when the tiled
+  // path would keep its working vectors in global memory (each right-hand
+  // side then costs a read of the factors, but in LDS)
   bool team = false, cteam = false;
-  if (W.team && nrhs <= h->team_rhs && !transpose) team_path<T>(h, A, cfg, team, cteam);
+  const int trhs = h->team_rhs > 0 ? h->team_rhs : (cfg.gx ? kTeamRhsAuto : 1);
+  if (W.team && nrhs <= trhs && !transpose) team_path<T>(h, A, cfg, team, cteam);
   if (team && !cteam) A.TC.team = 0;
   TeamWs tw{};
   if (team) {
     T* t = (T*)W.team;
     tw.ldxb = std::max<int64_t>(h->R.p, 1);
-    tw.lddb = (int64_t)A.nparts * A.TB.team * A.TB.ntopmax;
+    tw.lddb = (int64_t)A.TB.nitems * A.TB.ntopmax;
     tw.xb = t;
     t += tw.ldxb * nrhs;
     tw.dtopb = t;
     t += tw.lddb * nrhs;
     if (cteam) {
       tw.ldxc = std::max<int64_t>(h->R.q, 1);
-      tw.lddc = (int64_t)A.nparts * A.TC.team * A.TC.ntopmax;
+      tw.lddc = (int64_t)A.TC.nitems * A.TC.ntopmax;
       tw.xc = t;
       t += tw.ldxc * nrhs;
       tw.dtopc = t;
@@ -1844,7 +1894,7 @@ pslr_status pslr_host_stats(int64_t n, const int64_t* rowptr, const int32_t* col
   if (o.factor != 0 && o.factor != 1) return fail(PSLR_EINVAL, "factor must be 0 or 1");
   if (o.lowrank < 0 || o.lowrank > 2) return fail(PSLR_EINVAL, "lowrank must be 0, 1 or 2");
   if (o.team < 0 || o.team > 8) return fail(PSLR_EINVAL, "team must be 0 .. 8");
-  const int team = resolve_team(o, nparts);
+  const int team = resolve_team(o, n, part, nparts);
   const double tau = o.pivot_threshold > 0 ? o.pivot_threshold : 0.1;
   const double drop = o.drop_tol > 0 ? o.drop_tol : 1e-2;
   Reordering R = reorder(n, rowptr, colind, part, nparts);
@@ -1853,6 +1903,7 @@ pslr_status pslr_host_stats(int64_t n, const int64_t* rowptr, const int32_t* col
   for (auto& b : Bk.B) mats.push_back(&b);
   for (auto& c : Bk.C0) mats.push_back(&c);
   const int nB = (int)Bk.B.size();
+  const std::vector<int> bteam = block_teams(Bk, o.factor == 0 ? team : 0);
   std::vector<double> fres(mats.size(), 0.0), sres(mats.size(), 0.0);
   std::vector<std::string> errs(mats.size());
   std::vector<int> codes(mats.size(), 0), lvl(mats.size(), 0), valid(mats.size(), 1),
@@ -1869,11 +1920,11 @@ pslr_status pslr_host_stats(int64_t n, const int64_t* rowptr, const int32_t* col
       codes[t] = ilut_block(M, drop, o.want_transpose != 0, narrow, f, errs[t]);
       if (!codes[t]) codes[t] = ilut_factor(M, drop, I, errs[t]);
     } else {
-      codes[t] = factor_block(M, tau, o.want_transpose != 0, narrow, f, errs[t], team,
+      codes[t] = factor_block(M, tau, o.want_transpose != 0, narrow, f, errs[t], bteam[t],
                               t < nB ? kTopRowsB : kTopRowsC);
     }
     if (codes[t] || M.nrows == 0) return;
-    if (f.team > 1) {
+    if (f.team >= 1) {
       // team split: structure, and the groups applied in turn (subtrees, then
       // the top group's lower and upper solves, then the subtrees' upper
       // solves) against the plain packed solve
@@ -2115,7 +2166,7 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
   if (o.team < 0 || o.team > 8) return fail(PSLR_EINVAL, "team must be 0 .. 8");
   if (o.team_top < 0 || o.team_top > 2) return fail(PSLR_EINVAL, "team_top must be 0, 1 or 2");
   if (o.team_rhs < 0 || o.team_rhs > 64) return fail(PSLR_EINVAL, "team_rhs must be 0 .. 64");
-  o.team = resolve_team(o, nparts);
+  o.team = resolve_team(o, n, part, nparts);
   const double tau = o.pivot_threshold > 0 ? o.pivot_threshold : 0.1;
   for (int64_t k = 0; k < (n > 0 ? rowptr[n] : 0); ++k)
     if (!std::isfinite(vals[k])) return fail(PSLR_EINVAL, "non-finite value in A");
@@ -2171,13 +2222,14 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
   std::vector<std::string> errs(2 * np);
   std::vector<int> codes(2 * np, 0);
   const double drop = o.drop_tol > 0 ? o.drop_tol : 1e-2;
+  const std::vector<int> bteam = block_teams(Bk, o.factor == 0 ? o.team : 0);
   parallel_for(2 * np, o.nthreads, [&](int t) {
     const CsrL& M = t < np ? Bk.B[t] : Bk.C0[t - np];
     BlockFactor& F = t < np ? fB[t] : fC[t - np];
     const int narrow = t < np ? kNarrowWidthB : kNarrowWidthC;
     codes[t] = o.factor == 1 ? ilut_block(M, drop, h->want_T != 0, narrow, F, errs[t])
                              : factor_block(M, tau, h->want_T != 0, narrow, F, errs[t],
-                                            o.team, t < np ? kTopRowsB : kTopRowsC);
+                                            bteam[t], t < np ? kTopRowsB : kTopRowsC);
   });
   for (int t = 0; t < 2 * np; ++t)
     if (codes[t]) return fail(codes[t] == 3 ? PSLR_ENOTSUP : PSLR_ESINGULAR,
@@ -2225,7 +2277,7 @@ pslr_status setup_impl(int64_t n, const int64_t* rowptr, const int32_t* colind, 
   h->hA_ptr.assign(rowptr, rowptr + n + 1);
   h->hA_col.assign(colind, colind + h->nnzA);
   h->opt = o;
-  h->team_rhs = o.team_rhs > 0 ? o.team_rhs : 1;
+  h->team_rhs = o.team_rhs;
   if (o.v0) h->hv0.assign(o.v0, o.v0 + h->R.q);
   h->opt.v0 = nullptr;
   // per-system tables: subdomain -> system, V^T y row chunks, interface segments
@@ -2366,13 +2418,14 @@ pslr_status pslr_refactor(pslr_handle h, const double* vals, void* hip_stream) {
   std::vector<int> codes(2 * np, 0);
   const double tau = o.pivot_threshold > 0 ? o.pivot_threshold : 0.1;
   const double drop = o.drop_tol > 0 ? o.drop_tol : 1e-2;
+  const std::vector<int> bteam = block_teams(Bk, o.factor == 0 ? o.team : 0);
   parallel_for(2 * np, o.nthreads, [&](int t) {
     const CsrL& M = t < np ? Bk.B[t] : Bk.C0[t - np];
     BlockFactor& F = t < np ? fB[t] : fC[t - np];
     const int narrow = t < np ? kNarrowWidthB : kNarrowWidthC;
     codes[t] = o.factor == 1 ? ilut_block(M, drop, h->want_T != 0, narrow, F, errs[t])
                              : factor_block(M, tau, h->want_T != 0, narrow, F, errs[t],
-                                            o.team, t < np ? kTopRowsB : kTopRowsC);
+                                            bteam[t], t < np ? kTopRowsB : kTopRowsC);
   });
   for (int t = 0; t < 2 * np; ++t)
     if (codes[t]) return fail(codes[t] == 3 ? PSLR_ENOTSUP : PSLR_ESINGULAR,

@@ -50,23 +50,29 @@ struct DevCsr {
 };
 
 // Team split of one family of diagonal blocks (B_i or C_i): the supernodal
-// tree of every block cut into `team` groups of whole subtrees and a top
-// group (see BlockFactor::loS/upS).  L / U hold group g of block i at index
-// i * (team + 1) + g, the top group at g = team; ntopmax: the most top rows
-// of any block.  TI: the dense inverses of the top groups (null: the top
-// group runs its packed factors), block i's at TI + ti_off[i] in the
-// column-pair layout of BlockFactor::topinv, nrb workgroups of 64 top rows
-// per block.  team = 0: no split.
+// tree of block i cut into t_i groups of whole subtrees and a top group (see
+// BlockFactor::loS/upS), t_i sized to the block.  L / U hold group g of block
+// i at index gptr[i] + g, the top group at gptr[i + 1] - 1 (so t_i =
+// gptr[i + 1] - gptr[i] - 1).  The subtree groups of all blocks form one work
+// list of nitems items: item[w] = {i, gptr[i] + g, g, 0} for group g of block
+// i (one load gives a workgroup its block and group).
+// dtop holds ntopmax values (the most top rows of any block) per item.  TI:
+// the dense inverses of the top groups (null: the top group runs its packed
+// factors), block i's at TI + ti_off[i] in the column-pair layout of
+// BlockFactor::topinv, nrb workgroups of 64 top rows per block.  team: the
+// largest t_i (0: no split).
 template <typename T>
 struct TeamArrays {
   TriArrays<T> L, U;
-  int32_t team, ntopmax, nrb;
+  int32_t team, ntopmax, nrb, nitems;
+  const int32_t* gptr;
+  const int4* item;
   const T* TI;
   const int64_t* ti_off;
   // the groups' local positions (TriPacked::pos): group g of block i at
-  // pos[pos_off[i * (team + 1) + g] ..), its own rows first, then (subtree
-  // groups) the top group's rows; maxloc, maxlr: the most local positions and
-  // level rows of any group (the team kernels' LDS)
+  // pos[pos_off[gptr[i] + g] ..), its own rows first, then (subtree groups)
+  // the top group's rows; maxloc, maxlr: the most local positions and level
+  // rows of any group (the team kernels' LDS)
   const int32_t* pos;
   const int64_t* pos_off;
   int32_t maxloc, maxlr;
@@ -211,9 +217,9 @@ hipError_t set_lds_limit(size_t bytes);
 // rows' pushed updates live in the workspace TeamWs, one slice per column.
 struct TeamWs {
   void* xb;     // per column p values: the B-solve vector
-  void* dtopb;  // per column nparts * TB.team * TB.ntopmax values
+  void* dtopb;  // per column TB.nitems * TB.ntopmax values
   void* xc;     // per column q values: the C0-solve vector
-  void* dtopc;  // per column nparts * TC.team * TC.ntopmax values
+  void* dtopc;  // per column TC.nitems * TC.ntopmax values
   int64_t ldxb, lddb, ldxc, lddc;  // the slices' lengths (column strides)
 };
 // Vectors of nrhs columns with the given leading dimensions (y, u, src, dst:

@@ -529,7 +529,7 @@ int factor_block(const CsrL& M, double tau, bool want_T, int narrow_width, Block
     }
     out.lo.lower = out.loT.lower = true;
     out.up.lower = out.upT.lower = false;
-    if (team > 1) {  // empty groups keep the team layout uniform over the blocks
+    if (team >= 1) {  // an empty group: every block of a split family has one
       out.team = team;
       out.loS.assign(team + 1, out.lo);
       out.upS.assign(team + 1, out.up);
@@ -913,9 +913,9 @@ int factor_block(const CsrL& M, double tau, bool want_T, int narrow_width, Block
   };
   // team split: the groups of the supernodes and one packed factor per group,
   // each with its own level schedule (heights counted inside the group)
-  out.team = team > 1 ? team : 0;
+  out.team = team >= 1 ? team : 0;
   std::vector<int> grp;
-  if (team > 1) {
+  if (team >= 1) {
     std::vector<double> work(ns);
     for (int s = 0; s < ns; ++s) {
       const double w = sfirst[s + 1] - sfirst[s];
@@ -982,7 +982,7 @@ int factor_block(const CsrL& M, double tau, bool want_T, int narrow_width, Block
       err = "supernode wider than 32767 rows, panel taller than 32767 rows or block factor beyond 2^31 entries";
       return 3;
     }
-    if (team > 1 && !pack_groups(T, out.loS)) {
+    if (team >= 1 && !pack_groups(T, out.loS)) {
       err = "team split: packed factor beyond 2^31 entries";
       return 3;
     }
@@ -997,12 +997,12 @@ int factor_block(const CsrL& M, double tau, bool want_T, int narrow_width, Block
       err = "supernode wider than 32767 rows, panel taller than 32767 rows or block factor beyond 2^31 entries";
       return 3;
     }
-    if (team > 1 && !pack_groups(T, out.upS)) {
+    if (team >= 1 && !pack_groups(T, out.upS)) {
       err = "team split: packed factor beyond 2^31 entries";
       return 3;
     }
   }
-  if (team > 1) {
+  if (team >= 1) {
     out.ntop = out.loS[team].nlev > 0 ? out.loS[team].lev_ptr[out.loS[team].nlev] : 0;
     if (out.ntop <= kTopInvMaxRows && !top_inverse(out.loS[team], out.upS[team], n, out.topinv)) {
       err = "team split: the top group reaches outside itself";
@@ -1606,7 +1606,7 @@ bool check_levels(const TriPacked& T, std::string& err) {
 // team); the top group's solves stay inside the top group.
 bool check_team(const BlockFactor& F, std::string& err) {
   const int team = F.team;
-  if (team < 2) return true;
+  if (team < 1) return true;
   if ((int)F.loS.size() != team + 1 || (int)F.upS.size() != team + 1) {
     err = "team packing missing";
     return false;

@@ -144,16 +144,18 @@ struct BlockFactor {
   int32_t n = 0;
   std::vector<int32_t> gin, gout;
   TriPacked lo, up, loT, upT;
-  // Team split (team > 1): the supernodal elimination tree cut into `team`
+  // Team split (team >= 1): the supernodal elimination tree cut into `team`
   // groups of whole subtrees (balanced by factor entries) and the top group
   // of the supernodes above them.  loS[g] / upS[g] hold the same supernodes
   // as lo / up restricted to group g (g = team: the top group), each with its
   // own level schedule over the block's positions: a subtree's solve needs
   // no row of another subtree, its lower solve pushes into top rows only, and
-  // the top group's upper solve reads top rows only.
+  // the top group's upper solve reads top rows only.  team = 1 (a block of a
+  // split family too small to divide): one group of every supernode and an
+  // empty top group.
   int32_t team = 0;
   std::vector<TriPacked> loS, upS;
-  // Dense inverse of the top group's block of L U (team > 1, top group of at
+  // Dense inverse of the top group's block of L U (team >= 1, top group of at
   // most kTopInvMaxRows rows; empty otherwise).  Positions of the top group in
   // the order of loS[team]'s row records, T; the top group holds every
   // ancestor of its supernodes, so L[G, T] = 0 and U[T, G] = 0 for the other

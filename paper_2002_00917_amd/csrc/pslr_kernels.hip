@@ -1372,8 +1372,11 @@ __device__ __forceinline__ void team_load_u(const ApplyArrays<T>& A, const TeamI
 template <typename T, int FAM, int MODE>
 __global__ void __launch_bounds__(1024) k_team_lower(ApplyArrays<T> A, TeamIO<T> io) {
   const TeamArrays<T>& TA = team_fam<T, FAM>(A);
-  const int team = TA.team;
-  const int i = blockIdx.x / team, g = blockIdx.x - i * team, tid = threadIdx.x, nt = blockDim.x;
+  // work item w: subtree group g of block i, group index gi in TA.L / TA.U
+  const int w = blockIdx.x;
+  const int4 it = TA.item[w];
+  const int i = it.x, gi = it.y, g = it.z;
+  const int tid = threadIdx.x, nt = blockDim.x;
   int r0, nr;
   if (!tile_rhs<T, 1>(A, gridDim.y, i, r0, nr)) return;
   team_col(io);
@@ -1381,8 +1384,7 @@ __global__ void __launch_bounds__(1024) k_team_lower(ApplyArrays<T> A, TeamIO<T>
   T* X = L.X;
   const int64_t base = team_base<T, FAM>(A, i);
   team_load_u<T, FAM, MODE>(A, io, i, L.U, g == 0);
-  const int bs = i * (team + 1);
-  const TeamGroup<T> G = team_group<T>(TA, bs + g);
+  const TeamGroup<T> G = team_group<T>(TA, gi);
   for (int k = tid; k < G.nown; k += nt) X[k] = team_rhs<T, FAM, MODE>(A, io, i, base, G.P[k], L.U);
   // the top rows start from their right-hand side in group 0 and from zero in
   // the others, so that the sum of the groups' top rows is the right-hand side
@@ -1390,10 +1392,10 @@ __global__ void __launch_bounds__(1024) k_team_lower(ApplyArrays<T> A, TeamIO<T>
   for (int k = G.nown + tid; k < G.nloc; k += nt)
     X[k] = g == 0 ? team_rhs<T, FAM, MODE>(A, io, i, base, G.P[k], L.U) : (T)0;
   __syncthreads();
-  tri_solve<T, 1, false>(TA.L, bs + g, X, L.Rb, A.gshift);
+  tri_solve<T, 1, false>(TA.L, gi, X, L.Rb, A.gshift);
   __syncthreads();
   for (int k = tid; k < G.nown; k += nt) io.xw[base + G.P[k]] = X[k];
-  T* d = io.dtop + ((int64_t)i * team + g) * TA.ntopmax;
+  T* d = io.dtop + (int64_t)w * TA.ntopmax;
   for (int k = G.nown + tid; k < G.nloc; k += nt) d[k - G.nown] = X[k];
 }
 
@@ -1401,7 +1403,6 @@ __global__ void __launch_bounds__(1024) k_team_lower(ApplyArrays<T> A, TeamIO<T>
 template <typename T, int FAM, int MODE>
 __global__ void __launch_bounds__(1024) k_team_top(ApplyArrays<T> A, TeamIO<T> io) {
   const TeamArrays<T>& TA = team_fam<T, FAM>(A);
-  const int team = TA.team;
   const int i = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
   int r0, nr;
   if (!tile_rhs<T, 1>(A, gridDim.y, i, r0, nr)) return;
@@ -1409,9 +1410,9 @@ __global__ void __launch_bounds__(1024) k_team_top(ApplyArrays<T> A, TeamIO<T> i
   TeamLds<T> L = team_lds<T>(TA);
   T* X = L.X;
   const int64_t base = team_base<T, FAM>(A, i);
-  const int bs = i * (team + 1);
+  const int bs = TA.gptr[i], team = TA.gptr[i + 1] - bs - 1;
   const TeamGroup<T> G = team_group<T>(TA, bs + team);
-  const T* d = io.dtop + (int64_t)i * team * TA.ntopmax;
+  const T* d = io.dtop + (int64_t)(bs - i) * TA.ntopmax;
   for (int k = tid; k < G.nloc; k += nt) {
     T acc = (T)0;  // the right-hand side came with group 0's top rows
     for (int t = 0; t < team; ++t) acc += d[(int64_t)t * TA.ntopmax + k];
@@ -1435,12 +1436,13 @@ template <typename T, int FAM, int MODE>
 __global__ void __launch_bounds__(1024) k_team_topinv(ApplyArrays<T> A, TeamIO<T> io) {
   using P2 = typename Pair<T>::type;
   const TeamArrays<T>& TA = team_fam<T, FAM>(A);
-  const int team = TA.team, nrb = TA.nrb;
+  const int nrb = TA.nrb;
   const int i = blockIdx.x / nrb, rb = blockIdx.x - i * nrb, tid = threadIdx.x, nt = blockDim.x;
   int r0, nr;
   if (!tile_rhs<T, 1>(A, gridDim.y, i, r0, nr)) return;
   team_col(io);
-  const TeamGroup<T> G = team_group<T>(TA, i * (team + 1) + team);
+  const int bs = TA.gptr[i], team = TA.gptr[i + 1] - bs - 1;
+  const TeamGroup<T> G = team_group<T>(TA, bs + team);
   const int ntop = G.nloc;
   if (rb * kTopRows >= ntop) return;  // uniform over the workgroup
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1461,7 +1463,7 @@ __global__ void __launch_bounds__(1024) k_team_topinv(ApplyArrays<T> A, TeamIO<T
       const int cs = wv + s * nw < npair ? wv + s * nw : wv;
       v0[s] = M[(int64_t)cs * ld + row];
     }
-  const T* d = io.dtop + (int64_t)i * team * TA.ntopmax;
+  const T* d = io.dtop + (int64_t)(bs - i) * TA.ntopmax;
   for (int k = tid; k < ntop; k += nt) {
     T acc = (T)0;  // the right-hand side came with group 0's top rows
     for (int t = 0; t < team; ++t) acc += d[(int64_t)t * TA.ntopmax + k];
@@ -1506,20 +1508,20 @@ __global__ void __launch_bounds__(1024) k_team_topinv(ApplyArrays<T> A, TeamIO<T
 template <typename T, int FAM, int MODE>
 __global__ void __launch_bounds__(1024) k_team_upper(ApplyArrays<T> A, TeamIO<T> io) {
   const TeamArrays<T>& TA = team_fam<T, FAM>(A);
-  const int team = TA.team;
-  const int i = blockIdx.x / team, g = blockIdx.x - i * team, tid = threadIdx.x, nt = blockDim.x;
+  const int4 it = TA.item[blockIdx.x];
+  const int i = it.x, gi = it.y;
+  const int tid = threadIdx.x, nt = blockDim.x;
   int r0, nr;
   if (!tile_rhs<T, 1>(A, gridDim.y, i, r0, nr)) return;
   team_col(io);
   TeamLds<T> L = team_lds<T>(TA);
   T* X = L.X;
   const int64_t base = team_base<T, FAM>(A, i);
-  const int bs = i * (team + 1);
-  const TeamGroup<T> G = team_group<T>(TA, bs + g);
+  const TeamGroup<T> G = team_group<T>(TA, gi);
   // own rows (the lower solve's results) and the top rows
   for (int k = tid; k < G.nloc; k += nt) X[k] = io.xw[base + G.P[k]];
   __syncthreads();
-  tri_solve<T, 1, false>(TA.U, bs + g, X, L.Rb, A.gshift);
+  tri_solve<T, 1, false>(TA.U, gi, X, L.Rb, A.gshift);
   __syncthreads();
   for (int k = tid; k < G.nown; k += nt) team_out<T, FAM, MODE>(A, io, base, G.P[k], X[k], false);
 }
@@ -1779,7 +1781,7 @@ void launch_team(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, const Te
                  hipEvent_t ev1) {
   const TeamArrays<T>& TA = FAM == 0 ? A.TB : A.TC;
   const unsigned ny = (unsigned)nrhs;
-  const dim3 gt((unsigned)(A.nparts * TA.team), ny), bt(c.threads);
+  const dim3 gt((unsigned)TA.nitems, ny), bt(c.threads);
   const size_t lds = team_lds_bytes(TA, A.maxQB);
   if (ev0)
     hipExtLaunchKernelGGL((k_team_lower<T, FAM, MODE>), gt, bt, (uint32_t)lds, c.stream, ev0, nullptr, 0, A,

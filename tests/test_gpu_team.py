@@ -124,10 +124,11 @@ def test_team_top_auto_and_limits():
 def test_team_blocks_larger_than_lds(team):
     """Subdomains of 45000 rows (too large for one workgroup's LDS in FP64 and
     in FP32, so the unsplit path keeps their working vectors in global memory)
-    take the team split when each group (its own rows and top rows, level
-    scratch, the interface values) fits one workgroup's LDS, by the host's
-    count of those slots: the single-right-hand-side applies match the
-    unsplit path and the oracle either way."""
+    take the team split, cut into groups of at most about 2048 rows so that
+    each group (its own rows and top rows, level scratch, the interface
+    values) fits one workgroup's LDS, as the host's count of those slots
+    confirms: the single-right-hand-side applies match the unsplit path and
+    the oracle."""
     dev = _dev()
     N = 300
     A = wl.laplacian2d(N, 0.05, Ny=N)
@@ -147,12 +148,15 @@ def test_team_blocks_larger_than_lds(team):
         w = 8 if prec == 0 else 4
         assert w * blk.p // 2 > lds  # each block alone overflows the LDS
         fits = w * (st["team_lds_slots_B"] + blk.q) <= lds
+        assert fits
         zs = {}
         for t in (1, team):
             h = P.pslr_setup(A.rowptr, A.colind, A.vals, lab, 2, m=2, rank=0, precision=prec, team=t)
             inf = P.pslr_info(h)
             if t > 1:
-                assert inf["team"] == team and (inf["team_apply"] >= 1) == fits, (st, inf["team_apply"])
+                # blocks are cut into at least one group per 2048 rows
+                assert inf["team"] >= max(team, -(-blk.p // 2 // 2048))
+                assert (inf["team_apply"] >= 1) == fits, (st, inf["team_apply"])
             else:
                 assert inf["team_apply"] == 0
             P.pslr_set_lowrank(h, pre.V, pre.H)

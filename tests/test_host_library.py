@@ -203,6 +203,14 @@ def test_team_split_structure_and_host_solve(team):
     lab2 = opart.geometric_labels((9, 9), (4, 4))
     st = P.pslr_host_stats(A2.rowptr, A2.colind, A2.vals, lab2, 16, want_transpose=False, team=team)
     assert st["team"] == team and st["team_valid"] == 1
+    # blocks of very different sizes: each is cut into groups in proportion to
+    # its share of the largest block (the smallest into one group and an
+    # empty top group)
+    A3 = wl.laplacian2d(40, 0.1)
+    col = np.arange(A3.n) // 40
+    lab3 = np.where(col < 30, 0, np.where(col < 36, 1, 2)).astype(np.int32)
+    st = P.pslr_host_stats(A3.rowptr, A3.colind, A3.vals, lab3, 3, want_transpose=False, team=team)
+    assert st["team"] == team and st["team_valid"] == 1 and st["team_residual"] < 1e-14
     # threshold ILU has no team split
     st = P.pslr_host_stats(A.rowptr, A.colind, A.vals, lab, nl, want_transpose=False, team=team,
                            factor="ilut")
