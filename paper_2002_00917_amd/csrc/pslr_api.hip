@@ -2611,6 +2611,13 @@ pslr_status pslr_apply_transpose(pslr_handle h, int32_t nrhs, const double* b, i
   return apply_dir(h, true, nrhs, b, ldb, z, ldz, (hipStream_t)hip_stream);
 }
 
+// FGMRES enqueues iteration j + 1 before reading iteration j's results while
+// every active residual estimate is above this multiple of its target.
+#ifndef PSLR_SPEC_MARGIN
+#define PSLR_SPEC_MARGIN 4.0
+#endif
+constexpr double kSpecMargin = PSLR_SPEC_MARGIN;
+
 pslr_status fgmres_solve(pslr_handle h, int32_t nrhs, const double* b, int64_t ldb, double* x,
                          int64_t ldx, int32_t restart, int32_t maxit, double tol, int32_t transpose,
                          int32_t* iters, double* relres, void* hip_stream) {
@@ -2734,11 +2741,11 @@ pslr_status fgmres_solve(pslr_handle h, int32_t nrhs, const double* b, int64_t l
     if (!any) break;
     HIP_TRY(hipMemcpyAsync(h->fscl, sc.data(), sizeof(double) * ncol, hipMemcpyHostToDevice, s));
     HIP_TRY(launch_scale_chunk(nchF, h->fchF, cV, cV, Vb, h->fscl, Vb, s));
-    // Iteration j+1 is enqueued before the host reads iteration j's Hessenberg
-    // column: V_{j+1} is normalised on the device from its norm, the column
-    // travels to pinned host memory behind an event, and the host's Givens
-    // update of column j overlaps the device's iteration j+1.  Convergence is
-    // seen one iteration late; the extra iteration's results are not used.
+    // Far from convergence iteration j+1 is enqueued before the host reads
+    // iteration j's Hessenberg column: V_{j+1} is normalised on the device
+    // from its norm, the column travels to pinned host memory behind an
+    // event, and the host's Givens update of column j overlaps the device's
+    // iteration j+1 (whose results are dropped if column j converged).
     auto enqueue = [&](int j) -> pslr_status {
       double* Vj = Vb + (size_t)j * blk;
       double* Zj = Zb + (size_t)j * blk;
@@ -2779,7 +2786,16 @@ pslr_status fgmres_solve(pslr_handle h, int32_t nrhs, const double* b, int64_t l
     };
     if (pslr_status st = enqueue(0)) return st;
     for (int j = 0; j < restart; ++j) {
-      if (j + 1 < restart)
+      // Iteration j + 1 goes ahead of the host's reading of iteration j only
+      // while every active column's residual estimate |g_j| is above
+      // kSpecMargin times its target: near convergence the host waits for
+      // iteration j first, so that a converged solve does not pay for an
+      // iteration whose results it drops (an apply and its vector work) but
+      // for one host round trip per iteration instead.
+      bool spec = j + 1 < restart;
+      for (int c = 0; c < ncol && spec; ++c)
+        if (act[c] && std::fabs(g[(size_t)c * R1 + j]) <= kSpecMargin * tol * bn[c]) spec = false;
+      if (spec)
         if (pslr_status st = enqueue(j + 1)) return st;
       HIP_TRY(hipEventSynchronize(hev.e[j & 1]));
       const int nv = j + 1;
@@ -2814,6 +2830,8 @@ pslr_status fgmres_solve(pslr_handle h, int32_t nrhs, const double* b, int64_t l
         else cont = true;
       }
       if (!cont) break;
+      if (!spec && j + 1 < restart)
+        if (pslr_status st = enqueue(j + 1)) return st;
     }
     // x += Z y
     std::fill(yv.begin(), yv.end(), 0.0);
