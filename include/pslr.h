@@ -384,6 +384,8 @@ typedef struct {
                                split runs when (slots_B + max q_i) * value size and
                                slots_C * value size fit one workgroup's LDS */
   int64_t team_lds_slots_C; /* the same over the C_i */
+  int32_t team_groups_max_B; /* most subtree groups of one B_i (t_i, see pslr_options.team) */
+  int32_t team_items_B;      /* subtree groups of all B_i: the work list of one B launch */
 } pslr_host_stats_t;
 pslr_status pslr_host_stats(int64_t n, const int64_t* rowptr, const int32_t* colind,
                             const double* vals, const int32_t* part, int32_t nparts,

@@ -2090,6 +2090,10 @@ pslr_status pslr_host_stats(int64_t n, const int64_t* rowptr, const int32_t* col
     out->team_residual = std::max(out->team_residual, tres[t]);
     int64_t& sl = (int)t < nB ? out->team_lds_slots_B : out->team_lds_slots_C;
     sl = std::max(sl, tslots[t]);
+    if ((int)t < nB) {
+      out->team_items_B += bteam[t];
+      out->team_groups_max_B = std::max(out->team_groups_max_B, bteam[t]);
+    }
   }
   for (size_t t = 0; t < mats.size(); ++t) {
     const bool b = (int)t < nB;

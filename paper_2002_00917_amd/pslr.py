@@ -44,7 +44,8 @@ class pslr_host_stats_t(C.Structure):
                 ("max_levels_C0", C.c_int32), ("levels_valid", C.c_int32),
                 ("factor_residual", C.c_double), ("solve_residual", C.c_double),
                 ("team", C.c_int32), ("team_valid", C.c_int32), ("team_residual", C.c_double),
-                ("team_lds_slots_B", C.c_int64), ("team_lds_slots_C", C.c_int64)]
+                ("team_lds_slots_B", C.c_int64), ("team_lds_slots_C", C.c_int64),
+                ("team_groups_max_B", C.c_int32), ("team_items_B", C.c_int32)]
 
 
 class pslr_info_t(C.Structure):

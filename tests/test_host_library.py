@@ -211,6 +211,16 @@ def test_team_split_structure_and_host_solve(team):
     lab3 = np.where(col < 30, 0, np.where(col < 36, 1, 2)).astype(np.int32)
     st = P.pslr_host_stats(A3.rowptr, A3.colind, A3.vals, lab3, 3, want_transpose=False, team=team)
     assert st["team"] == team and st["team_valid"] == 1 and st["team_residual"] < 1e-14
+    p = [1200 - 40, 240 - 80, 160 - 40]  # interior rows: parts minus their lines next to a cut
+    share = [max(1, min(32, int(np.floor(team * pi / max(p) + 0.5)))) for pi in p]
+    assert st["team_groups_max_B"] == team and st["team_items_B"] == sum(share), (st, share)
+    # blocks above 2048 rows get at least one group per 2048 rows, whatever `team`
+    A4 = wl.laplacian2d(150, 0.05, Ny=150)
+    lab4 = opart.geometric_labels((150, 150), (2, 1))
+    st = P.pslr_host_stats(A4.rowptr, A4.colind, A4.vals, lab4, 2, want_transpose=False, team=team)
+    pi = int(np.sum(lab4 == 0)) - 150
+    assert st["team_valid"] == 1 and st["team_residual"] < 1e-12
+    assert st["team_groups_max_B"] == max(team, -(-pi // 2048)) and st["team_items_B"] == 2 * st["team_groups_max_B"]
     # threshold ILU has no team split
     st = P.pslr_host_stats(A.rowptr, A.colind, A.vals, lab, nl, want_transpose=False, team=team,
                            factor="ilut")
