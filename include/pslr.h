@@ -182,10 +182,10 @@ typedef struct {
   int32_t team_c;           /* most groups of one C_i in the team split (0: no split) */
   int32_t team_top_c;       /* the C_i top groups' solve, as team_top */
   int32_t team_apply;       /* solves of single-right-hand-side forward applies: 0 one workgroup
-                               per block, 1 team split of the B_i, 2 of the B_i and the C_i.  A
-                               split runs when each of its groups (rows, level scratch, the
-                               block's interface values) fits one workgroup's LDS, so it also
-                               serves blocks too large for the LDS of one workgroup */
+                               per block, 2 team split of the B_i and the C_i.  The split runs
+                               when each of its groups (rows, level scratch, the block's
+                               interface values) fits one workgroup's LDS, so it also serves
+                               blocks too large for the LDS of one workgroup */
 } pslr_info_t;
 
 /* Fill *opt with defaults: m = 3, rank = 16, FP64, no transpose, seed 1, tau 0.1,

@@ -854,18 +854,14 @@ LaunchCfg choose_launch(pslr_ctx* h, const ApplyArrays<T>& A, int nrhs, hipStrea
   return c;
 }
 
-// Team path of a forward apply with arrays A and launch configuration c (of
-// at most team_rhs right-hand sides): team (every B_i solve split over a team of
-// workgroups, each holding its group's rows in LDS) and cteam (the C_i solves
-// too).  The split also serves subdomains too large for one workgroup's LDS,
-// as long as each group fits; a C_i without a team split is then solved in
-// LDS by one workgroup, which needs the plain path's fit.
+// Whether a forward apply (of at most team_rhs right-hand sides) takes the
+// team solves: every B_i and C_i solve split over a team of workgroups, each
+// holding its group's rows in LDS, so that subdomains too large for one
+// workgroup's LDS are served too, as long as each group fits.
 template <typename T>
-void team_path(const pslr_ctx* h, const ApplyArrays<T>& A, const LaunchCfg& c, bool& team, bool& cteam) {
-  const bool tb_fit = A.TB.team > 1 && team_lds_bytes(A.TB, A.maxQB) <= h->lds_max;
-  const bool tc_fit = A.TC.team > 1 && team_lds_bytes(A.TC, A.maxQB) <= h->lds_max;
-  team = tb_fit && (tc_fit || !c.gx);
-  cteam = team && tc_fit;
+bool team_path(const pslr_ctx* h, const ApplyArrays<T>& A) {
+  return A.TB.team > 1 && A.TC.team > 1 && team_lds_bytes(A.TB, A.maxQB) <= h->lds_max &&
+         team_lds_bytes(A.TC, A.maxQB) <= h->lds_max;
 }
 
 // Device workspace of one apply (see WsSizes).
@@ -901,26 +897,22 @@ pslr_status run_apply(pslr_ctx* h, const ApplyArrays<T>& Ah, const ApplyWs& W, b
   // right-hand sides; automatic: one, or up to kTeamRhsAuto when the tiled
   // path would keep its working vectors in global memory (each right-hand
   // side then costs a read of the factors, but in LDS)
-  bool team = false, cteam = false;
   const int trhs = h->team_rhs > 0 ? h->team_rhs : (cfg.gx ? kTeamRhsAuto : 1);
-  if (W.team && nrhs <= trhs && !transpose) team_path<T>(h, A, cfg, team, cteam);
-  if (team && !cteam) A.TC.team = 0;
+  const bool team = W.team && nrhs <= trhs && !transpose && team_path<T>(h, A);
   TeamWs tw{};
   if (team) {
     T* t = (T*)W.team;
     tw.ldxb = std::max<int64_t>(h->R.p, 1);
     tw.lddb = (int64_t)A.TB.nitems * A.TB.ntopmax;
+    tw.ldxc = std::max<int64_t>(h->R.q, 1);
+    tw.lddc = (int64_t)A.TC.nitems * A.TC.ntopmax;
     tw.xb = t;
     t += tw.ldxb * nrhs;
     tw.dtopb = t;
     t += tw.lddb * nrhs;
-    if (cteam) {
-      tw.ldxc = std::max<int64_t>(h->R.q, 1);
-      tw.lddc = (int64_t)A.TC.nitems * A.TC.ntopmax;
-      tw.xc = t;
-      t += tw.ldxc * nrhs;
-      tw.dtopc = t;
-    }
+    tw.xc = t;
+    t += tw.ldxc * nrhs;
+    tw.dtopc = t;
   }
   HIP_TRY(tr.mark(PH_START));
   if (team) HIP_TRY(launch_head_team<T>(A, cfg, nrhs, b, ldb, y, q, tw));
@@ -935,18 +927,18 @@ pslr_status run_apply(pslr_ctx* h, const ApplyArrays<T>& Ah, const ApplyWs& W, b
       HIP_TRY(launch_lr_mfma(h->nchunk_lr, h->d_chunks, h->nsys, h->d_sys_chunk, k, h->Vbf, h->R.q,
                              h->Vbr, h->G32, 0, (float*)y, q, nrhs, (float*)part,
                              (__hip_bfloat16*)W.zp, h->cur_active, s));
-      if (cteam) HIP_TRY(launch_c0_team<T>(A, cfg, nrhs, y, ua, q, tw));
+      if (team) HIP_TRY(launch_c0_team<T>(A, cfg, nrhs, y, ua, q, tw));
       else HIP_TRY(launch_c0solve<T>(A, cfg, nrhs, y, q, ua, q));
     } else if (k > 0 && nrhs == 1) {
       HIP_TRY(lowrank1<T>(h, y, part, 0, s));
-      if (cteam) HIP_TRY(launch_c0_team<T>(A, cfg, nrhs, y, ua, q, tw));
+      if (team) HIP_TRY(launch_c0_team<T>(A, cfg, nrhs, y, ua, q, tw));
       else HIP_TRY(launch_c0solve<T>(A, cfg, nrhs, y, q, ua, q));
     } else if (k > 0) {
       HIP_TRY(lowrank_partial<T>(h, y, q, nrhs, part, s));
       // the expansion fused with the C0 solve, or the C_i team solves after it
-      HIP_TRY(lowrank_expand<T>(h, A, cfg, nrhs, 0, part, y, q, cteam ? 0 : 1, ua, q));
-      if (cteam) HIP_TRY(launch_c0_team<T>(A, cfg, nrhs, y, ua, q, tw));
-    } else if (cteam) {
+      HIP_TRY(lowrank_expand<T>(h, A, cfg, nrhs, 0, part, y, q, team ? 0 : 1, ua, q));
+      if (team) HIP_TRY(launch_c0_team<T>(A, cfg, nrhs, y, ua, q, tw));
+    } else if (team) {
       HIP_TRY(launch_c0_team<T>(A, cfg, nrhs, y, ua, q, tw));
     } else {
       HIP_TRY(launch_c0solve<T>(A, cfg, nrhs, y, q, ua, q));
@@ -1740,10 +1732,8 @@ void fill_info(pslr_ctx* h, const std::vector<BlockFactor>& fB, const std::vecto
   I.team_top = I.team ? (h->fw64.TB.TI ? 2 : 1) : 0;
   I.team_c = h->fw64.TC.team > 1 ? h->fw64.TC.team : 0;
   I.team_top_c = I.team_c ? (h->fw64.TC.TI ? 2 : 1) : 0;
-  bool tb = false, tc = false;
-  if (h->precision >= 1) team_path<float>(h, h->fw32, choose_launch(h, h->fw32, 1, nullptr), tb, tc);
-  else team_path<double>(h, h->fw64, choose_launch(h, h->fw64, 1, nullptr), tb, tc);
-  I.team_apply = tb ? (tc ? 2 : 1) : 0;
+  const bool tp = h->precision >= 1 ? team_path<float>(h, h->fw32) : team_path<double>(h, h->fw64);
+  I.team_apply = tp ? 2 : 0;
   const int64_t matrix = (m + 2) * bB + (m + 1) * bC + (m + 1) * bEF + m * bCg + 2 * q * k * wv +
                          k * k * w;
   const int64_t vectors = (int64_t)(m + 2) * vecB + (m + 1) * vecC + (int64_t)w * (2 * m + 3) * q +

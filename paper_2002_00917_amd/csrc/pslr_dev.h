@@ -224,11 +224,11 @@ struct TeamWs {
 };
 // Vectors of nrhs columns with the given leading dimensions (y, u, src, dst:
 // ldv; b: ldb; z: ldz):
-//   series step: unext = C0^{-1}(y [add_y] - C_g u + F B^{-1} E u)  (C0 solve split when
-//                A.TC.team > 1, else one workgroup per subdomain and column)
+//   series step: unext = C0^{-1}(y [add_y] - C_g u + F B^{-1} E u)
 //   head:        y = g - F B^{-1} f                                (+ a launch for F)
 //   tail:        z = P^T (B^{-1}(f - E u); u)
-//   c0:          dst = C0^{-1} src                                 (A.TC.team > 1 only)
+//   c0:          dst = C0^{-1} src
+// (both families split: A.TB.team > 1 and A.TC.team > 1)
 template <typename T>
 hipError_t launch_series_team(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, const T* y,
                               const T* uprev, T* unext, int64_t ldv, int add_y, const TeamWs& W);

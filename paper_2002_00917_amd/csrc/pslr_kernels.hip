@@ -1526,38 +1526,6 @@ __global__ void __launch_bounds__(1024) k_team_upper(ApplyArrays<T> A, TeamIO<T>
   for (int k = tid; k < G.nown; k += nt) team_out<T, FAM, MODE>(A, io, base, G.P[k], X[k], false);
 }
 
-// the C0 part of a power-series step with t = B^{-1} E u read from xb, one
-// workgroup per subdomain (C_i without a team split)
-template <typename T>
-__global__ void __launch_bounds__(1024) k_team_c0(ApplyArrays<T> A, const T* __restrict__ y,
-                                                  const T* __restrict__ uprev, T* unext,
-                                                  const T* __restrict__ xb, int add_y, int64_t ldv,
-                                                  int64_t ldxb) {
-  const int i = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
-  int r0, nr;
-  if (!tile_rhs<T, 1>(A, gridDim.y, i, r0, nr)) return;
-  // column blockIdx.y: y, uprev and unext with leading dimension ldv, xb with ldxb
-  y += (int64_t)r0 * ldv;
-  uprev += (int64_t)r0 * ldv;
-  unext += (int64_t)r0 * ldv;
-  xb += (int64_t)r0 * ldxb;
-  Lds<T> L = carve<T, 1, false>(A);
-  const int64_t f0 = A.if_ptr[i], qi = A.if_ptr[i + 1] - f0;
-  const int64_t i0 = A.int_ptr[i];
-  for (int64_t kk = tid; kk < qi; kk += nt) {
-    const int64_t row = f0 + kk;
-    T acc = add_y ? y[row] : (T)0;
-    for (int64_t q = A.Cg.ptr[row]; q < A.Cg.ptr[row + 1]; ++q) acc -= A.Cg.val[q] * uprev[A.Cg.col[q]];
-    for (int64_t q = A.Fout.ptr[row]; q < A.Fout.ptr[row + 1]; ++q)
-      acc += A.Fout.val[q] * xb[i0 + A.Fout.col[q]];
-    L.XC[A.gC_inv[row]] = acc;
-  }
-  __syncthreads();
-  tri_solve<T, 1, false>(A.LC, i, L.XC, L.Rb, A.gshift);
-  tri_solve<T, 1, false>(A.UC, i, L.XC, L.Rb, A.gshift);
-  for (int64_t c = tid; c < qi; c += nt) unext[f0 + A.gC_out[f0 + c]] = L.XC[c];
-}
-
 // y = g - F t of the head with t = B^{-1} f read from xb (one thread per interface row)
 template <typename T>
 __global__ void __launch_bounds__(256) k_team_headF(ApplyArrays<T> A, const double* __restrict__ b,
@@ -1640,7 +1608,6 @@ hipError_t set_lds_limit(size_t bytes) {
   PSLR_SETATTR_TEAM((k_team_upper<T, 0, 2>))
   PSLR_SETATTR_TEAM((k_team_upper<T, 1, 0>))
   PSLR_SETATTR_TEAM((k_team_upper<T, 1, 1>))
-  PSLR_SETATTR_TEAM((k_team_c0<T>))
 #undef PSLR_SETATTR_TEAM
   return hipSuccess;
 }
@@ -1820,14 +1787,14 @@ TeamIO<T> team_io(const TeamWs& W) {
 template <typename T>
 hipError_t launch_series_team(const ApplyArrays<T>& A, const LaunchCfg& c, int nrhs, const T* y,
                               const T* uprev, T* unext, int64_t ldv, int add_y, const TeamWs& W) {
-  if (A.TB.team < 2 || nrhs < 1 || (A.TC.team < 2 && c.gx)) return hipErrorInvalidValue;
+  if (A.TB.team < 2 || A.TC.team < 2 || nrhs < 1) return hipErrorInvalidValue;
   TeamIO<T> io = team_io<T>(W);
   io.u = uprev;
   io.ldu = ldv;
   io.xw = (T*)W.xb;
   io.dtop = (T*)W.dtopb;
   launch_team<T, 0, 0>(A, c, nrhs, io, c.ev_start, nullptr);
-  if (A.TC.team > 1) {
+  {
     TeamIO<T> ic = team_io<T>(W);
     ic.u = uprev;
     ic.y = y;
@@ -1840,14 +1807,6 @@ hipError_t launch_series_team(const ApplyArrays<T>& A, const LaunchCfg& c, int n
     ic.out = unext;
     ic.add_y = add_y;
     launch_team<T, 1, 0>(A, c, nrhs, ic, nullptr, c.ev_stop);
-  } else {
-    const dim3 g1((unsigned)A.nparts, (unsigned)nrhs), bt(c.threads);
-    if (c.ev_stop)
-      hipExtLaunchKernelGGL((k_team_c0<T>), g1, bt, (uint32_t)c.lds, c.stream, nullptr, c.ev_stop, 0, A, y,
-                            uprev, unext, (const T*)W.xb, add_y, ldv, W.ldxb);
-    else
-      hipLaunchKernelGGL((k_team_c0<T>), g1, bt, c.lds, c.stream, A, y, uprev, unext, (const T*)W.xb, add_y,
-                         ldv, W.ldxb);
   }
   return hipGetLastError();
 }

@@ -111,13 +111,16 @@ def test_team_fgmres_and_batched_fallback():
 
 def test_team_top_auto_and_limits():
     """team_top = 0 picks the dense inverse when it holds at most twice the
-    packed top factors' values; bad values are rejected."""
+    packed top factors' values; bad team_top and team_rhs values are
+    rejected."""
     _dev()
     name, A, lab, m, rank = CASES[0]
     h = P.pslr_setup(A.rowptr, A.colind, A.vals, lab, 8, m=m, rank=0, team=4)
     assert P.pslr_info(h)["team_top"] in (1, 2)
     with pytest.raises(P.PslrError):
         P.pslr_setup(A.rowptr, A.colind, A.vals, lab, 8, m=m, rank=0, team=4, team_top=3)
+    with pytest.raises(P.PslrError):
+        P.pslr_setup(A.rowptr, A.colind, A.vals, lab, 8, m=m, rank=0, team=4, team_rhs=65)
 
 
 @pytest.mark.parametrize("team", [4, 8])
