@@ -38,7 +38,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-# per-case bounds where kappa * eps exceeds the benchmark spec's 1e-12 / 1e-5
+# per-case bounds where kappa * eps exceeds the stated 1e-12 (FP64) / 1e-5 (FP32)
 TOL64 = {"c1": 1.5e-10}
 TOL32 = {"c1": 3.3e-2, "lap3d_9_2x2x2": 8.4e-5, "c4_shaped": 4.5e-4}
 # BF16 storage of V (8 significant bits) against the exact-V preconditioner,
