@@ -83,6 +83,24 @@ def test_workload_shifts():
     assert np.sum(wl.convdiff_eigs(128, 10.0) < wl.SIGMA_C4) == 133
 
 
+def test_random_field_correlation_length():
+    """The variable coefficient's log field: unit variance and the
+    squared-exponential correlation exp(-r^2 / (2 l^2)) at l = 0.1, measured
+    at lags of 6, 13 and 26 cells of a 128^2 grid (averaged over 16 seeds;
+    exp(-r^2 / l^2) would give 0.80 and 0.36 at the first two lags)."""
+    N, l = 128, 0.1
+    for cells, tol in ((6, 0.04), (13, 0.06), (26, 0.08)):
+        rs = []
+        for seed in range(16):
+            f = wl.gaussian_random_field(N, l, seed)
+            assert abs(f.std() - 1.0) < 1e-12 and abs(f.mean()) < 1e-12
+            rx = np.corrcoef(f[:-cells, :].ravel(), f[cells:, :].ravel())[0, 1]
+            ry = np.corrcoef(f[:, :-cells].ravel(), f[:, cells:].ravel())[0, 1]
+            rs.append(0.5 * (rx + ry))
+        r = cells / N
+        assert abs(np.mean(rs) - np.exp(-r * r / (2 * l * l))) < tol, (cells, np.mean(rs))
+
+
 def test_variable_coefficient_reduces_to_laplacian():
     k = np.ones((9, 9))
     A = wl.variable_coeff2d(k, 0.3).to_scipy()
@@ -154,6 +172,54 @@ def test_region_growing_is_nearest_seed_bfs():
         idx = np.flatnonzero(lab == l)
         ncomp, _ = csg.connected_components(A[idx][:, idx])
         assert ncomp == 1
+
+
+def _layered_region_labels(A, seeds):
+    """Region growing restated layer by layer: distances from scipy's BFS,
+    then each layer's vertices taken in the order of their discoverers (the
+    earlier vertex of the previous layer first, its neighbours ascending);
+    a vertex joins the region of the first vertex of the previous layer that
+    touches it.  This is the first-in-first-out growth without a queue."""
+    P = (abs(A) + abs(A).T).tocsr()
+    P.setdiag(0)
+    P.eliminate_zeros()
+    P.sort_indices()
+    dist = csg.shortest_path(P, unweighted=True, indices=seeds).min(axis=0)
+    label = np.full(A.shape[0], -1)
+    layer = list(seeds)
+    for l, v in enumerate(seeds):
+        label[v] = l
+    d = 0
+    while layer:
+        d += 1
+        nxt = []
+        for u in layer:
+            for w in P.indices[P.indptr[u]:P.indptr[u + 1]]:
+                if dist[w] == d and label[w] < 0:
+                    label[w] = label[u]
+                    nxt.append(w)
+        layer = nxt
+    return label, dist
+
+
+@pytest.mark.parametrize("nx,ny,s,seed", [(23, 17, 7, 123), (16, 16, 6, 9), (31, 9, 11, 77)])
+def test_region_growing_tie_rule(nx, ny, s, seed):
+    """Vertices equidistant from several seeds go to the region that reaches
+    them first in first-in-first-out growth (seeds in label order): equal to
+    the layer-by-layer restatement, on grids where such ties occur."""
+    A = wl.laplacian2d(nx, 0.0, Ny=ny).to_scipy()
+    lab = opart.region_growing_labels(A, s, seed)
+    g = opart.splitmix64(seed)
+    seeds = []
+    while len(seeds) < s:
+        v = next(g) % A.shape[0]
+        if v not in seeds:
+            seeds.append(v)
+    ref, dist = _layered_region_labels(A, seeds)
+    per_seed = csg.shortest_path(abs(A), unweighted=True, indices=seeds)
+    ties = int(np.sum(np.sum(per_seed == dist, axis=0) > 1))
+    assert ties > 0
+    assert np.array_equal(lab, ref)
 
 
 # ---------------------------------------------------------------- closed forms
