@@ -219,6 +219,7 @@ def run_batched(P, torch, wl, steps, warmup, restart=40, rank=32, tol=1e-8, lowr
         "apply_GBps": (info["apply_bytes"] + (nrhs - 1) * info["apply_bytes_rhs"]) / (apply_ms * 1e-3) / 1e9,
         "global_vectors": info["global_vectors"], "threads": info["threads"],
         "lane_shift": info["lane_shift"], "max_tile": info["max_tile"],
+        "team_groups_max": info["team"], "team_apply": info["team_apply"],
     }
 
 
