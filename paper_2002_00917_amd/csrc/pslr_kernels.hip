@@ -1245,7 +1245,7 @@ struct TeamIO {
   const T* y;       // C: [y] of mode 0, the vector solved in mode 1
   const T* xb;      // C mode 0: B^{-1} E u
   T* xw;            // the family's vector between the launches
-  T* dtop;          // nparts x team x ntopmax pushes into the top rows
+  T* dtop;          // nitems x ntopmax pushes into the top rows (one slice per item)
   double* z;        // B mode 2
   T* out;           // C: the result
   int add_y;
