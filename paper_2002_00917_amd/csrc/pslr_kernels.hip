@@ -1221,16 +1221,18 @@ __global__ void __launch_bounds__(1024) k_tail(ApplyArrays<T> A, int nrhs, const
   }
 }
 
-// ---- Team solves (one right-hand side, working vectors in LDS).  The
-// supernodal tree of every B_i (family 0) and C_i (family 1) is cut into
-// `team` groups of whole subtrees and a top group (BlockFactor::loS/upS).
-// Launch 1, workgroup (i, g): group g's rows from the right-hand side and its
+// ---- Team solves (a group's working vector in LDS, one right-hand side per
+// workgroup: column blockIdx.y).  The supernodal tree of every B_i (family 0)
+// and C_i (family 1) is cut into t_i groups of whole subtrees and a top group
+// (BlockFactor::loS/upS), all blocks' subtree groups forming one work list.
+// Launch 1, work item (i, g): group g's rows from the right-hand side and its
 // lower solve on an LDS copy whose top rows start at their right-hand side
 // (g = 0) or zero; the group's rows go to the family vector xw, its top rows
 // (right-hand side minus its pushes) to dtop.  Launch 2: the top group from
 // the sum of the groups' top rows, by its packed lower and upper solves (one
-// workgroup per block) or by its dense inverse (one workgroup per 64 top rows).  Launch 3, workgroup (i, g): group g's
-// upper solve, pulling the top rows.
+// workgroup per block) or by its dense inverse (one workgroup per 64 top
+// rows).  Launch 3, work item (i, g): group g's upper solve, pulling the top
+// rows.
 //
 // Right-hand sides and results by family and MODE:
 //   B, 0 (power-series step): E u                  x to xb
